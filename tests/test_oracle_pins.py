@@ -1,0 +1,528 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the oracle:
+textbook element matrices in Voigt notation, rigid-body modes, symmetry, the
+patch test, a closed-form bar, O(h^2) convergence on manufactured solutions,
+an independent sparse direct solver, dense brute force, and central finite
+differences of the compliance under a smooth mesh motion."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import fo_inputs as fi
+import oracle as oc
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+
+
+# ----------------------------------------------------------------------------
+# independent textbook element stiffness (Voigt notation, engineering shear)
+
+
+def grads_cofactor(P):
+    """Barycentric gradients from cofactors (not the oracle's Gauss-Jordan)."""
+    d = P.shape[1]
+    if d == 2:
+        x, y = P[:, 0], P[:, 1]
+        twoA = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0])
+        b = np.array([y[1] - y[2], y[2] - y[0], y[0] - y[1]]) / twoA
+        c = np.array([x[2] - x[1], x[0] - x[2], x[1] - x[0]]) / twoA
+        return np.stack([b, c], axis=1), abs(twoA) / 2
+    r1, r2, r3 = P[1] - P[0], P[2] - P[0], P[3] - P[0]
+    det = r1 @ np.cross(r2, r3)
+    g1, g2, g3 = np.cross(r2, r3) / det, np.cross(r3, r1) / det, np.cross(r1, r2) / det
+    return np.stack([-(g1 + g2 + g3), g1, g2, g3]), abs(det) / 6
+
+
+def voigt_D(dim, E, nu, plane_stress):
+    if dim == 2 and plane_stress:
+        return E / (1 - nu ** 2) * np.array([[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu) / 2]])
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    if dim == 2:  # plane strain
+        return np.array([[lam + 2 * mu, lam, 0], [lam, lam + 2 * mu, 0], [0, 0, mu]])
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[np.arange(3), np.arange(3)] = lam + 2 * mu
+    D[np.arange(3, 6), np.arange(3, 6)] = mu
+    return D
+
+
+def voigt_B(g):
+    nv, d = g.shape
+    if d == 2:
+        B = np.zeros((3, 2 * nv))
+        for a in range(nv):
+            B[0, 2 * a] = g[a, 0]
+            B[1, 2 * a + 1] = g[a, 1]
+            B[2, 2 * a] = g[a, 1]
+            B[2, 2 * a + 1] = g[a, 0]
+        return B
+    B = np.zeros((6, 3 * nv))
+    for a in range(nv):
+        gx, gy, gz = g[a]
+        B[0, 3 * a] = gx
+        B[1, 3 * a + 1] = gy
+        B[2, 3 * a + 2] = gz
+        B[3, 3 * a + 1], B[3, 3 * a + 2] = gz, gy  # gamma_yz
+        B[4, 3 * a], B[4, 3 * a + 2] = gz, gx      # gamma_xz
+        B[5, 3 * a], B[5, 3 * a + 1] = gy, gx      # gamma_xy
+    return B
+
+
+def voigt_Ke(P, E=1.0, nu=0.3, plane_stress=1):
+    g, vol = grads_cofactor(P)
+    B = voigt_B(g)
+    return vol * B.T @ voigt_D(P.shape[1], E, nu, plane_stress) @ B
+
+
+def dense_voigt_K(m, A_e, E=1.0, nu=0.3, plane_stress=1):
+    d = m.dim
+    K = np.zeros((m.n_dofs, m.n_dofs))
+    for e in range(m.n_elems):
+        nodes = m.conn[:, e]
+        Ke = A_e[e] * voigt_Ke(m.coords[nodes], E, nu, plane_stress)
+        idx = (nodes[:, None] * d + np.arange(d)[None, :]).ravel()
+        K[np.ix_(idx, idx)] += Ke
+    return K
+
+
+def single_element_mesh(P):
+    d = P.shape[1]
+    return fi.Mesh(d, P.astype(np.float64), np.arange(d + 1, dtype=np.int32).reshape(-1, 1),
+                   np.zeros((d, 0), np.int32), np.zeros((0, d)), (1.0,) * d, (1,) * d)
+
+
+# ----------------------------------------------------------------------------
+
+
+def test_lame_closed_forms():
+    lam, mu = oc.lame(1.0, 0.3, 2, 1)
+    assert lam == pytest.approx(GOLD["lame_plane_stress"]["lambda"], rel=1e-15)
+    assert mu == pytest.approx(GOLD["lame_plane_stress"]["mu"], rel=1e-15)
+    lam3, mu3 = oc.lame(1.0, 0.3, 3, 0)
+    assert lam3 == pytest.approx(GOLD["lame_3d"]["lambda"], rel=1e-15)
+    assert mu3 == pytest.approx(GOLD["lame_3d"]["mu"], rel=1e-15)
+
+
+def test_T1_reference_triangle_closed_form():
+    P = np.array(GOLD["reference_triangle_plane_stress"]["vertices"], dtype=float)
+    m = single_element_mesh(P)
+    lam, mu = oc.lame(1.0, 0.3, 2, 1)
+    K = oc.assemble_elasticity(2, m.coords, m.conn, np.ones(1), lam, mu).to_scipy().toarray()
+    g = GOLD["reference_triangle_plane_stress"]
+    assert K[2, 2] == pytest.approx(g["K_1x_1x"], rel=1e-14)
+    assert abs(K[2, 3]) < 1e-16
+    assert K[2, 5] == pytest.approx(g["K_1x_2y"], rel=1e-14)
+    assert K[3, 3] == pytest.approx(g["K_1y_1y"], rel=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T1_element_matrix_matches_voigt_textbook(dim):
+    rng = np.random.default_rng(11 + dim)
+    for trial in range(5):
+        P = rng.uniform(-1, 1, size=(dim + 1, dim))
+        if trial == 0:
+            P = P[::-1].copy()  # include a negatively oriented element
+        m = single_element_mesh(P)
+        ps = 1 if dim == 2 else 0
+        lam, mu = oc.lame(1.0, 0.3, dim, ps)
+        A = np.array([0.37])
+        K = oc.assemble_elasticity(dim, m.coords, m.conn, A, lam, mu).to_scipy().toarray()
+        Kv = A[0] * voigt_Ke(P, 1.0, 0.3, ps)
+        np.testing.assert_allclose(K, Kv, rtol=0, atol=1e-12 * np.abs(Kv).max())
+
+
+def rigid_modes(X):
+    N, d = X.shape
+    modes = []
+    for i in range(d):
+        r = np.zeros((N, d))
+        r[:, i] = 1.0
+        modes.append(r.ravel())
+    if d == 2:
+        modes.append(np.stack([-X[:, 1], X[:, 0]], axis=1).ravel())
+    else:
+        for w in np.eye(3):
+            modes.append(np.cross(w[None, :], X).ravel())
+    return modes
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T2_rigid_modes_in_kernel(dim):
+    w = fi.cantilever_2d((12, 6)) if dim == 2 else fi.cantilever_3d((8, 4, 4))
+    m = w.mesh
+    lam, mu = oc.lame(1.0, 0.3, dim, w.plane_stress)
+    A, _ = oc.element_coef(dim, m.conn, np.random.default_rng(dim).standard_normal(m.n_nodes), 1e-3)
+    assert 0 < (A == 1.0).sum() < m.n_elems
+    K = oc.assemble_elasticity(dim, m.coords, m.conn, A, lam, mu)
+    Knorm = np.abs(K.to_scipy()).sum(axis=1).max()
+    for r in rigid_modes(m.coords):
+        assert np.abs(K.matvec(r)).max() <= 1e-13 * Knorm * np.abs(r).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T3_symmetry(dim):
+    w = fi.cantilever_2d((10, 5)) if dim == 2 else fi.cantilever_3d((6, 3, 3))
+    m = w.mesh
+    lam, mu = oc.lame(1.0, 0.3, dim, w.plane_stress)
+    A, _ = oc.element_coef(dim, m.conn, w.phi, 1e-3)
+    K = oc.assemble_elasticity(dim, m.coords, m.conn, A, lam, mu)
+    Bd = oc.assemble_descent(dim, m.coords, m.conn, m.bfacets, m.bnormal, 0.01, 1e4, 1e4, w.boxes)
+    rng = np.random.default_rng(3)
+    for M in (K, Bd):
+        x, y = rng.standard_normal((2, m.n_dofs))
+        nrm = np.abs(M.to_scipy()).sum(axis=1).max()
+        assert abs(x @ M.matvec(y) - y @ M.matvec(x)) <= 1e-14 * nrm * np.linalg.norm(x) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T4_patch_test_linear_field(dim):
+    """Linear displacement imposed on the boundary is reproduced inside."""
+    m = fi.structured_mesh((8, 6) if dim == 2 else (5, 4, 4), (1.0, 1.0) if dim == 2 else (1.0, 1.0, 1.0))
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal((dim, dim))
+    c = rng.standard_normal(dim)
+    u_lin = (m.coords @ G.T + c).ravel()
+    bnd_nodes = np.unique(m.bfacets)
+    fixed = np.zeros(m.n_nodes, np.uint8)
+    fixed[bnd_nodes] = 1
+    fixed = np.repeat(fixed, dim)
+    lam, mu = oc.lame(1.0, 0.3, dim, 1 if dim == 2 else 0)
+    K = oc.assemble_elasticity(dim, m.coords, m.conn, np.ones(m.n_elems), lam, mu)
+    ug = np.where(fixed == 1, u_lin, 0.0)
+    w_, info = K.solve(-K.matvec(ug), fixed, rtol=1e-13)
+    assert info.status == 0
+    u = w_ + ug
+    np.testing.assert_allclose(u, u_lin, atol=1e-10 * np.abs(u_lin).max())
+
+
+def _bar(dim, cells):
+    L = 2.0
+    lengths = (L, 1.0) if dim == 2 else (L, 1.0, 0.5)
+    m = fi.structured_mesh(cells, lengths)
+    fixed = np.zeros((m.n_nodes, dim), np.uint8)
+    x0 = m.coords[:, 0] == 0.0
+    fixed[x0, 0] = 1  # rollers on x = 0
+    origin = np.nonzero(np.all(m.coords == 0.0, axis=1))[0][0]
+    fixed[origin, 1:] = 1
+    if dim == 3:  # stop the rotation about the x axis
+        n2 = np.nonzero(x0 & (m.coords[:, 1] == 1.0) & (m.coords[:, 2] == 0.0))[0][0]
+        fixed[n2, 2] = 1
+    s = 0.7  # end traction along x
+    b = fi.traction_load(m, (s,) + (0.0,) * (dim - 1), (0.0,) * (dim - 1), lengths[1:])
+    return m, fixed.ravel(), b, s, L, float(np.prod(lengths[1:]))
+
+
+@pytest.mark.parametrize("dim,cells", [(2, (8, 4)), (3, (6, 3, 2))])
+def test_T5_uniaxial_bar_closed_form(dim, cells):
+    m, fixed, b, s, L, Ac = _bar(dim, cells)
+    E, nu = 1.0, 0.3
+    lam, mu = oc.lame(E, nu, dim, 1 if dim == 2 else 0)
+    A = np.ones(m.n_elems)
+    K = oc.assemble_elasticity(dim, m.coords, m.conn, A, lam, mu)
+    u, info = K.solve(b, fixed, rtol=1e-13)
+    eps = s / E
+    U = u.reshape(-1, dim)
+    np.testing.assert_allclose(U[:, 0], eps * m.coords[:, 0], atol=1e-10)
+    for k in range(1, dim):
+        np.testing.assert_allclose(U[:, k], -nu * eps * m.coords[:, k], atol=1e-10)
+    F = s * Ac
+    J_exact = F ** 2 * L / (E * Ac)
+    assert b @ u == pytest.approx(J_exact, rel=1e-10)
+    rhs, S1, J, vol = oc.shape_derivative(dim, m.coords, m.conn, A, A, lam, mu, u, want_S1=True)
+    assert J[0] == pytest.approx(J_exact, rel=1e-10)
+    S1 = S1.reshape(dim, dim, -1)
+    expect = np.diag([E * eps ** 2] + [-E * eps ** 2] * (dim - 1))
+    np.testing.assert_allclose(np.moveaxis(S1, 2, 0), np.broadcast_to(expect, (m.n_elems, dim, dim)),
+                               atol=1e-9 * E * eps ** 2)
+
+
+# ---------------------------------------------------------------- MMS (T6)
+
+TRI_Q = (np.array([[0.445948490915965, 0.445948490915965], [0.445948490915965, 0.108103018168070],
+                   [0.108103018168070, 0.445948490915965], [0.091576213509771, 0.091576213509771],
+                   [0.091576213509771, 0.816847572980459], [0.816847572980459, 0.091576213509771]]),
+         np.array([0.223381589678011] * 3 + [0.109951743655322] * 3))
+_a, _b = 0.5854101966249685, 0.1381966011250105
+TET_Q = (np.array([[_b, _b, _b], [_a, _b, _b], [_b, _a, _b], [_b, _b, _a]]), np.full(4, 0.25))
+
+
+def _quad_points(m):
+    """Physical quadrature points, weights and barycentric values per element."""
+    ref, wts = TRI_Q if m.dim == 2 else TET_Q
+    lam = np.concatenate([1 - ref.sum(1, keepdims=True), ref], axis=1)  # [q, d+1]
+    P = m.coords[m.conn]  # [d+1, E, d]
+    X = np.einsum("qa,aei->eqi", lam, P)
+    vol = np.abs(np.linalg.det(np.moveaxis(P[1:] - P[0][None], 0, 1))) / (2 if m.dim == 2 else 6)
+    return X, wts[None, :] * vol[:, None], lam
+
+
+def _mms(dim, n, lam, mu):
+    m = fi.structured_mesh((n,) * dim, (1.0,) * dim)
+    c = np.array([1.0, -0.5, 0.7][:dim])
+
+    def s_and_derivs(X):
+        S = np.ones(X.shape[:-1])
+        for k in range(dim):
+            S = S * np.sin(np.pi * X[..., k])
+        H = np.zeros(X.shape[:-1] + (dim, dim))
+        for i in range(dim):
+            for j in range(dim):
+                t = np.ones(X.shape[:-1])
+                for k in range(dim):
+                    if k == i and k == j:
+                        t = t * (-np.pi ** 2 * np.sin(np.pi * X[..., k]))
+                    elif k == i or k == j:
+                        t = t * (np.pi * np.cos(np.pi * X[..., k]))
+                    else:
+                        t = t * np.sin(np.pi * X[..., k])
+                H[..., i, j] = t
+        return S, H
+
+    X, W, bary = _quad_points(m)
+    S, H = s_and_derivs(X)
+    lapS = np.trace(H, axis1=-2, axis2=-1)
+    # u = c s(x):  div sigma = (lam + mu) H c + mu c lap(s);  f = -div sigma
+    f = -((lam + mu) * np.einsum("eqij,j->eqi", H, c) + mu * lapS[..., None] * c)
+    b = np.zeros((m.n_nodes, dim))
+    for a in range(dim + 1):
+        np.add.at(b, m.conn[a], np.einsum("eq,eqi->ei", W * bary[None, :, a], f))
+    fixed = np.repeat(np.isin(np.arange(m.n_nodes), np.unique(m.bfacets)), dim).astype(np.uint8)
+    K = oc.assemble_elasticity(dim, m.coords, m.conn, np.ones(m.n_elems), lam, mu)
+    u, info = K.solve(b.ravel(), fixed, rtol=1e-12)
+    assert info.status == 0
+    U = u.reshape(-1, dim)
+    uh = np.einsum("qa,aei->eqi", bary, U[m.conn])
+    err = np.sqrt(np.sum(W[..., None] * (uh - S[..., None] * c) ** 2))
+    return err
+
+
+@pytest.mark.parametrize("dim,ns", [(2, (8, 16, 32, 64)), (3, (4, 8, 16))])
+def test_T6_mms_second_order(dim, ns):
+    lam, mu = oc.lame(1.0, 0.3, dim, 1 if dim == 2 else 0)
+    errs = [_mms(dim, n, lam, mu) for n in ns]
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert abs(rates[-1] - 2.0) < 0.15, rates
+
+
+def test_T7_pcg_matches_sparse_direct():
+    w = fi.cantilever_2d()
+    m = w.mesh
+    lam, mu = oc.lame(1.0, 0.3, 2, 1)
+    A, _ = oc.element_coef(2, m.conn, w.phi, w.ersatz)
+    K = oc.assemble_elasticity(2, m.coords, m.conn, A, lam, mu)
+    u, info = K.solve(w.b, w.fixed, rtol=1e-12)
+    free = w.fixed == 0
+    Ks = K.to_scipy()[free][:, free].tocsc()
+    ud = np.zeros(m.n_dofs)
+    ud[free] = spla.spsolve(Ks, w.b[free])
+    assert np.linalg.norm(u - ud) <= 1e-9 * np.linalg.norm(ud)
+    assert info.relres <= 1e-12
+
+
+@pytest.mark.parametrize("cells", [(1, 1), (2, 1)])
+def test_T8_brute_force_dense(cells):
+    m = fi.structured_mesh(cells, (float(cells[0]), 1.0))
+    phi = np.linspace(-1, 0.4, m.n_nodes)
+    lam, mu = oc.lame(1.0, 0.3, 2, 1)
+    A, chi = oc.element_coef(2, m.conn, phi, 1e-3)
+    Kd = dense_voigt_K(m, A)
+    K = oc.assemble_elasticity(2, m.coords, m.conn, A, lam, mu).to_scipy().toarray()
+    np.testing.assert_allclose(K, Kd, atol=1e-14 * np.abs(Kd).max())
+    fixed = fi.clamp_mask(m)
+    b = np.zeros(m.n_dofs)
+    b[-1] = -1.0
+    free = fixed == 0
+    ud = np.zeros(m.n_dofs)
+    ud[free] = np.linalg.solve(Kd[np.ix_(free, free)], b[free])
+    u, info = oc.assemble_elasticity(2, m.coords, m.conn, A, lam, mu).solve(b, fixed, rtol=1e-14)
+    np.testing.assert_allclose(u, ud, atol=1e-11 * np.abs(ud).max())
+
+
+def test_element_coefficient_rule():
+    """Vertex mean < 0 -> material; a mean of exactly 0 is outside (strict)."""
+    conn = np.array([[0, 0, 0], [1, 1, 1], [2, 3, 4]], dtype=np.int32)
+    phi = np.array([-1.0, 1.0, -0.5, 0.0, 0.5])
+    A, chi = oc.element_coef(2, conn, phi, 1e-3)
+    np.testing.assert_array_equal(chi, [1.0, 0.0, 0.0])
+    np.testing.assert_array_equal(A, [1.0, 1e-3, 1e-3])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T9_compliance_identities(dim):
+    w = fi.cantilever_2d((16, 8)) if dim == 2 else fi.cantilever_3d((8, 4, 4))
+    r = oc.run_iteration(w)
+    m = w.mesh
+    lam, mu = oc.lame(1.0, 0.3, dim, w.plane_stress)
+    K = oc.assemble_elasticity(dim, m.coords, m.conn, r.A_e, lam, mu)
+    uKu = r.u @ K.matvec(r.u)
+    assert r.J[0] > 0
+    assert r.J[0] == pytest.approx(w.b @ r.u, rel=1e-10)
+    assert r.J[0] == pytest.approx(uKu, rel=1e-12)
+
+
+# ---------------------------------------------------------------- T10 FD
+
+
+def _bubble_field(X, lengths):
+    d = X.shape[1]
+    bub = np.ones(X.shape[0])
+    for k in range(d):
+        bub *= X[:, k] * (lengths[k] - X[:, k])
+    cols = [bub * (1.0 + 0.5 * X[:, 0]), bub * np.sin(3.0 * X[:, 1] + 0.2)]
+    if d == 3:
+        cols.append(bub * (X[:, 2] - 0.3 * X[:, 0]))
+    return np.stack(cols, axis=1)
+
+
+def _J_direct(m, coords, A, lam, mu, b, fixed):
+    K = oc.assemble_elasticity(m.dim, coords, m.conn, A, lam, mu).to_scipy()
+    free = fixed == 0
+    u = np.zeros(m.n_dofs)
+    u[free] = spla.spsolve(K[free][:, free].tocsc(), b[free])
+    return b @ u, u
+
+
+@pytest.mark.parametrize("dim,multi", [(2, False), (3, False), (2, True)])
+def test_T10_shape_derivative_matches_finite_differences(dim, multi):
+    """J_h(X + t theta) for a P1 field theta vanishing on the boundary (so the
+    clamp and the loads do not move) and A_e frozen per element:
+    (J(t) - J(-t)) / 2t  ==  sum_e |T_e| S1_e : D theta_e  ==  -rhs . theta."""
+    if dim == 2:
+        w = fi.cantilever_2d((32, 16))
+    else:
+        w = fi.cantilever_3d((16, 8, 8))
+    m = w.mesh
+    lam, mu = oc.lame(1.0, 0.3, dim, w.plane_stress)
+    A, chi = oc.element_coef(dim, m.conn, w.phi, w.ersatz)
+    assert 0 < chi.sum() < m.n_elems
+    B = w.b.reshape(-1, 1)
+    if multi:
+        b2 = fi.traction_load(m, (0.6, 0.8), (0.1,), (0.3,))
+        B = np.stack([w.b, b2], axis=1)
+    theta = _bubble_field(m.coords, m.lengths)
+    theta /= np.abs(theta).max()
+    U = np.zeros_like(B)
+    for k in range(B.shape[1]):
+        _, U[:, k] = _J_direct(m, m.coords, A, lam, mu, B[:, k], w.fixed)
+    rhs, _, J, _ = oc.shape_derivative(dim, m.coords, m.conn, A, chi, lam, mu, U)
+    dJ = -rhs @ theta.ravel()
+    t = 1e-4
+    Jp = sum(_J_direct(m, m.coords + t * theta, A, lam, mu, B[:, k], w.fixed)[0] for k in range(B.shape[1]))
+    Jm = sum(_J_direct(m, m.coords - t * theta, A, lam, mu, B[:, k], w.fixed)[0] for k in range(B.shape[1]))
+    fd = (Jp - Jm) / (2 * t)
+    assert abs(fd - dJ) <= 1e-7 * abs(dJ), (fd, dJ)
+    assert J.sum() == pytest.approx(sum(B[:, k] @ U[:, k] for k in range(B.shape[1])), rel=1e-10)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T10_volume_term_matches_finite_differences(dim):
+    w = fi.cantilever_2d((32, 16)) if dim == 2 else fi.cantilever_3d((16, 8, 8))
+    m = w.mesh
+    lam, mu = oc.lame(1.0, 0.3, dim, w.plane_stress)
+    A, chi = oc.element_coef(dim, m.conn, w.phi, w.ersatz)
+    assert 0 < chi.sum() < m.n_elems
+    theta = _bubble_field(m.coords, m.lengths)
+    theta /= np.abs(theta).max()
+    V = 0.8
+    rhs, _, _, vol = oc.shape_derivative(dim, m.coords, m.conn, A, chi, lam, mu,
+                                         np.zeros(m.n_dofs), lambda_vol=1.0, V=V)
+    t = 1e-4
+
+    def volume(X):
+        v, _ = oc.element_geometry(dim, X, m.conn)
+        return (chi * v).sum() / V
+
+    fd = (volume(m.coords + t * theta) - volume(m.coords - t * theta)) / (2 * t)
+    assert fd == pytest.approx(-rhs @ theta.ravel(), rel=1e-8)
+    assert vol == pytest.approx(volume(m.coords) * V, rel=1e-14)
+
+
+# ---------------------------------------------------------------- descent
+
+
+def test_T11_descent_constants():
+    """For a constant field c: c^T B c = (alpha + gamma_s 1_{Omega0}) |.| |c|^2
+    + gamma_n sum_faces |face| (c.n)^2 on the box [0,2]x[0,1]."""
+    m = fi.structured_mesh((8, 4), (2.0, 1.0))
+    c = np.array([0.3, -1.1])
+    C_ = np.tile(c, m.n_nodes)
+    for alpha, gn in ((0.01, 0.0), (0.5, 0.0), (0.01, 1e4)):
+        Bd = oc.assemble_descent(2, m.coords, m.conn, m.bfacets, m.bnormal, alpha, gn, 0.0)
+        expect = alpha * 2.0 * (c @ c) + gn * (2 * 1.0 * c[0] ** 2 + 2 * 2.0 * c[1] ** 2)
+        assert C_ @ Bd.matvec(C_) == pytest.approx(expect, rel=1e-12)
+    # subdomain penalty: the box [1.5, 2] x [0.25, 0.75] holds whole cells
+    box = np.array([[1.5, 0.25, 2.0 + 1e-9, 0.75]])
+    Bd = oc.assemble_descent(2, m.coords, m.conn, m.bfacets, m.bnormal, 0.0, 0.0, 7.0, box)
+    assert C_ @ Bd.matvec(C_) == pytest.approx(7.0 * 0.5 * 0.5 * (c @ c), rel=1e-12)
+    # the Laplacian part annihilates constants
+    Bd = oc.assemble_descent(2, m.coords, m.conn, m.bfacets, m.bnormal, 0.0, 0.0, 0.0)
+    assert np.abs(Bd.matvec(C_)).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim,ns", [(2, (8, 16, 32)), (3, (4, 8, 16))])
+def test_T11_descent_mms_second_order(dim, ns):
+    """B = alpha M + K_lap with natural Neumann conditions: the field
+    theta_i = prod cos(pi x_k) solves (-lap + alpha) theta = (d pi^2 + alpha) theta."""
+    alpha = 0.01
+    errs = []
+    for n in ns:
+        m = fi.structured_mesh((n,) * dim, (1.0,) * dim)
+        X, W, bary = _quad_points(m)
+        th = np.prod(np.cos(np.pi * X), axis=-1)
+        f = (dim * np.pi ** 2 + alpha) * th
+        b = np.zeros(m.n_nodes)
+        for a in range(dim + 1):
+            np.add.at(b, m.conn[a], (W * bary[None, :, a] * f).sum(1))
+        Bd = oc.assemble_descent(dim, m.coords, m.conn, m.bfacets, m.bnormal, alpha, 0.0, 0.0)
+        rhs = np.repeat(b, dim)
+        th_h, info = Bd.solve(rhs, None, rtol=1e-12)
+        assert info.status == 0
+        Th = th_h.reshape(-1, dim)
+        for i in range(dim):
+            uh = np.einsum("qa,ae->eq", bary, Th[m.conn, i])
+            errs.append(np.sqrt(np.sum(W * (uh - th) ** 2))) if i == 0 else None
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert abs(rates[-1] - 2.0) < 0.15, rates
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T12_descent_property(dim):
+    w = fi.cantilever_2d((16, 8)) if dim == 2 else fi.cantilever_3d((8, 4, 4))
+    r = oc.run_iteration(w)
+    m = w.mesh
+    Bd = oc.assemble_descent(dim, m.coords, m.conn, m.bfacets, m.bnormal, w.alpha, w.gamma_n,
+                             w.gamma_s, w.boxes)
+    assert r.B_tt > 0
+    assert r.theta @ Bd.matvec(r.theta) == pytest.approx(r.B_tt, rel=1e-10)
+    # dJ(theta) = sum_e |T| S1 : D theta = -rhs . theta = -B(theta, theta) < 0
+    assert -(r.rhs @ r.theta) < 0
+
+
+# ---------------------------------------------------------------- update
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_T13_levelset_update_exact_for_linear_phi(dim):
+    m = fi.structured_mesh((6, 3) if dim == 2 else (4, 2, 2), (2.0, 1.0) if dim == 2 else (2.0, 1.0, 1.0))
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal(dim)
+    phi = m.coords @ a + 0.3
+    theta = rng.standard_normal((m.n_nodes, dim))
+    dt = 0.013
+    out = oc.levelset_update(dim, m.coords, m.conn, theta.ravel(), dt, phi)
+    np.testing.assert_allclose(out, phi - dt * theta @ a, atol=1e-13)
+    out0 = oc.levelset_update(dim, m.coords, m.conn, np.zeros(m.n_dofs), dt, phi)
+    np.testing.assert_array_equal(out0, phi)
+
+
+def test_adaptive_dt_rule():
+    """t_end = clip(dfactor/B), s from the concave rule, clipped and rounded."""
+    t, s, dt = oc.adaptive_dt(1.0)
+    assert t == pytest.approx(0.01) and s == round(8 * ((0.01 - 1e-3) / (0.1 - 1e-3)) ** (1 / 6) + 8)
+    t, s, dt = oc.adaptive_dt(1e-9)
+    assert t == 0.1 and s == 16 and dt == pytest.approx(0.1 / 16)
+    t, s, dt = oc.adaptive_dt(1e9)
+    assert t == 1e-3 and s == 8
