@@ -1,0 +1,176 @@
+/*
+ * fo.h -- C ABI of the MI355X hot path of level-set shape optimisation for
+ * compliance minimisation (arXiv 2601.05709).
+ *
+ * One iteration of the paper's level-set algorithm (Section "Main algorithm",
+ * Algorithm "Level set algorithm") for the compliance model (Section
+ * "Compliance minimization") is exposed as four calls:
+ *
+ *   fo_state_solve       state problem, eq. compli_weak: find u with
+ *                        int A_Omega sigma(u) : eps(v) = int_Gamma1 g . v
+ *                        (P1 elements, Jacobi-preconditioned CG, matrix free);
+ *   fo_shape_derivative  compliance J (eq. compli_cost) and the right-hand side
+ *                        -int S1 : D xi of the velocity equation (eq. velocity)
+ *                        with S1 = S1^J + lambda S1^C (eq. S0andS1,
+ *                        S1^J = A (2 Du^T sigma(u) - sigma(u):eps(u) I),
+ *                        S1^C = chi_Omega I / V);
+ *   fo_descent_solve     velocity problem B(theta, xi) = -dJ(Omega; xi)
+ *                        (eqs. velocity_eq0, velocity) with the bilinear form of
+ *                        eq. compli1_bili (mass, gradient, subdomain penalty
+ *                        eq. sub_dom, boundary normal penalty eq. bd_plt);
+ *   fo_levelset_update   transport of phi along theta (eq. transport without
+ *                        the diffusion term), one explicit step.
+ *
+ * Conventions
+ *   - Mesh arrays passed to fo_create are HOST pointers; the library copies
+ *     (and re-tiles) them, so the caller may free them afterwards.
+ *   - All per-iteration arrays (phi, b, u, rhs, theta, S1, J, ...) are DEVICE
+ *     pointers owned by the caller.  They must not alias each other unless
+ *     stated.  Nothing is retained after a call returns.
+ *   - Unknowns are node-blocked: dof = node * dim + component.  Several right
+ *     hand sides are stored RHS-contiguous: value (dof, k) at [dof * ld + k].
+ *   - Element arrays are structure-of-arrays: conn[a * n_elems + e].
+ *   - Every call enqueues its work on the context's stream.  Calls that must
+ *     test convergence (the two solves) synchronise that stream before they
+ *     return; the others return without synchronising.
+ *   - Errors are status codes; arguments are validated on the host before any
+ *     work is enqueued.  A context is not thread safe.
+ *   - Level set: Omega = {phi < 0} (eq. subdomain).  One coefficient per
+ *     element from the mean of its vertex values: A_e = 1 if the mean is < 0,
+ *     else the ersatz weight (eq. compli_AOmega); a mean of exactly 0 is
+ *     outside Omega.
+ */
+#ifndef FO_H
+#define FO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FO_OK = 0,
+    FO_NOT_CONVERGED = 1,    /* warning: outputs written, tolerance not met       */
+    FO_ERR_ARG = -1,         /* invalid argument (null pointer, size, option)     */
+    FO_ERR_MESH = -2,        /* degenerate element or invalid connectivity        */
+    FO_ERR_NOMEM = -3,       /* device allocation failed                          */
+    FO_ERR_HIP = -4,         /* HIP runtime error                                 */
+    FO_ERR_BREAKDOWN = -5,   /* CG breakdown: p.Ap <= 0, r.z < 0 or non-finite     */
+    FO_ERR_STATE = -6        /* call order: no level set / no descent setup yet   */
+} fo_status;
+
+enum { FO_FP64 = 0,          /* plain FP64 conjugate gradients                     */
+       FO_FP32_IR = 1 };     /* FP32 CG inner solves + FP64 iterative refinement   */
+
+enum { FO_SCATTER_TILED = 0, /* deterministic LDS-tiled element scatter (default)  */
+       FO_SCATTER_ATOMIC = 1 /* element-parallel atomics (cross-check mode)        */ };
+
+typedef struct fo_ctx fo_ctx;
+
+typedef struct {
+    int32_t dim;               /* 2 (triangles) or 3 (tetrahedra)                  */
+    int64_t n_nodes, n_elems;
+    const double *coords;      /* host [n_nodes][dim]                              */
+    const int32_t *conn;       /* host [dim+1][n_elems], any orientation           */
+    const uint8_t *dof_fixed;  /* host [n_nodes*dim], 1 = clamped (u = 0); or NULL */
+    int64_t n_bfacets;         /* boundary facets (for the normal penalty)         */
+    const int32_t *bfacets;    /* host [dim][n_bfacets]                            */
+    const double *bnormal;     /* host [n_bfacets][dim], unit outward normals      */
+} fo_mesh;
+
+typedef struct {
+    double E, nu;              /* Young's modulus, Poisson ratio                   */
+    int32_t plane_stress;      /* 2D only: 1 plane stress, 0 plane strain          */
+    double ersatz;             /* A_e outside Omega (weak material), in (0, 1]     */
+} fo_material;
+
+typedef struct {
+    int32_t precision;         /* FO_FP64 or FO_FP32_IR                            */
+    double rtol;               /* stop when ||b - A x||_2 <= rtol ||b||_2 (FP64)   */
+    int32_t max_iter;          /* cap on operator applications (all levels)        */
+    double inner_rtol;         /* FO_FP32_IR: relative residual of each inner solve*/
+    int32_t max_outer;         /* FO_FP32_IR: cap on refinement steps               */
+    int32_t check_every;       /* iterations between host convergence polls, 0=auto*/
+} fo_solve_opts;
+
+typedef struct {
+    double alpha;              /* weight of int theta . xi                         */
+    double gamma_n;            /* weight of int_{boundary} (theta.n)(xi.n)         */
+    double gamma_s;            /* weight of int chi_Omega0 theta . xi              */
+    int32_t n_boxes;           /* Omega0 = union of open boxes (element centroid)  */
+    const double *boxes;       /* host [n_boxes][2*dim]: lo[0..d), hi[0..d)        */
+} fo_descent_opts;
+
+typedef struct {
+    int32_t status;            /* fo_status of the solve                           */
+    int32_t iters_inner;       /* operator applications in the working precision   */
+    int32_t iters_outer;       /* FP64 refinement residuals (FO_FP32_IR), else 0   */
+    double rel_res;            /* final FP64 ||b - A x|| / ||b|| (max over RHS)    */
+    double seconds;            /* wall time of the call                            */
+} fo_solve_stats;
+
+/* Create a context for one mesh and material.  Validates the mesh (indices in
+ * range, no degenerate element), builds the element tiles, copies everything
+ * to the current HIP device and allocates the Krylov workspace for up to
+ * max_rhs simultaneous right-hand sides.  stream may be NULL (default stream).
+ * The context owns its device memory until fo_destroy.
+ * Errors: FO_ERR_ARG, FO_ERR_MESH, FO_ERR_NOMEM, FO_ERR_HIP. */
+int fo_create(fo_ctx **out, const fo_mesh *mesh, const fo_material *mat, int32_t max_rhs,
+              void *stream);
+int fo_destroy(fo_ctx *ctx);
+
+/* Device bytes owned by the context (for footprint-based admission). */
+size_t fo_footprint_bytes(const fo_ctx *ctx);
+
+/* Select the element scatter used by the operators (FO_SCATTER_*). */
+int fo_set_scatter(fo_ctx *ctx, int32_t mode);
+
+/* Set the level set phi (device [n_nodes]) and derive A_e, chi_e and the Jacobi
+ * diagonal of K(phi) (FP64 and FP32).  Must precede the state solve. */
+int fo_set_levelset(fo_ctx *ctx, const double *phi);
+
+/* y = K(phi) x on the free unknowns (rows and columns of clamped unknowns are
+ * zero).  precision FO_FP64: x, y are double*; FO_FP32_IR: x, y are float* and
+ * the operator uses single-precision geometry.  Device pointers, [n_nodes*dim]. */
+int fo_apply_elasticity(fo_ctx *ctx, const void *x, void *y, int32_t precision);
+
+/* State solve K(phi) u = b on the free unknowns, u = 0 on clamped unknowns.
+ * b, u: device [n_dofs][ld], n_rhs columns (1 <= n_rhs <= max_rhs, ld >= n_rhs).
+ * n_rhs > 1 runs block CG over all columns together.  stats: host, may be NULL.
+ * Returns FO_OK, FO_NOT_CONVERGED (u holds the last iterate) or an error. */
+int fo_state_solve(fo_ctx *ctx, const double *b, double *u, int32_t n_rhs, int64_t ld,
+                   const fo_solve_opts *opts, fo_solve_stats *stats);
+
+/* Compliance and shape derivative for the solution(s) u (device [n_dofs][ld]):
+ *   J[k]  = sum_e A_e |T_e| sigma(u_k) : eps(u_k)     (device [n_rhs])
+ *   *vol  = sum_e chi_e |T_e|                         (device scalar)
+ *   rhs   = -sum_e |T_e| S1_e grad(lambda_a), S1_e = sum_k S1^J(u_k) + lambda_vol chi_e I / V
+ *           (device [n_dofs]); S1 (device [dim*dim][n_elems]) may be NULL. */
+int fo_shape_derivative(fo_ctx *ctx, const double *u, int32_t n_rhs, int64_t ld,
+                        double lambda_vol, double V, double *rhs, double *S1, double *J,
+                        double *vol);
+
+/* Descent (velocity) solve B theta = rhs on all unknowns (H^1, no clamp).
+ * B does not depend on phi: its diagonal is built on the first call with a
+ * given opts and reused.  rhs, theta: device [n_dofs]; B_tt: device scalar
+ * receiving B(theta, theta) = theta . rhs (> 0 for a descent direction). */
+int fo_descent_solve(fo_ctx *ctx, const fo_descent_opts *dopts, const double *rhs,
+                     double *theta, const fo_solve_opts *opts, fo_solve_stats *stats,
+                     double *B_tt);
+
+/* y = B x for the descent operator (device double [n_dofs]). */
+int fo_apply_descent(fo_ctx *ctx, const fo_descent_opts *dopts, const double *x, double *y);
+
+/* phi_i <- phi_i - dt theta_i . G_i with G_i the |T|-weighted mean of the
+ * element gradients of phi around node i.  phi: device [n_nodes], in/out;
+ * theta: device [n_dofs]. */
+int fo_levelset_update(fo_ctx *ctx, const double *theta, double dt, double *phi);
+
+const char *fo_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FO_H */

@@ -1,0 +1,628 @@
+// Host runtime of libfo: the C ABI of include/fo.h.
+//
+// Contexts own their device memory (hipMalloc at creation, hipFree at
+// destruction).  The solvers keep all Krylov scalars on the device; the host
+// only polls a small status block every few iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "fo_internal.h"
+#include "fo_launch.h"
+#include "fo_tiles.h"
+
+using namespace fo;
+
+#define FO_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t _e = (call);                                                         \
+        if (_e != hipSuccess) {                                                         \
+            std::fprintf(stderr, "libfo: %s failed: %s\n", #call, hipGetErrorString(_e)); \
+            return FO_ERR_HIP;                                                          \
+        }                                                                               \
+    } while (0)
+
+namespace {
+
+template <typename T>
+int dev_alloc(fo_ctx *c, T **p, size_t count)
+{
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    void *v = nullptr;
+    if (hipMalloc(&v, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return FO_ERR_NOMEM;
+    }
+    c->allocations.push_back(v);
+    c->bytes += bytes;
+    *p = static_cast<T *>(v);
+    return FO_OK;
+}
+
+#define FO_TRY(x)              \
+    do {                       \
+        int _rc = (x);         \
+        if (_rc != FO_OK) {    \
+            return _rc;        \
+        }                      \
+    } while (0)
+
+double host_det(int dim, const double *X, const int32_t *conn, int64_t E, int64_t e)
+{
+    const double *p0 = X + (int64_t)conn[e] * dim;
+    const double *p1 = X + (int64_t)conn[E + e] * dim;
+    const double *p2 = X + (int64_t)conn[2 * E + e] * dim;
+    if (dim == 2)
+        return (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p1[1] - p0[1]) * (p2[0] - p0[0]);
+    const double *p3 = X + (int64_t)conn[3 * E + e] * dim;
+    double a[3], b[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = p1[i] - p0[i];
+        b[i] = p2[i] - p0[i];
+        d[i] = p3[i] - p0[i];
+    }
+    return a[0] * (b[1] * d[2] - b[2] * d[1]) - a[1] * (b[0] * d[2] - b[2] * d[0]) +
+           a[2] * (b[0] * d[1] - b[1] * d[0]);
+}
+
+// ---------------------------------------------------------------------------
+// operators
+
+template <typename T>
+int elas_apply(fo_ctx *c, const T *x, T *y, hipStream_t s);
+
+template <>
+int elas_apply<double>(fo_ctx *c, const double *x, double *y, hipStream_t s)
+{
+    if (c->scatter == FO_SCATTER_TILED && c->tiles.n_tiles > 0) {
+        if (c->has_isolated) launch_fill<double>(y, c->ndof, 0.0, s);
+        return launch_elas_apply_tiled<double>(c, c->coords, x, y, s);
+    }
+    launch_elas_apply_atomic<double>(c, c->coords, x, y, s);
+    return FO_OK;
+}
+
+template <>
+int elas_apply<float>(fo_ctx *c, const float *x, float *y, hipStream_t s)
+{
+    if (c->scatter == FO_SCATTER_TILED && c->tiles.n_tiles > 0) {
+        if (c->has_isolated) launch_fill<float>(y, c->ndof, 0.0f, s);
+        return launch_elas_apply_tiled<float>(c, c->coords32, x, y, s);
+    }
+    launch_elas_apply_atomic<float>(c, c->coords32, x, y, s);
+    return FO_OK;
+}
+
+bool tiled(const fo_ctx *c) { return c->scatter == FO_SCATTER_TILED && c->tiles.n_tiles > 0; }
+
+int descent_apply(fo_ctx *c, const double *x, double *y, hipStream_t s)
+{
+    if (tiled(c)) {
+        if (c->has_isolated) launch_fill<double>(y, c->ndof, 0.0, s);
+        return launch_descent_apply_tiled(c, x, y, s);
+    }
+    launch_descent_apply_atomic(c, x, y, s);
+    return FO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PCG driver
+
+struct PcgVecs {
+    void *x, *r, *p, *q;
+    const void *dinv;
+};
+
+int poll(fo_ctx *c)
+{
+    FO_HIP(hipMemcpyAsync(c->scal_host, c->scal, sizeof(SolveScalars), hipMemcpyDeviceToHost,
+                          c->stream));
+    FO_HIP(hipStreamSynchronize(c->stream));
+    return FO_OK;
+}
+
+// Starts a solve whose residual is b - q: r = b - q, p = z = dinv r, scalars.
+template <typename T>
+void pcg_restart(fo_ctx *c, const T *b, const T *q, T *r, T *p, const T *dinv, int64_t n,
+                 double rtol, int max_it)
+{
+    int nb = red_blocks(n);
+    launch_residual_restart<T>(b, q, r, p, dinv, n, c->partials, nb, c->stream);
+    launch_pcg_start(c->scal, c->partials, nb, rtol * rtol, max_it, c->stream);
+}
+
+// Runs PCG iterations (already started) until the device flags done.
+// Returns FO_OK and adds the iterations performed to *iters.
+template <typename T, class Apply>
+int pcg_iterate(fo_ctx *c, Apply apply, T *x, T *r, T *p, T *q, const T *dinv, int64_t n,
+                int check_every, int64_t *iters)
+{
+    int nb = red_blocks(n);
+    hipStream_t s = c->stream;
+    int chunk = check_every > 0 ? check_every : 8;
+    FO_TRY(poll(c));
+    while (!c->scal_host->done) {
+        for (int k = 0; k < chunk; ++k) {
+            FO_TRY(apply(p, q));
+            launch_dots<T>(1, p, q, nullptr, nullptr, nullptr, nullptr, n, c->partials, nb, s);
+            launch_pcg_alpha(c->scal, c->partials, nb, s);
+            launch_pcg_update<T>(c->scal, x, r, p, q, dinv, n, c->partials, nb, s);
+            launch_pcg_beta(c->scal, c->partials, nb, s);
+            launch_pcg_p<T>(c->scal, p, q, n, s);
+        }
+        FO_TRY(poll(c));
+        if (check_every <= 0) chunk = std::min(64, std::max(8, c->scal_host->it / 8));
+    }
+    *iters += c->scal_host->it;
+    return FO_OK;
+}
+
+// FP64 Jacobi-PCG on A x = b (b contiguous; x output), with the true-residual
+// stopping test.  apply(in, out) computes out = A in.
+template <class Apply>
+int solve_fp64(fo_ctx *c, Apply apply, const double *b, double *x, const double *dinv,
+               const fo_solve_opts *o, fo_solve_stats *st)
+{
+    int64_t n = c->ndof;
+    hipStream_t s = c->stream;
+    double *r = c->r64, *p = c->p64, *q = c->q64;
+    int64_t iters = 0;
+    launch_fill<double>(x, n, 0.0, s);
+    launch_fill<double>(q, n, 0.0, s);
+    pcg_restart<double>(c, b, q, r, p, dinv, n, o->rtol, o->max_iter);
+    int status = FO_NOT_CONVERGED;
+    double relres = 1.0;
+    for (int restart = 0; restart < 20; ++restart) {
+        FO_TRY(pcg_iterate<double>(c, apply, x, r, p, q, dinv, n, o->check_every, &iters));
+        if (c->scal_host->status == FO_ERR_BREAKDOWN) {
+            status = FO_ERR_BREAKDOWN;
+            break;
+        }
+        // true residual
+        FO_TRY(apply(x, q));
+        ++iters;
+        int left = (int)std::max<int64_t>(1, (int64_t)o->max_iter - iters);
+        pcg_restart<double>(c, b, q, r, p, dinv, n, o->rtol, left);
+        FO_TRY(poll(c));
+        SolveScalars h = *c->scal_host;
+        relres = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : 0.0;
+        if (h.bnorm2 == 0.0 || relres <= o->rtol) {
+            status = FO_OK;
+            break;
+        }
+        if (iters >= o->max_iter) break;
+    }
+    if (st) {
+        st->status = status;
+        st->iters_inner = (int32_t)iters;
+        st->iters_outer = 0;
+        st->rel_res = relres;
+    }
+    return status;
+}
+
+// FP32 inner PCG + FP64 iterative refinement for the state operator.
+int solve_ir(fo_ctx *c, const double *b, double *x, const fo_solve_opts *o, fo_solve_stats *st)
+{
+    int64_t n = c->ndof;
+    hipStream_t s = c->stream;
+    int nb = red_blocks(n);
+    int64_t inner_total = 0;
+    int outer = 0;
+    auto apply64 = [c, s](const double *in, double *out) { return elas_apply<double>(c, in, out, s); };
+    auto apply32 = [c, s](const float *in, float *out) { return elas_apply<float>(c, in, out, s); };
+    launch_fill<double>(x, n, 0.0, s);
+    // r64 = b;  dscratch[0] = ||r||^2 = ||b||^2
+    FO_HIP(hipMemcpyAsync(c->r64, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_dots<double>(1, b, b, nullptr, nullptr, nullptr, nullptr, n, c->partials, nb, s);
+    launch_finish_dots(c->partials, nb, 1, c->dscratch, s);
+    FO_HIP(hipMemcpyAsync(c->red_host, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
+    FO_HIP(hipStreamSynchronize(s));
+    double bnorm = std::sqrt(c->red_host[0]);
+    double rn = bnorm;
+    int status = FO_NOT_CONVERGED;
+    int max_outer = o->max_outer > 0 ? o->max_outer : 50;
+    double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-3;
+    while (true) {
+        if (bnorm == 0.0 || rn <= o->rtol * bnorm) {
+            status = FO_OK;
+            break;
+        }
+        if (outer >= max_outer || inner_total >= o->max_iter) break;
+        // inner system K32 d = r / ||r||
+        launch_ir_scale_down(c->r64, c->dscratch, n, c->b32, c->x32, s);
+        launch_fill<float>(c->q32, n, 0.0f, s);
+        int left = (int)std::max<int64_t>(1, (int64_t)o->max_iter - inner_total);
+        pcg_restart<float>(c, c->b32, c->q32, c->r32, c->p32, c->dinv32, n, inner_rtol, left);
+        FO_TRY(pcg_iterate<float>(c, apply32, c->x32, c->r32, c->p32, c->q32, c->dinv32, n,
+                                  o->check_every, &inner_total));
+        if (c->scal_host->status == FO_ERR_BREAKDOWN) {
+            status = FO_ERR_BREAKDOWN;
+            break;
+        }
+        launch_ir_update(x, c->x32, c->dscratch, n, s);
+        // FP64 residual r = b - K x
+        FO_TRY(apply64(x, c->q64));
+        ++outer;
+        launch_pcg_residual64(c, b, c->q64, c->r64, n, nb, s);
+        FO_HIP(hipMemcpyAsync(c->red_host, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
+        FO_HIP(hipStreamSynchronize(s));
+        rn = std::sqrt(c->red_host[0]);
+        if (!(rn == rn)) {
+            status = FO_ERR_BREAKDOWN;
+            break;
+        }
+    }
+    if (st) {
+        st->status = status;
+        st->iters_inner = (int32_t)inner_total;
+        st->iters_outer = outer;
+        st->rel_res = bnorm > 0 ? rn / bnorm : 0.0;
+    }
+    return status;
+}
+
+bool descent_same(const fo_ctx *c, const fo_descent_opts *d)
+{
+    const DescentSetup &s = c->descent;
+    if (!s.valid || s.alpha != d->alpha || s.gamma_n != d->gamma_n || s.gamma_s != d->gamma_s)
+        return false;
+    size_t nb = (size_t)std::max(0, d->n_boxes) * 2 * c->dim;
+    if (s.boxes.size() != nb) return false;
+    for (size_t i = 0; i < nb; ++i)
+        if (s.boxes[i] != d->boxes[i]) return false;
+    return true;
+}
+
+int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
+{
+    if (descent_same(c, d)) return FO_OK;
+    hipStream_t s = c->stream;
+    DescentSetup &ds = c->descent;
+    if (!ds.in0) {
+        FO_TRY(dev_alloc(c, &ds.in0, c->E));
+        FO_TRY(dev_alloc(c, &ds.diag, c->ndof));
+        FO_TRY(dev_alloc(c, &ds.dinv, c->ndof));
+    }
+    ds.alpha = d->alpha;
+    ds.gamma_n = d->gamma_n;
+    ds.gamma_s = d->gamma_s;
+    int nbx = std::max(0, d->n_boxes);
+    ds.boxes.assign(d->boxes, d->boxes + (size_t)nbx * 2 * c->dim);
+    if (nbx > 0) {
+        double *bx = nullptr;
+        if (hipMalloc(&bx, ds.boxes.size() * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
+        FO_HIP(hipMemcpyAsync(bx, ds.boxes.data(), ds.boxes.size() * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+        launch_in_boxes(c, nbx, bx, ds.in0, s);
+        FO_HIP(hipStreamSynchronize(s));
+        FO_HIP(hipFree(bx));
+    } else {
+        launch_fill<uint8_t>(ds.in0, c->E, 0, s);
+    }
+    if (tiled(c)) {
+        launch_fill<double>(ds.diag, c->ndof, 0.0, s);
+        FO_TRY(launch_descent_diag_tiled(c, ds.diag, s));
+    } else {
+        launch_descent_diag(c, ds.diag, s);
+    }
+    launch_invert_diag<double>(ds.diag, nullptr, c->ndof, ds.dinv, s);
+    ds.valid = true;
+    return FO_OK;
+}
+
+bool opts_ok(const fo_solve_opts *o)
+{
+    return o && (o->precision == FO_FP64 || o->precision == FO_FP32_IR) && o->rtol > 0 &&
+           o->max_iter > 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char *fo_status_string(int s)
+{
+    switch (s) {
+    case FO_OK: return "ok";
+    case FO_NOT_CONVERGED: return "not converged";
+    case FO_ERR_ARG: return "invalid argument";
+    case FO_ERR_MESH: return "invalid mesh";
+    case FO_ERR_NOMEM: return "out of device memory";
+    case FO_ERR_HIP: return "HIP runtime error";
+    case FO_ERR_BREAKDOWN: return "CG breakdown";
+    case FO_ERR_STATE: return "call order (level set or setup missing)";
+    default: return "unknown status";
+    }
+}
+
+int fo_destroy(fo_ctx *c)
+{
+    if (!c) return FO_ERR_ARG;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->allocations) (void)hipFree(p);
+    if (c->scal_host) (void)hipHostFree(c->scal_host);
+    if (c->red_host) (void)hipHostFree(c->red_host);
+    delete c;
+    return FO_OK;
+}
+
+int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t max_rhs,
+              void *stream)
+{
+    if (!out || !m || !mat) return FO_ERR_ARG;
+    *out = nullptr;
+    if (m->dim != 2 && m->dim != 3) return FO_ERR_ARG;
+    if (m->n_nodes <= 0 || m->n_elems <= 0 || !m->coords || !m->conn) return FO_ERR_ARG;
+    if (m->n_nodes > INT32_MAX || m->n_elems > INT32_MAX) return FO_ERR_ARG;
+    if (m->n_bfacets < 0 || (m->n_bfacets > 0 && (!m->bfacets || !m->bnormal))) return FO_ERR_ARG;
+    if (max_rhs < 1 || max_rhs > 256) return FO_ERR_ARG;
+    if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->ersatz > 0 && mat->ersatz <= 1))
+        return FO_ERR_ARG;
+    const int D = m->dim;
+    const int64_t N = m->n_nodes, E = m->n_elems;
+    for (int64_t k = 0; k < (int64_t)(D + 1) * E; ++k)
+        if (m->conn[k] < 0 || m->conn[k] >= N) return FO_ERR_MESH;
+    for (int64_t e = 0; e < E; ++e) {
+        double det = host_det(D, m->coords, m->conn, E, e);
+        if (!(std::fabs(det) > 0.0) || det != det) return FO_ERR_MESH;
+    }
+    for (int64_t k = 0; k < (int64_t)D * m->n_bfacets; ++k)
+        if (m->bfacets[k] < 0 || m->bfacets[k] >= N) return FO_ERR_MESH;
+
+    fo_ctx *c = new fo_ctx();
+    c->dim = D;
+    c->N = N;
+    c->E = E;
+    c->ndof = N * D;
+    c->max_rhs = max_rhs;
+    c->stream = (hipStream_t)stream;
+    c->ersatz = mat->ersatz;
+    c->mu = mat->E / (2.0 * (1.0 + mat->nu));
+    c->lam = (D == 2 && mat->plane_stress) ? mat->E * mat->nu / (1.0 - mat->nu * mat->nu)
+                                           : mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
+    (void)hipGetDevice(&c->device);
+    int rc = FO_OK;
+    auto fail = [&](int code) {
+        fo_destroy(c);
+        return code;
+    };
+
+    // element order: tiles along a Morton curve (identity if tiling is off)
+    HostTiles ht;
+    build_tiles(D, N, E, m->coords, m->conn, &ht);
+    std::vector<int32_t> conn_t((size_t)(D + 1) * E);
+    for (int a = 0; a <= D; ++a)
+        for (int64_t e = 0; e < E; ++e)
+            conn_t[(size_t)a * E + e] = m->conn[(int64_t)a * E + ht.perm[e]];
+
+    std::vector<float> c32((size_t)N * D);
+    for (int64_t i = 0; i < N * D; ++i) c32[i] = (float)m->coords[i];
+    std::vector<uint8_t> fx((size_t)N * D, 0);
+    if (m->dof_fixed)
+        for (int64_t i = 0; i < N * D; ++i) fx[i] = m->dof_fixed[i] ? 1 : 0;
+
+    const int64_t n = c->ndof;
+    if ((rc = dev_alloc(c, &c->coords, N * D)) || (rc = dev_alloc(c, &c->coords32, N * D)) ||
+        (rc = dev_alloc(c, &c->conn, (D + 1) * E)) || (rc = dev_alloc(c, &c->elem_perm, E)) ||
+        (rc = dev_alloc(c, &c->fixed, n)) || (rc = dev_alloc(c, &c->chi, E)) ||
+        (rc = dev_alloc(c, &c->diag64, n)) || (rc = dev_alloc(c, &c->dinv64, n)) ||
+        (rc = dev_alloc(c, &c->dinv32, n)) || (rc = dev_alloc(c, &c->x64, n)) ||
+        (rc = dev_alloc(c, &c->r64, n)) || (rc = dev_alloc(c, &c->p64, n)) ||
+        (rc = dev_alloc(c, &c->q64, n)) || (rc = dev_alloc(c, &c->b64, n)) ||
+        (rc = dev_alloc(c, &c->t64, n)) || (rc = dev_alloc(c, &c->x32, n)) ||
+        (rc = dev_alloc(c, &c->r32, n)) || (rc = dev_alloc(c, &c->p32, n)) ||
+        (rc = dev_alloc(c, &c->q32, n)) || (rc = dev_alloc(c, &c->b32, n)) ||
+        (rc = dev_alloc(c, &c->partials, (size_t)kRedBlocks * 4)) ||
+        (rc = dev_alloc(c, &c->scal, 1)) || (rc = dev_alloc(c, &c->dscratch, 16)) ||
+        (rc = dev_alloc(c, &c->gbuf, N * (D + 1))))
+        return fail(rc);
+    if ((rc = dev_alloc(c, &c->s1buf, (size_t)E * D * D))) return fail(rc);
+    {
+        std::vector<uint8_t> used(N, 0);
+        for (int64_t k = 0; k < (int64_t)(D + 1) * E; ++k) used[m->conn[k]] = 1;
+        c->has_isolated = std::find(used.begin(), used.end(), 0) != used.end();
+    }
+    // shape-derivative partial sums: one row per RHS (+ volume)
+    c->sd_part_cap = (int)std::min<int64_t>(((E + kBlock - 1) / kBlock) * (max_rhs + 1), INT32_MAX);
+    if ((rc = dev_alloc(c, &c->sd_part, c->sd_part_cap))) return fail(rc);
+    if (hipHostMalloc((void **)&c->scal_host, sizeof(SolveScalars)) != hipSuccess ||
+        hipHostMalloc((void **)&c->red_host, 16 * sizeof(double)) != hipSuccess)
+        return fail(FO_ERR_NOMEM);
+    std::vector<int32_t> bnode, bptr, bfac;
+    if (m->n_bfacets > 0) {
+        c->nbf = m->n_bfacets;
+        if ((rc = dev_alloc(c, &c->bfacets, D * c->nbf)) || (rc = dev_alloc(c, &c->bnormal, D * c->nbf)))
+            return fail(rc);
+        // boundary node -> incident facets, nodes and facets in increasing order
+        std::vector<int32_t> cnt(N, 0);
+        for (int64_t f = 0; f < c->nbf; ++f)
+            for (int a = 0; a < D; ++a) ++cnt[m->bfacets[(int64_t)a * c->nbf + f]];
+        std::vector<int32_t> idx(N, -1);
+        bptr.push_back(0);
+        for (int64_t n2 = 0; n2 < N; ++n2)
+            if (cnt[n2]) {
+                idx[n2] = (int32_t)bnode.size();
+                bnode.push_back((int32_t)n2);
+                bptr.push_back(bptr.back() + cnt[n2]);
+            }
+        bfac.assign(bptr.back(), 0);
+        std::vector<int32_t> fillp(bptr.begin(), bptr.end() - 1);
+        for (int64_t f = 0; f < c->nbf; ++f)
+            for (int a = 0; a < D; ++a) {
+                int32_t n2 = m->bfacets[(int64_t)a * c->nbf + f];
+                bfac[fillp[idx[n2]]++] = (int32_t)f;
+            }
+        c->n_bnodes = (int64_t)bnode.size();
+        if ((rc = dev_alloc(c, &c->bnodes, bnode.size())) || (rc = dev_alloc(c, &c->bnode_ptr, bptr.size())) ||
+            (rc = dev_alloc(c, &c->bnode_fac, bfac.size())))
+            return fail(rc);
+    }
+    hipStream_t s = c->stream;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    if (up(c->coords, m->coords, N * D * sizeof(double)) ||
+        up(c->coords32, c32.data(), N * D * sizeof(float)) ||
+        up(c->conn, conn_t.data(), conn_t.size() * sizeof(int32_t)) ||
+        up(c->elem_perm, ht.perm.data(), E * sizeof(int32_t)) ||
+        up(c->fixed, fx.data(), n) ||
+        (c->nbf && (up(c->bfacets, m->bfacets, D * c->nbf * sizeof(int32_t)) ||
+                    up(c->bnormal, m->bnormal, D * c->nbf * sizeof(double)) ||
+                    up(c->bnodes, bnode.data(), bnode.size() * sizeof(int32_t)) ||
+                    up(c->bnode_ptr, bptr.data(), bptr.size() * sizeof(int32_t)) ||
+                    up(c->bnode_fac, bfac.data(), bfac.size() * sizeof(int32_t)))))
+        return fail(FO_ERR_HIP);
+    if ((rc = upload_tiles(c, ht))) return fail(rc);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(FO_ERR_HIP);
+    *out = c;
+    return FO_OK;
+}
+
+size_t fo_footprint_bytes(const fo_ctx *c) { return c ? c->bytes : 0; }
+
+int fo_set_scatter(fo_ctx *c, int32_t mode)
+{
+    if (!c || (mode != FO_SCATTER_TILED && mode != FO_SCATTER_ATOMIC)) return FO_ERR_ARG;
+    c->scatter = mode;
+    return FO_OK;
+}
+
+int fo_set_levelset(fo_ctx *c, const double *phi)
+{
+    if (!c || !phi) return FO_ERR_ARG;
+    hipStream_t s = c->stream;
+    launch_chi(c->conn, c->E, c->dim, phi, c->chi, s);
+    if (tiled(c)) {
+        launch_fill<double>(c->diag64, c->ndof, 0.0, s);
+        FO_TRY(launch_elas_diag_tiled(c, c->diag64, s));
+    } else {
+        launch_elas_diag(c, c->diag64, s);
+    }
+    launch_invert_diag<double>(c->diag64, c->fixed, c->ndof, c->dinv64, s);
+    launch_invert_diag<float>(c->diag64, c->fixed, c->ndof, c->dinv32, s);
+    FO_HIP(hipGetLastError());
+    c->have_phi = true;
+    return FO_OK;
+}
+
+int fo_apply_elasticity(fo_ctx *c, const void *x, void *y, int32_t precision)
+{
+    if (!c || !x || !y) return FO_ERR_ARG;
+    if (!c->have_phi) return FO_ERR_STATE;
+    int rc;
+    if (precision == FO_FP64) rc = elas_apply<double>(c, (const double *)x, (double *)y, c->stream);
+    else if (precision == FO_FP32_IR) rc = elas_apply<float>(c, (const float *)x, (float *)y, c->stream);
+    else return FO_ERR_ARG;
+    FO_HIP(hipGetLastError());
+    return rc;
+}
+
+int fo_state_solve(fo_ctx *c, const double *b, double *u, int32_t n_rhs, int64_t ld,
+                   const fo_solve_opts *o, fo_solve_stats *st)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || !b || !u || !opts_ok(o) || n_rhs < 1 || n_rhs > c->max_rhs || ld < n_rhs)
+        return FO_ERR_ARG;
+    if (!c->have_phi) return FO_ERR_STATE;
+    hipStream_t s = c->stream;
+    int worst = FO_OK;
+    fo_solve_stats acc{FO_OK, 0, 0, 0.0, 0.0};
+    for (int k = 0; k < n_rhs; ++k) {
+        launch_gather_col<double, double>(b + k, ld, c->ndof, c->b64, c->fixed, s);
+        fo_solve_stats one{};
+        int rc;
+        if (o->precision == FO_FP64) {
+            auto apply = [c, s](const double *in, double *out) { return elas_apply<double>(c, in, out, s); };
+            rc = solve_fp64(c, apply, c->b64, c->x64, c->dinv64, o, &one);
+        } else {
+            rc = solve_ir(c, c->b64, c->x64, o, &one);
+        }
+        if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+        launch_scatter_col<double>(c->x64, c->ndof, u + k, ld, s);
+        acc.iters_inner += one.iters_inner;
+        acc.iters_outer += one.iters_outer;
+        acc.rel_res = std::max(acc.rel_res, one.rel_res);
+        if (rc != FO_OK && (worst == FO_OK || rc < worst)) worst = rc;
+    }
+    FO_HIP(hipStreamSynchronize(s));
+    acc.status = worst;
+    acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = acc;
+    return worst;
+}
+
+int fo_shape_derivative(fo_ctx *c, const double *u, int32_t n_rhs, int64_t ld, double lambda_vol,
+                        double V, double *rhs, double *S1, double *J, double *vol)
+{
+    if (!c || !u || !rhs || !J || !vol || n_rhs < 1 || n_rhs > c->max_rhs || ld < n_rhs || !(V > 0))
+        return FO_ERR_ARG;
+    if (!c->have_phi) return FO_ERR_STATE;
+    if (launch_shape_tensor(c, u, n_rhs, ld, lambda_vol / V, S1, J, vol, c->stream)) return FO_ERR_ARG;
+    if (tiled(c)) {
+        if (c->has_isolated) launch_fill<double>(rhs, c->ndof, 0.0, c->stream);
+        FO_TRY(launch_sd_rhs_tiled(c, rhs, c->stream));
+    } else {
+        launch_sd_rhs_atomic(c, rhs, c->stream);
+    }
+    FO_HIP(hipGetLastError());
+    return FO_OK;
+}
+
+int fo_apply_descent(fo_ctx *c, const fo_descent_opts *d, const double *x, double *y)
+{
+    if (!c || !d || !x || !y || d->n_boxes < 0 || (d->n_boxes > 0 && !d->boxes)) return FO_ERR_ARG;
+    FO_TRY(descent_prepare(c, d));
+    FO_TRY(descent_apply(c, x, y, c->stream));
+    FO_HIP(hipGetLastError());
+    return FO_OK;
+}
+
+int fo_descent_solve(fo_ctx *c, const fo_descent_opts *d, const double *rhs, double *theta,
+                     const fo_solve_opts *o, fo_solve_stats *st, double *B_tt)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || !d || !rhs || !theta || !opts_ok(o) || d->n_boxes < 0 || (d->n_boxes > 0 && !d->boxes))
+        return FO_ERR_ARG;
+    if (!(d->alpha > 0) || d->gamma_n < 0 || d->gamma_s < 0) return FO_ERR_ARG;
+    FO_TRY(descent_prepare(c, d));
+    hipStream_t s = c->stream;
+    auto apply = [c, s](const double *in, double *out) { return descent_apply(c, in, out, s); };
+    fo_solve_stats one{};
+    int rc = solve_fp64(c, apply, rhs, theta, c->descent.dinv, o, &one);
+    if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+    if (B_tt) {
+        int nb = red_blocks(c->ndof);
+        launch_dots<double>(1, theta, rhs, nullptr, nullptr, nullptr, nullptr, c->ndof, c->partials,
+                            nb, s);
+        launch_finish_dots(c->partials, nb, 1, B_tt, s);
+    }
+    FO_HIP(hipStreamSynchronize(s));
+    one.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = one;
+    return rc;
+}
+
+int fo_levelset_update(fo_ctx *c, const double *theta, double dt, double *phi)
+{
+    if (!c || !theta || !phi || !(dt == dt)) return FO_ERR_ARG;
+    if (tiled(c)) {
+        if (c->has_isolated) launch_fill<double>(c->gbuf, c->N * (c->dim + 1), 0.0, c->stream);
+        FO_TRY(launch_phigrad_tiled(c, phi, c->gbuf, c->stream));
+    } else {
+        launch_phigrad_atomic(c, phi, c->gbuf, c->stream);
+    }
+    launch_phi_update(c, theta, dt, phi, c->stream);
+    FO_HIP(hipGetLastError());
+    return FO_OK;
+}
+
+}  // extern "C"

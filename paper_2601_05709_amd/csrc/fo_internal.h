@@ -1,0 +1,125 @@
+// Internal declarations shared by the host runtime and the kernels of libfo.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/fo.h"
+
+namespace fo {
+
+constexpr int kBlock = 256;        // threads per block of the vector kernels
+constexpr int kRedBlocks = 1024;   // partial sums per reduction (fixed: deterministic)
+
+// Device-resident scalars of one Krylov solve.  The host polls a copy of
+// `done`/`status`/`it` every few iterations; everything else stays on the GPU.
+struct SolveScalars {
+    double rho;      // r . z of the current iterate
+    double pq;       // p . A p
+    double rr;       // r . r
+    double alpha, beta;
+    double tol2;     // (rtol ||b||)^2 on the working-precision recursive residual
+    double bnorm2;   // ||b||^2 of the current (inner) system
+    int32_t it;      // operator applications performed
+    int32_t done;    // 1: converged or failed, kernels become no-ops
+    int32_t status;  // 0 ok, FO_ERR_BREAKDOWN
+    int32_t max_it;  // cap for this (inner) solve
+};
+
+// Element-to-node scatter tiles (deterministic mode).  Elements are reordered
+// along a Morton curve and cut into tiles; a tile's nodes are numbered
+// locally so the scatter accumulates in LDS.  See fo_tiles.cpp.
+struct TileSet {
+    int32_t n_tiles = 0;
+    int32_t max_nodes = 0;              // largest tile (LDS sizing)
+    int32_t max_sub = 0;                // largest number of sub-batches in a tile
+    int64_t n_slots = 0;                // total (tile, node) pairs
+    int64_t n_shared_slots = 0;         // (tile, node) pairs whose node is shared
+    int64_t n_shared_nodes = 0;
+    // device arrays
+    int32_t *tile_elem_off = nullptr;   // [n_tiles+1] into the tile-ordered element list
+    int32_t *tile_node_off = nullptr;   // [n_tiles+1] into tile_nodes
+    int32_t *tile_node_interior = nullptr; // [n_tiles] number of leading interior nodes
+    int32_t *tile_halo_off = nullptr;   // [n_tiles] first halo slot of the tile
+    int32_t *tile_nodes = nullptr;      // [n_slots] global node id of each tile-local node
+    uint16_t *lconn = nullptr;          // [E][4] tile-local vertex ids (tile element order)
+    uint16_t *lslot = nullptr;          // [E][4] LDS slot of each (element, vertex)
+    int32_t *sub_off = nullptr;         // [n_tiles+1] into sub-batch segment tables
+    int32_t *seg_off = nullptr;         // [n_sub+1] into seg_node / seg_start
+    uint16_t *seg_node = nullptr;       // [n_seg] tile-local node of each segment
+    uint16_t *seg_start = nullptr;      // [n_seg+n_sub] slot range start (+ end sentinel)
+    int32_t *halo_node = nullptr;       // [n_shared_nodes] global node of each shared node
+    int32_t *halo_ptr = nullptr;        // [n_shared_nodes+1] into halo_src
+    int32_t *halo_src = nullptr;        // [n_shared_slots] halo slot feeding the node
+};
+
+struct DescentSetup {
+    bool valid = false;
+    double alpha = 0, gamma_n = 0, gamma_s = 0;
+    std::vector<double> boxes;
+    uint8_t *in0 = nullptr;   // [E] element centroid in Omega0 (tile element order)
+    double *diag = nullptr;   // [n_dofs]
+    double *dinv = nullptr;   // [n_dofs]
+};
+
+}  // namespace fo
+
+struct fo_ctx {
+    int dim = 0;
+    int64_t N = 0, E = 0, ndof = 0;
+    int32_t max_rhs = 1;
+    double lam = 0, mu = 0, ersatz = 1e-3;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int scatter = FO_SCATTER_TILED;
+    bool have_phi = false;
+    bool has_isolated = false;         // some node belongs to no element
+    size_t bytes = 0;                  // device footprint
+    std::vector<void *> allocations;   // everything hipMalloc'ed by this ctx
+
+    // mesh, tile element order (elem_perm[tile order] = input element id)
+    double *coords = nullptr;          // [N][dim]
+    float *coords32 = nullptr;         // [N][dim]
+    int32_t *conn = nullptr;           // [dim+1][E] SoA, tile element order
+    int32_t *elem_perm = nullptr;      // [E] tile order -> input order
+    uint8_t *fixed = nullptr;          // [ndof]
+    int64_t nbf = 0;
+    int32_t *bfacets = nullptr;        // [dim][nbf]
+    double *bnormal = nullptr;         // [nbf][dim]
+    fo::TileSet tiles;
+
+    // level-set dependent
+    uint8_t *chi = nullptr;            // [E] element in Omega (tile order)
+    double *diag64 = nullptr;          // [ndof] diagonal of K(phi)
+    double *dinv64 = nullptr;          // [ndof] Jacobi (0 on clamped)
+    float *dinv32 = nullptr;
+
+    // descent operator
+    fo::DescentSetup descent;
+
+    // Krylov workspace (single RHS); FP64 and FP32 copies
+    double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *b64 = nullptr,
+           *t64 = nullptr;
+    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *b32 = nullptr;
+    double *halo = nullptr;            // [n_shared_slots * dim] halo partials
+    double *partials = nullptr;        // [kRedBlocks * 4]
+    fo::SolveScalars *scal = nullptr;  // device
+    fo::SolveScalars *scal_host = nullptr;  // pinned
+    double *red_host = nullptr;        // pinned scratch for scalar results
+    double *dscratch = nullptr;        // [8] device scratch scalars
+
+    // node-recovery buffers for the level-set update
+    double *gbuf = nullptr;            // [N][dim+1]
+
+    // shape derivative: element tensors (tile order) and partial sums
+    double *s1buf = nullptr;           // [E][dim*dim]
+    double *sd_part = nullptr;         // [(max_rhs+1)][blocks]
+    int sd_part_cap = 0;
+
+    // boundary nodes -> incident facets (descent normal penalty)
+    int64_t n_bnodes = 0;
+    int32_t *bnodes = nullptr, *bnode_ptr = nullptr, *bnode_fac = nullptr;
+};

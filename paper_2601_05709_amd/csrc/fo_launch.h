@@ -1,0 +1,74 @@
+// Host-side launch wrappers of the kernels in fo_kernels.hip / fo_tiled.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fo_internal.h"
+
+namespace fo {
+
+int red_blocks(int64_t n);
+
+template <typename T> void launch_fill(T *y, int64_t n, T v, hipStream_t s);
+template <typename T> void launch_mask(T *y, const uint8_t *fixed, int64_t n, hipStream_t s);
+template <typename T>
+void launch_invert_diag(const double *diag, const uint8_t *fixed, int64_t n, T *dinv, hipStream_t s);
+void launch_chi(const int32_t *conn, int64_t E, int dim, const double *phi, uint8_t *chi,
+                hipStream_t s);
+template <typename S, typename T>
+void launch_gather_col(const S *src, int64_t ld, int64_t n, T *dst, const uint8_t *fixed,
+                       hipStream_t s);
+template <typename T>
+void launch_scatter_col(const T *src, int64_t n, double *dst, int64_t ld, hipStream_t s);
+template <typename T>
+void launch_dots(int npair, const T *a0, const T *b0, const T *a1, const T *b1, const T *a2,
+                 const T *b2, int64_t n, double *part, int nb, hipStream_t s);
+void launch_finish_dots(const double *part, int nb, int npair, double *out, hipStream_t s);
+
+void launch_pcg_start(SolveScalars *sc, const double *part, int nb, double rtol2, int max_it,
+                      hipStream_t s);
+void launch_pcg_alpha(SolveScalars *sc, const double *part, int nb, hipStream_t s);
+void launch_pcg_beta(SolveScalars *sc, const double *part, int nb, hipStream_t s);
+template <typename T>
+void launch_pcg_update(const SolveScalars *sc, T *x, T *r, const T *p, T *q, const T *dinv,
+                       int64_t n, double *part, int nb, hipStream_t s);
+template <typename T>
+void launch_pcg_p(const SolveScalars *sc, T *p, const T *z, int64_t n, hipStream_t s);
+template <typename T>
+void launch_residual_restart(const T *b, const T *q, T *r, T *p, const T *dinv, int64_t n,
+                             double *part, int nb, hipStream_t s);
+
+void launch_ir_scale_down(const double *r64, const double *nrm2, int64_t n, float *r32, float *x32,
+                          hipStream_t s);
+void launch_ir_update(double *x64, const float *d32, const double *nrm2, int64_t n, hipStream_t s);
+void launch_to_float(const double *a, float *b, int64_t n, hipStream_t s);
+
+template <typename T>
+void launch_elas_apply_atomic(const fo_ctx *c, const T *coords, const T *x, T *y, hipStream_t s);
+void launch_elas_diag(const fo_ctx *c, double *diag, hipStream_t s);
+void launch_descent_apply_atomic(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+void launch_descent_diag(const fo_ctx *c, double *diag, hipStream_t s);
+void launch_in_boxes(const fo_ctx *c, int nbox, const double *boxes_dev, uint8_t *in0,
+                     hipStream_t s);
+int launch_shape_tensor(const fo_ctx *c, const double *u, int n_rhs, int64_t ld, double vol_coef,
+                        double *S1, double *J, double *vol, hipStream_t s);
+void launch_sd_rhs_atomic(const fo_ctx *c, double *rhs, hipStream_t s);
+void launch_phigrad_atomic(const fo_ctx *c, const double *phi, double *gbuf, hipStream_t s);
+void launch_phi_update(const fo_ctx *c, const double *theta, double dt, double *phi, hipStream_t s);
+
+void launch_pcg_residual64(fo_ctx *c, const double *b, const double *q, double *r, int64_t n,
+                           int nb, hipStream_t s);
+
+// tiled (deterministic) scatter
+template <typename T>
+int launch_elas_apply_tiled(const fo_ctx *c, const T *coords, const T *x, T *y, hipStream_t s);
+int launch_elas_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s);
+int launch_descent_apply_tiled(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+int launch_descent_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s);
+int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s);
+int launch_phigrad_tiled(const fo_ctx *c, const double *phi, double *gbuf, hipStream_t s);
+void launch_facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+
+}  // namespace fo

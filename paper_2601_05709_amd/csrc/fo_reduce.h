@@ -1,0 +1,38 @@
+// Deterministic wave64/block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fo {
+
+// reductions: wave64 shuffle, then LDS across the waves of a block
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a 256-thread block; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds /*[4]*/)
+{
+    v = wave_sum(v);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    __syncthreads();
+    return s;
+}
+
+// Deterministic sum of n partials by one 256-thread block (thread 0 gets it).
+__device__ __forceinline__ double block_sum_partials(const double *part, int n, double *lds)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+    return block_sum(s, lds);
+}
+
+}  // namespace fo

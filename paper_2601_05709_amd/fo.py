@@ -1,0 +1,286 @@
+"""ctypes binding of libfo (include/fo.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Device arrays are torch tensors on the ROCm device; the binding
+passes their data pointers and torch's current HIP stream.  If libfo.so is
+missing the import fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfo.so")
+
+FO_OK, FO_NOT_CONVERGED = 0, 1
+FO_ERR_ARG, FO_ERR_MESH, FO_ERR_NOMEM, FO_ERR_HIP, FO_ERR_BREAKDOWN, FO_ERR_STATE = -1, -2, -3, -4, -5, -6
+FO_FP64, FO_FP32_IR = 0, 1
+FO_SCATTER_TILED, FO_SCATTER_ATOMIC = 0, 1
+
+
+class FoError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s: %s (status %d)" % (what, status_string(status), status))
+        self.status = status
+
+
+class fo_mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("n_elems", C.c_int64),
+                ("coords", C.c_void_p), ("conn", C.c_void_p), ("dof_fixed", C.c_void_p),
+                ("n_bfacets", C.c_int64), ("bfacets", C.c_void_p), ("bnormal", C.c_void_p)]
+
+
+class fo_material(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("plane_stress", C.c_int32),
+                ("ersatz", C.c_double)]
+
+
+class fo_solve_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("max_iter", C.c_int32),
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32)]
+
+
+class fo_descent_opts(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("gamma_n", C.c_double), ("gamma_s", C.c_double),
+                ("n_boxes", C.c_int32), ("boxes", C.c_void_p)]
+
+
+class fo_solve_stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters_inner", C.c_int32), ("iters_outer", C.c_int32),
+                ("rel_res", C.c_double), ("seconds", C.c_double)]
+
+
+_vp = C.c_void_p
+EXPORTS = {
+    "fo_create": ([C.POINTER(_vp), C.POINTER(fo_mesh), C.POINTER(fo_material), C.c_int32, _vp], C.c_int),
+    "fo_destroy": ([_vp], C.c_int),
+    "fo_footprint_bytes": ([_vp], C.c_size_t),
+    "fo_set_scatter": ([_vp, C.c_int32], C.c_int),
+    "fo_set_levelset": ([_vp, _vp], C.c_int),
+    "fo_apply_elasticity": ([_vp, _vp, _vp, C.c_int32], C.c_int),
+    "fo_state_solve": ([_vp, _vp, _vp, C.c_int32, C.c_int64, C.POINTER(fo_solve_opts),
+                        C.POINTER(fo_solve_stats)], C.c_int),
+    "fo_shape_derivative": ([_vp, _vp, C.c_int32, C.c_int64, C.c_double, C.c_double, _vp, _vp,
+                             _vp, _vp], C.c_int),
+    "fo_descent_solve": ([_vp, C.POINTER(fo_descent_opts), _vp, _vp, C.POINTER(fo_solve_opts),
+                          C.POINTER(fo_solve_stats), _vp], C.c_int),
+    "fo_apply_descent": ([_vp, C.POINTER(fo_descent_opts), _vp, _vp], C.c_int),
+    "fo_levelset_update": ([_vp, _vp, C.c_double, _vp], C.c_int),
+    "fo_status_string": ([C.c_int], C.c_char_p),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libfo.so (built in-tree by build()); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfo.so is not built (%s); run __graft_entry__.build() or "
+                               "python -m paper_2601_05709_amd.build" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    try:
+        return lib().fo_status_string(int(s)).decode()
+    except Exception:  # library not loadable: still format the error
+        return "status %d" % s
+
+
+def _check(rc: int, what: str, allow=(FO_OK,)) -> int:
+    if rc not in allow:
+        raise FoError(rc, what)
+    return rc
+
+
+def _ptr(t, dtype=None, numel=None, name="array"):
+    """Device pointer of a contiguous torch tensor (validated), or None."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a torch tensor on the GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must have dtype %s (got %s)" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s has %d elements, needs %d" % (name, t.numel(), numel))
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveOpts:
+    precision: int = FO_FP64
+    rtol: float = 1e-8
+    max_iter: int = 200000
+    inner_rtol: float = 1e-3
+    max_outer: int = 60
+    check_every: int = 0
+
+    def c(self) -> fo_solve_opts:
+        return fo_solve_opts(self.precision, self.rtol, self.max_iter, self.inner_rtol,
+                             self.max_outer, self.check_every)
+
+
+@dataclass
+class Stats:
+    status: int
+    iters_inner: int
+    iters_outer: int
+    rel_res: float
+    seconds: float
+
+
+class DescentOpts:
+    def __init__(self, alpha=0.01, gamma_n=1e4, gamma_s=1e4, boxes=None, dim=None):
+        self.alpha, self.gamma_n, self.gamma_s = float(alpha), float(gamma_n), float(gamma_s)
+        b = np.zeros((0, 2 * (dim or 2))) if boxes is None else np.asarray(boxes, dtype=np.float64)
+        self.boxes = np.ascontiguousarray(b.reshape(b.shape[0], -1))
+
+    def c(self) -> fo_descent_opts:
+        n = self.boxes.shape[0]
+        ptr = self.boxes.ctypes.data_as(C.c_void_p) if n else None
+        return fo_descent_opts(self.alpha, self.gamma_n, self.gamma_s, n, ptr)
+
+
+def current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One mesh + material resident on the GPU (fo_create / fo_destroy)."""
+
+    def __init__(self, dim, coords, conn, fixed=None, bfacets=None, bnormal=None, E=1.0, nu=0.3,
+                 plane_stress=1, ersatz=1e-3, max_rhs=1, stream=None):
+        L = lib()
+        self.dim = int(dim)
+        self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+        self._conn = np.ascontiguousarray(conn, dtype=np.int32)
+        self.n_nodes = int(self._coords.shape[0])
+        self.n_elems = int(self._conn.shape[1])
+        self.n_dofs = self.n_nodes * self.dim
+        self.max_rhs = int(max_rhs)
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        bf = None if bfacets is None else np.ascontiguousarray(bfacets, dtype=np.int32)
+        bn = None if bnormal is None else np.ascontiguousarray(bnormal, dtype=np.float64)
+        if fx is not None and fx.size != self.n_dofs:
+            raise ValueError("fixed must have n_nodes*dim entries")
+        nbf = 0 if bf is None else int(bf.shape[1])
+        m = fo_mesh(self.dim, self.n_nodes, self.n_elems, self._coords.ctypes.data, self._conn.ctypes.data,
+                    None if fx is None else fx.ctypes.data, nbf,
+                    None if bf is None else bf.ctypes.data, None if bn is None else bn.ctypes.data)
+        mat = fo_material(E, nu, int(plane_stress), ersatz)
+        h = C.c_void_p()
+        self.stream = stream if stream is not None else current_stream()
+        _check(L.fo_create(C.byref(h), C.byref(m), C.byref(mat), self.max_rhs, self.stream), "fo_create")
+        self.h = h
+
+    @classmethod
+    def from_workload(cls, w, max_rhs=None, stream=None):
+        m = w.mesh
+        return cls(m.dim, m.coords, m.conn, w.fixed, m.bfacets, m.bnormal, w.E, w.nu, w.plane_stress,
+                   w.ersatz, max_rhs or w.n_rhs, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def footprint(self) -> int:
+        return int(lib().fo_footprint_bytes(self.h))
+
+    def set_scatter(self, mode: int):
+        _check(lib().fo_set_scatter(self.h, mode), "fo_set_scatter")
+
+    def set_levelset(self, phi):
+        import torch
+        _check(lib().fo_set_levelset(self.h, _ptr(phi, torch.float64, self.n_nodes, "phi")),
+               "fo_set_levelset")
+
+    def apply_elasticity(self, x, y, precision=FO_FP64):
+        import torch
+        dt = torch.float64 if precision == FO_FP64 else torch.float32
+        _check(lib().fo_apply_elasticity(self.h, _ptr(x, dt, self.n_dofs, "x"),
+                                         _ptr(y, dt, self.n_dofs, "y"), precision),
+               "fo_apply_elasticity")
+
+    def state_solve(self, b, u, opts: SolveOpts, n_rhs: int = 1, ld: Optional[int] = None,
+                    allow_not_converged=False) -> Stats:
+        import torch
+        ld = n_rhs if ld is None else ld
+        st = fo_solve_stats()
+        allow = (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,)
+        rc = lib().fo_state_solve(self.h, _ptr(b, torch.float64, self.n_dofs * ld, "b"),
+                                  _ptr(u, torch.float64, self.n_dofs * ld, "u"), n_rhs, ld,
+                                  C.byref(opts.c()), C.byref(st))
+        _check(rc, "fo_state_solve", allow)
+        return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
+
+    def shape_derivative(self, u, rhs, J, vol, n_rhs=1, ld=None, lambda_vol=0.0, V=1.0, S1=None):
+        import torch
+        ld = n_rhs if ld is None else ld
+        _check(lib().fo_shape_derivative(
+            self.h, _ptr(u, torch.float64, self.n_dofs * ld, "u"), n_rhs, ld, lambda_vol, V,
+            _ptr(rhs, torch.float64, self.n_dofs, "rhs"),
+            _ptr(S1, torch.float64, self.dim * self.dim * self.n_elems, "S1"),
+            _ptr(J, torch.float64, n_rhs, "J"), _ptr(vol, torch.float64, 1, "vol")),
+            "fo_shape_derivative")
+
+    def descent_solve(self, dopts: DescentOpts, rhs, theta, opts: SolveOpts, B_tt=None,
+                      allow_not_converged=False) -> Stats:
+        import torch
+        st = fo_solve_stats()
+        allow = (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,)
+        rc = lib().fo_descent_solve(self.h, C.byref(dopts.c()),
+                                    _ptr(rhs, torch.float64, self.n_dofs, "rhs"),
+                                    _ptr(theta, torch.float64, self.n_dofs, "theta"),
+                                    C.byref(opts.c()), C.byref(st),
+                                    _ptr(B_tt, torch.float64, 1, "B_tt"))
+        _check(rc, "fo_descent_solve", allow)
+        return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
+
+    def apply_descent(self, dopts: DescentOpts, x, y):
+        import torch
+        _check(lib().fo_apply_descent(self.h, C.byref(dopts.c()), _ptr(x, torch.float64, self.n_dofs, "x"),
+                                      _ptr(y, torch.float64, self.n_dofs, "y")), "fo_apply_descent")
+
+    def levelset_update(self, theta, dt: float, phi):
+        import torch
+        _check(lib().fo_levelset_update(self.h, _ptr(theta, torch.float64, self.n_dofs, "theta"),
+                                        float(dt), _ptr(phi, torch.float64, self.n_nodes, "phi")),
+               "fo_levelset_update")
+
+
+def adaptive_dt(B_tt: float, dfactor=1e-2, t_range=(1e-3, 1e-1), s_range=(8, 16)):
+    """Time step of one explicit level-set step from the adaptive rule of the
+    paper (Section "Other implementation aspects", eqs. tend and steps, no
+    noise): t_end = dfactor / B(theta,theta) clipped to t_range; the step count
+    s from the concave rule, clipped to s_range and rounded; dt = t_end / s."""
+    tmin, tmax = t_range
+    smin, smax = s_range
+    t_end = min(max(dfactor / max(float(B_tt), 1e-300), tmin), tmax)
+    s = (smax - smin) * ((t_end - tmin) / (tmax - tmin)) ** (1.0 / 6.0) + smin
+    s = int(round(min(max(s, smin), smax)))
+    return t_end, s, t_end / s
