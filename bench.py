@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload: the 3D cantilever box [0,2]x[0,1]^2 meshed with 96x48x48 cubes x 6
+tetrahedra (1,327,104 elements, 232,897 nodes, 698,691 unknowns), 16 spherical
+holes, clamp at x=0, unit -z traction on a 0.1x0.1 patch at the centre of the
+face x=2.  A step is one full iteration of the hot path: level set ->
+coefficients and Jacobi diagonal, state solve to relative residual 1e-8 (FP32
+CG + FP64 iterative refinement), compliance and shape derivative, H1 descent
+solve, explicit level-set update.  The same steps are also run with a plain
+FP64 state solve for comparison.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def apply_bytes(mesh, width):
+    """Algorithmic bytes of one K(phi) application: x read + y written
+    (DOF values each), node coordinates, and per element 4 int32 vertex ids
+    plus one byte for the level-set coefficient (17 B per tetrahedron)."""
+    d = mesh.dim
+    return 2 * mesh.n_dofs * width + mesh.n_nodes * d * width + mesh.n_elems * (4 * (d + 1) + 1)
+
+
+def run_steps(it, k):
+    import torch
+    outs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        outs.append(it.run(update=True, reset_phi=True))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, outs
+
+
+def cpu_baseline(w, iters_needed, budget_s):
+    """FP64 oracle (CSR + Jacobi-PCG) on the same mesh: assembly, then a
+    bounded number of PCG iterations; the full solve time is extrapolated
+    with the iteration count of the same algorithm on the GPU."""
+    import numpy as np
+    import oracle as oc
+    m = w.mesh
+    t0 = time.perf_counter()
+    lam, mu = oc.lame(w.E, w.nu, m.dim, w.plane_stress)
+    A, _ = oc.element_coef(m.dim, m.conn, w.phi, w.ersatz)
+    K = oc.assemble_elasticity(m.dim, m.coords, m.conn, A, lam, mu)
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, info = K.solve(w.b, w.fixed, rtol=1e-8, max_iter=10)
+    t10 = time.perf_counter() - t0
+    per = t10 / max(info.iters, 1)
+    n = int(max(10, min(iters_needed, (budget_s - t_asm) / max(per, 1e-9))))
+    t0 = time.perf_counter()
+    _, info = K.solve(w.b, w.fixed, rtol=1e-8, max_iter=n)
+    t_it = time.perf_counter() - t0
+    per = t_it / max(info.iters, 1)
+    solve_s = t_asm + iters_needed * per
+    return {
+        "value": 1.0 / solve_s,
+        "unit": "solves/s",
+        "cores": oc.get_threads(),
+        "kind": "oracle",
+        "sample": "FP64 CSR assembly (%.2f s) + %d Jacobi-PCG iterations (%.2f s) on the same mesh; "
+                  "solve time extrapolated to the %d iterations the same algorithm needs to reach "
+                  "rel. res. 1e-8" % (t_asm, info.iters, t_it, iters_needed),
+        "dof_iters_per_s": m.n_dofs / per,
+        "cpu_model": cpu_model(),
+        "assemble_s": t_asm,
+        "s_per_iter": per,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cells", default="96,48,48")
+    ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the plain FP64 variant")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--profile-only", action="store_true", help="short run for profilers")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the hot path is a single-GPU build "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import fo_inputs as fi
+    from paper_2601_05709_amd import fo
+    from paper_2601_05709_amd.pipeline import Iteration
+
+    cells = tuple(int(c) for c in args.cells.split(","))
+    log("building workload %s" % (cells,))
+    w = fi.cantilever_3d(cells)
+    m = w.mesh
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    it_ir = Iteration(w, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), fo.SolveOpts(rtol=1e-8))
+    log("context created in %.2f s (footprint %.1f MB, tiles %s)"
+        % (time.perf_counter() - t0, it_ir.ctx.footprint / 1e6, it_ir.ctx.tile_stats()))
+    it_64 = Iteration(w, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-8), fo.SolveOpts(rtol=1e-8))
+
+    K = 1 if args.profile_only else args.steps
+    W = 0 if args.profile_only else args.warmup
+    for _ in range(W):
+        it_ir.run()
+    log("warmup done; timing %d steps (FP32 CG + FP64 refinement)" % K)
+    t_ir, outs_ir = run_steps(it_ir, K)
+    st = outs_ir[-1].state_stats
+    log("IR: %.3f s/step, state %d inner + %d outer its, rel.res %.2e"
+        % (t_ir / K, st.iters_inner, st.iters_outer, st.rel_res))
+    if args.profile_only:
+        return
+
+    K64 = args.fp64_steps if args.fp64_steps is not None else K
+    it_64.run()
+    t_64, outs_64 = run_steps(it_64, K64)
+    st64 = outs_64[-1].state_stats
+    log("FP64: %.3f s/step, state %d its, rel.res %.2e" % (t_64 / K64, st64.iters_inner, st64.rel_res))
+
+    # agreement of the two precisions (both at rel. res 1e-8)
+    u_ir = it_ir.u[:, 0].double()
+    u_64 = it_64.u[:, 0].double()
+    err_u = float(torch.linalg.norm(u_ir - u_64) / torch.linalg.norm(u_64))
+    err_rhs = float(torch.linalg.norm(it_ir.rhs - it_64.rhs) / torch.linalg.norm(it_64.rhs))
+
+    # roofline of the dominant kernel: the tiled FP32 elasticity element kernel
+    ctx = it_ir.ctx
+    ctx.profile_enable(True)
+    out_p = it_ir.run()
+    ms32, n32 = ctx.profile_read(fo.FO_PROF_ELAS_TILE_FP32)
+    msh, nh = ctx.profile_read(fo.FO_PROF_HALO_FP32)
+    ms64, n64 = ctx.profile_read(fo.FO_PROF_ELAS_TILE_FP64)
+    ctx.profile_enable(False)
+    avg32 = ms32 / max(n32, 1) * 1e-3
+    bytes32 = apply_bytes(m, 4)
+    achieved = bytes32 / avg32 / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_tile_scatter<3,float,ElasOp> (tiled FP32 elasticity apply)",
+                "bytes_per_launch": bytes32, "avg_us": avg32 * 1e6, "launches": n32,
+                "halo_avg_us": msh / max(nh, 1) * 1e3,
+                "fp64_tile_avg_us": ms64 / max(n64, 1) * 1e3,
+                "fp64_bytes_per_launch": apply_bytes(m, 8)}
+    log("roofline: %.1f us/launch, %.0f GB/s (%.1f%% of HBM peak)" % (avg32 * 1e6, achieved, 100 * achieved / HBM_PEAK_GBS))
+
+    st_s = [o.state_stats for o in outs_ir]
+    state_secs = sum(s.seconds for s in st_s)
+    state_its = sum(s.iters_inner + s.iters_outer for s in st_s)
+    st64_s = [o.state_stats for o in outs_64]
+    state64_secs = sum(s.seconds for s in st64_s)
+    state64_its = sum(s.iters_inner for s in st64_s)
+    value = K / t_ir
+    result = {
+        "metric": "solves/s and DOF-iters/s at rel. res 1e-8: batched FP32+refine vs plain FP64",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * t_ir / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "3D cantilever %dx%dx%d cubes x 6 tets, FP32 CG + FP64 refinement to rel. res 1e-8, one full hot-path iteration per step" % cells,
+                   "n_elems": m.n_elems, "n_nodes": m.n_nodes, "n_dofs": m.n_dofs},
+        "dof_iters_per_s": m.n_dofs * state_its / state_secs,
+        "state_iters": {"inner_fp32": st.iters_inner, "outer_fp64": st.iters_outer},
+        "fp64": {"solves_per_s": K64 / t_64, "ms_per_step": 1e3 * t_64 / K64,
+                 "dof_iters_per_s": m.n_dofs * state64_its / state64_secs,
+                 "state_iters": st64.iters_inner,
+                 "state_solve_ms": 1e3 * state64_secs / K64},
+        "state_solve_ms": 1e3 * state_secs / K,
+        "descent_iters": outs_ir[-1].descent_stats.iters_inner,
+        "err_u_ir_vs_fp64": err_u,
+        "err_rhs_ir_vs_fp64": err_rhs,
+        "J": float(outs_ir[-1].J[0].item()),
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        log("CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(w, st64.iters_inner, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

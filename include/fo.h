@@ -168,6 +168,24 @@ int fo_apply_descent(fo_ctx *ctx, const fo_descent_opts *dopts, const double *x,
  * theta: device [n_dofs]. */
 int fo_levelset_update(fo_ctx *ctx, const double *theta, double dt, double *phi);
 
+/* Kernel timing for measurement tools.  While enabled, every launch of the
+ * kernels named below is bracketed by a pair of HIP events recorded on the
+ * context's stream; fo_profile_read synchronises the stream and returns the
+ * summed event time (ms) and launch count since the last enable.  Enabling
+ * resets the totals; timing adds a few microseconds of launch overhead. */
+enum { FO_PROF_ELAS_TILE_FP64 = 0,   /* tiled elasticity element kernel, FP64  */
+       FO_PROF_ELAS_TILE_FP32 = 1,   /* tiled elasticity element kernel, FP32  */
+       FO_PROF_HALO_FP64 = 2,        /* shared-node (halo) reduction, FP64      */
+       FO_PROF_HALO_FP32 = 3,        /* shared-node (halo) reduction, FP32      */
+       FO_PROF_COUNT = 4 };
+int fo_profile_enable(fo_ctx *ctx, int32_t on);
+int fo_profile_read(fo_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
+
+/* Tile statistics of the deterministic scatter: tiles, largest tile (nodes),
+ * tile-node pairs, shared nodes and halo slots (any pointer may be NULL). */
+int fo_tile_stats(const fo_ctx *ctx, int64_t *n_tiles, int64_t *max_nodes, int64_t *n_slots,
+                  int64_t *n_shared_nodes, int64_t *n_halo_slots);
+
 const char *fo_status_string(int status);
 
 #ifdef __cplusplus

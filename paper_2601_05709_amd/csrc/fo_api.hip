@@ -348,6 +348,11 @@ int fo_destroy(fo_ctx *c)
 {
     if (!c) return FO_ERR_ARG;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &v : c->prof_events)
+        for (auto &pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
     for (void *p : c->allocations) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
     if (c->red_host) (void)hipHostFree(c->red_host);
@@ -488,6 +493,42 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
 }
 
 size_t fo_footprint_bytes(const fo_ctx *c) { return c ? c->bytes : 0; }
+
+int fo_profile_enable(fo_ctx *c, int32_t on)
+{
+    if (!c) return FO_ERR_ARG;
+    FO_HIP(hipStreamSynchronize(c->stream));
+    c->prof = on != 0;
+    for (int k = 0; k < FO_PROF_COUNT; ++k) c->prof_used[k] = 0;
+    return FO_OK;
+}
+
+int fo_profile_read(fo_ctx *c, int32_t which, double *total_ms, int64_t *launches)
+{
+    if (!c || which < 0 || which >= FO_PROF_COUNT) return FO_ERR_ARG;
+    FO_HIP(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < c->prof_used[which]; ++i) {
+        float ms = 0.0f;
+        FO_HIP(hipEventElapsedTime(&ms, c->prof_events[which][i].first, c->prof_events[which][i].second));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)c->prof_used[which];
+    return FO_OK;
+}
+
+int fo_tile_stats(const fo_ctx *c, int64_t *n_tiles, int64_t *max_nodes, int64_t *n_slots,
+                  int64_t *n_shared_nodes, int64_t *n_halo_slots)
+{
+    if (!c) return FO_ERR_ARG;
+    if (n_tiles) *n_tiles = c->tiles.n_tiles;
+    if (max_nodes) *max_nodes = c->tiles.max_nodes;
+    if (n_slots) *n_slots = c->tiles.n_slots;
+    if (n_shared_nodes) *n_shared_nodes = c->tiles.n_shared_nodes;
+    if (n_halo_slots) *n_halo_slots = c->tiles.n_shared_slots;
+    return FO_OK;
+}
 
 int fo_set_scatter(fo_ctx *c, int32_t mode)
 {

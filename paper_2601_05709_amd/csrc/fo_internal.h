@@ -119,6 +119,11 @@ struct fo_ctx {
     double *sd_part = nullptr;         // [(max_rhs+1)][blocks]
     int sd_part_cap = 0;
 
+    // kernel timing (fo_profile_*): event pairs per counter
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[FO_PROF_COUNT];
+    size_t prof_used[FO_PROF_COUNT] = {0, 0, 0, 0};
+
     // boundary nodes -> incident facets (descent normal penalty)
     int64_t n_bnodes = 0;
     int32_t *bnodes = nullptr, *bnode_ptr = nullptr, *bnode_fac = nullptr;

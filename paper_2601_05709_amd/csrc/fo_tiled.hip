@@ -144,9 +144,28 @@ static size_t tile_lds_bytes(int max_nodes)
     return ((size_t)max_nodes * (D + Op::NX + Op::NV) + (size_t)kSub * (D + 1) * Op::NV) * sizeof(T);
 }
 
+// Event pair for one timed launch (fo_profile_enable), or null when off.
+static std::pair<hipEvent_t, hipEvent_t> *prof_slot(const fo_ctx *cc, int which)
+{
+    fo_ctx *c = const_cast<fo_ctx *>(cc);
+    if (!c->prof || which < 0) return nullptr;
+    auto &v = c->prof_events[which];
+    size_t &used = c->prof_used[which];
+    if (used == v.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return nullptr;
+        }
+        v.emplace_back(a, b);
+    }
+    return &v[used++];
+}
+
 template <int D, typename T, class Op>
 static int run_tiled(const fo_ctx *c, const Op &op, const T *coords, const T *xin, T *out,
-                     const uint8_t *fixed, hipStream_t s)
+                     const uint8_t *fixed, hipStream_t s, int prof_tile = -1, int prof_halo = -1)
 {
     size_t lds = tile_lds_bytes<D, T, Op>(c->tiles.max_nodes);
     static bool attr_done = false;  // one per template instance: allow the largest tile
@@ -158,14 +177,20 @@ static int run_tiled(const fo_ctx *c, const Op &op, const T *coords, const T *xi
         attr_done = true;
     }
     if (c->tiles.max_nodes > tile_max_nodes(D)) return FO_ERR_MESH;
+    auto *pt = prof_slot(c, prof_tile);
+    if (pt) (void)hipEventRecord(pt->first, s);
     hipLaunchKernelGGL((k_tile_scatter<D, T, Op>), dim3(c->tiles.n_tiles), dim3(kSub), lds, s, op,
                        tile_args(c), coords, xin, out, reinterpret_cast<T *>(c->halo), fixed);
+    if (pt) (void)hipEventRecord(pt->second, s);
     if (c->tiles.n_shared_nodes > 0) {
         int64_t S = c->tiles.n_shared_nodes;
         int nb = (int)std::min<int64_t>((S + 255) / 256, 65535);
+        auto *ph = prof_slot(c, prof_halo);
+        if (ph) (void)hipEventRecord(ph->first, s);
         hipLaunchKernelGGL((k_halo<T, Op::NV>), dim3(nb), dim3(256), 0, s, c->tiles.halo_node,
                            c->tiles.halo_ptr, c->tiles.halo_src, S,
                            reinterpret_cast<const T *>(c->halo), out, fixed);
+        if (ph) (void)hipEventRecord(ph->second, s);
     }
     return FO_OK;
 }
@@ -258,11 +283,14 @@ void launch_facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t
 template <typename T>
 int launch_elas_apply_tiled(const fo_ctx *c, const T *coords, const T *x, T *y, hipStream_t s)
 {
+    const bool f64 = sizeof(T) == 8;
+    const int pt = f64 ? FO_PROF_ELAS_TILE_FP64 : FO_PROF_ELAS_TILE_FP32;
+    const int ph = f64 ? FO_PROF_HALO_FP64 : FO_PROF_HALO_FP32;
     if (c->dim == 2)
         return run_tiled<2, T>(c, ElasOp<2, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, coords,
-                               x, y, c->fixed, s);
+                               x, y, c->fixed, s, pt, ph);
     return run_tiled<3, T>(c, ElasOp<3, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, coords, x,
-                           y, c->fixed, s);
+                           y, c->fixed, s, pt, ph);
 }
 template int launch_elas_apply_tiled<double>(const fo_ctx *, const double *, const double *,
                                              double *, hipStream_t);

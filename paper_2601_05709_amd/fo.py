@@ -71,8 +71,13 @@ EXPORTS = {
                           C.POINTER(fo_solve_stats), _vp], C.c_int),
     "fo_apply_descent": ([_vp, C.POINTER(fo_descent_opts), _vp, _vp], C.c_int),
     "fo_levelset_update": ([_vp, _vp, C.c_double, _vp], C.c_int),
+    "fo_profile_enable": ([_vp, C.c_int32], C.c_int),
+    "fo_profile_read": ([_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+    "fo_tile_stats": ([_vp] + [C.POINTER(C.c_int64)] * 5, C.c_int),
     "fo_status_string": ([C.c_int], C.c_char_p),
 }
+
+FO_PROF_ELAS_TILE_FP64, FO_PROF_ELAS_TILE_FP32, FO_PROF_HALO_FP64, FO_PROF_HALO_FP32 = 0, 1, 2, 3
 
 _lib = None
 
@@ -210,6 +215,20 @@ class Context:
     @property
     def footprint(self) -> int:
         return int(lib().fo_footprint_bytes(self.h))
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().fo_profile_enable(self.h, 1 if on else 0), "fo_profile_enable")
+
+    def profile_read(self, which: int):
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().fo_profile_read(self.h, which, C.byref(ms), C.byref(n)), "fo_profile_read")
+        return ms.value, n.value
+
+    def tile_stats(self) -> dict:
+        v = [C.c_int64() for _ in range(5)]
+        _check(lib().fo_tile_stats(self.h, *[C.byref(x) for x in v]), "fo_tile_stats")
+        keys = ("n_tiles", "max_nodes", "n_slots", "n_shared_nodes", "n_halo_slots")
+        return dict(zip(keys, (x.value for x in v)))
 
     def set_scatter(self, mode: int):
         _check(lib().fo_set_scatter(self.h, mode), "fo_set_scatter")
