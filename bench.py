@@ -49,6 +49,13 @@ def apply_bytes(mesh, width):
     return 2 * mesh.n_dofs * width + mesh.n_nodes * d * width + mesh.n_elems * (4 * (d + 1) + 1)
 
 
+def fused_cg_bytes(mesh, width):
+    """Algorithmic bytes of the fused CG operator kernel: the K(phi) apply of
+    p plus the direction update p = D^-1 r + beta p_old folded into it, i.e.
+    r, D^-1 and p_old read and p written in addition to q written."""
+    return apply_bytes(mesh, width) + 3 * mesh.n_dofs * width
+
+
 def run_steps(it, k):
     import torch
     outs = []
@@ -165,15 +172,15 @@ def main():
     ms64, n64 = ctx.profile_read(fo.FO_PROF_ELAS_TILE_FP64)
     ctx.profile_enable(False)
     avg32 = ms32 / max(n32, 1) * 1e-3
-    bytes32 = apply_bytes(m, 4)
+    bytes32 = fused_cg_bytes(m, 4)
     achieved = bytes32 / avg32 / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_tile_scatter<3,float,ElasOp> (tiled FP32 elasticity apply)",
+                "kernel": "k_tile_cg<3,float> (fused FP32 CG operator: direction update + tiled K(phi) apply)",
                 "bytes_per_launch": bytes32, "avg_us": avg32 * 1e6, "launches": n32,
                 "halo_avg_us": msh / max(nh, 1) * 1e3,
                 "fp64_tile_avg_us": ms64 / max(n64, 1) * 1e3,
-                "fp64_bytes_per_launch": apply_bytes(m, 8)}
+                "fp64_bytes_per_launch": fused_cg_bytes(m, 8)}
     log("roofline: %.1f us/launch, %.0f GB/s (%.1f%% of HBM peak)" % (avg32 * 1e6, achieved, 100 * achieved / HBM_PEAK_GBS))
 
     st_s = [o.state_stats for o in outs_ir]

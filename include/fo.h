@@ -124,7 +124,9 @@ int fo_destroy(fo_ctx *ctx);
 /* Device bytes owned by the context (for footprint-based admission). */
 size_t fo_footprint_bytes(const fo_ctx *ctx);
 
-/* Select the element scatter used by the operators (FO_SCATTER_*). */
+/* Select the element scatter used by the operators (FO_SCATTER_*).  The
+ * atomic mode is a cross-check of the operators and of FP64 solves; FO_FP32_IR
+ * solves need the tiled mode (FO_ERR_ARG otherwise). */
 int fo_set_scatter(fo_ctx *ctx, int32_t mode);
 
 /* Set the level set phi (device [n_nodes]) and derive A_e, chi_e and the Jacobi

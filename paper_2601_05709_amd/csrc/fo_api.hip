@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -111,11 +112,14 @@ int descent_apply(fo_ctx *c, const double *x, double *y, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// PCG driver
+// conjugate-gradient driver
 
-struct PcgVecs {
-    void *x, *r, *p, *q;
-    const void *dinv;
+enum OpKind { OP_ELAS64 = 0, OP_ELAS32 = 1, OP_DESCENT64 = 2 };
+
+template <typename T>
+struct CgVecs {
+    T *x, *r, *p, *q;
+    const T *dinv;
 };
 
 int poll(fo_ctx *c)
@@ -126,70 +130,206 @@ int poll(fo_ctx *c)
     return FO_OK;
 }
 
-// Starts a solve whose residual is b - q: r = b - q, p = z = dinv r, scalars.
+// q = A p inside the CG loop; the p.q partials land in c->pq_part.  done:
+// device flag that turns the operator kernels into no-ops.
 template <typename T>
-void pcg_restart(fo_ctx *c, const T *b, const T *q, T *r, T *p, const T *dinv, int64_t n,
-                 double rtol, int max_it)
+int cg_apply(fo_ctx *c, OpKind k, const T *p, T *q, const int32_t *done, hipStream_t s, int *n_pq)
 {
+    const int64_t n = c->ndof;
+    if (k != OP_DESCENT64 && tiled(c)) {
+        if (c->has_isolated) launch_fill<T>(q, n, T(0), s);
+        *n_pq = c->tiles.n_tiles;
+        if constexpr (sizeof(T) == 8)
+            return launch_elas_apply_tiled<double>(c, c->coords, (const double *)p, (double *)q, s,
+                                                   c->pq_part, done);
+        else
+            return launch_elas_apply_tiled<float>(c, c->coords32, (const float *)p, (float *)q, s,
+                                                  c->pq_part, done);
+    }
+    if (k == OP_DESCENT64) {
+        if (tiled(c)) {
+            if (c->has_isolated) launch_fill<double>((double *)q, n, 0.0, s);
+            FO_TRY(launch_descent_apply_tiled(c, (const double *)p, (double *)q, s, done));
+        } else {
+            launch_descent_apply_atomic(c, (const double *)p, (double *)q, s);
+        }
+    } else {
+        FO_TRY(elas_apply<T>(c, p, q, s));
+    }
     int nb = red_blocks(n);
-    launch_residual_restart<T>(b, q, r, p, dinv, n, c->partials, nb, c->stream);
-    launch_pcg_start(c->scal, c->partials, nb, rtol * rtol, max_it, c->stream);
+    launch_dots<T>(1, p, q, nullptr, nullptr, nullptr, nullptr, n, c->pq_part, nb, s);
+    *n_pq = nb;
+    return FO_OK;
 }
 
-// Runs PCG iterations (already started) until the device flags done.
-// Returns FO_OK and adds the iterations performed to *iters.
-template <typename T, class Apply>
-int pcg_iterate(fo_ctx *c, Apply apply, T *x, T *r, T *p, T *q, const T *dinv, int64_t n,
-                int check_every, int64_t *iters)
+// `chunk` (even) iterations of the generic CG (any operator); the final
+// state is in slot 0.
+template <typename T>
+int cg_chunk(fo_ctx *c, OpKind k, CgVecs<T> v, int chunk, hipStream_t s)
 {
-    int nb = red_blocks(n);
-    hipStream_t s = c->stream;
-    int chunk = check_every > 0 ? check_every : 8;
+    const int64_t n = c->ndof;
+    for (int i = 0; i < chunk; ++i) {
+        const int P = i & 1;
+        int n_pq = 0;
+        FO_TRY(cg_apply<T>(c, k, v.p, v.q, &c->scal[P].done, s, &n_pq));
+        launch_cg_update<T>(c->scal, P, v.x, v.r, v.p, v.q, v.dinv, n, c->pq_part, n_pq,
+                            c->rz_part, s);
+        launch_cg_direction<T>(c->scal, P, v.p, v.r, v.dinv, n, c->rz_part, s);
+    }
+    return FO_OK;
+}
+
+// Vectors of the fused CG (tiled elasticity): the direction alternates
+// between p[0] and p[1]; iteration j reads p[j & 1] and writes p[(j+1) & 1].
+template <typename T>
+struct FusedVecs {
+    T *x, *r, *q;
+    T *p[2];
+    const T *dinv;
+};
+
+template <typename T>
+int fused_chunk(fo_ctx *c, FusedVecs<T> v, int chunk, hipStream_t s)
+{
+    const int nb = node_blocks(c->N);
+    for (int j = 0; j < chunk; ++j) {
+        const int A = j & 1;
+        FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[A], v.p[A ^ 1], v.q, c->scal, A, c->rz_part,
+                                 nb, c->pq_part, s));
+        launch_cgn_update<T>(c, A ^ 1, v.x, v.r, v.p[A ^ 1], v.q, v.dinv, s);
+    }
+    return FO_OK;
+}
+
+// Enqueues one chunk; with profiling off, a captured graph of it is replayed
+// on the private stream, fenced by events against the context stream.
+template <class Enqueue>
+int launch_chunk(fo_ctx *c, std::tuple<int, int, int, int> key, Enqueue enqueue)
+{
+    if (c->prof) return enqueue(c->stream);
+    auto it = c->graphs.find(key);
+    FO_HIP(hipEventRecord(c->ev_in, c->stream));
+    FO_HIP(hipStreamWaitEvent(c->work, c->ev_in, 0));
+    hipGraphExec_t exec = nullptr;
+    if (it == c->graphs.end()) {
+        hipGraph_t g = nullptr;
+        FO_HIP(hipStreamBeginCapture(c->work, hipStreamCaptureModeRelaxed));
+        int rc = enqueue(c->work);
+        hipError_t e = hipStreamEndCapture(c->work, &g);
+        if (rc != FO_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return FO_ERR_HIP;
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return FO_ERR_HIP;
+        c->graphs[key] = exec;
+    } else {
+        exec = it->second;
+    }
+    FO_HIP(hipGraphLaunch(exec, c->work));
+    FO_HIP(hipEventRecord(c->ev_out, c->work));
+    FO_HIP(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    return FO_OK;
+}
+
+// Polls slot 0 between chunks until the device flags done; adds iterations.
+template <class Chunk>
+int cg_loop(fo_ctx *c, Chunk chunk_fn, int64_t *iters)
+{
     FO_TRY(poll(c));
     while (!c->scal_host->done) {
-        for (int k = 0; k < chunk; ++k) {
-            FO_TRY(apply(p, q));
-            launch_dots<T>(1, p, q, nullptr, nullptr, nullptr, nullptr, n, c->partials, nb, s);
-            launch_pcg_alpha(c->scal, c->partials, nb, s);
-            launch_pcg_update<T>(c->scal, x, r, p, q, dinv, n, c->partials, nb, s);
-            launch_pcg_beta(c->scal, c->partials, nb, s);
-            launch_pcg_p<T>(c->scal, p, q, n, s);
-        }
+        const int32_t before = c->scal_host->it;
+        FO_TRY(chunk_fn());
         FO_TRY(poll(c));
-        if (check_every <= 0) chunk = std::min(64, std::max(8, c->scal_host->it / 8));
+        if (!c->scal_host->done && c->scal_host->it == before) {  // no progress: a launch failed
+            hipError_t e = hipGetLastError();
+            std::fprintf(stderr, "libfo: CG chunk made no progress (%s)\n", hipGetErrorString(e));
+            return FO_ERR_HIP;
+        }
     }
     *iters += c->scal_host->it;
     return FO_OK;
 }
 
-// FP64 Jacobi-PCG on A x = b (b contiguous; x output), with the true-residual
-// stopping test.  apply(in, out) computes out = A in.
-template <class Apply>
-int solve_fp64(fo_ctx *c, Apply apply, const double *b, double *x, const double *dinv,
-               const fo_solve_opts *o, fo_solve_stats *st)
+int chunk_len(const fo_solve_opts *o)
 {
-    int64_t n = c->ndof;
+    int chunk = o->check_every > 0 ? o->check_every : 16;
+    return chunk + (chunk & 1);  // even: the final state is in slot 0
+}
+
+template <typename T>
+int cg_run(fo_ctx *c, OpKind k, CgVecs<T> v, const fo_solve_opts *o, int64_t *iters)
+{
+    const int chunk = chunk_len(o);
+    auto key = std::make_tuple((int)k, chunk, c->scatter, k == OP_DESCENT64 ? c->descent_version : 0);
+    return cg_loop(c, [&]() {
+        return launch_chunk(c, key, [&](hipStream_t s) { return cg_chunk<T>(c, k, v, chunk, s); });
+    }, iters);
+}
+
+template <typename T>
+int fused_run(fo_ctx *c, FusedVecs<T> v, const fo_solve_opts *o, int64_t *iters)
+{
+    const int chunk = chunk_len(o);
+    auto key = std::make_tuple(sizeof(T) == 8 ? 10 : 11, chunk, c->scatter, 0);
+    return cg_loop(c, [&]() {
+        return launch_chunk(c, key, [&](hipStream_t s) { return fused_chunk<T>(c, v, chunk, s); });
+    }, iters);
+}
+
+template <typename T>
+int op_apply(fo_ctx *c, OpKind k, const T *x, T *y, hipStream_t s)
+{
+    if (k == OP_DESCENT64) return descent_apply(c, (const double *)x, (double *)y, s);
+    return elas_apply<T>(c, x, y, s);
+}
+
+bool fused_path(const fo_ctx *c, OpKind k) { return k != OP_DESCENT64 && tiled(c); }
+
+// FP64 Jacobi-PCG on A x = b (b contiguous), stopping on the recomputed
+// residual ||b - A x|| <= rtol ||b||.  The solution is left in c->x64.
+int solve_fp64(fo_ctx *c, OpKind k, const double *b, const double *dinv, const fo_solve_opts *o,
+               fo_solve_stats *st)
+{
+    const int64_t n = c->ndof;
     hipStream_t s = c->stream;
-    double *r = c->r64, *p = c->p64, *q = c->q64;
+    const bool fused = fused_path(c, k);
+    CgVecs<double> v{c->x64, c->r64, c->p64, c->q64, dinv};
+    FusedVecs<double> fv{c->x64, c->r64, c->q64, {c->p64, c->p64b}, dinv};
     int64_t iters = 0;
-    launch_fill<double>(x, n, 0.0, s);
-    launch_fill<double>(q, n, 0.0, s);
-    pcg_restart<double>(c, b, q, r, p, dinv, n, o->rtol, o->max_iter);
+    launch_fill<double>(v.x, n, 0.0, s);
+    if (fused) {
+        if (c->has_isolated) {
+            launch_fill<double>(c->q64, n, 0.0, s);
+            launch_fill<double>(c->p64, n, 0.0, s);
+            launch_fill<double>(c->p64b, n, 0.0, s);
+        }
+        launch_cgn_start<double>(c, b, nullptr, v.r, dinv, o->rtol, o->max_iter, s);
+    } else {
+        launch_cg_start<double>(b, nullptr, v.r, v.p, dinv, n, c->partials, c->scal, o->rtol, -1.0,
+                                o->max_iter, s);
+    }
     int status = FO_NOT_CONVERGED;
     double relres = 1.0;
     for (int restart = 0; restart < 20; ++restart) {
-        FO_TRY(pcg_iterate<double>(c, apply, x, r, p, q, dinv, n, o->check_every, &iters));
+        FO_TRY(fused ? fused_run<double>(c, fv, o, &iters) : cg_run<double>(c, k, v, o, &iters));
         if (c->scal_host->status == FO_ERR_BREAKDOWN) {
             status = FO_ERR_BREAKDOWN;
             break;
         }
-        // true residual
-        FO_TRY(apply(x, q));
+        // recompute the residual in FP64; restart from it if needed
+        FO_TRY(op_apply<double>(c, k, v.x, v.q, s));
         ++iters;
         int left = (int)std::max<int64_t>(1, (int64_t)o->max_iter - iters);
-        pcg_restart<double>(c, b, q, r, p, dinv, n, o->rtol, left);
+        if (fused)
+            launch_cgn_start<double>(c, b, v.q, v.r, dinv, o->rtol, left, s);
+        else
+            launch_cg_start<double>(b, v.q, v.r, v.p, dinv, n, c->partials, c->scal, o->rtol, -1.0,
+                                    left, s);
         FO_TRY(poll(c));
-        SolveScalars h = *c->scal_host;
+        const SolveScalars h = *c->scal_host;
         relres = h.bnorm2 > 0 ? std::sqrt(h.rr / h.bnorm2) : 0.0;
         if (h.bnorm2 == 0.0 || relres <= o->rtol) {
             status = FO_OK;
@@ -206,61 +346,69 @@ int solve_fp64(fo_ctx *c, Apply apply, const double *b, double *x, const double 
     return status;
 }
 
-// FP32 inner PCG + FP64 iterative refinement for the state operator.
-int solve_ir(fo_ctx *c, const double *b, double *x, const fo_solve_opts *o, fo_solve_stats *st)
+// FP32 CG with FP64 residual replacement.  Phases of FP32 CG each lower the
+// (rescaled) residual by inner_rtol; between phases x64 += s x32, the FP64
+// residual b - K x64 is recomputed, the FP32 residual is replaced by it and
+// the search direction is kept (rescaled), so the Krylov process continues
+// instead of restarting.  Stops when ||b - K x64|| <= rtol ||b|| (FP64).
+int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats *st)
 {
-    int64_t n = c->ndof;
+    const int64_t n = c->ndof;
     hipStream_t s = c->stream;
-    int nb = red_blocks(n);
-    int64_t inner_total = 0;
+    const int nb = red_blocks(n);
+    int64_t inner = 0;
     int outer = 0;
-    auto apply64 = [c, s](const double *in, double *out) { return elas_apply<double>(c, in, out, s); };
-    auto apply32 = [c, s](const float *in, float *out) { return elas_apply<float>(c, in, out, s); };
-    launch_fill<double>(x, n, 0.0, s);
-    // r64 = b;  dscratch[0] = ||r||^2 = ||b||^2
+    double *s2 = c->dscratch;  // [0] current scale^2, [1] new residual^2
+    launch_fill<double>(c->x64, n, 0.0, s);
     FO_HIP(hipMemcpyAsync(c->r64, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_dots<double>(1, b, b, nullptr, nullptr, nullptr, nullptr, n, c->partials, nb, s);
-    launch_finish_dots(c->partials, nb, 1, c->dscratch, s);
-    FO_HIP(hipMemcpyAsync(c->red_host, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
+    launch_finish_dots(c->partials, nb, 1, s2 + 1, s);
+    FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
     FO_HIP(hipStreamSynchronize(s));
-    double bnorm = std::sqrt(c->red_host[0]);
+    const double bnorm = std::sqrt(c->red_host[0]);
     double rn = bnorm;
     int status = FO_NOT_CONVERGED;
-    int max_outer = o->max_outer > 0 ? o->max_outer : 50;
-    double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-3;
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
+    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-2;
+    int fresh = 1;
+    FusedVecs<float> v{c->x32, c->r32, c->q32, {c->p32, c->p32b}, c->dinv32};
+    if (c->has_isolated) {
+        launch_fill<float>(c->q32, n, 0.0f, s);
+        launch_fill<float>(c->p32, n, 0.0f, s);
+        launch_fill<float>(c->p32b, n, 0.0f, s);
+    }
     while (true) {
         if (bnorm == 0.0 || rn <= o->rtol * bnorm) {
             status = FO_OK;
             break;
         }
-        if (outer >= max_outer || inner_total >= o->max_iter) break;
-        // inner system K32 d = r / ||r||
-        launch_ir_scale_down(c->r64, c->dscratch, n, c->b32, c->x32, s);
-        launch_fill<float>(c->q32, n, 0.0f, s);
-        int left = (int)std::max<int64_t>(1, (int64_t)o->max_iter - inner_total);
-        pcg_restart<float>(c, c->b32, c->q32, c->r32, c->p32, c->dinv32, n, inner_rtol, left);
-        FO_TRY(pcg_iterate<float>(c, apply32, c->x32, c->r32, c->p32, c->q32, c->dinv32, n,
-                                  o->check_every, &inner_total));
-        if (c->scal_host->status == FO_ERR_BREAKDOWN) {
-            status = FO_ERR_BREAKDOWN;
-            break;
-        }
-        launch_ir_update(x, c->x32, c->dscratch, n, s);
-        // FP64 residual r = b - K x
-        FO_TRY(apply64(x, c->q64));
+        if (outer >= max_outer || inner >= o->max_iter) break;
+        const int left = (int)std::max<int64_t>(1, (int64_t)o->max_iter - inner);
+        launch_ir_phase(c, c->r64, s2, v.r, v.x, v.dinv, phase_rtol, left, fresh, s);
+        FO_TRY(fused_run<float>(c, v, o, &inner));
+        fresh = c->scal_host->status == FO_ERR_BREAKDOWN ? 1 : 0;
+        if (c->scal_host->it & 1)  // the last direction is in p[1]; phases start from p[0]
+            FO_HIP(hipMemcpyAsync(v.p[0], v.p[1], n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        launch_ir_accumulate(c->x64, v.x, s2, n, s);
+        FO_TRY(elas_apply<double>(c, c->x64, c->q64, s));
         ++outer;
-        launch_pcg_residual64(c, b, c->q64, c->r64, n, nb, s);
-        FO_HIP(hipMemcpyAsync(c->red_host, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
+        launch_residual64(b, c->q64, c->r64, n, c->partials, s2 + 1, s);
+        FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
         FO_HIP(hipStreamSynchronize(s));
-        rn = std::sqrt(c->red_host[0]);
-        if (!(rn == rn)) {
+        const double rn_new = std::sqrt(c->red_host[0]);
+        if (!(rn_new == rn_new)) {
             status = FO_ERR_BREAKDOWN;
             break;
         }
+        if (fresh && rn_new >= rn) {  // FP32 cannot make progress from here
+            rn = rn_new;
+            break;
+        }
+        rn = rn_new;
     }
     if (st) {
         st->status = status;
-        st->iters_inner = (int32_t)inner_total;
+        st->iters_inner = (int32_t)inner;
         st->iters_outer = outer;
         st->rel_res = bnorm > 0 ? rn / bnorm : 0.0;
     }
@@ -289,6 +437,7 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
         FO_TRY(dev_alloc(c, &ds.diag, c->ndof));
         FO_TRY(dev_alloc(c, &ds.dinv, c->ndof));
     }
+    ++c->descent_version;
     ds.alpha = d->alpha;
     ds.gamma_n = d->gamma_n;
     ds.gamma_s = d->gamma_s;
@@ -348,6 +497,10 @@ int fo_destroy(fo_ctx *c)
 {
     if (!c) return FO_ERR_ARG;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    if (c->work) (void)hipStreamDestroy(c->work);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     for (auto &v : c->prof_events)
         for (auto &pr : v) {
             (void)hipEventDestroy(pr.first);
@@ -403,7 +556,18 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
 
     // element order: tiles along a Morton curve (identity if tiling is off)
     HostTiles ht;
-    build_tiles(D, N, E, m->coords, m->conn, &ht);
+    int cus = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    int tile_elems = tile_target_elems(D, E, cus);
+    if (const char *env = std::getenv("FO_TILE_ELEMS")) {  // tuning override
+        int v = std::atoi(env);
+        if (v > 0) tile_elems = std::min(v, tile_max_elems(D));
+    }
+    build_tiles(D, N, E, m->coords, m->conn, tile_elems, &ht);
     std::vector<int32_t> conn_t((size_t)(D + 1) * E);
     for (int a = 0; a <= D; ++a)
         for (int64_t e = 0; e < E; ++e)
@@ -426,8 +590,12 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         (rc = dev_alloc(c, &c->t64, n)) || (rc = dev_alloc(c, &c->x32, n)) ||
         (rc = dev_alloc(c, &c->r32, n)) || (rc = dev_alloc(c, &c->p32, n)) ||
         (rc = dev_alloc(c, &c->q32, n)) || (rc = dev_alloc(c, &c->b32, n)) ||
+        (rc = dev_alloc(c, &c->p64b, n)) || (rc = dev_alloc(c, &c->p32b, n)) ||
+        (rc = dev_alloc(c, &c->bb_part, (size_t)kRedBlocks)) ||
         (rc = dev_alloc(c, &c->partials, (size_t)kRedBlocks * 4)) ||
-        (rc = dev_alloc(c, &c->scal, 1)) || (rc = dev_alloc(c, &c->dscratch, 16)) ||
+        (rc = dev_alloc(c, &c->pq_part, (size_t)std::max<int64_t>(ht.n_tiles, kRedBlocks))) ||
+        (rc = dev_alloc(c, &c->rz_part, (size_t)kRedBlocks * 2)) ||
+        (rc = dev_alloc(c, &c->scal, 2)) || (rc = dev_alloc(c, &c->dscratch, 16)) ||
         (rc = dev_alloc(c, &c->gbuf, N * (D + 1))))
         return fail(rc);
     if ((rc = dev_alloc(c, &c->s1buf, (size_t)E * D * D))) return fail(rc);
@@ -487,6 +655,11 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
                     up(c->bnode_fac, bfac.data(), bfac.size() * sizeof(int32_t)))))
         return fail(FO_ERR_HIP);
     if ((rc = upload_tiles(c, ht))) return fail(rc);
+    if ((rc = tiled_prepare(c))) return fail(rc);
+    if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+        return fail(FO_ERR_HIP);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(FO_ERR_HIP);
     *out = c;
     return FO_OK;
@@ -574,19 +747,15 @@ int fo_state_solve(fo_ctx *c, const double *b, double *u, int32_t n_rhs, int64_t
     if (!c || !b || !u || !opts_ok(o) || n_rhs < 1 || n_rhs > c->max_rhs || ld < n_rhs)
         return FO_ERR_ARG;
     if (!c->have_phi) return FO_ERR_STATE;
+    if (o->precision == FO_FP32_IR && !tiled(c)) return FO_ERR_ARG;  // IR runs on the tiled operator
     hipStream_t s = c->stream;
     int worst = FO_OK;
     fo_solve_stats acc{FO_OK, 0, 0, 0.0, 0.0};
     for (int k = 0; k < n_rhs; ++k) {
         launch_gather_col<double, double>(b + k, ld, c->ndof, c->b64, c->fixed, s);
         fo_solve_stats one{};
-        int rc;
-        if (o->precision == FO_FP64) {
-            auto apply = [c, s](const double *in, double *out) { return elas_apply<double>(c, in, out, s); };
-            rc = solve_fp64(c, apply, c->b64, c->x64, c->dinv64, o, &one);
-        } else {
-            rc = solve_ir(c, c->b64, c->x64, o, &one);
-        }
+        int rc = o->precision == FO_FP64 ? solve_fp64(c, OP_ELAS64, c->b64, c->dinv64, o, &one)
+                                         : solve_ir(c, c->b64, o, &one);
         if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
         launch_scatter_col<double>(c->x64, c->ndof, u + k, ld, s);
         acc.iters_inner += one.iters_inner;
@@ -636,10 +805,10 @@ int fo_descent_solve(fo_ctx *c, const fo_descent_opts *d, const double *rhs, dou
     if (!(d->alpha > 0) || d->gamma_n < 0 || d->gamma_s < 0) return FO_ERR_ARG;
     FO_TRY(descent_prepare(c, d));
     hipStream_t s = c->stream;
-    auto apply = [c, s](const double *in, double *out) { return descent_apply(c, in, out, s); };
     fo_solve_stats one{};
-    int rc = solve_fp64(c, apply, rhs, theta, c->descent.dinv, o, &one);
+    int rc = solve_fp64(c, OP_DESCENT64, rhs, c->descent.dinv, o, &one);
     if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+    FO_HIP(hipMemcpyAsync(theta, c->x64, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (B_tt) {
         int nb = red_blocks(c->ndof);
         launch_dots<double>(1, theta, rhs, nullptr, nullptr, nullptr, nullptr, c->ndof, c->partials,

@@ -5,6 +5,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fo.h"
@@ -23,37 +25,34 @@ struct SolveScalars {
     double alpha, beta;
     double tol2;     // (rtol ||b||)^2 on the working-precision recursive residual
     double bnorm2;   // ||b||^2 of the current (inner) system
+    double rho_new;  // r . z after the last update (also when done)
     int32_t it;      // operator applications performed
     int32_t done;    // 1: converged or failed, kernels become no-ops
     int32_t status;  // 0 ok, FO_ERR_BREAKDOWN
     int32_t max_it;  // cap for this (inner) solve
+    int32_t first;   // fused CG: next direction uses `beta` as given (restart)
+    int32_t pad;
 };
 
-// Element-to-node scatter tiles (deterministic mode).  Elements are reordered
-// along a Morton curve and cut into tiles; a tile's nodes are numbered
-// locally so the scatter accumulates in LDS.  See fo_tiles.cpp.
+// Element-to-node scatter tiles (deterministic mode), see fo_tiles.h.
+// Per-tile arrays use fixed strides MN (nodes) and ME (elements).
 struct TileSet {
     int32_t n_tiles = 0;
-    int32_t max_nodes = 0;              // largest tile (LDS sizing)
-    int32_t max_sub = 0;                // largest number of sub-batches in a tile
-    int64_t n_slots = 0;                // total (tile, node) pairs
-    int64_t n_shared_slots = 0;         // (tile, node) pairs whose node is shared
+    int32_t max_nodes = 0;              // MN: node stride, LDS sizing
+    int32_t max_elems = 0;              // ME: element stride, block size
+    int64_t n_slots = 0;                // tile-node pairs
+    int64_t n_shared_slots = 0;         // halo slots (tile-node pairs of shared nodes)
     int64_t n_shared_nodes = 0;
     // device arrays
-    int32_t *tile_elem_off = nullptr;   // [n_tiles+1] into the tile-ordered element list
-    int32_t *tile_node_off = nullptr;   // [n_tiles+1] into tile_nodes
-    int32_t *tile_node_interior = nullptr; // [n_tiles] number of leading interior nodes
-    int32_t *tile_halo_off = nullptr;   // [n_tiles] first halo slot of the tile
-    int32_t *tile_nodes = nullptr;      // [n_slots] global node id of each tile-local node
-    uint16_t *lconn = nullptr;          // [E][4] tile-local vertex ids (tile element order)
-    uint16_t *lslot = nullptr;          // [E][4] LDS slot of each (element, vertex)
-    int32_t *sub_off = nullptr;         // [n_tiles+1] into sub-batch segment tables
-    int32_t *seg_off = nullptr;         // [n_sub+1] into seg_node / seg_start
-    uint16_t *seg_node = nullptr;       // [n_seg] tile-local node of each segment
-    uint16_t *seg_start = nullptr;      // [n_seg+n_sub] slot range start (+ end sentinel)
+    int32_t *info = nullptr;            // [n_tiles][8] first element, counts (kTile*)
+    uint16_t *lconn = nullptr;          // [n_tiles][ME][4] local vertex ids
+    uint16_t *lslot = nullptr;          // [n_tiles][ME][4] LDS slot of each (element, vertex)
+    int32_t *nodes = nullptr;           // [n_tiles][MN] global node of each tile node
+    uint16_t *seg = nullptr;            // [n_tiles][MN+1] first slot of each node's segment
+    int32_t *hpos = nullptr;            // [n_tiles][MN] halo slot of a shared tile node
     int32_t *halo_node = nullptr;       // [n_shared_nodes] global node of each shared node
-    int32_t *halo_ptr = nullptr;        // [n_shared_nodes+1] into halo_src
-    int32_t *halo_src = nullptr;        // [n_shared_slots] halo slot feeding the node
+    int32_t *halo_ptr = nullptr;        // [n_shared_nodes+1] node-major halo slot ranges
+    int32_t *node_hrange = nullptr;     // [N][2] halo range of a node, (-1,-1) if interior
 };
 
 struct DescentSetup {
@@ -102,12 +101,21 @@ struct fo_ctx {
 
     // Krylov workspace (single RHS); FP64 and FP32 copies
     double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *b64 = nullptr,
-           *t64 = nullptr;
-    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *b32 = nullptr;
+           *t64 = nullptr, *p64b = nullptr;
+    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *b32 = nullptr,
+          *p32b = nullptr;  // p*b: second direction buffer of the fused CG
     double *halo = nullptr;            // [n_shared_slots * dim] halo partials
-    double *partials = nullptr;        // [kRedBlocks * 4]
-    fo::SolveScalars *scal = nullptr;  // device
-    fo::SolveScalars *scal_host = nullptr;  // pinned
+    double *partials = nullptr;        // [kRedBlocks * 4] general partial sums
+    double *pq_part = nullptr;         // [max(n_tiles, kRedBlocks)] p.Ap partials
+    double *rz_part = nullptr;         // [2 * kRedBlocks] r.z, r.r partials
+    double *bb_part = nullptr;         // [kRedBlocks] b.b partials
+    fo::SolveScalars *scal = nullptr;  // device, two parity slots
+    fo::SolveScalars *scal_host = nullptr;  // pinned copy of slot 0
+    hipStream_t work = nullptr;        // private non-blocking stream for graph replay
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // captured CG iteration chunks: key (operator, chunk, scatter, descent version)
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+    int descent_version = 0;
     double *red_host = nullptr;        // pinned scratch for scalar results
     double *dscratch = nullptr;        // [8] device scratch scalars
 

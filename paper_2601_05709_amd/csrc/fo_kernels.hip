@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_scatter_atomic(Op op, const int32_t *__
         Up[a] = Uv[a];
     }
     T res[D + 1][NV];
-    op(e, nodes, Xp, Up, res);
+    op(op.load(e), Xp, Up, res);
 #pragma unroll
     for (int a = 0; a <= D; ++a)
 #pragma unroll
@@ -166,171 +166,7 @@ __global__ __launch_bounds__(256) void k_finish_dots(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi PCG, device-side control (no host round trip per iteration)
-
-// rho = r.z, rr = r.r, bnorm2 = b.b from partial rows 0, 1, 2.
-__global__ __launch_bounds__(256) void k_pcg_start(SolveScalars *sc, const double *__restrict__ part,
-                                                   int nb, double rtol2, int max_it)
-{
-    __shared__ double lds[4];
-    double rz = block_sum_partials(part, nb, lds);
-    double rr = block_sum_partials(part + nb, nb, lds);
-    double bb = block_sum_partials(part + 2 * nb, nb, lds);
-    if (threadIdx.x == 0) {
-        sc->rho = rz;
-        sc->rr = rr;
-        sc->bnorm2 = bb;
-        sc->tol2 = rtol2 * bb;
-        sc->alpha = sc->beta = 0.0;
-        sc->it = 0;
-        sc->max_it = max_it;
-        sc->status = 0;
-        sc->done = (rr <= sc->tol2) ? 1 : 0;
-        if (!(rz >= 0.0) || rz != rz) {
-            sc->status = FO_ERR_BREAKDOWN;
-            sc->done = 1;
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void k_pcg_alpha(SolveScalars *sc, const double *__restrict__ part,
-                                                   int nb)
-{
-    __shared__ double lds[4];
-    if (sc->done) return;
-    double pq = block_sum_partials(part, nb, lds);
-    if (threadIdx.x == 0) {
-        sc->pq = pq;
-        if (!(pq > 0.0) || pq != pq || pq == INFINITY) {
-            sc->status = FO_ERR_BREAKDOWN;
-            sc->done = 1;
-            sc->alpha = 0.0;
-        } else {
-            sc->alpha = sc->rho / pq;
-        }
-    }
-}
-
-// x += alpha p; r -= alpha q; z = dinv r (stored in q); partial rows: r.z, r.r
-template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_update(const SolveScalars *__restrict__ sc,
-                                                    T *__restrict__ x, T *__restrict__ r,
-                                                    const T *__restrict__ p, T *__restrict__ q,
-                                                    const T *__restrict__ dinv, int64_t n,
-                                                    double *__restrict__ part)
-{
-    __shared__ double lds[4];
-    if (sc->done) return;
-    T alpha = (T)sc->alpha;
-    double rz = 0.0, rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        T pi = p[i];
-        x[i] += alpha * pi;
-        T ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        T zi = dinv[i] * ri;
-        q[i] = zi;
-        rz += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
-    }
-    double s0 = block_sum(rz, lds);
-    double s1 = block_sum(rr, lds);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = s0;
-        part[gridDim.x + blockIdx.x] = s1;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_pcg_beta(SolveScalars *sc, const double *__restrict__ part,
-                                                  int nb)
-{
-    __shared__ double lds[4];
-    if (sc->done) return;
-    double rz = block_sum_partials(part, nb, lds);
-    double rr = block_sum_partials(part + nb, nb, lds);
-    if (threadIdx.x == 0) {
-        sc->it += 1;
-        sc->rr = rr;
-        if (rr != rr || !(rz >= 0.0)) {
-            sc->status = FO_ERR_BREAKDOWN;
-            sc->done = 1;
-            return;
-        }
-        if (rr <= sc->tol2 || sc->it >= sc->max_it) {
-            sc->done = 1;
-            return;
-        }
-        sc->beta = rz / sc->rho;
-        sc->rho = rz;
-    }
-}
-
-// p = z + beta p  (z lives in q)
-template <typename T>
-__global__ void k_pcg_p(const SolveScalars *__restrict__ sc, T *__restrict__ p,
-                        const T *__restrict__ z, int64_t n)
-{
-    if (sc->done) return;
-    T beta = (T)sc->beta;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + beta * p[i];
-}
-
-// r = b - q (true residual), z = dinv r into zout, p = z; partial rows r.z, r.r, b.b
-template <typename T>
-__global__ __launch_bounds__(256) void k_residual_restart(const T *__restrict__ b,
-                                                          const T *__restrict__ q,
-                                                          T *__restrict__ r, T *__restrict__ p,
-                                                          const T *__restrict__ dinv, int64_t n,
-                                                          double *__restrict__ part)
-{
-    __shared__ double lds[4];
-    double rz = 0.0, rr = 0.0, bb = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        T ri = b[i] - q[i];
-        r[i] = ri;
-        T zi = dinv[i] * ri;
-        p[i] = zi;
-        rz += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
-        bb += (double)b[i] * (double)b[i];
-    }
-    double s0 = block_sum(rz, lds), s1 = block_sum(rr, lds), s2 = block_sum(bb, lds);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = s0;
-        part[gridDim.x + blockIdx.x] = s1;
-        part[2 * gridDim.x + blockIdx.x] = s2;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // mixed precision helpers
-
-// r32 = (float)(r64 / s), where s = sqrt(*nrm2) (device scalar); x32 = 0
-__global__ void k_ir_scale_down(const double *__restrict__ r64, const double *__restrict__ nrm2,
-                                int64_t n, float *__restrict__ r32, float *__restrict__ x32)
-{
-    double s = sqrt(*nrm2);
-    double inv = s > 0.0 ? 1.0 / s : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        r32[i] = (float)(r64[i] * inv);
-        x32[i] = 0.0f;
-    }
-}
-
-// x64 += s * d32
-__global__ void k_ir_update(double *__restrict__ x64, const float *__restrict__ d32,
-                            const double *__restrict__ nrm2, int64_t n)
-{
-    double s = sqrt(*nrm2);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        x64[i] += s * (double)d32[i];
-}
 
 __global__ void k_to_float(const double *__restrict__ a, float *__restrict__ b, int64_t n)
 {
@@ -469,23 +305,6 @@ __global__ void k_phi_update(const double *__restrict__ gbuf, const double *__re
     }
 }
 
-// r = b - q and ||r||^2 partials (row 0)
-__global__ __launch_bounds__(256) void k_residual64(const double *__restrict__ b,
-                                                    const double *__restrict__ q,
-                                                    double *__restrict__ r, int64_t n,
-                                                    double *__restrict__ part)
-{
-    __shared__ double lds[4];
-    double rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double ri = b[i] - q[i];
-        r[i] = ri;
-        rr += ri * ri;
-    }
-    double t = block_sum(rr, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
 
 // ---------------------------------------------------------------------------
 // launch wrappers
@@ -567,61 +386,6 @@ void launch_finish_dots(const double *part, int nb, int npair, double *out, hipS
     hipLaunchKernelGGL(k_finish_dots, dim3(1), dim3(kBlock), 0, s, part, nb, npair, out);
 }
 
-void launch_pcg_start(SolveScalars *sc, const double *part, int nb, double rtol2, int max_it,
-                      hipStream_t s)
-{
-    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(kBlock), 0, s, sc, part, nb, rtol2, max_it);
-}
-void launch_pcg_alpha(SolveScalars *sc, const double *part, int nb, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kBlock), 0, s, sc, part, nb);
-}
-void launch_pcg_beta(SolveScalars *sc, const double *part, int nb, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kBlock), 0, s, sc, part, nb);
-}
-template <typename T>
-void launch_pcg_update(const SolveScalars *sc, T *x, T *r, const T *p, T *q, const T *dinv,
-                       int64_t n, double *part, int nb, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_pcg_update<T>, dim3(nb), dim3(kBlock), 0, s, sc, x, r, p, q, dinv, n, part);
-}
-template void launch_pcg_update<double>(const SolveScalars *, double *, double *, const double *,
-                                        double *, const double *, int64_t, double *, int,
-                                        hipStream_t);
-template void launch_pcg_update<float>(const SolveScalars *, float *, float *, const float *,
-                                       float *, const float *, int64_t, double *, int, hipStream_t);
-template <typename T>
-void launch_pcg_p(const SolveScalars *sc, T *p, const T *z, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_pcg_p<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, sc, p, z, n);
-}
-template void launch_pcg_p<double>(const SolveScalars *, double *, const double *, int64_t,
-                                   hipStream_t);
-template void launch_pcg_p<float>(const SolveScalars *, float *, const float *, int64_t,
-                                  hipStream_t);
-template <typename T>
-void launch_residual_restart(const T *b, const T *q, T *r, T *p, const T *dinv, int64_t n,
-                             double *part, int nb, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_residual_restart<T>, dim3(nb), dim3(kBlock), 0, s, b, q, r, p, dinv, n,
-                       part);
-}
-template void launch_residual_restart<double>(const double *, const double *, double *, double *,
-                                              const double *, int64_t, double *, int, hipStream_t);
-template void launch_residual_restart<float>(const float *, const float *, float *, float *,
-                                             const float *, int64_t, double *, int, hipStream_t);
-
-void launch_ir_scale_down(const double *r64, const double *nrm2, int64_t n, float *r32, float *x32,
-                          hipStream_t s)
-{
-    hipLaunchKernelGGL(k_ir_scale_down, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, r64, nrm2, n, r32,
-                       x32);
-}
-void launch_ir_update(double *x64, const float *d32, const double *nrm2, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_ir_update, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, x64, d32, nrm2, n);
-}
 void launch_to_float(const double *a, float *b, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_to_float, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, a, b, n);
@@ -758,11 +522,5 @@ void launch_phi_update(const fo_ctx *c, const double *theta, double dt, double *
                            theta, dt, phi, c->N);
 }
 
-void launch_pcg_residual64(fo_ctx *c, const double *b, const double *q, double *r, int64_t n,
-                           int nb, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_residual64, dim3(nb), dim3(kBlock), 0, s, b, q, r, n, c->partials);
-    launch_finish_dots(c->partials, nb, 1, c->dscratch, s);
-}
 
 }  // namespace fo

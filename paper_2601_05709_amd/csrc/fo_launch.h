@@ -27,22 +27,34 @@ void launch_dots(int npair, const T *a0, const T *b0, const T *a1, const T *b1, 
                  const T *b2, int64_t n, double *part, int nb, hipStream_t s);
 void launch_finish_dots(const double *part, int nb, int npair, double *out, hipStream_t s);
 
-void launch_pcg_start(SolveScalars *sc, const double *part, int nb, double rtol2, int max_it,
-                      hipStream_t s);
-void launch_pcg_alpha(SolveScalars *sc, const double *part, int nb, hipStream_t s);
-void launch_pcg_beta(SolveScalars *sc, const double *part, int nb, hipStream_t s);
-template <typename T>
-void launch_pcg_update(const SolveScalars *sc, T *x, T *r, const T *p, T *q, const T *dinv,
-                       int64_t n, double *part, int nb, hipStream_t s);
-template <typename T>
-void launch_pcg_p(const SolveScalars *sc, T *p, const T *z, int64_t n, hipStream_t s);
-template <typename T>
-void launch_residual_restart(const T *b, const T *q, T *r, T *p, const T *dinv, int64_t n,
-                             double *part, int nb, hipStream_t s);
 
-void launch_ir_scale_down(const double *r64, const double *nrm2, int64_t n, float *r32, float *x32,
-                          hipStream_t s);
-void launch_ir_update(double *x64, const float *d32, const double *nrm2, int64_t n, hipStream_t s);
+// conjugate gradients (fo_cg.hip)
+template <typename T>
+void launch_cg_start(const T *b, const T *q, T *r, T *p, const T *dinv, int64_t n, double *part,
+                     SolveScalars *sc, double rtol, double ref2, int max_it, hipStream_t s);
+template <typename T>
+void launch_cg_update(SolveScalars *sc, int P, T *x, T *r, const T *p, const T *q, const T *dinv,
+                      int64_t n, const double *pq_part, int n_pq, double *rz_part, hipStream_t s);
+template <typename T>
+void launch_cg_direction(SolveScalars *sc, int P, T *p, const T *r, const T *dinv, int64_t n,
+                         const double *rz_part, hipStream_t s);
+void launch_ir_accumulate(double *x64, const float *x32, const double *s2, int64_t n, hipStream_t s);
+void launch_residual64(const double *b, const double *q, double *r, int64_t n, double *part,
+                       double *out2, hipStream_t s);
+// fused CG for the tiled elasticity operator
+int node_blocks(int64_t N);
+template <typename T>
+void launch_cgn_start(const fo_ctx *c, const T *b, const T *q, T *r, const T *dinv, double rtol,
+                      int max_it, hipStream_t s);
+template <typename T>
+void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *q, const T *dinv,
+                       hipStream_t s);
+template <typename T>
+int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *pout, T *q,
+                   SolveScalars *sc, int A, const double *rz_part, int rz_nb, double *pq_part,
+                   hipStream_t s);
+void launch_ir_phase(const fo_ctx *c, const double *r64, double *s2, float *r32, float *x32,
+                     const float *dinv, double phase_rtol, int max_it, int fresh, hipStream_t s);
 void launch_to_float(const double *a, float *b, int64_t n, hipStream_t s);
 
 template <typename T>
@@ -58,14 +70,16 @@ void launch_sd_rhs_atomic(const fo_ctx *c, double *rhs, hipStream_t s);
 void launch_phigrad_atomic(const fo_ctx *c, const double *phi, double *gbuf, hipStream_t s);
 void launch_phi_update(const fo_ctx *c, const double *theta, double dt, double *phi, hipStream_t s);
 
-void launch_pcg_residual64(fo_ctx *c, const double *b, const double *q, double *r, int64_t n,
-                           int nb, hipStream_t s);
 
 // tiled (deterministic) scatter
 template <typename T>
-int launch_elas_apply_tiled(const fo_ctx *c, const T *coords, const T *x, T *y, hipStream_t s);
+int launch_elas_apply_tiled(const fo_ctx *c, const T *coords, const T *x, T *y, hipStream_t s,
+                            double *dot_part = nullptr, const int32_t *done = nullptr,
+                            bool skip_halo = false);
 int launch_elas_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s);
-int launch_descent_apply_tiled(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+int launch_descent_apply_tiled(const fo_ctx *c, const double *x, double *y, hipStream_t s,
+                               const int32_t *done = nullptr);
+int tiled_prepare(const fo_ctx *c);
 int launch_descent_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s);
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s);
 int launch_phigrad_tiled(const fo_ctx *c, const double *phi, double *gbuf, hipStream_t s);

@@ -7,17 +7,20 @@
 
 namespace fo {
 
-// Ops read vertex coordinates X[a] and staged vertex values U[a] and return
-// NV values per vertex.  Element index e is in tile order.
+// An op maps one element to NV values per vertex.  `load(e)` fetches the
+// element's own data (element index e in tile order) so that kernels can
+// prefetch it; the call operator receives it with the vertex coordinates
+// X[a] and NX staged values U[a] per vertex.
 template <int D, typename T>
 struct ElasOp {
     static constexpr int NX = D, NV = D;
+    using Elem = uint8_t;
     const uint8_t *chi;
     T ersatz, lam, mu;
-    __device__ void operator()(int64_t e, const int32_t *, const T *const *X, const T *const *U,
-                               T out[D + 1][NV]) const
+    __device__ Elem load(int64_t e) const { return chi[e]; }
+    __device__ void operator()(Elem in, const T *const *X, const T *const *U, T out[D + 1][NV]) const
     {
-        T A = chi[e] ? T(1) : ersatz;
+        T A = in ? T(1) : ersatz;
         elas_element<D, T>(X, U, A, lam, mu, out);
     }
 };
@@ -25,12 +28,13 @@ struct ElasOp {
 template <int D, typename T>
 struct ElasDiagOp {
     static constexpr int NX = 0, NV = D;
+    using Elem = uint8_t;
     const uint8_t *chi;
     T ersatz, lam, mu;
-    __device__ void operator()(int64_t e, const int32_t *, const T *const *X, const T *const *,
-                               T out[D + 1][NV]) const
+    __device__ Elem load(int64_t e) const { return chi[e]; }
+    __device__ void operator()(Elem in, const T *const *X, const T *const *, T out[D + 1][NV]) const
     {
-        T A = chi[e] ? T(1) : ersatz;
+        T A = in ? T(1) : ersatz;
         elas_diag_element<D, T>(X, A, lam, mu, out);
     }
 };
@@ -38,12 +42,14 @@ struct ElasDiagOp {
 template <int D>
 struct DescentOp {
     static constexpr int NX = D, NV = D;
+    using Elem = uint8_t;
     const uint8_t *in0;
     double alpha, gamma_s;
-    __device__ void operator()(int64_t e, const int32_t *, const double *const *X,
-                               const double *const *U, double out[D + 1][NV]) const
+    __device__ Elem load(int64_t e) const { return in0[e]; }
+    __device__ void operator()(Elem in, const double *const *X, const double *const *U,
+                               double out[D + 1][NV]) const
     {
-        double mw = alpha + (in0[e] ? gamma_s : 0.0);
+        double mw = alpha + (in ? gamma_s : 0.0);
         descent_element<D, double>(X, U, mw, out);
     }
 };
@@ -51,12 +57,14 @@ struct DescentOp {
 template <int D>
 struct DescentDiagOp {
     static constexpr int NX = 0, NV = D;
+    using Elem = uint8_t;
     const uint8_t *in0;
     double alpha, gamma_s;
-    __device__ void operator()(int64_t e, const int32_t *, const double *const *X,
-                               const double *const *, double out[D + 1][NV]) const
+    __device__ Elem load(int64_t e) const { return in0[e]; }
+    __device__ void operator()(Elem in, const double *const *X, const double *const *,
+                               double out[D + 1][NV]) const
     {
-        double mw = alpha + (in0[e] ? gamma_s : 0.0);
+        double mw = alpha + (in ? gamma_s : 0.0);
         descent_diag_element<D, double>(X, mw, out);
     }
 };
@@ -65,8 +73,10 @@ struct DescentDiagOp {
 template <int D>
 struct PhiGradOp {
     static constexpr int NX = 1, NV = D + 1;
-    __device__ void operator()(int64_t, const int32_t *, const double *const *X,
-                               const double *const *U, double out[D + 1][NV]) const
+    using Elem = uint8_t;
+    __device__ Elem load(int64_t) const { return 0; }
+    __device__ void operator()(Elem, const double *const *X, const double *const *U,
+                               double out[D + 1][NV]) const
     {
         Geom<D, double> g = geom<D, double>(X);
         double adet = fabs(g.det);
@@ -96,16 +106,26 @@ struct PhiGradOp {
 template <int D>
 struct SdRhsOp {
     static constexpr int NX = 0, NV = D;
+    struct Elem {
+        double s[D * D];
+    };
     const double *s1;  // [E][D*D], tile element order
-    __device__ void operator()(int64_t e, const int32_t *, const double *const *X,
-                               const double *const *, double out[D + 1][NV]) const
+    __device__ Elem load(int64_t e) const
+    {
+        Elem v;
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) v.s[k] = s1[e * D * D + k];
+        return v;
+    }
+    __device__ void operator()(const Elem &in, const double *const *X, const double *const *,
+                               double out[D + 1][NV]) const
     {
         Geom<D, double> g = geom<D, double>(X);
         double S[D][D];
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
-            for (int j = 0; j < D; ++j) S[i][j] = s1[e * D * D + i * D + j];
+            for (int j = 0; j < D; ++j) S[i][j] = in.s[i * D + j];
         double vol = fabs(g.det) / (D == 2 ? 2.0 : 6.0);
         vertex_loads<D, double>(g, S, -vol / g.det, out);
     }

@@ -35,4 +35,33 @@ __device__ __forceinline__ double block_sum_partials(const double *part, int n, 
     return block_sum(s, lds);
 }
 
+// Sum over a block of any size that is a multiple of 64 (at most 1024
+// threads); waves are combined in a fixed order.  Valid in thread 0.
+__device__ __forceinline__ double block_sum_any(double v, double *lds /*[16]*/)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nw; ++k) s += lds[k];
+    __syncthreads();
+    return s;
+}
+
+// Every thread of the block gets the same fixed-order sum of n partials.
+__device__ __forceinline__ double block_sum_partials_any(const double *part, int n, double *lds)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+    s = block_sum_any(s, lds);
+    if (threadIdx.x == 0) lds[0] = s;
+    __syncthreads();
+    s = lds[0];
+    __syncthreads();
+    return s;
+}
+
 }  // namespace fo

@@ -1,5 +1,6 @@
 // Deterministic element-to-node scatter through LDS tiles (see fo_tiles.h),
-// and the node-parallel boundary-facet term of the descent operator.
+// the fused CG operator kernel, and the node-parallel boundary-facet term of
+// the descent operator.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,134 +15,366 @@
 namespace fo {
 
 struct TileArgs {
-    const int32_t *elem_off, *node_off, *node_int, *halo_off, *nodes, *sub_off, *seg_off;
-    const uint64_t *lconn, *lslot;  // 4 x uint16 per element
-    const uint16_t *seg_node, *seg_start;
+    const int32_t *info;            // [n_tiles][8]
+    const uint64_t *lconn, *lslot;  // [n_tiles][ME], 4 x uint16 each
+    const int32_t *nodes;           // [n_tiles][MN]
+    const uint16_t *seg;            // [n_tiles][MN+1]
+    const int32_t *hpos;            // [n_tiles][MN]
+    int ME, MN, n_tiles;
 };
 
 static TileArgs tile_args(const fo_ctx *c)
 {
     const TileSet &t = c->tiles;
-    return TileArgs{t.tile_elem_off, t.tile_node_off, t.tile_node_interior, t.tile_halo_off,
-                    t.tile_nodes,    t.sub_off,       t.seg_off,
-                    reinterpret_cast<const uint64_t *>(t.lconn),
-                    reinterpret_cast<const uint64_t *>(t.lslot), t.seg_node, t.seg_start};
+    return TileArgs{t.info, reinterpret_cast<const uint64_t *>(t.lconn),
+                    reinterpret_cast<const uint64_t *>(t.lslot), t.nodes, t.seg, t.hpos,
+                    t.max_elems, t.max_nodes, t.n_tiles};
 }
 
-// One block per tile.  LDS: node coordinates [nn][D], staged inputs [nn][NX],
-// node accumulators [nn][NV], sub-batch slots [kSub*(D+1)][NV].
+// Blocks are dealt to the XCDs round-robin; give each XCD a contiguous run of
+// tiles (spatial neighbours) so shared nodes are fetched into one L2.
+// Launch with xcd_grid(n_tiles) blocks; returns -1 for the few spare blocks.
+__device__ __forceinline__ int xcd_tile(int b, int n_tiles)
+{
+    const int per = (n_tiles + 7) >> 3;
+    const int t = (b & 7) * per + (b >> 3);
+    return t < n_tiles ? t : -1;
+}
+
+static int xcd_grid(int n_tiles) { return 8 * ((n_tiles + 7) / 8); }
+
+// Element phase shared by the tile kernels: thread = element of the tile;
+// writes its (d+1) x NV vertex values into the node-sorted LDS slots.
 template <int D, typename T, class Op>
-__global__ __launch_bounds__(kSub) void k_tile_scatter(Op op, TileArgs ta,
-                                                       const T *__restrict__ coords,
-                                                       const T *__restrict__ xin,
-                                                       T *__restrict__ out, T *__restrict__ halo,
-                                                       const uint8_t *__restrict__ fixed)
+__device__ __forceinline__ void tile_elements(const Op &op, typename Op::Elem ed, uint64_t lc,
+                                              uint64_t ls, const T *sX, const T *sU, T *sS)
 {
     constexpr int NX = Op::NX, NV = Op::NV;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *smem = reinterpret_cast<T *>(smem_raw);
-    const int t = blockIdx.x;
-    const int n0 = ta.node_off[t];
-    const int nn = ta.node_off[t + 1] - n0;
-    const int nint = ta.node_int[t];
-    T *sX = smem;
-    T *sU = sX + nn * D;
-    T *sA = sU + nn * NX;
-    T *sS = sA + nn * NV;
-    for (int l = threadIdx.x; l < nn; l += kSub) {
-        int64_t g = ta.nodes[n0 + l];
+    const T *Xp[D + 1];
+    const T *Up[D + 1];
 #pragma unroll
-        for (int i = 0; i < D; ++i) sX[l * D + i] = coords[g * D + i];
-#pragma unroll
-        for (int k = 0; k < NX; ++k) sU[l * NX + k] = xin[g * NX + k];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sA[l * NV + v] = T(0);
+    for (int a = 0; a <= D; ++a) {
+        int l = (int)((lc >> (16 * a)) & 0xFFFF);
+        Xp[a] = sX + l * D;
+        Up[a] = sU + l * NX;
     }
-    __syncthreads();
-    const int e0 = ta.elem_off[t], e1 = ta.elem_off[t + 1];
-    const int s0 = ta.sub_off[t], s1 = ta.sub_off[t + 1];
-    for (int sb = s0; sb < s1; ++sb) {
-        int i = e0 + (sb - s0) * kSub + threadIdx.x;
-        if (i < e1) {
-            uint64_t lc = ta.lconn[i], ls = ta.lslot[i];
-            const T *Xp[D + 1];
-            const T *Up[D + 1];
-            int32_t unused[D + 1];
+    T res[D + 1][NV];
+    op(ed, Xp, Up, res);
 #pragma unroll
-            for (int a = 0; a <= D; ++a) {
-                int l = (int)((lc >> (16 * a)) & 0xFFFF);
-                Xp[a] = sX + l * D;
-                Up[a] = sU + l * NX;
-                unused[a] = l;
-            }
-            T res[D + 1][NV];
-            op(i, unused, Xp, Up, res);
+    for (int a = 0; a <= D; ++a) {
+        int sl = (int)((ls >> (16 * a)) & 0xFFFF);
 #pragma unroll
-            for (int a = 0; a <= D; ++a) {
-                int sl = (int)((ls >> (16 * a)) & 0xFFFF);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) sS[sl * NV + v] = res[a][v];
-            }
-        }
-        __syncthreads();
-        const int g0 = ta.seg_off[sb], g1 = ta.seg_off[sb + 1] - 1;  // last entry = sentinel
-        for (int s = g0 + threadIdx.x; s < g1; s += kSub) {
-            int node = ta.seg_node[s];
-            int a = ta.seg_start[s], b = ta.seg_start[s + 1];
-            T acc[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] = T(0);
-            for (int k = a; k < b; ++k)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] += sS[k * NV + v];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sA[node * NV + v] += acc[v];
-        }
-        __syncthreads();
-    }
-    const int hoff = ta.halo_off[t];
-    for (int l = threadIdx.x; l < nn; l += kSub) {
-        int64_t g = ta.nodes[n0 + l];
-        if (l < nint) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T val = sA[l * NV + v];
-                if (fixed && fixed[g * NV + v]) val = T(0);
-                out[g * NV + v] = val;
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) halo[(int64_t)(hoff + l - nint) * NV + v] = sA[l * NV + v];
-        }
+        for (int v = 0; v < NV; ++v) sS[sl * NV + v] = res[a][v];
     }
 }
 
-// Shared nodes: sum the halo slots of each node in tile order.
-template <typename T, int NV>
-__global__ void k_halo(const int32_t *__restrict__ hnode, const int32_t *__restrict__ hptr,
-                       const int32_t *__restrict__ hsrc, int64_t S, const T *__restrict__ halo,
-                       T *__restrict__ out, const uint8_t *__restrict__ fixed)
+// Generic scatter: out = sum over elements of op(element) at its vertices.
+// One block per tile, one thread per element (blockDim >= elements and nodes
+// of every tile).  LDS: node coordinates [nn][D], staged inputs [nn][NX],
+// slots [ne*(d+1)][NV].  Interior nodes are written to `out` (zero on clamped
+// unknowns when `fixed` is given); shared nodes to their halo slot.
+// Optional dot_part[tile] = sum over the tile's nodes of xin . (the tile's
+// share of the output), so the partials add up to xin . out (NX == NV).
+// `done` (nullable) turns the launch into a no-op.
+template <int D, typename T, class Op>
+__global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
+                                                     const T *__restrict__ coords,
+                                                     const T *__restrict__ xin,
+                                                     T *__restrict__ out, T *__restrict__ halo,
+                                                     const uint8_t *__restrict__ fixed,
+                                                     double *__restrict__ dot_part,
+                                                     const int32_t *__restrict__ done)
 {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int64_t g = hnode[k];
+    constexpr int NX = Op::NX, NV = Op::NV;
+    using Elem = typename Op::Elem;
+    if (done && *done) return;
+    const int t = xcd_tile(blockIdx.x, ta.n_tiles);
+    if (t < 0) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *smem = reinterpret_cast<T *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int32_t *inf = ta.info + (int64_t)t * kTileInfo;
+    const int e0 = inf[kTileE0], ne = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt];
+    T *sX = smem;
+    T *sU = sX + nn * D;
+    T *sS = sU + nn * NX;
+
+    uint64_t lc = 0, ls = 0;
+    Elem ed{};
+    if (tid < ne) {
+        lc = ta.lconn[(int64_t)t * ta.ME + tid];
+        ls = ta.lslot[(int64_t)t * ta.ME + tid];
+        ed = op.load(e0 + tid);
+    }
+    int64_t g = 0;
+    int sa = 0, sb = 0, hp = -1;
+    if (tid < nn) {
+        const int64_t tn = (int64_t)t * ta.MN + tid;
+        g = ta.nodes[tn];
+        hp = ta.hpos[tn];
+        sa = ta.seg[(int64_t)t * (ta.MN + 1) + tid];
+        sb = ta.seg[(int64_t)t * (ta.MN + 1) + tid + 1];
+        T xv[D], uv[NX > 0 ? NX : 1];
+#pragma unroll
+        for (int q = 0; q < D; ++q) xv[q] = coords[g * D + q];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) uv[k] = xin[g * NX + k];
+#pragma unroll
+        for (int q = 0; q < D; ++q) sX[tid * D + q] = xv[q];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) sU[tid * NX + k] = uv[k];
+    }
+    __syncthreads();
+    if (tid < ne) tile_elements<D, T, Op>(op, ed, lc, ls, sX, sU, sS);
+    __syncthreads();
+    double dsum = 0.0;
+    if (tid < nn) {
         T acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = T(0);
-        for (int j = hptr[k]; j < hptr[k + 1]; ++j) {
-            int64_t src = hsrc[j];
+        for (int k = sa; k < sb; ++k)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += halo[src * NV + v];
+            for (int v = 0; v < NV; ++v) acc[v] += sS[k * NV + v];
+        if (tid < nint) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T val = acc[v];
+                if (fixed && fixed[g * NV + v]) val = T(0);
+                out[g * NV + v] = val;
+                if constexpr (NX == NV) dsum += (double)sU[tid * NX + v] * (double)val;
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                halo[(int64_t)hp * NV + v] = acc[v];
+                if constexpr (NX == NV) {
+                    bool fx = fixed && fixed[g * NV + v];
+                    dsum += fx ? 0.0 : (double)sU[tid * NX + v] * (double)acc[v];
+                }
+            }
         }
+    }
+    if (dot_part) {
+        __shared__ double lds[16];
+        double s = block_sum_any(dsum, lds);
+        if (tid == 0) dot_part[t] = s;
+    }
+}
+
+// Operator kernel of one fused CG iteration (elasticity, tiled):
+//   rho_k = r.D^-1 r, rr_k = r.r from the partials of the previous update;
+//   convergence test; beta = rho_k / rho_{k-1} (or the slot's first-iteration
+//   coefficient); p_k = D^-1 r + beta p_{k-1} at node staging (the owner tile
+//   writes p_k); q = K p_k with interior nodes in q and shared nodes in the
+//   halo; pq_part[tile] = p_k . (the tile's share of q).
+// Reads scalar slot A, writes slot A ^ 1 (block 0).
+template <int D, typename T>
+__global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
+                                                  const T *__restrict__ coords,
+                                                  const T *__restrict__ r,
+                                                  const T *__restrict__ dinv,
+                                                  const T *__restrict__ pin, T *__restrict__ pout,
+                                                  T *__restrict__ q, T *__restrict__ halo,
+                                                  const uint8_t *__restrict__ fixed,
+                                                  SolveScalars *sc, int A,
+                                                  const double *__restrict__ rz_part, int rz_nb,
+                                                  double *__restrict__ pq_part)
+{
+    using Op = ElasOp<D, T>;
+    constexpr int NV = D;
+    __shared__ double lds[16];
+    __shared__ double s_beta;
+    __shared__ int s_go;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int t = xcd_tile(blockIdx.x, ta.n_tiles);
+    const int tid = threadIdx.x;
+    if (t < 0) return;
+    if (sc[A].done) {
+        if (t == 0 && tid == 0) sc[A ^ 1] = sc[A];
+        return;
+    }
+    // issue the element and node index loads before the reductions
+    const int32_t *inf = ta.info + (int64_t)t * kTileInfo;
+    const int e0 = inf[kTileE0], ne = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt],
+              nown = inf[kTileNOwn];
+    uint64_t lc = 0, ls = 0;
+    uint8_t ed = 0;
+    if (tid < ne) {
+        lc = ta.lconn[(int64_t)t * ta.ME + tid];
+        ls = ta.lslot[(int64_t)t * ta.ME + tid];
+        ed = op.load(e0 + tid);
+    }
+    int64_t g = 0;
+    int sa = 0, sb = 0, hp = -1;
+    if (tid < nn) {
+        const int64_t tn = (int64_t)t * ta.MN + tid;
+        g = ta.nodes[tn];
+        hp = ta.hpos[tn];
+        sa = ta.seg[(int64_t)t * (ta.MN + 1) + tid];
+        sb = ta.seg[(int64_t)t * (ta.MN + 1) + tid + 1];
+    }
+    const double rho_k = block_sum_partials_any(rz_part, rz_nb, lds);
+    const double rr_k = block_sum_partials_any(rz_part + rz_nb, rz_nb, lds);
+    if (tid == 0) {
+        const SolveScalars cur = sc[A];
+        const bool bad = !(rho_k >= 0.0) || rho_k != rho_k || rr_k != rr_k ||
+                         rho_k == INFINITY || rr_k == INFINITY;
+        const bool stop = bad || rr_k <= cur.tol2 || cur.it >= cur.max_it;
+        s_go = !stop;
+        s_beta = cur.first ? cur.beta : (cur.rho > 0.0 ? rho_k / cur.rho : 0.0);
+        if (t == 0) {
+            SolveScalars nx = cur;
+            nx.rr = rr_k;
+            nx.rho_new = rho_k;
+            if (stop) {
+                nx.done = 1;
+                nx.status = bad ? FO_ERR_BREAKDOWN : 0;
+            } else {
+                nx.rho = rho_k;
+                nx.beta = s_beta;
+                nx.first = 0;
+                nx.it = cur.it + 1;
+            }
+            sc[A ^ 1] = nx;
+        }
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const T beta = (T)s_beta;
+    const bool fresh = beta == T(0);
+    T *smem = reinterpret_cast<T *>(smem_raw);
+    T *sX = smem;
+    T *sU = sX + nn * D;
+    T *sS = sU + nn * D;
+    if (tid < nn) {
+        T xv[D], pv[D];
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            xv[v] = coords[g * D + v];
+            T z = dinv[g * D + v] * r[g * D + v];
+            pv[v] = fresh ? z : z + beta * pin[g * D + v];
+        }
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            sX[tid * D + v] = xv[v];
+            sU[tid * D + v] = pv[v];
+        }
+        if (tid < nown)
+#pragma unroll
+            for (int v = 0; v < D; ++v) pout[g * D + v] = pv[v];
+    }
+    __syncthreads();
+    if (tid < ne) tile_elements<D, T, Op>(op, ed, lc, ls, sX, sU, sS);
+    __syncthreads();
+    double dsum = 0.0;
+    if (tid < nn) {
+        T acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = T(0);
+        for (int k = sa; k < sb; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += sS[k * NV + v];
+        if (tid < nint) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T val = fixed[g * NV + v] ? T(0) : acc[v];
+                q[g * NV + v] = val;
+                dsum += (double)sU[tid * D + v] * (double)val;
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                halo[(int64_t)hp * NV + v] = acc[v];
+                dsum += fixed[g * NV + v] ? 0.0 : (double)sU[tid * D + v] * (double)acc[v];
+            }
+        }
+    }
+    const double s = block_sum_any(dsum, lds);
+    if (tid == 0) pq_part[t] = s;
+}
+
+// Shared nodes: sum the node's halo slots (contiguous, in tile order).
+template <typename T, int NV>
+__global__ void k_halo(const int32_t *__restrict__ hnode, const int32_t *__restrict__ hptr,
+                       int64_t S, const T *__restrict__ halo, T *__restrict__ out,
+                       const uint8_t *__restrict__ fixed, const int32_t *__restrict__ done)
+{
+    if (done && *done) return;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t g = hnode[k];
+        int j0 = hptr[k], j1 = hptr[k + 1];
+        T acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = T(0);
+        for (int j = j0; j < j1; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += halo[(int64_t)j * NV + v];
 #pragma unroll
         for (int v = 0; v < NV; ++v) out[g * NV + v] = (fixed && fixed[g * NV + v]) ? T(0) : acc[v];
     }
 }
 
-template <int D, typename T, class Op>
-static size_t tile_lds_bytes(int max_nodes)
+// ---------------------------------------------------------------------------
+// launch configuration
+
+template <int D, typename T, int NX, int NV>
+static size_t tile_lds_bytes(int max_nodes, int max_elems)
 {
-    return ((size_t)max_nodes * (D + Op::NX + Op::NV) + (size_t)kSub * (D + 1) * Op::NV) * sizeof(T);
+    return ((size_t)max_nodes * (D + NX) + (size_t)max_elems * (D + 1) * NV) * sizeof(T);
+}
+
+static int tile_threads(const fo_ctx *c)
+{
+    int m = std::max(c->tiles.max_elems, c->tiles.max_nodes);
+    return std::min(1024, (m + 63) / 64 * 64);
+}
+
+static int set_lds(const void *fn, size_t cap)
+{
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap) !=
+           hipSuccess;
+}
+
+// Allows the dynamic LDS of the largest possible tile, once per kernel
+// instance (must happen outside graph capture: see tiled_prepare).
+template <int D, typename T, class Op>
+static int ensure_lds_attr()
+{
+    static bool done = false;
+    if (done) return 0;
+    size_t cap = tile_lds_bytes<D, T, Op::NX, Op::NV>(tile_max_nodes(D), tile_max_elems(D));
+    if (set_lds((const void *)k_tile_apply<D, T, Op>, cap)) return 1;
+    done = true;
+    return 0;
+}
+
+template <int D, typename T>
+static int ensure_lds_attr_cg()
+{
+    static bool done = false;
+    if (done) return 0;
+    size_t cap = tile_lds_bytes<D, T, D, D>(tile_max_nodes(D), tile_max_elems(D));
+    if (set_lds((const void *)k_tile_cg<D, T>, cap)) return 1;
+    done = true;
+    return 0;
+}
+
+template <int D>
+static int prepare_dim()
+{
+    return ensure_lds_attr<D, double, ElasOp<D, double>>() | ensure_lds_attr<D, float, ElasOp<D, float>>() |
+           ensure_lds_attr<D, double, ElasDiagOp<D, double>>() | ensure_lds_attr<D, double, DescentOp<D>>() |
+           ensure_lds_attr<D, double, DescentDiagOp<D>>() | ensure_lds_attr<D, double, SdRhsOp<D>>() |
+           ensure_lds_attr<D, double, PhiGradOp<D>>() | ensure_lds_attr_cg<D, double>() |
+           ensure_lds_attr_cg<D, float>();
+}
+
+int tiled_prepare(const fo_ctx *c)
+{
+    if (c->tiles.max_nodes > tile_max_nodes(c->dim) || c->tiles.max_elems > tile_max_elems(c->dim))
+        return FO_ERR_MESH;
+    return (c->dim == 2 ? prepare_dim<2>() : prepare_dim<3>()) ? FO_ERR_HIP : FO_OK;
 }
 
 // Event pair for one timed launch (fo_profile_enable), or null when off.
@@ -165,35 +398,68 @@ static std::pair<hipEvent_t, hipEvent_t> *prof_slot(const fo_ctx *cc, int which)
 
 template <int D, typename T, class Op>
 static int run_tiled(const fo_ctx *c, const Op &op, const T *coords, const T *xin, T *out,
-                     const uint8_t *fixed, hipStream_t s, int prof_tile = -1, int prof_halo = -1)
+                     const uint8_t *fixed, hipStream_t s, int prof_tile = -1, int prof_halo = -1,
+                     double *dot_part = nullptr, const int32_t *done = nullptr,
+                     bool skip_halo = false)
 {
-    size_t lds = tile_lds_bytes<D, T, Op>(c->tiles.max_nodes);
-    static bool attr_done = false;  // one per template instance: allow the largest tile
-    if (!attr_done) {
-        size_t cap = tile_lds_bytes<D, T, Op>(tile_max_nodes(D));
-        if (hipFuncSetAttribute((const void *)k_tile_scatter<D, T, Op>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap) != hipSuccess)
-            return FO_ERR_HIP;
-        attr_done = true;
-    }
-    if (c->tiles.max_nodes > tile_max_nodes(D)) return FO_ERR_MESH;
+    size_t lds = tile_lds_bytes<D, T, Op::NX, Op::NV>(c->tiles.max_nodes, c->tiles.max_elems);
+    if (ensure_lds_attr<D, T, Op>()) return FO_ERR_HIP;
     auto *pt = prof_slot(c, prof_tile);
     if (pt) (void)hipEventRecord(pt->first, s);
-    hipLaunchKernelGGL((k_tile_scatter<D, T, Op>), dim3(c->tiles.n_tiles), dim3(kSub), lds, s, op,
-                       tile_args(c), coords, xin, out, reinterpret_cast<T *>(c->halo), fixed);
+    hipLaunchKernelGGL((k_tile_apply<D, T, Op>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds,
+                       s, op, tile_args(c), coords, xin, out, reinterpret_cast<T *>(c->halo), fixed,
+                       dot_part, done);
     if (pt) (void)hipEventRecord(pt->second, s);
-    if (c->tiles.n_shared_nodes > 0) {
+    if (c->tiles.n_shared_nodes > 0 && !skip_halo) {
         int64_t S = c->tiles.n_shared_nodes;
         int nb = (int)std::min<int64_t>((S + 255) / 256, 65535);
         auto *ph = prof_slot(c, prof_halo);
         if (ph) (void)hipEventRecord(ph->first, s);
         hipLaunchKernelGGL((k_halo<T, Op::NV>), dim3(nb), dim3(256), 0, s, c->tiles.halo_node,
-                           c->tiles.halo_ptr, c->tiles.halo_src, S,
-                           reinterpret_cast<const T *>(c->halo), out, fixed);
+                           c->tiles.halo_ptr, S, reinterpret_cast<const T *>(c->halo), out, fixed,
+                           done);
         if (ph) (void)hipEventRecord(ph->second, s);
     }
     return FO_OK;
 }
+
+template <typename T>
+int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *pout, T *q,
+                   SolveScalars *sc, int A, const double *rz_part, int rz_nb, double *pq_part,
+                   hipStream_t s)
+{
+    const int D = c->dim;
+    const int which = sizeof(T) == 8 ? FO_PROF_ELAS_TILE_FP64 : FO_PROF_ELAS_TILE_FP32;
+    auto *pt = prof_slot(c, which);
+    if (pt) (void)hipEventRecord(pt->first, s);
+    const T *coords;
+    if constexpr (sizeof(T) == 8) coords = c->coords;
+    else coords = c->coords32;
+    T *halo = reinterpret_cast<T *>(c->halo);
+    if (D == 2) {
+        if (ensure_lds_attr_cg<2, T>()) return FO_ERR_HIP;
+        size_t lds = tile_lds_bytes<2, T, 2, 2>(c->tiles.max_nodes, c->tiles.max_elems);
+        hipLaunchKernelGGL((k_tile_cg<2, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
+                           ElasOp<2, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
+                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, rz_part, rz_nb,
+                           pq_part);
+    } else {
+        if (ensure_lds_attr_cg<3, T>()) return FO_ERR_HIP;
+        size_t lds = tile_lds_bytes<3, T, 3, 3>(c->tiles.max_nodes, c->tiles.max_elems);
+        hipLaunchKernelGGL((k_tile_cg<3, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
+                           ElasOp<3, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
+                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, rz_part, rz_nb,
+                           pq_part);
+    }
+    if (pt) (void)hipEventRecord(pt->second, s);
+    return FO_OK;
+}
+template int launch_tile_cg<double>(const fo_ctx *, const double *, const double *, const double *,
+                                    double *, double *, SolveScalars *, int, const double *, int,
+                                    double *, hipStream_t);
+template int launch_tile_cg<float>(const fo_ctx *, const float *, const float *, const float *,
+                                   float *, float *, SolveScalars *, int, const double *, int,
+                                   double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // boundary facets of the descent operator, node-parallel (deterministic)
@@ -224,8 +490,10 @@ __global__ void k_facet_nodes(const int32_t *__restrict__ bnode, const int32_t *
                               const int32_t *__restrict__ bfac, int64_t NB,
                               const int32_t *__restrict__ bf, const double *__restrict__ bn,
                               int64_t F, const double *__restrict__ coords, double gamma_n,
-                              const double *__restrict__ x, double *__restrict__ y)
+                              const double *__restrict__ x, double *__restrict__ y,
+                              const int32_t *__restrict__ done)
 {
+    if (done && *done) return;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < NB;
          k += (int64_t)gridDim.x * blockDim.x) {
         int64_t g = bnode[k];
@@ -258,18 +526,19 @@ __global__ void k_facet_nodes(const int32_t *__restrict__ bnode, const int32_t *
     }
 }
 
-static void facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t s)
+static void facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t s,
+                        const int32_t *done = nullptr)
 {
     if (c->n_bnodes == 0 || c->descent.gamma_n == 0.0) return;
     int nb = (int)std::min<int64_t>((c->n_bnodes + 255) / 256, 65535);
     if (c->dim == 2)
         hipLaunchKernelGGL(k_facet_nodes<2>, dim3(nb), dim3(256), 0, s, c->bnodes, c->bnode_ptr,
                            c->bnode_fac, c->n_bnodes, c->bfacets, c->bnormal, c->nbf, c->coords,
-                           c->descent.gamma_n, x, y);
+                           c->descent.gamma_n, x, y, done);
     else
         hipLaunchKernelGGL(k_facet_nodes<3>, dim3(nb), dim3(256), 0, s, c->bnodes, c->bnode_ptr,
                            c->bnode_fac, c->n_bnodes, c->bfacets, c->bnormal, c->nbf, c->coords,
-                           c->descent.gamma_n, x, y);
+                           c->descent.gamma_n, x, y, done);
 }
 
 void launch_facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t s)
@@ -281,21 +550,22 @@ void launch_facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t
 // tiled launchers
 
 template <typename T>
-int launch_elas_apply_tiled(const fo_ctx *c, const T *coords, const T *x, T *y, hipStream_t s)
+int launch_elas_apply_tiled(const fo_ctx *c, const T *coords, const T *x, T *y, hipStream_t s,
+                            double *dot_part, const int32_t *done, bool skip_halo)
 {
     const bool f64 = sizeof(T) == 8;
     const int pt = f64 ? FO_PROF_ELAS_TILE_FP64 : FO_PROF_ELAS_TILE_FP32;
     const int ph = f64 ? FO_PROF_HALO_FP64 : FO_PROF_HALO_FP32;
     if (c->dim == 2)
         return run_tiled<2, T>(c, ElasOp<2, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, coords,
-                               x, y, c->fixed, s, pt, ph);
+                               x, y, c->fixed, s, pt, ph, dot_part, done, skip_halo);
     return run_tiled<3, T>(c, ElasOp<3, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, coords, x,
-                           y, c->fixed, s, pt, ph);
+                           y, c->fixed, s, pt, ph, dot_part, done, skip_halo);
 }
 template int launch_elas_apply_tiled<double>(const fo_ctx *, const double *, const double *,
-                                             double *, hipStream_t);
+                                             double *, hipStream_t, double *, const int32_t *, bool);
 template int launch_elas_apply_tiled<float>(const fo_ctx *, const float *, const float *, float *,
-                                            hipStream_t);
+                                            hipStream_t, double *, const int32_t *, bool);
 
 int launch_elas_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s)
 {
@@ -306,18 +576,19 @@ int launch_elas_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s)
                                 c->coords, (const double *)nullptr, diag, nullptr, s);
 }
 
-int launch_descent_apply_tiled(const fo_ctx *c, const double *x, double *y, hipStream_t s)
+int launch_descent_apply_tiled(const fo_ctx *c, const double *x, double *y, hipStream_t s,
+                               const int32_t *done)
 {
     const DescentSetup &d = c->descent;
     int rc;
     if (c->dim == 2)
         rc = run_tiled<2, double>(c, DescentOp<2>{d.in0, d.alpha, d.gamma_s}, c->coords, x, y,
-                                  nullptr, s);
+                                  nullptr, s, -1, -1, nullptr, done);
     else
         rc = run_tiled<3, double>(c, DescentOp<3>{d.in0, d.alpha, d.gamma_s}, c->coords, x, y,
-                                  nullptr, s);
+                                  nullptr, s, -1, -1, nullptr, done);
     if (rc) return rc;
-    facet_terms(c, x, y, s);
+    facet_terms(c, x, y, s, done);
     return FO_OK;
 }
 
@@ -375,23 +646,18 @@ int upload_tiles(fo_ctx *c, const HostTiles &h)
     TileSet &t = c->tiles;
     t.n_tiles = h.n_tiles;
     t.max_nodes = h.max_nodes;
-    t.max_sub = h.max_sub;
-    t.n_slots = (int64_t)h.tile_nodes.size();
+    t.max_elems = h.max_elems;
+    t.n_slots = h.n_slots;
     t.n_shared_nodes = (int64_t)h.halo_node.size();
-    t.n_shared_slots = (int64_t)h.halo_src.size();
+    t.n_shared_slots = h.halo_ptr.empty() ? 0 : (int64_t)h.halo_ptr.back();
     int rc;
-    if ((rc = up_vec(c, &t.tile_elem_off, h.tile_elem_off)) ||
-        (rc = up_vec(c, &t.tile_node_off, h.tile_node_off)) ||
-        (rc = up_vec(c, &t.tile_node_interior, h.tile_node_interior)) ||
-        (rc = up_vec(c, &t.tile_halo_off, h.tile_halo_off)) ||
-        (rc = up_vec(c, &t.tile_nodes, h.tile_nodes)) || (rc = up_vec(c, &t.lconn, h.lconn)) ||
-        (rc = up_vec(c, &t.lslot, h.lslot)) || (rc = up_vec(c, &t.sub_off, h.sub_off)) ||
-        (rc = up_vec(c, &t.seg_off, h.seg_off)) || (rc = up_vec(c, &t.seg_node, h.seg_node)) ||
-        (rc = up_vec(c, &t.seg_start, h.seg_start)) || (rc = up_vec(c, &t.halo_node, h.halo_node)) ||
-        (rc = up_vec(c, &t.halo_ptr, h.halo_ptr)) || (rc = up_vec(c, &t.halo_src, h.halo_src)))
+    if ((rc = up_vec(c, &t.info, h.info)) || (rc = up_vec(c, &t.lconn, h.lconn)) ||
+        (rc = up_vec(c, &t.lslot, h.lslot)) || (rc = up_vec(c, &t.nodes, h.nodes)) ||
+        (rc = up_vec(c, &t.seg, h.seg)) || (rc = up_vec(c, &t.hpos, h.hpos)) ||
+        (rc = up_vec(c, &t.halo_node, h.halo_node)) || (rc = up_vec(c, &t.halo_ptr, h.halo_ptr)) ||
+        (rc = up_vec(c, &t.node_hrange, h.node_hrange)))
         return rc;
     // halo partials: widest op has d+1 values per node
-    std::vector<double> zero;
     size_t n = std::max<size_t>((size_t)t.n_shared_slots * (c->dim + 1), 1);
     void *p = nullptr;
     if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;

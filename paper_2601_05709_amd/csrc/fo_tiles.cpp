@@ -8,8 +8,15 @@
 
 namespace fo {
 
-int tile_max_nodes(int dim) { return dim == 2 ? 1024 : 768; }
-int tile_max_elems(int dim) { return dim == 2 ? 2048 : 3072; }
+int tile_max_nodes(int dim) { return dim == 2 ? 512 : 320; }
+int tile_max_elems(int dim) { return dim == 2 ? 512 : 512; }
+
+int tile_target_elems(int dim, int64_t E, int cus)
+{
+    int64_t per = E / std::max<int64_t>(8 * (int64_t)std::max(cus, 1), 1);
+    per = (per + 63) / 64 * 64;
+    return (int)std::min<int64_t>(std::max<int64_t>(per, 128), tile_max_elems(dim));
+}
 
 namespace {
 
@@ -38,7 +45,8 @@ uint64_t spread2(uint64_t v)
 
 }  // namespace
 
-void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *conn, HostTiles *h)
+void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *conn, int max_elems,
+                 HostTiles *h)
 {
     const int NV = D + 1;
     // 1. Morton order of element centroids in the bounding cube
@@ -74,9 +82,10 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
     key.shrink_to_fit();
 
     // 2. greedy tiles bounded by element and node counts
-    const int max_n = tile_max_nodes(D), max_e = tile_max_elems(D);
+    const int max_n = tile_max_nodes(D);
+    const int max_e = std::min(std::max(max_elems, 1), tile_max_elems(D));
     std::vector<int32_t> mark(N, -1);  // tile currently holding the node
-    h->tile_elem_off.assign(1, 0);
+    h->tile_elem_off_tmp.assign(1, 0);
     {
         int32_t tile = 0;
         int nn = 0, ne = 0;
@@ -86,7 +95,7 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
             for (int a = 0; a < NV; ++a)
                 if (mark[conn[a * E + e]] != tile) ++fresh;
             if (ne > 0 && (ne + 1 > max_e || nn + fresh > max_n)) {
-                h->tile_elem_off.push_back((int32_t)i);
+                h->tile_elem_off_tmp.push_back((int32_t)i);
                 ++tile;
                 nn = ne = 0;
             }
@@ -99,42 +108,41 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
             }
             ++ne;
         }
-        h->tile_elem_off.push_back((int32_t)E);
+        h->tile_elem_off_tmp.push_back((int32_t)E);
     }
-    const int32_t T = (int32_t)h->tile_elem_off.size() - 1;
+    const int32_t T = (int32_t)h->tile_elem_off_tmp.size() - 1;
     h->n_tiles = T;
 
     // 3. how many tiles touch each node; owner = first tile touching it
-    std::vector<int32_t> ntouch(N, 0);
-    h->owner_tile.assign(N, -1);
+    std::vector<int32_t> ntouch(N, 0), owner(N, -1);
     std::fill(mark.begin(), mark.end(), -1);
     for (int32_t t = 0; t < T; ++t)
-        for (int32_t i = h->tile_elem_off[t]; i < h->tile_elem_off[t + 1]; ++i) {
+        for (int32_t i = h->tile_elem_off_tmp[t]; i < h->tile_elem_off_tmp[t + 1]; ++i) {
             int32_t e = h->perm[i];
             for (int a = 0; a < NV; ++a) {
                 int32_t n = conn[a * E + e];
                 if (mark[n] != t) {
                     mark[n] = t;
                     ++ntouch[n];
-                    if (h->owner_tile[n] < 0) h->owner_tile[n] = t;
+                    if (owner[n] < 0) owner[n] = t;
                 }
             }
         }
 
-    // 4. per tile: local numbering (interior first), local conn, sub-batch slots
-    h->tile_node_off.assign(1, 0);
-    h->tile_node_interior.resize(T);
-    h->tile_halo_off.resize(T);
-    h->lconn.assign((size_t)E * 4, 0);
-    h->lslot.assign((size_t)E * 4, 0);
-    h->sub_off.assign(1, 0);
-    h->seg_off.assign(1, 0);
-    h->tile_nodes.clear();
+    // 4. per tile: local numbering (interior, owned shared, other shared),
+    //    local connectivity and node-sorted LDS slots (unpadded first)
+    struct Tile {
+        int32_t e0, ne, nint, nown;
+        std::vector<int32_t> nodes;
+        std::vector<uint16_t> seg;
+    };
+    std::vector<Tile> tiles(T);
+    std::vector<uint16_t> lconn((size_t)E * 4, 0), lslot((size_t)E * 4, 0);
     std::vector<int32_t> local(N, -1);
-    std::vector<int32_t> inter, shared;
-    int32_t halo_total = 0;
+    std::vector<int32_t> inter, own, other;
     h->max_nodes = 0;
-    h->max_sub = 0;
+    h->max_elems = 0;
+    h->n_slots = 0;
     struct SlotKey {
         uint16_t node;
         uint16_t elem;
@@ -143,73 +151,68 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
     std::vector<SlotKey> keys;
     for (int32_t t = 0; t < T; ++t) {
         inter.clear();
-        shared.clear();
-        int32_t e0 = h->tile_elem_off[t], e1 = h->tile_elem_off[t + 1];
+        own.clear();
+        other.clear();
+        const int32_t e0 = h->tile_elem_off_tmp[t], e1 = h->tile_elem_off_tmp[t + 1];
         for (int32_t i = e0; i < e1; ++i) {
             int32_t e = h->perm[i];
             for (int a = 0; a < NV; ++a) {
                 int32_t n = conn[a * E + e];
                 if (local[n] == -1) {
                     local[n] = -2;
-                    (ntouch[n] == 1 ? inter : shared).push_back(n);
+                    (ntouch[n] == 1 ? inter : owner[n] == t ? own : other).push_back(n);
                 }
             }
         }
         std::sort(inter.begin(), inter.end());
-        std::sort(shared.begin(), shared.end());
+        std::sort(own.begin(), own.end());
+        std::sort(other.begin(), other.end());
+        Tile &tl = tiles[t];
+        tl.e0 = e0;
+        tl.ne = e1 - e0;
+        tl.nint = (int32_t)inter.size();
+        tl.nown = (int32_t)(inter.size() + own.size());
         int32_t li = 0;
-        for (int32_t n : inter) {
-            local[n] = li++;
-            h->tile_nodes.push_back(n);
-        }
-        for (int32_t n : shared) {
-            local[n] = li++;
-            h->tile_nodes.push_back(n);
-        }
-        h->tile_node_off.push_back((int32_t)h->tile_nodes.size());
-        h->tile_node_interior[t] = (int32_t)inter.size();
-        h->tile_halo_off[t] = halo_total;
-        halo_total += (int32_t)shared.size();
+        for (const std::vector<int32_t> *grp : {&inter, &own, &other})
+            for (int32_t n : *grp) {
+                local[n] = li++;
+                tl.nodes.push_back(n);
+            }
+        h->n_slots += li;
         h->max_nodes = std::max(h->max_nodes, li);
+        h->max_elems = std::max(h->max_elems, tl.ne);
+        keys.clear();
         for (int32_t i = e0; i < e1; ++i) {
             int32_t e = h->perm[i];
-            for (int a = 0; a < NV; ++a) h->lconn[(size_t)i * 4 + a] = (uint16_t)local[conn[a * E + e]];
-        }
-        int nsub = 0;
-        for (int32_t s0 = e0; s0 < e1; s0 += kSub) {
-            int32_t s1 = std::min(e1, s0 + kSub);
-            keys.clear();
-            for (int32_t i = s0; i < s1; ++i)
-                for (int a = 0; a < NV; ++a)
-                    keys.push_back({h->lconn[(size_t)i * 4 + a], (uint16_t)(i - s0), (uint8_t)a});
-            std::sort(keys.begin(), keys.end(), [](const SlotKey &x, const SlotKey &y) {
-                if (x.node != y.node) return x.node < y.node;
-                if (x.elem != y.elem) return x.elem < y.elem;
-                return x.vert < y.vert;
-            });
-            for (size_t k = 0; k < keys.size(); ++k) {
-                h->lslot[(size_t)(s0 + keys[k].elem) * 4 + keys[k].vert] = (uint16_t)k;
-                if (k == 0 || keys[k].node != keys[k - 1].node) {
-                    h->seg_node.push_back(keys[k].node);
-                    h->seg_start.push_back((uint16_t)k);
-                }
+            for (int a = 0; a < NV; ++a) {
+                uint16_t l = (uint16_t)local[conn[a * E + e]];
+                lconn[(size_t)i * 4 + a] = l;
+                keys.push_back({l, (uint16_t)(i - e0), (uint8_t)a});
             }
-            h->seg_node.push_back(0xFFFF);  // sentinel: end of the last segment
-            h->seg_start.push_back((uint16_t)keys.size());
-            h->seg_off.push_back((int32_t)h->seg_node.size());
-            ++nsub;
         }
-        h->sub_off.push_back(h->sub_off.back() + nsub);
-        h->max_sub = std::max(h->max_sub, nsub);
-        for (int32_t n : inter) local[n] = -1;
-        for (int32_t n : shared) local[n] = -1;
+        std::sort(keys.begin(), keys.end(), [](const SlotKey &x, const SlotKey &y) {
+            if (x.node != y.node) return x.node < y.node;
+            if (x.elem != y.elem) return x.elem < y.elem;
+            return x.vert < y.vert;
+        });
+        // every tile node has at least one slot, so segments follow node order
+        size_t k = 0;
+        for (int32_t l = 0; l < li; ++l) {
+            tl.seg.push_back((uint16_t)k);
+            while (k < keys.size() && keys[k].node == l) {
+                lslot[(size_t)(e0 + keys[k].elem) * 4 + keys[k].vert] = (uint16_t)k;
+                ++k;
+            }
+        }
+        tl.seg.push_back((uint16_t)k);  // sentinel
+        for (int32_t n : tl.nodes) local[n] = -1;
     }
 
-    // 5. halo: each shared node sums its halo slots in tile order
+    // 5. halo: node-major slots; each shared node owns a contiguous range that
+    //    its tiles fill in tile order
     std::vector<int32_t> cnt(N, 0);
     for (int32_t t = 0; t < T; ++t)
-        for (int32_t l = h->tile_node_interior[t]; l < h->tile_node_off[t + 1] - h->tile_node_off[t]; ++l)
-            ++cnt[h->tile_nodes[h->tile_node_off[t] + l]];
+        for (int32_t l = tiles[t].nint; l < (int32_t)tiles[t].nodes.size(); ++l) ++cnt[tiles[t].nodes[l]];
     std::vector<int32_t> hidx(N, -1);
     h->halo_node.clear();
     for (int64_t n = 0; n < N; ++n)
@@ -220,17 +223,42 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
     const int32_t S = (int32_t)h->halo_node.size();
     h->halo_ptr.assign(S + 1, 0);
     for (int32_t k = 0; k < S; ++k) h->halo_ptr[k + 1] = h->halo_ptr[k] + cnt[h->halo_node[k]];
-    h->halo_src.assign(h->halo_ptr[S], 0);
-    std::vector<int32_t> fill(h->halo_ptr.begin(), h->halo_ptr.end() - 1);
-    for (int32_t t = 0; t < T; ++t) {
-        int32_t base = h->tile_node_off[t];
-        int32_t nint = h->tile_node_interior[t];
-        int32_t nn = h->tile_node_off[t + 1] - base;
-        for (int32_t l = nint; l < nn; ++l) {
-            int32_t n = h->tile_nodes[base + l];
-            h->halo_src[fill[hidx[n]]++] = h->tile_halo_off[t] + (l - nint);
-        }
+    h->node_hrange.assign((size_t)N * 2, -1);
+    for (int32_t k = 0; k < S; ++k) {
+        h->node_hrange[(size_t)h->halo_node[k] * 2] = h->halo_ptr[k];
+        h->node_hrange[(size_t)h->halo_node[k] * 2 + 1] = h->halo_ptr[k + 1];
     }
+    std::vector<int32_t> fill(h->halo_ptr.begin(), h->halo_ptr.end() - 1);
+
+    // 6. padded per-tile arrays
+    const int64_t MN = h->max_nodes, ME = h->max_elems;
+    h->info.assign((size_t)T * kTileInfo, 0);
+    h->lconn.assign((size_t)T * ME * 4, 0);
+    h->lslot.assign((size_t)T * ME * 4, 0);
+    h->nodes.assign((size_t)T * MN, 0);
+    h->seg.assign((size_t)T * (MN + 1), 0);
+    h->hpos.assign((size_t)T * MN, -1);
+    for (int32_t t = 0; t < T; ++t) {
+        const Tile &tl = tiles[t];
+        int32_t *inf = &h->info[(size_t)t * kTileInfo];
+        inf[kTileE0] = tl.e0;
+        inf[kTileNE] = tl.ne;
+        inf[kTileNN] = (int32_t)tl.nodes.size();
+        inf[kTileNInt] = tl.nint;
+        inf[kTileNOwn] = tl.nown;
+        for (int32_t i = 0; i < tl.ne; ++i)
+            for (int a = 0; a < 4; ++a) {
+                h->lconn[((size_t)t * ME + i) * 4 + a] = lconn[((size_t)tl.e0 + i) * 4 + a];
+                h->lslot[((size_t)t * ME + i) * 4 + a] = lslot[((size_t)tl.e0 + i) * 4 + a];
+            }
+        for (size_t l = 0; l < tl.nodes.size(); ++l) {
+            h->nodes[(size_t)t * MN + l] = tl.nodes[l];
+            if ((int32_t)l >= tl.nint) h->hpos[(size_t)t * MN + l] = fill[hidx[tl.nodes[l]]]++;
+        }
+        for (size_t l = 0; l < tl.seg.size(); ++l) h->seg[(size_t)t * (MN + 1) + l] = tl.seg[l];
+    }
+    h->tile_elem_off_tmp.clear();
+    h->tile_elem_off_tmp.shrink_to_fit();
 }
 
 }  // namespace fo

@@ -132,7 +132,7 @@ class SolveOpts:
     precision: int = FO_FP64
     rtol: float = 1e-8
     max_iter: int = 200000
-    inner_rtol: float = 1e-3
+    inner_rtol: float = 1e-2
     max_outer: int = 60
     check_every: int = 0
 
