@@ -183,6 +183,20 @@ enum { FO_PROF_ELAS_TILE_FP64 = 0,   /* tiled elasticity element kernel, FP64  *
 int fo_profile_enable(fo_ctx *ctx, int32_t on);
 int fo_profile_read(fo_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
 
+/* Average duration of one kernel, for measurement tools: `reps` back-to-back
+ * launches of the named kernel on the context's stream between two HIP
+ * events; *avg_us receives the elapsed time divided by reps.  The fused CG
+ * operator kernels run on the context's CG work vectors with a private
+ * scalar slot that never signals convergence, so every launch does the full
+ * work; the work vectors (not the level set, coefficients or Jacobi
+ * diagonal) hold undefined values afterwards and the next solve
+ * reinitialises them.  Requires the tiled scatter and a level set.
+ * Synchronises the stream.  reps in [1, 100000]. */
+enum { FO_KERNEL_CG_OP_FP64 = 0,     /* fused CG operator: direction update + K(phi) p, FP64 */
+       FO_KERNEL_CG_OP_FP32 = 1,     /* the same in FP32                                      */
+       FO_KERNEL_COUNT = 2 };
+int fo_time_kernel(fo_ctx *ctx, int32_t kernel, int32_t reps, double *avg_us);
+
 /* Tile statistics of the deterministic scatter: tiles, largest tile (nodes),
  * tile-node pairs, shared nodes and halo slots (any pointer may be NULL). */
 int fo_tile_stats(const fo_ctx *ctx, int64_t *n_tiles, int64_t *max_nodes, int64_t *n_slots,

@@ -471,6 +471,47 @@ bool opts_ok(const fo_solve_opts *o)
            o->max_iter > 0;
 }
 
+template <typename T>
+int time_cg_op(fo_ctx *c, FusedVecs<T> v, int reps, double *avg_us)
+{
+    hipStream_t s = c->stream;
+    const int64_t n = c->ndof;
+    // slot 2: never converges (tol2 < 0, unbounded iteration count) and
+    // reuses beta = 1/2 on every launch, so each launch reads p_old.
+    SolveScalars h{};
+    h.tol2 = -1.0;
+    h.beta = 0.5;
+    h.first = 1;
+    h.max_it = INT32_MAX;
+    FO_HIP(hipMemcpyAsync(c->scal + 2, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    launch_fill<double>(c->rz_part, 2 * kRedBlocks, 0.0, s);
+    launch_fill<T>(v.r, n, T(1), s);
+    launch_fill<T>(v.p[0], n, T(1), s);
+    FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, c->rz_part,
+                             kRedBlocks, c->pq_part, s));  // warm-up
+    hipEvent_t e0, e1;
+    FO_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FO_ERR_HIP;
+    }
+    int rc = FO_OK;
+    (void)hipEventRecord(e0, s);
+    for (int k = 0; k < reps && rc == FO_OK; ++k)
+        rc = launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, c->rz_part,
+                               kRedBlocks, c->pq_part, s);
+    (void)hipEventRecord(e1, s);
+    float ms = 0.0f;
+    if (rc == FO_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = FO_ERR_HIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == FO_OK && hipGetLastError() != hipSuccess) rc = FO_ERR_HIP;
+    if (rc == FO_OK) *avg_us = 1e3 * (double)ms / reps;
+    return rc;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -595,7 +636,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         (rc = dev_alloc(c, &c->partials, (size_t)kRedBlocks * 4)) ||
         (rc = dev_alloc(c, &c->pq_part, (size_t)std::max<int64_t>(ht.n_tiles, kRedBlocks))) ||
         (rc = dev_alloc(c, &c->rz_part, (size_t)kRedBlocks * 2)) ||
-        (rc = dev_alloc(c, &c->scal, 2)) || (rc = dev_alloc(c, &c->dscratch, 16)) ||
+        (rc = dev_alloc(c, &c->scal, 4)) || (rc = dev_alloc(c, &c->dscratch, 16)) ||
         (rc = dev_alloc(c, &c->gbuf, N * (D + 1))))
         return fail(rc);
     if ((rc = dev_alloc(c, &c->s1buf, (size_t)E * D * D))) return fail(rc);
@@ -689,6 +730,19 @@ int fo_profile_read(fo_ctx *c, int32_t which, double *total_ms, int64_t *launche
     if (total_ms) *total_ms = tot;
     if (launches) *launches = (int64_t)c->prof_used[which];
     return FO_OK;
+}
+
+int fo_time_kernel(fo_ctx *c, int32_t kernel, int32_t reps, double *avg_us)
+{
+    if (!c || !avg_us || reps < 1 || reps > 100000 || kernel < 0 || kernel >= FO_KERNEL_COUNT)
+        return FO_ERR_ARG;
+    if (c->scatter != FO_SCATTER_TILED) return FO_ERR_ARG;
+    if (!c->have_phi) return FO_ERR_STATE;
+    if (kernel == FO_KERNEL_CG_OP_FP64)
+        return time_cg_op<double>(c, FusedVecs<double>{c->x64, c->r64, c->q64, {c->p64, c->p64b}, c->dinv64},
+                                  reps, avg_us);
+    return time_cg_op<float>(c, FusedVecs<float>{c->x32, c->r32, c->q32, {c->p32, c->p32b}, c->dinv32},
+                             reps, avg_us);
 }
 
 int fo_tile_stats(const fo_ctx *c, int64_t *n_tiles, int64_t *max_nodes, int64_t *n_slots,

@@ -73,11 +73,13 @@ EXPORTS = {
     "fo_levelset_update": ([_vp, _vp, C.c_double, _vp], C.c_int),
     "fo_profile_enable": ([_vp, C.c_int32], C.c_int),
     "fo_profile_read": ([_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+    "fo_time_kernel": ([_vp, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "fo_tile_stats": ([_vp] + [C.POINTER(C.c_int64)] * 5, C.c_int),
     "fo_status_string": ([C.c_int], C.c_char_p),
 }
 
 FO_PROF_ELAS_TILE_FP64, FO_PROF_ELAS_TILE_FP32, FO_PROF_HALO_FP64, FO_PROF_HALO_FP32 = 0, 1, 2, 3
+FO_KERNEL_CG_OP_FP64, FO_KERNEL_CG_OP_FP32 = 0, 1
 
 _lib = None
 
@@ -223,6 +225,13 @@ class Context:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().fo_profile_read(self.h, which, C.byref(ms), C.byref(n)), "fo_profile_read")
         return ms.value, n.value
+
+    def time_kernel(self, kernel: int, reps: int = 200) -> float:
+        """Average duration (us) of `reps` back-to-back launches of a kernel
+        (fo_time_kernel); clobbers the CG work vectors."""
+        us = C.c_double()
+        _check(lib().fo_time_kernel(self.h, kernel, reps, C.byref(us)), "fo_time_kernel")
+        return us.value
 
     def tile_stats(self) -> dict:
         v = [C.c_int64() for _ in range(5)]
