@@ -375,6 +375,22 @@ def multi_load_3d(cells=(64, 32, 32), n_loads: int = 64, seed: int = 3) -> Workl
     return w
 
 
+def multi_load_2d(cells=(64, 32), n_loads: int = 16, seed: int = 5) -> Workload:
+    """2D counterpart of multi_load_3d: load segments of length 0.1 on the face
+    x=2 with centre uniform on [0.05,0.95], unit direction uniform on the circle."""
+    w = cantilever_2d(cells)
+    rng = np.random.default_rng(seed)
+    centers = rng.uniform(0.05, 0.95, size=n_loads)
+    ang = rng.uniform(0.0, 2.0 * np.pi, size=n_loads)
+    B = np.zeros((w.mesh.n_dofs, n_loads))
+    for k in range(n_loads):
+        B[:, k] = traction_load(w.mesh, (np.cos(ang[k]), np.sin(ang[k])), (centers[k] - 0.05,),
+                                (centers[k] + 0.05,))
+    w.b = np.ascontiguousarray(B)
+    w.name = "multiload2d_%dx%d_s%d" % (cells + (n_loads,))
+    return w
+
+
 SERVING_MESHES = (("2d", (128, 64)), ("2d", (256, 128)), ("3d", (32, 16, 16)),
                   ("3d", (64, 32, 32)), ("3d", (80, 40, 40)))
 

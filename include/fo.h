@@ -140,7 +140,9 @@ int fo_apply_elasticity(fo_ctx *ctx, const void *x, void *y, int32_t precision);
 
 /* State solve K(phi) u = b on the free unknowns, u = 0 on clamped unknowns.
  * b, u: device [n_dofs][ld], n_rhs columns (1 <= n_rhs <= max_rhs, ld >= n_rhs).
- * n_rhs > 1 runs block CG over all columns together.  stats: host, may be NULL.
+ * n_rhs > 1: FO_FP64 solves the columns one after another; FO_FP32_IR runs the
+ * batched path (all columns of a block at once, see fo_batch_tune).  stats:
+ * host, may be NULL.
  * Returns FO_OK, FO_NOT_CONVERGED (u holds the last iterate) or an error. */
 int fo_state_solve(fo_ctx *ctx, const double *b, double *u, int32_t n_rhs, int64_t ld,
                    const fo_solve_opts *opts, fo_solve_stats *stats);
@@ -194,8 +196,42 @@ int fo_profile_read(fo_ctx *ctx, int32_t which, double *total_ms, int64_t *launc
  * Synchronises the stream.  reps in [1, 100000]. */
 enum { FO_KERNEL_CG_OP_FP64 = 0,     /* fused CG operator: direction update + K(phi) p, FP64 */
        FO_KERNEL_CG_OP_FP32 = 1,     /* the same in FP32                                      */
-       FO_KERNEL_COUNT = 2 };
+       FO_KERNEL_BATCH_APPLY = 2,    /* batched FP32 apply on the matrix cores, all columns of
+                                        the context's block (needs max_rhs > 1)               */
+       FO_KERNEL_COUNT = 3 };
 int fo_time_kernel(fo_ctx *ctx, int32_t kernel, int32_t reps, double *avg_us);
+
+/* Batched multi-load solves (fo_state_solve with n_rhs > 1 and FO_FP32_IR,
+ * on a context created with max_rhs > 1).  The load cases share K(phi); the
+ * multi-load compliance problem sums their derivatives (Section "Compliance
+ * minimization", several loads) and the paper solves such PDE sets in its
+ * task-parallel mode (Section "Parallelization").  Columns are processed in
+ * blocks of up to 64; each block runs CG on all its columns at once, the
+ * element contraction K_e X_e on the matrix cores in FP32, with the same FP64
+ * residual replacement and stopping rule per column as the single-load
+ * solve.  stats: iters_inner counts block iterations (one block operator
+ * application each), summed over blocks; rel_res is the worst column.
+ *
+ * fo_batch_tune times the batched apply for every tile node cap that fits
+ * the LDS and both element group sizes (elements with pairwise disjoint node
+ * sets that a wave contracts together: 4, 8) and keeps the fastest pair
+ * (tile_nodes: node cap, group: group size, apply_us: apply time for
+ * min(n_rhs, 64) columns rounded up to a multiple of 16).  It rebuilds the
+ * batch tiles (synchronises the stream) and needs a level set.  Errors:
+ * FO_ERR_ARG without batch buffers or n_rhs out of [1, max_rhs]. */
+int fo_batch_tune(fo_ctx *ctx, int32_t n_rhs, int32_t *tile_nodes, int32_t *group, double *apply_us);
+
+/* Y = K(phi) X for a block of load cases through the batched operator (FP32,
+ * matrix cores): x, y device float [n_dofs][ncols], load case fastest; ncols
+ * a multiple of 16 up to the context's column block width (fo_batch_stats).
+ * Clamped rows of y are 0.  Synchronises the stream. */
+int fo_apply_elasticity_batch(fo_ctx *ctx, const float *x, float *y, int32_t ncols);
+
+/* Shape of the batched path: column block width (0 when max_rhs = 1), largest
+ * tile (nodes), register group size, tile count and halo slots (any pointer
+ * may be NULL). */
+int fo_batch_stats(const fo_ctx *ctx, int32_t *columns, int32_t *tile_nodes, int32_t *group,
+                   int64_t *n_tiles, int64_t *n_halo_slots);
 
 /* Tile statistics of the deterministic scatter: tiles, largest tile (nodes),
  * tile-node pairs, shared nodes and halo slots (any pointer may be NULL). */

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfo.so")
 ARCH = os.environ.get("FO_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fo_api.hip", "fo_kernels.hip", "fo_tiled.hip", "fo_cg.hip", "fo_blockcg.hip", "fo_pool.hip",
+SOURCES = ["fo_api.hip", "fo_kernels.hip", "fo_tiled.hip", "fo_cg.hip", "fo_batch.hip", "fo_pool.hip",
            "fo_tiles.cpp"]
 
 HIP_FLAGS = [

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -19,14 +20,43 @@
 
 using namespace fo;
 
-#define FO_HIP(call)                                                                    \
-    do {                                                                                \
-        hipError_t _e = (call);                                                         \
-        if (_e != hipSuccess) {                                                         \
-            std::fprintf(stderr, "libfo: %s failed: %s\n", #call, hipGetErrorString(_e)); \
-            return FO_ERR_HIP;                                                          \
-        }                                                                               \
-    } while (0)
+
+namespace fo {
+
+// Enqueues one chunk; with profiling off, a captured graph of it is replayed
+// on the private stream, fenced by events against the context stream.
+int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
+                const std::function<int(hipStream_t)> &enqueue)
+{
+    if (c->prof) return enqueue(c->stream);
+    auto it = c->graphs.find(key);
+    FO_HIP(hipEventRecord(c->ev_in, c->stream));
+    FO_HIP(hipStreamWaitEvent(c->work, c->ev_in, 0));
+    hipGraphExec_t exec = nullptr;
+    if (it == c->graphs.end()) {
+        hipGraph_t g = nullptr;
+        FO_HIP(hipStreamBeginCapture(c->work, hipStreamCaptureModeRelaxed));
+        int rc = enqueue(c->work);
+        hipError_t e = hipStreamEndCapture(c->work, &g);
+        if (rc != FO_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return FO_ERR_HIP;
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return FO_ERR_HIP;
+        c->graphs[key] = exec;
+    } else {
+        exec = it->second;
+    }
+    FO_HIP(hipGraphLaunch(exec, c->work));
+    FO_HIP(hipEventRecord(c->ev_out, c->work));
+    FO_HIP(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    return FO_OK;
+}
+
+}  // namespace fo
 
 namespace {
 
@@ -45,13 +75,6 @@ int dev_alloc(fo_ctx *c, T **p, size_t count)
     return FO_OK;
 }
 
-#define FO_TRY(x)              \
-    do {                       \
-        int _rc = (x);         \
-        if (_rc != FO_OK) {    \
-            return _rc;        \
-        }                      \
-    } while (0)
 
 double host_det(int dim, const double *X, const int32_t *conn, int64_t E, int64_t e)
 {
@@ -110,6 +133,15 @@ int descent_apply(fo_ctx *c, const double *x, double *y, hipStream_t s)
     launch_descent_apply_atomic(c, x, y, s);
     return FO_OK;
 }
+
+}  // namespace
+
+int fo::elas_apply64(fo_ctx *c, const double *x, double *y, hipStream_t s)
+{
+    return elas_apply<double>(c, x, y, s);
+}
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // conjugate-gradient driver
@@ -201,37 +233,10 @@ int fused_chunk(fo_ctx *c, FusedVecs<T> v, int chunk, hipStream_t s)
     return FO_OK;
 }
 
-// Enqueues one chunk; with profiling off, a captured graph of it is replayed
-// on the private stream, fenced by events against the context stream.
 template <class Enqueue>
 int launch_chunk(fo_ctx *c, std::tuple<int, int, int, int> key, Enqueue enqueue)
 {
-    if (c->prof) return enqueue(c->stream);
-    auto it = c->graphs.find(key);
-    FO_HIP(hipEventRecord(c->ev_in, c->stream));
-    FO_HIP(hipStreamWaitEvent(c->work, c->ev_in, 0));
-    hipGraphExec_t exec = nullptr;
-    if (it == c->graphs.end()) {
-        hipGraph_t g = nullptr;
-        FO_HIP(hipStreamBeginCapture(c->work, hipStreamCaptureModeRelaxed));
-        int rc = enqueue(c->work);
-        hipError_t e = hipStreamEndCapture(c->work, &g);
-        if (rc != FO_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
-        }
-        if (e != hipSuccess) return FO_ERR_HIP;
-        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return FO_ERR_HIP;
-        c->graphs[key] = exec;
-    } else {
-        exec = it->second;
-    }
-    FO_HIP(hipGraphLaunch(exec, c->work));
-    FO_HIP(hipEventRecord(c->ev_out, c->work));
-    FO_HIP(hipStreamWaitEvent(c->stream, c->ev_out, 0));
-    return FO_OK;
+    return graph_chunk(c, key, std::function<int(hipStream_t)>(enqueue));
 }
 
 // Polls slot 0 between chunks until the device flags done; adds iterations.
@@ -547,6 +552,7 @@ int fo_destroy(fo_ctx *c)
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
         }
+    batch_release(c);
     for (void *p : c->allocations) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
     if (c->red_host) (void)hipHostFree(c->red_host);
@@ -701,6 +707,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
         return fail(FO_ERR_HIP);
+    if (max_rhs > 1 && tiled(c) && (rc = batch_setup(c, max_rhs))) return fail(rc);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(FO_ERR_HIP);
     *out = c;
     return FO_OK;
@@ -738,11 +745,49 @@ int fo_time_kernel(fo_ctx *c, int32_t kernel, int32_t reps, double *avg_us)
         return FO_ERR_ARG;
     if (c->scatter != FO_SCATTER_TILED) return FO_ERR_ARG;
     if (!c->have_phi) return FO_ERR_STATE;
+    if (kernel == FO_KERNEL_BATCH_APPLY) {
+        if (c->batch.S == 0) return FO_ERR_ARG;
+        return batch_time_apply(c, c->batch.S / 16, reps, avg_us);
+    }
     if (kernel == FO_KERNEL_CG_OP_FP64)
         return time_cg_op<double>(c, FusedVecs<double>{c->x64, c->r64, c->q64, {c->p64, c->p64b}, c->dinv64},
                                   reps, avg_us);
     return time_cg_op<float>(c, FusedVecs<float>{c->x32, c->r32, c->q32, {c->p32, c->p32b}, c->dinv32},
                              reps, avg_us);
+}
+
+int fo_batch_tune(fo_ctx *c, int32_t n_rhs, int32_t *tile_nodes, int32_t *group, double *apply_us)
+{
+    if (!c || n_rhs < 1 || n_rhs > c->max_rhs) return FO_ERR_ARG;
+    if (c->batch.S == 0) return FO_ERR_ARG;
+    if (!c->have_phi) return FO_ERR_STATE;
+    int best = 0, kc = 0;
+    double us = 0.0;
+    FO_TRY(batch_tune(c, std::min<int>(n_rhs, c->batch.S), &best, &kc, &us));
+    if (tile_nodes) *tile_nodes = best;
+    if (group) *group = kc;
+    if (apply_us) *apply_us = us;
+    return FO_OK;
+}
+
+int fo_apply_elasticity_batch(fo_ctx *c, const float *x, float *y, int32_t ncols)
+{
+    if (!c || !x || !y || ncols < 16 || ncols % 16 != 0 || ncols > c->batch.S) return FO_ERR_ARG;
+    if (!c->have_phi) return FO_ERR_STATE;
+    return batch_apply_block(c, ncols / 16, x, y);
+}
+
+int fo_batch_stats(const fo_ctx *c, int32_t *columns, int32_t *tile_nodes, int32_t *group,
+                   int64_t *n_tiles, int64_t *n_halo_slots)
+{
+    if (!c) return FO_ERR_ARG;
+    const BatchState &b = c->batch;
+    if (columns) *columns = b.S;
+    if (tile_nodes) *tile_nodes = b.tiles.max_nodes;
+    if (group) *group = b.group;
+    if (n_tiles) *n_tiles = b.tiles.n_tiles;
+    if (n_halo_slots) *n_halo_slots = b.tiles.n_shared_slots;
+    return FO_OK;
 }
 
 int fo_tile_stats(const fo_ctx *c, int64_t *n_tiles, int64_t *max_nodes, int64_t *n_slots,
@@ -777,6 +822,7 @@ int fo_set_levelset(fo_ctx *c, const double *phi)
     }
     launch_invert_diag<double>(c->diag64, c->fixed, c->ndof, c->dinv64, s);
     launch_invert_diag<float>(c->diag64, c->fixed, c->ndof, c->dinv32, s);
+    FO_TRY(batch_levelset(c));
     FO_HIP(hipGetLastError());
     c->have_phi = true;
     return FO_OK;
@@ -805,6 +851,14 @@ int fo_state_solve(fo_ctx *c, const double *b, double *u, int32_t n_rhs, int64_t
     hipStream_t s = c->stream;
     int worst = FO_OK;
     fo_solve_stats acc{FO_OK, 0, 0, 0.0, 0.0};
+    if (o->precision == FO_FP32_IR && n_rhs > 1 && c->batch.S > 0) {
+        worst = batch_solve(c, b, u, n_rhs, ld, o, &acc);
+        if (worst < 0 && worst != FO_ERR_BREAKDOWN) return worst;
+        acc.status = worst;
+        acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st) *st = acc;
+        return worst;
+    }
     for (int k = 0; k < n_rhs; ++k) {
         launch_gather_col<double, double>(b + k, ld, c->ndof, c->b64, c->fixed, s);
         fo_solve_stats one{};

@@ -1,0 +1,1372 @@
+// Batched multi-load elasticity solves on one level set.
+//
+// Many load cases share the operator K(phi) (the multi-load compliance
+// problem sums the derivative over the cases; the paper solves such PDE sets
+// in its task-parallel mode, Numerics, Parallelization).  With s right-hand
+// sides the element contraction Y_e = K_e X_e -- K_e the d(d+1)-square
+// element stiffness, X_e one row per (vertex, component) and one column per
+// load case -- is a dense product, and it runs on the matrix cores:
+// v_mfma_f32_16x16x4f32 with K_e as the A operand and a 16-column slice of
+// X_e as the B operand.  K_e annihilates rigid translations, so the product
+// is formed as K_e[:, b>=1] (X_b - X_0): the differences remove the large
+// common part of smooth fields before the FP32 products (the explicit
+// product of X_e itself loses about two digits on a displacement field),
+// and the contraction length drops from d(d+1) to d^2 (one MFMA per element
+// in 2D, three in 3D).
+//
+// Block vectors are [n_dofs][S], load case fastest, S = 16 NC (NC = 1..4).
+// One block per element tile; wave w owns columns 16w..16w+15 and walks the
+// tile's elements in order, accumulating into its own columns of the tile's
+// node rows in LDS, so the sum is deterministic and needs no atomics.  K_e is
+// built once per element (in batches of kBatchKB elements, in the MFMA
+// fragment order) and shared by the waves.  Interior nodes are written
+// directly; shared nodes go to a node-major halo that the update kernel sums
+// in tile order.
+//
+// The solver is CG on every column at once (per-column alpha, beta and
+// convergence) inside the same FP64 residual-replacement scheme as the
+// single-load path: FP32 phases, x64 += s x32, r64 = b - K x64 in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "fo_element.h"
+#include "fo_internal.h"
+#include "fo_launch.h"
+#include "fo_reduce.h"
+#include "fo_tiles.h"
+#include "fo_xcd.h"
+
+namespace fo {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBatchKB = 32;          // elements per K_e batch held in LDS
+constexpr int kBatchLds = 163840;     // LDS per workgroup on gfx950
+constexpr int kBatchStaticLds = 64;   // static LDS of the apply kernel (rounded up)
+
+// Batch tiles: element slots in node-disjoint groups of G (padding slots
+// have local ids 0xFFFF and weight 0), per-tile fixed strides MN (nodes) and
+// MS (slots).
+struct BatchTileArgs {
+    const int32_t *info;      // [n_tiles][8]: kTileNE = slots, kTileNN, kTileNInt
+    const int32_t *nodes;     // [n_tiles][MN] global node of each tile node
+    const int32_t *hpos;      // [n_tiles][MN] halo slot of a shared tile node
+    const uint64_t *slconn;   // [n_tiles][MS] 4 x uint16 local vertex ids
+    const int4 *sgconn;       // [n_tiles][MS] global vertex ids
+    int MN, MS, n_tiles;
+};
+
+static BatchTileArgs batch_tile_args(const fo_ctx *c)
+{
+    const BatchState &b = c->batch;
+    return BatchTileArgs{b.tiles.info, b.tiles.nodes, b.tiles.hpos, b.slconn, b.sgconn, b.tiles.max_nodes,
+                         b.slot_stride, b.tiles.n_tiles};
+}
+
+size_t batch_lds_bytes(int D, int S, int MN)
+{
+    const int KS = (D * D + 3) / 4;
+    return (size_t)MN * D * S * 4 + (size_t)kBatchKB * KS * 64 * 4 + (size_t)kBatchKB * (D + 1) * D * 4 +
+           (size_t)kBatchKB * 4 + (size_t)2 * kBatchKB * 16 + (size_t)MN * 8 + (((size_t)MN * D + 15) / 16) * 16;
+}
+
+__device__ __forceinline__ int pick4(const int4 v, int k)
+{
+    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
+}
+
+// Element data of the batched operator, once per level set and per slot:
+// the cofactor vectors c_a (c_0 = -sum) and w = A_e / (d! |det|), so that
+// K_e[(a,i),(b,j)] = w (lam c_ai c_bj + mu c_aj c_bi + mu delta_ij c_a.c_b).
+// [slots][16] floats: c at a*D+i, w at 12; padding slots are all zero.
+template <int D>
+__global__ __launch_bounds__(256) void k_batch_geom(const int32_t *__restrict__ selem,
+                                                    const int4 *__restrict__ sgconn, int64_t n_slots,
+                                                    const float *__restrict__ coords,
+                                                    const uint8_t *__restrict__ chi, float ersatz,
+                                                    float *__restrict__ geo)
+{
+    constexpr int NV = D + 1;
+    for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < n_slots;
+         sl += (int64_t)gridDim.x * blockDim.x) {
+        float out[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) out[k] = 0.f;
+        const int32_t e = selem[sl];
+        if (e >= 0) {
+            const int4 gv = sgconn[sl];
+            const int gid[4] = {gv.x, gv.y, gv.z, gv.w};
+            float X[NV][D];
+            const float *Xp[NV];
+#pragma unroll
+            for (int a = 0; a < NV; ++a) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) X[a][i] = coords[(int64_t)gid[a] * D + i];
+                Xp[a] = X[a];
+            }
+            const Geom<D, float> gm = geom<D, float>(Xp);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                float c0 = 0.f;
+#pragma unroll
+                for (int a = 1; a < NV; ++a) {
+                    out[a * D + i] = gm.c[a - 1][i];
+                    c0 -= gm.c[a - 1][i];
+                }
+                out[i] = c0;
+            }
+            out[12] = (chi[e] ? 1.f : ersatz) * inv_measure_det2<D, float>(gm.det);
+        }
+        f32x4 *g4 = reinterpret_cast<f32x4 *>(geo + sl * 16);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g4[k] = f32x4{out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]};
+    }
+}
+
+// Q = K(phi) P for S = 16 NC columns, p.q partials per tile and column.
+// Every block first decides whether the solve is over (all columns done or
+// the iteration cap reached) from state that no kernel of this launch
+// writes, so all blocks agree; block 0 records the decision.
+//
+// Per batch of kBatchKB slots: (A) element data to LDS (prefetched into
+// registers during the previous batch), (B) K_e[:, b>=1] in MFMA fragment
+// order, (C) groups of G node-disjoint elements: a wave loads the operands
+// of the next group while it contracts the current one, and since no two
+// elements of a group share a node, the group's read-add-writes of the node
+// rows are all in flight together.  A wave owns its columns, so the rows sum
+// in slot order without atomics.
+template <int D, int NC, int G>
+__global__ __launch_bounds__(64 * NC) void k_batch_apply(
+    BatchTileArgs ta, const float *__restrict__ geo, float lam, float mu, const float *__restrict__ P,
+    float *__restrict__ Q, float *__restrict__ halo, const uint8_t *__restrict__ fixed,
+    double *__restrict__ pq_part, BatchCtl *ctl, const BatchCol *__restrict__ cols)
+{
+    constexpr int S = 16 * NC, NV = D + 1, NR = D * NV, NK = D * D, KS = (NK + 3) / 4, NT = 64 * NC;
+    constexpr int KB = kBatchKB;
+    static_assert(KB % G == 0, "groups tile a batch");
+    __shared__ int s_stop;
+    const int tid = threadIdx.x;
+    const int t = xcd_tile(blockIdx.x, ta.n_tiles);
+    if (t < 0) return;
+    if (tid == 0) {
+        int stop = ctl->done;
+        if (!stop) {
+            stop = ctl->it >= ctl->max_it;
+            if (!stop) {
+                int all = 1;
+                for (int k = 0; k < S; ++k) all &= cols[k].done;
+                stop = all;
+            }
+            if (stop && blockIdx.x == 0) ctl->done = 1;
+        }
+        s_stop = stop;
+    }
+    __syncthreads();
+    if (s_stop) return;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *sY = reinterpret_cast<float *>(smem_raw);       // [MN][D][S]
+    float *sK = sY + (size_t)ta.MN * D * S;                // [KB][KS][64] K_e fragments
+    float *sC = sK + KB * KS * 64;                         // [KB][NV][D] cofactor vectors
+    float *sW = sC + KB * NV * D;                          // [KB] w
+    int4 *sEN = reinterpret_cast<int4 *>(sW + KB);         // [KB] global vertex ids
+    uint2 *sEL = reinterpret_cast<uint2 *>(sEN + KB);      // [KB] local vertex ids (4 x uint16)
+    int32_t *sNode = reinterpret_cast<int32_t *>(sEL + KB);  // [MN]
+    int32_t *sHp = sNode + ta.MN;                          // [MN] halo slot, -1 interior
+    uint8_t *sFix = reinterpret_cast<uint8_t *>(sHp + ta.MN);  // [MN*D]
+
+    const int32_t *inf = ta.info + (int64_t)t * kTileInfo;
+    const int ns = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt];
+    for (int l = tid; l < nn; l += NT) {
+        const int32_t gn = ta.nodes[(int64_t)t * ta.MN + l];
+        sNode[l] = gn;
+        sHp[l] = l < nint ? -1 : ta.hpos[(int64_t)t * ta.MN + l];
+#pragma unroll
+        for (int i = 0; i < D; ++i) sFix[l * D + i] = fixed[(int64_t)gn * D + i];
+    }
+    {
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        f32x4 *y4 = reinterpret_cast<f32x4 *>(sY);
+        for (int i = tid; i < nn * D * S / 4; i += NT) y4[i] = z;
+        f32x4 *k4 = reinterpret_cast<f32x4 *>(sK);
+        for (int i = tid; i < KB * KS * 16; i += NT) k4[i] = z;  // padding stays zero
+    }
+    f32x4 pg[4];
+    int4 pn = make_int4(0, 0, 0, 0);
+    uint64_t plc = 0;
+    const int64_t slot0 = (int64_t)t * ta.MS;
+    auto fetch = [&](int base) {
+        if (tid < KB && base + tid < ns) {
+            const int64_t sl = slot0 + base + tid;
+            const f32x4 *g4 = reinterpret_cast<const f32x4 *>(geo + sl * 16);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pg[k] = g4[k];
+            pn = ta.sgconn[sl];
+            plc = ta.slconn[sl];
+        }
+    };
+    fetch(0);
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63, g = lane >> 4;
+    const int colg = wave * 16 + (lane & 15);
+    const int a0 = (4 * g) / D, a1 = (4 * g + 3) / D;  // vertices of this lane's output rows
+    for (int base = 0; base < ns; base += KB) {
+        const int nb = min(KB, ns - base);
+        // (A) element data of this batch to LDS
+        if (tid < nb) {
+            float gv[16];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                gv[4 * k] = pg[k].x;
+                gv[4 * k + 1] = pg[k].y;
+                gv[4 * k + 2] = pg[k].z;
+                gv[4 * k + 3] = pg[k].w;
+            }
+#pragma unroll
+            for (int k = 0; k < NV * D; ++k) sC[tid * NV * D + k] = gv[k];
+            sW[tid] = gv[12];
+            sEN[tid] = pn;
+            sEL[tid] = make_uint2((uint32_t)plc, (uint32_t)(plc >> 32));
+        }
+        __syncthreads();
+        // (B) K_e[:, b>=1] in fragment order: row r = (a, i), column
+        // k = (b-1, j); lane (row r, k-group) of k-step s reads its A entry
+        // at [s][16 (k mod 4) + r]
+        for (int task = tid; task < nb * NV * D; task += NT) {
+            const int e = task / (NV * D), ab = task - e * (NV * D), a = ab / D, b = ab - a * D + 1;
+            const float *ca = sC + (e * NV + a) * D, *cb = sC + (e * NV + b) * D;
+            float d = 0.f;
+#pragma unroll
+            for (int i = 0; i < D; ++i) d += ca[i] * cb[i];
+            const float w = sW[e];
+            float *ke = sK + e * KS * 64;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const float v = w * (lam * ca[i] * cb[j] + mu * ca[j] * cb[i] + (i == j ? mu * d : 0.f));
+                    const int r = a * D + i, k = (b - 1) * D + j;
+                    ke[(k >> 2) * 64 + ((k & 3) << 4) + r] = v;
+                }
+        }
+        __syncthreads();
+        // (C) node-disjoint groups, operands double-buffered
+        const int ngr = nb / G;
+        float avA[G][KS], bvA[G][KS], avB[G][KS], bvB[G][KS];
+        uint32_t lvA[G], lvB[G];
+        auto load = [&](int gi, float (&av)[G][KS], float (&bv)[G][KS], uint32_t (&lv)[G]) {
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                const int el = gi * G + e;
+                const int4 en = sEN[el];
+                const uint2 lc = sEL[el];
+                float v0[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) v0[j] = P[((int64_t)en.x * D + j) * S + colg];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int k = 4 * s + g, j = k % D;
+                    const float x0 = D == 2 ? (j == 0 ? v0[0] : v0[D - 1])
+                                            : (j == 0 ? v0[0] : j == 1 ? v0[1] : v0[D - 1]);
+                    bv[e][s] = k < NK ? P[((int64_t)pick4(en, 1 + k / D) * D + j) * S + colg] - x0 : 0.f;
+                    av[e][s] = sK[(el * KS + s) * 64 + lane];
+                }
+                const uint32_t l0 = (a0 < 2 ? lc.x >> (16 * a0) : lc.y >> (16 * (a0 - 2))) & 0xFFFF;
+                const uint32_t l1 = (a1 < 2 ? lc.x >> (16 * a1) : lc.y >> (16 * (a1 - 2))) & 0xFFFF;
+                lv[e] = l0 | (l1 << 16);
+            }
+        };
+        auto contract = [&](const float (&av)[G][KS], const float (&bv)[G][KS], const uint32_t (&lv)[G]) {
+            f32x4 acc[G];
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                acc[e] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    acc[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e][s], bv[e][s], acc[e], 0, 0, 0);
+            }
+            // the group's elements share no node: all reads, then all writes
+            float old[G][4];
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = 4 * g + q;
+                    old[e][q] = 0.f;
+                    if (r < NR && (lv[e] & 0xFFFF) != 0xFFFF) {
+                        const int ln = (int)(r / D == a0 ? (lv[e] & 0xFFFF) : (lv[e] >> 16));
+                        old[e][q] = sY[(ln * D + (r % D)) * S + colg];
+                    }
+                }
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = 4 * g + q;
+                    if (r < NR && (lv[e] & 0xFFFF) != 0xFFFF) {
+                        const int ln = (int)(r / D == a0 ? (lv[e] & 0xFFFF) : (lv[e] >> 16));
+                        sY[(ln * D + (r % D)) * S + colg] = old[e][q] + acc[e][q];
+                    }
+                }
+        };
+        load(0, avA, bvA, lvA);
+        fetch(base + KB);
+        for (int gi = 0; gi < ngr; gi += 2) {
+            if (gi + 1 < ngr) load(gi + 1, avB, bvB, lvB);
+            contract(avA, bvA, lvA);
+            if (gi + 1 < ngr) {
+                if (gi + 2 < ngr) load(gi + 2, avA, bvA, lvA);
+                contract(avB, bvB, lvB);
+            }
+        }
+        __syncthreads();
+    }
+
+    // outputs: 4 columns per thread, 16 rows per pass; interior rows to Q,
+    // shared rows to the halo; p.q partials per column (the K_e area is free)
+    constexpr int C4 = S / 4, RP = NT / C4;  // RP = 16
+    double *s_red = reinterpret_cast<double *>(sK);   // [RP][S]
+    const int c4 = tid % C4, rp = tid / C4;
+    double pq[4] = {0.0, 0.0, 0.0, 0.0};
+    const f32x4 *P4 = reinterpret_cast<const f32x4 *>(P);
+    f32x4 *Q4 = reinterpret_cast<f32x4 *>(Q);
+    f32x4 *H4 = reinterpret_cast<f32x4 *>(halo);
+    const f32x4 *Y4 = reinterpret_cast<const f32x4 *>(sY);
+#pragma unroll 2
+    for (int row = rp; row < nn * D; row += RP) {
+        const int ln = row / D, i = row - ln * D;
+        const int64_t gr = (int64_t)sNode[ln] * D + i;
+        const int hp = sHp[ln];
+        const bool fx = sFix[row] != 0;
+        const f32x4 y = Y4[row * C4 + c4];
+        if (hp < 0)
+            Q4[gr * C4 + c4] = fx ? f32x4{0.f, 0.f, 0.f, 0.f} : y;
+        else
+            H4[((int64_t)hp * D + i) * C4 + c4] = y;
+        if (!fx) {
+            const f32x4 p = P4[gr * C4 + c4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pq[k] += (double)p[k] * (double)y[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_red[rp * S + 4 * c4 + k] = pq[k];
+    __syncthreads();
+    if (tid < S) {
+        double sum = 0.0;
+        for (int k = 0; k < RP; ++k) sum += s_red[k * S + tid];
+        pq_part[(int64_t)t * S + tid] = sum;
+    }
+}
+
+// alpha_k = rho_k / (p_k . q_k), one block per column.
+__global__ __launch_bounds__(256) void k_batch_alpha(const BatchCtl *ctl, BatchCol *cols,
+                                                     const double *__restrict__ pq_part,
+                                                     int n_tiles, int S)
+{
+    __shared__ double lds[4];
+    if (ctl->done) return;
+    const int k = blockIdx.x;
+    if (cols[k].done) {
+        if (threadIdx.x == 0) cols[k].alpha = 0.0;
+        return;
+    }
+    double s = 0.0;
+    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) s += pq_part[(int64_t)t * S + k];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) {
+        BatchCol &c = cols[k];
+        c.pq = s;
+        if (s > 0.0 && isfinite(s)) {
+            c.alpha = c.rho / s;
+        } else {  // not SPD or non-finite: this column stops and restarts next phase
+            c.alpha = 0.0;
+            c.status = FO_ERR_BREAKDOWN;
+            c.done = 1;
+            c.fresh = 1;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q (q of shared nodes: their halo slots in tile
+// order; clamped rows q = 0); partials of r.D^-1 r and r.r per column.
+template <int D, int S>
+__global__ __launch_bounds__(256) void k_batch_update(
+    const BatchCtl *ctl, const BatchCol *__restrict__ cols, float *__restrict__ X,
+    float *__restrict__ R, const float *__restrict__ P, const float *__restrict__ Q,
+    const float *__restrict__ dinv, const int2 *__restrict__ hrange,
+    const float *__restrict__ halo, int64_t ndof, double *__restrict__ rz_part)
+{
+    constexpr int RG = 256 / S;
+    __shared__ double red[2][256];
+    if (ctl->done) return;
+    const int tid = threadIdx.x, col = tid % S, rg = tid / S;
+    const float alpha = (float)cols[col].alpha;
+    double rz = 0.0, rr = 0.0;
+    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
+        const int64_t node = row / D;
+        const int i = (int)(row - node * D);
+        const int2 hr = hrange[node];
+        float q;
+        if (hr.x < 0) {
+            q = Q[row * S + col];
+        } else {
+            q = 0.f;
+            for (int j = hr.x; j < hr.y; ++j) q += halo[((int64_t)j * D + i) * S + col];
+        }
+        const float di = dinv[row];
+        if (di == 0.f) q = 0.f;
+        const int64_t ix = row * S + col;
+        X[ix] += alpha * P[ix];
+        const float r = R[ix] - alpha * q;
+        R[ix] = r;
+        rz += (double)r * (double)(di * r);
+        rr += (double)r * (double)r;
+    }
+    red[0][tid] = rz;
+    red[1][tid] = rr;
+    __syncthreads();
+    if (tid < S) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < RG; ++k) {
+            a += red[0][k * S + tid];
+            b += red[1][k * S + tid];
+        }
+        rz_part[(int64_t)blockIdx.x * S + tid] = a;
+        rz_part[((int64_t)gridDim.x + blockIdx.x) * S + tid] = b;
+    }
+}
+
+// Per column: convergence on r.r, beta = rho_new / rho.  A column that
+// converges keeps the rho of the residual that built its direction (the
+// direction is not updated), so a later phase continues from it.
+__global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *cols,
+                                                    const double *__restrict__ rz_part, int nb,
+                                                    int S)
+{
+    __shared__ double lds[4];
+    if (ctl->done) return;
+    const int k = blockIdx.x;
+    if (k == 0 && threadIdx.x == 0) ctl->it += 1;
+    if (cols[k].done) return;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += rz_part[(int64_t)i * S + k];
+        b += rz_part[((int64_t)nb + i) * S + k];
+    }
+    a = block_sum(a, lds);
+    b = block_sum(b, lds);
+    if (threadIdx.x == 0) {
+        BatchCol &c = cols[k];
+        c.rho_new = a;
+        c.rr = b;
+        if (!(a >= 0.0) || !isfinite(a) || !isfinite(b)) {
+            c.status = FO_ERR_BREAKDOWN;
+            c.done = 1;
+            c.fresh = 1;
+        } else if (b <= c.tol2) {
+            c.done = 1;
+        } else {
+            c.beta = c.rho > 0.0 ? a / c.rho : 0.0;
+            c.rho = a;
+        }
+    }
+}
+
+// p = D^-1 r + beta p for the columns still running, or (mask != null) for
+// the columns whose residual was just replaced (beta = the phase coefficient).
+template <int S>
+__global__ __launch_bounds__(256) void k_batch_direction(const BatchCtl *ctl,
+                                                         const BatchCol *__restrict__ cols,
+                                                         const uint8_t *__restrict__ mask,
+                                                         float *__restrict__ P,
+                                                         const float *__restrict__ R,
+                                                         const float *__restrict__ dinv, int64_t ndof)
+{
+    constexpr int RG = 256 / S;
+    if (!mask && ctl->done) return;
+    const int tid = threadIdx.x, col = tid % S, rg = tid / S;
+    if (mask ? !mask[col] : cols[col].done) return;
+    const float beta = (float)cols[col].beta;
+    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
+        const int64_t ix = row * S + col;
+        const float z = dinv[row] * R[ix];
+        P[ix] = beta == 0.f ? z : z + beta * P[ix];
+    }
+}
+
+// Phase start of the masked columns: r32 = r64 / s_k (s_k^2 in s2new),
+// x32 = 0; partials r.z, r.r (columns outside the mask are left alone).
+template <int S>
+__global__ __launch_bounds__(256) void k_batch_rescale(const double *__restrict__ R64,
+                                                       const double *__restrict__ s2new,
+                                                       const uint8_t *__restrict__ mask,
+                                                       float *__restrict__ R32,
+                                                       float *__restrict__ X32,
+                                                       const float *__restrict__ dinv, int64_t ndof,
+                                                       double *__restrict__ rz_part)
+{
+    constexpr int RG = 256 / S;
+    __shared__ double red[2][256];
+    const int tid = threadIdx.x, col = tid % S, rg = tid / S;
+    const double sn = s2new[col];
+    const double inv = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;
+    double rz = 0.0, rr = 0.0;
+    if (mask[col]) {
+        for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof;
+             row += (int64_t)gridDim.x * RG) {
+            const int64_t ix = row * S + col;
+            const float r = (float)(R64[ix] * inv);
+            R32[ix] = r;
+            X32[ix] = 0.f;
+            rz += (double)r * (double)(dinv[row] * r);
+            rr += (double)r * (double)r;
+        }
+    }
+    red[0][tid] = rz;
+    red[1][tid] = rr;
+    __syncthreads();
+    if (tid < S) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < RG; ++k) {
+            a += red[0][k * S + tid];
+            b += red[1][k * S + tid];
+        }
+        rz_part[(int64_t)blockIdx.x * S + tid] = a;
+        rz_part[((int64_t)gridDim.x + blockIdx.x) * S + tid] = b;
+    }
+}
+
+// New phase state of the masked columns after a residual replacement (the
+// single-load rule per column): with old scale s_o and new scale s_n, the
+// first direction is D^-1 r32 + beta (s_o / s_n) p_old, beta = rho_n s_n^2 /
+// (rho_o s_o^2); a fresh column restarts (coefficient 0).  Other columns keep
+// running; the solve is marked live again.
+__global__ __launch_bounds__(256) void k_batch_phase(BatchCtl *ctl, BatchCol *cols,
+                                                     const double *__restrict__ rz_part, int nb,
+                                                     int S, double *s2, const uint8_t *mask,
+                                                     double phase_rtol)
+{
+    __shared__ double lds[4];
+    const int k = blockIdx.x;
+    if (k == 0 && threadIdx.x == 0) ctl->done = 0;
+    if (!mask[k]) return;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += rz_part[(int64_t)i * S + k];
+        b += rz_part[((int64_t)nb + i) * S + k];
+    }
+    a = block_sum(a, lds);
+    b = block_sum(b, lds);
+    if (threadIdx.x == 0) {
+        const BatchCol c = cols[k];
+        const double so2 = s2[k], sn2 = s2[S + k];
+        double coef = 0.0;
+        if (!c.fresh && c.rho > 0.0 && isfinite(c.rho) && so2 > 0.0 && sn2 > 0.0)
+            coef = (a * sn2) / (c.rho * so2) * sqrt(so2 / sn2);
+        BatchCol n{};
+        n.rho = a;
+        n.rho_new = a;
+        n.rr = b;
+        n.tol2 = phase_rtol * phase_rtol;
+        n.beta = coef;
+        n.fresh = 0;
+        n.done = b <= n.tol2 ? 1 : 0;
+        if (!(a >= 0.0) || !isfinite(a)) {
+            n.status = FO_ERR_BREAKDOWN;
+            n.done = 1;
+            n.fresh = 1;
+        }
+        cols[k] = n;
+        s2[k] = sn2;
+    }
+}
+
+// Column sums of squares of a [n_dofs][S] FP64 block: partials per block.
+template <int S>
+__global__ __launch_bounds__(256) void k_batch_colsq(const double *__restrict__ V, int64_t ndof,
+                                                     double *__restrict__ part)
+{
+    constexpr int RG = 256 / S;
+    __shared__ double red[256];
+    const int tid = threadIdx.x, col = tid % S, rg = tid / S;
+    double s = 0.0;
+    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
+        const double v = V[row * S + col];
+        s += v * v;
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (tid < S) {
+        double a = 0.0;
+        for (int k = 0; k < RG; ++k) a += red[k * S + tid];
+        part[(int64_t)blockIdx.x * S + tid] = a;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_colsum(const double *__restrict__ part, int nb, int S,
+                                                      double *__restrict__ out)
+{
+    __shared__ double lds[4];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[(int64_t)i * S + k];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) out[k] = s;
+}
+
+// x64 += s_k x32 (s_k^2 in s2) for the masked columns.
+__global__ __launch_bounds__(256) void k_batch_accumulate(double *__restrict__ X64,
+                                                          const float *__restrict__ X32,
+                                                          const double *__restrict__ s2,
+                                                          const uint8_t *__restrict__ mask, int S,
+                                                          int64_t n)
+{
+    for (int64_t ix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ix < n;
+         ix += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(ix % S);
+        if (mask[k]) X64[ix] += sqrt(s2[k]) * (double)X32[ix];
+    }
+}
+
+// r64[:, k] = b[:, k] - q (clamped rows 0).
+__global__ __launch_bounds__(256) void k_batch_residual_col(const double *__restrict__ B,
+                                                            const double *__restrict__ q,
+                                                            const uint8_t *__restrict__ fixed,
+                                                            double *__restrict__ R, int S, int k,
+                                                            int64_t ndof)
+{
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < ndof;
+         row += (int64_t)gridDim.x * blockDim.x)
+        R[row * S + k] = fixed[row] ? 0.0 : B[row * S + k] - q[row];
+}
+
+// Caller's b [n_dofs][ld] (columns c0..c0+n-1) -> [n_dofs][S], clamped rows
+// and padding columns zero.
+__global__ __launch_bounds__(256) void k_batch_pack(const double *__restrict__ b, int64_t ld,
+                                                    int n, const uint8_t *__restrict__ fixed,
+                                                    double *__restrict__ B, int S, int64_t ndof)
+{
+    const int64_t total = ndof * S;
+    for (int64_t ix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ix < total;
+         ix += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = ix / S;
+        const int k = (int)(ix - row * S);
+        B[ix] = (k < n && !fixed[row]) ? b[row * ld + k] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_unpack(const double *__restrict__ X, int S, int n,
+                                                      double *__restrict__ u, int64_t ld,
+                                                      int64_t ndof)
+{
+    const int64_t total = ndof * n;
+    for (int64_t ix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ix < total;
+         ix += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = ix / n;
+        const int k = (int)(ix - row * n);
+        u[row * ld + k] = X[row * S + k];
+    }
+}
+
+// Y = K(phi) X assembled from the apply's outputs: interior rows from Q,
+// shared rows summed over their halo slots in tile order, clamped rows 0.
+template <int D, int S>
+__global__ __launch_bounds__(256) void k_batch_collect(const float *__restrict__ Q,
+                                                       const float *__restrict__ halo,
+                                                       const int2 *__restrict__ hrange,
+                                                       const uint8_t *__restrict__ fixed,
+                                                       float *__restrict__ Y, int64_t ndof)
+{
+    constexpr int RG = 256 / S;
+    const int tid = threadIdx.x, col = tid % S, rg = tid / S;
+    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
+        const int64_t node = row / D;
+        const int i = (int)(row - node * D);
+        const int2 hr = hrange[node];
+        float q;
+        if (hr.x < 0) {
+            q = Q[row * S + col];
+        } else {
+            q = 0.f;
+            for (int j = hr.x; j < hr.y; ++j) q += halo[((int64_t)j * D + i) * S + col];
+        }
+        Y[row * S + col] = fixed[row] ? 0.f : q;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static int grid_of(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096); }
+
+template <int D, int NC, int G>
+static int set_apply_lds1(int bytes)
+{
+    return hipFuncSetAttribute((const void *)k_batch_apply<D, NC, G>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess;
+}
+
+template <int D, int NC>
+static int set_apply_lds(int bytes)
+{
+    return set_apply_lds1<D, NC, 4>(bytes) | set_apply_lds1<D, NC, 8>(bytes);
+}
+
+// Allows the largest dynamic LDS for every instance (outside graph capture).
+static int batch_prepare_lds(int D)
+{
+    const int cap = kBatchLds - kBatchStaticLds;
+    if (D == 2)
+        return set_apply_lds<2, 1>(cap) | set_apply_lds<2, 2>(cap) | set_apply_lds<2, 3>(cap) |
+               set_apply_lds<2, 4>(cap);
+    return set_apply_lds<3, 1>(cap) | set_apply_lds<3, 2>(cap) | set_apply_lds<3, 3>(cap) |
+           set_apply_lds<3, 4>(cap);
+}
+
+template <int D, int NC, int G>
+static void apply_t(const fo_ctx *c, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
+                    hipStream_t s)
+{
+    const BatchState &b = c->batch;
+    const size_t lds = batch_lds_bytes(D, 16 * NC, b.tiles.max_nodes);
+    hipLaunchKernelGGL((k_batch_apply<D, NC, G>), dim3(xcd_grid(b.tiles.n_tiles)), dim3(64 * NC), lds, s,
+                       batch_tile_args(c), b.geo, (float)c->lam, (float)c->mu, P, Q, b.halo, c->fixed,
+                       b.pq_part, ctl, cols);
+}
+
+template <int D, int NC>
+static void apply_g(const fo_ctx *c, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
+                    hipStream_t s)
+{
+    if (c->batch.group == 4)
+        apply_t<D, NC, 4>(c, P, Q, ctl, cols, s);
+    else
+        apply_t<D, NC, 8>(c, P, Q, ctl, cols, s);
+}
+
+static void launch_batch_apply(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl,
+                               const BatchCol *cols, hipStream_t s)
+{
+    if (c->dim == 2) {
+        switch (NC) {
+        case 1: apply_g<2, 1>(c, P, Q, ctl, cols, s); break;
+        case 2: apply_g<2, 2>(c, P, Q, ctl, cols, s); break;
+        case 3: apply_g<2, 3>(c, P, Q, ctl, cols, s); break;
+        default: apply_g<2, 4>(c, P, Q, ctl, cols, s); break;
+        }
+    } else {
+        switch (NC) {
+        case 1: apply_g<3, 1>(c, P, Q, ctl, cols, s); break;
+        case 2: apply_g<3, 2>(c, P, Q, ctl, cols, s); break;
+        case 3: apply_g<3, 3>(c, P, Q, ctl, cols, s); break;
+        default: apply_g<3, 4>(c, P, Q, ctl, cols, s); break;
+        }
+    }
+}
+
+// Dispatch on S = 16 NC for the node-parallel kernels.
+template <template <int> class K, class... A>
+static void by_s(int S, A... a)
+{
+    switch (S) {
+    case 16: K<16>::run(a...); break;
+    case 32: K<32>::run(a...); break;
+    case 48: K<48>::run(a...); break;
+    default: K<64>::run(a...); break;
+    }
+}
+
+template <int S>
+struct UpdateL {
+    static void run(const fo_ctx *c, hipStream_t s)
+    {
+        const BatchState &b = c->batch;
+        const int2 *hr = reinterpret_cast<const int2 *>(b.tiles.node_hrange);
+        if (c->dim == 2)
+            hipLaunchKernelGGL((k_batch_update<2, S>), dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, b.x32,
+                               b.r32, b.p32, b.q32, c->dinv32, hr, b.halo, c->ndof, b.rz_part);
+        else
+            hipLaunchKernelGGL((k_batch_update<3, S>), dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, b.x32,
+                               b.r32, b.p32, b.q32, c->dinv32, hr, b.halo, c->ndof, b.rz_part);
+    }
+};
+
+template <int S>
+struct DirectionL {
+    static void run(const fo_ctx *c, const uint8_t *mask, hipStream_t s)
+    {
+        const BatchState &b = c->batch;
+        hipLaunchKernelGGL(k_batch_direction<S>, dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, mask,
+                           b.p32, b.r32, c->dinv32, c->ndof);
+    }
+};
+
+template <int S>
+struct RescaleL {
+    static void run(const fo_ctx *c, hipStream_t s)
+    {
+        const BatchState &b = c->batch;
+        hipLaunchKernelGGL(k_batch_rescale<S>, dim3(b.n_upd), dim3(256), 0, s, b.r64, b.s2 + S, b.mask,
+                           b.r32, b.x32, c->dinv32, c->ndof, b.rz_part);
+    }
+};
+
+template <int S>
+struct ColsqL {
+    static void run(const fo_ctx *c, const double *V, double *out, hipStream_t s)
+    {
+        const BatchState &b = c->batch;
+        hipLaunchKernelGGL(k_batch_colsq<S>, dim3(b.n_upd), dim3(256), 0, s, V, c->ndof, b.rz_part);
+        hipLaunchKernelGGL(k_batch_colsum, dim3(S), dim3(256), 0, s, b.rz_part, b.n_upd, S, out);
+    }
+};
+
+// One CG iteration for all columns: apply, alpha, update, beta, direction.
+static void batch_iteration(const fo_ctx *c, int NC, hipStream_t s)
+{
+    const BatchState &b = c->batch;
+    const int S = 16 * NC;
+    launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+    hipLaunchKernelGGL(k_batch_alpha, dim3(S), dim3(256), 0, s, b.ctl, b.cols, b.pq_part,
+                       b.tiles.n_tiles, S);
+    by_s<UpdateL>(S, c, s);
+    hipLaunchKernelGGL(k_batch_beta, dim3(S), dim3(256), 0, s, b.ctl, b.cols, b.rz_part, b.n_upd, S);
+    by_s<DirectionL>(S, c, (const uint8_t *)nullptr, s);
+}
+
+// ---------------------------------------------------------------------------
+// host side: tiles, buffers, solve
+
+static int balloc(fo_ctx *c, void **p, size_t bytes, bool tile)
+{
+    void *v = nullptr;
+    if (hipMalloc(&v, std::max<size_t>(bytes, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return FO_ERR_NOMEM;
+    }
+    (tile ? c->batch.tile_allocs : c->allocations).push_back(v);
+    c->bytes += std::max<size_t>(bytes, 1);
+    if (tile) c->batch.tile_bytes += std::max<size_t>(bytes, 1);
+    *p = v;
+    return FO_OK;
+}
+
+template <typename T>
+static int bup(fo_ctx *c, T **dst, const std::vector<T> &v)
+{
+    FO_TRY(balloc(c, (void **)dst, v.size() * sizeof(T), true));
+    if (!v.empty() &&
+        hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return FO_ERR_HIP;
+    return FO_OK;
+}
+
+static void free_batch_tiles(fo_ctx *c)
+{
+    BatchState &b = c->batch;
+    for (void *p : b.tile_allocs) (void)hipFree(p);
+    b.tile_allocs.clear();
+    c->bytes -= b.tile_bytes;
+    b.tile_bytes = 0;
+    b.tiles = TileSet{};
+}
+
+void batch_release(fo_ctx *c)
+{
+    free_batch_tiles(c);
+    BatchState &b = c->batch;
+    if (b.ctl_host) (void)hipHostFree(b.ctl_host);
+    if (b.cols_host) (void)hipHostFree(b.cols_host);
+    if (b.s2_host) (void)hipHostFree(b.s2_host);
+    if (b.mask_host) (void)hipHostFree(b.mask_host);
+    b.ctl_host = nullptr;
+    b.cols_host = nullptr;
+    b.s2_host = nullptr;
+    b.mask_host = nullptr;
+}
+
+int batch_max_nodes(int D, int S)
+{
+    const int fixed = (int)batch_lds_bytes(D, S, 0) + 16;
+    const int per = D * S * 4 + 8 + D;
+    return std::max(0, (kBatchLds - kBatchStaticLds - fixed) / per);
+}
+
+// Batch tiles with at most `mn` nodes over the context's element order; the
+// elements of each tile are packed into groups of G with pairwise disjoint
+// node sets (greedy first fit in Morton order), each group padded to G
+// slots.  Slot arrays get a fixed per-tile stride.
+static int build_batch_tiles(fo_ctx *c, int mn, int G, const std::vector<double> &X,
+                             const std::vector<int32_t> &conn)
+{
+    BatchState &b = c->batch;
+    const int D = c->dim, NV = D + 1;
+    HostTiles h;
+    build_tiles(D, c->N, c->E, X.data(), conn.data(), 16383, &h, mn, true);
+    const int T = h.n_tiles;
+    const int words = (h.max_nodes + 63) / 64;
+    std::vector<std::vector<int32_t>> tslots(T);  // per tile: slot -> tile element index, -1 padding
+    int MS = 0;
+    for (int t = 0; t < T; ++t) {
+        const int ne = h.info[(size_t)t * kTileInfo + kTileNE];
+        std::vector<std::vector<int32_t>> groups;
+        std::vector<std::vector<uint64_t>> masks;
+        size_t first_open = 0;
+        for (int i = 0; i < ne; ++i) {
+            const uint16_t *lc = &h.lconn[((size_t)t * h.max_elems + i) * 4];
+            size_t gsel = groups.size();
+            for (size_t k = first_open; k < groups.size(); ++k) {
+                if ((int)groups[k].size() >= G) continue;
+                bool clash = false;
+                for (int a = 0; a < NV && !clash; ++a) clash = (masks[k][lc[a] >> 6] >> (lc[a] & 63)) & 1;
+                if (!clash) {
+                    gsel = k;
+                    break;
+                }
+            }
+            if (gsel == groups.size()) {
+                groups.emplace_back();
+                masks.emplace_back(words, 0);
+            }
+            groups[gsel].push_back(i);
+            for (int a = 0; a < NV; ++a) masks[gsel][lc[a] >> 6] |= 1ULL << (lc[a] & 63);
+            while (first_open < groups.size() && (int)groups[first_open].size() >= G) ++first_open;
+        }
+        std::vector<int32_t> &sl = tslots[t];
+        for (auto &gr : groups) {
+            for (int32_t i : gr) sl.push_back(i);
+            for (size_t k = gr.size(); k < (size_t)G; ++k) sl.push_back(-1);
+        }
+        MS = std::max(MS, (int)sl.size());
+    }
+    std::vector<int32_t> selem((size_t)T * MS, -1);
+    std::vector<uint64_t> slconn((size_t)T * MS, ~0ULL);
+    std::vector<int32_t> sgconn((size_t)T * MS * 4, 0);
+    std::vector<int32_t> info(h.info);
+    for (int t = 0; t < T; ++t) {
+        const int e0 = h.info[(size_t)t * kTileInfo + kTileE0];
+        const std::vector<int32_t> &sl = tslots[t];
+        info[(size_t)t * kTileInfo + kTileNE] = (int32_t)sl.size();
+        for (size_t k = 0; k < sl.size(); ++k) {
+            const size_t o = (size_t)t * MS + k;
+            if (sl[k] < 0) continue;
+            const int64_t e = e0 + sl[k];
+            selem[o] = (int32_t)e;
+            const uint16_t *lc = &h.lconn[((size_t)t * h.max_elems + sl[k]) * 4];
+            uint64_t v = 0;
+            for (int a = 0; a < 4; ++a) v |= (uint64_t)(a < NV ? lc[a] : 0) << (16 * a);
+            slconn[o] = v;
+            for (int a = 0; a < NV; ++a) sgconn[o * 4 + a] = conn[(size_t)a * c->E + e];
+        }
+    }
+    free_batch_tiles(c);
+    TileSet &ts = b.tiles;
+    ts.n_tiles = T;
+    ts.max_nodes = h.max_nodes;
+    ts.max_elems = MS;
+    ts.n_slots = h.n_slots;
+    ts.n_shared_nodes = (int64_t)h.halo_node.size();
+    ts.n_shared_slots = h.halo_ptr.empty() ? 0 : (int64_t)h.halo_ptr.back();
+    FO_TRY(bup(c, &ts.info, info));
+    FO_TRY(bup(c, &ts.nodes, h.nodes));
+    FO_TRY(bup(c, &ts.hpos, h.hpos));
+    FO_TRY(bup(c, &ts.node_hrange, h.node_hrange));
+    FO_TRY(bup(c, &b.selem, selem));
+    FO_TRY(bup(c, &b.slconn, slconn));
+    int32_t *sg = nullptr;
+    FO_TRY(bup(c, &sg, sgconn));
+    b.sgconn = reinterpret_cast<int4 *>(sg);
+    b.slot_stride = MS;
+    b.n_slot_total = (int64_t)T * MS;
+    b.group = G;
+    FO_TRY(balloc(c, (void **)&b.geo, (size_t)std::max<int64_t>(b.n_slot_total, 1) * 16 * sizeof(float), true));
+    b.halo_cap = (size_t)std::max<int64_t>(ts.n_shared_slots, 1) * c->dim * b.S;
+    FO_TRY(balloc(c, (void **)&b.halo, b.halo_cap * sizeof(float), true));
+    const size_t need_pq = (size_t)std::max(T, 1) * b.S;
+    FO_TRY(balloc(c, (void **)&b.pq_part, need_pq * sizeof(double), true));
+    b.pq_cap = need_pq;
+    b.mn_cap = mn;
+    ++b.version;
+    if (c->have_phi) FO_TRY(batch_levelset(c));
+    return FO_OK;
+}
+
+// Host copies of the mesh in the context's element order (for tile builds).
+static int mesh_host(fo_ctx *c, std::vector<double> &X, std::vector<int32_t> &conn)
+{
+    X.resize((size_t)c->N * c->dim);
+    conn.resize((size_t)(c->dim + 1) * c->E);
+    if (hipMemcpy(X.data(), c->coords, X.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(conn.data(), c->conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return FO_ERR_HIP;
+    return FO_OK;
+}
+
+int batch_default_nodes(int D) { return D == 2 ? 256 : 160; }
+
+int batch_setup(fo_ctx *c, int max_rhs)
+{
+    BatchState &b = c->batch;
+    const int D = c->dim;
+    b.S = 16 * std::min(4, (max_rhs + 15) / 16);
+    const int64_t n = c->ndof * b.S;
+    const int RG = 256 / b.S;
+    b.n_upd = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (c->ndof + RG - 1) / RG));
+    FO_TRY(balloc(c, (void **)&b.x32, n * sizeof(float), false));
+    FO_TRY(balloc(c, (void **)&b.r32, n * sizeof(float), false));
+    FO_TRY(balloc(c, (void **)&b.p32, n * sizeof(float), false));
+    FO_TRY(balloc(c, (void **)&b.q32, n * sizeof(float), false));
+    FO_TRY(balloc(c, (void **)&b.x64, n * sizeof(double), false));
+    FO_TRY(balloc(c, (void **)&b.r64, n * sizeof(double), false));
+    FO_TRY(balloc(c, (void **)&b.b64, n * sizeof(double), false));
+    FO_TRY(balloc(c, (void **)&b.rz_part, (size_t)2 * b.n_upd * b.S * sizeof(double), false));
+    FO_TRY(balloc(c, (void **)&b.s2, (size_t)3 * b.S * sizeof(double), false));
+    FO_TRY(balloc(c, (void **)&b.mask, (size_t)b.S, false));
+    FO_TRY(balloc(c, (void **)&b.cols, (size_t)b.S * sizeof(BatchCol), false));
+    FO_TRY(balloc(c, (void **)&b.ctl, sizeof(BatchCtl), false));
+    if (hipHostMalloc((void **)&b.ctl_host, sizeof(BatchCtl)) != hipSuccess ||
+        hipHostMalloc((void **)&b.cols_host, b.S * sizeof(BatchCol)) != hipSuccess ||
+        hipHostMalloc((void **)&b.s2_host, b.S * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&b.mask_host, b.S) != hipSuccess)
+        return FO_ERR_NOMEM;
+    // directions start at zero (the first direction of a column ignores them,
+    // but stale non-finite bits must not survive a zero coefficient)
+    launch_fill<float>(b.p32, n, 0.0f, c->stream);
+    launch_fill<float>(b.q32, n, 0.0f, c->stream);
+    if (batch_prepare_lds(D)) return FO_ERR_HIP;
+    std::vector<double> X;
+    std::vector<int32_t> conn;
+    FO_TRY(mesh_host(c, X, conn));
+    const int mn = std::min(batch_default_nodes(D), batch_max_nodes(D, b.S));
+    FO_TRY(build_batch_tiles(c, mn, 8, X, conn));
+    FO_HIP(hipStreamSynchronize(c->stream));
+    return FO_OK;
+}
+
+static void destroy_batch_graphs(fo_ctx *c)
+{
+    for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+        if (std::get<0>(it->first) >= 40 && std::get<0>(it->first) < 50) {
+            (void)hipGraphExecDestroy(it->second);
+            it = c->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// Times `reps` back-to-back launches of the batched apply (NC column
+// chunks) on the current batch tiles; columns are all active.
+int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us)
+{
+    BatchState &b = c->batch;
+    hipStream_t s = c->stream;
+    const int S = 16 * NC;
+    std::vector<BatchCol> cols(S);
+    for (auto &col : cols) col = BatchCol{};
+    BatchCtl ctl{0, 0, INT32_MAX, 0};
+    FO_HIP(hipMemcpyAsync(b.cols, cols.data(), S * sizeof(BatchCol), hipMemcpyHostToDevice, s));
+    FO_HIP(hipMemcpyAsync(b.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
+    launch_fill<float>(b.p32, c->ndof * S, 1.0f, s);
+    launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+    hipEvent_t e0, e1;
+    FO_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FO_ERR_HIP;
+    }
+    (void)hipEventRecord(e0, s);
+    for (int k = 0; k < reps; ++k) launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+    (void)hipEventRecord(e1, s);
+    float ms = 0.0f;
+    int rc = FO_OK;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+        hipGetLastError() != hipSuccess)
+        rc = FO_ERR_HIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    launch_fill<float>(b.p32, c->ndof * S, 0.0f, s);
+    if (rc == FO_OK) *avg_us = 1e3 * (double)ms / reps;
+    return rc;
+}
+
+template <int S>
+struct CollectL {
+    static void run(const fo_ctx *c, float *Y, hipStream_t s)
+    {
+        const BatchState &b = c->batch;
+        const int2 *hr = reinterpret_cast<const int2 *>(b.tiles.node_hrange);
+        if (c->dim == 2)
+            hipLaunchKernelGGL((k_batch_collect<2, S>), dim3(b.n_upd), dim3(256), 0, s, b.q32, b.halo, hr,
+                               c->fixed, Y, c->ndof);
+        else
+            hipLaunchKernelGGL((k_batch_collect<3, S>), dim3(b.n_upd), dim3(256), 0, s, b.q32, b.halo, hr,
+                               c->fixed, Y, c->ndof);
+    }
+};
+
+// Y = K(phi) X for one FP32 block of S = 16 NC columns (device [n_dofs][S]).
+int batch_apply_block(fo_ctx *c, int NC, const float *X, float *Y)
+{
+    BatchState &b = c->batch;
+    hipStream_t s = c->stream;
+    const int S = 16 * NC;
+    std::vector<BatchCol> cols(S);
+    for (auto &col : cols) col = BatchCol{};
+    BatchCtl ctl{0, 0, INT32_MAX, 0};
+    FO_HIP(hipMemcpyAsync(b.cols, cols.data(), S * sizeof(BatchCol), hipMemcpyHostToDevice, s));
+    FO_HIP(hipMemcpyAsync(b.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
+    FO_HIP(hipMemcpyAsync(b.p32, X, c->ndof * S * sizeof(float), hipMemcpyDeviceToDevice, s));
+    launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+    by_s<CollectL>(S, (const fo_ctx *)c, Y, s);
+    FO_HIP(hipGetLastError());
+    FO_HIP(hipStreamSynchronize(s));
+    return FO_OK;
+}
+
+// Tries the node caps that fit the LDS and both group sizes, and keeps the
+// fastest apply.
+int batch_tune(fo_ctx *c, int n_rhs, int *best_nodes, int *best_group, double *best_us)
+{
+    BatchState &b = c->batch;
+    const int NC = std::min(4, std::max(1, (n_rhs + 15) / 16));
+    const int S = 16 * NC;
+    const int D = c->dim;
+    const int cap = batch_max_nodes(D, S);
+    std::vector<int> cand = D == 2 ? std::vector<int>{96, 128, 192, 256, 288}
+                                   : std::vector<int>{64, 96, 128, 160, 176};
+    std::vector<double> X;
+    std::vector<int32_t> conn;
+    FO_TRY(mesh_host(c, X, conn));
+    destroy_batch_graphs(c);
+    int best = 0, bg = 8;
+    double best_t = 1e300;
+    for (int mn : cand) {
+        if (mn > cap) continue;
+        for (int G : {4, 8}) {
+            FO_TRY(build_batch_tiles(c, mn, G, X, conn));
+            double us = 0.0;
+            FO_TRY(batch_time_apply(c, NC, 20, &us));
+            if (us < best_t) {
+                best_t = us;
+                best = mn;
+                bg = G;
+            }
+        }
+    }
+    if (best == 0) return FO_ERR_ARG;
+    if (best != b.mn_cap || bg != b.group) FO_TRY(build_batch_tiles(c, best, bg, X, conn));
+    FO_HIP(hipStreamSynchronize(c->stream));
+    if (best_nodes) *best_nodes = best;
+    if (best_group) *best_group = bg;
+    if (best_us) *best_us = best_t;
+    return FO_OK;
+}
+
+static int poll_batch(fo_ctx *c)
+{
+    FO_HIP(hipMemcpyAsync(c->batch.ctl_host, c->batch.ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost,
+                          c->stream));
+    FO_HIP(hipStreamSynchronize(c->stream));
+    return FO_OK;
+}
+
+// Column norms^2 of the FP64 residual block into s2[S..2S) and the host.
+static int residual_norms(fo_ctx *c, int S)
+{
+    BatchState &b = c->batch;
+    by_s<ColsqL>(S, (const fo_ctx *)c, (const double *)b.r64, b.s2 + S, c->stream);
+    FO_HIP(hipMemcpyAsync(b.s2_host, b.s2 + S, S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FO_HIP(hipStreamSynchronize(c->stream));
+    return FO_OK;
+}
+
+// Element data of the batched operator for the current level set.
+int batch_levelset(fo_ctx *c)
+{
+    const BatchState &b = c->batch;
+    if (b.S == 0 || b.n_slot_total == 0) return FO_OK;
+    const int grid = grid_of(b.n_slot_total);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_batch_geom<2>, dim3(grid), dim3(256), 0, c->stream, b.selem, b.sgconn,
+                           b.n_slot_total, c->coords32, c->chi, (float)c->ersatz, b.geo);
+    else
+        hipLaunchKernelGGL(k_batch_geom<3>, dim3(grid), dim3(256), 0, c->stream, b.selem, b.sgconn,
+                           b.n_slot_total, c->coords32, c->chi, (float)c->ersatz, b.geo);
+    FO_HIP(hipGetLastError());
+    return FO_OK;
+}
+
+// FP32 CG on all columns of one block with FP64 residual replacement per
+// column: a column whose FP32 residual fell by inner_rtol is stopped, its
+// x64 += s x32 and r64 = b - K x64 (FP64) are formed, and it continues from
+// the replaced residual with its direction kept (rescaled), while the other
+// columns keep iterating.  Columns c0..c0+n-1 of b (ld) -> u.
+static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t ld,
+                       const fo_solve_opts *o, fo_solve_stats *st)
+{
+    BatchState &b = c->batch;
+    hipStream_t s = c->stream;
+    const int NC = std::min(4, (n + 15) / 16);
+    const int S = 16 * NC;
+    const int64_t nd = c->ndof;
+    const int chunk = o->check_every > 0 ? o->check_every : 16;
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
+    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-2;
+    hipLaunchKernelGGL(k_batch_pack, dim3(grid_of(nd * S)), dim3(256), 0, s, b_in, ld, n, c->fixed, b.b64,
+                       S, nd);
+    launch_fill<double>(b.x64, nd * S, 0.0, s);
+    FO_HIP(hipMemcpyAsync(b.r64, b.b64, nd * S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    {
+        std::vector<BatchCol> cols(S);
+        for (auto &col : cols) {
+            col = BatchCol{};
+            col.fresh = 1;
+            col.done = 1;
+        }
+        BatchCtl ctl{0, 0, o->max_iter, 0};
+        FO_HIP(hipMemcpyAsync(b.cols, cols.data(), S * sizeof(BatchCol), hipMemcpyHostToDevice, s));
+        FO_HIP(hipMemcpyAsync(b.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
+        FO_HIP(hipStreamSynchronize(s));
+    }
+    FO_TRY(residual_norms(c, S));
+    std::vector<double> bnorm(S), rn(S);
+    std::vector<int> conv(S, 0), status(S, FO_OK), restart(S, 1), outer(S, 0), fail(S, 0);
+    for (int k = 0; k < S; ++k) {
+        bnorm[k] = rn[k] = std::sqrt(b.s2_host[k]);
+        conv[k] = k >= n || bnorm[k] == 0.0;
+    }
+    // columns to (re)start from r64: mask_host
+    auto select = [&](const std::vector<int> &fin) {
+        bool any = false;
+        for (int k = 0; k < S; ++k) {
+            b.mask_host[k] = (fin[k] && !conv[k]) ? 1 : 0;
+            any = any || b.mask_host[k];
+        }
+        return any;
+    };
+    auto restart_columns = [&]() -> int {
+        FO_HIP(hipMemcpyAsync(b.mask, b.mask_host, S, hipMemcpyHostToDevice, s));
+        by_s<RescaleL>(S, (const fo_ctx *)c, s);
+        hipLaunchKernelGGL(k_batch_phase, dim3(S), dim3(256), 0, s, b.ctl, b.cols, b.rz_part, b.n_upd, S, b.s2,
+                           b.mask, phase_rtol);
+        by_s<DirectionL>(S, (const fo_ctx *)c, (const uint8_t *)b.mask, s);
+        FO_HIP(hipGetLastError());
+        return FO_OK;
+    };
+    std::vector<int> fin(S, 1);
+    if (select(fin)) FO_TRY(restart_columns());
+    int result = FO_NOT_CONVERGED;
+    int32_t it_total = 0;
+    while (true) {
+        bool all = true;
+        for (int k = 0; k < S; ++k) all = all && conv[k];
+        if (all) {
+            result = FO_OK;
+            break;
+        }
+        FO_TRY(poll_batch(c));
+        it_total = b.ctl_host->it;
+        if (it_total >= o->max_iter) break;
+        if (!b.ctl_host->done) {
+            const int32_t before = b.ctl_host->it;
+            auto key = std::make_tuple(40 + NC, chunk, b.version, 0);
+            FO_TRY(graph_chunk(c, key, [&](hipStream_t ws) {
+                for (int j = 0; j < chunk; ++j) batch_iteration(c, NC, ws);
+                return (int)FO_OK;
+            }));
+            FO_TRY(poll_batch(c));
+            if (!b.ctl_host->done && b.ctl_host->it == before) {
+                hipError_t e = hipGetLastError();
+                std::fprintf(stderr, "libfo: batched CG chunk made no progress (%s)\n", hipGetErrorString(e));
+                return FO_ERR_HIP;
+            }
+        }
+        // columns that finished their phase (or broke down)
+        FO_HIP(hipMemcpyAsync(b.cols_host, b.cols, S * sizeof(BatchCol), hipMemcpyDeviceToHost, s));
+        FO_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (int k = 0; k < S; ++k) {
+            fin[k] = !conv[k] && b.cols_host[k].done;
+            b.mask_host[k] = fin[k] ? 1 : 0;
+            any = any || fin[k];
+        }
+        if (!any) continue;
+        FO_HIP(hipMemcpyAsync(b.mask, b.mask_host, S, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_batch_accumulate, dim3(grid_of(nd * S)), dim3(256), 0, s, b.x64, b.x32, b.s2,
+                           b.mask, S, nd * S);
+        for (int k = 0; k < S; ++k) {
+            if (!fin[k]) continue;
+            launch_gather_col<double, double>(b.x64 + k, S, nd, c->t64, nullptr, s);
+            FO_TRY(elas_apply64(c, c->t64, c->q64, s));
+            hipLaunchKernelGGL(k_batch_residual_col, dim3(grid_of(nd)), dim3(256), 0, s, b.b64, c->q64,
+                               c->fixed, b.r64, S, k, nd);
+        }
+        FO_TRY(residual_norms(c, S));
+        for (int k = 0; k < S; ++k) {
+            if (!fin[k]) continue;
+            ++outer[k];
+            const double r = std::sqrt(b.s2_host[k]);
+            if (!(r == r)) {  // non-finite FP64 residual: the column fails
+                status[k] = FO_ERR_BREAKDOWN;
+                conv[k] = 1;
+                fail[k] = 1;
+                continue;
+            }
+            // a column restarted in the last phase that made no progress
+            // cannot improve in FP32 any more
+            const bool stalled = restart[k] && r >= rn[k];
+            restart[k] = b.cols_host[k].fresh;
+            rn[k] = r;
+            if (r <= o->rtol * bnorm[k]) {
+                conv[k] = 1;
+            } else if (stalled || outer[k] >= max_outer) {
+                conv[k] = 1;
+                fail[k] = 1;
+            }
+        }
+        if (select(fin)) FO_TRY(restart_columns());
+    }
+    hipLaunchKernelGGL(k_batch_unpack, dim3(grid_of(nd * n)), dim3(256), 0, s, b.x64, S, n, u, ld, nd);
+    FO_HIP(hipStreamSynchronize(s));
+    double worst = 0.0;
+    int max_outer_seen = 0;
+    for (int k = 0; k < n; ++k) {
+        if (bnorm[k] > 0) worst = std::max(worst, rn[k] / bnorm[k]);
+        max_outer_seen = std::max(max_outer_seen, outer[k]);
+        if (fail[k] && result == FO_OK) result = FO_NOT_CONVERGED;
+    }
+    for (int k = 0; k < n; ++k)
+        if (status[k] == FO_ERR_BREAKDOWN) result = FO_ERR_BREAKDOWN;
+    if (st) {
+        st->status = result;
+        st->iters_inner += it_total;
+        st->iters_outer = std::max(st->iters_outer, max_outer_seen);
+        st->rel_res = std::max(st->rel_res, worst);
+    }
+    return result;
+}
+
+int batch_solve(fo_ctx *c, const double *b, double *u, int n_rhs, int64_t ld, const fo_solve_opts *o,
+                fo_solve_stats *st)
+{
+    const int G = c->batch.S;
+    int worst = FO_OK;
+    for (int c0 = 0; c0 < n_rhs; c0 += G) {
+        const int n = std::min(G, n_rhs - c0);
+        int rc = batch_group(c, b + c0, u + c0, n, ld, o, st);
+        if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+        if (rc != FO_OK && (worst == FO_OK || rc < worst)) worst = rc;
+    }
+    return worst;
+}
+
+}  // namespace fo

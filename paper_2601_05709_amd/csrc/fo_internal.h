@@ -5,11 +5,31 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstdio>
 #include <map>
 #include <tuple>
 #include <vector>
 
 #include "../../include/fo.h"
+
+// Status plumbing of the host runtime: a failing HIP call is reported on
+// stderr and turns into FO_ERR_HIP; FO_TRY forwards any non-OK status.
+#define FO_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t _e = (call);                                                         \
+        if (_e != hipSuccess) {                                                         \
+            std::fprintf(stderr, "libfo: %s failed: %s\n", #call, hipGetErrorString(_e)); \
+            return FO_ERR_HIP;                                                          \
+        }                                                                               \
+    } while (0)
+
+#define FO_TRY(x)              \
+    do {                       \
+        int _rc = (x);         \
+        if (_rc != FO_OK) {    \
+            return _rc;        \
+        }                      \
+    } while (0)
 
 namespace fo {
 
@@ -53,6 +73,64 @@ struct TileSet {
     int32_t *halo_node = nullptr;       // [n_shared_nodes] global node of each shared node
     int32_t *halo_ptr = nullptr;        // [n_shared_nodes+1] node-major halo slot ranges
     int32_t *node_hrange = nullptr;     // [N][2] halo range of a node, (-1,-1) if interior
+};
+
+// Per-column state of the batched (multi-load) CG, one entry per column of
+// the block of right-hand sides.
+struct BatchCol {
+    double rho;      // r . z of the residual that built the current direction
+    double rho_new;  // r . z of the latest residual
+    double rr;       // r . r of the latest residual
+    double alpha, beta;
+    double tol2;     // phase target for r . r (rescaled residual)
+    double pq;       // p . A p
+    double pad;
+    int32_t done;    // converged in this phase, breakdown, or inactive
+    int32_t status;  // 0 ok, FO_ERR_BREAKDOWN
+    int32_t fresh;   // next phase restarts this column's direction
+    int32_t pad2;
+};
+
+// Iteration control of the batched CG (device; the host polls a copy).
+struct BatchCtl {
+    int32_t it;      // completed iterations of the current phase
+    int32_t done;    // every column done, or it >= max_it
+    int32_t max_it;
+    int32_t pad;
+};
+
+// Buffers of the batched path: block vectors are [n_dofs][S] (column
+// fastest), S = 16 NC right-hand sides per block, NC = 1..4.
+struct BatchState {
+    int S = 0;                          // column stride of the allocated block vectors
+    int mn_cap = 0;                     // node cap of the current batch tiles
+    int group = 8;                      // G: node-disjoint elements per contraction group
+    int slot_stride = 0;                // MS: element slots per tile (fixed stride)
+    int64_t n_slot_total = 0;           // n_tiles * MS
+    int version = 0;                    // bumps when the tiles change (graph keys)
+    int n_upd = 0;                      // blocks of the node-parallel batch kernels
+    TileSet tiles;                      // batch tiles over the context's element order
+    int32_t *selem = nullptr;           // [n_tiles][MS] element of each slot, -1 padding
+    uint64_t *slconn = nullptr;         // [n_tiles][MS] local vertex ids (4 x uint16)
+    int4 *sgconn = nullptr;             // [n_tiles][MS] global vertex ids
+    std::vector<void *> tile_allocs;    // released when the tiles are rebuilt
+    size_t tile_bytes = 0;
+    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    float *halo = nullptr;              // [halo_cap]
+    size_t halo_cap = 0;
+    double *x64 = nullptr, *r64 = nullptr, *b64 = nullptr;
+    double *pq_part = nullptr;          // [pq_cap] per tile and column
+    size_t pq_cap = 0;
+    double *rz_part = nullptr;          // [2][n_upd][S]
+    double *s2 = nullptr;               // [3][S]: scale^2 of the phase, new residual^2, b^2
+    uint8_t *mask = nullptr;            // [S] columns selected for a residual replacement
+    float *geo = nullptr;               // [n_tiles][MS][16] slot cofactors and weight (per level set)
+    BatchCol *cols = nullptr;           // [S]
+    BatchCtl *ctl = nullptr;
+    BatchCtl *ctl_host = nullptr;       // pinned
+    BatchCol *cols_host = nullptr;      // pinned [S]
+    double *s2_host = nullptr;          // pinned [S]
+    uint8_t *mask_host = nullptr;       // pinned [S]
 };
 
 struct DescentSetup {
@@ -131,6 +209,9 @@ struct fo_ctx {
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[FO_PROF_COUNT];
     size_t prof_used[FO_PROF_COUNT] = {0, 0, 0, 0};
+
+    // batched multi-load solves (allocated when max_rhs > 1)
+    fo::BatchState batch;
 
     // boundary nodes -> incident facets (descent normal penalty)
     int64_t n_bnodes = 0;

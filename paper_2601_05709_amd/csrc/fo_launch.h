@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
+#include <tuple>
 
 #include "fo_internal.h"
 
@@ -84,5 +86,25 @@ int launch_descent_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s);
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s);
 int launch_phigrad_tiled(const fo_ctx *c, const double *phi, double *gbuf, hipStream_t s);
 void launch_facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+
+
+// runtime helpers (fo_api.hip)
+// Enqueues one chunk of solver kernels on the context stream: captured once
+// into a HIP graph under `key` and replayed on the private stream (eager
+// while kernel profiling is on).
+int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
+                const std::function<int(hipStream_t)> &enqueue);
+int elas_apply64(fo_ctx *c, const double *x, double *y, hipStream_t s);
+
+// batched multi-load path (fo_batch.hip)
+int batch_setup(fo_ctx *c, int max_rhs);
+int batch_levelset(fo_ctx *c);
+void batch_release(fo_ctx *c);
+int batch_solve(fo_ctx *c, const double *b, double *u, int n_rhs, int64_t ld, const fo_solve_opts *o,
+                fo_solve_stats *st);
+int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us);
+int batch_apply_block(fo_ctx *c, int NC, const float *X, float *Y);
+int batch_tune(fo_ctx *c, int n_rhs, int *best_nodes, int *best_group, double *best_us);
+int batch_max_nodes(int D, int S);
 
 }  // namespace fo

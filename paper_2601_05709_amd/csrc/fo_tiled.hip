@@ -11,6 +11,7 @@
 #include "fo_ops.h"
 #include "fo_reduce.h"
 #include "fo_tiles.h"
+#include "fo_xcd.h"
 
 namespace fo {
 
@@ -31,17 +32,6 @@ static TileArgs tile_args(const fo_ctx *c)
                     t.max_elems, t.max_nodes, t.n_tiles};
 }
 
-// Blocks are dealt to the XCDs round-robin; give each XCD a contiguous run of
-// tiles (spatial neighbours) so shared nodes are fetched into one L2.
-// Launch with xcd_grid(n_tiles) blocks; returns -1 for the few spare blocks.
-__device__ __forceinline__ int xcd_tile(int b, int n_tiles)
-{
-    const int per = (n_tiles + 7) >> 3;
-    const int t = (b & 7) * per + (b >> 3);
-    return t < n_tiles ? t : -1;
-}
-
-static int xcd_grid(int n_tiles) { return 8 * ((n_tiles + 7) / 8); }
 
 // Element phase shared by the tile kernels: thread = element of the tile;
 // writes its (d+1) x NV vertex values into the node-sorted LDS slots.

@@ -43,13 +43,11 @@ uint64_t spread2(uint64_t v)
     return v;
 }
 
-}  // namespace
-
-void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *conn, int max_elems,
-                 HostTiles *h)
+// Stable order of the elements along a Morton curve of their centroids.
+void morton_order(int D, int64_t N, int64_t E, const double *X, const int32_t *conn,
+                  std::vector<int32_t> &perm)
 {
     const int NV = D + 1;
-    // 1. Morton order of element centroids in the bounding cube
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t n = 0; n < N; ++n)
         for (int i = 0; i < D; ++i) {
@@ -74,16 +72,24 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
         key[e] = D == 3 ? (spread3(q[0]) | spread3(q[1]) << 1 | spread3(q[2]) << 2)
                         : (spread2(q[0]) | spread2(q[1]) << 1);
     }
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+}
+
+}  // namespace
+
+void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *conn, int max_elems,
+                 HostTiles *h, int max_nodes, bool presorted)
+{
+    const int NV = D + 1;
     h->perm.resize(E);
     std::iota(h->perm.begin(), h->perm.end(), 0);
-    std::stable_sort(h->perm.begin(), h->perm.end(),
-                     [&](int32_t a, int32_t b) { return key[a] < key[b]; });
-    key.clear();
-    key.shrink_to_fit();
+    if (!presorted) morton_order(D, N, E, X, conn, h->perm);
 
-    // 2. greedy tiles bounded by element and node counts
-    const int max_n = tile_max_nodes(D);
-    const int max_e = std::min(std::max(max_elems, 1), tile_max_elems(D));
+    // greedy tiles bounded by element and node counts
+    const int max_n = max_nodes > 0 ? std::min(max_nodes, 65535) : tile_max_nodes(D);
+    const int max_e = max_nodes > 0 ? std::min(std::max(max_elems, 1), 16383)
+                                    : std::min(std::max(max_elems, 1), tile_max_elems(D));
     std::vector<int32_t> mark(N, -1);  // tile currently holding the node
     h->tile_elem_off_tmp.assign(1, 0);
     {
@@ -113,7 +119,7 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
     const int32_t T = (int32_t)h->tile_elem_off_tmp.size() - 1;
     h->n_tiles = T;
 
-    // 3. how many tiles touch each node; owner = first tile touching it
+    // how many tiles touch each node; owner = first tile touching it
     std::vector<int32_t> ntouch(N, 0), owner(N, -1);
     std::fill(mark.begin(), mark.end(), -1);
     for (int32_t t = 0; t < T; ++t)
@@ -129,7 +135,7 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
             }
         }
 
-    // 4. per tile: local numbering (interior, owned shared, other shared),
+    // per tile: local numbering (interior, owned shared, other shared),
     //    local connectivity and node-sorted LDS slots (unpadded first)
     struct Tile {
         int32_t e0, ne, nint, nown;
@@ -208,7 +214,7 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
         for (int32_t n : tl.nodes) local[n] = -1;
     }
 
-    // 5. halo: node-major slots; each shared node owns a contiguous range that
+    // halo: node-major slots; each shared node owns a contiguous range that
     //    its tiles fill in tile order
     std::vector<int32_t> cnt(N, 0);
     for (int32_t t = 0; t < T; ++t)
@@ -230,7 +236,7 @@ void build_tiles(int D, int64_t N, int64_t E, const double *X, const int32_t *co
     }
     std::vector<int32_t> fill(h->halo_ptr.begin(), h->halo_ptr.end() - 1);
 
-    // 6. padded per-tile arrays
+    // padded per-tile arrays
     const int64_t MN = h->max_nodes, ME = h->max_elems;
     h->info.assign((size_t)T * kTileInfo, 0);
     h->lconn.assign((size_t)T * ME * 4, 0);

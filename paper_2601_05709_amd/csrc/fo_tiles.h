@@ -53,8 +53,12 @@ int tile_max_elems(int dim);
 int tile_target_elems(int dim, int64_t E, int cus);
 
 // Builds tiles of at most max_elems elements.  Never fails for a valid mesh.
+// With max_nodes > 0 the tiles hold at most max_nodes nodes and max_elems is
+// not clamped to tile_max_elems (tiles of the batched operator); presorted
+// keeps the given element order instead of sorting along a Morton curve
+// (perm is then the identity).
 void build_tiles(int dim, int64_t N, int64_t E, const double *coords, const int32_t *conn,
-                 int max_elems, HostTiles *out);
+                 int max_elems, HostTiles *out, int max_nodes = 0, bool presorted = false);
 
 // Copies the tiles to the device arrays of c->tiles (allocated in c).
 int upload_tiles(fo_ctx *c, const HostTiles &h);

@@ -74,12 +74,17 @@ EXPORTS = {
     "fo_profile_enable": ([_vp, C.c_int32], C.c_int),
     "fo_profile_read": ([_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "fo_time_kernel": ([_vp, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "fo_batch_tune": ([_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
+                      C.c_int),
+    "fo_apply_elasticity_batch": ([_vp, _vp, _vp, C.c_int32], C.c_int),
+    "fo_batch_stats": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "fo_tile_stats": ([_vp] + [C.POINTER(C.c_int64)] * 5, C.c_int),
     "fo_status_string": ([C.c_int], C.c_char_p),
 }
 
 FO_PROF_ELAS_TILE_FP64, FO_PROF_ELAS_TILE_FP32, FO_PROF_HALO_FP64, FO_PROF_HALO_FP32 = 0, 1, 2, 3
-FO_KERNEL_CG_OP_FP64, FO_KERNEL_CG_OP_FP32 = 0, 1
+FO_KERNEL_CG_OP_FP64, FO_KERNEL_CG_OP_FP32, FO_KERNEL_BATCH_APPLY = 0, 1, 2
 
 _lib = None
 
@@ -253,6 +258,29 @@ class Context:
         _check(lib().fo_apply_elasticity(self.h, _ptr(x, dt, self.n_dofs, "x"),
                                          _ptr(y, dt, self.n_dofs, "y"), precision),
                "fo_apply_elasticity")
+
+    def apply_elasticity_batch(self, x, y, ncols: int):
+        """y = K(phi) x on FP32 blocks [n_dofs][ncols] (batched operator)."""
+        import torch
+        _check(lib().fo_apply_elasticity_batch(self.h, _ptr(x, torch.float32, self.n_dofs * ncols, "x"),
+                                               _ptr(y, torch.float32, self.n_dofs * ncols, "y"), ncols),
+               "fo_apply_elasticity_batch")
+
+    def batch_tune(self, n_rhs: int):
+        """Picks the batch tile node cap and register group size with the
+        fastest batched apply; returns (node cap, group, apply microseconds)."""
+        nodes, group, us = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().fo_batch_tune(self.h, n_rhs, C.byref(nodes), C.byref(group), C.byref(us)),
+               "fo_batch_tune")
+        return nodes.value, group.value, us.value
+
+    def batch_stats(self) -> dict:
+        cols, nodes, group = C.c_int32(), C.c_int32(), C.c_int32()
+        nt, hs = C.c_int64(), C.c_int64()
+        _check(lib().fo_batch_stats(self.h, C.byref(cols), C.byref(nodes), C.byref(group), C.byref(nt),
+                                    C.byref(hs)), "fo_batch_stats")
+        return {"columns": cols.value, "tile_nodes": nodes.value, "group": group.value,
+                "n_tiles": nt.value, "n_halo_slots": hs.value}
 
     def state_solve(self, b, u, opts: SolveOpts, n_rhs: int = 1, ld: Optional[int] = None,
                     allow_not_converged=False) -> Stats:
