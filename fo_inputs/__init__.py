@@ -12,6 +12,7 @@ loaded by a traction patch on the face x = Lx.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import List, Optional, Sequence, Tuple
 
@@ -395,6 +396,12 @@ SERVING_MESHES = (("2d", (128, 64)), ("2d", (256, 128)), ("3d", (32, 16, 16)),
                   ("3d", (64, 32, 32)), ("3d", (80, 40, 40)))
 
 
+@functools.lru_cache(maxsize=8)
+def _shared_mesh(cells, lengths) -> Mesh:
+    """Structured mesh shared (read-only) by the requests on the same grid."""
+    return structured_mesh(cells, lengths)
+
+
 def serving_request(req_id: int, base_seed: int = 1000, meshes=SERVING_MESHES) -> Workload:
     """One serving request: mesh drawn uniformly from `meshes`, 4..16 spherical
     holes of radius 0.15 with uniform centres, a load patch of side 0.1 on the
@@ -403,7 +410,7 @@ def serving_request(req_id: int, base_seed: int = 1000, meshes=SERVING_MESHES) -
     kind, cells = meshes[int(rng.integers(len(meshes)))]
     dim = 2 if kind == "2d" else 3
     lengths = (2.0, 1.0) if dim == 2 else (2.0, 1.0, 1.0)
-    mesh = structured_mesh(cells, lengths)
+    mesh = _shared_mesh(tuple(cells), lengths)
     n_holes = int(rng.integers(4, 17))
     centers = rng.uniform(0.0, 1.0, size=(n_holes, dim)) * np.asarray(lengths)
     phi = levelset_balls(mesh.coords, centers, 0.15)

@@ -58,7 +58,8 @@ typedef enum {
     FO_ERR_NOMEM = -3,       /* device allocation failed                          */
     FO_ERR_HIP = -4,         /* HIP runtime error                                 */
     FO_ERR_BREAKDOWN = -5,   /* CG breakdown: p.Ap <= 0, r.z < 0 or non-finite     */
-    FO_ERR_STATE = -6        /* call order: no level set / no descent setup yet   */
+    FO_ERR_STATE = -6,       /* call order: no level set / no descent setup yet   */
+    FO_ERR_BUSY = -7         /* serving pool: no free slot or HBM budget for it   */
 } fo_status;
 
 enum { FO_FP64 = 0,          /* plain FP64 conjugate gradients                     */
@@ -123,6 +124,13 @@ int fo_destroy(fo_ctx *ctx);
 
 /* Device bytes owned by the context (for footprint-based admission). */
 size_t fo_footprint_bytes(const fo_ctx *ctx);
+
+/* Estimate of fo_footprint_bytes for a context created on this mesh with
+ * max_rhs = 1, from the mesh sizes alone (no GPU, no tile build; 0 for an
+ * invalid mesh description).  The tile and halo terms assume the node ratios
+ * of structured simplicial meshes and lean high (up to about 2x on small
+ * meshes); admission control uses it until the actual footprint is known. */
+size_t fo_footprint_estimate(const fo_mesh *mesh);
 
 /* Select the element scatter used by the operators (FO_SCATTER_*).  The
  * atomic mode is a cross-check of the operators and of FP64 solves; FO_FP32_IR
@@ -237,6 +245,80 @@ int fo_batch_stats(const fo_ctx *ctx, int32_t *columns, int32_t *tile_nodes, int
  * tile-node pairs, shared nodes and halo slots (any pointer may be NULL). */
 int fo_tile_stats(const fo_ctx *ctx, int64_t *n_tiles, int64_t *max_nodes, int64_t *n_slots,
                   int64_t *n_shared_nodes, int64_t *n_halo_slots);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a pool of requests with continuous batching.  The paper solves sets
+ * of PDEs with varying parameters in its task-parallel and mixed modes
+ * (Section "Parallelization"); here such a set is a stream of requests, each
+ * one iteration's finite-element work on its own mesh: level set, state
+ * solve, compliance and shape derivative, descent solve.  A request is
+ * admitted into a free slot when the device-memory budget has room for its
+ * context (fo_footprint_estimate, replaced by the actual footprint once
+ * created).  Every running request owns a context and a HIP stream and is
+ * driven by a host worker thread, so requests admitted while others run
+ * overlap on the GPU; the results of a request do not depend on what else
+ * runs (every reduction has a fixed order).  A finished request's context
+ * stays resident, keyed by mesh_key, and a later request with the same
+ * nonzero key reuses it (mesh, tiles and workspace) instead of creating one;
+ * idle resident contexts are evicted, least recently used first, when a new
+ * context needs the memory.
+ *
+ * Host memory: every pointer in fo_request is a host pointer; the arrays must
+ * stay valid until the request is done (fo_pool_poll).  Requests with the
+ * same nonzero mesh_key must have identical mesh and material. */
+typedef struct fo_pool fo_pool;
+
+typedef struct {
+    fo_mesh mesh;
+    fo_material mat;
+    uint64_t mesh_key;             /* 0: never shared                                  */
+    const double *phi;             /* [n_nodes] level set                              */
+    const double *b;               /* [n_dofs] load                                    */
+    fo_solve_opts state_opts;
+    fo_solve_opts descent_solve_opts;
+    fo_descent_opts descent;
+    double lambda_vol, V;          /* volume term of the derivative (V > 0)            */
+    double *u_out;                 /* [n_dofs] displacement, or NULL                   */
+    double *rhs_out;               /* [n_dofs] shape-derivative load, or NULL          */
+    double *theta_out;             /* [n_dofs] descent direction, or NULL              */
+} fo_request;
+
+typedef struct {
+    int32_t status;                /* worst fo_status of the request's calls           */
+    int32_t reused_context;        /* 1 if a resident context was reused               */
+    fo_solve_stats state, descent;
+    double J, vol, B_tt;           /* compliance, volume, B(theta, theta)              */
+    double t_admit, t_start, t_end;/* seconds since fo_pool_create                     */
+} fo_pool_result;
+
+/* budget_bytes: device memory the pool may hold (contexts and request
+ * buffers); max_slots: requests running at once (1..64).  Uses the current
+ * HIP device.  Errors: FO_ERR_ARG, FO_ERR_HIP. */
+int fo_pool_create(fo_pool **out, size_t budget_bytes, int32_t max_slots);
+
+/* Starts a request in a free slot (*slot receives its index).  Returns
+ * FO_ERR_BUSY, starting nothing, when no slot is free or the budget cannot
+ * fit its context even after evicting idle resident contexts; FO_ERR_ARG for
+ * an invalid request. */
+int fo_pool_admit(fo_pool *pool, const fo_request *req, int32_t *slot);
+
+/* Blocks up to timeout_us microseconds (< 0: no limit) until some request is
+ * done and not yet released; *slot receives its index, or -1 on timeout or
+ * when nothing runs. */
+int fo_pool_wait(fo_pool *pool, int64_t timeout_us, int32_t *slot);
+
+/* *done = 1 when the slot's request finished (then *res is filled; the
+ * request's output arrays are written). */
+int fo_pool_poll(fo_pool *pool, int32_t slot, int32_t *done, fo_pool_result *res);
+
+/* Frees a finished slot for a new request (FO_ERR_STATE if still running). */
+int fo_pool_release(fo_pool *pool, int32_t slot);
+
+/* Budget accounting: bytes reserved, running requests, resident contexts. */
+int fo_pool_stats(const fo_pool *pool, size_t *used_bytes, int32_t *running, int32_t *resident);
+
+/* Waits for every running request, then frees all contexts. */
+int fo_pool_destroy(fo_pool *pool);
 
 const char *fo_status_string(int status);
 

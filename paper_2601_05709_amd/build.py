@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfo.so")
 ARCH = os.environ.get("FO_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fo_api.hip", "fo_kernels.hip", "fo_tiled.hip", "fo_cg.hip", "fo_batch.hip", "fo_pool.hip",
+SOURCES = ["fo_api.hip", "fo_kernels.hip", "fo_tiled.hip", "fo_cg.hip", "fo_batch.hip", "fo_pool.cpp",
            "fo_tiles.cpp"]
 
 HIP_FLAGS = [
@@ -43,7 +43,7 @@ def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     cmd = [hipcc()] + HIP_FLAGS + ["-c", path, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-Wall", "-c", path, "-o", obj]
+        cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
@@ -59,7 +59,7 @@ def build(jobs: int = 8) -> str:
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-Wl,--no-undefined", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-Wl,--no-undefined", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))

@@ -535,6 +535,7 @@ const char *fo_status_string(int s)
     case FO_ERR_HIP: return "HIP runtime error";
     case FO_ERR_BREAKDOWN: return "CG breakdown";
     case FO_ERR_STATE: return "call order (level set or setup missing)";
+    case FO_ERR_BUSY: return "no free slot or device-memory budget";
     default: return "unknown status";
     }
 }
@@ -714,6 +715,33 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
 }
 
 size_t fo_footprint_bytes(const fo_ctx *c) { return c ? c->bytes : 0; }
+size_t fo_footprint_estimate(const fo_mesh *m)
+{
+    if (!m || (m->dim != 2 && m->dim != 3) || m->n_nodes <= 0 || m->n_elems <= 0) return 0;
+    const size_t D = (size_t)m->dim, N = (size_t)m->n_nodes, E = (size_t)m->n_elems, n = N * D;
+    const size_t F = m->n_bfacets > 0 ? (size_t)m->n_bfacets : 0;
+    size_t b = 0;
+    b += N * D * 12 + (D + 1) * E * 4 + E * 4 + n + E;   // coordinates, connectivity, perm, clamp, chi
+    b += n * 8 * 2 + n * 4;                               // diagonal, Jacobi FP64/FP32
+    b += n * 8 * 7 + n * 4 * 6;                           // Krylov vectors FP64 / FP32
+    b += (size_t)kRedBlocks * 8 * 8 + 8192;               // partial sums, scalars
+    b += N * (D + 1) * 8 + E * D * D * 8;                 // level-set recovery, S1 tensors
+    b += ((E + kBlock - 1) / kBlock) * 2 * 8;             // derivative partials
+    b += F * D * 12 + F * 8 + N * 8;                      // facets, normals, boundary nodes
+    // tiles of the target size for 256 CUs (a quarter more for tiles that the
+    // node cap closes early), nodes per tile at 2.5x the mesh's node/element
+    // ratio (the tile surface), padded per-tile arrays, tile-node pairs and
+    // halo slots, halo partials of d+1 values per slot
+    const size_t target = (size_t)tile_target_elems((int)D, (int64_t)E, 256);
+    const size_t T = (E + target - 1) / target * 5 / 4 + 1;
+    const size_t ME = std::min<size_t>(E, target);
+    const size_t MN = std::min<size_t>((size_t)tile_max_nodes((int)D), (ME * N * 5) / (2 * E) + 16);
+    b += T * (32 + ME * 16 + MN * 10) + N * 8 + N * 3 * 4;
+    b += std::min(T * MN, (D + 1) * E) * (D + 1) * 8;
+    b += E + 2 * n * 8;                                   // descent: Omega0 flags, diagonal
+    b += 64 * 256;                                        // allocation rounding
+    return b;
+}
 
 int fo_profile_enable(fo_ctx *c, int32_t on)
 {

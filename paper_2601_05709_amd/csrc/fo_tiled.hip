@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "fo_element.h"
 #include "fo_internal.h"
@@ -331,22 +332,22 @@ static int set_lds(const void *fn, size_t cap)
 template <int D, typename T, class Op>
 static int ensure_lds_attr()
 {
-    static bool done = false;
-    if (done) return 0;
+    static std::atomic<bool> done{false};
+    if (done.load(std::memory_order_acquire)) return 0;
     size_t cap = tile_lds_bytes<D, T, Op::NX, Op::NV>(tile_max_nodes(D), tile_max_elems(D));
     if (set_lds((const void *)k_tile_apply<D, T, Op>, cap)) return 1;
-    done = true;
+    done.store(true, std::memory_order_release);
     return 0;
 }
 
 template <int D, typename T>
 static int ensure_lds_attr_cg()
 {
-    static bool done = false;
-    if (done) return 0;
+    static std::atomic<bool> done{false};
+    if (done.load(std::memory_order_acquire)) return 0;
     size_t cap = tile_lds_bytes<D, T, D, D>(tile_max_nodes(D), tile_max_elems(D));
     if (set_lds((const void *)k_tile_cg<D, T>, cap)) return 1;
-    done = true;
+    done.store(true, std::memory_order_release);
     return 0;
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfo.so")
 
 FO_OK, FO_NOT_CONVERGED = 0, 1
 FO_ERR_ARG, FO_ERR_MESH, FO_ERR_NOMEM, FO_ERR_HIP, FO_ERR_BREAKDOWN, FO_ERR_STATE = -1, -2, -3, -4, -5, -6
+FO_ERR_BUSY = -7
 FO_FP64, FO_FP32_IR = 0, 1
 FO_SCATTER_TILED, FO_SCATTER_ATOMIC = 0, 1
 
@@ -56,6 +57,20 @@ class fo_solve_stats(C.Structure):
 
 
 _vp = C.c_void_p
+class fo_request(C.Structure):
+    _fields_ = [("mesh", fo_mesh), ("mat", fo_material), ("mesh_key", C.c_uint64),
+                ("phi", C.c_void_p), ("b", C.c_void_p), ("state_opts", fo_solve_opts),
+                ("descent_solve_opts", fo_solve_opts), ("descent", fo_descent_opts),
+                ("lambda_vol", C.c_double), ("V", C.c_double), ("u_out", C.c_void_p),
+                ("rhs_out", C.c_void_p), ("theta_out", C.c_void_p)]
+
+
+class fo_pool_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reused_context", C.c_int32), ("state", fo_solve_stats),
+                ("descent", fo_solve_stats), ("J", C.c_double), ("vol", C.c_double), ("B_tt", C.c_double),
+                ("t_admit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double)]
+
+
 EXPORTS = {
     "fo_create": ([C.POINTER(_vp), C.POINTER(fo_mesh), C.POINTER(fo_material), C.c_int32, _vp], C.c_int),
     "fo_destroy": ([_vp], C.c_int),
@@ -80,6 +95,14 @@ EXPORTS = {
     "fo_batch_stats": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "fo_tile_stats": ([_vp] + [C.POINTER(C.c_int64)] * 5, C.c_int),
+    "fo_footprint_estimate": ([C.POINTER(fo_mesh)], C.c_size_t),
+    "fo_pool_create": ([C.POINTER(_vp), C.c_size_t, C.c_int32], C.c_int),
+    "fo_pool_admit": ([_vp, C.POINTER(fo_request), C.POINTER(C.c_int32)], C.c_int),
+    "fo_pool_wait": ([_vp, C.c_int64, C.POINTER(C.c_int32)], C.c_int),
+    "fo_pool_poll": ([_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(fo_pool_result)], C.c_int),
+    "fo_pool_release": ([_vp, C.c_int32], C.c_int),
+    "fo_pool_stats": ([_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "fo_pool_destroy": ([_vp], C.c_int),
     "fo_status_string": ([C.c_int], C.c_char_p),
 }
 

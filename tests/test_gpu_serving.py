@@ -1,0 +1,138 @@
+"""Serving pool on the GPU: results alone and in the mix, parity with the
+oracle, admission by device-memory budget, context reuse, and a short
+Poisson stream."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import fo_inputs as fi
+import oracle as oc
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2601_05709_amd import fo, serving  # noqa: E402
+
+SMALL = (("2d", (64, 32)), ("2d", (37, 19)), ("3d", (12, 6, 6)), ("3d", (16, 8, 8)))
+
+
+def requests(ids, keyed=True):
+    out = []
+    for i in ids:
+        w = fi.serving_request(i, base_seed=500, meshes=SMALL)
+        out.append(serving.Request(w, key=serving.mesh_key(w) if keyed else 0,
+                                   state_opts=fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-10),
+                                   descent_opts=fo.SolveOpts(rtol=1e-10)))
+    return out
+
+
+def run_all(pool, reqs):
+    slots = {}
+    for k, r in enumerate(reqs):
+        s = pool.admit(r)
+        assert s is not None
+        slots[s] = k
+    res = [None] * len(reqs)
+    while slots:
+        pool.wait(1.0)
+        for s in list(slots):
+            r = pool.poll(s)
+            if r is not None:
+                res[slots.pop(s)] = r
+                pool.release(s)
+    return res
+
+
+def test_results_alone_and_in_the_mix_are_identical():
+    """T18: every request's outputs are bitwise the same whether it runs alone
+    or together with five others on the device."""
+    alone = requests(range(6))
+    for r in alone:
+        pool = serving.Pool(4 << 30, max_slots=1)
+        (res,) = run_all(pool, [r])
+        assert res.status == 0
+        r.res = res
+        pool.close()
+    mix = requests(range(6))
+    pool = serving.Pool(4 << 30, max_slots=6)
+    out = run_all(pool, mix)
+    assert max(r.t_start for r in out) < min(r.t_end for r in out)  # they did overlap
+    for a, b, rb in zip(alone, mix, out):
+        assert rb.status == 0
+        assert np.array_equal(a.u, b.u) and np.array_equal(a.rhs, b.rhs) and np.array_equal(a.theta, b.theta)
+        assert a.res.J == rb.J and a.res.B_tt == rb.B_tt and a.res.vol == rb.vol
+    pool.close()
+
+
+def test_request_matches_oracle():
+    (r,) = requests([3])
+    w = r.w
+    pool = serving.Pool(2 << 30, max_slots=2)
+    (res,) = run_all(pool, [r])
+    pool.close()
+    ref = oc.run_iteration(w, rtol=1e-12, lambda_vol=0.0, V=1.0, dt=0.0)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(r.u, ref.u) < 1e-8
+    assert rel(r.rhs, ref.rhs) < 1e-6
+    assert rel(r.theta, ref.theta) < 1e-6
+    assert res.J == pytest.approx(ref.J[0], rel=1e-6)
+    assert res.B_tt == pytest.approx(ref.B_tt, rel=1e-6)
+
+
+def test_budget_admission_and_context_reuse():
+    reqs = requests([0, 4, 8, 12])   # same seed base: mixed meshes
+    pool = serving.Pool(1 << 40, max_slots=4)
+    (res0,) = run_all(pool, [reqs[0]])
+    used_one = pool.stats()["used_bytes"]
+    assert pool.stats()["resident"] == 1 and used_one > 0
+    # same mesh again: the resident context is reused, no new memory
+    again = requests([0])[0]
+    (res1,) = run_all(pool, [again])
+    assert res1.reused_context and pool.stats()["used_bytes"] == used_one
+    assert np.array_equal(again.u, reqs[0].u)
+    pool.close()
+    # a budget that fits one context: the second admission waits for the first
+    pool = serving.Pool(int(used_one * 1.6), max_slots=4)
+    a = requests([0], keyed=False)[0]
+    b = requests([0], keyed=False)[0]
+    s = pool.admit(a)
+    assert s is not None
+    assert pool.admit(b) is None          # busy: budget taken by the running request
+    pool.wait(None)
+    assert pool.poll(s) is not None
+    pool.release(s)
+    assert pool.stats()["used_bytes"] == 0  # unkeyed contexts are freed at completion
+    s2 = pool.admit(b)
+    assert s2 is not None
+    pool.wait(None)
+    assert pool.poll(s2).status == 0
+    pool.release(s2)
+    assert np.array_equal(a.u, b.u)
+    pool.close()
+
+
+def test_footprint_estimate_close_to_actual():
+    for cells in ((64, 32), (128, 64), (16, 8, 8), (32, 16, 16)):
+        w = fi.cantilever_2d(cells) if len(cells) == 2 else fi.cantilever_3d(cells)
+        ctx = fo.Context.from_workload(w)
+        m = w.mesh
+        coords = np.ascontiguousarray(m.coords)
+        conn = np.ascontiguousarray(m.conn, dtype=np.int32)
+        bf = np.ascontiguousarray(m.bfacets, dtype=np.int32)
+        bn = np.ascontiguousarray(m.bnormal)
+        mesh = fo.fo_mesh(m.dim, m.n_nodes, m.n_elems, coords.ctypes.data, conn.ctypes.data, None,
+                          int(bf.shape[1]), bf.ctypes.data, bn.ctypes.data)
+        est = fo.lib().fo_footprint_estimate(C.byref(mesh))
+        actual = ctx.footprint
+        print(cells, est, actual, flush=True)
+        assert 0.5 * est <= actual <= 1.25 * est, (cells, est, actual)
+
+
+def test_poisson_stream_completes():
+    reqs = requests(range(24))
+    arrivals = np.cumsum(np.random.default_rng(4).exponential(1.0 / 400.0, size=24))
+    out = serving.serve(reqs, arrivals, budget_bytes=2 << 30, max_slots=8)
+    assert out["statuses"] == [0]
+    assert 0 < out["latency_p50_s"] <= out["latency_p99_s"]
+    assert out["reused_contexts"] > 0
