@@ -185,6 +185,41 @@ def batched_case(cells=(64, 32, 32), n_loads=64):
     }
 
 
+def serving_case(n=120, rate=200.0, budget_bytes=16 << 30, max_slots=8):
+    """Serving stream: n requests (state solve FP32+refinement to 1e-8,
+    shape derivative, descent solve FP64 to 1e-8) on meshes drawn from the
+    five serving sizes, Poisson arrivals at `rate`, admission by a device
+    memory budget, contexts kept resident per mesh."""
+    import fo_inputs as fi
+    from paper_2601_05709_amd import fo, serving
+    reqs = []
+    for i in range(n):
+        w = fi.serving_request(i)
+        # small problems are launch-latency bound: FP32 saves no time there and
+        # only adds iterations, so they are solved in FP64
+        prec = fo.FO_FP32_IR if w.mesh.n_dofs >= 100000 else fo.FO_FP64
+        reqs.append(serving.Request(w, key=serving.mesh_key(w),
+                                    state_opts=fo.SolveOpts(precision=prec, rtol=1e-8),
+                                    descent_opts=fo.SolveOpts(rtol=1e-8)))
+    arrivals = fi.poisson_arrivals(n, rate, seed=4)
+    out = serving.serve(reqs, arrivals, budget_bytes, max_slots)
+    kinds = {}
+    for r, q in zip(out["results"], reqs):
+        k = q.w.name.split("_", 1)[1]
+        kinds.setdefault(k, []).append(r.t_end - r.t_start)
+    return {
+        "workload": "Poisson arrivals %.0f/s, %d requests, meshes 2D 128x64/256x128, 3D 32x16x16/64x32x32/"
+                    "80x40x40; state (FP32+refinement from 100k DOFs, else FP64) + derivative + descent "
+                    "per request, rel. res 1e-8" % (rate, n),
+        "solves_per_s": out["solves_per_s"], "wall_s": out["wall_s"],
+        "latency_p50_s": out["latency_p50_s"], "latency_p99_s": out["latency_p99_s"],
+        "service_p50_s": out["service_p50_s"], "max_queue": out["max_queue"],
+        "reused_contexts": out["reused_contexts"], "statuses": out["statuses"],
+        "budget_bytes": budget_bytes, "max_slots": max_slots,
+        "service_s_by_mesh": {k: {"n": len(v), "mean": float(sum(v) / len(v))} for k, v in sorted(kinds.items())},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +231,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-only", action="store_true", help="short run for profilers")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-load case")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-requests", type=int, default=120)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -312,6 +349,12 @@ def main():
         log("batched: %.1f solves/s vs %.1f column-wise FP64 (x%.2f); apply %.0f us"
             % (result["batched"]["solves_per_s"], result["batched"]["fp64_columnwise"]["solves_per_s"],
                result["batched"]["speedup_vs_fp64_columnwise"], result["batched"]["apply"]["avg_us"]))
+    if not args.no_serving:
+        log("serving stream (%d requests, 200/s)" % args.serving_requests)
+        result["serving"] = serving_case(args.serving_requests)
+        sv = result["serving"]
+        log("serving: %.1f solves/s, latency p50 %.3f s p99 %.3f s" % (sv["solves_per_s"], sv["latency_p50_s"],
+                                                                       sv["latency_p99_s"]))
     if not args.no_cpu:
         log("CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
         result["cpu_baseline"] = cpu_baseline(w, st64.iters_inner, args.cpu_seconds)

@@ -351,11 +351,26 @@ int solve_fp64(fo_ctx *c, OpKind k, const double *b, const double *dinv, const f
     return status;
 }
 
+// Iteration cap of a first FP32 phase (no completed phase to compare with):
+// Jacobi-PCG iteration counts of the elasticity operator grow like the mesh
+// width, i.e. like sqrt(n) in 2D and n^(1/3) in 3D; 8 sqrt(n) is far above what
+// a well-resolved first phase needs on both.
+}  // namespace
+
+int64_t fo::first_phase_cap(int64_t n) { return std::max<int64_t>(512, (int64_t)(8.0 * std::sqrt((double)n))); }
+
+namespace {
+
 // FP32 CG with FP64 residual replacement.  Phases of FP32 CG each lower the
 // (rescaled) residual by inner_rtol; between phases x64 += s x32, the FP64
 // residual b - K x64 is recomputed, the FP32 residual is replaced by it and
 // the search direction is kept (rescaled), so the Krylov process continues
 // instead of restarting.  Stops when ||b - K x64|| <= rtol ||b|| (FP64).
+// A phase running twice as long as the longest completed one (the first:
+// first_phase_cap) is stopped and the next one restarts its direction; after
+// two such phases in a row (FP32
+// cannot resolve the operator: kappa * eps_32 near 1) the solve finishes with
+// FP64 CG on the residual equation.
 int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats *st)
 {
     const int64_t n = c->ndof;
@@ -376,6 +391,9 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
     const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
     const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-2;
     int fresh = 1;
+    int64_t longest = 0;  // iterations of the longest phase that reached its target
+    int capped_run = 0;   // consecutive phases stopped at their cap
+    const int64_t first_cap = first_phase_cap(n);
     FusedVecs<float> v{c->x32, c->r32, c->q32, {c->p32, c->p32b}, c->dinv32};
     if (c->has_isolated) {
         launch_fill<float>(c->q32, n, 0.0f, s);
@@ -389,9 +407,17 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
         }
         if (outer >= max_outer || inner >= o->max_iter) break;
         const int left = (int)std::max<int64_t>(1, (int64_t)o->max_iter - inner);
-        launch_ir_phase(c, c->r64, s2, v.r, v.x, v.dinv, phase_rtol, left, fresh, s);
+        // a phase that runs twice as long as the longest completed one has
+        // stagnated (the FP32 recursion lost conjugacy): end it, replace the
+        // residual and restart the direction
+        const int cap = (int)std::min<int64_t>(left, longest > 0 ? std::max<int64_t>(2 * longest, 64) : first_cap);
+        launch_ir_phase(c, c->r64, s2, v.r, v.x, v.dinv, phase_rtol, cap, fresh, s);
+        const int64_t before = inner;
         FO_TRY(fused_run<float>(c, v, o, &inner));
-        fresh = c->scal_host->status == FO_ERR_BREAKDOWN ? 1 : 0;
+        const bool capped = c->scal_host->it >= cap && c->scal_host->status != FO_ERR_BREAKDOWN;
+        if (!capped) longest = std::max<int64_t>(longest, inner - before);
+        capped_run = capped ? capped_run + 1 : 0;
+        fresh = (c->scal_host->status == FO_ERR_BREAKDOWN || capped) ? 1 : 0;
         if (c->scal_host->it & 1)  // the last direction is in p[1]; phases start from p[0]
             FO_HIP(hipMemcpyAsync(v.p[0], v.p[1], n * sizeof(float), hipMemcpyDeviceToDevice, s));
         launch_ir_accumulate(c->x64, v.x, s2, n, s);
@@ -410,6 +436,28 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
             break;
         }
         rn = rn_new;
+        if (capped_run >= 2) break;  // FP32 stagnates (kappa * eps_32 too large): finish in FP64
+    }
+    if (status == FO_NOT_CONVERGED && capped_run >= 2 && !(rn <= o->rtol * bnorm) && inner < o->max_iter) {
+        // FP64 CG on the residual equation K d = r64 to the same absolute
+        // target, then x64 += d
+        FO_HIP(hipMemcpyAsync(c->x64b, c->x64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        FO_HIP(hipMemcpyAsync(c->t64, c->r64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        fo_solve_opts o2 = *o;
+        o2.rtol = o->rtol * bnorm / rn;
+        o2.max_iter = (int32_t)std::max<int64_t>(1, (int64_t)o->max_iter - inner);
+        fo_solve_stats s2st{};
+        int rc = solve_fp64(c, OP_ELAS64, c->t64, c->dinv64, &o2, &s2st);
+        if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+        inner += s2st.iters_inner;
+        launch_add64(c->x64, c->x64b, n, s);
+        FO_TRY(elas_apply<double>(c, c->x64, c->q64, s));
+        ++outer;
+        launch_residual64(b, c->q64, c->r64, n, c->partials, s2 + 1, s);
+        FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        FO_HIP(hipStreamSynchronize(s));
+        rn = std::sqrt(c->red_host[0]);
+        status = rc == FO_ERR_BREAKDOWN ? FO_ERR_BREAKDOWN : (rn <= o->rtol * bnorm ? FO_OK : FO_NOT_CONVERGED);
     }
     if (st) {
         st->status = status;
@@ -419,6 +467,15 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
     }
     return status;
 }
+
+}  // namespace
+
+int fo::fp64_solve(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats *st)
+{
+    return solve_fp64(c, OP_ELAS64, b, c->dinv64, o, st);
+}
+
+namespace {
 
 bool descent_same(const fo_ctx *c, const fo_descent_opts *d)
 {
@@ -639,6 +696,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         (rc = dev_alloc(c, &c->r32, n)) || (rc = dev_alloc(c, &c->p32, n)) ||
         (rc = dev_alloc(c, &c->q32, n)) || (rc = dev_alloc(c, &c->b32, n)) ||
         (rc = dev_alloc(c, &c->p64b, n)) || (rc = dev_alloc(c, &c->p32b, n)) ||
+        (rc = dev_alloc(c, &c->x64b, n)) ||
         (rc = dev_alloc(c, &c->bb_part, (size_t)kRedBlocks)) ||
         (rc = dev_alloc(c, &c->partials, (size_t)kRedBlocks * 4)) ||
         (rc = dev_alloc(c, &c->pq_part, (size_t)std::max<int64_t>(ht.n_tiles, kRedBlocks))) ||
@@ -703,6 +761,24 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
                     up(c->bnode_fac, bfac.data(), bfac.size() * sizeof(int32_t)))))
         return fail(FO_ERR_HIP);
     if ((rc = upload_tiles(c, ht))) return fail(rc);
+    // FP32 operator geometry: tile-node coordinates relative to the tile's
+    // first node, formed in FP64 (kept alive until the stream sync below)
+    std::vector<float> tx((size_t)std::max<int64_t>((int64_t)ht.n_tiles * ht.max_nodes * D, 1), 0.0f);
+    {
+        const int64_t T = ht.n_tiles, MN = ht.max_nodes;
+        for (int64_t t = 0; t < T; ++t) {
+            const int32_t nn = ht.info[(size_t)t * kTileInfo + kTileNN];
+            const double *o = m->coords + (int64_t)ht.nodes[(size_t)t * MN] * D;
+            for (int32_t l = 0; l < nn; ++l) {
+                const double *x = m->coords + (int64_t)ht.nodes[(size_t)(t * MN + l)] * D;
+                for (int q = 0; q < D; ++q) tx[(size_t)(t * MN + l) * D + q] = (float)(x[q] - o[q]);
+            }
+        }
+        if ((rc = dev_alloc(c, &c->tiles.tx32, tx.size())) ||
+            hipMemcpyAsync(c->tiles.tx32, tx.data(), tx.size() * sizeof(float), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
+            return fail(rc ? rc : FO_ERR_HIP);
+    }
     if ((rc = tiled_prepare(c))) return fail(rc);
     if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||

@@ -88,8 +88,8 @@ __device__ __forceinline__ int pick4(const int4 v, int k)
 template <int D>
 __global__ __launch_bounds__(256) void k_batch_geom(const int32_t *__restrict__ selem,
                                                     const int4 *__restrict__ sgconn, int64_t n_slots,
-                                                    const float *__restrict__ coords,
-                                                    const uint8_t *__restrict__ chi, float ersatz,
+                                                    const double *__restrict__ coords,
+                                                    const uint8_t *__restrict__ chi, double ersatz,
                                                     float *__restrict__ geo)
 {
     constexpr int NV = D + 1;
@@ -102,26 +102,27 @@ __global__ __launch_bounds__(256) void k_batch_geom(const int32_t *__restrict__ 
         if (e >= 0) {
             const int4 gv = sgconn[sl];
             const int gid[4] = {gv.x, gv.y, gv.z, gv.w};
-            float X[NV][D];
-            const float *Xp[NV];
+            // geometry in FP64, stored in FP32
+            double X[NV][D];
+            const double *Xp[NV];
 #pragma unroll
             for (int a = 0; a < NV; ++a) {
 #pragma unroll
                 for (int i = 0; i < D; ++i) X[a][i] = coords[(int64_t)gid[a] * D + i];
                 Xp[a] = X[a];
             }
-            const Geom<D, float> gm = geom<D, float>(Xp);
+            const Geom<D, double> gm = geom<D, double>(Xp);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                float c0 = 0.f;
+                double c0 = 0.0;
 #pragma unroll
                 for (int a = 1; a < NV; ++a) {
-                    out[a * D + i] = gm.c[a - 1][i];
+                    out[a * D + i] = (float)gm.c[a - 1][i];
                     c0 -= gm.c[a - 1][i];
                 }
-                out[i] = c0;
+                out[i] = (float)c0;
             }
-            out[12] = (chi[e] ? 1.f : ersatz) * inv_measure_det2<D, float>(gm.det);
+            out[12] = (float)((chi[e] ? 1.0 : ersatz) * inv_measure_det2<D, double>(gm.det));
         }
         f32x4 *g4 = reinterpret_cast<f32x4 *>(geo + sl * 16);
 #pragma unroll
@@ -473,6 +474,10 @@ __global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *col
             c.fresh = 1;
         } else if (b <= c.tol2) {
             c.done = 1;
+        } else if (++c.it >= c.cap) {  // stagnating phase: stop, restart after the replacement
+            c.done = 1;
+            c.capped = 1;
+            c.fresh = 1;
         } else {
             c.beta = c.rho > 0.0 ? a / c.rho : 0.0;
             c.rho = a;
@@ -552,7 +557,7 @@ __global__ __launch_bounds__(256) void k_batch_rescale(const double *__restrict_
 __global__ __launch_bounds__(256) void k_batch_phase(BatchCtl *ctl, BatchCol *cols,
                                                      const double *__restrict__ rz_part, int nb,
                                                      int S, double *s2, const uint8_t *mask,
-                                                     double phase_rtol)
+                                                     const int32_t *caps, double phase_rtol)
 {
     __shared__ double lds[4];
     const int k = blockIdx.x;
@@ -578,6 +583,8 @@ __global__ __launch_bounds__(256) void k_batch_phase(BatchCtl *ctl, BatchCol *co
         n.tol2 = phase_rtol * phase_rtol;
         n.beta = coef;
         n.fresh = 0;
+        n.it = 0;
+        n.cap = caps[k];
         n.done = b <= n.tol2 ? 1 : 0;
         if (!(a >= 0.0) || !isfinite(a)) {
             n.status = FO_ERR_BREAKDOWN;
@@ -646,6 +653,15 @@ __global__ __launch_bounds__(256) void k_batch_residual_col(const double *__rest
     for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < ndof;
          row += (int64_t)gridDim.x * blockDim.x)
         R[row * S + k] = fixed[row] ? 0.0 : B[row * S + k] - q[row];
+}
+
+// X[:, k] += d (one column of a [n_dofs][S] block).
+__global__ __launch_bounds__(256) void k_batch_add_col(double *__restrict__ X, const double *__restrict__ d,
+                                                       int S, int k, int64_t ndof)
+{
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < ndof;
+         row += (int64_t)gridDim.x * blockDim.x)
+        X[row * S + k] += d[row];
 }
 
 // Caller's b [n_dofs][ld] (columns c0..c0+n-1) -> [n_dofs][S], clamped rows
@@ -863,8 +879,9 @@ template <typename T>
 static int bup(fo_ctx *c, T **dst, const std::vector<T> &v)
 {
     FO_TRY(balloc(c, (void **)dst, v.size() * sizeof(T), true));
-    if (!v.empty() &&
-        hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    if (!v.empty() && (hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream) !=
+                           hipSuccess ||
+                       hipStreamSynchronize(c->stream) != hipSuccess))
         return FO_ERR_HIP;
     return FO_OK;
 }
@@ -887,6 +904,8 @@ void batch_release(fo_ctx *c)
     if (b.cols_host) (void)hipHostFree(b.cols_host);
     if (b.s2_host) (void)hipHostFree(b.s2_host);
     if (b.mask_host) (void)hipHostFree(b.mask_host);
+    if (b.caps_host) (void)hipHostFree(b.caps_host);
+    b.caps_host = nullptr;
     b.ctl_host = nullptr;
     b.cols_host = nullptr;
     b.s2_host = nullptr;
@@ -1004,8 +1023,11 @@ static int mesh_host(fo_ctx *c, std::vector<double> &X, std::vector<int32_t> &co
 {
     X.resize((size_t)c->N * c->dim);
     conn.resize((size_t)(c->dim + 1) * c->E);
-    if (hipMemcpy(X.data(), c->coords, X.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(conn.data(), c->conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(X.data(), c->coords, X.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(conn.data(), c->conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
         return FO_ERR_HIP;
     return FO_OK;
 }
@@ -1030,12 +1052,14 @@ int batch_setup(fo_ctx *c, int max_rhs)
     FO_TRY(balloc(c, (void **)&b.rz_part, (size_t)2 * b.n_upd * b.S * sizeof(double), false));
     FO_TRY(balloc(c, (void **)&b.s2, (size_t)3 * b.S * sizeof(double), false));
     FO_TRY(balloc(c, (void **)&b.mask, (size_t)b.S, false));
+    FO_TRY(balloc(c, (void **)&b.caps, (size_t)b.S * sizeof(int32_t), false));
     FO_TRY(balloc(c, (void **)&b.cols, (size_t)b.S * sizeof(BatchCol), false));
     FO_TRY(balloc(c, (void **)&b.ctl, sizeof(BatchCtl), false));
     if (hipHostMalloc((void **)&b.ctl_host, sizeof(BatchCtl)) != hipSuccess ||
         hipHostMalloc((void **)&b.cols_host, b.S * sizeof(BatchCol)) != hipSuccess ||
         hipHostMalloc((void **)&b.s2_host, b.S * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&b.mask_host, b.S) != hipSuccess)
+        hipHostMalloc((void **)&b.mask_host, b.S) != hipSuccess ||
+        hipHostMalloc((void **)&b.caps_host, b.S * sizeof(int32_t)) != hipSuccess)
         return FO_ERR_NOMEM;
     // directions start at zero (the first direction of a column ignores them,
     // but stale non-finite bits must not survive a zero coefficient)
@@ -1197,10 +1221,10 @@ int batch_levelset(fo_ctx *c)
     const int grid = grid_of(b.n_slot_total);
     if (c->dim == 2)
         hipLaunchKernelGGL(k_batch_geom<2>, dim3(grid), dim3(256), 0, c->stream, b.selem, b.sgconn,
-                           b.n_slot_total, c->coords32, c->chi, (float)c->ersatz, b.geo);
+                           b.n_slot_total, c->coords, c->chi, c->ersatz, b.geo);
     else
         hipLaunchKernelGGL(k_batch_geom<3>, dim3(grid), dim3(256), 0, c->stream, b.selem, b.sgconn,
-                           b.n_slot_total, c->coords32, c->chi, (float)c->ersatz, b.geo);
+                           b.n_slot_total, c->coords, c->chi, c->ersatz, b.geo);
     FO_HIP(hipGetLastError());
     return FO_OK;
 }
@@ -1240,15 +1264,21 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
     FO_TRY(residual_norms(c, S));
     std::vector<double> bnorm(S), rn(S);
     std::vector<int> conv(S, 0), status(S, FO_OK), restart(S, 1), outer(S, 0), fail(S, 0);
+    std::vector<int64_t> longest(S, 0);  // longest phase of a column that reached its target
+    std::vector<int> capped_run(S, 0), finish64(S, 0);
     for (int k = 0; k < S; ++k) {
         bnorm[k] = rn[k] = std::sqrt(b.s2_host[k]);
         conv[k] = k >= n || bnorm[k] == 0.0;
     }
     // columns to (re)start from r64: mask_host
+    // a phase twice as long as the column's longest completed one has
+    // stagnated: it is stopped and restarted after the replacement
     auto select = [&](const std::vector<int> &fin) {
         bool any = false;
         for (int k = 0; k < S; ++k) {
             b.mask_host[k] = (fin[k] && !conv[k]) ? 1 : 0;
+            b.caps_host[k] = (int32_t)std::min<int64_t>(
+                INT32_MAX / 2, longest[k] > 0 ? std::max<int64_t>(2 * longest[k], 64) : first_phase_cap(nd));
             any = any || b.mask_host[k];
         }
         return any;
@@ -1256,8 +1286,9 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
     auto restart_columns = [&]() -> int {
         FO_HIP(hipMemcpyAsync(b.mask, b.mask_host, S, hipMemcpyHostToDevice, s));
         by_s<RescaleL>(S, (const fo_ctx *)c, s);
+        FO_HIP(hipMemcpyAsync(b.caps, b.caps_host, S * sizeof(int32_t), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_batch_phase, dim3(S), dim3(256), 0, s, b.ctl, b.cols, b.rz_part, b.n_upd, S, b.s2,
-                           b.mask, phase_rtol);
+                           b.mask, b.caps, phase_rtol);
         by_s<DirectionL>(S, (const fo_ctx *)c, (const uint8_t *)b.mask, s);
         FO_HIP(hipGetLastError());
         return FO_OK;
@@ -1325,15 +1356,43 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
             // cannot improve in FP32 any more
             const bool stalled = restart[k] && r >= rn[k];
             restart[k] = b.cols_host[k].fresh;
+            if (!b.cols_host[k].capped && b.cols_host[k].status == 0)
+                longest[k] = std::max<int64_t>(longest[k], b.cols_host[k].it);
+            capped_run[k] = b.cols_host[k].capped ? capped_run[k] + 1 : 0;
             rn[k] = r;
             if (r <= o->rtol * bnorm[k]) {
                 conv[k] = 1;
+            } else if (capped_run[k] >= 2) {  // FP32 stagnates on this column: finish it in FP64
+                conv[k] = 1;
+                finish64[k] = 1;
             } else if (stalled || outer[k] >= max_outer) {
                 conv[k] = 1;
                 fail[k] = 1;
             }
         }
         if (select(fin)) FO_TRY(restart_columns());
+    }
+    // columns that FP32 cannot resolve: FP64 CG on their residual equation
+    int64_t extra = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!finish64[k]) continue;
+        launch_gather_col<double, double>(b.r64 + k, S, nd, c->t64, nullptr, s);
+        fo_solve_opts o2 = *o;
+        o2.rtol = o->rtol * bnorm[k] / rn[k];
+        fo_solve_stats s2st{};
+        const int rc = fp64_solve(c, c->t64, &o2, &s2st);
+        if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+        extra += s2st.iters_inner;
+        hipLaunchKernelGGL(k_batch_add_col, dim3(grid_of(nd)), dim3(256), 0, s, b.x64, c->x64, S, k, nd);
+        launch_gather_col<double, double>(b.x64 + k, S, nd, c->t64, nullptr, s);
+        FO_TRY(elas_apply64(c, c->t64, c->q64, s));
+        hipLaunchKernelGGL(k_batch_residual_col, dim3(grid_of(nd)), dim3(256), 0, s, b.b64, c->q64, c->fixed,
+                           b.r64, S, k, nd);
+        FO_TRY(residual_norms(c, S));
+        rn[k] = std::sqrt(b.s2_host[k]);
+        ++outer[k];
+        if (rc == FO_ERR_BREAKDOWN) status[k] = FO_ERR_BREAKDOWN;
+        else if (!(rn[k] <= o->rtol * bnorm[k])) fail[k] = 1;
     }
     hipLaunchKernelGGL(k_batch_unpack, dim3(grid_of(nd * n)), dim3(256), 0, s, b.x64, S, n, u, ld, nd);
     FO_HIP(hipStreamSynchronize(s));
@@ -1348,7 +1407,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         if (status[k] == FO_ERR_BREAKDOWN) result = FO_ERR_BREAKDOWN;
     if (st) {
         st->status = result;
-        st->iters_inner += it_total;
+        st->iters_inner += it_total + (int32_t)extra;
         st->iters_outer = std::max(st->iters_outer, max_outer_seen);
         st->rel_res = std::max(st->rel_res, worst);
     }

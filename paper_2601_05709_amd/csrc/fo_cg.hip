@@ -185,6 +185,14 @@ __global__ void k_ir_accumulate(double *__restrict__ x64, const float *__restric
         x64[i] += s * (double)x32[i];
 }
 
+// y += x (FP64).
+__global__ void k_add64(double *__restrict__ y, const double *__restrict__ x, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
+}
+
 // r64 = b - q64 and partial ||r64||^2
 __global__ __launch_bounds__(256) void k_residual64(const double *__restrict__ b,
                                                     const double *__restrict__ q,
@@ -454,6 +462,11 @@ template void launch_cg_direction<double>(SolveScalars *, int, double *, const d
                                           const double *, int64_t, const double *, hipStream_t);
 template void launch_cg_direction<float>(SolveScalars *, int, float *, const float *, const float *,
                                          int64_t, const double *, hipStream_t);
+
+void launch_add64(double *y, const double *x, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add64, dim3(red_blocks(n) * 4), dim3(kBlock), 0, s, y, x, n);
+}
 
 void launch_ir_accumulate(double *x64, const float *x32, const double *s2, int64_t n, hipStream_t s)
 {

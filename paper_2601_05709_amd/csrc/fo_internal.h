@@ -73,6 +73,8 @@ struct TileSet {
     int32_t *halo_node = nullptr;       // [n_shared_nodes] global node of each shared node
     int32_t *halo_ptr = nullptr;        // [n_shared_nodes+1] node-major halo slot ranges
     int32_t *node_hrange = nullptr;     // [N][2] halo range of a node, (-1,-1) if interior
+    float *tx32 = nullptr;              // [n_tiles][MN][dim] node coordinates minus the tile's
+                                        // first node, formed in FP64 (FP32 operator geometry)
 };
 
 // Per-column state of the batched (multi-load) CG, one entry per column of
@@ -84,11 +86,12 @@ struct BatchCol {
     double alpha, beta;
     double tol2;     // phase target for r . r (rescaled residual)
     double pq;       // p . A p
-    double pad;
-    int32_t done;    // converged in this phase, breakdown, or inactive
+    int32_t done;    // converged in this phase, breakdown, capped, or inactive
     int32_t status;  // 0 ok, FO_ERR_BREAKDOWN
     int32_t fresh;   // next phase restarts this column's direction
-    int32_t pad2;
+    int32_t it;      // iterations of the current phase
+    int32_t cap;     // iteration cap of the current phase
+    int32_t capped;  // the phase ended at its cap
 };
 
 // Iteration control of the batched CG (device; the host polls a copy).
@@ -124,6 +127,8 @@ struct BatchState {
     double *rz_part = nullptr;          // [2][n_upd][S]
     double *s2 = nullptr;               // [3][S]: scale^2 of the phase, new residual^2, b^2
     uint8_t *mask = nullptr;            // [S] columns selected for a residual replacement
+    int32_t *caps = nullptr;            // [S] phase iteration caps of the selected columns
+    int32_t *caps_host = nullptr;       // pinned [S]
     float *geo = nullptr;               // [n_tiles][MS][16] slot cofactors and weight (per level set)
     BatchCol *cols = nullptr;           // [S]
     BatchCtl *ctl = nullptr;
@@ -179,7 +184,7 @@ struct fo_ctx {
 
     // Krylov workspace (single RHS); FP64 and FP32 copies
     double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *b64 = nullptr,
-           *t64 = nullptr, *p64b = nullptr;
+           *t64 = nullptr, *p64b = nullptr, *x64b = nullptr;  // x64b: saved iterate (FP64 finish)
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *b32 = nullptr,
           *p32b = nullptr;  // p*b: second direction buffer of the fused CG
     double *halo = nullptr;            // [n_shared_slots * dim] halo partials

@@ -41,6 +41,7 @@ template <typename T>
 void launch_cg_direction(SolveScalars *sc, int P, T *p, const T *r, const T *dinv, int64_t n,
                          const double *rz_part, hipStream_t s);
 void launch_ir_accumulate(double *x64, const float *x32, const double *s2, int64_t n, hipStream_t s);
+void launch_add64(double *y, const double *x, int64_t n, hipStream_t s);
 void launch_residual64(const double *b, const double *q, double *r, int64_t n, double *part,
                        double *out2, hipStream_t s);
 // fused CG for the tiled elasticity operator
@@ -95,6 +96,9 @@ void launch_facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t
 int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
                 const std::function<int(hipStream_t)> &enqueue);
 int elas_apply64(fo_ctx *c, const double *x, double *y, hipStream_t s);
+// FP64 Jacobi-PCG of K(phi) x = b (contiguous b), solution left in c->x64.
+int fp64_solve(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats *st);
+int64_t first_phase_cap(int64_t n);
 
 // batched multi-load path (fo_batch.hip)
 int batch_setup(fo_ctx *c, int max_rhs);

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -147,6 +148,8 @@ void fo_pool::run(int s)
             res.B_tt = scal[2];
         }
     }
+    if (st < 0)
+        std::fprintf(stderr, "libfo pool: request in slot %d failed: %s (%d)\n", s, fo_status_string(st), st);
     res.status = st;
     res.t_end = now();
     {

@@ -22,6 +22,7 @@ struct TileArgs {
     const int32_t *nodes;           // [n_tiles][MN]
     const uint16_t *seg;            // [n_tiles][MN+1]
     const int32_t *hpos;            // [n_tiles][MN]
+    const float *tx32;              // [n_tiles][MN][D] node offsets from the tile's first node
     int ME, MN, n_tiles;
 };
 
@@ -29,7 +30,7 @@ static TileArgs tile_args(const fo_ctx *c)
 {
     const TileSet &t = c->tiles;
     return TileArgs{t.info, reinterpret_cast<const uint64_t *>(t.lconn),
-                    reinterpret_cast<const uint64_t *>(t.lslot), t.nodes, t.seg, t.hpos,
+                    reinterpret_cast<const uint64_t *>(t.lslot), t.nodes, t.seg, t.hpos, t.tx32,
                     t.max_elems, t.max_nodes, t.n_tiles};
 }
 
@@ -106,8 +107,12 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
         sa = ta.seg[(int64_t)t * (ta.MN + 1) + tid];
         sb = ta.seg[(int64_t)t * (ta.MN + 1) + tid + 1];
         T xv[D], uv[NX > 0 ? NX : 1];
+        // FP32 geometry from tile-local offsets (formed in FP64 on the host):
+        // edge vectors then keep FP32 accuracy relative to the element size
 #pragma unroll
-        for (int q = 0; q < D; ++q) xv[q] = coords[g * D + q];
+        for (int q = 0; q < D; ++q)
+            if constexpr (sizeof(T) == 4) xv[q] = ta.tx32[tn * D + q];
+            else xv[q] = coords[g * D + q];
 #pragma unroll
         for (int k = 0; k < NX; ++k) uv[k] = xin[g * NX + k];
 #pragma unroll
@@ -241,7 +246,8 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
         T xv[D], pv[D];
 #pragma unroll
         for (int v = 0; v < D; ++v) {
-            xv[v] = coords[g * D + v];
+            if constexpr (sizeof(T) == 4) xv[v] = ta.tx32[((int64_t)t * ta.MN + tid) * D + v];
+            else xv[v] = coords[g * D + v];
             T z = dinv[g * D + v] * r[g * D + v];
             pv[v] = fresh ? z : z + beta * pin[g * D + v];
         }

@@ -268,3 +268,23 @@ def test_cantilever_96x48x48_residual_checked_by_oracle(precision):
     rhs = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
     ctx.shape_derivative(u, rhs, J, vol)
     assert J.item() == pytest.approx(float(w.b @ uh), rel=1e-6)
+
+
+def test_ir_finishes_in_fp64_when_fp32_stagnates():
+    """2D 256x128 with random holes: Jacobi-PCG needs ~3800 FP64 iterations
+    (kappa * eps_32 near 1), so the FP32 phases stagnate; the solve must still
+    reach the FP64 residual target (through its FP64 finish) and match the
+    oracle."""
+    w = fi.serving_request(0)
+    assert w.mesh.dim == 2 and w.mesh.cells == (256, 128)
+    print("case serving req0 2d 256x128", flush=True)
+    m = w.mesh
+    ctx = fo.Context.from_workload(w)
+    ctx.set_levelset(dev(w.phi))
+    u = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    st = ctx.state_solve(dev(w.b), u, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-10))
+    assert st.status == 0 and st.rel_res <= 1e-10
+    assert st.iters_inner < 40000
+    K, *_ = oracle_K(w)
+    u_ref, _ = K.solve(w.b, w.fixed, rtol=1e-12)
+    assert rel(u.cpu().numpy(), u_ref) < 1e-8
