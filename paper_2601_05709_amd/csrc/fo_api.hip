@@ -223,11 +223,9 @@ struct FusedVecs {
 template <typename T>
 int fused_chunk(fo_ctx *c, FusedVecs<T> v, int chunk, hipStream_t s)
 {
-    const int nb = node_blocks(c->N);
     for (int j = 0; j < chunk; ++j) {
         const int A = j & 1;
-        FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[A], v.p[A ^ 1], v.q, c->scal, A, c->rz_part,
-                                 nb, c->pq_part, s));
+        FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[A], v.p[A ^ 1], v.q, c->scal, A, s));
         launch_cgn_update<T>(c, A ^ 1, v.x, v.r, v.p[A ^ 1], v.q, v.dinv, s);
     }
     return FO_OK;
@@ -549,8 +547,7 @@ int time_cg_op(fo_ctx *c, FusedVecs<T> v, int reps, double *avg_us)
     launch_fill<double>(c->rz_part, 2 * kRedBlocks, 0.0, s);
     launch_fill<T>(v.r, n, T(1), s);
     launch_fill<T>(v.p[0], n, T(1), s);
-    FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, c->rz_part,
-                             kRedBlocks, c->pq_part, s));  // warm-up
+    FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s));  // warm-up
     hipEvent_t e0, e1;
     FO_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -560,8 +557,7 @@ int time_cg_op(fo_ctx *c, FusedVecs<T> v, int reps, double *avg_us)
     int rc = FO_OK;
     (void)hipEventRecord(e0, s);
     for (int k = 0; k < reps && rc == FO_OK; ++k)
-        rc = launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, c->rz_part,
-                               kRedBlocks, c->pq_part, s);
+        rc = launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s);
     (void)hipEventRecord(e1, s);
     float ms = 0.0f;
     if (rc == FO_OK && (hipEventSynchronize(e1) != hipSuccess ||

@@ -214,8 +214,14 @@ __global__ __launch_bounds__(256) void k_residual64(const double *__restrict__ b
 // ---------------------------------------------------------------------------
 // Fused CG for the tiled elasticity operator (see k_tile_cg): one iteration =
 // k_tile_cg (beta, direction, operator, p.q partials) + k_cgn_update.  The
-// r.z / r.r partials are written by node-parallel kernels on node_blocks(N)
+// r.z / r.r partials are written by node-parallel kernels on upd_blocks(N)
 // blocks, the layout k_tile_cg reduces.
+
+int upd_blocks(int64_t N)
+{
+    int64_t b = (N + kUpdBlock - 1) / kUpdBlock;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), kRedBlocks);
+}
 
 int node_blocks(int64_t N)
 {
@@ -284,20 +290,44 @@ __global__ __launch_bounds__(256) void k_cgn_start_finish(SolveScalars *sc,
     }
 }
 
-// x += alpha p; r -= alpha q, alpha = rho / sum(pq_part); q at shared nodes is
-// the fixed-order sum of the node's halo slots; clamped unknowns (dinv = 0)
-// get q = 0.  Partials r.z, r.r.  Reads slot B.
+// x += alpha p; r -= alpha q, alpha = rho / sum(pq_part) (summed by every
+// block in the same fixed order, after the node loads are issued);
+// q at shared nodes is the fixed-order sum of the node's halo slots; clamped
+// unknowns (dinv = 0) get q = 0.  Partials r.z, r.r per block.  Reads slot B.
+// Blocks of kUpdBlock threads, one node per thread (grid-stride beyond).
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cgn_update(
+__global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
     SolveScalars *sc, int B, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
     const T *__restrict__ q, const T *__restrict__ dinv, int64_t N,
     const double *__restrict__ pq_part, int n_pq, double *__restrict__ rz_part,
     const int2 *__restrict__ hrange, const T *__restrict__ halo)
 {
-    __shared__ double lds[4];
+    __shared__ double lds[16];
     __shared__ double s_alpha;
     if (sc[B].done) return;
-    double pq = block_sum_partials(pq_part, n_pq, lds);
+    // first node of this thread: load everything but alpha's inputs first
+    int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    T di[D], qi[D], xi[D], ri[D], pi[D];
+    auto load = [&](int64_t nd) {
+        const int2 hr = hrange[nd];
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            const int64_t i = nd * D + v;
+            di[v] = dinv[i];
+            xi[v] = x[i];
+            ri[v] = r[i];
+            pi[v] = p[i];
+            if (hr.x < 0) {
+                qi[v] = q[i];
+            } else {
+                T a = T(0);
+                for (int j = hr.x; j < hr.y; ++j) a += halo[(int64_t)j * D + v];
+                qi[v] = a;
+            }
+        }
+    };
+    if (node < N) load(node);
+    const double pq = block_sum_partials_any(pq_part, n_pq, lds);
     if (threadIdx.x == 0) {
         const bool ok = pq > 0.0 && finite(pq);
         s_alpha = ok ? sc[B].rho / pq : 0.0;
@@ -313,30 +343,21 @@ __global__ __launch_bounds__(256) void k_cgn_update(
     __syncthreads();
     const T alpha = (T)s_alpha;
     double rz = 0.0, rr = 0.0;
-    for (int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; node < N;
-         node += (int64_t)gridDim.x * blockDim.x) {
-        const int2 hr = hrange[node];
-        const int j0 = hr.x, j1 = hr.y;
+    while (node < N) {
 #pragma unroll
         for (int v = 0; v < D; ++v) {
             const int64_t i = node * D + v;
-            const T di = dinv[i];
-            T qi;
-            if (j0 < 0) {
-                qi = q[i];
-            } else {
-                qi = T(0);
-                for (int j = j0; j < j1; ++j) qi += halo[(int64_t)j * D + v];
-            }
-            if (di == T(0)) qi = T(0);
-            x[i] += alpha * p[i];
-            const T ri = r[i] - alpha * qi;
-            r[i] = ri;
-            rz += (double)ri * (double)(di * ri);
-            rr += (double)ri * (double)ri;
+            const T qv = di[v] == T(0) ? T(0) : qi[v];
+            x[i] = xi[v] + alpha * pi[v];
+            const T rv = ri[v] - alpha * qv;
+            r[i] = rv;
+            rz += (double)rv * (double)(di[v] * rv);
+            rr += (double)rv * (double)rv;
         }
+        node += (int64_t)gridDim.x * blockDim.x;
+        if (node < N) load(node);
     }
-    double s0 = block_sum(rz, lds), s1 = block_sum(rr, lds);
+    double s0 = block_sum_any(rz, lds), s1 = block_sum_any(rr, lds);
     if (threadIdx.x == 0) {
         rz_part[blockIdx.x] = s0;
         rz_part[gridDim.x + blockIdx.x] = s1;
@@ -485,7 +506,7 @@ template <typename T>
 void launch_cgn_start(const fo_ctx *c, const T *b, const T *q, T *r, const T *dinv, double rtol,
                       int max_it, hipStream_t s)
 {
-    const int nb = node_blocks(c->N);
+    const int nb = upd_blocks(c->N);  // the partial layout k_tile_cg reads
     if (c->dim == 2)
         hipLaunchKernelGGL((k_cgn_residual<T, 2>), dim3(nb), dim3(kBlock), 0, s, b, q, r, dinv, c->N,
                            c->rz_part, c->bb_part);
@@ -504,14 +525,14 @@ template <typename T>
 void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *q, const T *dinv,
                        hipStream_t s)
 {
-    const int nb = node_blocks(c->N);
+    const int nb = upd_blocks(c->N);
     const T *halo = reinterpret_cast<const T *>(c->halo);
     if (c->dim == 2)
-        hipLaunchKernelGGL((k_cgn_update<T, 2>), dim3(nb), dim3(kBlock), 0, s, c->scal, B, x, r, p, q,
+        hipLaunchKernelGGL((k_cgn_update<T, 2>), dim3(nb), dim3(kUpdBlock), 0, s, c->scal, B, x, r, p, q,
                            dinv, c->N, c->pq_part, c->tiles.n_tiles, c->rz_part,
                            reinterpret_cast<const int2 *>(c->tiles.node_hrange), halo);
     else
-        hipLaunchKernelGGL((k_cgn_update<T, 3>), dim3(nb), dim3(kBlock), 0, s, c->scal, B, x, r, p, q,
+        hipLaunchKernelGGL((k_cgn_update<T, 3>), dim3(nb), dim3(kUpdBlock), 0, s, c->scal, B, x, r, p, q,
                            dinv, c->N, c->pq_part, c->tiles.n_tiles, c->rz_part,
                            reinterpret_cast<const int2 *>(c->tiles.node_hrange), halo);
 }
@@ -523,7 +544,7 @@ template void launch_cgn_update<float>(const fo_ctx *, int, float *, float *, co
 void launch_ir_phase(const fo_ctx *c, const double *r64, double *s2, float *r32, float *x32,
                      const float *dinv, double phase_rtol, int max_it, int fresh, hipStream_t s)
 {
-    const int nb = node_blocks(c->N);
+    const int nb = upd_blocks(c->N);  // the partial layout k_tile_cg reads
     if (c->dim == 2)
         hipLaunchKernelGGL(k_ir_rescale<2>, dim3(nb), dim3(kBlock), 0, s, r64, s2, r32, x32, dinv,
                            c->N, c->rz_part);

@@ -35,6 +35,7 @@ namespace fo {
 
 constexpr int kBlock = 256;        // threads per block of the vector kernels
 constexpr int kRedBlocks = 1024;   // partial sums per reduction (fixed: deterministic)
+constexpr int kUpdBlock = 1024;    // threads per block of the fused CG update (one node each)
 
 // Device-resident scalars of one Krylov solve.  The host polls a copy of
 // `done`/`status`/`it` every few iterations; everything else stays on the GPU.

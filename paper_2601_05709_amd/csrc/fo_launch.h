@@ -46,6 +46,7 @@ void launch_residual64(const double *b, const double *q, double *r, int64_t n, d
                        double *out2, hipStream_t s);
 // fused CG for the tiled elasticity operator
 int node_blocks(int64_t N);
+int upd_blocks(int64_t N);  // blocks of the fused update = r.z/r.r partials per sum
 template <typename T>
 void launch_cgn_start(const fo_ctx *c, const T *b, const T *q, T *r, const T *dinv, double rtol,
                       int max_it, hipStream_t s);
@@ -54,8 +55,7 @@ void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *
                        hipStream_t s);
 template <typename T>
 int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *pout, T *q,
-                   SolveScalars *sc, int A, const double *rz_part, int rz_nb, double *pq_part,
-                   hipStream_t s);
+                   SolveScalars *sc, int A, hipStream_t s);
 void launch_ir_phase(const fo_ctx *c, const double *r64, double *s2, float *r32, float *x32,
                      const float *dinv, double phase_rtol, int max_it, int fresh, hipStream_t s);
 void launch_to_float(const double *a, float *b, int64_t n, hipStream_t s);

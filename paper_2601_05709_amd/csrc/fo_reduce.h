@@ -64,4 +64,14 @@ __device__ __forceinline__ double block_sum_partials_any(const double *part, int
     return s;
 }
 
+// Sum of n partials by the first wave of a block, in a fixed order (lane
+// strided sums, then a butterfly): every block that calls it gets the same
+// value.  Valid in all lanes of wave 0.
+__device__ __forceinline__ double wave0_sum_partials(const double *part, int n)
+{
+    double s = 0.0;
+    for (int i = (int)(threadIdx.x & 63); i < n; i += 64) s += part[i];
+    return wave_sum(s);
+}
+
 }  // namespace fo

@@ -158,8 +158,9 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
 }
 
 // Operator kernel of one fused CG iteration (elasticity, tiled):
-//   rho_k = r.D^-1 r, rr_k = r.r from the partials of the previous update;
-//   convergence test; beta = rho_k / rho_{k-1} (or the slot's first-iteration
+//   rho_k = r.D^-1 r and rr_k = r.r from the partials of the previous update
+//   (summed by wave 0 while the other waves load their nodes); convergence
+//   test; beta = rho_k / rho_{k-1} (or the slot's first-iteration
 //   coefficient); p_k = D^-1 r + beta p_{k-1} at node staging (the owner tile
 //   writes p_k); q = K p_k with interior nodes in q and shared nodes in the
 //   halo; pq_part[tile] = p_k . (the tile's share of q).
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
         if (t == 0 && tid == 0) sc[A ^ 1] = sc[A];
         return;
     }
-    // issue the element and node index loads before the reductions
+    // issue the index and node loads before the scalar decision
     const int32_t *inf = ta.info + (int64_t)t * kTileInfo;
     const int e0 = inf[kTileE0], ne = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt],
               nown = inf[kTileNOwn];
@@ -202,36 +203,47 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
     }
     int64_t g = 0;
     int sa = 0, sb = 0, hp = -1;
+    T xv[D], zv[D], po[D];
     if (tid < nn) {
         const int64_t tn = (int64_t)t * ta.MN + tid;
         g = ta.nodes[tn];
         hp = ta.hpos[tn];
         sa = ta.seg[(int64_t)t * (ta.MN + 1) + tid];
         sb = ta.seg[(int64_t)t * (ta.MN + 1) + tid + 1];
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            // FP32 geometry from tile-local offsets (formed in FP64 on the host)
+            if constexpr (sizeof(T) == 4) xv[v] = ta.tx32[tn * D + v];
+            else xv[v] = coords[g * D + v];
+            zv[v] = dinv[g * D + v] * r[g * D + v];
+            po[v] = pin[g * D + v];
+        }
     }
-    const double rho_k = block_sum_partials_any(rz_part, rz_nb, lds);
-    const double rr_k = block_sum_partials_any(rz_part + rz_nb, rz_nb, lds);
-    if (tid == 0) {
-        const SolveScalars cur = sc[A];
-        const bool bad = !(rho_k >= 0.0) || rho_k != rho_k || rr_k != rr_k ||
-                         rho_k == INFINITY || rr_k == INFINITY;
-        const bool stop = bad || rr_k <= cur.tol2 || cur.it >= cur.max_it;
-        s_go = !stop;
-        s_beta = cur.first ? cur.beta : (cur.rho > 0.0 ? rho_k / cur.rho : 0.0);
-        if (t == 0) {
-            SolveScalars nx = cur;
-            nx.rr = rr_k;
-            nx.rho_new = rho_k;
-            if (stop) {
-                nx.done = 1;
-                nx.status = bad ? FO_ERR_BREAKDOWN : 0;
-            } else {
-                nx.rho = rho_k;
-                nx.beta = s_beta;
-                nx.first = 0;
-                nx.it = cur.it + 1;
+    if (tid < 64) {
+        const double rho_k = wave0_sum_partials(rz_part, rz_nb);
+        const double rr_k = wave0_sum_partials(rz_part + rz_nb, rz_nb);
+        if (tid == 0) {
+            const SolveScalars cur = sc[A];
+            const bool bad = !(rho_k >= 0.0) || rho_k != rho_k || rr_k != rr_k ||
+                             rho_k == INFINITY || rr_k == INFINITY;
+            const bool stop = bad || rr_k <= cur.tol2 || cur.it >= cur.max_it;
+            s_go = !stop;
+            s_beta = cur.first ? cur.beta : (cur.rho > 0.0 ? rho_k / cur.rho : 0.0);
+            if (t == 0) {
+                SolveScalars nx = cur;
+                nx.rr = rr_k;
+                nx.rho_new = rho_k;
+                if (stop) {
+                    nx.done = 1;
+                    nx.status = bad ? FO_ERR_BREAKDOWN : 0;
+                } else {
+                    nx.rho = rho_k;
+                    nx.beta = s_beta;
+                    nx.first = 0;
+                    nx.it = cur.it + 1;
+                }
+                sc[A ^ 1] = nx;
             }
-            sc[A ^ 1] = nx;
         }
     }
     __syncthreads();
@@ -243,14 +255,9 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
     T *sU = sX + nn * D;
     T *sS = sU + nn * D;
     if (tid < nn) {
-        T xv[D], pv[D];
+        T pv[D];
 #pragma unroll
-        for (int v = 0; v < D; ++v) {
-            if constexpr (sizeof(T) == 4) xv[v] = ta.tx32[((int64_t)t * ta.MN + tid) * D + v];
-            else xv[v] = coords[g * D + v];
-            T z = dinv[g * D + v] * r[g * D + v];
-            pv[v] = fresh ? z : z + beta * pin[g * D + v];
-        }
+        for (int v = 0; v < D; ++v) pv[v] = fresh ? zv[v] : zv[v] + beta * po[v];
 #pragma unroll
         for (int v = 0; v < D; ++v) {
             sX[tid * D + v] = xv[v];
@@ -422,8 +429,7 @@ static int run_tiled(const fo_ctx *c, const Op &op, const T *coords, const T *xi
 
 template <typename T>
 int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *pout, T *q,
-                   SolveScalars *sc, int A, const double *rz_part, int rz_nb, double *pq_part,
-                   hipStream_t s)
+                   SolveScalars *sc, int A, hipStream_t s)
 {
     const int D = c->dim;
     const int which = sizeof(T) == 8 ? FO_PROF_ELAS_TILE_FP64 : FO_PROF_ELAS_TILE_FP32;
@@ -438,25 +444,23 @@ int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *
         size_t lds = tile_lds_bytes<2, T, 2, 2>(c->tiles.max_nodes, c->tiles.max_elems);
         hipLaunchKernelGGL((k_tile_cg<2, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
                            ElasOp<2, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
-                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, rz_part, rz_nb,
-                           pq_part);
+                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, c->rz_part, upd_blocks(c->N),
+                           c->pq_part);
     } else {
         if (ensure_lds_attr_cg<3, T>()) return FO_ERR_HIP;
         size_t lds = tile_lds_bytes<3, T, 3, 3>(c->tiles.max_nodes, c->tiles.max_elems);
         hipLaunchKernelGGL((k_tile_cg<3, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
                            ElasOp<3, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
-                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, rz_part, rz_nb,
-                           pq_part);
+                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, c->rz_part, upd_blocks(c->N),
+                           c->pq_part);
     }
     if (pt) (void)hipEventRecord(pt->second, s);
     return FO_OK;
 }
 template int launch_tile_cg<double>(const fo_ctx *, const double *, const double *, const double *,
-                                    double *, double *, SolveScalars *, int, const double *, int,
-                                    double *, hipStream_t);
+                                    double *, double *, SolveScalars *, int, hipStream_t);
 template int launch_tile_cg<float>(const fo_ctx *, const float *, const float *, const float *,
-                                   float *, float *, SolveScalars *, int, const double *, int,
-                                   double *, hipStream_t);
+                                   float *, float *, SolveScalars *, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // boundary facets of the descent operator, node-parallel (deterministic)
