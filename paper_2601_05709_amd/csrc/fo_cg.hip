@@ -304,8 +304,10 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
 {
     __shared__ double lds[16];
     __shared__ double s_alpha;
+    // the p.q partials first (they depend on nothing), then the node data
+    PartLoad<4> ppq;
+    part_issue(ppq, pq_part, n_pq, threadIdx.x, blockDim.x);
     if (sc[B].done) return;
-    // first node of this thread: load everything but alpha's inputs first
     int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     T di[D], qi[D], xi[D], ri[D], pi[D];
     auto load = [&](int64_t nd) {
@@ -327,7 +329,10 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
         }
     };
     if (node < N) load(node);
-    const double pq = block_sum_partials_any(pq_part, n_pq, lds);
+    double pq = block_sum_any(part_finish(ppq, pq_part, n_pq, threadIdx.x, blockDim.x), lds);
+    if (threadIdx.x == 0) lds[0] = pq;
+    __syncthreads();
+    pq = lds[0];
     if (threadIdx.x == 0) {
         const bool ok = pq > 0.0 && finite(pq);
         s_alpha = ok ? sc[B].rho / pq : 0.0;

@@ -74,4 +74,36 @@ __device__ __forceinline__ double wave0_sum_partials(const double *part, int n)
     return wave_sum(s);
 }
 
+// Partial sums read in two steps, so that the loads overlap other work:
+// part_issue() loads the first KP strides of partials into registers
+// (indices clamped to n - 1: no branch, every load in bounds, n >= 1) and
+// part_finish() drops the clamped copies, adds the partials beyond KP
+// strides and returns the thread's strided sum.  The order of the additions
+// is that of the plain strided loop (s = 0; s += part[i], i = lane, lane +
+// width, ...), so the reductions built on it keep their results bit for bit.
+template <int KP>
+struct PartLoad {
+    double v[KP];
+};
+
+template <int KP>
+__device__ __forceinline__ void part_issue(PartLoad<KP> &pl, const double *__restrict__ part, int n,
+                                           int lane, int width)
+{
+#pragma unroll
+    for (int k = 0; k < KP; ++k) pl.v[k] = part[min(lane + k * width, n - 1)];
+}
+
+template <int KP>
+__device__ __forceinline__ double part_finish(const PartLoad<KP> &pl, const double *__restrict__ part,
+                                              int n, int lane, int width)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+        if (lane + k * width < n) s += pl.v[k];
+    for (int i = lane + KP * width; i < n; i += width) s += part[i];
+    return s;
+}
+
 }  // namespace fo

@@ -162,8 +162,10 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
 //   (summed by wave 0 while the other waves load their nodes); convergence
 //   test; beta = rho_k / rho_{k-1} (or the slot's first-iteration
 //   coefficient); p_k = D^-1 r + beta p_{k-1} at node staging (the owner tile
-//   writes p_k); q = K p_k with interior nodes in q and shared nodes in the
-//   halo; pq_part[tile] = p_k . (the tile's share of q).
+//   writes p_k); q = K p_k with interior nodes in q (zero on unknowns with
+//   dinv = 0: clamped, or in no element) and shared nodes in the halo;
+//   pq_part[tile] = p_k . (the tile's share of q) over the unknowns with
+//   dinv != 0.
 // Reads scalar slot A, writes slot A ^ 1 (block 0).
 template <int D, typename T>
 __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
@@ -172,7 +174,6 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
                                                   const T *__restrict__ dinv,
                                                   const T *__restrict__ pin, T *__restrict__ pout,
                                                   T *__restrict__ q, T *__restrict__ halo,
-                                                  const uint8_t *__restrict__ fixed,
                                                   SolveScalars *sc, int A,
                                                   const double *__restrict__ rz_part, int rz_nb,
                                                   double *__restrict__ pq_part)
@@ -186,6 +187,13 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
     const int t = xcd_tile(blockIdx.x, ta.n_tiles);
     const int tid = threadIdx.x;
     if (t < 0) return;
+    // wave 0 issues the loads of the r.z / r.r partials first: they depend on
+    // nothing, and their latency then overlaps the index and node loads
+    PartLoad<4> prz, prr;
+    if (tid < 64) {
+        part_issue(prz, rz_part, rz_nb, tid, 64);
+        part_issue(prr, rz_part + rz_nb, rz_nb, tid, 64);
+    }
     if (sc[A].done) {
         if (t == 0 && tid == 0) sc[A ^ 1] = sc[A];
         return;
@@ -203,6 +211,7 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
     }
     int64_t g = 0;
     int sa = 0, sb = 0, hp = -1;
+    unsigned clamp = 0;  // bit v: dinv = 0 (clamped unknown, or no element): q = 0 there
     T xv[D], zv[D], po[D];
     if (tid < nn) {
         const int64_t tn = (int64_t)t * ta.MN + tid;
@@ -215,13 +224,15 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
             // FP32 geometry from tile-local offsets (formed in FP64 on the host)
             if constexpr (sizeof(T) == 4) xv[v] = ta.tx32[tn * D + v];
             else xv[v] = coords[g * D + v];
-            zv[v] = dinv[g * D + v] * r[g * D + v];
+            const T di = dinv[g * D + v];
+            zv[v] = di * r[g * D + v];
             po[v] = pin[g * D + v];
+            clamp |= (di == T(0) ? 1u : 0u) << v;
         }
     }
     if (tid < 64) {
-        const double rho_k = wave0_sum_partials(rz_part, rz_nb);
-        const double rr_k = wave0_sum_partials(rz_part + rz_nb, rz_nb);
+        const double rho_k = wave_sum(part_finish(prz, rz_part, rz_nb, tid, 64));
+        const double rr_k = wave_sum(part_finish(prr, rz_part + rz_nb, rz_nb, tid, 64));
         if (tid == 0) {
             const SolveScalars cur = sc[A];
             const bool bad = !(rho_k >= 0.0) || rho_k != rho_k || rr_k != rr_k ||
@@ -281,7 +292,7 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
         if (tid < nint) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                T val = fixed[g * NV + v] ? T(0) : acc[v];
+                T val = (clamp >> v) & 1u ? T(0) : acc[v];
                 q[g * NV + v] = val;
                 dsum += (double)sU[tid * D + v] * (double)val;
             }
@@ -289,7 +300,7 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 halo[(int64_t)hp * NV + v] = acc[v];
-                dsum += fixed[g * NV + v] ? 0.0 : (double)sU[tid * D + v] * (double)acc[v];
+                dsum += (clamp >> v) & 1u ? 0.0 : (double)sU[tid * D + v] * (double)acc[v];
             }
         }
     }
@@ -444,14 +455,14 @@ int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *
         size_t lds = tile_lds_bytes<2, T, 2, 2>(c->tiles.max_nodes, c->tiles.max_elems);
         hipLaunchKernelGGL((k_tile_cg<2, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
                            ElasOp<2, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
-                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, c->rz_part, upd_blocks(c->N),
+                           coords, r, dinv, pin, pout, q, halo, sc, A, c->rz_part, upd_blocks(c->N),
                            c->pq_part);
     } else {
         if (ensure_lds_attr_cg<3, T>()) return FO_ERR_HIP;
         size_t lds = tile_lds_bytes<3, T, 3, 3>(c->tiles.max_nodes, c->tiles.max_elems);
         hipLaunchKernelGGL((k_tile_cg<3, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
                            ElasOp<3, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
-                           coords, r, dinv, pin, pout, q, halo, c->fixed, sc, A, c->rz_part, upd_blocks(c->N),
+                           coords, r, dinv, pin, pout, q, halo, sc, A, c->rz_part, upd_blocks(c->N),
                            c->pq_part);
     }
     if (pt) (void)hipEventRecord(pt->second, s);
