@@ -669,6 +669,8 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         if (v > 0) tile_elems = std::min(v, tile_max_elems(D));
     }
     build_tiles(D, N, E, m->coords, m->conn, tile_elems, &ht);
+    // the fused CG kernel packs (halo slot + 1) << 3 into 32 bits
+    if (!ht.halo_ptr.empty() && ht.halo_ptr.back() >= (1 << 28)) return fail(FO_ERR_MESH);
     std::vector<int32_t> conn_t((size_t)(D + 1) * E);
     for (int a = 0; a <= D; ++a)
         for (int64_t e = 0; e < E; ++e)

@@ -157,6 +157,78 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
     }
 }
 
+// LDS layout of the fused CG operator kernel (k_tile_cg):
+//   node records [nn][8]: position (D values) in the first 16-byte half,
+//     the direction p in the second; the global node id and the packed
+//     halo slot / clamp bits sit in the two halves' last entries;
+//   element-vertex slots [ne * (D+1)][SS]: one padded D-vector each.
+// Whole-record vector reads and writes replace one LDS access per value.
+template <int D, typename T>
+struct CgLds {
+    static constexpr int RS = 8;             // T per node record
+    static constexpr int PO = 4;             // offset of p in the record
+    static constexpr int SS = D == 3 ? 4 : 2;  // T per slot
+    static size_t bytes(int nn, int ne) { return ((size_t)nn * RS + (size_t)ne * (D + 1) * SS) * sizeof(T); }
+};
+
+template <typename T>
+__device__ __forceinline__ T int_bits(int32_t v)
+{
+    if constexpr (sizeof(T) == 4) return __int_as_float(v);
+    else return __longlong_as_double((long long)v);
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t bits_int(T v)
+{
+    if constexpr (sizeof(T) == 4) return __float_as_int(v);
+    else return (int32_t)__double_as_longlong(v);
+}
+
+// N contiguous values of T at a 16-byte (N * sizeof(T) >= 16) or 8-byte
+// aligned LDS address, moved as 16- or 8-byte vectors.
+template <typename T, int N>
+__device__ __forceinline__ void lds_get(const T *p, T (&out)[N])
+{
+    constexpr int B = N * (int)sizeof(T);
+    static_assert(B % 8 == 0, "vector size");
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int i = 0; i < B / 16; ++i) {
+            const float4 v = reinterpret_cast<const float4 *>(p)[i];
+            __builtin_memcpy(reinterpret_cast<char *>(out) + 16 * i, &v, 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < B / 8; ++i) {
+            const float2 v = reinterpret_cast<const float2 *>(p)[i];
+            __builtin_memcpy(reinterpret_cast<char *>(out) + 8 * i, &v, 8);
+        }
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void lds_put(T *p, const T (&in)[N])
+{
+    constexpr int B = N * (int)sizeof(T);
+    static_assert(B % 8 == 0, "vector size");
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int i = 0; i < B / 16; ++i) {
+            float4 v;
+            __builtin_memcpy(&v, reinterpret_cast<const char *>(in) + 16 * i, 16);
+            reinterpret_cast<float4 *>(p)[i] = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < B / 8; ++i) {
+            float2 v;
+            __builtin_memcpy(&v, reinterpret_cast<const char *>(in) + 8 * i, 8);
+            reinterpret_cast<float2 *>(p)[i] = v;
+        }
+    }
+}
+
 // Operator kernel of one fused CG iteration (elasticity, tiled):
 //   rho_k = r.D^-1 r and rr_k = r.r from the partials of the previous update
 //   (summed by wave 0 while the other waves load their nodes); convergence
@@ -166,6 +238,9 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
 //   dinv = 0: clamped, or in no element) and shared nodes in the halo;
 //   pq_part[tile] = p_k . (the tile's share of q) over the unknowns with
 //   dinv != 0.
+// Node phase: L = 4, 2 or 1 lanes per node (as many as the block holds)
+// each add every L-th slot of the node's segment, then the L partial sums
+// are combined by a butterfly (every lane of the group gets the same value).
 // Reads scalar slot A, writes slot A ^ 1 (block 0).
 template <int D, typename T>
 __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
@@ -178,8 +253,8 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
                                                   const double *__restrict__ rz_part, int rz_nb,
                                                   double *__restrict__ pq_part)
 {
-    using Op = ElasOp<D, T>;
-    constexpr int NV = D;
+    using L_ = CgLds<D, T>;
+    constexpr int RS = L_::RS, PO = L_::PO, SS = L_::SS;
     __shared__ double lds[16];
     __shared__ double s_beta;
     __shared__ int s_go;
@@ -202,6 +277,9 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
     const int32_t *inf = ta.info + (int64_t)t * kTileInfo;
     const int e0 = inf[kTileE0], ne = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt],
               nown = inf[kTileNOwn];
+    const int nt = blockDim.x;
+    const int lg = nn * 4 <= nt ? 2 : (nn * 2 <= nt ? 1 : 0);  // log2 of lanes per node
+    const int m = tid >> lg, sub = tid & ((1 << lg) - 1);
     uint64_t lc = 0, ls = 0;
     uint8_t ed = 0;
     if (tid < ne) {
@@ -209,24 +287,26 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
         ls = ta.lslot[(int64_t)t * ta.ME + tid];
         ed = op.load(e0 + tid);
     }
-    int64_t g = 0;
-    int sa = 0, sb = 0, hp = -1;
+    int sa = 0, sb = 0;
+    if (m < nn) {
+        sa = ta.seg[(int64_t)t * (ta.MN + 1) + m];
+        sb = ta.seg[(int64_t)t * (ta.MN + 1) + m + 1];
+    }
+    int32_t g = 0, hp = -1;
     unsigned clamp = 0;  // bit v: dinv = 0 (clamped unknown, or no element): q = 0 there
     T xv[D], zv[D], po[D];
     if (tid < nn) {
         const int64_t tn = (int64_t)t * ta.MN + tid;
         g = ta.nodes[tn];
         hp = ta.hpos[tn];
-        sa = ta.seg[(int64_t)t * (ta.MN + 1) + tid];
-        sb = ta.seg[(int64_t)t * (ta.MN + 1) + tid + 1];
 #pragma unroll
         for (int v = 0; v < D; ++v) {
             // FP32 geometry from tile-local offsets (formed in FP64 on the host)
             if constexpr (sizeof(T) == 4) xv[v] = ta.tx32[tn * D + v];
-            else xv[v] = coords[g * D + v];
-            const T di = dinv[g * D + v];
-            zv[v] = di * r[g * D + v];
-            po[v] = pin[g * D + v];
+            else xv[v] = coords[(int64_t)g * D + v];
+            const T di = dinv[(int64_t)g * D + v];
+            zv[v] = di * r[(int64_t)g * D + v];
+            po[v] = pin[(int64_t)g * D + v];
             clamp |= (di == T(0) ? 1u : 0u) << v;
         }
     }
@@ -261,46 +341,86 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
     if (!s_go) return;
     const T beta = (T)s_beta;
     const bool fresh = beta == T(0);
-    T *smem = reinterpret_cast<T *>(smem_raw);
-    T *sX = smem;
-    T *sU = sX + nn * D;
-    T *sS = sU + nn * D;
+    T *sN = reinterpret_cast<T *>(smem_raw);
+    T *sS = sN + (size_t)nn * RS;
     if (tid < nn) {
-        T pv[D];
+        T rec[RS];
 #pragma unroll
-        for (int v = 0; v < D; ++v) pv[v] = fresh ? zv[v] : zv[v] + beta * po[v];
+        for (int k = 0; k < RS; ++k) rec[k] = T(0);
 #pragma unroll
         for (int v = 0; v < D; ++v) {
-            sX[tid * D + v] = xv[v];
-            sU[tid * D + v] = pv[v];
+            rec[v] = xv[v];
+            rec[PO + v] = fresh ? zv[v] : zv[v] + beta * po[v];
         }
+        rec[PO - 1] = int_bits<T>(g);
+        rec[RS - 1] = int_bits<T>((int32_t)(((uint32_t)(hp + 1) << 3) | clamp));
+        lds_put(sN + (size_t)tid * RS, rec);
         if (tid < nown)
 #pragma unroll
-            for (int v = 0; v < D; ++v) pout[g * D + v] = pv[v];
+            for (int v = 0; v < D; ++v) pout[(int64_t)g * D + v] = rec[PO + v];
     }
     __syncthreads();
-    if (tid < ne) tile_elements<D, T, Op>(op, ed, lc, ls, sX, sU, sS);
+    if (tid < ne) {
+        T X[D + 1][PO], U[D + 1][PO];
+        const T *Xp[D + 1];
+        const T *Up[D + 1];
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            const int l = (int)((lc >> (16 * a)) & 0xFFFF);
+            T rec[RS];
+            lds_get(sN + (size_t)l * RS, rec);
+#pragma unroll
+            for (int k = 0; k < PO; ++k) {
+                X[a][k] = rec[k];
+                U[a][k] = rec[PO + k];
+            }
+            Xp[a] = X[a];
+            Up[a] = U[a];
+        }
+        T res[D + 1][D];
+        op(ed, Xp, Up, res);
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            const int sl = (int)((ls >> (16 * a)) & 0xFFFF);
+            T o[SS];
+#pragma unroll
+            for (int k = 0; k < SS; ++k) o[k] = k < D ? res[a][k] : T(0);
+            lds_put(sS + (size_t)sl * SS, o);
+        }
+    }
     __syncthreads();
+    T acc[D];
+#pragma unroll
+    for (int v = 0; v < D; ++v) acc[v] = T(0);
+    for (int k = sa + sub; k < sb; k += 1 << lg) {
+        T sv[SS];
+        lds_get(sS + (size_t)k * SS, sv);
+#pragma unroll
+        for (int v = 0; v < D; ++v) acc[v] += sv[v];
+    }
+    for (int o = 1; o < (1 << lg); o <<= 1)
+#pragma unroll
+        for (int v = 0; v < D; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
     double dsum = 0.0;
-    if (tid < nn) {
-        T acc[NV];
+    if (m < nn && sub == 0) {
+        T rec[RS];
+        lds_get(sN + (size_t)m * RS, rec);
+        const int64_t gm = bits_int<T>(rec[PO - 1]);
+        const uint32_t hc = (uint32_t)bits_int<T>(rec[RS - 1]);
+        const unsigned cm = hc & 7u;
+        if (m < nint) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = T(0);
-        for (int k = sa; k < sb; ++k)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += sS[k * NV + v];
-        if (tid < nint) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T val = (clamp >> v) & 1u ? T(0) : acc[v];
-                q[g * NV + v] = val;
-                dsum += (double)sU[tid * D + v] * (double)val;
+            for (int v = 0; v < D; ++v) {
+                const T val = (cm >> v) & 1u ? T(0) : acc[v];
+                q[gm * D + v] = val;
+                dsum += (double)rec[PO + v] * (double)val;
             }
         } else {
+            const int64_t hm = (int64_t)(hc >> 3) - 1;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                halo[(int64_t)hp * NV + v] = acc[v];
-                dsum += (clamp >> v) & 1u ? 0.0 : (double)sU[tid * D + v] * (double)acc[v];
+            for (int v = 0; v < D; ++v) {
+                halo[hm * D + v] = acc[v];
+                dsum += (cm >> v) & 1u ? 0.0 : (double)rec[PO + v] * (double)acc[v];
             }
         }
     }
@@ -369,7 +489,7 @@ static int ensure_lds_attr_cg()
 {
     static std::atomic<bool> done{false};
     if (done.load(std::memory_order_acquire)) return 0;
-    size_t cap = tile_lds_bytes<D, T, D, D>(tile_max_nodes(D), tile_max_elems(D));
+    size_t cap = CgLds<D, T>::bytes(tile_max_nodes(D), tile_max_elems(D));
     if (set_lds((const void *)k_tile_cg<D, T>, cap)) return 1;
     done.store(true, std::memory_order_release);
     return 0;
@@ -452,14 +572,14 @@ int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *
     T *halo = reinterpret_cast<T *>(c->halo);
     if (D == 2) {
         if (ensure_lds_attr_cg<2, T>()) return FO_ERR_HIP;
-        size_t lds = tile_lds_bytes<2, T, 2, 2>(c->tiles.max_nodes, c->tiles.max_elems);
+        size_t lds = CgLds<2, T>::bytes(c->tiles.max_nodes, c->tiles.max_elems);
         hipLaunchKernelGGL((k_tile_cg<2, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
                            ElasOp<2, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
                            coords, r, dinv, pin, pout, q, halo, sc, A, c->rz_part, upd_blocks(c->N),
                            c->pq_part);
     } else {
         if (ensure_lds_attr_cg<3, T>()) return FO_ERR_HIP;
-        size_t lds = tile_lds_bytes<3, T, 3, 3>(c->tiles.max_nodes, c->tiles.max_elems);
+        size_t lds = CgLds<3, T>::bytes(c->tiles.max_nodes, c->tiles.max_elems);
         hipLaunchKernelGGL((k_tile_cg<3, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
                            ElasOp<3, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
                            coords, r, dinv, pin, pout, q, halo, sc, A, c->rz_part, upd_blocks(c->N),
