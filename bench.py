@@ -253,7 +253,8 @@ def main():
     m = w.mesh
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    it_ir = Iteration(w, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), fo.SolveOpts(rtol=1e-8))
+    it_ir = Iteration(w, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8),
+                      fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8))
     log("context created in %.2f s (footprint %.1f MB, tiles %s)"
         % (time.perf_counter() - t0, it_ir.ctx.footprint / 1e6, it_ir.ctx.tile_stats()))
     it_64 = Iteration(w, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-8), fo.SolveOpts(rtol=1e-8))

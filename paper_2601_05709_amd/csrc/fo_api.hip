@@ -218,6 +218,7 @@ struct FusedVecs {
     T *x, *r, *q;
     T *p[2];
     const T *dinv;
+    int kind;  // FusedKind: the operator
 };
 
 template <typename T>
@@ -225,7 +226,7 @@ int fused_chunk(fo_ctx *c, FusedVecs<T> v, int chunk, hipStream_t s)
 {
     for (int j = 0; j < chunk; ++j) {
         const int A = j & 1;
-        FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[A], v.p[A ^ 1], v.q, c->scal, A, s));
+        FO_TRY(launch_tile_cg<T>(c, v.kind, v.r, v.dinv, v.p[A], v.p[A ^ 1], v.q, c->scal, A, s));
         launch_cgn_update<T>(c, A ^ 1, v.x, v.r, v.p[A ^ 1], v.q, v.dinv, s);
     }
     return FO_OK;
@@ -276,7 +277,8 @@ template <typename T>
 int fused_run(fo_ctx *c, FusedVecs<T> v, const fo_solve_opts *o, int64_t *iters)
 {
     const int chunk = chunk_len(o);
-    auto key = std::make_tuple(sizeof(T) == 8 ? 10 : 11, chunk, c->scatter, 0);
+    auto key = std::make_tuple((sizeof(T) == 8 ? 10 : 11) + 2 * v.kind, chunk, c->scatter,
+                               v.kind == FUSED_DESCENT ? c->descent_version : 0);
     return cg_loop(c, [&]() {
         return launch_chunk(c, key, [&](hipStream_t s) { return fused_chunk<T>(c, v, chunk, s); });
     }, iters);
@@ -289,7 +291,14 @@ int op_apply(fo_ctx *c, OpKind k, const T *x, T *y, hipStream_t s)
     return elas_apply<T>(c, x, y, s);
 }
 
-bool fused_path(const fo_ctx *c, OpKind k) { return k != OP_DESCENT64 && tiled(c); }
+// Fused CG kernels: elasticity on tiles; the descent operator too when every
+// boundary facet lies in a tile.
+bool fused_path(const fo_ctx *c, OpKind k)
+{
+    return tiled(c) && (k != OP_DESCENT64 || c->tiles.facets_ok);
+}
+
+int fused_kind(OpKind k) { return k == OP_DESCENT64 ? FUSED_DESCENT : FUSED_ELAS; }
 
 // FP64 Jacobi-PCG on A x = b (b contiguous), stopping on the recomputed
 // residual ||b - A x|| <= rtol ||b||.  The solution is left in c->x64.
@@ -300,7 +309,7 @@ int solve_fp64(fo_ctx *c, OpKind k, const double *b, const double *dinv, const f
     hipStream_t s = c->stream;
     const bool fused = fused_path(c, k);
     CgVecs<double> v{c->x64, c->r64, c->p64, c->q64, dinv};
-    FusedVecs<double> fv{c->x64, c->r64, c->q64, {c->p64, c->p64b}, dinv};
+    FusedVecs<double> fv{c->x64, c->r64, c->q64, {c->p64, c->p64b}, dinv, fused_kind(k)};
     int64_t iters = 0;
     launch_fill<double>(v.x, n, 0.0, s);
     if (fused) {
@@ -364,13 +373,15 @@ namespace {
 // residual b - K x64 is recomputed, the FP32 residual is replaced by it and
 // the search direction is kept (rescaled), so the Krylov process continues
 // instead of restarting.  Stops when ||b - K x64|| <= rtol ||b|| (FP64).
-// A phase running twice as long as the longest completed one (the first:
-// first_phase_cap) is stopped and the next one restarts its direction; after
-// two such phases in a row (FP32
+// A phase running four times as long as the longest completed one (at
+// least 256 iterations; the first phase: first_phase_cap) is stopped and the
+// next one restarts its direction; after two such phases in a row (FP32
 // cannot resolve the operator: kappa * eps_32 near 1) the solve finishes with
 // FP64 CG on the residual equation.
-int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats *st)
+int solve_ir(fo_ctx *c, OpKind k, const double *b, const fo_solve_opts *o, fo_solve_stats *st)
 {
+    const bool desc = k == OP_DESCENT64;
+    const double *dinv64 = desc ? c->descent.dinv : c->dinv64;
     const int64_t n = c->ndof;
     hipStream_t s = c->stream;
     const int nb = red_blocks(n);
@@ -392,7 +403,9 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
     int64_t longest = 0;  // iterations of the longest phase that reached its target
     int capped_run = 0;   // consecutive phases stopped at their cap
     const int64_t first_cap = first_phase_cap(n);
-    FusedVecs<float> v{c->x32, c->r32, c->q32, {c->p32, c->p32b}, c->dinv32};
+    const bool trace = std::getenv("FO_TRACE_IR") != nullptr;  // per-phase log on stderr
+    FusedVecs<float> v{c->x32, c->r32, c->q32, {c->p32, c->p32b}, desc ? c->descent.dinv32 : c->dinv32,
+                       fused_kind(k)};
     if (c->has_isolated) {
         launch_fill<float>(c->q32, n, 0.0f, s);
         launch_fill<float>(c->p32, n, 0.0f, s);
@@ -408,7 +421,7 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
         // a phase that runs twice as long as the longest completed one has
         // stagnated (the FP32 recursion lost conjugacy): end it, replace the
         // residual and restart the direction
-        const int cap = (int)std::min<int64_t>(left, longest > 0 ? std::max<int64_t>(2 * longest, 64) : first_cap);
+        const int cap = (int)std::min<int64_t>(left, longest > 0 ? std::max<int64_t>(4 * longest, 256) : first_cap);
         launch_ir_phase(c, c->r64, s2, v.r, v.x, v.dinv, phase_rtol, cap, fresh, s);
         const int64_t before = inner;
         FO_TRY(fused_run<float>(c, v, o, &inner));
@@ -419,7 +432,7 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
         if (c->scal_host->it & 1)  // the last direction is in p[1]; phases start from p[0]
             FO_HIP(hipMemcpyAsync(v.p[0], v.p[1], n * sizeof(float), hipMemcpyDeviceToDevice, s));
         launch_ir_accumulate(c->x64, v.x, s2, n, s);
-        FO_TRY(elas_apply<double>(c, c->x64, c->q64, s));
+        FO_TRY(op_apply<double>(c, k, c->x64, c->q64, s));
         ++outer;
         launch_residual64(b, c->q64, c->r64, n, c->partials, s2 + 1, s);
         FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -433,6 +446,9 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
             rn = rn_new;
             break;
         }
+        if (trace)
+            std::fprintf(stderr, "libfo: IR phase %d: %lld FP32 its (cap %d%s), |r| %.3e -> %.3e\n", outer,
+                         (long long)(inner - before), cap, capped ? ", capped" : "", rn, rn_new);
         rn = rn_new;
         if (capped_run >= 2) break;  // FP32 stagnates (kappa * eps_32 too large): finish in FP64
     }
@@ -445,11 +461,11 @@ int solve_ir(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats 
         o2.rtol = o->rtol * bnorm / rn;
         o2.max_iter = (int32_t)std::max<int64_t>(1, (int64_t)o->max_iter - inner);
         fo_solve_stats s2st{};
-        int rc = solve_fp64(c, OP_ELAS64, c->t64, c->dinv64, &o2, &s2st);
+        int rc = solve_fp64(c, k, c->t64, dinv64, &o2, &s2st);
         if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
         inner += s2st.iters_inner;
         launch_add64(c->x64, c->x64b, n, s);
-        FO_TRY(elas_apply<double>(c, c->x64, c->q64, s));
+        FO_TRY(op_apply<double>(c, k, c->x64, c->q64, s));
         ++outer;
         launch_residual64(b, c->q64, c->r64, n, c->partials, s2 + 1, s);
         FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -496,6 +512,7 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
         FO_TRY(dev_alloc(c, &ds.in0, c->E));
         FO_TRY(dev_alloc(c, &ds.diag, c->ndof));
         FO_TRY(dev_alloc(c, &ds.dinv, c->ndof));
+        FO_TRY(dev_alloc(c, &ds.dinv32, c->ndof));
     }
     ++c->descent_version;
     ds.alpha = d->alpha;
@@ -521,6 +538,7 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
         launch_descent_diag(c, ds.diag, s);
     }
     launch_invert_diag<double>(ds.diag, nullptr, c->ndof, ds.dinv, s);
+    launch_invert_diag<float>(ds.diag, nullptr, c->ndof, ds.dinv32, s);
     ds.valid = true;
     return FO_OK;
 }
@@ -547,7 +565,7 @@ int time_cg_op(fo_ctx *c, FusedVecs<T> v, int reps, double *avg_us)
     launch_fill<double>(c->rz_part, 2 * kRedBlocks, 0.0, s);
     launch_fill<T>(v.r, n, T(1), s);
     launch_fill<T>(v.p[0], n, T(1), s);
-    FO_TRY(launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s));  // warm-up
+    FO_TRY(launch_tile_cg<T>(c, v.kind, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s));  // warm-up
     hipEvent_t e0, e1;
     FO_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -557,7 +575,7 @@ int time_cg_op(fo_ctx *c, FusedVecs<T> v, int reps, double *avg_us)
     int rc = FO_OK;
     (void)hipEventRecord(e0, s);
     for (int k = 0; k < reps && rc == FO_OK; ++k)
-        rc = launch_tile_cg<T>(c, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s);
+        rc = launch_tile_cg<T>(c, v.kind, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s);
     (void)hipEventRecord(e1, s);
     float ms = 0.0f;
     if (rc == FO_OK && (hipEventSynchronize(e1) != hipSuccess ||
@@ -777,6 +795,126 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
                 hipSuccess)
             return fail(rc ? rc : FO_ERR_HIP);
     }
+    // Boundary facets of the descent operator per tile node: a facet goes to
+    // the tile of an element that has it as a face (so all its vertices are
+    // nodes of that tile); each of its vertices gets an incidence holding the
+    // facet's local vertex ids and a = sqrt(|F| / (d (d+1))) n, so that the
+    // facet adds gamma_n a (a . (x_vertex + sum over the facet's vertices x))
+    // at the vertex.  Kept alive until the stream sync below.
+    std::vector<int32_t> fptr_h;
+    std::vector<uint64_t> fconn_h;
+    std::vector<double> fa64_h;
+    std::vector<float> fa32_h;
+    c->tiles.facets_ok = true;
+    if (c->nbf > 0 && ht.n_tiles > 0) {
+        const int64_t F = c->nbf, T = ht.n_tiles, MN = ht.max_nodes;
+        std::vector<int32_t> nptr((size_t)N + 1, 0), nel((size_t)(D + 1) * E);
+        for (int64_t k = 0; k < (int64_t)(D + 1) * E; ++k) ++nptr[(size_t)conn_t[k] + 1];
+        for (int64_t i = 0; i < N; ++i) nptr[i + 1] += nptr[i];
+        {
+            std::vector<int32_t> fill(nptr.begin(), nptr.end() - 1);
+            for (int64_t e = 0; e < E; ++e)
+                for (int a = 0; a <= D; ++a) nel[fill[conn_t[(size_t)a * E + e]]++] = (int32_t)e;
+        }
+        std::vector<int32_t> etile((size_t)E);
+        for (int64_t t = 0; t < T; ++t) {
+            const int32_t e0 = ht.info[(size_t)t * kTileInfo + kTileE0];
+            const int32_t ne = ht.info[(size_t)t * kTileInfo + kTileNE];
+            for (int32_t i = 0; i < ne; ++i) etile[(size_t)e0 + i] = (int32_t)t;
+        }
+        std::vector<int32_t> ftile((size_t)F, -1);
+        for (int64_t f = 0; f < F && c->tiles.facets_ok; ++f) {
+            const int32_t v0 = m->bfacets[f];
+            for (int32_t k = nptr[v0]; k < nptr[v0 + 1] && ftile[f] < 0; ++k) {
+                const int64_t e = nel[k];
+                bool all = true;
+                for (int b = 1; b < D && all; ++b) {
+                    const int32_t vb = m->bfacets[(int64_t)b * F + f];
+                    bool in = false;
+                    for (int a = 0; a <= D; ++a) in = in || conn_t[(size_t)a * E + e] == vb;
+                    all = in;
+                }
+                if (all) ftile[f] = etile[e];
+            }
+            if (ftile[f] < 0) c->tiles.facets_ok = false;
+        }
+        if (c->tiles.facets_ok) {
+            // facets grouped by tile (increasing facet id within a tile)
+            std::vector<int64_t> tptr((size_t)T + 1, 0), tfac((size_t)F);
+            for (int64_t f = 0; f < F; ++f) ++tptr[(size_t)ftile[f] + 1];
+            for (int64_t t = 0; t < T; ++t) tptr[t + 1] += tptr[t];
+            {
+                std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+                for (int64_t f = 0; f < F; ++f) tfac[fill[ftile[f]]++] = f;
+            }
+            std::vector<int32_t> loc((size_t)N, -1);
+            fptr_h.assign((size_t)T * (MN + 1), 0);
+            struct Inc {
+                int32_t l;
+                int64_t f;
+                uint64_t conn;
+            };
+            std::vector<Inc> inc;
+            for (int64_t t = 0; t < T; ++t) {
+                const int32_t nn = ht.info[(size_t)t * kTileInfo + kTileNN];
+                for (int32_t l = 0; l < nn; ++l) loc[ht.nodes[(size_t)t * MN + l]] = l;
+                inc.clear();
+                for (int64_t k = tptr[t]; k < tptr[t + 1]; ++k) {
+                    const int64_t f = tfac[k];
+                    uint64_t cw = 0;
+                    int32_t lid[3] = {0, 0, 0};
+                    for (int b = 0; b < D; ++b) {
+                        lid[b] = loc[m->bfacets[(int64_t)b * F + f]];
+                        cw |= (uint64_t)(uint16_t)lid[b] << (16 * b);
+                    }
+                    for (int b = 0; b < D; ++b) inc.push_back(Inc{lid[b], f, cw});
+                }
+                std::stable_sort(inc.begin(), inc.end(), [](const Inc &x, const Inc &y) { return x.l < y.l; });
+                const int64_t base = (int64_t)fconn_h.size();
+                size_t j = 0;
+                for (int32_t l = 0; l <= MN; ++l) {
+                    fptr_h[(size_t)t * (MN + 1) + l] = (int32_t)(base + (int64_t)j);
+                    while (j < inc.size() && inc[j].l == l) ++j;
+                }
+                for (const Inc &x : inc) {
+                    const int64_t f = x.f;
+                    double P[3][3] = {};
+                    for (int b = 0; b < D; ++b)
+                        for (int q = 0; q < D; ++q) P[b][q] = m->coords[(int64_t)m->bfacets[(int64_t)b * F + f] * D + q];
+                    double area;
+                    if (D == 2) {
+                        area = std::hypot(P[1][0] - P[0][0], P[1][1] - P[0][1]);
+                    } else {
+                        const double u0 = P[1][0] - P[0][0], u1 = P[1][1] - P[0][1], u2 = P[1][2] - P[0][2];
+                        const double v0 = P[2][0] - P[0][0], v1 = P[2][1] - P[0][1], v2 = P[2][2] - P[0][2];
+                        const double c0 = u1 * v2 - u2 * v1, c1 = u2 * v0 - u0 * v2, c2 = u0 * v1 - u1 * v0;
+                        area = 0.5 * std::sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+                    }
+                    const double sw = std::sqrt(area / (double)(D * (D + 1)));
+                    fconn_h.push_back(x.conn);
+                    for (int q = 0; q < 4; ++q) {
+                        const double a = q < D ? sw * m->bnormal[f * D + q] : 0.0;
+                        fa64_h.push_back(a);
+                        fa32_h.push_back((float)a);
+                    }
+                }
+                for (int32_t l = 0; l < nn; ++l) loc[ht.nodes[(size_t)t * MN + l]] = -1;
+            }
+            c->tiles.n_fent = (int64_t)fconn_h.size();
+            if (c->tiles.n_fent > INT32_MAX) return fail(FO_ERR_MESH);
+            if ((rc = dev_alloc(c, &c->tiles.fptr, fptr_h.size())) ||
+                (rc = dev_alloc(c, &c->tiles.fconn, std::max<size_t>(fconn_h.size(), 1))) ||
+                (rc = dev_alloc(c, &c->tiles.fa64, std::max<size_t>(fa64_h.size(), 4))) ||
+                (rc = dev_alloc(c, &c->tiles.fa32, std::max<size_t>(fa32_h.size(), 4))))
+                return fail(rc);
+            if (up(c->tiles.fptr, fptr_h.data(), fptr_h.size() * sizeof(int32_t)) ||
+                (c->tiles.n_fent > 0 &&
+                 (up(c->tiles.fconn, fconn_h.data(), fconn_h.size() * sizeof(uint64_t)) ||
+                  up(c->tiles.fa64, fa64_h.data(), fa64_h.size() * sizeof(double)) ||
+                  up(c->tiles.fa32, fa32_h.data(), fa32_h.size() * sizeof(float)))))
+                return fail(FO_ERR_HIP);
+        }
+    }
     if ((rc = tiled_prepare(c))) return fail(rc);
     if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -852,9 +990,9 @@ int fo_time_kernel(fo_ctx *c, int32_t kernel, int32_t reps, double *avg_us)
         return batch_time_apply(c, c->batch.S / 16, reps, avg_us);
     }
     if (kernel == FO_KERNEL_CG_OP_FP64)
-        return time_cg_op<double>(c, FusedVecs<double>{c->x64, c->r64, c->q64, {c->p64, c->p64b}, c->dinv64},
+        return time_cg_op<double>(c, FusedVecs<double>{c->x64, c->r64, c->q64, {c->p64, c->p64b}, c->dinv64, FUSED_ELAS},
                                   reps, avg_us);
-    return time_cg_op<float>(c, FusedVecs<float>{c->x32, c->r32, c->q32, {c->p32, c->p32b}, c->dinv32},
+    return time_cg_op<float>(c, FusedVecs<float>{c->x32, c->r32, c->q32, {c->p32, c->p32b}, c->dinv32, FUSED_ELAS},
                              reps, avg_us);
 }
 
@@ -965,7 +1103,7 @@ int fo_state_solve(fo_ctx *c, const double *b, double *u, int32_t n_rhs, int64_t
         launch_gather_col<double, double>(b + k, ld, c->ndof, c->b64, c->fixed, s);
         fo_solve_stats one{};
         int rc = o->precision == FO_FP64 ? solve_fp64(c, OP_ELAS64, c->b64, c->dinv64, o, &one)
-                                         : solve_ir(c, c->b64, o, &one);
+                                         : solve_ir(c, OP_ELAS64, c->b64, o, &one);
         if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
         launch_scatter_col<double>(c->x64, c->ndof, u + k, ld, s);
         acc.iters_inner += one.iters_inner;
@@ -1016,7 +1154,9 @@ int fo_descent_solve(fo_ctx *c, const fo_descent_opts *d, const double *rhs, dou
     FO_TRY(descent_prepare(c, d));
     hipStream_t s = c->stream;
     fo_solve_stats one{};
-    int rc = solve_fp64(c, OP_DESCENT64, rhs, c->descent.dinv, o, &one);
+    int rc = o->precision == FO_FP32_IR && fused_path(c, OP_DESCENT64)
+                 ? solve_ir(c, OP_DESCENT64, rhs, o, &one)
+                 : solve_fp64(c, OP_DESCENT64, rhs, c->descent.dinv, o, &one);
     if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
     FO_HIP(hipMemcpyAsync(theta, c->x64, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (B_tt) {

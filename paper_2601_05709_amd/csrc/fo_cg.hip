@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
     // the p.q partials first (they depend on nothing), then the node data
     PartLoad<4> ppq;
     part_issue(ppq, pq_part, n_pq, threadIdx.x, blockDim.x);
-    if (sc[B].done) return;
+    const int32_t done = sc[B].done;
     int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     T di[D], qi[D], xi[D], ri[D], pi[D];
     auto load = [&](int64_t nd) {
@@ -329,6 +329,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
         }
     };
     if (node < N) load(node);
+    if (done) return;
     double pq = block_sum_any(part_finish(ppq, pq_part, n_pq, threadIdx.x, blockDim.x), lds);
     if (threadIdx.x == 0) lds[0] = pq;
     __syncthreads();

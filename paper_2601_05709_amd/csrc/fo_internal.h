@@ -76,6 +76,13 @@ struct TileSet {
     int32_t *node_hrange = nullptr;     // [N][2] halo range of a node, (-1,-1) if interior
     float *tx32 = nullptr;              // [n_tiles][MN][dim] node coordinates minus the tile's
                                         // first node, formed in FP64 (FP32 operator geometry)
+    // boundary facets of the descent operator, per tile node (see fo_create)
+    bool facets_ok = false;             // every facet lies in a tile (else: node-parallel facets)
+    int64_t n_fent = 0;                 // tile-node / facet incidences
+    int32_t *fptr = nullptr;            // [n_tiles][MN+1] first incidence of each tile node
+    uint64_t *fconn = nullptr;          // [n_fent] local ids of the facet's vertices (4 x uint16)
+    double *fa64 = nullptr;             // [n_fent][4] a = sqrt(|F| / (d (d+1))) n
+    float *fa32 = nullptr;              // [n_fent][4] FP32 copy
 };
 
 // Per-column state of the batched (multi-load) CG, one entry per column of
@@ -146,6 +153,7 @@ struct DescentSetup {
     uint8_t *in0 = nullptr;   // [E] element centroid in Omega0 (tile element order)
     double *diag = nullptr;   // [n_dofs]
     double *dinv = nullptr;   // [n_dofs]
+    float *dinv32 = nullptr;  // [n_dofs]
 };
 
 }  // namespace fo

@@ -53,8 +53,10 @@ void launch_cgn_start(const fo_ctx *c, const T *b, const T *q, T *r, const T *di
 template <typename T>
 void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *q, const T *dinv,
                        hipStream_t s);
+// Operator of the fused CG kernels.
+enum FusedKind { FUSED_ELAS = 0, FUSED_DESCENT = 1 };
 template <typename T>
-int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *pout, T *q,
+int launch_tile_cg(const fo_ctx *c, int kind, const T *r, const T *dinv, const T *pin, T *pout, T *q,
                    SolveScalars *sc, int A, hipStream_t s);
 void launch_ir_phase(const fo_ctx *c, const double *r64, double *s2, float *r32, float *x32,
                      const float *dinv, double phase_rtol, int max_it, int fresh, hipStream_t s);

@@ -39,18 +39,17 @@ struct ElasDiagOp {
     }
 };
 
-template <int D>
+template <int D, typename T = double>
 struct DescentOp {
     static constexpr int NX = D, NV = D;
     using Elem = uint8_t;
     const uint8_t *in0;
-    double alpha, gamma_s;
+    T alpha, gamma_s;
     __device__ Elem load(int64_t e) const { return in0[e]; }
-    __device__ void operator()(Elem in, const double *const *X, const double *const *U,
-                               double out[D + 1][NV]) const
+    __device__ void operator()(Elem in, const T *const *X, const T *const *U, T out[D + 1][NV]) const
     {
-        double mw = alpha + (in ? gamma_s : 0.0);
-        descent_element<D, double>(X, U, mw, out);
+        T mw = alpha + (in ? gamma_s : T(0));
+        descent_element<D, T>(X, U, mw, out);
     }
 };
 

@@ -157,6 +157,15 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
     }
 }
 
+// Boundary-facet term of the descent operator in tile form (fptr null: none).
+template <typename T>
+struct FacetArgs {
+    const int32_t *fptr;    // [n_tiles][MN+1] incidence ranges per tile node
+    const uint64_t *fconn;  // [n_fent] local ids of the facet's vertices
+    const T *fa;            // [n_fent][4] a = sqrt(|F| / (d (d+1))) n
+    T gamma_n;
+};
+
 // LDS layout of the fused CG operator kernel (k_tile_cg):
 //   node records [nn][8]: position (D values) in the first 16-byte half,
 //     the direction p in the second; the global node id and the packed
@@ -229,7 +238,8 @@ __device__ __forceinline__ void lds_put(T *p, const T (&in)[N])
     }
 }
 
-// Operator kernel of one fused CG iteration (elasticity, tiled):
+// Operator kernel of one fused CG iteration (tiled; elasticity, or the
+// descent operator with its boundary-facet term added at the nodes):
 //   rho_k = r.D^-1 r and rr_k = r.r from the partials of the previous update
 //   (summed by wave 0 while the other waves load their nodes); convergence
 //   test; beta = rho_k / rho_{k-1} (or the slot's first-iteration
@@ -242,8 +252,8 @@ __device__ __forceinline__ void lds_put(T *p, const T (&in)[N])
 // each add every L-th slot of the node's segment, then the L partial sums
 // are combined by a butterfly (every lane of the group gets the same value).
 // Reads scalar slot A, writes slot A ^ 1 (block 0).
-template <int D, typename T>
-__global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
+template <int D, typename T, class Op>
+__global__ __launch_bounds__(1024) void k_tile_cg(Op op, TileArgs ta, FacetArgs<T> fa,
                                                   const T *__restrict__ coords,
                                                   const T *__restrict__ r,
                                                   const T *__restrict__ dinv,
@@ -265,37 +275,36 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
     // wave 0 issues the loads of the r.z / r.r partials first: they depend on
     // nothing, and their latency then overlaps the index and node loads
     PartLoad<4> prz, prr;
+    SolveScalars cur;
     if (tid < 64) {
         part_issue(prz, rz_part, rz_nb, tid, 64);
         part_issue(prr, rz_part + rz_nb, rz_nb, tid, 64);
+        cur = sc[A];
     }
-    if (sc[A].done) {
-        if (t == 0 && tid == 0) sc[A ^ 1] = sc[A];
-        return;
-    }
-    // issue the index and node loads before the scalar decision
+    // Index loads at fixed strides: they do not wait for the tile's counts
+    // (every thread below ME / MN reads inside the tile's arrays; padding
+    // entries are never used).  Lanes per node from the node stride MN.
     const int32_t *inf = ta.info + (int64_t)t * kTileInfo;
-    const int e0 = inf[kTileE0], ne = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt],
-              nown = inf[kTileNOwn];
     const int nt = blockDim.x;
-    const int lg = nn * 4 <= nt ? 2 : (nn * 2 <= nt ? 1 : 0);  // log2 of lanes per node
+    const int lg = ta.MN * 4 <= nt ? 2 : (ta.MN * 2 <= nt ? 1 : 0);  // log2 of lanes per node
     const int m = tid >> lg, sub = tid & ((1 << lg) - 1);
     uint64_t lc = 0, ls = 0;
-    uint8_t ed = 0;
-    if (tid < ne) {
+    if (tid < ta.ME) {
         lc = ta.lconn[(int64_t)t * ta.ME + tid];
         ls = ta.lslot[(int64_t)t * ta.ME + tid];
-        ed = op.load(e0 + tid);
     }
-    int sa = 0, sb = 0;
-    if (m < nn) {
+    int sa = 0, sb = 0, fk0 = 0, fk1 = 0;
+    if (m < ta.MN) {
         sa = ta.seg[(int64_t)t * (ta.MN + 1) + m];
         sb = ta.seg[(int64_t)t * (ta.MN + 1) + m + 1];
+        if (fa.fptr) {
+            fk0 = fa.fptr[(int64_t)t * (ta.MN + 1) + m];
+            fk1 = fa.fptr[(int64_t)t * (ta.MN + 1) + m + 1];
+        }
     }
     int32_t g = 0, hp = -1;
-    unsigned clamp = 0;  // bit v: dinv = 0 (clamped unknown, or no element): q = 0 there
-    T xv[D], zv[D], po[D];
-    if (tid < nn) {
+    T xv[D];
+    if (tid < ta.MN) {
         const int64_t tn = (int64_t)t * ta.MN + tid;
         g = ta.nodes[tn];
         hp = ta.hpos[tn];
@@ -303,7 +312,19 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
         for (int v = 0; v < D; ++v) {
             // FP32 geometry from tile-local offsets (formed in FP64 on the host)
             if constexpr (sizeof(T) == 4) xv[v] = ta.tx32[tn * D + v];
-            else xv[v] = coords[(int64_t)g * D + v];
+        }
+    }
+    const int e0 = inf[kTileE0], ne = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt],
+              nown = inf[kTileNOwn];
+    if (m >= nn) sa = sb = fk0 = fk1 = 0;
+    typename Op::Elem ed{};
+    if (tid < ne) ed = op.load(e0 + tid);
+    unsigned clamp = 0;  // bit v: dinv = 0 (clamped unknown, or no element): q = 0 there
+    T zv[D], po[D];
+    if (tid < nn) {
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            if constexpr (sizeof(T) == 8) xv[v] = coords[(int64_t)g * D + v];
             const T di = dinv[(int64_t)g * D + v];
             zv[v] = di * r[(int64_t)g * D + v];
             po[v] = pin[(int64_t)g * D + v];
@@ -314,26 +335,30 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
         const double rho_k = wave_sum(part_finish(prz, rz_part, rz_nb, tid, 64));
         const double rr_k = wave_sum(part_finish(prr, rz_part + rz_nb, rz_nb, tid, 64));
         if (tid == 0) {
-            const SolveScalars cur = sc[A];
-            const bool bad = !(rho_k >= 0.0) || rho_k != rho_k || rr_k != rr_k ||
-                             rho_k == INFINITY || rr_k == INFINITY;
-            const bool stop = bad || rr_k <= cur.tol2 || cur.it >= cur.max_it;
-            s_go = !stop;
-            s_beta = cur.first ? cur.beta : (cur.rho > 0.0 ? rho_k / cur.rho : 0.0);
-            if (t == 0) {
-                SolveScalars nx = cur;
-                nx.rr = rr_k;
-                nx.rho_new = rho_k;
-                if (stop) {
-                    nx.done = 1;
-                    nx.status = bad ? FO_ERR_BREAKDOWN : 0;
-                } else {
-                    nx.rho = rho_k;
-                    nx.beta = s_beta;
-                    nx.first = 0;
-                    nx.it = cur.it + 1;
+            if (cur.done) {  // converged or failed earlier: the launch is a no-op
+                s_go = 0;
+                if (t == 0) sc[A ^ 1] = cur;
+            } else {
+                const bool bad = !(rho_k >= 0.0) || rho_k != rho_k || rr_k != rr_k ||
+                                 rho_k == INFINITY || rr_k == INFINITY;
+                const bool stop = bad || rr_k <= cur.tol2 || cur.it >= cur.max_it;
+                s_go = !stop;
+                s_beta = cur.first ? cur.beta : (cur.rho > 0.0 ? rho_k / cur.rho : 0.0);
+                if (t == 0) {
+                    SolveScalars nx = cur;
+                    nx.rr = rr_k;
+                    nx.rho_new = rho_k;
+                    if (stop) {
+                        nx.done = 1;
+                        nx.status = bad ? FO_ERR_BREAKDOWN : 0;
+                    } else {
+                        nx.rho = rho_k;
+                        nx.beta = s_beta;
+                        nx.first = 0;
+                        nx.it = cur.it + 1;
+                    }
+                    sc[A ^ 1] = nx;
                 }
-                sc[A ^ 1] = nx;
             }
         }
     }
@@ -408,6 +433,25 @@ __global__ __launch_bounds__(1024) void k_tile_cg(ElasOp<D, T> op, TileArgs ta,
         const int64_t gm = bits_int<T>(rec[PO - 1]);
         const uint32_t hc = (uint32_t)bits_int<T>(rec[RS - 1]);
         const unsigned cm = hc & 7u;
+        // boundary facets of this tile at node m (descent operator):
+        // gamma_n a (a . (p_m + sum over the facet's vertices p_b))
+        for (int k = fk0; k < fk1; ++k) {
+            const uint64_t fc = fa.fconn[k];
+            T av[D], sn = T(0), self = T(0);
+#pragma unroll
+            for (int v = 0; v < D; ++v) av[v] = fa.fa[(int64_t)k * 4 + v];
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const T *pb = sN + (size_t)((fc >> (16 * b)) & 0xFFFF) * RS + PO;
+#pragma unroll
+                for (int v = 0; v < D; ++v) sn += av[v] * pb[v];
+            }
+#pragma unroll
+            for (int v = 0; v < D; ++v) self += av[v] * rec[PO + v];
+            const T c = fa.gamma_n * (self + sn);
+#pragma unroll
+            for (int v = 0; v < D; ++v) acc[v] += c * av[v];
+        }
         if (m < nint) {
 #pragma unroll
             for (int v = 0; v < D; ++v) {
@@ -484,13 +528,13 @@ static int ensure_lds_attr()
     return 0;
 }
 
-template <int D, typename T>
+template <int D, typename T, class Op>
 static int ensure_lds_attr_cg()
 {
     static std::atomic<bool> done{false};
     if (done.load(std::memory_order_acquire)) return 0;
     size_t cap = CgLds<D, T>::bytes(tile_max_nodes(D), tile_max_elems(D));
-    if (set_lds((const void *)k_tile_cg<D, T>, cap)) return 1;
+    if (set_lds((const void *)k_tile_cg<D, T, Op>, cap)) return 1;
     done.store(true, std::memory_order_release);
     return 0;
 }
@@ -501,8 +545,10 @@ static int prepare_dim()
     return ensure_lds_attr<D, double, ElasOp<D, double>>() | ensure_lds_attr<D, float, ElasOp<D, float>>() |
            ensure_lds_attr<D, double, ElasDiagOp<D, double>>() | ensure_lds_attr<D, double, DescentOp<D>>() |
            ensure_lds_attr<D, double, DescentDiagOp<D>>() | ensure_lds_attr<D, double, SdRhsOp<D>>() |
-           ensure_lds_attr<D, double, PhiGradOp<D>>() | ensure_lds_attr_cg<D, double>() |
-           ensure_lds_attr_cg<D, float>();
+           ensure_lds_attr<D, double, PhiGradOp<D>>() | ensure_lds_attr_cg<D, double, ElasOp<D, double>>() |
+           ensure_lds_attr_cg<D, float, ElasOp<D, float>>() |
+           ensure_lds_attr_cg<D, double, DescentOp<D, double>>() |
+           ensure_lds_attr_cg<D, float, DescentOp<D, float>>();
 }
 
 int tiled_prepare(const fo_ctx *c)
@@ -558,39 +604,58 @@ static int run_tiled(const fo_ctx *c, const Op &op, const T *coords, const T *xi
     return FO_OK;
 }
 
-template <typename T>
-int launch_tile_cg(const fo_ctx *c, const T *r, const T *dinv, const T *pin, T *pout, T *q,
-                   SolveScalars *sc, int A, hipStream_t s)
+template <int D, typename T, class Op>
+static int launch_tile_cg_op(const fo_ctx *c, Op op, FacetArgs<T> fa, const T *r, const T *dinv,
+                             const T *pin, T *pout, T *q, SolveScalars *sc, int A, hipStream_t s)
 {
-    const int D = c->dim;
-    const int which = sizeof(T) == 8 ? FO_PROF_ELAS_TILE_FP64 : FO_PROF_ELAS_TILE_FP32;
-    auto *pt = prof_slot(c, which);
-    if (pt) (void)hipEventRecord(pt->first, s);
+    if (ensure_lds_attr_cg<D, T, Op>()) return FO_ERR_HIP;
     const T *coords;
     if constexpr (sizeof(T) == 8) coords = c->coords;
     else coords = c->coords32;
-    T *halo = reinterpret_cast<T *>(c->halo);
-    if (D == 2) {
-        if (ensure_lds_attr_cg<2, T>()) return FO_ERR_HIP;
-        size_t lds = CgLds<2, T>::bytes(c->tiles.max_nodes, c->tiles.max_elems);
-        hipLaunchKernelGGL((k_tile_cg<2, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
-                           ElasOp<2, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
-                           coords, r, dinv, pin, pout, q, halo, sc, A, c->rz_part, upd_blocks(c->N),
-                           c->pq_part);
-    } else {
-        if (ensure_lds_attr_cg<3, T>()) return FO_ERR_HIP;
-        size_t lds = CgLds<3, T>::bytes(c->tiles.max_nodes, c->tiles.max_elems);
-        hipLaunchKernelGGL((k_tile_cg<3, T>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds, s,
-                           ElasOp<3, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu}, tile_args(c),
-                           coords, r, dinv, pin, pout, q, halo, sc, A, c->rz_part, upd_blocks(c->N),
-                           c->pq_part);
-    }
-    if (pt) (void)hipEventRecord(pt->second, s);
+    size_t lds = CgLds<D, T>::bytes(c->tiles.max_nodes, c->tiles.max_elems);
+    hipLaunchKernelGGL((k_tile_cg<D, T, Op>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds,
+                       s, op, tile_args(c), fa, coords, r, dinv, pin, pout, q,
+                       reinterpret_cast<T *>(c->halo), sc, A, c->rz_part, upd_blocks(c->N), c->pq_part);
     return FO_OK;
 }
-template int launch_tile_cg<double>(const fo_ctx *, const double *, const double *, const double *,
+
+template <int D, typename T>
+static int launch_tile_cg_dim(const fo_ctx *c, int kind, const T *r, const T *dinv, const T *pin,
+                              T *pout, T *q, SolveScalars *sc, int A, hipStream_t s)
+{
+    if (kind == FUSED_ELAS)
+        return launch_tile_cg_op<D, T>(c, ElasOp<D, T>{c->chi, (T)c->ersatz, (T)c->lam, (T)c->mu},
+                                       FacetArgs<T>{nullptr, nullptr, nullptr, T(0)}, r, dinv, pin, pout,
+                                       q, sc, A, s);
+    const DescentSetup &d = c->descent;
+    const TileSet &ts = c->tiles;
+    FacetArgs<T> fa{nullptr, nullptr, nullptr, T(0)};
+    if (ts.n_fent > 0 && d.gamma_n != 0.0) {
+        const T *a;
+        if constexpr (sizeof(T) == 8) a = ts.fa64;
+        else a = ts.fa32;
+        fa = FacetArgs<T>{ts.fptr, ts.fconn, a, (T)d.gamma_n};
+    }
+    return launch_tile_cg_op<D, T>(c, DescentOp<D, T>{d.in0, (T)d.alpha, (T)d.gamma_s}, fa, r, dinv,
+                                   pin, pout, q, sc, A, s);
+}
+
+template <typename T>
+int launch_tile_cg(const fo_ctx *c, int kind, const T *r, const T *dinv, const T *pin, T *pout, T *q,
+                   SolveScalars *sc, int A, hipStream_t s)
+{
+    int which = -1;
+    if (kind == FUSED_ELAS) which = sizeof(T) == 8 ? FO_PROF_ELAS_TILE_FP64 : FO_PROF_ELAS_TILE_FP32;
+    auto *pt = which >= 0 ? prof_slot(c, which) : nullptr;
+    if (pt) (void)hipEventRecord(pt->first, s);
+    const int rc = c->dim == 2 ? launch_tile_cg_dim<2, T>(c, kind, r, dinv, pin, pout, q, sc, A, s)
+                               : launch_tile_cg_dim<3, T>(c, kind, r, dinv, pin, pout, q, sc, A, s);
+    if (pt) (void)hipEventRecord(pt->second, s);
+    return rc;
+}
+template int launch_tile_cg<double>(const fo_ctx *, int, const double *, const double *, const double *,
                                     double *, double *, SolveScalars *, int, hipStream_t);
-template int launch_tile_cg<float>(const fo_ctx *, const float *, const float *, const float *,
+template int launch_tile_cg<float>(const fo_ctx *, int, const float *, const float *, const float *,
                                    float *, float *, SolveScalars *, int, hipStream_t);
 
 // ---------------------------------------------------------------------------

@@ -164,6 +164,47 @@ def test_descent_apply_and_solve(name):
     assert Btt.item() == pytest.approx(th_ref @ rhs, rel=1e-9)
 
 
+@pytest.mark.parametrize("name", ["2d_37x19", "3d_12x6x6", "3d_26x13x11"])
+def test_descent_solve_fp32_ir(name):
+    """FP32 fused descent CG with FP64 residual replacement reaches the same
+    FP64 tolerance as the FP64 solve (facet term in the tile kernel)."""
+    w = WORKLOADS[name]()
+    m = w.mesh
+    Bd = oc.assemble_descent(m.dim, m.coords, m.conn, m.bfacets, m.bnormal, w.alpha, w.gamma_n,
+                             w.gamma_s, w.boxes)
+    ctx = fo.Context.from_workload(w)
+    dop = fo.DescentOpts(w.alpha, w.gamma_n, w.gamma_s, w.boxes, dim=m.dim)
+    rhs = np.random.default_rng(16).standard_normal(m.n_dofs)
+    th_ref, _ = Bd.solve(rhs, None, rtol=1e-12)
+    th = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    Btt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = ctx.descent_solve(dop, dev(rhs), th, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-10), Btt)
+    assert st.status == 0 and st.iters_outer >= 1
+    r = rhs - Bd.matvec(th.cpu().numpy())
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(rhs)
+    assert rel(th.cpu().numpy(), th_ref) < 1e-7
+    assert Btt.item() == pytest.approx(th_ref @ rhs, rel=1e-8)
+
+
+@pytest.mark.parametrize("name", ["2d_37x19", "3d_12x6x6"])
+def test_descent_fused_matches_node_parallel_facets(name):
+    """The fused descent CG (facets per tile node) and the generic CG on the
+    atomic scatter (node-parallel facets) solve the same system."""
+    w = WORKLOADS[name]()
+    m = w.mesh
+    dop = fo.DescentOpts(w.alpha, w.gamma_n, w.gamma_s, w.boxes, dim=m.dim)
+    rhs = dev(np.random.default_rng(17).standard_normal(m.n_dofs))
+    out = []
+    for scatter in (fo.FO_SCATTER_TILED, fo.FO_SCATTER_ATOMIC):
+        ctx = fo.Context.from_workload(w)
+        ctx.set_scatter(scatter)
+        th = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+        st = ctx.descent_solve(dop, rhs, th, fo.SolveOpts(rtol=1e-12))
+        assert st.status == 0
+        out.append(th.cpu().numpy())
+    assert rel(out[0], out[1]) < 1e-9
+
+
 @pytest.mark.parametrize("name", ["2d_37x19", "3d_26x13x11"])
 def test_levelset_update_matches_oracle(name):
     w = WORKLOADS[name]()
