@@ -238,22 +238,48 @@ int launch_chunk(fo_ctx *c, std::tuple<int, int, int, int> key, Enqueue enqueue)
     return graph_chunk(c, key, std::function<int(hipStream_t)>(enqueue));
 }
 
-// Polls slot 0 between chunks until the device flags done; adds iterations.
+// Status copy of slot 0 into scal_host[k], behind everything enqueued so far.
+int status_async(fo_ctx *c, int k)
+{
+    FO_HIP(hipMemcpyAsync(c->scal_host + k, c->scal, sizeof(SolveScalars), hipMemcpyDeviceToHost,
+                          c->stream));
+    FO_HIP(hipEventRecord(c->ev_poll[k], c->stream));
+    return FO_OK;
+}
+
+// Runs chunks until the device flags done; adds iterations.  Two chunks are
+// in flight: the next chunk is enqueued before the host waits for the status
+// of the previous one, so the GPU does not idle while the host polls.  Chunks
+// after `done` are no-ops (even length: the state stays in slot 0); the final
+// status ends in scal_host[0].
 template <class Chunk>
 int cg_loop(fo_ctx *c, Chunk chunk_fn, int64_t *iters)
 {
     FO_TRY(poll(c));
-    while (!c->scal_host->done) {
-        const int32_t before = c->scal_host->it;
+    if (!c->scal_host[0].done) {
+        int32_t before = c->scal_host[0].it;
         FO_TRY(chunk_fn());
-        FO_TRY(poll(c));
-        if (!c->scal_host->done && c->scal_host->it == before) {  // no progress: a launch failed
-            hipError_t e = hipGetLastError();
-            std::fprintf(stderr, "libfo: CG chunk made no progress (%s)\n", hipGetErrorString(e));
-            return FO_ERR_HIP;
+        FO_TRY(status_async(c, 1));
+        int k = 1;
+        while (true) {
+            FO_TRY(chunk_fn());
+            FO_TRY(status_async(c, k ^ 1));
+            FO_HIP(hipEventSynchronize(c->ev_poll[k]));
+            const SolveScalars &h = c->scal_host[k];
+            if (h.done) break;
+            if (h.it == before) {  // no progress: a launch failed
+                hipError_t e = hipGetLastError();
+                std::fprintf(stderr, "libfo: CG chunk made no progress (%s)\n", hipGetErrorString(e));
+                (void)hipStreamSynchronize(c->stream);
+                return FO_ERR_HIP;
+            }
+            before = h.it;
+            k ^= 1;
         }
+        FO_HIP(hipEventSynchronize(c->ev_poll[k ^ 1]));
+        c->scal_host[0] = c->scal_host[k ^ 1];
     }
-    *iters += c->scal_host->it;
+    *iters += c->scal_host[0].it;
     return FO_OK;
 }
 
@@ -619,6 +645,8 @@ int fo_destroy(fo_ctx *c)
     if (c->work) (void)hipStreamDestroy(c->work);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    for (hipEvent_t e : c->ev_poll)
+        if (e) (void)hipEventDestroy(e);
     for (auto &v : c->prof_events)
         for (auto &pr : v) {
             (void)hipEventDestroy(pr.first);
@@ -729,7 +757,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
     // shape-derivative partial sums: one row per RHS (+ volume)
     c->sd_part_cap = (int)std::min<int64_t>(((E + kBlock - 1) / kBlock) * (max_rhs + 1), INT32_MAX);
     if ((rc = dev_alloc(c, &c->sd_part, c->sd_part_cap))) return fail(rc);
-    if (hipHostMalloc((void **)&c->scal_host, sizeof(SolveScalars)) != hipSuccess ||
+    if (hipHostMalloc((void **)&c->scal_host, 2 * sizeof(SolveScalars)) != hipSuccess ||
         hipHostMalloc((void **)&c->red_host, 16 * sizeof(double)) != hipSuccess)
         return fail(FO_ERR_NOMEM);
     std::vector<int32_t> bnode, bptr, bfac;
@@ -918,7 +946,9 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
     if ((rc = tiled_prepare(c))) return fail(rc);
     if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess)
         return fail(FO_ERR_HIP);
     if (max_rhs > 1 && tiled(c) && (rc = batch_setup(c, max_rhs))) return fail(rc);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(FO_ERR_HIP);

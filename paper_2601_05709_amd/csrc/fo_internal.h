@@ -202,9 +202,10 @@ struct fo_ctx {
     double *rz_part = nullptr;         // [2 * kRedBlocks] r.z, r.r partials
     double *bb_part = nullptr;         // [kRedBlocks] b.b partials
     fo::SolveScalars *scal = nullptr;  // device, two parity slots
-    fo::SolveScalars *scal_host = nullptr;  // pinned copy of slot 0
+    fo::SolveScalars *scal_host = nullptr;  // pinned [2]: copies of slot 0 (final state in [0])
     hipStream_t work = nullptr;        // private non-blocking stream for graph replay
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};  // status copies of chunks in flight
     // captured CG iteration chunks: key (operator, chunk, scatter, descent version)
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
     int descent_version = 0;
