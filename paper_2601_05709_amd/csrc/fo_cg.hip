@@ -319,13 +319,32 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
             xi[v] = x[i];
             ri[v] = r[i];
             pi[v] = p[i];
-            if (hr.x < 0) {
-                qi[v] = q[i];
-            } else {
-                T a = T(0);
-                for (int j = hr.x; j < hr.y; ++j) a += halo[(int64_t)j * D + v];
-                qi[v] = a;
+        }
+        if (hr.x < 0) {
+#pragma unroll
+            for (int v = 0; v < D; ++v) qi[v] = q[(int64_t)nd * D + v];
+        } else {
+            // the node's halo slots in order; the first KH are loaded together
+            // (indices clamped into the range, so every load is in bounds)
+            constexpr int KH = 4;
+            const int cnt = hr.y - hr.x;
+            T hv[KH][D];
+#pragma unroll
+            for (int k = 0; k < KH; ++k) {
+                const int64_t j = hr.x + min(k, cnt - 1);
+#pragma unroll
+                for (int v = 0; v < D; ++v) hv[k][v] = halo[j * D + v];
             }
+#pragma unroll
+            for (int v = 0; v < D; ++v) qi[v] = T(0);
+#pragma unroll
+            for (int k = 0; k < KH; ++k)
+                if (k < cnt)
+#pragma unroll
+                    for (int v = 0; v < D; ++v) qi[v] += hv[k][v];
+            for (int j = hr.x + KH; j < hr.y; ++j)
+#pragma unroll
+                for (int v = 0; v < D; ++v) qi[v] += halo[(int64_t)j * D + v];
         }
     };
     if (node < N) load(node);
