@@ -81,6 +81,25 @@ __device__ __forceinline__ int pick4(const int4 v, int k)
     return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
 }
 
+// Sum of a shared row's halo entries (slots hr.x .. hr.y-1 in order, entry
+// off of each slot of `stride` floats); the first KH slots are loaded
+// together (indices clamped into the range, every load in bounds).
+__device__ __forceinline__ float halo_row_sum(const float *__restrict__ halo, int2 hr, int64_t off,
+                                              int64_t stride)
+{
+    constexpr int KH = 4;
+    const int cnt = hr.y - hr.x;
+    float hv[KH];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) hv[k] = halo[(int64_t)(hr.x + min(k, cnt - 1)) * stride + off];
+    float q = 0.f;
+#pragma unroll
+    for (int k = 0; k < KH; ++k)
+        if (k < cnt) q += hv[k];
+    for (int j = hr.x + KH; j < hr.y; ++j) q += halo[(int64_t)j * stride + off];
+    return q;
+}
+
 // Element data of the batched operator, once per level set and per slot:
 // the cofactor vectors c_a (c_0 = -sum) and w = A_e / (d! |det|), so that
 // K_e[(a,i),(b,j)] = w (lam c_ai c_bj + mu c_aj c_bi + mu delta_ij c_a.c_b).
@@ -419,8 +438,7 @@ __global__ __launch_bounds__(256) void k_batch_update(
         if (hr.x < 0) {
             q = Q[row * S + col];
         } else {
-            q = 0.f;
-            for (int j = hr.x; j < hr.y; ++j) q += halo[((int64_t)j * D + i) * S + col];
+            q = halo_row_sum(halo, hr, (int64_t)i * S + col, (int64_t)D * S);
         }
         const float di = dinv[row];
         if (di == 0.f) q = 0.f;
@@ -711,8 +729,7 @@ __global__ __launch_bounds__(256) void k_batch_collect(const float *__restrict__
         if (hr.x < 0) {
             q = Q[row * S + col];
         } else {
-            q = 0.f;
-            for (int j = hr.x; j < hr.y; ++j) q += halo[((int64_t)j * D + i) * S + col];
+            q = halo_row_sum(halo, hr, (int64_t)i * S + col, (int64_t)D * S);
         }
         Y[row * S + col] = fixed[row] ? 0.f : q;
     }
