@@ -58,7 +58,7 @@ def fused_cg_bytes(mesh, width):
 
 # Kernel sources whose change invalidates recorded HBM traffic counters.
 TRAFFIC_SOURCES = ["fo_tiled.hip", "fo_element.h", "fo_ops.h", "fo_reduce.h", "fo_internal.h",
-                   "fo_tiles.cpp", "fo_tiles.h"]
+                   "fo_tiles.cpp", "fo_tiles.h", "fo_xcd.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_tile_cg_fp32_cantilever3d_96x48x48.md")
 
 
