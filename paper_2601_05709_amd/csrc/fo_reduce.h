@@ -5,13 +5,50 @@
 
 namespace fo {
 
-// reductions: wave64 shuffle, then LDS across the waves of a block
+// reductions: wave64 DPP, then LDS across the waves of a block
 
-__device__ __forceinline__ double wave_sum(double v)
+// x of the lane that the DPP control CTRL selects, 0 where it selects none
+// or the row/bank mask disables the lane (register-only cross-lane read).
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_read(double x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, BANK_MASK, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, BANK_MASK, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), valid in every lane:
+// prefix sums within each row of 16 lanes (row_shr 1, 2, 3, then 4 and 8 on
+// the upper banks), the row totals chained by row_bcast 15 and 31 into lane
+// 63, then read from lane 63.  A fixed order: the same inputs give the same
+// bits in every wave.
+__device__ __forceinline__ double wave_sum(double x)
+{
+    double v = x + dpp_read<0x111, 0xf, 0xf>(x);
+    v += dpp_read<0x112, 0xf, 0xf>(x);
+    v += dpp_read<0x113, 0xf, 0xf>(x);
+    v += dpp_read<0x114, 0xf, 0xe>(v);
+    v += dpp_read<0x118, 0xf, 0xc>(v);
+    v += dpp_read<0x142, 0xa, 0xf>(v);
+    v += dpp_read<0x143, 0xc, 0xf>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// x of lane (lane ^ 1) or (lane ^ 2) within each group of four (DPP quad_perm).
+template <int XOR, typename T>
+__device__ __forceinline__ T quad_xor(T x)
+{
+    static_assert(XOR == 1 || XOR == 2, "quad lanes");
+    constexpr int QP = XOR == 1 ? 0xB1 : 0x4E;  // (1,0,3,2) or (2,3,0,1)
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), QP, 0xf, 0xf, false));
+    } else {
+        const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), QP, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), QP, 0xf, 0xf, false);
+        return __hiloint2double(hi, lo);
+    }
 }
 
 // Sum over a 256-thread block; the result is valid in thread 0.

@@ -423,9 +423,12 @@ __global__ __launch_bounds__(1024) void k_tile_cg(Op op, TileArgs ta, FacetArgs<
 #pragma unroll
         for (int v = 0; v < D; ++v) acc[v] += sv[v];
     }
-    for (int o = 1; o < (1 << lg); o <<= 1)
+    if (lg >= 1)
 #pragma unroll
-        for (int v = 0; v < D; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
+        for (int v = 0; v < D; ++v) acc[v] += quad_xor<1>(acc[v]);
+    if (lg >= 2)
+#pragma unroll
+        for (int v = 0; v < D; ++v) acc[v] += quad_xor<2>(acc[v]);
     double dsum = 0.0;
     if (m < nn && sub == 0) {
         T rec[RS];
