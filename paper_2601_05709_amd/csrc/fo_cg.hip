@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
     const double *__restrict__ pq_part, int n_pq, double *__restrict__ rz_part,
     const int2 *__restrict__ hrange, const T *__restrict__ halo)
 {
-    __shared__ double lds[16];
+    __shared__ double lds[32];
     __shared__ double s_alpha;
     // the p.q partials first (they depend on nothing), then the node data
     PartLoad<4> ppq;
@@ -382,10 +382,10 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
         node += (int64_t)gridDim.x * blockDim.x;
         if (node < N) load(node);
     }
-    double s0 = block_sum_any(rz, lds), s1 = block_sum_any(rr, lds);
+    block_sum2_any(rz, rr, lds);
     if (threadIdx.x == 0) {
-        rz_part[blockIdx.x] = s0;
-        rz_part[gridDim.x + blockIdx.x] = s1;
+        rz_part[blockIdx.x] = rz;
+        rz_part[gridDim.x + blockIdx.x] = rr;
     }
 }
 

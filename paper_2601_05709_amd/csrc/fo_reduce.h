@@ -73,7 +73,8 @@ __device__ __forceinline__ double block_sum_partials(const double *part, int n, 
 }
 
 // Sum over a block of any size that is a multiple of 64 (at most 1024
-// threads); waves are combined in a fixed order.  Valid in thread 0.
+// threads): wave sums, then wave 0 sums the wave totals (a fixed order).
+// Valid in every lane of wave 0.
 __device__ __forceinline__ double block_sum_any(double v, double *lds /*[16]*/)
 {
     v = wave_sum(v);
@@ -82,10 +83,28 @@ __device__ __forceinline__ double block_sum_any(double v, double *lds /*[16]*/)
     if (lane == 0) lds[w] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int k = 0; k < nw; ++k) s += lds[k];
+    if (threadIdx.x < 64) s = wave_sum(lane < nw ? lds[lane] : 0.0);
     __syncthreads();
     return s;
+}
+
+// Two block sums in one pass (lds[32]); valid in every lane of wave 0.
+__device__ __forceinline__ void block_sum2_any(double &a, double &b, double *lds /*[32]*/)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+        lds[w] = a;
+        lds[16 + w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        a = wave_sum(lane < nw ? lds[lane] : 0.0);
+        b = wave_sum(lane < nw ? lds[16 + lane] : 0.0);
+    }
+    __syncthreads();
 }
 
 // Every thread of the block gets the same fixed-order sum of n partials.
