@@ -308,6 +308,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
     PartLoad<4> ppq;
     part_issue(ppq, pq_part, n_pq, threadIdx.x, blockDim.x);
     const int32_t done = sc[B].done;
+    const double rho = sc[B].rho;
     int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     T di[D], qi[D], xi[D], ri[D], pi[D];
     auto load = [&](int64_t nd) {
@@ -349,23 +350,29 @@ __global__ __launch_bounds__(kUpdBlock) void k_cgn_update(
     };
     if (node < N) load(node);
     if (done) return;
-    double pq = block_sum_any(part_finish(ppq, pq_part, n_pq, threadIdx.x, blockDim.x), lds);
-    if (threadIdx.x == 0) lds[0] = pq;
-    __syncthreads();
-    pq = lds[0];
-    if (threadIdx.x == 0) {
-        const bool ok = pq > 0.0 && finite(pq);
-        s_alpha = ok ? sc[B].rho / pq : 0.0;
-        if (blockIdx.x == 0) {
-            sc[B].pq = pq;
-            sc[B].alpha = s_alpha;
-            if (!ok) {  // not SPD or non-finite: stop (benign race with the done test above)
-                sc[B].status = FO_ERR_BREAKDOWN;
-                sc[B].done = 1;
+    {
+        // p.q: wave sums, then wave 0 sums the wave totals and sets alpha
+        const double v = wave_sum(part_finish(ppq, pq_part, n_pq, threadIdx.x, blockDim.x));
+        const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        if (lane == 0) lds[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const double pq = wave_sum(lane < nw ? lds[lane] : 0.0);
+            if (threadIdx.x == 0) {
+                const bool ok = pq > 0.0 && finite(pq);
+                s_alpha = ok ? rho / pq : 0.0;
+                if (blockIdx.x == 0) {
+                    sc[B].pq = pq;
+                    sc[B].alpha = s_alpha;
+                    if (!ok) {  // not SPD or non-finite: stop (benign race with the done test above)
+                        sc[B].status = FO_ERR_BREAKDOWN;
+                        sc[B].done = 1;
+                    }
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
     const T alpha = (T)s_alpha;
     double rz = 0.0, rr = 0.0;
     while (node < N) {

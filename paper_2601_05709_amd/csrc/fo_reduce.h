@@ -88,6 +88,17 @@ __device__ __forceinline__ double block_sum_any(double v, double *lds /*[16]*/)
     return s;
 }
 
+// block_sum_any for the last use of lds in a kernel (no trailing barrier).
+__device__ __forceinline__ double block_sum_last(double v, double *lds /*[16]*/)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    return threadIdx.x < 64 ? wave_sum(lane < nw ? lds[lane] : 0.0) : 0.0;
+}
+
 // Two block sums in one pass (lds[32]); valid in every lane of wave 0.
 __device__ __forceinline__ void block_sum2_any(double &a, double &b, double *lds /*[32]*/)
 {

@@ -471,7 +471,7 @@ __global__ __launch_bounds__(1024) void k_tile_cg(Op op, TileArgs ta, FacetArgs<
             }
         }
     }
-    const double s = block_sum_any(dsum, lds);
+    const double s = block_sum_last(dsum, lds);
     if (tid == 0) pq_part[t] = s;
 }
 
