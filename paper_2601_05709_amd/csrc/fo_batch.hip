@@ -72,7 +72,7 @@ static BatchTileArgs batch_tile_args(const fo_ctx *c)
 size_t batch_lds_bytes(int D, int S, int MN)
 {
     const int KS = (D * D + 3) / 4;
-    return (size_t)MN * D * S * 4 + (size_t)kBatchKB * KS * 64 * 4 + (size_t)kBatchKB * (D + 1) * D * 4 +
+    return (size_t)MN * D * S * 4 + (size_t)S * 16 + (size_t)kBatchKB * KS * 64 * 4 + (size_t)kBatchKB * (D + 1) * D * 4 +
            (size_t)kBatchKB * 4 + (size_t)2 * kBatchKB * 16 + (size_t)MN * 8 + (((size_t)MN * D + 15) / 16) * 16;
 }
 
@@ -192,7 +192,9 @@ __global__ __launch_bounds__(64 * NC) void k_batch_apply(
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *sY = reinterpret_cast<float *>(smem_raw);       // [MN][D][S]
-    float *sK = sY + (size_t)ta.MN * D * S;                // [KB][KS][64] K_e fragments
+    float *sDummy = sY + (size_t)ta.MN * D * S;            // [S * 4]: sink of rows without a node
+    float *sK = sDummy + S * 4;                            // [KB][KS][64] K_e fragments
+    const int sink = (int)(sDummy - sY);
     float *sC = sK + KB * KS * 64;                         // [KB][NV][D] cofactor vectors
     float *sW = sC + KB * NV * D;                          // [KB] w
     int4 *sEN = reinterpret_cast<int4 *>(sW + KB);         // [KB] global vertex ids
@@ -292,10 +294,13 @@ __global__ __launch_bounds__(64 * NC) void k_batch_apply(
                 for (int j = 0; j < D; ++j) v0[j] = P[((int64_t)en.x * D + j) * S + colg];
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
-                    const int k = 4 * s + g, j = k % D;
+                    // lanes past the contraction length (k >= NK) load a valid
+                    // row and use 0: no divergent branch, so no wait here
+                    const int k = 4 * s + g, kc = k < NK ? k : NK - 1, j = kc % D;
                     const float x0 = D == 2 ? (j == 0 ? v0[0] : v0[D - 1])
                                             : (j == 0 ? v0[0] : j == 1 ? v0[1] : v0[D - 1]);
-                    bv[e][s] = k < NK ? P[((int64_t)pick4(en, 1 + k / D) * D + j) * S + colg] - x0 : 0.f;
+                    const float xb = P[((int64_t)pick4(en, 1 + kc / D) * D + j) * S + colg];
+                    bv[e][s] = k < NK ? xb - x0 : 0.f;
                     av[e][s] = sK[(el * KS + s) * 64 + lane];
                 }
                 const uint32_t l0 = (a0 < 2 ? lc.x >> (16 * a0) : lc.y >> (16 * (a0 - 2))) & 0xFFFF;
@@ -312,29 +317,28 @@ __global__ __launch_bounds__(64 * NC) void k_batch_apply(
                 for (int s = 0; s < KS; ++s)
                     acc[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e][s], bv[e][s], acc[e], 0, 0, 0);
             }
-            // the group's elements share no node: all reads, then all writes
+            // the group's elements share no node: all reads, then all writes.
+            // Rows past d(d+1) and padding slots go to a per-lane sink in LDS
+            // (no divergent branch); the sink is never read back.
+            int ad[G][4];
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = 4 * g + q;
+                    const bool ok = r < NR && (lv[e] & 0xFFFF) != 0xFFFF;
+                    const int ln = (int)(r / D == a0 ? (lv[e] & 0xFFFF) : (lv[e] >> 16));
+                    ad[e][q] = ok ? (ln * D + (r % D)) * S + colg : sink + q * S + colg;
+                }
             float old[G][4];
 #pragma unroll
             for (int e = 0; e < G; ++e)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = 4 * g + q;
-                    old[e][q] = 0.f;
-                    if (r < NR && (lv[e] & 0xFFFF) != 0xFFFF) {
-                        const int ln = (int)(r / D == a0 ? (lv[e] & 0xFFFF) : (lv[e] >> 16));
-                        old[e][q] = sY[(ln * D + (r % D)) * S + colg];
-                    }
-                }
+                for (int q = 0; q < 4; ++q) old[e][q] = sY[ad[e][q]];
 #pragma unroll
             for (int e = 0; e < G; ++e)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = 4 * g + q;
-                    if (r < NR && (lv[e] & 0xFFFF) != 0xFFFF) {
-                        const int ln = (int)(r / D == a0 ? (lv[e] & 0xFFFF) : (lv[e] >> 16));
-                        sY[(ln * D + (r % D)) * S + colg] = old[e][q] + acc[e][q];
-                    }
-                }
+                for (int q = 0; q < 4; ++q) sY[ad[e][q]] = old[e][q] + acc[e][q];
         };
         load(0, avA, bvA, lvA);
         fetch(base + KB);
