@@ -23,15 +23,13 @@ using namespace fo;
 
 namespace fo {
 
-// Enqueues one chunk; with profiling off, a captured graph of it is replayed
-// on the private stream, fenced by events against the context stream.
+// Enqueues one chunk; with profiling off, a graph of it (captured once on the
+// private stream, which only records) is replayed on the context stream.
 int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
                 const std::function<int(hipStream_t)> &enqueue)
 {
     if (c->prof) return enqueue(c->stream);
     auto it = c->graphs.find(key);
-    FO_HIP(hipEventRecord(c->ev_in, c->stream));
-    FO_HIP(hipStreamWaitEvent(c->work, c->ev_in, 0));
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {
         hipGraph_t g = nullptr;
@@ -50,9 +48,7 @@ int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
     } else {
         exec = it->second;
     }
-    FO_HIP(hipGraphLaunch(exec, c->work));
-    FO_HIP(hipEventRecord(c->ev_out, c->work));
-    FO_HIP(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    FO_HIP(hipGraphLaunch(exec, c->stream));
     return FO_OK;
 }
 
@@ -255,9 +251,10 @@ int status_async(fo_ctx *c, int k)
 template <class Chunk>
 int cg_loop(fo_ctx *c, Chunk chunk_fn, int64_t *iters)
 {
-    FO_TRY(poll(c));
-    if (!c->scal_host[0].done) {
-        int32_t before = c->scal_host[0].it;
+    {
+        // the first chunk goes out without waiting for the start state (a
+        // solve that is done from the start makes it a no-op)
+        int32_t before = -1;
         FO_TRY(chunk_fn());
         FO_TRY(status_async(c, 1));
         int k = 1;
@@ -643,8 +640,6 @@ int fo_destroy(fo_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
     if (c->work) (void)hipStreamDestroy(c->work);
-    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
-    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     for (hipEvent_t e : c->ev_poll)
         if (e) (void)hipEventDestroy(e);
     for (auto &v : c->prof_events)
@@ -945,8 +940,6 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
     }
     if ((rc = tiled_prepare(c))) return fail(rc);
     if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess)
         return fail(FO_ERR_HIP);

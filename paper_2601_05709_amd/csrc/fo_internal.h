@@ -203,8 +203,7 @@ struct fo_ctx {
     double *bb_part = nullptr;         // [kRedBlocks] b.b partials
     fo::SolveScalars *scal = nullptr;  // device, two parity slots
     fo::SolveScalars *scal_host = nullptr;  // pinned [2]: copies of slot 0 (final state in [0])
-    hipStream_t work = nullptr;        // private non-blocking stream for graph replay
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t work = nullptr;        // private non-blocking stream on which graphs are captured
     hipEvent_t ev_poll[2] = {nullptr, nullptr};  // status copies of chunks in flight
     // captured CG iteration chunks: key (operator, chunk, scatter, descent version)
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
