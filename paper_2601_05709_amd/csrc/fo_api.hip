@@ -243,40 +243,56 @@ int status_async(fo_ctx *c, int k)
     return FO_OK;
 }
 
-// Runs chunks until the device flags done; adds iterations.  Two chunks are
-// in flight: the next chunk is enqueued before the host waits for the status
-// of the previous one, so the GPU does not idle while the host polls.  Chunks
-// after `done` are no-ops (even length: the state stays in slot 0); the final
-// status ends in scal_host[0].
+// Runs chunks of `chunk` iterations until the device flags done; adds
+// iterations.  Normally two chunks are in flight: the next one is enqueued
+// before the host waits for the status of the previous one, so the GPU does
+// not idle while the host polls.  When the residual trend of the last two
+// statuses says the chunk in flight will finish the solve, no further chunk
+// is enqueued ahead of it (a chunk after `done` would be all no-op launches).
+// Chunks have even length, so the state stays in slot 0; the final status
+// ends in scal_host[0].  A status copy still in flight after the loop only
+// rewrites the same final bytes (launches after `done` change nothing).
 template <class Chunk>
-int cg_loop(fo_ctx *c, Chunk chunk_fn, int64_t *iters)
+int cg_loop(fo_ctx *c, Chunk chunk_fn, int chunk, int64_t *iters)
 {
-    {
-        // the first chunk goes out without waiting for the start state (a
-        // solve that is done from the start makes it a no-op)
-        int32_t before = -1;
+    int pending[2], inflight = 0, slot = 0;
+    auto launch = [&]() -> int {
         FO_TRY(chunk_fn());
-        FO_TRY(status_async(c, 1));
-        int k = 1;
-        while (true) {
-            FO_TRY(chunk_fn());
-            FO_TRY(status_async(c, k ^ 1));
-            FO_HIP(hipEventSynchronize(c->ev_poll[k]));
-            const SolveScalars &h = c->scal_host[k];
-            if (h.done) break;
-            if (h.it == before) {  // no progress: a launch failed
-                hipError_t e = hipGetLastError();
-                std::fprintf(stderr, "libfo: CG chunk made no progress (%s)\n", hipGetErrorString(e));
-                (void)hipStreamSynchronize(c->stream);
-                return FO_ERR_HIP;
-            }
-            before = h.it;
-            k ^= 1;
+        FO_TRY(status_async(c, slot));
+        pending[inflight++] = slot;
+        slot ^= 1;
+        return FO_OK;
+    };
+    FO_TRY(launch());  // the first chunk goes out without waiting for the start state
+    FO_TRY(launch());
+    int32_t before = -1;
+    double prev_rr = -1.0;
+    SolveScalars last{};
+    while (true) {
+        const int k = pending[0];
+        pending[0] = pending[1];
+        --inflight;
+        FO_HIP(hipEventSynchronize(c->ev_poll[k]));
+        last = c->scal_host[k];
+        if (last.done) break;
+        if (last.it == before) {  // no progress: a launch failed
+            hipError_t e = hipGetLastError();
+            std::fprintf(stderr, "libfo: CG chunk made no progress (%s)\n", hipGetErrorString(e));
+            (void)hipStreamSynchronize(c->stream);
+            return FO_ERR_HIP;
         }
-        FO_HIP(hipEventSynchronize(c->ev_poll[k ^ 1]));
-        c->scal_host[0] = c->scal_host[k ^ 1];
+        // iterations still needed at the rate of the last chunk
+        bool near = false;
+        if (prev_rr > 0.0 && last.rr > 0.0 && last.rr < prev_rr && last.tol2 > 0.0 && before >= 0) {
+            const double per_it = std::log(last.rr / prev_rr) / (double)(last.it - before);
+            near = std::log(last.tol2 / last.rr) / per_it <= (double)chunk;
+        }
+        prev_rr = last.rr;
+        before = last.it;
+        if (inflight == 0 || !near) FO_TRY(launch());
     }
-    *iters += c->scal_host[0].it;
+    c->scal_host[0] = last;
+    *iters += last.it;
     return FO_OK;
 }
 
@@ -293,7 +309,7 @@ int cg_run(fo_ctx *c, OpKind k, CgVecs<T> v, const fo_solve_opts *o, int64_t *it
     auto key = std::make_tuple((int)k, chunk, c->scatter, k == OP_DESCENT64 ? c->descent_version : 0);
     return cg_loop(c, [&]() {
         return launch_chunk(c, key, [&](hipStream_t s) { return cg_chunk<T>(c, k, v, chunk, s); });
-    }, iters);
+    }, chunk, iters);
 }
 
 template <typename T>
@@ -304,7 +320,7 @@ int fused_run(fo_ctx *c, FusedVecs<T> v, const fo_solve_opts *o, int64_t *iters)
                                v.kind == FUSED_DESCENT ? c->descent_version : 0);
     return cg_loop(c, [&]() {
         return launch_chunk(c, key, [&](hipStream_t s) { return fused_chunk<T>(c, v, chunk, s); });
-    }, iters);
+    }, chunk, iters);
 }
 
 template <typename T>
