@@ -199,11 +199,11 @@ def batched_case(cells=(64, 32, 32), n_loads=64):
     }
 
 
-def serving_case(n=120, rate=200.0, budget_bytes=16 << 30, max_slots=8):
-    """Serving stream: n requests (state solve FP32+refinement to 1e-8,
-    shape derivative, descent solve FP64 to 1e-8) on meshes drawn from the
-    five serving sizes, Poisson arrivals at `rate`, admission by a device
-    memory budget, contexts kept resident per mesh."""
+def serving_case(n=120, rate=200.0, budget_bytes=16 << 30, max_slots=12, fp32_descent=True):
+    """Serving stream: n requests (state solve and descent solve to 1e-8,
+    FP32+refinement from 100k DOFs, else FP64; shape derivative) on meshes
+    drawn from the five serving sizes, Poisson arrivals at `rate`, admission
+    by a device memory budget, contexts kept resident per mesh."""
     import fo_inputs as fi
     from paper_2601_05709_amd import fo, serving
     reqs = []
@@ -212,9 +212,10 @@ def serving_case(n=120, rate=200.0, budget_bytes=16 << 30, max_slots=8):
         # small problems are launch-latency bound: FP32 saves no time there and
         # only adds iterations, so they are solved in FP64
         prec = fo.FO_FP32_IR if w.mesh.n_dofs >= 100000 else fo.FO_FP64
+        dprec = prec if fp32_descent else fo.FO_FP64
         reqs.append(serving.Request(w, key=serving.mesh_key(w),
                                     state_opts=fo.SolveOpts(precision=prec, rtol=1e-8),
-                                    descent_opts=fo.SolveOpts(rtol=1e-8)))
+                                    descent_opts=fo.SolveOpts(precision=dprec, rtol=1e-8)))
     arrivals = fi.poisson_arrivals(n, rate, seed=4)
     out = serving.serve(reqs, arrivals, budget_bytes, max_slots)
     kinds = {}
@@ -223,8 +224,8 @@ def serving_case(n=120, rate=200.0, budget_bytes=16 << 30, max_slots=8):
         kinds.setdefault(k, []).append(r.t_end - r.t_start)
     return {
         "workload": "Poisson arrivals %.0f/s, %d requests, meshes 2D 128x64/256x128, 3D 32x16x16/64x32x32/"
-                    "80x40x40; state (FP32+refinement from 100k DOFs, else FP64) + derivative + descent "
-                    "per request, rel. res 1e-8" % (rate, n),
+                    "80x40x40; state + derivative + descent per request (solves FP32+refinement from "
+                    "100k DOFs, else FP64), rel. res 1e-8" % (rate, n),
         "solves_per_s": out["solves_per_s"], "wall_s": out["wall_s"],
         "latency_p50_s": out["latency_p50_s"], "latency_p99_s": out["latency_p99_s"],
         "service_p50_s": out["service_p50_s"], "max_queue": out["max_queue"],
