@@ -24,7 +24,11 @@
  *     eq. compli1_bili: mass + gradient term + subdomain penalty (eq. sub_dom)
  *     + boundary normal penalty (eq. bd_plt)  (Section "Velocity");
  *   - level-set transport theta . grad(phi) (eq. transport), advanced by one
- *     explicit step with a recovered nodal gradient.
+ *     explicit step with a recovered nodal gradient;
+ *   - the paper's own transport step (Section "Transport equation", eqs.
+ *     transport, weak_transport, tau_lv): Petrov-Galerkin test functions
+ *     psi + tau theta . grad psi, Crank-Nicolson in time, optional h^2
+ *     diffusion; each time step solved by Jacobi-preconditioned BiCGStab.
  */
 #include <math.h>
 #include <stdint.h>
@@ -633,6 +637,272 @@ int oc_levelset_update(int dim, int64_t N, int64_t E, const double *coords, cons
     free(G);
     free(W);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* transport step of the paper (Section "Transport equation")               */
+
+/* The diffusion coefficient h^2.  The paper's "mesh diameter" expression,
+ * 4|D|/(N_T sqrt 3) in 2D and (6 sqrt 2 |D|/N_T)^(2/3) in 3D, is the square
+ * of the edge length of N_T equilateral triangles / regular tetrahedra
+ * filling D, so it is used as h^2 itself.  |D| = sum of element measures. */
+double oc_transport_h2(int dim, int64_t E, const double *coords, const int32_t *conn)
+{
+    double area = 0.0;
+    for (int64_t e = 0; e < E; ++e) {
+        double g[OC_MAXV][3], vol;
+        if (oc_simplex(dim, coords, conn, E, e, g, &vol)) return -1.0;
+        area += vol;
+    }
+    if (dim == 2) return 4.0 * area / ((double)E * sqrt(3.0));
+    return pow(6.0 * sqrt(2.0) * area / (double)E, 2.0 / 3.0);
+}
+
+/* Sparsity of a scalar P1 operator (one unknown per node). */
+static oc_csr *oc_csr_scalar(int dim, int64_t N, int64_t E, const int32_t *conn)
+{
+    /* the vector structure with one component: build it for "dimension 1"
+     * connectivity rows of dim+1 vertices */
+    int nv = dim + 1;
+    int64_t *cnt = calloc((size_t)N + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < nv; ++a) cnt[conn[(int64_t)a * E + e] + 1] += nv;
+    for (int64_t n = 0; n < N; ++n) cnt[n + 1] += cnt[n];
+    int64_t *lst = malloc((size_t)(cnt[N] ? cnt[N] : 1) * sizeof(int64_t));
+    int64_t *fill = malloc((size_t)(N ? N : 1) * sizeof(int64_t));
+    memcpy(fill, cnt, (size_t)N * sizeof(int64_t));
+    for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < nv; ++a) {
+            int64_t na = conn[(int64_t)a * E + e];
+            for (int b = 0; b < nv; ++b) lst[fill[na]++] = conn[(int64_t)b * E + e];
+        }
+    int64_t *uptr = calloc((size_t)N + 1, sizeof(int64_t));
+    for (int64_t n = 0; n < N; ++n) {
+        int64_t s0 = cnt[n], len = cnt[n + 1] - cnt[n];
+        qsort(lst + s0, (size_t)len, sizeof(int64_t), cmp_i64);
+        int64_t u = 0;
+        for (int64_t k = 0; k < len; ++k)
+            if (k == 0 || lst[s0 + k] != lst[s0 + k - 1]) lst[s0 + u++] = lst[s0 + k];
+        uptr[n + 1] = u;
+    }
+    for (int64_t n = 0; n < N; ++n) uptr[n + 1] += uptr[n];
+    int64_t *adj = malloc((size_t)(uptr[N] ? uptr[N] : 1) * sizeof(int64_t));
+    for (int64_t n = 0; n < N; ++n)
+        memcpy(adj + uptr[n], lst + cnt[n], (size_t)(uptr[n + 1] - uptr[n]) * sizeof(int64_t));
+    free(lst);
+    free(fill);
+    free(cnt);
+    oc_csr *A = calloc(1, sizeof(oc_csr));
+    A->dim = 1;
+    A->n = N;
+    A->nadj_ptr = uptr;
+    A->nadj = adj;
+    A->rowptr = malloc((size_t)(N + 1) * sizeof(int64_t));
+    A->rowptr[0] = 0;
+    for (int64_t n = 0; n < N; ++n) A->rowptr[n + 1] = A->rowptr[n] + (uptr[n + 1] - uptr[n]);
+    A->col = malloc((size_t)(A->rowptr[N] ? A->rowptr[N] : 1) * sizeof(int64_t));
+    A->val = calloc((size_t)(A->rowptr[N] ? A->rowptr[N] : 1), sizeof(double));
+    for (int64_t n = 0; n < N; ++n)
+        for (int64_t k = uptr[n]; k < uptr[n + 1]; ++k) A->col[A->rowptr[n] + (k - uptr[n])] = adj[k];
+    return A;
+}
+
+/* One time step of eq. weak_transport reads, with F(u, v) = (theta . grad u)
+ * v / 2 + h^2 grad u . grad v / 2 and the test function psi_hat = psi + tau
+ * theta . grad psi,
+ *   int phi' psi_hat + dt F(phi', psi_hat) = int phi psi_hat - dt F(phi, psi_hat).
+ * theta and tau enter per element, at the element mean of the nodal theta
+ * (a one-point rule; tau = (1/2) (dt^-2 + |theta|^2 / h^2)^(-1/2), eq.
+ * tau_lv), so the stabilised test function is linear on the element and its
+ * second derivatives vanish.  With lambda_a the hat functions, g_a = grad
+ * lambda_a and |T| the measure, the element entries (row a = test, column b
+ * = trial) are
+ *   mass          |T| (1 + delta_ab) / ((d+1)(d+2))
+ *   stab. mass    tau (theta . g_a) |T| / (d+1)
+ *   advection     (1/2) (theta . g_b) |T| / (d+1)
+ *   stab. advect. (1/2) tau (theta . g_a) (theta . g_b) |T|
+ *   diffusion     (1/2) h^2 (g_a . g_b) |T|                (smooth only)
+ * and the step matrix is mass + stab. mass + sign dt (advection + stab.
+ * advection + diffusion): sign +1 gives the left-hand side L, -1 the
+ * right-hand side R.  Returns NULL for a degenerate element. */
+oc_csr *oc_assemble_transport(int dim, int64_t N, int64_t E, const double *coords,
+                              const int32_t *conn, const double *theta, double h2, int smooth,
+                              double dt, double sign)
+{
+    oc_csr *A = oc_csr_scalar(dim, N, E, conn);
+    int nv = dim + 1;
+    for (int64_t e = 0; e < E; ++e) {
+        double g[OC_MAXV][3], vol;
+        if (oc_simplex(dim, coords, conn, E, e, g, &vol)) {
+            oc_csr_free(A);
+            return NULL;
+        }
+        double th[3] = {0, 0, 0};
+        for (int a = 0; a < nv; ++a) {
+            int64_t node = conn[(int64_t)a * E + e];
+            for (int i = 0; i < dim; ++i) th[i] += theta[node * dim + i] / nv;
+        }
+        double t2 = 0.0;
+        for (int i = 0; i < dim; ++i) t2 += th[i] * th[i];
+        double tau = 0.5 / sqrt(1.0 / (dt * dt) + t2 / h2);
+        double tg[OC_MAXV];
+        for (int a = 0; a < nv; ++a) {
+            tg[a] = 0.0;
+            for (int i = 0; i < dim; ++i) tg[a] += th[i] * g[a][i];
+        }
+        for (int a = 0; a < nv; ++a) {
+            int64_t na = conn[(int64_t)a * E + e];
+            for (int b = 0; b < nv; ++b) {
+                int64_t nb = conn[(int64_t)b * E + e];
+                double gg = 0.0;
+                for (int i = 0; i < dim; ++i) gg += g[a][i] * g[b][i];
+                double mass = vol * (a == b ? 2.0 : 1.0) / ((dim + 1) * (dim + 2));
+                double smass = tau * tg[a] * vol / nv;
+                double adv = 0.5 * tg[b] * vol / nv;
+                double sadv = 0.5 * tau * tg[a] * tg[b] * vol;
+                double diff = smooth ? 0.5 * h2 * gg * vol : 0.0;
+                oc_csr_add(A, na, 0, nb, 0, mass + smass + sign * dt * (adv + sadv + diff));
+            }
+        }
+    }
+    return A;
+}
+
+/* Jacobi-preconditioned BiCGStab (van der Vorst's method with the
+ * preconditioner on the right: search directions M^-1 p and M^-1 s) for a
+ * nonsymmetric A x = b, from the given x, until the recomputed residual
+ * ||b - A x||_2 <= rtol ||b||_2.  Returns operator applications; status 0
+ * converged, 1 iteration limit, -5 breakdown. */
+int64_t oc_bicgstab(const oc_csr *A, const double *b, double *x, double rtol, int64_t max_iter,
+                    double *relres, int *status)
+{
+    int64_t n = A->n;
+    double *r = malloc((size_t)n * sizeof(double));
+    double *rh = malloc((size_t)n * sizeof(double));
+    double *p = calloc((size_t)n, sizeof(double));
+    double *v = calloc((size_t)n, sizeof(double));
+    double *y = malloc((size_t)n * sizeof(double));
+    double *z = malloc((size_t)n * sizeof(double));
+    double *s = malloc((size_t)n * sizeof(double));
+    double *t = malloc((size_t)n * sizeof(double));
+    double *dinv = malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+            if (A->col[k] == i) d = A->val[k];
+        dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+    }
+    double bnorm = sqrt(oc_dot(n, b, b));
+    int64_t it = 0;
+    *status = 1;
+    for (int restart = 0; restart < 50; ++restart) {
+        oc_csr_matvec(A, x, t);
+        if (restart > 0) ++it;
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+        double rn = sqrt(oc_dot(n, r, r));
+        *relres = bnorm > 0.0 ? rn / bnorm : 0.0;
+        if (!(rn == rn)) {
+            *status = -5;
+            break;
+        }
+        if (rn <= rtol * bnorm) {
+            *status = 0;
+            break;
+        }
+        if (it >= max_iter) break;
+        memcpy(rh, r, (size_t)n * sizeof(double));
+        memset(p, 0, (size_t)n * sizeof(double));
+        memset(v, 0, (size_t)n * sizeof(double));
+        double rho = 1.0, alpha = 1.0, omega = 1.0;
+        int bad = 0;
+        while (it < max_iter) {
+            double rho_new = oc_dot(n, rh, r);
+            if (rho_new == 0.0 || !(rho_new == rho_new)) {
+                bad = 1;
+                break;
+            }
+            double beta = (rho_new / rho) * (alpha / omega);
+            rho = rho_new;
+            for (int64_t i = 0; i < n; ++i) {
+                p[i] = r[i] + beta * (p[i] - omega * v[i]);
+                y[i] = dinv[i] * p[i];
+            }
+            oc_csr_matvec(A, y, v);
+            ++it;
+            double rv = oc_dot(n, rh, v);
+            if (rv == 0.0) {
+                bad = 1;
+                break;
+            }
+            alpha = rho / rv;
+            for (int64_t i = 0; i < n; ++i) {
+                x[i] += alpha * y[i];
+                s[i] = r[i] - alpha * v[i];
+                z[i] = dinv[i] * s[i];
+            }
+            if (sqrt(oc_dot(n, s, s)) <= rtol * bnorm) break;
+            oc_csr_matvec(A, z, t);
+            ++it;
+            double tt = oc_dot(n, t, t);
+            if (tt == 0.0) {
+                bad = 1;
+                break;
+            }
+            omega = oc_dot(n, t, s) / tt;
+            for (int64_t i = 0; i < n; ++i) {
+                x[i] += omega * z[i];
+                r[i] = s[i] - omega * t[i];
+            }
+            if (sqrt(oc_dot(n, r, r)) <= rtol * bnorm) break;
+            if (omega == 0.0) {
+                bad = 1;
+                break;
+            }
+        }
+        if (bad && restart == 49) *status = -5;
+    }
+    free(r);
+    free(rh);
+    free(p);
+    free(v);
+    free(y);
+    free(z);
+    free(s);
+    free(t);
+    free(dinv);
+    return it;
+}
+
+/* `steps` time steps of eq. weak_transport from phi_in: each solves
+ * L phi' = R phi with L, R from oc_assemble_transport (the same for every
+ * step), starting from phi.  iters: total operator applications.  Returns 0,
+ * -1 for a degenerate element, -5 if a solve broke down or did not converge. */
+int oc_transport(int dim, int64_t N, int64_t E, const double *coords, const int32_t *conn,
+                 const double *theta, double h2, int smooth, double dt, int steps, double rtol,
+                 int64_t max_iter, const double *phi_in, double *phi_out, int64_t *iters)
+{
+    oc_csr *L = oc_assemble_transport(dim, N, E, coords, conn, theta, h2, smooth, dt, 1.0);
+    oc_csr *R = oc_assemble_transport(dim, N, E, coords, conn, theta, h2, smooth, dt, -1.0);
+    if (!L || !R) {
+        oc_csr_free(L);
+        oc_csr_free(R);
+        return -1;
+    }
+    double *b = malloc((size_t)(N ? N : 1) * sizeof(double));
+    memcpy(phi_out, phi_in, (size_t)N * sizeof(double));
+    int rc = 0;
+    *iters = 0;
+    for (int k = 0; k < steps && rc == 0; ++k) {
+        oc_csr_matvec(R, phi_out, b);
+        double rr;
+        int st;
+        *iters += oc_bicgstab(L, b, phi_out, rtol, max_iter, &rr, &st);
+        if (st != 0) rc = -5;
+    }
+    free(b);
+    oc_csr_free(L);
+    oc_csr_free(R);
+    return rc;
 }
 
 /* Element measures and barycentric gradients, exported for tests. */

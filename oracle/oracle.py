@@ -73,6 +73,16 @@ def lib():
         L.oc_levelset_update.argtypes = [C.c_int, _i64, _i64, _dp, _ip32, _dp, C.c_double, _dp,
                                          _dp]
         L.oc_levelset_update.restype = C.c_int
+        L.oc_transport_h2.argtypes = [C.c_int, _i64, _dp, _ip32]
+        L.oc_transport_h2.restype = C.c_double
+        L.oc_assemble_transport.argtypes = [C.c_int, _i64, _i64, _dp, _ip32, _dp, C.c_double, C.c_int,
+                                            C.c_double, C.c_double]
+        L.oc_assemble_transport.restype = C.c_void_p
+        L.oc_bicgstab.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _i64, _dp, C.POINTER(C.c_int)]
+        L.oc_bicgstab.restype = _i64
+        L.oc_transport.argtypes = [C.c_int, _i64, _i64, _dp, _ip32, _dp, C.c_double, C.c_int, C.c_double,
+                                   C.c_int, C.c_double, _i64, _dp, _dp, C.POINTER(_i64)]
+        L.oc_transport.restype = C.c_int
         L.oc_element_geometry.argtypes = [C.c_int, _i64, _dp, _ip32, _dp, _dp]
         L.oc_element_geometry.restype = C.c_int
         L.oc_set_threads.argtypes = [C.c_int]
@@ -236,6 +246,53 @@ def levelset_update(dim, coords, conn, theta, dt, phi):
     if rc:
         raise ValueError("degenerate element")
     return out
+
+
+def transport_h2(dim, coords, conn) -> float:
+    """h^2 of the transport diffusion: the paper's mesh-diameter expression
+    (Section "Transport equation"), read as h^2."""
+    coords, conn = _c64(coords), _c32(conn)
+    return float(lib().oc_transport_h2(dim, conn.shape[1], _d(coords), conn.ctypes.data_as(_ip32)))
+
+
+def assemble_transport(dim, coords, conn, theta, h2, smooth, dt, sign) -> CSR:
+    """Step matrix of eq. weak_transport: sign +1 left-hand side L, -1
+    right-hand side R (see fo_oracle.c)."""
+    coords, conn = _c64(coords), _c32(conn)
+    N, E = coords.shape[0], conn.shape[1]
+    return CSR(lib().oc_assemble_transport(dim, N, E, _d(coords), conn.ctypes.data_as(_ip32),
+                                           _d(_c64(theta)), float(h2), int(bool(smooth)), float(dt),
+                                           float(sign)))
+
+
+def bicgstab(A: CSR, b, x0=None, rtol=1e-12, max_iter=100_000):
+    """Jacobi-preconditioned BiCGStab on an oracle matrix from x0 (default 0)."""
+    b = _c64(b)
+    x = np.zeros(A.n) if x0 is None else _c64(x0).copy()
+    rr = C.c_double()
+    st = C.c_int()
+    it = lib().oc_bicgstab(A.h, _d(b), _d(x), float(rtol), int(max_iter), C.byref(rr), C.byref(st))
+    return x, SolveInfo(int(it), rr.value, st.value)
+
+
+def transport(dim, coords, conn, theta, dt, steps, phi, smooth=True, h2=None, rtol=1e-12,
+              max_iter=100_000):
+    """`steps` Crank-Nicolson Petrov-Galerkin steps of eq. weak_transport;
+    returns (phi_new, operator applications)."""
+    coords, conn = _c64(coords), _c32(conn)
+    N, E = coords.shape[0], conn.shape[1]
+    if h2 is None:
+        h2 = transport_h2(dim, coords, conn)
+    out = np.empty(N)
+    its = _i64()
+    rc = lib().oc_transport(dim, N, E, _d(coords), conn.ctypes.data_as(_ip32), _d(_c64(theta)),
+                            float(h2), int(bool(smooth)), float(dt), int(steps), float(rtol),
+                            int(max_iter), _d(_c64(phi)), _d(out), C.byref(its))
+    if rc == -1:
+        raise ValueError("degenerate element")
+    if rc:
+        raise RuntimeError("transport solve did not converge")
+    return out, int(its.value)
 
 
 # ----------------------------------------------------------------------------
