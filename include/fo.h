@@ -180,6 +180,26 @@ int fo_apply_descent(fo_ctx *ctx, const fo_descent_opts *dopts, const double *x,
  * theta: device [n_dofs]. */
 int fo_levelset_update(fo_ctx *ctx, const double *theta, double dt, double *phi);
 
+/* The paper's transport step of the level set (Section "Transport
+ * equation", eqs. transport, weak_transport, tau_lv): `steps` Crank-Nicolson
+ * steps of length dt (> 0) of d/dt phi + theta . grad phi = h^2 lap phi
+ * (Neumann) with Petrov-Galerkin test functions psi + tau theta . grad psi,
+ * tau = (1/2)(dt^-2 + |theta|^2/h^2)^(-1/2); theta and tau are taken per
+ * element at the element mean of theta.  smooth != 0 adds the h^2 diffusion,
+ * h^2 being the paper's mesh-size expression (4|D|/(N_T sqrt 3) in 2D,
+ * (6 sqrt 2 |D|/N_T)^(2/3) in 3D).  Each step solves its nonsymmetric system
+ * by Jacobi-preconditioned BiCGStab in FP64 from the previous phi until the
+ * recomputed residual is <= opts->rtol times the right-hand side
+ * (opts->max_iter operator applications per step; precision ignored).
+ * theta: device [n_dofs] (e.g. from fo_descent_solve); phi: device
+ * [n_nodes], in: phi(t), out: phi(t + steps dt).  stats (host, may be NULL):
+ * iters_inner = operator applications, iters_outer = steps, rel_res = the
+ * largest accepted relative residual.  Requires the tiled scatter.  Returns
+ * FO_OK, FO_NOT_CONVERGED (phi holds the last iterate), FO_ERR_BREAKDOWN,
+ * FO_ERR_STATE (atomic scatter) or FO_ERR_ARG. */
+int fo_transport(fo_ctx *ctx, const double *theta, double dt, int32_t steps, int32_t smooth, double *phi,
+                 const fo_solve_opts *opts, fo_solve_stats *stats);
+
 /* Kernel timing for measurement tools.  While enabled, every launch of the
  * kernels named below is bracketed by a pair of HIP events recorded on the
  * context's stream; fo_profile_read synchronises the stream and returns the

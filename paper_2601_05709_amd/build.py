@@ -19,8 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfo.so")
 ARCH = os.environ.get("FO_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fo_api.hip", "fo_kernels.hip", "fo_tiled.hip", "fo_cg.hip", "fo_batch.hip", "fo_pool.cpp",
-           "fo_tiles.cpp"]
+SOURCES = ["fo_api.hip", "fo_kernels.hip", "fo_tiled.hip", "fo_cg.hip", "fo_batch.hip", "fo_transport.hip",
+           "fo_pool.cpp", "fo_tiles.cpp"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -733,6 +733,17 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         for (int64_t e = 0; e < E; ++e)
             conn_t[(size_t)a * E + e] = m->conn[(int64_t)a * E + ht.perm[e]];
 
+    // h^2 of the transport diffusion: the paper's mesh-size expression
+    // (Section "Transport equation"), 4|D|/(N_T sqrt 3) in 2D and
+    // (6 sqrt 2 |D|/N_T)^(2/3) in 3D, which is the squared edge of N_T
+    // equilateral triangles / regular tetrahedra filling D; |D| = sum of |T|
+    {
+        double area = 0.0;
+        for (int64_t e = 0; e < E; ++e) area += std::fabs(host_det(D, m->coords, m->conn, E, e));
+        area /= (D == 2 ? 2.0 : 6.0);
+        c->transport_h2 = D == 2 ? 4.0 * area / ((double)E * std::sqrt(3.0))
+                                 : std::pow(6.0 * std::sqrt(2.0) * area / (double)E, 2.0 / 3.0);
+    }
     std::vector<float> c32((size_t)N * D);
     for (int64_t i = 0; i < N * D; ++i) c32[i] = (float)m->coords[i];
     std::vector<uint8_t> fx((size_t)N * D, 0);

@@ -224,6 +224,11 @@ struct fo_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[FO_PROF_COUNT];
     size_t prof_used[FO_PROF_COUNT] = {0, 0, 0, 0};
 
+    // transport step: h^2 of the diffusion term (the paper's mesh-size
+    // expression) and the work buffers, allocated on the first call
+    double transport_h2 = 0.0;
+    void *tr_buf = nullptr;
+
     // batched multi-load solves (allocated when max_rhs > 1)
     fo::BatchState batch;
 

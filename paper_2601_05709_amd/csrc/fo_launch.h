@@ -53,6 +53,13 @@ void launch_cgn_start(const fo_ctx *c, const T *b, const T *q, T *r, const T *di
 template <typename T>
 void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *q, const T *dinv,
                        hipStream_t s);
+// Transport step matrix of the level set (TransportOp): y = (L or R) x with
+// sdt = +dt or -dt; the diagonal of L.  coef: [E][4] element theta and tau.
+int launch_transport_apply(const fo_ctx *c, const double *coef, double sdt, double h2, const double *x,
+                           double *y, hipStream_t s);
+int launch_transport_diag(const fo_ctx *c, const double *coef, double dt, double h2, double *diag,
+                          hipStream_t s);
+
 // Operator of the fused CG kernels.
 enum FusedKind { FUSED_ELAS = 0, FUSED_DESCENT = 1 };
 template <typename T>

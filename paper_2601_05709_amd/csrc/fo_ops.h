@@ -130,4 +130,113 @@ struct SdRhsOp {
     }
 };
 
+// Transport step of the level set (Section "Transport equation", eqs.
+// weak_transport, tau_lv): the Crank-Nicolson Petrov-Galerkin step matrix
+// applied to a nodal scalar.  Per element the velocity theta and tau are the
+// element-mean values (coef); with g_a the hat-function gradients, |T| the
+// measure, grad x = sum_b x_b g_b and s = sum_b x_b, row a is
+//   |T| [ (x_a + s) / ((d+1)(d+2))                        mass
+//       + tau (theta.g_a) s / (d+1)                        stabilised mass
+//       + sdt ( (theta.grad x) / (2 (d+1))                  advection
+//             + tau (theta.g_a) (theta.grad x) / 2          stabilised advection
+//             + h2 (g_a . grad x) / 2 ) ]                   diffusion
+// sdt = +dt gives the left-hand side L, -dt the right-hand side R.
+template <int D>
+struct TransportOp {
+    static constexpr int NX = 1, NV = 1;
+    struct Elem {
+        double th[D];
+        double tau;
+    };
+    const double *coef;  // [E][4] element-mean theta (D values) and tau, tile element order
+    double sdt;          // +dt or -dt
+    double h2;           // diffusion coefficient, 0 without diffusion
+    __device__ Elem load(int64_t e) const
+    {
+        Elem v;
+#pragma unroll
+        for (int i = 0; i < D; ++i) v.th[i] = coef[e * 4 + i];
+        v.tau = coef[e * 4 + 3];
+        return v;
+    }
+    __device__ void operator()(const Elem &in, const double *const *X, const double *const *U,
+                               double out[D + 1][1]) const
+    {
+        const Geom<D, double> g = geom<D, double>(X);
+        const double inv = 1.0 / g.det;
+        const double vol = fabs(g.det) / (D == 2 ? 2.0 : 6.0);
+        double ga[D + 1][D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            ga[0][j] = 0.0;
+#pragma unroll
+            for (int a = 1; a <= D; ++a) {
+                ga[a][j] = g.c[a - 1][j] * inv;
+                ga[0][j] -= ga[a][j];
+            }
+        }
+        double sx = 0.0, gx[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) gx[j] = 0.0;
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            sx += U[a][0];
+#pragma unroll
+            for (int j = 0; j < D; ++j) gx[j] += U[a][0] * ga[a][j];
+        }
+        double tgx = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) tgx += in.th[j] * gx[j];
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double tg = 0.0, ggx = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                tg += in.th[j] * ga[a][j];
+                ggx += ga[a][j] * gx[j];
+            }
+            out[a][0] = vol * ((U[a][0] + sx) / ((D + 1) * (D + 2)) + in.tau * tg * sx / (D + 1) +
+                               sdt * (0.5 * tgx / (D + 1) + 0.5 * in.tau * tg * tgx + 0.5 * h2 * ggx));
+        }
+    }
+};
+
+// Diagonal of the transport left-hand side L (TransportOp with sdt = dt).
+template <int D>
+struct TransportDiagOp {
+    static constexpr int NX = 0, NV = 1;
+    using Elem = typename TransportOp<D>::Elem;
+    const double *coef;
+    double dt, h2;
+    __device__ Elem load(int64_t e) const { return TransportOp<D>{coef, dt, h2}.load(e); }
+    __device__ void operator()(const Elem &in, const double *const *X, const double *const *,
+                               double out[D + 1][1]) const
+    {
+        const Geom<D, double> g = geom<D, double>(X);
+        const double inv = 1.0 / g.det;
+        const double vol = fabs(g.det) / (D == 2 ? 2.0 : 6.0);
+        double ga[D + 1][D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            ga[0][j] = 0.0;
+#pragma unroll
+            for (int a = 1; a <= D; ++a) {
+                ga[a][j] = g.c[a - 1][j] * inv;
+                ga[0][j] -= ga[a][j];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double tg = 0.0, gg = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                tg += in.th[j] * ga[a][j];
+                gg += ga[a][j] * ga[a][j];
+            }
+            out[a][0] = vol * (2.0 / ((D + 1) * (D + 2)) + in.tau * tg / (D + 1) +
+                               dt * (0.5 * tg / (D + 1) + 0.5 * in.tau * tg * tg + 0.5 * h2 * gg));
+        }
+    }
+};
+
 }  // namespace fo

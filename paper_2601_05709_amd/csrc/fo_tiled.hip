@@ -551,7 +551,8 @@ static int prepare_dim()
            ensure_lds_attr<D, double, PhiGradOp<D>>() | ensure_lds_attr_cg<D, double, ElasOp<D, double>>() |
            ensure_lds_attr_cg<D, float, ElasOp<D, float>>() |
            ensure_lds_attr_cg<D, double, DescentOp<D, double>>() |
-           ensure_lds_attr_cg<D, float, DescentOp<D, float>>();
+           ensure_lds_attr_cg<D, float, DescentOp<D, float>>() | ensure_lds_attr<D, double, TransportOp<D>>() |
+           ensure_lds_attr<D, double, TransportDiagOp<D>>();
 }
 
 int tiled_prepare(const fo_ctx *c)
@@ -805,6 +806,26 @@ int launch_descent_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s)
     if (rc) return rc;
     facet_terms(c, nullptr, diag, s);
     return FO_OK;
+}
+
+int launch_transport_apply(const fo_ctx *c, const double *coef, double sdt, double h2, const double *x,
+                           double *y, hipStream_t s)
+{
+    if (c->has_isolated) launch_fill<double>(y, c->N, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, TransportOp<2>{coef, sdt, h2}, c->coords, x, y, nullptr, s);
+    return run_tiled<3, double>(c, TransportOp<3>{coef, sdt, h2}, c->coords, x, y, nullptr, s);
+}
+
+int launch_transport_diag(const fo_ctx *c, const double *coef, double dt, double h2, double *diag,
+                          hipStream_t s)
+{
+    launch_fill<double>(diag, c->N, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, TransportDiagOp<2>{coef, dt, h2}, c->coords, (const double *)nullptr,
+                                    diag, nullptr, s);
+    return run_tiled<3, double>(c, TransportDiagOp<3>{coef, dt, h2}, c->coords, (const double *)nullptr,
+                                diag, nullptr, s);
 }
 
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s)

@@ -86,6 +86,8 @@ EXPORTS = {
                           C.POINTER(fo_solve_stats), _vp], C.c_int),
     "fo_apply_descent": ([_vp, C.POINTER(fo_descent_opts), _vp, _vp], C.c_int),
     "fo_levelset_update": ([_vp, _vp, C.c_double, _vp], C.c_int),
+    "fo_transport": ([_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.POINTER(fo_solve_opts),
+                      C.POINTER(fo_solve_stats)], C.c_int),
     "fo_profile_enable": ([_vp, C.c_int32], C.c_int),
     "fo_profile_read": ([_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "fo_time_kernel": ([_vp, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
@@ -344,6 +346,20 @@ class Context:
         import torch
         _check(lib().fo_apply_descent(self.h, C.byref(dopts.c()), _ptr(x, torch.float64, self.n_dofs, "x"),
                                       _ptr(y, torch.float64, self.n_dofs, "y")), "fo_apply_descent")
+
+    def transport(self, theta, dt: float, steps: int, phi, opts: Optional[SolveOpts] = None,
+                  smooth: bool = True, allow_not_converged=False) -> Stats:
+        """The paper's transport step: `steps` Crank-Nicolson Petrov-Galerkin
+        steps of length dt (fo_transport); phi is updated in place."""
+        import torch
+        opts = opts or SolveOpts(rtol=1e-10)
+        st = fo_solve_stats()
+        allow = (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,)
+        rc = lib().fo_transport(self.h, _ptr(theta, torch.float64, self.n_dofs, "theta"), float(dt), int(steps),
+                                int(bool(smooth)), _ptr(phi, torch.float64, self.n_nodes, "phi"),
+                                C.byref(opts.c()), C.byref(st))
+        _check(rc, "fo_transport", allow)
+        return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
 
     def levelset_update(self, theta, dt: float, phi):
         import torch
