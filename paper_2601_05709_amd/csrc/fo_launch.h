@@ -53,12 +53,13 @@ void launch_cgn_start(const fo_ctx *c, const T *b, const T *q, T *r, const T *di
 template <typename T>
 void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *q, const T *dinv,
                        hipStream_t s);
-// Transport step matrix of the level set (TransportOp): y = (L or R) x with
-// sdt = +dt or -dt; the diagonal of L.  coef: [E][4] element theta and tau.
-int launch_transport_apply(const fo_ctx *c, const double *coef, double sdt, double h2, const double *x,
-                           double *y, hipStream_t s);
-int launch_transport_diag(const fo_ctx *c, const double *coef, double dt, double h2, double *diag,
-                          hipStream_t s);
+// Transport step matrix of the level set (TransportOp): y = L x (which 0)
+// or R x (which 1); the diagonal of L.  theta: device [N][D] nodal velocity;
+// par: device [5] dt, -dt, h2 of the diffusion (0: none), h2 of tau, 1/dt^2.
+// done (nullable): device flag that turns the launch into a no-op.
+int launch_transport_apply(const fo_ctx *c, const double *theta, const double *par, int which, const double *x,
+                           double *y, hipStream_t s, const int32_t *done = nullptr);
+int launch_transport_diag(const fo_ctx *c, const double *theta, const double *par, double *diag, hipStream_t s);
 
 // Operator of the fused CG kernels.
 enum FusedKind { FUSED_ELAS = 0, FUSED_DESCENT = 1 };

@@ -141,27 +141,48 @@ struct SdRhsOp {
 //             + tau (theta.g_a) (theta.grad x) / 2          stabilised advection
 //             + h2 (g_a . grad x) / 2 ) ]                   diffusion
 // sdt = +dt gives the left-hand side L, -dt the right-hand side R.
+// Element-mean velocity and tau = (1/2) (dt^-2 + |theta|^2 / h^2)^(-1/2) of
+// the Petrov-Galerkin test functions (eq. tau_lv), from the tile-staged nodal
+// velocity A[a][0..D).
+template <int D>
+__device__ __forceinline__ double transport_tau(const double *const *A, double rdt2, double h2, double th[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) th[i] = 0.0;
+#pragma unroll
+    for (int a = 0; a <= D; ++a)
+#pragma unroll
+        for (int i = 0; i < D; ++i) th[i] += A[a][i];
+    double t2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        th[i] /= (double)(D + 1);
+        t2 += th[i] * th[i];
+    }
+    return 0.5 / sqrt(rdt2 + t2 / h2);
+}
+
+// Transport step matrices (eq. weak_transport): y = L x (which 0) or R x
+// (which 1).  The nodal velocity is staged per tile (aux, NA values per
+// node) and the step parameters come from device memory (par: [0] dt, [1]
+// -dt, [2] h2 of the diffusion, 0 without it, [3] h2 of tau, [4] 1 / dt^2),
+// so one captured graph of the solver serves every call.
 template <int D>
 struct TransportOp {
-    static constexpr int NX = 1, NV = 1;
+    static constexpr int NX = 1, NV = 1, NA = D;
     struct Elem {
-        double th[D];
-        double tau;
+        double sdt, h2e, rdt2, h2;
     };
-    const double *coef;  // [E][4] element-mean theta (D values) and tau, tile element order
-    double sdt;          // +dt or -dt
-    double h2;           // diffusion coefficient, 0 without diffusion
-    __device__ Elem load(int64_t e) const
-    {
-        Elem v;
-#pragma unroll
-        for (int i = 0; i < D; ++i) v.th[i] = coef[e * 4 + i];
-        v.tau = coef[e * 4 + 3];
-        return v;
-    }
+    const double *aux;  // [N][D] nodal velocity theta
+    const double *par;
+    int which;
+    __device__ Elem load(int64_t) const { return Elem{par[which], par[2], par[4], par[3]}; }
     __device__ void operator()(const Elem &in, const double *const *X, const double *const *U,
-                               double out[D + 1][1]) const
+                               const double *const *A, double out[D + 1][1]) const
     {
+        const double sdt = in.sdt, h2 = in.h2e;
+        double th[D];
+        const double tau = transport_tau<D>(A, in.rdt2, in.h2, th);
         const Geom<D, double> g = geom<D, double>(X);
         const double inv = 1.0 / g.det;
         const double vol = fabs(g.det) / (D == 2 ? 2.0 : 6.0);
@@ -186,32 +207,35 @@ struct TransportOp {
         }
         double tgx = 0.0;
 #pragma unroll
-        for (int j = 0; j < D; ++j) tgx += in.th[j] * gx[j];
+        for (int j = 0; j < D; ++j) tgx += th[j] * gx[j];
 #pragma unroll
         for (int a = 0; a <= D; ++a) {
             double tg = 0.0, ggx = 0.0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                tg += in.th[j] * ga[a][j];
+                tg += th[j] * ga[a][j];
                 ggx += ga[a][j] * gx[j];
             }
-            out[a][0] = vol * ((U[a][0] + sx) / ((D + 1) * (D + 2)) + in.tau * tg * sx / (D + 1) +
-                               sdt * (0.5 * tgx / (D + 1) + 0.5 * in.tau * tg * tgx + 0.5 * h2 * ggx));
+            out[a][0] = vol * ((U[a][0] + sx) / ((D + 1) * (D + 2)) + tau * tg * sx / (D + 1) +
+                               sdt * (0.5 * tgx / (D + 1) + 0.5 * tau * tg * tgx + 0.5 * h2 * ggx));
         }
     }
 };
 
-// Diagonal of the transport left-hand side L (TransportOp with sdt = dt).
+// Diagonal of the transport left-hand side L.
 template <int D>
 struct TransportDiagOp {
-    static constexpr int NX = 0, NV = 1;
+    static constexpr int NX = 0, NV = 1, NA = D;
     using Elem = typename TransportOp<D>::Elem;
-    const double *coef;
-    double dt, h2;
-    __device__ Elem load(int64_t e) const { return TransportOp<D>{coef, dt, h2}.load(e); }
+    const double *aux;
+    const double *par;
+    __device__ Elem load(int64_t e) const { return TransportOp<D>{aux, par, 0}.load(e); }
     __device__ void operator()(const Elem &in, const double *const *X, const double *const *,
-                               double out[D + 1][1]) const
+                               const double *const *A, double out[D + 1][1]) const
     {
+        const double dt = in.sdt, h2 = in.h2e;
+        double th[D];
+        const double tau = transport_tau<D>(A, in.rdt2, in.h2, th);
         const Geom<D, double> g = geom<D, double>(X);
         const double inv = 1.0 / g.det;
         const double vol = fabs(g.det) / (D == 2 ? 2.0 : 6.0);
@@ -230,11 +254,11 @@ struct TransportDiagOp {
             double tg = 0.0, gg = 0.0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                tg += in.th[j] * ga[a][j];
+                tg += th[j] * ga[a][j];
                 gg += ga[a][j] * ga[a][j];
             }
-            out[a][0] = vol * (2.0 / ((D + 1) * (D + 2)) + in.tau * tg / (D + 1) +
-                               dt * (0.5 * tg / (D + 1) + 0.5 * in.tau * tg * tg + 0.5 * h2 * gg));
+            out[a][0] = vol * (2.0 / ((D + 1) * (D + 2)) + tau * tg / (D + 1) +
+                               dt * (0.5 * tg / (D + 1) + 0.5 * tau * tg * tg + 0.5 * h2 * gg));
         }
     }
 };

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "fo_element.h"
 #include "fo_internal.h"
@@ -35,23 +36,39 @@ static TileArgs tile_args(const fo_ctx *c)
 }
 
 
+// Nodal values an operator stages per tile besides the coordinates and its
+// input (Op::NA values per node from op.aux; none unless the Op says so).
+template <class Op, class = void>
+struct OpAux {
+    static constexpr int NA = 0;
+};
+template <class Op>
+struct OpAux<Op, std::void_t<decltype(Op::NA)>> {
+    static constexpr int NA = Op::NA;
+};
+
 // Element phase shared by the tile kernels: thread = element of the tile;
 // writes its (d+1) x NV vertex values into the node-sorted LDS slots.
 template <int D, typename T, class Op>
 __device__ __forceinline__ void tile_elements(const Op &op, typename Op::Elem ed, uint64_t lc,
-                                              uint64_t ls, const T *sX, const T *sU, T *sS)
+                                              uint64_t ls, const T *sX, const T *sU, const T *sA, T *sS)
 {
-    constexpr int NX = Op::NX, NV = Op::NV;
+    constexpr int NX = Op::NX, NV = Op::NV, NA = OpAux<Op>::NA;
     const T *Xp[D + 1];
     const T *Up[D + 1];
+    const T *Ap[D + 1];
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
         int l = (int)((lc >> (16 * a)) & 0xFFFF);
         Xp[a] = sX + l * D;
         Up[a] = sU + l * NX;
+        Ap[a] = sA + l * NA;
     }
     T res[D + 1][NV];
-    op(ed, Xp, Up, res);
+    if constexpr (NA > 0)
+        op(ed, Xp, Up, Ap, res);
+    else
+        op(ed, Xp, Up, res);
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
         int sl = (int)((ls >> (16 * a)) & 0xFFFF);
@@ -77,7 +94,7 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
                                                      double *__restrict__ dot_part,
                                                      const int32_t *__restrict__ done)
 {
-    constexpr int NX = Op::NX, NV = Op::NV;
+    constexpr int NX = Op::NX, NV = Op::NV, NA = OpAux<Op>::NA;
     using Elem = typename Op::Elem;
     if (done && *done) return;
     const int t = xcd_tile(blockIdx.x, ta.n_tiles);
@@ -89,7 +106,8 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
     const int e0 = inf[kTileE0], ne = inf[kTileNE], nn = inf[kTileNN], nint = inf[kTileNInt];
     T *sX = smem;
     T *sU = sX + nn * D;
-    T *sS = sU + nn * NX;
+    T *sA = sU + nn * NX;
+    T *sS = sA + nn * NA;
 
     uint64_t lc = 0, ls = 0;
     Elem ed{};
@@ -119,9 +137,16 @@ __global__ __launch_bounds__(1024) void k_tile_apply(Op op, TileArgs ta,
         for (int q = 0; q < D; ++q) sX[tid * D + q] = xv[q];
 #pragma unroll
         for (int k = 0; k < NX; ++k) sU[tid * NX + k] = uv[k];
+        if constexpr (NA > 0) {
+            T av[NA];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) av[k] = op.aux[g * NA + k];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) sA[tid * NA + k] = av[k];
+        }
     }
     __syncthreads();
-    if (tid < ne) tile_elements<D, T, Op>(op, ed, lc, ls, sX, sU, sS);
+    if (tid < ne) tile_elements<D, T, Op>(op, ed, lc, ls, sX, sU, sA, sS);
     __syncthreads();
     double dsum = 0.0;
     if (tid < nn) {
@@ -525,7 +550,7 @@ static int ensure_lds_attr()
 {
     static std::atomic<bool> done{false};
     if (done.load(std::memory_order_acquire)) return 0;
-    size_t cap = tile_lds_bytes<D, T, Op::NX, Op::NV>(tile_max_nodes(D), tile_max_elems(D));
+    size_t cap = tile_lds_bytes<D, T, Op::NX + OpAux<Op>::NA, Op::NV>(tile_max_nodes(D), tile_max_elems(D));
     if (set_lds((const void *)k_tile_apply<D, T, Op>, cap)) return 1;
     done.store(true, std::memory_order_release);
     return 0;
@@ -587,7 +612,7 @@ static int run_tiled(const fo_ctx *c, const Op &op, const T *coords, const T *xi
                      double *dot_part = nullptr, const int32_t *done = nullptr,
                      bool skip_halo = false)
 {
-    size_t lds = tile_lds_bytes<D, T, Op::NX, Op::NV>(c->tiles.max_nodes, c->tiles.max_elems);
+    size_t lds = tile_lds_bytes<D, T, Op::NX + OpAux<Op>::NA, Op::NV>(c->tiles.max_nodes, c->tiles.max_elems);
     if (ensure_lds_attr<D, T, Op>()) return FO_ERR_HIP;
     auto *pt = prof_slot(c, prof_tile);
     if (pt) (void)hipEventRecord(pt->first, s);
@@ -808,24 +833,25 @@ int launch_descent_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s)
     return FO_OK;
 }
 
-int launch_transport_apply(const fo_ctx *c, const double *coef, double sdt, double h2, const double *x,
-                           double *y, hipStream_t s)
+int launch_transport_apply(const fo_ctx *c, const double *theta, const double *par, int which, const double *x,
+                           double *y, hipStream_t s, const int32_t *done)
 {
     if (c->has_isolated) launch_fill<double>(y, c->N, 0.0, s);
     if (c->dim == 2)
-        return run_tiled<2, double>(c, TransportOp<2>{coef, sdt, h2}, c->coords, x, y, nullptr, s);
-    return run_tiled<3, double>(c, TransportOp<3>{coef, sdt, h2}, c->coords, x, y, nullptr, s);
+        return run_tiled<2, double>(c, TransportOp<2>{theta, par, which}, c->coords, x, y, nullptr, s, -1, -1,
+                                    nullptr, done);
+    return run_tiled<3, double>(c, TransportOp<3>{theta, par, which}, c->coords, x, y, nullptr, s, -1, -1,
+                                nullptr, done);
 }
 
-int launch_transport_diag(const fo_ctx *c, const double *coef, double dt, double h2, double *diag,
-                          hipStream_t s)
+int launch_transport_diag(const fo_ctx *c, const double *theta, const double *par, double *diag, hipStream_t s)
 {
     launch_fill<double>(diag, c->N, 0.0, s);
     if (c->dim == 2)
-        return run_tiled<2, double>(c, TransportDiagOp<2>{coef, dt, h2}, c->coords, (const double *)nullptr,
-                                    diag, nullptr, s);
-    return run_tiled<3, double>(c, TransportDiagOp<3>{coef, dt, h2}, c->coords, (const double *)nullptr,
-                                diag, nullptr, s);
+        return run_tiled<2, double>(c, TransportDiagOp<2>{theta, par}, c->coords, (const double *)nullptr, diag,
+                                    nullptr, s);
+    return run_tiled<3, double>(c, TransportDiagOp<3>{theta, par}, c->coords, (const double *)nullptr, diag,
+                                nullptr, s);
 }
 
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s)

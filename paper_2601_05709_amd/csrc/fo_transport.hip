@@ -3,15 +3,21 @@
 // Petrov-Galerkin form with test functions psi + tau theta . grad psi and
 // optional h^2 diffusion.  Each step solves L phi' = R phi (L, R from
 // TransportOp with sdt = +dt / -dt, the same for every step) by
-// Jacobi-preconditioned BiCGStab in FP64, from phi, with the Krylov scalars
-// on the device.  The host polls the residual every few iterations and
-// checks the recomputed residual before it accepts a step.
+// Jacobi-preconditioned BiCGStab in FP64, from phi.  The Krylov scalars stay
+// on the device: every block of a vector kernel sums the dot-product
+// partials of the kernel before it in the same fixed order, so all blocks
+// take the same coefficients and the same stop decision, and a device stop
+// flag turns the rest of a launched chunk into no-ops.  Chunks of iterations
+// are replayed as graphs; the host reads the flag after each batch of chunks
+// (sized from the previous step's count) and checks the recomputed residual
+// b - L x before it accepts a step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <tuple>
 
 #include "fo_internal.h"
 #include "fo_launch.h"
@@ -21,107 +27,129 @@ namespace fo {
 
 namespace {
 
-// Device scalars of one BiCGStab solve.
+// Device state of one BiCGStab pass.  Each field is written by block 0 of one
+// kernel and read only by later kernels (rho_prev / rho_cur are separate so
+// that no kernel reads a field it writes); the flag only ever goes from 0 to
+// a stop code, and every block that sees it set would have set it itself.
 struct TrScal {
-    double rho, alpha, omega, beta;
-    double rho_new, rv, ts, tt, rr, bb;
-    int32_t bad;  // a division by zero or a non-finite coefficient: restart
+    double rho_prev, rho_cur, alpha, omega;
+    double bb;       // |b|^2
+    double target2;  // (rtol |b|)^2
+    double rr;       // |r|^2 at the last check
+    int32_t flag;    // TR_RUN or a stop code
+    int32_t its;     // operator applications of this pass
+    int32_t max_its; // applications allowed in this pass
     int32_t pad;
 };
 
-// Element-mean velocity and tau = (1/2) (dt^-2 + |theta|^2 / h^2)^(-1/2).
-template <int D>
-__global__ __launch_bounds__(256) void k_tr_coef(const int32_t *__restrict__ conn, int64_t E,
-                                                 const double *__restrict__ theta, double dt, double h2,
-                                                 double *__restrict__ coef)
+enum : int32_t { TR_RUN = 0, TR_CONVERGED = 1, TR_RESTART = 2, TR_LIMIT = 3, TR_NAN = 4 };
+
+// Step parameters of TransportOp: dt, -dt, h2 of the diffusion, h2 of tau,
+// 1 / dt^2.
+__global__ void k_tr_par(double *par, double dt, double h2e, double h2)
 {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        double th[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) th[i] = 0.0;
-#pragma unroll
-        for (int a = 0; a <= D; ++a) {
-            const int64_t node = conn[(int64_t)a * E + e];
-#pragma unroll
-            for (int i = 0; i < D; ++i) th[i] += theta[node * D + i];
+    par[0] = dt;
+    par[1] = -dt;
+    par[2] = h2e;
+    par[3] = h2;
+    par[4] = 1.0 / (dt * dt);
+}
+
+__device__ __forceinline__ bool fin(double x) { return x == x && x != INFINITY && x != -INFINITY; }
+
+// Sums of one or two partial arrays [nb], the same in every thread and block.
+__device__ __forceinline__ void sum_parts(const double *pa, const double *pb, int nb, double *bc, double &a,
+                                          double &b)
+{
+    if (threadIdx.x < 64) {
+        const double sa = wave0_sum_partials(pa, nb);
+        const double sb = pb ? wave0_sum_partials(pb, nb) : 0.0;
+        if (threadIdx.x == 0) {
+            bc[0] = sa;
+            bc[1] = sb;
         }
-        double t2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            th[i] /= (double)(D + 1);
-            t2 += th[i] * th[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) coef[e * 4 + i] = i < D ? th[i] : 0.0;
-        coef[e * 4 + 3] = 0.5 / sqrt(1.0 / (dt * dt) + t2 / h2);
+    }
+    __syncthreads();
+    a = bc[0];
+    b = bc[1];
+}
+
+// Block sums of two per-thread values into part[blockIdx.x], part[nb + blockIdx.x].
+__device__ __forceinline__ void put_parts(double a, double b, double *part, int nb, double *lds /*[32]*/)
+{
+    block_sum2_any(a, b, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[nb + blockIdx.x] = b;
     }
 }
 
-// r = b - t; rh = r; p = v = 0
-__global__ __launch_bounds__(256) void k_tr_start(const double *__restrict__ b, const double *__restrict__ t,
-                                                  double *__restrict__ r, double *__restrict__ rh,
-                                                  double *__restrict__ p, double *__restrict__ v, int64_t n)
+// r = b - t; rh = r; p = v = 0; partials r.r and rh.r (= r.r) into prr.
+__global__ __launch_bounds__(256) void k_trs_start(const double *__restrict__ b, const double *__restrict__ t,
+                                                   double *__restrict__ r, double *__restrict__ rh,
+                                                   double *__restrict__ p, double *__restrict__ v,
+                                                   double *__restrict__ prr, int nb, int64_t n)
 {
+    __shared__ double lds[32];
+    double rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double ri = b[i] - t[i];
         r[i] = ri;
         rh[i] = ri;
         p[i] = 0.0;
         v[i] = 0.0;
+        rr += ri * ri;
+    }
+    put_parts(rr, rr, prr, nb, lds);
+}
+
+// Start of a pass (one block of 64 threads): rho = alpha = omega = 1, the
+// residual |r|^2 from the start partials and the convergence test.
+__global__ __launch_bounds__(64) void k_trs_check(TrScal *sc, const double *__restrict__ prr, int nb, double rtol,
+                                                  int32_t max_its)
+{
+    const double rr = wave0_sum_partials(prr, nb);
+    if (threadIdx.x == 0) {
+        const double target2 = rtol * rtol * sc->bb;
+        sc->rho_prev = sc->alpha = sc->omega = 1.0;
+        sc->rho_cur = 0.0;
+        sc->rr = rr;
+        sc->target2 = target2;
+        sc->its = 0;
+        sc->max_its = max_its;
+        sc->flag = !fin(rr) ? TR_NAN : rr <= target2 ? TR_CONVERGED : TR_RUN;
     }
 }
 
-__global__ void k_tr_reset(TrScal *sc)
+// Iteration start: |r|^2 and rho = rh.r from prr; stop on convergence, the
+// iteration limit or a breakdown; else beta = (rho / rho_prev)(alpha / omega),
+// p = r + beta (p - omega v), y = D^-1 p.
+__global__ __launch_bounds__(256) void k_trs_p(TrScal *sc, const double *__restrict__ prr, int nb,
+                                               const double *__restrict__ r, double *__restrict__ p,
+                                               const double *__restrict__ v, const double *__restrict__ dinv,
+                                               double *__restrict__ y, int64_t n)
 {
-    sc->rho = sc->alpha = sc->omega = 1.0;
-    sc->bad = 0;
-}
-
-__device__ __forceinline__ bool fin(double x) { return x == x && x != INFINITY && x != -INFINITY; }
-
-// beta = (rho_new / rho) (alpha / omega); rho = rho_new
-__global__ void k_tr_beta(TrScal *sc)
-{
-    const double rn = sc->rho_new;
-    if (!(rn != 0.0) || !fin(rn) || sc->rho == 0.0 || sc->omega == 0.0) {
-        sc->bad = 1;
-        sc->beta = 0.0;
-        return;
+    __shared__ double bc[2];
+    if (sc->flag) return;
+    double rr, rho;
+    sum_parts(prr, prr + nb, nb, bc, rr, rho);
+    const double rho_prev = sc->rho_prev, alpha = sc->alpha, omega = sc->omega;
+    int32_t flag = TR_RUN;
+    if (!fin(rr))
+        flag = TR_NAN;
+    else if (rr <= sc->target2)
+        flag = TR_CONVERGED;
+    else if (sc->its >= sc->max_its)
+        flag = TR_LIMIT;
+    else if (!(rho != 0.0) || !fin(rho) || rho_prev == 0.0 || omega == 0.0)
+        flag = TR_RESTART;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rr = rr;
+        sc->rho_cur = rho;
+        if (flag) sc->flag = flag;
     }
-    sc->beta = (rn / sc->rho) * (sc->alpha / sc->omega);
-    sc->rho = rn;
-}
-
-__global__ void k_tr_alpha(TrScal *sc)
-{
-    if (sc->bad) return;
-    const double rv = sc->rv;
-    if (!(rv != 0.0) || !fin(rv)) {
-        sc->bad = 1;
-        return;
-    }
-    sc->alpha = sc->rho / rv;
-}
-
-__global__ void k_tr_omega(TrScal *sc)
-{
-    if (sc->bad) return;
-    const double tt = sc->tt;
-    if (!(tt > 0.0) || !fin(tt) || !fin(sc->ts)) {
-        sc->bad = 1;
-        return;
-    }
-    sc->omega = sc->ts / tt;
-}
-
-// p = r + beta (p - omega v); y = D^-1 p
-__global__ __launch_bounds__(256) void k_tr_p(const TrScal *sc, const double *__restrict__ r, double *__restrict__ p,
-                                              const double *__restrict__ v, const double *__restrict__ dinv,
-                                              double *__restrict__ y, int64_t n)
-{
-    if (sc->bad) return;
-    const double beta = sc->beta, omega = sc->omega;
+    if (flag) return;
+    const double beta = (rho / rho_prev) * (alpha / omega);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double pi = r[i] + beta * (p[i] - omega * v[i]);
         p[i] = pi;
@@ -129,14 +157,46 @@ __global__ __launch_bounds__(256) void k_tr_p(const TrScal *sc, const double *__
     }
 }
 
-// x += alpha y; s = r - alpha v; z = D^-1 s
-__global__ __launch_bounds__(256) void k_tr_s(const TrScal *sc, double *__restrict__ x, const double *__restrict__ y,
-                                              const double *__restrict__ r, const double *__restrict__ v,
-                                              const double *__restrict__ dinv, double *__restrict__ s,
-                                              double *__restrict__ z, int64_t n)
+// Partials of a0.b0 and a1.b1 (b1 == nullptr: the second is 0).
+__global__ __launch_bounds__(256) void k_trs_dot(const TrScal *sc, const double *__restrict__ a0,
+                                                 const double *__restrict__ b0, const double *__restrict__ a1,
+                                                 const double *__restrict__ b1, double *__restrict__ part,
+                                                 int nb, int64_t n)
 {
-    if (sc->bad) return;
-    const double alpha = sc->alpha;
+    __shared__ double lds[32];
+    if (sc->flag) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        s0 += a0[i] * b0[i];
+        if (b1) s1 += a1[i] * b1[i];
+    }
+    put_parts(s0, s1, part, nb, lds);
+}
+
+// alpha = rho / rh.v; x += alpha y; s = r - alpha v; z = D^-1 s.
+__global__ __launch_bounds__(256) void k_trs_s(TrScal *sc, const double *__restrict__ prv, int nb,
+                                               double *__restrict__ x, const double *__restrict__ y,
+                                               const double *__restrict__ r, const double *__restrict__ v,
+                                               const double *__restrict__ dinv, double *__restrict__ s,
+                                               double *__restrict__ z, int64_t n)
+{
+    __shared__ double bc[2];
+    if (sc->flag) return;
+    double rv, unused;
+    sum_parts(prv, nullptr, nb, bc, rv, unused);
+    const double rho = sc->rho_cur;
+    const bool bad = !(rv != 0.0) || !fin(rv);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->its += bad ? 1 : 2;
+        if (bad) {
+            sc->flag = TR_RESTART;
+        } else {
+            sc->alpha = rho / rv;
+            sc->rho_prev = rho;
+        }
+    }
+    if (bad) return;
+    const double alpha = rho / rv;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += alpha * y[i];
         const double si = r[i] - alpha * v[i];
@@ -145,20 +205,37 @@ __global__ __launch_bounds__(256) void k_tr_s(const TrScal *sc, double *__restri
     }
 }
 
-// x += omega z; r = s - omega t
-__global__ __launch_bounds__(256) void k_tr_xr(const TrScal *sc, double *__restrict__ x, const double *__restrict__ z,
-                                               const double *__restrict__ s, const double *__restrict__ t,
-                                               double *__restrict__ r, int64_t n)
+// omega = t.s / t.t; x += omega z; r = s - omega t; partials r.r and rh.r.
+__global__ __launch_bounds__(256) void k_trs_xr(TrScal *sc, const double *__restrict__ pts, int nb,
+                                                double *__restrict__ x, const double *__restrict__ z,
+                                                const double *__restrict__ s, const double *__restrict__ t,
+                                                double *__restrict__ r, const double *__restrict__ rh,
+                                                double *__restrict__ prr, int64_t n)
 {
-    if (sc->bad) return;
-    const double omega = sc->omega;
+    __shared__ double bc[2];
+    __shared__ double lds[32];
+    if (sc->flag) return;
+    double ts, tt;
+    sum_parts(pts, pts + nb, nb, bc, ts, tt);
+    const bool bad = !(tt > 0.0) || !fin(tt) || !fin(ts);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bad)
+            sc->flag = TR_RESTART;
+        else
+            sc->omega = ts / tt;
+    }
+    if (bad) return;
+    const double omega = ts / tt;
+    double rr = 0.0, rhr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += omega * z[i];
-        r[i] = s[i] - omega * t[i];
+        const double ri = s[i] - omega * t[i];
+        r[i] = ri;
+        rr += ri * ri;
+        rhr += rh[i] * ri;
     }
+    put_parts(rr, rhr, prr, nb, lds);
 }
-
-int blocks_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096); }
 
 }  // namespace
 
@@ -168,17 +245,20 @@ using namespace fo;
 
 namespace {
 
-// Transport work buffers of a context, allocated on first use.
+// Transport work buffers of a context, allocated on first use.  The
+// captured graphs hold these addresses, so the velocity is copied in.
 struct TrBufs {
-    double *coef, *b, *x, *r, *rh, *p, *v, *y, *s, *z, *t, *dinv;
+    double *theta, *par, *b, *x, *r, *rh, *p, *v, *y, *s, *z, *t, *dinv;
+    double *prr, *prv, *pts;  // partials [2 nb], [nb], [2 nb]
     TrScal *sc;
 };
 
 int tr_buffers(fo_ctx *c, TrBufs *o)
 {
+    const int64_t N = c->N;
+    const int64_t n_dbl = N * c->dim + 8 + 11 * N + 5 * (int64_t)kRedBlocks;
     if (!c->tr_buf) {
-        const int64_t N = c->N, E = c->E;
-        const size_t bytes = (size_t)(E * 4 + 11 * N) * sizeof(double) + 256;
+        const size_t bytes = (size_t)n_dbl * sizeof(double) + sizeof(TrScal) + 256;
         void *mem = nullptr;
         if (hipMalloc(&mem, bytes) != hipSuccess) return FO_ERR_NOMEM;
         c->tr_buf = mem;
@@ -186,15 +266,53 @@ int tr_buffers(fo_ctx *c, TrBufs *o)
         c->bytes += bytes;
     }
     double *m = reinterpret_cast<double *>(c->tr_buf);
-    const int64_t N = c->N;
-    o->coef = m;
-    m += c->E * 4;
+    o->theta = m;
+    m += N * c->dim;
+    o->par = m;
+    m += 8;
     double **vec[] = {&o->b, &o->x, &o->r, &o->rh, &o->p, &o->v, &o->y, &o->s, &o->z, &o->t, &o->dinv};
     for (double **q : vec) {
         *q = m;
         m += N;
     }
+    o->prr = m;
+    o->prv = m + 2 * kRedBlocks;
+    o->pts = m + 3 * kRedBlocks;
+    m += 5 * kRedBlocks;
     o->sc = reinterpret_cast<TrScal *>(m);
+    return FO_OK;
+}
+
+// Enqueues g BiCGStab iterations (each a no-op once the stop flag is set).
+int tr_iterations(const fo_ctx *c, const TrBufs &B, int g, hipStream_t s)
+{
+    const int64_t N = c->N;
+    const int nb = red_blocks(N);
+    const int32_t *stop = &B.sc->flag;
+    for (int k = 0; k < g; ++k) {
+        hipLaunchKernelGGL(k_trs_p, dim3(nb), dim3(kBlock), 0, s, B.sc, B.prr, nb, B.r, B.p, B.v, B.dinv, B.y, N);
+        FO_TRY(launch_transport_apply(c, B.theta, B.par, 0, B.y, B.v, s, stop));  // v = L y
+        hipLaunchKernelGGL(k_trs_dot, dim3(nb), dim3(kBlock), 0, s, B.sc, B.rh, B.v, (const double *)nullptr,
+                           (const double *)nullptr, B.prv, nb, N);
+        hipLaunchKernelGGL(k_trs_s, dim3(nb), dim3(kBlock), 0, s, B.sc, B.prv, nb, B.x, B.y, B.r, B.v, B.dinv,
+                           B.s, B.z, N);
+        FO_TRY(launch_transport_apply(c, B.theta, B.par, 0, B.z, B.t, s, stop));  // t = L z
+        hipLaunchKernelGGL(k_trs_dot, dim3(nb), dim3(kBlock), 0, s, B.sc, B.t, B.s, B.t, B.t, B.pts, nb, N);
+        hipLaunchKernelGGL(k_trs_xr, dim3(nb), dim3(kBlock), 0, s, B.sc, B.pts, nb, B.x, B.z, B.s, B.t, B.r, B.rh,
+                           B.prr, N);
+    }
+    return FO_OK;
+}
+
+// Enqueues g iterations as graphs of 32, 16, ..., 1 iterations.
+int tr_enqueue(fo_ctx *c, const TrBufs &B, int g)
+{
+    for (int len = 32; len >= 1; len >>= 1)
+        while (g >= len) {
+            auto key = std::make_tuple(40, len, (int)c->scatter, 0);
+            FO_TRY(graph_chunk(c, key, [&](hipStream_t s) { return tr_iterations(c, B, len, s); }));
+            g -= len;
+        }
     return FO_OK;
 }
 
@@ -215,77 +333,59 @@ int fo_transport(fo_ctx *c, const double *theta, double dt, int32_t steps, int32
     hipStream_t s = c->stream;
     const int64_t N = c->N;
     const double h2 = c->transport_h2;
-    const double h2e = smooth ? h2 : 0.0;
-    const int nb = blocks_for(N), red = red_blocks(N);
-    if (c->dim == 2)
-        hipLaunchKernelGGL(k_tr_coef<2>, dim3(blocks_for(c->E)), dim3(256), 0, s, c->conn, c->E, theta, dt, h2,
-                           B.coef);
-    else
-        hipLaunchKernelGGL(k_tr_coef<3>, dim3(blocks_for(c->E)), dim3(256), 0, s, c->conn, c->E, theta, dt, h2,
-                           B.coef);
-    FO_TRY(launch_transport_diag(c, B.coef, dt, h2e, B.dinv, s));
+    const int nb = red_blocks(N);
+    FO_HIP(hipMemcpyAsync(B.theta, theta, (size_t)N * c->dim * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_tr_par, dim3(1), dim3(1), 0, s, B.par, dt, smooth ? h2 : 0.0, h2);
+    FO_TRY(launch_transport_diag(c, B.theta, B.par, B.dinv, s));
     launch_invert_diag<double>(B.dinv, nullptr, N, B.dinv, s);
-    TrScal *sc = B.sc;
     TrScal h{};
     auto read = [&]() -> int {
-        FO_HIP(hipMemcpyAsync(&h, sc, sizeof(TrScal), hipMemcpyDeviceToHost, s));
+        FO_HIP(hipMemcpyAsync(&h, B.sc, sizeof(TrScal), hipMemcpyDeviceToHost, s));
         FO_HIP(hipStreamSynchronize(s));
         return FO_OK;
-    };
-    auto dot = [&](int npair, const double *a0, const double *b0, const double *a1, const double *b1,
-                   double *out) {
-        launch_dots<double>(npair, a0, b0, a1, b1, nullptr, nullptr, N, c->partials, red, s);
-        launch_finish_dots(c->partials, red, npair, out, s);
     };
     int64_t iters = 0;
     double worst = 0.0;  // largest accepted relative residual
     int status = FO_OK;
-    const int poll_every = 4;
+    int pred = 4;  // iterations of the first batch: the previous step's first pass plus its stop test
     for (int step = 0; step < steps && status == FO_OK; ++step) {
-        FO_TRY(launch_transport_apply(c, B.coef, -dt, h2e, phi, B.b, s));  // b = R phi
+        FO_TRY(launch_transport_apply(c, B.theta, B.par, 1, phi, B.b, s));  // b = R phi
         FO_HIP(hipMemcpyAsync(B.x, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        dot(1, B.b, B.b, nullptr, nullptr, &sc->bb);
+        launch_dots<double>(1, B.b, B.b, nullptr, nullptr, nullptr, nullptr, N, c->partials, red_blocks(N), s);
+        launch_finish_dots(c->partials, red_blocks(N), 1, &B.sc->bb, s);
         bool ok = false;
         int64_t its = 0;  // operator applications of this step
         double rel = 0.0;
-        for (int restart = 0; restart < 50 && !ok; ++restart) {
-            FO_TRY(launch_transport_apply(c, B.coef, dt, h2e, B.x, B.t, s));  // t = L x
+        for (int restart = 0; restart < 50 && !ok && status == FO_OK; ++restart) {
+            FO_TRY(launch_transport_apply(c, B.theta, B.par, 0, B.x, B.t, s));  // t = L x
             if (restart > 0) ++its;
-            hipLaunchKernelGGL(k_tr_start, dim3(nb), dim3(256), 0, s, B.b, B.t, B.r, B.rh, B.p, B.v, N);
-            hipLaunchKernelGGL(k_tr_reset, dim3(1), dim3(1), 0, s, sc);
-            dot(1, B.r, B.r, nullptr, nullptr, &sc->rr);
+            hipLaunchKernelGGL(k_trs_start, dim3(nb), dim3(kBlock), 0, s, B.b, B.t, B.r, B.rh, B.p, B.v, B.prr,
+                               nb, N);
+            const int64_t left = std::max<int64_t>(o->max_iter - its, 0);
+            hipLaunchKernelGGL(k_trs_check, dim3(1), dim3(64), 0, s, B.sc, B.prr, nb, o->rtol,
+                               (int32_t)std::min<int64_t>(left, INT32_MAX));
             FO_TRY(read());
-            const double target = o->rtol * std::sqrt(h.bb);
             rel = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
-            if (!(h.rr == h.rr)) {
+            if (h.flag == TR_NAN) {
                 status = FO_ERR_BREAKDOWN;
                 break;
             }
-            if (std::sqrt(h.rr) <= target) {
+            if (h.flag == TR_CONVERGED) {
                 ok = true;
                 break;
             }
             if (its >= o->max_iter) break;
-            for (int k = 0; its < o->max_iter; ++k) {
-                dot(1, B.rh, B.r, nullptr, nullptr, &sc->rho_new);
-                hipLaunchKernelGGL(k_tr_beta, dim3(1), dim3(1), 0, s, sc);
-                hipLaunchKernelGGL(k_tr_p, dim3(nb), dim3(256), 0, s, sc, B.r, B.p, B.v, B.dinv, B.y, N);
-                FO_TRY(launch_transport_apply(c, B.coef, dt, h2e, B.y, B.v, s));  // v = L y
-                dot(1, B.rh, B.v, nullptr, nullptr, &sc->rv);
-                hipLaunchKernelGGL(k_tr_alpha, dim3(1), dim3(1), 0, s, sc);
-                hipLaunchKernelGGL(k_tr_s, dim3(nb), dim3(256), 0, s, sc, B.x, B.y, B.r, B.v, B.dinv, B.s, B.z, N);
-                FO_TRY(launch_transport_apply(c, B.coef, dt, h2e, B.z, B.t, s));  // t = L z
-                dot(2, B.t, B.s, B.t, B.t, &sc->ts);  // t.s and t.t (adjacent fields)
-                hipLaunchKernelGGL(k_tr_omega, dim3(1), dim3(1), 0, s, sc);
-                hipLaunchKernelGGL(k_tr_xr, dim3(nb), dim3(256), 0, s, sc, B.x, B.z, B.s, B.t, B.r, N);
-                dot(1, B.r, B.r, nullptr, nullptr, &sc->rr);
-                its += 2;
-                if ((k + 1) % poll_every == 0 || its >= o->max_iter) {
-                    FO_TRY(read());
-                    if (h.bad || !(h.rr == h.rr) || std::sqrt(h.rr) <= target) break;
-                }
+            // iterate until the device stops; the next pass recomputes b - L x
+            // and accepts the step or restarts
+            int batch = pred;
+            while (true) {
+                FO_TRY(tr_enqueue(c, B, batch));
+                FO_TRY(read());
+                if (h.flag != TR_RUN) break;
+                batch = 2;
             }
-            // the next pass recomputes b - L x and accepts the step or restarts
+            if (restart == 0) pred = std::min(std::max(h.its / 2 + 1, 1), 64);
+            its += h.its;
         }
         iters += its;
         worst = std::max(worst, rel);
