@@ -110,3 +110,44 @@ def test_transport_after_a_descent_solve_matches_oracle():
     st = ctx.transport(dev(theta), dt, steps, phi, fo.SolveOpts(rtol=1e-12))
     assert st.status == 0 and st.iters_outer == steps
     assert np.linalg.norm(phi.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_repeated_calls_reuse_the_captured_solver():
+    """The solver's iterations are captured once per context and replayed:
+    later calls with another dt, another velocity array (at another address)
+    and the diffusion switched off still match the oracle."""
+    w = WORKLOADS["3d_12x6x6"]()
+    m = w.mesh
+    ctx = fo.Context.from_workload(w)
+    cases = [(0.006, 4, 21, True), (0.011, 3, 22, False), (0.003, 5, 23, True)]
+    for dt, steps, seed, smooth in cases:
+        theta = smooth_velocity(m.coords, seed).ravel()
+        ref, _ = oc.transport(m.dim, m.coords, m.conn, theta, dt, steps, w.phi, smooth=smooth, rtol=1e-13)
+        th_dev = dev(theta)  # a fresh allocation each call
+        phi = dev(w.phi)
+        print("case transport dt %g steps %d seed %d smooth %s" % (dt, steps, seed, smooth), flush=True)
+        st = ctx.transport(th_dev, dt, steps, phi, fo.SolveOpts(rtol=1e-12), smooth=smooth)
+        assert st.status == 0 and st.iters_outer == steps
+        assert np.linalg.norm(phi.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_iteration_limit_reports_not_converged():
+    """A cap on operator applications below what a step needs ends the call
+    with FO_NOT_CONVERGED (raised unless allowed) and leaves phi finite."""
+    w = WORKLOADS["3d_12x6x6"]()
+    m = w.mesh
+    ctx = fo.Context.from_workload(w)
+    theta = dev(smooth_velocity(m.coords, 9).ravel())
+    phi = dev(w.phi)
+    with pytest.raises(fo.FoError):
+        ctx.transport(theta, 0.01, 2, phi, fo.SolveOpts(rtol=1e-14, max_iter=2))
+    phi = dev(w.phi)
+    st = ctx.transport(theta, 0.01, 2, phi, fo.SolveOpts(rtol=1e-14, max_iter=2), allow_not_converged=True)
+    assert st.status == fo.FO_NOT_CONVERGED
+    assert torch.isfinite(phi).all()
+    # the same context still solves to tolerance afterwards
+    ref, _ = oc.transport(m.dim, m.coords, m.conn, theta.cpu().numpy(), 0.01, 2, w.phi, smooth=True, rtol=1e-13)
+    phi = dev(w.phi)
+    st = ctx.transport(theta, 0.01, 2, phi, fo.SolveOpts(rtol=1e-12))
+    assert st.status == 0
+    assert np.linalg.norm(phi.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
