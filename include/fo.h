@@ -200,6 +200,60 @@ int fo_levelset_update(fo_ctx *ctx, const double *theta, double dt, double *phi)
 int fo_transport(fo_ctx *ctx, const double *theta, double dt, int32_t steps, int32_t smooth, double *phi,
                  const fo_solve_opts *opts, fo_solve_stats *stats);
 
+/* Parameters of the level-set loop (fo_optimize).  The paper's defaults:
+ * dfactor 1e-2, t in [1e-3, 1e-1], steps in [8, 16], smooth 0,
+ * start_to_check 30, prev 10, cost/lgrn/ctrn tolerances 1e-2, and the PPL
+ * parameters r 0.999, delta0 0.5, alpha 2000, beta 0.5. */
+typedef struct {
+    int32_t n_iter;            /* iterations at most (niter)                       */
+    double V;                  /* > 0: constraint vol(Omega) / V = 1 (PPL); <= 0: none */
+    double dfactor;            /* t_end = dfactor / B(theta, theta)                */
+    double t_min, t_max;       /* clamp of t_end                                    */
+    int32_t s_min, s_max;      /* clamp of the transport step count                */
+    int32_t smooth;            /* transport with the h^2 diffusion                 */
+    int32_t start_to_check;    /* the stopping test runs for i > start_to_check    */
+    int32_t prev;              /* window of earlier iterates in the test            */
+    double cost_tol, lgrn_tol, ctrn_tol;
+    double ppl_r, ppl_delta0, ppl_alpha, ppl_beta;
+    fo_solve_opts state;       /* state solve                                       */
+    fo_solve_opts descent;     /* velocity solve                                    */
+    fo_solve_opts transport;   /* transport solves (rtol, max_iter per step)       */
+    fo_descent_opts velocity;  /* the velocity bilinear form                        */
+} fo_loop_opts;
+
+/* One iteration of fo_optimize (host). */
+typedef struct {
+    double J;                  /* compliance b . u                                  */
+    double vol;                /* sum_e chi_e |T_e|                                 */
+    double C;                  /* vol / V (vol without a constraint)                */
+    double L;                  /* Proximal-Perturbed Lagrangian (J without a constraint) */
+    double lambda;             /* multiplier used in the derivative                 */
+    double B_tt;               /* B(theta, theta); NaN on a stopping iteration      */
+    double t_end, dt;          /* transport final time and step                     */
+    int32_t steps;             /* transport steps (0 on a stopping iteration)      */
+    int32_t state_iters, descent_iters, transport_iters;  /* operator applications */
+    int32_t status;            /* worst status of the iteration's solves            */
+    int32_t pad;
+} fo_loop_record;
+
+/* The level-set loop (Algorithm 1; Sections "Lagrangian method" and "Other
+ * implementation aspects"): per iteration i, set phi, state solve, cost J =
+ * b . u and volume; with V > 0 the PPL update of eq. lag_method for i >= 1
+ * (iteration 0 uses z = lambda = mu = 0) and the Lagrangian of eq.
+ * lagrangian; the stopping test (i > start_to_check: over the previous `prev`
+ * iterates, the relative change of J, or of L together with |C - 1| <
+ * ctrn_tol, below its tolerance); then the descent right-hand side of S =
+ * S^J + lambda S^C (eq. S0andS1), the velocity solve, t_end and the step
+ * count from eqs. tend and steps (no noise), and fo_transport of phi.
+ * b: device [n_dofs], one load case; phi: device [n_nodes], in: phi^0, out:
+ * the last level set.  records: host [opts->n_iter]; *n_done receives the
+ * number of iterations recorded and *stopped 1 when the stopping test ended
+ * the loop.  Allocates its work vectors (4 n_dofs + 4 doubles) per call.
+ * Returns FO_OK, FO_NOT_CONVERGED (a solve hit its cap; the loop went on),
+ * FO_ERR_ARG, or the first error of a step (the loop stops there). */
+int fo_optimize(fo_ctx *ctx, const fo_loop_opts *opts, const double *b, double *phi,
+                fo_loop_record *records, int32_t *n_done, int32_t *stopped);
+
 /* Kernel timing for measurement tools.  While enabled, every launch of the
  * kernels named below is bracketed by a pair of HIP events recorded on the
  * context's stream; fo_profile_read synchronises the stream and returns the

@@ -56,6 +56,23 @@ class fo_solve_stats(C.Structure):
                 ("rel_res", C.c_double), ("seconds", C.c_double)]
 
 
+class fo_loop_opts(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("V", C.c_double), ("dfactor", C.c_double), ("t_min", C.c_double),
+                ("t_max", C.c_double), ("s_min", C.c_int32), ("s_max", C.c_int32), ("smooth", C.c_int32),
+                ("start_to_check", C.c_int32), ("prev", C.c_int32), ("cost_tol", C.c_double),
+                ("lgrn_tol", C.c_double), ("ctrn_tol", C.c_double), ("ppl_r", C.c_double),
+                ("ppl_delta0", C.c_double), ("ppl_alpha", C.c_double), ("ppl_beta", C.c_double),
+                ("state", fo_solve_opts), ("descent", fo_solve_opts), ("transport", fo_solve_opts),
+                ("velocity", fo_descent_opts)]
+
+
+class fo_loop_record(C.Structure):
+    _fields_ = [("J", C.c_double), ("vol", C.c_double), ("C", C.c_double), ("L", C.c_double),
+                ("lambda_", C.c_double), ("B_tt", C.c_double), ("t_end", C.c_double), ("dt", C.c_double),
+                ("steps", C.c_int32), ("state_iters", C.c_int32), ("descent_iters", C.c_int32),
+                ("transport_iters", C.c_int32), ("status", C.c_int32), ("pad", C.c_int32)]
+
+
 _vp = C.c_void_p
 class fo_request(C.Structure):
     _fields_ = [("mesh", fo_mesh), ("mat", fo_material), ("mesh_key", C.c_uint64),
@@ -86,6 +103,8 @@ EXPORTS = {
                           C.POINTER(fo_solve_stats), _vp], C.c_int),
     "fo_apply_descent": ([_vp, C.POINTER(fo_descent_opts), _vp, _vp], C.c_int),
     "fo_levelset_update": ([_vp, _vp, C.c_double, _vp], C.c_int),
+    "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
+                     C.POINTER(C.c_int32)], C.c_int),
     "fo_transport": ([_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.POINTER(fo_solve_opts),
                       C.POINTER(fo_solve_stats)], C.c_int),
     "fo_profile_enable": ([_vp, C.c_int32], C.c_int),
@@ -360,6 +379,37 @@ class Context:
                                 C.byref(opts.c()), C.byref(st))
         _check(rc, "fo_transport", allow)
         return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
+
+    def optimize(self, b, phi, n_iter: int, dopts: "DescentOpts", V: Optional[float] = None, smooth=False,
+                 dfactor=1e-2, lv_time=(1e-3, 1e-1), lv_iter=(8, 16), start_to_check=30, prev=10,
+                 cost_tol=1e-2, lgrn_tol=1e-2, ctrn_tol=1e-2, ppl=(0.999, 0.5, 2000.0, 0.5),
+                 state_opts: Optional[SolveOpts] = None, descent_opts: Optional[SolveOpts] = None,
+                 transport_opts: Optional[SolveOpts] = None, allow_not_converged=False):
+        """The level-set loop (fo_optimize): up to n_iter iterations of the
+        paper's Algorithm 1 from phi (updated in place) with the load b;
+        V given: volume constraint vol / V = 1 by the PPL method.  Returns
+        (records as dicts, stopped)."""
+        import torch
+        so = state_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
+        do = descent_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
+        to = transport_opts or SolveOpts(rtol=1e-10)
+        o = fo_loop_opts(int(n_iter), float(V) if V else 0.0, float(dfactor), float(lv_time[0]),
+                         float(lv_time[1]), int(lv_iter[0]), int(lv_iter[1]), int(bool(smooth)),
+                         int(start_to_check), int(prev), float(cost_tol), float(lgrn_tol), float(ctrn_tol),
+                         float(ppl[0]), float(ppl[1]), float(ppl[2]), float(ppl[3]), so.c(), do.c(), to.c(),
+                         dopts.c())
+        recs = (fo_loop_record * max(1, int(n_iter)))()
+        n_done, stopped = C.c_int32(0), C.c_int32(0)
+        rc = lib().fo_optimize(self.h, C.byref(o), _ptr(b, torch.float64, self.n_dofs, "b"),
+                               _ptr(phi, torch.float64, self.n_nodes, "phi"), recs, C.byref(n_done),
+                               C.byref(stopped))
+        _check(rc, "fo_optimize", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
+        out = []
+        for r in recs[:n_done.value]:
+            d = {k: getattr(r, k) for k, _ in fo_loop_record._fields_ if k != "pad"}
+            d["lambda"] = d.pop("lambda_")
+            out.append(d)
+        return out, bool(stopped.value)
 
     def levelset_update(self, theta, dt: float, phi):
         import torch
