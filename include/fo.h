@@ -217,8 +217,12 @@ typedef struct {
     double ppl_r, ppl_delta0, ppl_alpha, ppl_beta;
     fo_solve_opts state;       /* state solve                                       */
     fo_solve_opts descent;     /* velocity solve                                    */
-    fo_solve_opts transport;   /* transport solves (rtol, max_iter per step)       */
+    fo_solve_opts transport;   /* transport and reinitialisation solves            */
     fo_descent_opts velocity;  /* the velocity bilinear form                        */
+    int32_t reinit_step;       /* > 0: reinitialise after the transport of every
+                                  iteration i with i % reinit_step == 0            */
+    int32_t reinit_iters;      /* reinitialisation steps (the paper: 8)             */
+    double reinit_t;           /* reinitialisation pseudo-time (the paper: 0.1)     */
 } fo_loop_opts;
 
 /* One iteration of fo_optimize (host). */
@@ -233,7 +237,7 @@ typedef struct {
     int32_t steps;             /* transport steps (0 on a stopping iteration)      */
     int32_t state_iters, descent_iters, transport_iters;  /* operator applications */
     int32_t status;            /* worst status of the iteration's solves            */
-    int32_t pad;
+    int32_t reinit_iters;      /* reinitialisation operator applications (0: none) */
 } fo_loop_record;
 
 /* The level-set loop (Algorithm 1; Sections "Lagrangian method" and "Other
@@ -244,7 +248,9 @@ typedef struct {
  * iterates, the relative change of J, or of L together with |C - 1| <
  * ctrn_tol, below its tolerance); then the descent right-hand side of S =
  * S^J + lambda S^C (eq. S0andS1), the velocity solve, t_end and the step
- * count from eqs. tend and steps (no noise), and fo_transport of phi.
+ * count from eqs. tend and steps (no noise), fo_transport of phi, and with
+ * reinit_step > 0 fo_reinit of the transported phi at every iteration i
+ * with i % reinit_step == 0.
  * b: device [n_dofs], one load case; phi: device [n_nodes], in: phi^0, out:
  * the last level set.  records: host [opts->n_iter]; *n_done receives the
  * number of iterations recorded and *stopped 1 when the stopping test ended
@@ -253,6 +259,25 @@ typedef struct {
  * FO_ERR_ARG, or the first error of a step (the loop stops there). */
 int fo_optimize(fo_ctx *ctx, const fo_loop_opts *opts, const double *b, double *phi,
                 fo_loop_record *records, int32_t *n_done, int32_t *stopped);
+
+/* Reinitialisation of the level set (Section "Other implementation
+ * aspects", eqs. Eikonal, HJ, grad_H, weak_HJ): `steps` pseudo-time steps up
+ * to t_end (the paper's defaults: 8 steps, 0.1) of
+ *   d/dt varphi + S(phi) |grad varphi| = S(phi) + h^2 lap varphi (Neumann),
+ * S(phi) = phi / sqrt(phi^2 + h^2), from varphi(0) = phi, with
+ * Petrov-Galerkin test functions psi + tau grad H . grad psi (grad H =
+ * S g / |g| for the element gradient g of varphi(t), 0 on an element whose
+ * vertex values agree to 1e-12 relative; tau = (1/2)(dt^-2 +
+ * S^2/h^2)^(-1/2)); S enters per element at the mean of its nodal values,
+ * h^2 is the transport step's mesh-size expression.  The first step is
+ * explicit Euler, the others two-step Adams-Bashforth; each solves its
+ * nonsymmetric mass system by Jacobi BiCGStab in FP64 to opts->rtol
+ * (recomputed residual; opts->max_iter applications per step).  phi: device
+ * [n_nodes], in: phi, out: varphi(t_end).  stats (host, may be NULL) as for
+ * fo_transport.  Requires the tiled scatter.  Returns FO_OK,
+ * FO_NOT_CONVERGED, FO_ERR_BREAKDOWN, FO_ERR_STATE or FO_ERR_ARG. */
+int fo_reinit(fo_ctx *ctx, double *phi, int32_t steps, double t_end, const fo_solve_opts *opts,
+              fo_solve_stats *stats);
 
 /* Kernel timing for measurement tools.  While enabled, every launch of the
  * kernels named below is bracketed by a pair of HIP events recorded on the

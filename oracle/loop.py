@@ -14,7 +14,10 @@ Readings (where the paper leaves a choice):
 * the constraint is the volume fraction C(Omega) = vol(Omega) / V;
 * the stopping test runs once per iteration, after the cost and the
   constraint are known and before the derivative, for i > start_to_check;
-* no noise in the adaptive time stepping, and no reinitialisation.
+* no noise in the adaptive time stepping;
+* with reinit_step > 0 the transported level set of iteration i is
+  reinitialised when i % reinit_step == 0 (the paper's "reinit_step % i = 0"
+  read with the operands the other way round, which also covers i = 0).
 """
 from __future__ import annotations
 
@@ -25,6 +28,7 @@ import numpy as np
 
 from .oracle import (adaptive_dt, assemble_descent, assemble_elasticity, element_coef, lame,
                     shape_derivative, transport)
+from .reinit import reinit
 
 # the paper's PPL parameters (Section "Lagrangian method")
 PPL_R, PPL_DELTA0, PPL_ALPHA, PPL_BETA = 0.999, 0.5, 2000.0, 0.5
@@ -109,13 +113,14 @@ class LoopResult:
 
 def optimize(w, n_iter: int, V: Optional[float] = None, smooth: bool = False, dfactor=1e-2,
              t_range=(1e-3, 1e-1), s_range=(8, 16), start_to_check=30, prev=10, cost_tol=1e-2,
-             lgrn_tol=1e-2, ctrn_tol=1e-2, rtol=1e-12) -> LoopResult:
+             lgrn_tol=1e-2, ctrn_tol=1e-2, rtol=1e-12, reinit_step=0, reinit_pars=(8, 0.1)) -> LoopResult:
     """Algorithm 1 on a fo_inputs.Workload with one load case: per iteration
     the state solve, cost J = b.u and volume, the stopping test, the PPL
     update (V given: constraint vol / V = 1), the descent right-hand side of
     S = S^J + lambda S^C (eq. S0andS1), the velocity solve, the adaptive final
-    time and step count (eqs. tend, steps) and the paper's transport step of
-    phi.  Returns the final phi and one record per iteration."""
+    time and step count (eqs. tend, steps), the paper's transport step of
+    phi and, every reinit_step iterations, its reinitialisation.  Returns the
+    final phi and one record per iteration."""
     m = w.mesh
     dim = m.dim
     lam_e, mu_e = lame(w.E, w.nu, dim, w.plane_stress)
@@ -156,5 +161,7 @@ def optimize(w, n_iter: int, V: Optional[float] = None, smooth: bool = False, df
         rec.B_tt = float(theta @ rhs)
         rec.t_end, rec.steps, rec.dt = adaptive_dt(rec.B_tt, dfactor, t_range, s_range)
         phi, _ = transport(dim, m.coords, m.conn, theta, rec.dt, rec.steps, phi, smooth=smooth, rtol=rtol)
+        if reinit_step and i % reinit_step == 0:
+            phi = reinit(dim, m.coords, m.conn, phi, steps=reinit_pars[0], t_end=reinit_pars[1])
     out.phi = phi
     return out

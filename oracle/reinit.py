@@ -18,7 +18,11 @@ Readings (where the paper leaves a choice):
   nodal values (a one-point rule, as theta in the transport step); h^2 is
   the paper's mesh-size expression (as in the transport step);
 * grad H on an element is S_e g / |g| with g the element gradient of
-  varphi(t) (0 where g = 0), and tau_e = 1/2 (dt^-2 + S_e^2 / h^2)^(-1/2);
+  varphi(t), and tau_e = 1/2 (dt^-2 + S_e^2 / h^2)^(-1/2).  p / |p| has no
+  limit at p = 0, and an element whose vertex values agree (a symmetric
+  extremum of the level set) has a gradient of pure rounding, pointing
+  anywhere: grad H is taken as 0 where max_a u_a - min_a u_a <= 1e-12
+  max_a |u_a| (and where g = 0);
 * the paper's defaults: 8 steps up to pseudo-time 0.1.
 """
 from __future__ import annotations
@@ -44,7 +48,9 @@ def step_system(dim, conn, vol, grad, Sbar, h2, dt, u, v=None):
     E = conn.shape[1]
     gu = _elem_grad(u, conn, grad)
     nu = np.linalg.norm(gu, axis=1)
-    dirn = np.where(nu[:, None] > 0, gu / np.where(nu > 0, nu, 1.0)[:, None], 0.0)
+    ue0 = u[conn.T]
+    flat = (ue0.max(axis=1) - ue0.min(axis=1) <= 1e-12 * np.abs(ue0).max(axis=1)) | (nu == 0)
+    dirn = np.where(flat[:, None], 0.0, gu / np.where(flat, 1.0, nu)[:, None])
     gH = Sbar[:, None] * dirn                                   # grad H per element
     tau = 0.5 / np.sqrt(1.0 / dt ** 2 + Sbar ** 2 / h2)
     tg = np.einsum("ei,eai->ea", gH, grad)                      # grad H . grad lambda_a

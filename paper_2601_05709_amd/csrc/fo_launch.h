@@ -60,6 +60,13 @@ void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *
 int launch_transport_apply(const fo_ctx *c, const double *theta, const double *par, int which, const double *x,
                            double *y, hipStream_t s, const int32_t *done = nullptr);
 int launch_transport_diag(const fo_ctx *c, const double *theta, const double *par, double *diag, hipStream_t s);
+// Reinitialisation step (ReinitOp): y = Lhat x, the diagonal of Lhat, and
+// the step's right-hand side.  w: device [N][3] nodal u = varphi(t), v =
+// varphi(t - dt), S(phi); par: device [4] dt, h^2, 1/dt^2, Euler flag.
+int launch_reinit_apply(const fo_ctx *c, const double *w, const double *par, const double *x, double *y,
+                        hipStream_t s, const int32_t *done = nullptr);
+int launch_reinit_diag(const fo_ctx *c, const double *w, const double *par, double *diag, hipStream_t s);
+int launch_reinit_rhs(const fo_ctx *c, const double *w, const double *par, double *rhs, hipStream_t s);
 
 // Operator of the fused CG kernels.
 enum FusedKind { FUSED_ELAS = 0, FUSED_DESCENT = 1 };

@@ -2,10 +2,10 @@
 // stopping test, the Proximal-Perturbed Lagrangian multiplier update
 // (Section "Lagrangian method", eqs. lagrangian, lag_method, S0andS1), the
 // velocity solve, the adaptive final time and step count (Section "Other
-// implementation aspects", eqs. tend and steps) and the paper's transport
-// step.  Every step runs on the device through the library's entry points;
-// the host keeps the multipliers and the histories (a few scalars per
-// iteration).
+// implementation aspects", eqs. tend and steps), the paper's transport step
+// and, every reinit_step iterations, the reinitialisation.  Every step runs
+// on the device through the library's entry points; the host keeps the
+// multipliers and the histories (a few scalars per iteration).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -83,6 +83,8 @@ int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, 
     if (o->n_iter < 0 || !(o->dfactor > 0.0) || !(o->t_min > 0.0) || !(o->t_max > o->t_min) || o->s_min < 1 ||
         o->s_max < o->s_min || o->prev < 1 || o->start_to_check < 0)
         return FO_ERR_ARG;
+    if (o->reinit_step < 0 || (o->reinit_step > 0 && (o->reinit_iters < 1 || !(o->reinit_t > 0.0))))
+        return FO_ERR_ARG;
     const bool constrained = o->V > 0.0;
     if (constrained && (!(o->ppl_r > 0.0 && o->ppl_r < 1.0) || !(o->ppl_alpha > 0.0) || !(o->ppl_beta > 0.0) ||
                         !(o->ppl_delta0 > 0.0)))
@@ -154,6 +156,11 @@ int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, 
             rec.dt = rec.t_end / steps;
             st = worse(st, fo_transport(c, theta, rec.dt, steps, o->smooth, phi, &o->transport, &ts));
             rec.transport_iters = ts.iters_inner;
+        }
+        if (st >= 0 && o->reinit_step > 0 && i % o->reinit_step == 0) {
+            fo_solve_stats rs{};
+            st = worse(st, fo_reinit(c, phi, o->reinit_iters, o->reinit_t, &o->transport, &rs));
+            rec.reinit_iters = rs.iters_inner;
         }
         rec.status = st;
         result = worse(result, st);

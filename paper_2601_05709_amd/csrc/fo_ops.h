@@ -263,4 +263,159 @@ struct TransportDiagOp {
     }
 };
 
+// Reinitialisation step of the level set (eqs. HJ, grad_H, weak_HJ), from
+// the tile-staged nodal values A[a] = (u = varphi(t), v = varphi(t - dt),
+// S(phi)): S_e = element mean of S, g = grad u, grad H = S_e g / |g|,
+// tau_e = 1/2 (dt^-2 + S_e^2 / h^2)^(-1/2).  p / |p| has no limit at 0: on
+// an element whose vertex values agree to 1e-12 relative (g is rounding
+// noise) or with g = 0, grad H = 0.  par: device [4] dt, h^2, 1/dt^2, 1 for
+// the explicit Euler first step (else Adams-Bashforth).
+template <int D>
+struct ReinitCoef {
+    double ga[D + 1][D];  // gradients of the barycentric functions
+    double vol, S, tau, nu;
+    double gu[D], gH[D];
+};
+
+template <int D>
+__device__ __forceinline__ ReinitCoef<D> reinit_coef(const double *const *X, const double *const *A, double rdt2,
+                                                     double h2)
+{
+    ReinitCoef<D> k;
+    const Geom<D, double> g = geom<D, double>(X);
+    const double inv = 1.0 / g.det;
+    k.vol = fabs(g.det) / (D == 2 ? 2.0 : 6.0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        k.ga[0][j] = 0.0;
+#pragma unroll
+        for (int a = 1; a <= D; ++a) {
+            k.ga[a][j] = g.c[a - 1][j] * inv;
+            k.ga[0][j] -= k.ga[a][j];
+        }
+    }
+    double S = 0.0, n2 = 0.0, umax = A[0][0], umin = A[0][0], uabs = fabs(A[0][0]);
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+        S += A[a][2];
+        umax = fmax(umax, A[a][0]);
+        umin = fmin(umin, A[a][0]);
+        uabs = fmax(uabs, fabs(A[a][0]));
+    }
+    k.S = S / (double)(D + 1);
+    const bool flat = umax - umin <= 1e-12 * uabs;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a <= D; ++a) s += A[a][0] * k.ga[a][j];
+        k.gu[j] = s;
+        n2 += s * s;
+    }
+    k.nu = sqrt(n2);
+#pragma unroll
+    for (int j = 0; j < D; ++j) k.gH[j] = (!flat && k.nu > 0.0) ? k.S * k.gu[j] / k.nu : 0.0;
+    k.tau = 0.5 / sqrt(rdt2 + k.S * k.S / h2);
+    return k;
+}
+
+// y = Lhat x with Lhat_ab = int lambda_b psi_hat_a = M_ab + tau (grad H .
+// grad lambda_a) |T| / (d+1).
+template <int D>
+struct ReinitOp {
+    static constexpr int NX = 1, NV = 1, NA = 3;
+    struct Elem {
+        double rdt2, h2;
+    };
+    const double *aux;  // [N][3]: u, v, S
+    const double *par;
+    __device__ Elem load(int64_t) const { return Elem{par[2], par[1]}; }
+    __device__ void operator()(const Elem &in, const double *const *X, const double *const *U,
+                               const double *const *A, double out[D + 1][1]) const
+    {
+        const ReinitCoef<D> k = reinit_coef<D>(X, A, in.rdt2, in.h2);
+        double sx = 0.0;
+#pragma unroll
+        for (int a = 0; a <= D; ++a) sx += U[a][0];
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double tg = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) tg += k.gH[j] * k.ga[a][j];
+            out[a][0] = k.vol * ((U[a][0] + sx) / ((D + 1) * (D + 2)) + k.tau * tg * sx / (D + 1));
+        }
+    }
+};
+
+// Diagonal of Lhat.
+template <int D>
+struct ReinitDiagOp {
+    static constexpr int NX = 0, NV = 1, NA = 3;
+    using Elem = typename ReinitOp<D>::Elem;
+    const double *aux;
+    const double *par;
+    __device__ Elem load(int64_t e) const { return ReinitOp<D>{aux, par}.load(e); }
+    __device__ void operator()(const Elem &in, const double *const *X, const double *const *,
+                               const double *const *A, double out[D + 1][1]) const
+    {
+        const ReinitCoef<D> k = reinit_coef<D>(X, A, in.rdt2, in.h2);
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double tg = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) tg += k.gH[j] * k.ga[a][j];
+            out[a][0] = k.vol * (2.0 / ((D + 1) * (D + 2)) + k.tau * tg / (D + 1));
+        }
+    }
+};
+
+// Right-hand side of one step: int (u + dt S) psi_hat_a + dt int G(u, v,
+// psi_hat_a), G(u, v, w) = (H(grad v) - 3 H(grad u)) / 2 w + h^2 (grad v -
+// 3 grad u) / 2 . grad w; the Euler step takes -H(grad u) w - h^2 grad u .
+// grad w.  grad psi_hat_a = grad lambda_a (the tau term is constant per
+// element).
+template <int D>
+struct ReinitRhsOp {
+    static constexpr int NX = 0, NV = 1, NA = 3;
+    struct Elem {
+        double dt, h2, rdt2, euler;
+    };
+    const double *aux;
+    const double *par;
+    __device__ Elem load(int64_t) const { return Elem{par[0], par[1], par[2], par[3]}; }
+    __device__ void operator()(const Elem &in, const double *const *X, const double *const *,
+                               const double *const *A, double out[D + 1][1]) const
+    {
+        const ReinitCoef<D> k = reinit_coef<D>(X, A, in.rdt2, in.h2);
+        const bool euler = in.euler != 0.0;
+        double su = 0.0, gv[D], nv2 = 0.0;
+#pragma unroll
+        for (int a = 0; a <= D; ++a) su += A[a][0];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a <= D; ++a) s += A[a][1] * k.ga[a][j];
+            gv[j] = s;
+            nv2 += s * s;
+        }
+        const double c = euler ? -k.S * k.nu : 0.5 * k.S * (sqrt(nv2) - 3.0 * k.nu);
+        double dv[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) dv[j] = euler ? -k.gu[j] : 0.5 * (gv[j] - 3.0 * k.gu[j]);
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double tg = 0.0, dg = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                tg += k.gH[j] * k.ga[a][j];
+                dg += dv[j] * k.ga[a][j];
+            }
+            const double ones_hat = k.vol / (D + 1) + k.tau * tg * k.vol;
+            out[a][0] = k.vol * (A[a][0] + su) / ((D + 1) * (D + 2)) + k.tau * tg * k.vol * su / (D + 1) +
+                        in.dt * (k.S + c) * ones_hat + in.dt * in.h2 * k.vol * dg;
+        }
+    }
+};
+
 }  // namespace fo

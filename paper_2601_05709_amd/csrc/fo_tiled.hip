@@ -577,7 +577,8 @@ static int prepare_dim()
            ensure_lds_attr_cg<D, float, ElasOp<D, float>>() |
            ensure_lds_attr_cg<D, double, DescentOp<D, double>>() |
            ensure_lds_attr_cg<D, float, DescentOp<D, float>>() | ensure_lds_attr<D, double, TransportOp<D>>() |
-           ensure_lds_attr<D, double, TransportDiagOp<D>>();
+           ensure_lds_attr<D, double, TransportDiagOp<D>>() | ensure_lds_attr<D, double, ReinitOp<D>>() |
+           ensure_lds_attr<D, double, ReinitDiagOp<D>>() | ensure_lds_attr<D, double, ReinitRhsOp<D>>();
 }
 
 int tiled_prepare(const fo_ctx *c)
@@ -852,6 +853,34 @@ int launch_transport_diag(const fo_ctx *c, const double *theta, const double *pa
                                     nullptr, s);
     return run_tiled<3, double>(c, TransportDiagOp<3>{theta, par}, c->coords, (const double *)nullptr, diag,
                                 nullptr, s);
+}
+
+int launch_reinit_apply(const fo_ctx *c, const double *w, const double *par, const double *x, double *y,
+                        hipStream_t s, const int32_t *done)
+{
+    if (c->has_isolated) launch_fill<double>(y, c->N, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, ReinitOp<2>{w, par}, c->coords, x, y, nullptr, s, -1, -1, nullptr, done);
+    return run_tiled<3, double>(c, ReinitOp<3>{w, par}, c->coords, x, y, nullptr, s, -1, -1, nullptr, done);
+}
+
+int launch_reinit_diag(const fo_ctx *c, const double *w, const double *par, double *diag, hipStream_t s)
+{
+    launch_fill<double>(diag, c->N, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, ReinitDiagOp<2>{w, par}, c->coords, (const double *)nullptr, diag,
+                                    nullptr, s);
+    return run_tiled<3, double>(c, ReinitDiagOp<3>{w, par}, c->coords, (const double *)nullptr, diag, nullptr,
+                                s);
+}
+
+int launch_reinit_rhs(const fo_ctx *c, const double *w, const double *par, double *rhs, hipStream_t s)
+{
+    launch_fill<double>(rhs, c->N, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, ReinitRhsOp<2>{w, par}, c->coords, (const double *)nullptr, rhs, nullptr,
+                                    s);
+    return run_tiled<3, double>(c, ReinitRhsOp<3>{w, par}, c->coords, (const double *)nullptr, rhs, nullptr, s);
 }
 
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s)

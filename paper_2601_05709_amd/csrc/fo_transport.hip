@@ -2,15 +2,20 @@
 // transport, weak_transport, tau_lv): `steps` Crank-Nicolson steps of the
 // Petrov-Galerkin form with test functions psi + tau theta . grad psi and
 // optional h^2 diffusion.  Each step solves L phi' = R phi (L, R from
-// TransportOp with sdt = +dt / -dt, the same for every step) by
-// Jacobi-preconditioned BiCGStab in FP64, from phi.  The Krylov scalars stay
-// on the device: every block of a vector kernel sums the dot-product
-// partials of the kernel before it in the same fixed order, so all blocks
-// take the same coefficients and the same stop decision, and a device stop
-// flag turns the rest of a launched chunk into no-ops.  Chunks of iterations
-// are replayed as graphs; the host reads the flag after each batch of chunks
-// (sized from the previous step's count) and checks the recomputed residual
-// b - L x before it accepts a step.
+// TransportOp with +dt / -dt, the same for every step).  Reinitialisation
+// of the level set (Section "Other implementation aspects", eqs. HJ,
+// grad_H, weak_HJ): pseudo-time steps of the diffusive Eikonal equation,
+// each solving Lhat varphi' = rhs (ReinitOp, ReinitRhsOp), explicit Euler
+// first and Adams-Bashforth 2 after it.
+//
+// Both solve with Jacobi-preconditioned BiCGStab in FP64 from the previous
+// iterate.  The Krylov scalars stay on the device: every block of a vector
+// kernel sums the dot-product partials of the kernel before it in the same
+// fixed order, so all blocks take the same coefficients and the same stop
+// decision, and a device stop flag turns the rest of a launched chunk into
+// no-ops.  Chunks of iterations are replayed as graphs; the host reads the
+// flag once per batch of chunks (sized from the previous step's count) and
+// checks the recomputed residual b - A x before it accepts a step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -245,18 +250,23 @@ using namespace fo;
 
 namespace {
 
-// Transport work buffers of a context, allocated on first use.  The
-// captured graphs hold these addresses, so the velocity is copied in.
+// Work buffers of the transport and reinitialisation solves, allocated on
+// first use.  The captured graphs hold these addresses, so the velocity and
+// the nodal data of a reinitialisation step are copied in.
 struct TrBufs {
-    double *theta, *par, *b, *x, *r, *rh, *p, *v, *y, *s, *z, *t, *dinv;
+    double *theta, *par, *w, *prev, *b, *x, *r, *rh, *p, *v, *y, *s, *z, *t, *dinv;
     double *prr, *prv, *pts;  // partials [2 nb], [nb], [2 nb]
     TrScal *sc;
 };
 
+// Which step matrix the solver applies: the transport L or the
+// reinitialisation Lhat (its parameters at par + 8).
+enum { SYS_TRANSPORT = 0, SYS_REINIT = 1 };
+
 int tr_buffers(fo_ctx *c, TrBufs *o)
 {
     const int64_t N = c->N;
-    const int64_t n_dbl = N * c->dim + 8 + 11 * N + 5 * (int64_t)kRedBlocks;
+    const int64_t n_dbl = N * c->dim + 16 + 3 * N + N + 11 * N + 5 * (int64_t)kRedBlocks;
     if (!c->tr_buf) {
         const size_t bytes = (size_t)n_dbl * sizeof(double) + sizeof(TrScal) + 256;
         void *mem = nullptr;
@@ -269,7 +279,11 @@ int tr_buffers(fo_ctx *c, TrBufs *o)
     o->theta = m;
     m += N * c->dim;
     o->par = m;
-    m += 8;
+    m += 16;
+    o->w = m;
+    m += 3 * N;
+    o->prev = m;
+    m += N;
     double **vec[] = {&o->b, &o->x, &o->r, &o->rh, &o->p, &o->v, &o->y, &o->s, &o->z, &o->t, &o->dinv};
     for (double **q : vec) {
         *q = m;
@@ -283,20 +297,27 @@ int tr_buffers(fo_ctx *c, TrBufs *o)
     return FO_OK;
 }
 
+int sys_apply(const fo_ctx *c, const TrBufs &B, int sys, const double *x, double *y, hipStream_t s,
+              const int32_t *stop = nullptr)
+{
+    if (sys == SYS_REINIT) return launch_reinit_apply(c, B.w, B.par + 8, x, y, s, stop);
+    return launch_transport_apply(c, B.theta, B.par, 0, x, y, s, stop);
+}
+
 // Enqueues g BiCGStab iterations (each a no-op once the stop flag is set).
-int tr_iterations(const fo_ctx *c, const TrBufs &B, int g, hipStream_t s)
+int tr_iterations(const fo_ctx *c, const TrBufs &B, int sys, int g, hipStream_t s)
 {
     const int64_t N = c->N;
     const int nb = red_blocks(N);
     const int32_t *stop = &B.sc->flag;
     for (int k = 0; k < g; ++k) {
         hipLaunchKernelGGL(k_trs_p, dim3(nb), dim3(kBlock), 0, s, B.sc, B.prr, nb, B.r, B.p, B.v, B.dinv, B.y, N);
-        FO_TRY(launch_transport_apply(c, B.theta, B.par, 0, B.y, B.v, s, stop));  // v = L y
+        FO_TRY(sys_apply(c, B, sys, B.y, B.v, s, stop));  // v = A y
         hipLaunchKernelGGL(k_trs_dot, dim3(nb), dim3(kBlock), 0, s, B.sc, B.rh, B.v, (const double *)nullptr,
                            (const double *)nullptr, B.prv, nb, N);
         hipLaunchKernelGGL(k_trs_s, dim3(nb), dim3(kBlock), 0, s, B.sc, B.prv, nb, B.x, B.y, B.r, B.v, B.dinv,
                            B.s, B.z, N);
-        FO_TRY(launch_transport_apply(c, B.theta, B.par, 0, B.z, B.t, s, stop));  // t = L z
+        FO_TRY(sys_apply(c, B, sys, B.z, B.t, s, stop));  // t = A z
         hipLaunchKernelGGL(k_trs_dot, dim3(nb), dim3(kBlock), 0, s, B.sc, B.t, B.s, B.t, B.t, B.pts, nb, N);
         hipLaunchKernelGGL(k_trs_xr, dim3(nb), dim3(kBlock), 0, s, B.sc, B.pts, nb, B.x, B.z, B.s, B.t, B.r, B.rh,
                            B.prr, N);
@@ -305,16 +326,104 @@ int tr_iterations(const fo_ctx *c, const TrBufs &B, int g, hipStream_t s)
 }
 
 // Enqueues g iterations as graphs of 32, 16, ..., 1 iterations.
-int tr_enqueue(fo_ctx *c, const TrBufs &B, int g)
+int tr_enqueue(fo_ctx *c, const TrBufs &B, int sys, int g)
 {
     for (int len = 32; len >= 1; len >>= 1)
         while (g >= len) {
-            auto key = std::make_tuple(40, len, (int)c->scatter, 0);
-            FO_TRY(graph_chunk(c, key, [&](hipStream_t s) { return tr_iterations(c, B, len, s); }));
+            auto key = std::make_tuple(40 + sys, len, (int)c->scatter, 0);
+            FO_TRY(graph_chunk(c, key, [&](hipStream_t s) { return tr_iterations(c, B, sys, len, s); }));
             g -= len;
         }
     return FO_OK;
 }
+
+// One step's solve A x = b (A by `sys`; B.b, B.x = the initial guess, B.dinv
+// the inverted diagonal set by the caller): passes of BiCGStab, each from
+// the recomputed residual, until that residual meets rtol |b|.  pred carries
+// the first batch size from step to step.  Adds operator applications to
+// *iters, raises *worst to the accepted relative residual.
+int solve_step(fo_ctx *c, const TrBufs &B, int sys, const fo_solve_opts *o, int *pred, int64_t *iters,
+               double *worst, int *status)
+{
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    const int nb = red_blocks(N);
+    TrScal h{};
+    auto read = [&]() -> int {
+        FO_HIP(hipMemcpyAsync(&h, B.sc, sizeof(TrScal), hipMemcpyDeviceToHost, s));
+        FO_HIP(hipStreamSynchronize(s));
+        return FO_OK;
+    };
+    launch_dots<double>(1, B.b, B.b, nullptr, nullptr, nullptr, nullptr, N, c->partials, red_blocks(N), s);
+    launch_finish_dots(c->partials, red_blocks(N), 1, &B.sc->bb, s);
+    bool ok = false;
+    int64_t its = 0;  // operator applications of this step
+    double rel = 0.0;
+    for (int restart = 0; restart < 50 && !ok && *status == FO_OK; ++restart) {
+        FO_TRY(sys_apply(c, B, sys, B.x, B.t, s));  // t = A x
+        if (restart > 0) ++its;
+        hipLaunchKernelGGL(k_trs_start, dim3(nb), dim3(kBlock), 0, s, B.b, B.t, B.r, B.rh, B.p, B.v, B.prr, nb,
+                           N);
+        const int64_t left = std::max<int64_t>(o->max_iter - its, 0);
+        hipLaunchKernelGGL(k_trs_check, dim3(1), dim3(64), 0, s, B.sc, B.prr, nb, o->rtol,
+                           (int32_t)std::min<int64_t>(left, INT32_MAX));
+        FO_TRY(read());
+        rel = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        if (h.flag == TR_NAN) {
+            *status = FO_ERR_BREAKDOWN;
+            break;
+        }
+        if (h.flag == TR_CONVERGED) {
+            ok = true;
+            break;
+        }
+        if (its >= o->max_iter) break;
+        // iterate until the device stops; the next pass recomputes b - A x
+        // and accepts the step or restarts
+        int batch = *pred;
+        while (true) {
+            FO_TRY(tr_enqueue(c, B, sys, batch));
+            FO_TRY(read());
+            if (h.flag != TR_RUN) break;
+            batch = 2;
+        }
+        if (restart == 0) *pred = std::min(std::max(h.its / 2 + 1, 1), 64);
+        its += h.its;
+    }
+    *iters += its;
+    *worst = std::max(*worst, rel);
+    if (*status == FO_OK && !ok) *status = FO_NOT_CONVERGED;
+    return FO_OK;
+}
+
+// Reinitialisation: nodal S(phi) = phi / sqrt(phi^2 + h^2) into w[.][2].
+__global__ __launch_bounds__(256) void k_rn_s(const double *__restrict__ phi, double h2, double *__restrict__ w,
+                                              int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i * 3 + 2] = phi[i] / sqrt(phi[i] * phi[i] + h2);
+}
+
+// w[.][0] = u = varphi(t), w[.][1] = v = varphi(t - dt).
+__global__ __launch_bounds__(256) void k_rn_pack(const double *__restrict__ u, const double *__restrict__ v,
+                                                 double *__restrict__ w, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        w[i * 3] = u[i];
+        w[i * 3 + 1] = v[i];
+    }
+}
+
+// Reinitialisation step parameters: dt, h^2, 1/dt^2, Euler flag.
+__global__ void k_rn_par(double *par, double dt, double h2, int euler)
+{
+    par[0] = dt;
+    par[1] = h2;
+    par[2] = 1.0 / (dt * dt);
+    par[3] = euler ? 1.0 : 0.0;
+}
+
+int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096); }
 
 }  // namespace
 
@@ -333,17 +442,10 @@ int fo_transport(fo_ctx *c, const double *theta, double dt, int32_t steps, int32
     hipStream_t s = c->stream;
     const int64_t N = c->N;
     const double h2 = c->transport_h2;
-    const int nb = red_blocks(N);
     FO_HIP(hipMemcpyAsync(B.theta, theta, (size_t)N * c->dim * sizeof(double), hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_tr_par, dim3(1), dim3(1), 0, s, B.par, dt, smooth ? h2 : 0.0, h2);
     FO_TRY(launch_transport_diag(c, B.theta, B.par, B.dinv, s));
     launch_invert_diag<double>(B.dinv, nullptr, N, B.dinv, s);
-    TrScal h{};
-    auto read = [&]() -> int {
-        FO_HIP(hipMemcpyAsync(&h, B.sc, sizeof(TrScal), hipMemcpyDeviceToHost, s));
-        FO_HIP(hipStreamSynchronize(s));
-        return FO_OK;
-    };
     int64_t iters = 0;
     double worst = 0.0;  // largest accepted relative residual
     int status = FO_OK;
@@ -351,45 +453,49 @@ int fo_transport(fo_ctx *c, const double *theta, double dt, int32_t steps, int32
     for (int step = 0; step < steps && status == FO_OK; ++step) {
         FO_TRY(launch_transport_apply(c, B.theta, B.par, 1, phi, B.b, s));  // b = R phi
         FO_HIP(hipMemcpyAsync(B.x, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        launch_dots<double>(1, B.b, B.b, nullptr, nullptr, nullptr, nullptr, N, c->partials, red_blocks(N), s);
-        launch_finish_dots(c->partials, red_blocks(N), 1, &B.sc->bb, s);
-        bool ok = false;
-        int64_t its = 0;  // operator applications of this step
-        double rel = 0.0;
-        for (int restart = 0; restart < 50 && !ok && status == FO_OK; ++restart) {
-            FO_TRY(launch_transport_apply(c, B.theta, B.par, 0, B.x, B.t, s));  // t = L x
-            if (restart > 0) ++its;
-            hipLaunchKernelGGL(k_trs_start, dim3(nb), dim3(kBlock), 0, s, B.b, B.t, B.r, B.rh, B.p, B.v, B.prr,
-                               nb, N);
-            const int64_t left = std::max<int64_t>(o->max_iter - its, 0);
-            hipLaunchKernelGGL(k_trs_check, dim3(1), dim3(64), 0, s, B.sc, B.prr, nb, o->rtol,
-                               (int32_t)std::min<int64_t>(left, INT32_MAX));
-            FO_TRY(read());
-            rel = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
-            if (h.flag == TR_NAN) {
-                status = FO_ERR_BREAKDOWN;
-                break;
-            }
-            if (h.flag == TR_CONVERGED) {
-                ok = true;
-                break;
-            }
-            if (its >= o->max_iter) break;
-            // iterate until the device stops; the next pass recomputes b - L x
-            // and accepts the step or restarts
-            int batch = pred;
-            while (true) {
-                FO_TRY(tr_enqueue(c, B, batch));
-                FO_TRY(read());
-                if (h.flag != TR_RUN) break;
-                batch = 2;
-            }
-            if (restart == 0) pred = std::min(std::max(h.its / 2 + 1, 1), 64);
-            its += h.its;
-        }
-        iters += its;
-        worst = std::max(worst, rel);
-        if (status == FO_OK && !ok) status = FO_NOT_CONVERGED;
+        FO_TRY(solve_step(c, B, SYS_TRANSPORT, o, &pred, &iters, &worst, &status));
+        FO_HIP(hipMemcpyAsync(phi, B.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    FO_HIP(hipStreamSynchronize(s));
+    if (st) {
+        st->status = status;
+        st->iters_inner = (int32_t)std::min<int64_t>(iters, INT32_MAX);
+        st->iters_outer = steps;
+        st->rel_res = worst;
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+int fo_reinit(fo_ctx *c, double *phi, int32_t steps, double t_end, const fo_solve_opts *o, fo_solve_stats *st)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || !phi || !o || !(t_end > 0.0) || !(t_end < INFINITY) || steps < 0 || !(o->rtol > 0.0) ||
+        o->max_iter <= 0)
+        return FO_ERR_ARG;
+    if (c->scatter != FO_SCATTER_TILED || c->tiles.n_tiles <= 0) return FO_ERR_STATE;
+    TrBufs B;
+    FO_TRY(tr_buffers(c, &B));
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    const double h2 = c->transport_h2;
+    const double dt = steps > 0 ? t_end / steps : t_end;
+    const int ng = grid_for(N);
+    hipLaunchKernelGGL(k_rn_s, dim3(ng), dim3(256), 0, s, phi, h2, B.w, N);
+    FO_HIP(hipMemcpyAsync(B.prev, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int64_t iters = 0;
+    double worst = 0.0;
+    int status = FO_OK;
+    int pred = 4;
+    for (int step = 0; step < steps && status == FO_OK; ++step) {
+        hipLaunchKernelGGL(k_rn_pack, dim3(ng), dim3(256), 0, s, phi, B.prev, B.w, N);
+        hipLaunchKernelGGL(k_rn_par, dim3(1), dim3(1), 0, s, B.par + 8, dt, h2, step == 0 ? 1 : 0);
+        FO_TRY(launch_reinit_rhs(c, B.w, B.par + 8, B.b, s));
+        FO_TRY(launch_reinit_diag(c, B.w, B.par + 8, B.dinv, s));
+        launch_invert_diag<double>(B.dinv, nullptr, N, B.dinv, s);
+        FO_HIP(hipMemcpyAsync(B.x, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        FO_TRY(solve_step(c, B, SYS_REINIT, o, &pred, &iters, &worst, &status));
+        FO_HIP(hipMemcpyAsync(B.prev, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         FO_HIP(hipMemcpyAsync(phi, B.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     FO_HIP(hipStreamSynchronize(s));

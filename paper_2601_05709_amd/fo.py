@@ -63,14 +63,15 @@ class fo_loop_opts(C.Structure):
                 ("lgrn_tol", C.c_double), ("ctrn_tol", C.c_double), ("ppl_r", C.c_double),
                 ("ppl_delta0", C.c_double), ("ppl_alpha", C.c_double), ("ppl_beta", C.c_double),
                 ("state", fo_solve_opts), ("descent", fo_solve_opts), ("transport", fo_solve_opts),
-                ("velocity", fo_descent_opts)]
+                ("velocity", fo_descent_opts), ("reinit_step", C.c_int32), ("reinit_iters", C.c_int32),
+                ("reinit_t", C.c_double)]
 
 
 class fo_loop_record(C.Structure):
     _fields_ = [("J", C.c_double), ("vol", C.c_double), ("C", C.c_double), ("L", C.c_double),
                 ("lambda_", C.c_double), ("B_tt", C.c_double), ("t_end", C.c_double), ("dt", C.c_double),
                 ("steps", C.c_int32), ("state_iters", C.c_int32), ("descent_iters", C.c_int32),
-                ("transport_iters", C.c_int32), ("status", C.c_int32), ("pad", C.c_int32)]
+                ("transport_iters", C.c_int32), ("status", C.c_int32), ("reinit_iters", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -103,6 +104,8 @@ EXPORTS = {
                           C.POINTER(fo_solve_stats), _vp], C.c_int),
     "fo_apply_descent": ([_vp, C.POINTER(fo_descent_opts), _vp, _vp], C.c_int),
     "fo_levelset_update": ([_vp, _vp, C.c_double, _vp], C.c_int),
+    "fo_reinit": ([_vp, _vp, C.c_int32, C.c_double, C.POINTER(fo_solve_opts), C.POINTER(fo_solve_stats)],
+                  C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int32)], C.c_int),
     "fo_transport": ([_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.POINTER(fo_solve_opts),
@@ -380,11 +383,24 @@ class Context:
         _check(rc, "fo_transport", allow)
         return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
 
+    def reinit(self, phi, steps: int = 8, t_end: float = 0.1, opts: Optional[SolveOpts] = None,
+               allow_not_converged=False) -> Stats:
+        """Reinitialisation of the level set (fo_reinit): `steps` pseudo-time
+        steps of the diffusive Eikonal equation up to t_end; phi in place."""
+        import torch
+        opts = opts or SolveOpts(rtol=1e-10)
+        st = fo_solve_stats()
+        rc = lib().fo_reinit(self.h, _ptr(phi, torch.float64, self.n_nodes, "phi"), int(steps), float(t_end),
+                             C.byref(opts.c()), C.byref(st))
+        _check(rc, "fo_reinit", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
+        return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
+
     def optimize(self, b, phi, n_iter: int, dopts: "DescentOpts", V: Optional[float] = None, smooth=False,
                  dfactor=1e-2, lv_time=(1e-3, 1e-1), lv_iter=(8, 16), start_to_check=30, prev=10,
                  cost_tol=1e-2, lgrn_tol=1e-2, ctrn_tol=1e-2, ppl=(0.999, 0.5, 2000.0, 0.5),
                  state_opts: Optional[SolveOpts] = None, descent_opts: Optional[SolveOpts] = None,
-                 transport_opts: Optional[SolveOpts] = None, allow_not_converged=False):
+                 transport_opts: Optional[SolveOpts] = None, reinit_step=0, reinit_pars=(8, 0.1),
+                 allow_not_converged=False):
         """The level-set loop (fo_optimize): up to n_iter iterations of the
         paper's Algorithm 1 from phi (updated in place) with the load b;
         V given: volume constraint vol / V = 1 by the PPL method.  Returns
@@ -397,7 +413,7 @@ class Context:
                          float(lv_time[1]), int(lv_iter[0]), int(lv_iter[1]), int(bool(smooth)),
                          int(start_to_check), int(prev), float(cost_tol), float(lgrn_tol), float(ctrn_tol),
                          float(ppl[0]), float(ppl[1]), float(ppl[2]), float(ppl[3]), so.c(), do.c(), to.c(),
-                         dopts.c())
+                         dopts.c(), int(reinit_step or 0), int(reinit_pars[0]), float(reinit_pars[1]))
         recs = (fo_loop_record * max(1, int(n_iter)))()
         n_done, stopped = C.c_int32(0), C.c_int32(0)
         rc = lib().fo_optimize(self.h, C.byref(o), _ptr(b, torch.float64, self.n_dofs, "b"),
@@ -406,7 +422,7 @@ class Context:
         _check(rc, "fo_optimize", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
         out = []
         for r in recs[:n_done.value]:
-            d = {k: getattr(r, k) for k, _ in fo_loop_record._fields_ if k != "pad"}
+            d = {k: getattr(r, k) for k, _ in fo_loop_record._fields_}
             d["lambda"] = d.pop("lambda_")
             out.append(d)
         return out, bool(stopped.value)
