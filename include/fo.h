@@ -279,6 +279,30 @@ int fo_optimize(fo_ctx *ctx, const fo_loop_opts *opts, const double *b, double *
 int fo_reinit(fo_ctx *ctx, double *phi, int32_t steps, double t_end, const fo_solve_opts *opts,
               fo_solve_stats *stats);
 
+/* Heat-conduction model (Section "Heat conduction": eqs. heat_cost,
+ * heat_prob, heat_weak, heat_AOmega): minimise J = int A |grad u|^2 for
+ * -div A grad u = f, u = 0 on Gamma_0, insulated elsewhere, A = 1 in Omega
+ * and the context's ersatz value (the paper: 1e-3) outside, per element from
+ * the level set of fo_set_levelset; P1 u and f (nodal).  The adjoint is
+ * p = -u.  All on the tiled scatter; device pointers; N = n_nodes.
+ *
+ * fo_heat_load: b = int f lambda_a (exact P1 mass), b and f [N].
+ * fo_heat_solve: u [N] with K u = b on the free nodes, u = 0 where gamma0
+ *   [N] (uint8) is nonzero, by the transport step's FP64 Jacobi BiCGStab to
+ *   opts->rtol (recomputed residual).  Returns FO_OK, FO_NOT_CONVERGED,
+ *   FO_ERR_BREAKDOWN, FO_ERR_STATE (no level set, or the atomic scatter) or
+ *   FO_ERR_ARG.
+ * fo_heat_derivative: the descent right-hand side rhs [n_dofs] of S0 =
+ *   2 u grad f, S1 = (2 u f - A |grad u|^2) I + 2 A grad u (x) grad u +
+ *   lambda_vol chi I / V (rhs_(a,i) = -(int S0_i lambda_a + int (S1 grad
+ *   lambda_a)_i), exact for P1), the cost *J = u . K u and *vol = sum_e chi_e
+ *   |T_e| (device scalars).  Feeds fo_descent_solve like fo_shape_derivative. */
+int fo_heat_load(fo_ctx *ctx, const double *f, double *b);
+int fo_heat_solve(fo_ctx *ctx, const uint8_t *gamma0, const double *b, double *u, const fo_solve_opts *opts,
+                  fo_solve_stats *stats);
+int fo_heat_derivative(fo_ctx *ctx, const double *u, const double *f, double lambda_vol, double V, double *rhs,
+                       double *J, double *vol);
+
 /* Kernel timing for measurement tools.  While enabled, every launch of the
  * kernels named below is bracketed by a pair of HIP events recorded on the
  * context's stream; fo_profile_read synchronises the stream and returns the

@@ -67,6 +67,16 @@ int launch_reinit_apply(const fo_ctx *c, const double *w, const double *par, con
                         hipStream_t s, const int32_t *done = nullptr);
 int launch_reinit_diag(const fo_ctx *c, const double *w, const double *par, double *diag, hipStream_t s);
 int launch_reinit_rhs(const fo_ctx *c, const double *w, const double *par, double *rhs, hipStream_t s);
+// Heat-conduction model (HeatOp, HeatDiagOp, MassOp, HeatSdOp): y = K x
+// with the rows of fixed nodes zeroed; the diagonal of K (zero on fixed
+// rows); y = M x (scalar P1 mass); the descent right-hand side [n_dofs] of
+// the heat cost from u and the P1 source f.  Device arrays, N = nodes.
+int launch_heat_apply(const fo_ctx *c, const uint8_t *fixed, const double *x, double *y, hipStream_t s,
+                      const int32_t *done = nullptr);
+int launch_heat_diag(const fo_ctx *c, const uint8_t *fixed, double *diag, hipStream_t s);
+int launch_mass_apply(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+int launch_heat_rhs(const fo_ctx *c, const double *u, const double *f, double lambda_vol, double V, double *rhs,
+                    hipStream_t s);
 
 // Operator of the fused CG kernels.
 enum FusedKind { FUSED_ELAS = 0, FUSED_DESCENT = 1 };

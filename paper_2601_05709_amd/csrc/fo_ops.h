@@ -418,4 +418,145 @@ struct ReinitRhsOp {
     }
 };
 
+// Gradients of the barycentric functions and the measure of a P1 element.
+template <int D>
+__device__ __forceinline__ double p1_grads(const double *const *X, double ga[D + 1][D])
+{
+    const Geom<D, double> g = geom<D, double>(X);
+    const double inv = 1.0 / g.det;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        ga[0][j] = 0.0;
+#pragma unroll
+        for (int a = 1; a <= D; ++a) {
+            ga[a][j] = g.c[a - 1][j] * inv;
+            ga[0][j] -= ga[a][j];
+        }
+    }
+    return fabs(g.det) / (D == 2 ? 2.0 : 6.0);
+}
+
+// Heat-conduction model (eqs. heat_prob, heat_weak, heat_AOmega): scalar
+// P1 operator y_a = sum_b A_e |T| grad lambda_a . grad lambda_b x_b with A_e
+// = 1 in Omega, the ersatz value outside.
+template <int D>
+struct HeatOp {
+    static constexpr int NX = 1, NV = 1;
+    using Elem = uint8_t;
+    const uint8_t *chi;
+    double ersatz;
+    __device__ Elem load(int64_t e) const { return chi[e]; }
+    __device__ void operator()(Elem in, const double *const *X, const double *const *U,
+                               double out[D + 1][1]) const
+    {
+        double ga[D + 1][D];
+        const double w = (in ? 1.0 : ersatz) * p1_grads<D>(X, ga);
+        double gx[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            gx[j] = 0.0;
+#pragma unroll
+            for (int b = 0; b <= D; ++b) gx[j] += U[b][0] * ga[b][j];
+        }
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += ga[a][j] * gx[j];
+            out[a][0] = w * s;
+        }
+    }
+};
+
+template <int D>
+struct HeatDiagOp {
+    static constexpr int NX = 0, NV = 1;
+    using Elem = uint8_t;
+    const uint8_t *chi;
+    double ersatz;
+    __device__ Elem load(int64_t e) const { return chi[e]; }
+    __device__ void operator()(Elem in, const double *const *X, const double *const *,
+                               double out[D + 1][1]) const
+    {
+        double ga[D + 1][D];
+        const double w = (in ? 1.0 : ersatz) * p1_grads<D>(X, ga);
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += ga[a][j] * ga[a][j];
+            out[a][0] = w * s;
+        }
+    }
+};
+
+// Scalar P1 mass: y_a = int lambda_a x = |T| (x_a + sum_b x_b) / ((d+1)(d+2)).
+template <int D>
+struct MassOp {
+    static constexpr int NX = 1, NV = 1;
+    using Elem = uint8_t;
+    __device__ Elem load(int64_t) const { return 0; }
+    __device__ void operator()(Elem, const double *const *X, const double *const *U, double out[D + 1][1]) const
+    {
+        double ga[D + 1][D];
+        const double vol = p1_grads<D>(X, ga);
+        double sx = 0.0;
+#pragma unroll
+        for (int a = 0; a <= D; ++a) sx += U[a][0];
+#pragma unroll
+        for (int a = 0; a <= D; ++a) out[a][0] = vol * (U[a][0] + sx) / ((D + 1) * (D + 2));
+    }
+};
+
+// Descent right-hand side of the heat model from u (input) and the P1 heat
+// source f (tile-staged, aux): S0 = 2 u grad f, S1 = (2 u f - A |grad u|^2) I
+// + 2 A grad u (x) grad u + lambda chi I / V; out[a][i] = -(int S0_i lambda_a
+// + int (S1 grad lambda_a)_i), exact for P1 u and f.
+template <int D>
+struct HeatSdOp {
+    static constexpr int NX = 1, NV = D, NA = 1;
+    using Elem = uint8_t;
+    const uint8_t *chi;
+    const double *aux;  // [N] f
+    double ersatz, lambda_vol, V;
+    __device__ Elem load(int64_t e) const { return chi[e]; }
+    __device__ void operator()(Elem in, const double *const *X, const double *const *U, const double *const *F,
+                               double out[D + 1][D]) const
+    {
+        double ga[D + 1][D];
+        const double vol = p1_grads<D>(X, ga);
+        const double A = in ? 1.0 : ersatz;
+        double su = 0.0, gu[D], gf[D], Mu[D + 1];
+#pragma unroll
+        for (int a = 0; a <= D; ++a) su += U[a][0];
+        double uf = 0.0;
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            Mu[a] = vol * (U[a][0] + su) / ((D + 1) * (D + 2));
+            uf += Mu[a] * F[a][0];
+        }
+        double g2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            gu[j] = gf[j] = 0.0;
+#pragma unroll
+            for (int a = 0; a <= D; ++a) {
+                gu[j] += U[a][0] * ga[a][j];
+                gf[j] += F[a][0] * ga[a][j];
+            }
+            g2 += gu[j] * gu[j];
+        }
+        const double iso = 2.0 * uf - A * vol * g2 + (in ? lambda_vol * vol / V : 0.0);
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            double ug = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) ug += gu[j] * ga[a][j];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                out[a][i] = -(2.0 * gf[i] * Mu[a] + iso * ga[a][i] + 2.0 * A * vol * gu[i] * ug);
+        }
+    }
+};
+
 }  // namespace fo

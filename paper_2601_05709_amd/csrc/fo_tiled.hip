@@ -578,7 +578,9 @@ static int prepare_dim()
            ensure_lds_attr_cg<D, double, DescentOp<D, double>>() |
            ensure_lds_attr_cg<D, float, DescentOp<D, float>>() | ensure_lds_attr<D, double, TransportOp<D>>() |
            ensure_lds_attr<D, double, TransportDiagOp<D>>() | ensure_lds_attr<D, double, ReinitOp<D>>() |
-           ensure_lds_attr<D, double, ReinitDiagOp<D>>() | ensure_lds_attr<D, double, ReinitRhsOp<D>>();
+           ensure_lds_attr<D, double, ReinitDiagOp<D>>() | ensure_lds_attr<D, double, ReinitRhsOp<D>>() |
+           ensure_lds_attr<D, double, HeatOp<D>>() | ensure_lds_attr<D, double, HeatDiagOp<D>>() |
+           ensure_lds_attr<D, double, MassOp<D>>() | ensure_lds_attr<D, double, HeatSdOp<D>>();
 }
 
 int tiled_prepare(const fo_ctx *c)
@@ -881,6 +883,44 @@ int launch_reinit_rhs(const fo_ctx *c, const double *w, const double *par, doubl
         return run_tiled<2, double>(c, ReinitRhsOp<2>{w, par}, c->coords, (const double *)nullptr, rhs, nullptr,
                                     s);
     return run_tiled<3, double>(c, ReinitRhsOp<3>{w, par}, c->coords, (const double *)nullptr, rhs, nullptr, s);
+}
+
+int launch_heat_apply(const fo_ctx *c, const uint8_t *fixed, const double *x, double *y, hipStream_t s,
+                      const int32_t *done)
+{
+    if (c->has_isolated) launch_fill<double>(y, c->N, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, HeatOp<2>{c->chi, c->ersatz}, c->coords, x, y, fixed, s, -1, -1, nullptr,
+                                    done);
+    return run_tiled<3, double>(c, HeatOp<3>{c->chi, c->ersatz}, c->coords, x, y, fixed, s, -1, -1, nullptr, done);
+}
+
+int launch_heat_diag(const fo_ctx *c, const uint8_t *fixed, double *diag, hipStream_t s)
+{
+    launch_fill<double>(diag, c->N, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, HeatDiagOp<2>{c->chi, c->ersatz}, c->coords, (const double *)nullptr, diag,
+                                    fixed, s);
+    return run_tiled<3, double>(c, HeatDiagOp<3>{c->chi, c->ersatz}, c->coords, (const double *)nullptr, diag,
+                                fixed, s);
+}
+
+int launch_mass_apply(const fo_ctx *c, const double *x, double *y, hipStream_t s)
+{
+    launch_fill<double>(y, c->N, 0.0, s);
+    if (c->dim == 2) return run_tiled<2, double>(c, MassOp<2>{}, c->coords, x, y, nullptr, s);
+    return run_tiled<3, double>(c, MassOp<3>{}, c->coords, x, y, nullptr, s);
+}
+
+int launch_heat_rhs(const fo_ctx *c, const double *u, const double *f, double lambda_vol, double V, double *rhs,
+                    hipStream_t s)
+{
+    launch_fill<double>(rhs, c->ndof, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, HeatSdOp<2>{c->chi, f, c->ersatz, lambda_vol, V}, c->coords, u, rhs,
+                                    nullptr, s);
+    return run_tiled<3, double>(c, HeatSdOp<3>{c->chi, f, c->ersatz, lambda_vol, V}, c->coords, u, rhs, nullptr,
+                                s);
 }
 
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s)

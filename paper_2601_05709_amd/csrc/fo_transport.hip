@@ -6,7 +6,9 @@
 // of the level set (Section "Other implementation aspects", eqs. HJ,
 // grad_H, weak_HJ): pseudo-time steps of the diffusive Eikonal equation,
 // each solving Lhat varphi' = rhs (ReinitOp, ReinitRhsOp), explicit Euler
-// first and Adams-Bashforth 2 after it.
+// first and Adams-Bashforth 2 after it.  The heat-conduction model's state
+// (Section "Heat conduction": scalar P1 stiffness with identity rows on
+// Gamma_0) is solved the same way.
 //
 // Both solve with Jacobi-preconditioned BiCGStab in FP64 from the previous
 // iterate.  The Krylov scalars stay on the device: every block of a vector
@@ -257,16 +259,18 @@ struct TrBufs {
     double *theta, *par, *w, *prev, *b, *x, *r, *rh, *p, *v, *y, *s, *z, *t, *dinv;
     double *prr, *prv, *pts;  // partials [2 nb], [nb], [2 nb]
     TrScal *sc;
+    uint8_t *mask;            // [N] fixed nodes of the heat problem
 };
 
-// Which step matrix the solver applies: the transport L or the
-// reinitialisation Lhat (its parameters at par + 8).
-enum { SYS_TRANSPORT = 0, SYS_REINIT = 1 };
+// Which matrix the solver applies: the transport L, the reinitialisation
+// Lhat (its parameters at par + 8), or the heat stiffness with identity rows
+// on the fixed nodes.
+enum { SYS_TRANSPORT = 0, SYS_REINIT = 1, SYS_HEAT = 2 };
 
 int tr_buffers(fo_ctx *c, TrBufs *o)
 {
     const int64_t N = c->N;
-    const int64_t n_dbl = N * c->dim + 16 + 3 * N + N + 11 * N + 5 * (int64_t)kRedBlocks;
+    const int64_t n_dbl = N * c->dim + 16 + 3 * N + N + 11 * N + 5 * (int64_t)kRedBlocks + (N + 7) / 8;
     if (!c->tr_buf) {
         const size_t bytes = (size_t)n_dbl * sizeof(double) + sizeof(TrScal) + 256;
         void *mem = nullptr;
@@ -293,14 +297,31 @@ int tr_buffers(fo_ctx *c, TrBufs *o)
     o->prv = m + 2 * kRedBlocks;
     o->pts = m + 3 * kRedBlocks;
     m += 5 * kRedBlocks;
+    o->mask = reinterpret_cast<uint8_t *>(m);
+    m += (N + 7) / 8;
     o->sc = reinterpret_cast<TrScal *>(m);
     return FO_OK;
+}
+
+// Heat system: y_i = x_i on fixed nodes (their rows of K were zeroed).
+__global__ __launch_bounds__(256) void k_heat_identity(const uint8_t *__restrict__ mask, const double *__restrict__ x,
+                                                       double *__restrict__ y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (mask[i]) y[i] = x[i];
 }
 
 int sys_apply(const fo_ctx *c, const TrBufs &B, int sys, const double *x, double *y, hipStream_t s,
               const int32_t *stop = nullptr)
 {
     if (sys == SYS_REINIT) return launch_reinit_apply(c, B.w, B.par + 8, x, y, s, stop);
+    if (sys == SYS_HEAT) {
+        FO_TRY(launch_heat_apply(c, B.mask, x, y, s, stop));
+        const int64_t N = c->N;
+        hipLaunchKernelGGL(k_heat_identity, dim3((int)std::min<int64_t>((N + 255) / 256, 4096)), dim3(256), 0, s,
+                           B.mask, x, y, N);
+        return FO_OK;
+    }
     return launch_transport_apply(c, B.theta, B.par, 0, x, y, s, stop);
 }
 
@@ -423,6 +444,53 @@ __global__ void k_rn_par(double *par, double dt, double h2, int euler)
     par[3] = euler ? 1.0 : 0.0;
 }
 
+// Heat system set-up: b = 0 and diag = 1 on fixed nodes.
+__global__ __launch_bounds__(256) void k_heat_fix(const uint8_t *__restrict__ mask, double *__restrict__ b,
+                                                  double *__restrict__ diag, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (mask[i]) {
+            b[i] = 0.0;
+            diag[i] = 1.0;
+        }
+}
+
+// Volume sum_e chi_e |T_e|: partials per block into part[blockIdx.x].
+template <int D>
+__global__ __launch_bounds__(256) void k_heat_vol(const int32_t *__restrict__ conn, int64_t E,
+                                                  const double *__restrict__ coords, const uint8_t *__restrict__ chi,
+                                                  double *__restrict__ part)
+{
+    __shared__ double lds[16];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        if (!chi[e]) continue;
+        double P[D + 1][D];
+#pragma unroll
+        for (int a = 0; a <= D; ++a)
+#pragma unroll
+            for (int j = 0; j < D; ++j) P[a][j] = coords[(int64_t)conn[(int64_t)a * E + e] * D + j];
+        double det;
+        if constexpr (D == 2) {
+            det = (P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[2][0] - P[0][0]) * (P[1][1] - P[0][1]);
+            s += fabs(det) / 2.0;
+        } else {
+            double u[3], v[3], w[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                u[j] = P[1][j] - P[0][j];
+                v[j] = P[2][j] - P[0][j];
+                w[j] = P[3][j] - P[0][j];
+            }
+            det = u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
+                  u[2] * (v[0] * w[1] - v[1] * w[0]);
+            s += fabs(det) / 6.0;
+        }
+    }
+    s = block_sum_last(s, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096); }
 
 }  // namespace
@@ -507,6 +575,73 @@ int fo_reinit(fo_ctx *c, double *phi, int32_t steps, double t_end, const fo_solv
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
+}
+
+int fo_heat_load(fo_ctx *c, const double *f, double *b)
+{
+    if (!c || !f || !b) return FO_ERR_ARG;
+    if (c->scatter != FO_SCATTER_TILED || c->tiles.n_tiles <= 0) return FO_ERR_STATE;
+    FO_TRY(launch_mass_apply(c, f, b, c->stream));
+    FO_HIP(hipStreamSynchronize(c->stream));
+    return FO_OK;
+}
+
+int fo_heat_solve(fo_ctx *c, const uint8_t *gamma0, const double *b, double *u, const fo_solve_opts *o,
+                  fo_solve_stats *st)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || !gamma0 || !b || !u || !o || !(o->rtol > 0.0) || o->max_iter <= 0) return FO_ERR_ARG;
+    if (c->scatter != FO_SCATTER_TILED || c->tiles.n_tiles <= 0 || !c->have_phi) return FO_ERR_STATE;
+    TrBufs B;
+    FO_TRY(tr_buffers(c, &B));
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    const int ng = grid_for(N);
+    FO_HIP(hipMemcpyAsync(B.mask, gamma0, (size_t)N, hipMemcpyDeviceToDevice, s));
+    FO_HIP(hipMemcpyAsync(B.b, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    FO_TRY(launch_heat_diag(c, B.mask, B.dinv, s));
+    hipLaunchKernelGGL(k_heat_fix, dim3(ng), dim3(256), 0, s, B.mask, B.b, B.dinv, N);
+    launch_invert_diag<double>(B.dinv, nullptr, N, B.dinv, s);
+    launch_fill<double>(B.x, N, 0.0, s);
+    int64_t iters = 0;
+    double worst = 0.0;
+    int status = FO_OK;
+    int pred = 8;
+    FO_TRY(solve_step(c, B, SYS_HEAT, o, &pred, &iters, &worst, &status));
+    FO_HIP(hipMemcpyAsync(u, B.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    FO_HIP(hipStreamSynchronize(s));
+    if (st) {
+        st->status = status;
+        st->iters_inner = (int32_t)std::min<int64_t>(iters, INT32_MAX);
+        st->iters_outer = 0;
+        st->rel_res = worst;
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+int fo_heat_derivative(fo_ctx *c, const double *u, const double *f, double lambda_vol, double V, double *rhs,
+                       double *J, double *vol)
+{
+    if (!c || !u || !f || !rhs || !J || !vol || !(V > 0.0)) return FO_ERR_ARG;
+    if (c->scatter != FO_SCATTER_TILED || c->tiles.n_tiles <= 0 || !c->have_phi) return FO_ERR_STATE;
+    TrBufs B;
+    FO_TRY(tr_buffers(c, &B));
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    FO_TRY(launch_heat_rhs(c, u, f, lambda_vol, V, rhs, s));
+    // J = u . K u over all nodes (u vanishes on the fixed ones)
+    FO_TRY(launch_heat_apply(c, nullptr, u, B.t, s));
+    launch_dots<double>(1, u, B.t, nullptr, nullptr, nullptr, nullptr, N, c->partials, red_blocks(N), s);
+    launch_finish_dots(c->partials, red_blocks(N), 1, J, s);
+    const int nb = red_blocks(c->E);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_heat_vol<2>, dim3(nb), dim3(256), 0, s, c->conn, c->E, c->coords, c->chi, c->partials);
+    else
+        hipLaunchKernelGGL(k_heat_vol<3>, dim3(nb), dim3(256), 0, s, c->conn, c->E, c->coords, c->chi, c->partials);
+    launch_finish_dots(c->partials, nb, 1, vol, s);
+    FO_HIP(hipStreamSynchronize(s));
+    return FO_OK;
 }
 
 }  // extern "C"

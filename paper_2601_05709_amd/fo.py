@@ -104,6 +104,9 @@ EXPORTS = {
                           C.POINTER(fo_solve_stats), _vp], C.c_int),
     "fo_apply_descent": ([_vp, C.POINTER(fo_descent_opts), _vp, _vp], C.c_int),
     "fo_levelset_update": ([_vp, _vp, C.c_double, _vp], C.c_int),
+    "fo_heat_load": ([_vp, _vp, _vp], C.c_int),
+    "fo_heat_solve": ([_vp, _vp, _vp, _vp, C.POINTER(fo_solve_opts), C.POINTER(fo_solve_stats)], C.c_int),
+    "fo_heat_derivative": ([_vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp, _vp], C.c_int),
     "fo_reinit": ([_vp, _vp, C.c_int32, C.c_double, C.POINTER(fo_solve_opts), C.POINTER(fo_solve_stats)],
                   C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
@@ -382,6 +385,31 @@ class Context:
                                 C.byref(opts.c()), C.byref(st))
         _check(rc, "fo_transport", allow)
         return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
+
+    def heat_load(self, f, b):
+        """b = int f lambda_a for the nodal heat source f (fo_heat_load)."""
+        import torch
+        _check(lib().fo_heat_load(self.h, _ptr(f, torch.float64, self.n_nodes, "f"),
+                                  _ptr(b, torch.float64, self.n_nodes, "b")), "fo_heat_load")
+
+    def heat_solve(self, gamma0, b, u, opts: Optional[SolveOpts] = None, allow_not_converged=False) -> Stats:
+        """Heat state u (fo_heat_solve): K u = b, u = 0 where gamma0 (uint8 [N]) is set."""
+        import torch
+        opts = opts or SolveOpts(rtol=1e-10)
+        st = fo_solve_stats()
+        rc = lib().fo_heat_solve(self.h, _ptr(gamma0, torch.uint8, self.n_nodes, "gamma0"),
+                                 _ptr(b, torch.float64, self.n_nodes, "b"), _ptr(u, torch.float64, self.n_nodes, "u"),
+                                 C.byref(opts.c()), C.byref(st))
+        _check(rc, "fo_heat_solve", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
+        return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
+
+    def heat_derivative(self, u, f, rhs, J, vol, lambda_vol=0.0, V=1.0):
+        """Descent right-hand side, cost and volume of the heat model (fo_heat_derivative)."""
+        import torch
+        _check(lib().fo_heat_derivative(self.h, _ptr(u, torch.float64, self.n_nodes, "u"),
+                                        _ptr(f, torch.float64, self.n_nodes, "f"), float(lambda_vol), float(V),
+                                        _ptr(rhs, torch.float64, self.n_dofs, "rhs"), _ptr(J, torch.float64, 1, "J"),
+                                        _ptr(vol, torch.float64, 1, "vol")), "fo_heat_derivative")
 
     def reinit(self, phi, steps: int = 8, t_end: float = 0.1, opts: Optional[SolveOpts] = None,
                allow_not_converged=False) -> Stats:

@@ -1,0 +1,94 @@
+"""GPU parity of the heat-conduction model (fo_heat_load, fo_heat_solve,
+fo_heat_derivative: scalar P1 state on the tiled operators, FP64 Jacobi
+BiCGStab, and the S0/S1 descent right-hand side) against the FP64 oracle,
+through the C ABI."""
+import numpy as np
+import pytest
+
+import fo_inputs as fi
+from oracle import heat as oh
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2601_05709_amd import fo  # noqa: E402
+
+WORKLOADS = {
+    "2d_37x19": lambda: fi.cantilever_2d((37, 19)),
+    "3d_16x8x8": lambda: fi.cantilever_3d((16, 8, 8)),
+    "3d_26x13x11": lambda: fi.cantilever_3d((26, 13, 11)),
+}
+
+
+def dev(a, dtype=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def source(X):
+    return 1.0 + 0.5 * np.sin(2.0 * X[:, 0]) * np.cos(1.5 * X[:, 1])
+
+
+def gamma0(m):
+    return (np.abs(m.coords[:, 0]) < 1e-12).astype(np.uint8)
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+@pytest.mark.parametrize("lam", [0.0, 0.7])
+def test_heat_matches_oracle(name, lam):
+    w = WORKLOADS[name]()
+    m = w.mesh
+    f = source(m.coords)
+    fx = gamma0(m)
+    V = 0.6
+    print("case heat %s lambda %g" % (name, lam), flush=True)
+    u_ref, J_ref, vol_ref, rhs_ref, A, chi = oh.heat_iteration(m.dim, m.coords, m.conn, w.phi, f, fx,
+                                                               ersatz=w.ersatz, lambda_vol=lam, V=V)
+    b_ref = oh.mass(m.dim, m.coords, m.conn) @ f
+    ctx = fo.Context.from_workload(w)
+    ctx.set_levelset(dev(w.phi))
+    f_d = dev(f)
+    b = torch.zeros(m.n_nodes, dtype=torch.float64, device="cuda")
+    ctx.heat_load(f_d, b)
+    np.testing.assert_allclose(b.cpu().numpy(), b_ref, rtol=1e-13, atol=1e-16)
+    u = torch.zeros_like(b)
+    st = ctx.heat_solve(dev(fx, np.uint8), b, u, fo.SolveOpts(rtol=1e-12))
+    assert st.status == 0 and st.iters_inner > 0
+    assert np.linalg.norm(u.cpu().numpy() - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    assert np.all(u.cpu().numpy()[fx == 1] == 0.0)
+    rhs = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vol = torch.zeros(1, dtype=torch.float64, device="cuda")
+    # the derivative from the oracle's state, so that it is checked on its own
+    ctx.heat_derivative(dev(u_ref), f_d, rhs, J, vol, lambda_vol=lam, V=V)
+    np.testing.assert_allclose(rhs.cpu().numpy().reshape(-1, m.dim), rhs_ref, rtol=1e-12,
+                               atol=1e-13 * np.abs(rhs_ref).max())
+    assert float(J) == pytest.approx(J_ref, rel=1e-12)
+    assert float(vol) == pytest.approx(vol_ref, rel=1e-13)
+
+
+def test_heat_edge_cases():
+    w = WORKLOADS["2d_37x19"]()
+    m = w.mesh
+    ctx = fo.Context.from_workload(w)
+    b = torch.zeros(m.n_nodes, dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(b)
+    fx = dev(gamma0(m), np.uint8)
+    # no level set yet: refused
+    with pytest.raises(fo.FoError):
+        ctx.heat_solve(fx, b, u)
+    ctx.set_levelset(dev(w.phi))
+    # a zero source gives u = 0 at once
+    st = ctx.heat_solve(fx, b, u, fo.SolveOpts(rtol=1e-12))
+    assert st.status == 0 and torch.count_nonzero(u) == 0
+    with pytest.raises(fo.FoError):
+        ctx.heat_derivative(u, b, torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda"),
+                            torch.zeros(1, dtype=torch.float64, device="cuda"),
+                            torch.zeros(1, dtype=torch.float64, device="cuda"), V=0.0)
+    # the heat solve shares the transport solver: both stay right when interleaved
+    f = source(m.coords)
+    u_ref, *_ = oh.heat_iteration(m.dim, m.coords, m.conn, w.phi, f, gamma0(m), ersatz=w.ersatz)
+    ctx.heat_load(dev(f), b)
+    phi = dev(w.phi)
+    ctx.transport(dev(np.full(m.n_dofs, 0.1)), 0.01, 2, phi, fo.SolveOpts(rtol=1e-12))
+    ctx.heat_solve(fx, b, u, fo.SolveOpts(rtol=1e-12))
+    assert np.linalg.norm(u.cpu().numpy() - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
