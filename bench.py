@@ -322,6 +322,37 @@ def main():
     t_rn = time.perf_counter() - t0
     log("reinitialisation: 8 steps, %d BiCGStab operator applications, %.1f ms" % (st_rn.iters_inner, t_rn * 1e3))
 
+    # the heat-conduction model on the same mesh (scalar P1 state, f = 1,
+    # temperature fixed on the x = 0 face): load, state solve to rel. res
+    # 1e-8, derivative, then the velocity solve as in the timed iteration
+    f_ht = torch.ones(m.n_nodes, dtype=torch.float64, device="cuda")
+    g0_ht = torch.from_numpy((np.abs(m.coords[:, 0]) < 1e-12).astype(np.uint8)).cuda()
+    b_ht = torch.zeros_like(f_ht)
+    u_ht = torch.zeros_like(f_ht)
+    rhs_ht = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    J_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vol_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
+    th_ht = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    Bt_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
+    it_ir.ctx.set_levelset(it_ir.phi0)
+
+    def heat_step():
+        it_ir.ctx.heat_load(f_ht, b_ht)
+        s_ht = it_ir.ctx.heat_solve(g0_ht, b_ht, u_ht, fo.SolveOpts(rtol=1e-8))
+        it_ir.ctx.heat_derivative(u_ht, f_ht, rhs_ht, J_ht, vol_ht)
+        d_ht = it_ir.ctx.descent_solve(it_ir.dopts, rhs_ht, th_ht, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8),
+                                       Bt_ht)
+        return s_ht, d_ht
+
+    heat_step()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_ht, dst_ht = heat_step()
+    torch.cuda.synchronize()
+    t_ht = time.perf_counter() - t0
+    log("heat model: state %d BiCGStab applications (%.1f ms), descent %d its, %.1f ms in all"
+        % (st_ht.iters_inner, st_ht.seconds * 1e3, dst_ht.iters_inner, t_ht * 1e3))
+
     # the paper's loop (Algorithm 1, fo_optimize): a few iterations from the
     # initial design with the PPL volume constraint at 90% of its volume, the
     # paper's time-stepping defaults and transport step
@@ -409,6 +440,10 @@ def main():
                            "Adams-Bashforth 2, 8 steps to pseudo-time 0.1, FP64 Jacobi BiCGStab to rel. res 1e-10) "
                            "of the transported level set, not part of the timed iteration",
                    "ms": t_rn * 1e3, "operator_applications": st_rn.iters_inner, "max_rel_res": st_rn.rel_res},
+        "heat": {"what": "the paper's heat-conduction model on the same mesh (f = 1, u = 0 on x = 0): load, "
+                         "FP64 state solve to rel. res 1e-8, S0/S1 derivative, FP32 + refinement velocity solve",
+                 "ms": t_ht * 1e3, "state_ms": st_ht.seconds * 1e3, "state_operator_applications": st_ht.iters_inner,
+                 "descent_iters": dst_ht.iters_inner, "J": float(J_ht.item())},
         "loop": {"what": "the paper's Algorithm 1 (fo_optimize): state and velocity solves in FP32 + FP64 "
                          "refinement, PPL volume constraint at 90% of the initial volume, transport step, "
                          "from the initial design", "iterations": len(lp_recs), "seconds": t_lp,
