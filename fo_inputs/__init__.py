@@ -396,6 +396,45 @@ SERVING_MESHES = (("2d", (128, 64)), ("2d", (256, 128)), ("3d", (32, 16, 16)),
                   ("3d", (64, 32, 32)), ("3d", (80, 40, 40)))
 
 
+class InverseWorkload:
+    """Inverse elasticity (Kohn-Vogelius) inputs, all on the host: the mesh
+    with its boundary facets restricted to Gamma_1 (the faces other than
+    x = 0), the clamp masks of Gamma_0 and of the whole boundary, one force
+    f on Gamma_1 with its displacement data g (a field on the whole domain
+    that vanishes on Gamma_0, here linear: g(x) = x_0 a), the initial level
+    set (a disk or ball of the stiffer material) and the weights."""
+
+    def __init__(self, mesh, fixed0, fixed_all, f, g, phi, kappa=10.0, alpha=1.0, beta=1.0, E=1.0, nu=0.3,
+                 plane_stress=1):
+        self.mesh, self.fixed0, self.fixed_all = mesh, fixed0, fixed_all
+        self.f, self.g, self.phi = f, g, phi
+        self.kappa, self.alpha, self.beta = kappa, alpha, beta
+        self.E, self.nu, self.plane_stress = E, nu, plane_stress
+
+
+def inverse_elasticity(cells, g_scale=(0.02, -0.01, 0.015)) -> InverseWorkload:
+    """[0,2]x[0,1] (2D) or [0,2]x[0,1]^2 (3D); Gamma_0 = {x = 0}; an inward
+    unit traction on the middle of the face x = 2; an inclusion of radius
+    0.25 centred at (1, 0.5[, 0.5])."""
+    d = len(cells)
+    lengths = (2.0, 1.0) if d == 2 else (2.0, 1.0, 1.0)
+    base = structured_mesh(cells, lengths)
+    keep = base.bnormal[:, 0] != -1.0
+    mesh = Mesh(base.dim, base.coords, base.conn, np.ascontiguousarray(base.bfacets[:, keep]),
+                np.ascontiguousarray(base.bnormal[keep]), base.lengths, base.cells)
+    lo, hi = ((0.3,), (0.7,)) if d == 2 else ((0.3, 0.3), (0.7, 0.7))
+    f = traction_load(base, (-1.0,) + (0.0,) * (d - 1), lo, hi)
+    bnodes = np.unique(base.bfacets.ravel())
+    fixed_all = np.zeros(mesh.n_nodes * d, dtype=np.uint8)
+    for i in range(d):
+        fixed_all[bnodes * d + i] = 1
+    a = np.asarray(g_scale[:d], dtype=np.float64)
+    g = (mesh.coords[:, :1] * a[None, :]).ravel()
+    c = np.array([1.0, 0.5, 0.5][:d])
+    phi = np.linalg.norm(mesh.coords - c, axis=1) - 0.25
+    return InverseWorkload(mesh, clamp_mask(base), fixed_all, f, g, phi, plane_stress=1 if d == 2 else 0)
+
+
 @functools.lru_cache(maxsize=8)
 def _shared_mesh(cells, lengths) -> Mesh:
     """Structured mesh shared (read-only) by the requests on the same grid."""

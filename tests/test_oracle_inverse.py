@@ -1,0 +1,78 @@
+"""Pins of the oracle's inverse elasticity problem (eqs. cost, f-prob, g-prob,
+w-f, w-g, the adjoints of eqs. dL1/dL2 and the shape derivative of eq.
+SDelast_inv) against facts that do not come from its formulas: central
+finite differences of the discrete cost under a smooth mesh motion that
+fixes the boundary (exact for P1 with a linear g and A frozen per element),
+the vanishing of cost, adjoints and derivative at the true inclusion, and
+the boundary conditions of each solution."""
+import numpy as np
+import pytest
+
+import fo_inputs as fi
+from oracle import inverse as oi
+
+
+def bubble(X, lengths):
+    d = X.shape[1]
+    bub = np.ones(X.shape[0])
+    for k in range(d):
+        bub *= X[:, k] * (lengths[k] - X[:, k])
+    cols = [bub * (1.0 + 0.5 * X[:, 0]), bub * np.sin(3.0 * X[:, 1] + 0.2)]
+    if d == 3:
+        cols.append(bub * (X[:, 2] - 0.3 * X[:, 0]))
+    th = np.stack(cols, axis=1)
+    return th / np.abs(th).max()
+
+
+def moved_cost(wi, X, a):
+    """Cost of the inverse problem on the mesh moved to X (A frozen by phi,
+    g = x_0 a re-evaluated at the moved nodes)."""
+    g = (X[:, :1] * a[None, :]).ravel()
+    wj = fi.InverseWorkload(wi.mesh, wi.fixed0, wi.fixed_all, wi.f, g, wi.phi, wi.kappa, wi.alpha, wi.beta,
+                            wi.E, wi.nu, wi.plane_stress)
+    return oi.inverse_iteration(wj, X=X)["J"]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_shape_derivative_matches_finite_differences(dim):
+    cells = (24, 12) if dim == 2 else (12, 6, 6)
+    wi = fi.inverse_elasticity(cells)
+    m = wi.mesh
+    a = np.array([0.02, -0.01, 0.015][:dim])
+    r = oi.inverse_iteration(wi)
+    assert 0 < r["chi"].sum() < m.n_elems
+    assert r["J"] > 0
+    theta = bubble(m.coords, m.lengths)
+    dJ = -float(r["rhs"] @ theta.ravel())
+    t = 1e-4
+    fd = (moved_cost(wi, m.coords + t * theta, a) - moved_cost(wi, m.coords - t * theta, a)) / (2 * t)
+    assert abs(fd - dJ) <= 1e-6 * abs(dJ), (fd, dJ)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_true_inclusion_gives_zero_cost_and_derivative(dim):
+    """With g the f-problem's solution for the inclusion itself, y = u: the
+    lifted part v and both adjoints vanish, and so do J and S."""
+    cells = (24, 12) if dim == 2 else (12, 6, 6)
+    wi = fi.inverse_elasticity(cells)
+    r0 = oi.inverse_iteration(wi)
+    wi.g = r0["u"].copy()
+    r = oi.inverse_iteration(wi)
+    scale = np.abs(r0["u"]).max()
+    assert np.abs(r["v"]).max() <= 1e-12 * scale
+    assert r["J"] <= 1e-24
+    assert np.abs(r["p"]).max() <= 1e-14 and np.abs(r["q"]).max() <= 1e-14
+    assert np.abs(r["rhs"]).max() <= 1e-12 * np.abs(r0["rhs"]).max()
+
+
+def test_boundary_conditions_of_each_solution():
+    wi = fi.inverse_elasticity((24, 12))
+    r = oi.inverse_iteration(wi)
+    assert np.all(r["u"][wi.fixed0 == 1] == 0) and np.all(r["p"][wi.fixed0 == 1] == 0)
+    assert np.all(r["v"][wi.fixed_all == 1] == 0) and np.all(r["q"][wi.fixed_all == 1] == 0)
+    # g vanishes on Gamma_0, so y = v + g meets u's clamp there
+    assert np.all(wi.g[wi.fixed0 == 1] == 0)
+    # theta in H^1_0
+    th, info = oi.velocity(wi, r["rhs"])
+    assert info.status == 0 and np.all(th[wi.fixed_all == 1] == 0)
+    assert float(th @ r["rhs"]) > 0
