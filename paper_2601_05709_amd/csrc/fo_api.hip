@@ -120,13 +120,31 @@ int elas_apply<float>(fo_ctx *c, const float *x, float *y, hipStream_t s)
 
 bool tiled(const fo_ctx *c) { return c->scatter == FO_SCATTER_TILED && c->tiles.n_tiles > 0; }
 
+// y = 0 where the mask is set.
+__global__ __launch_bounds__(256) void k_zero_masked(const uint8_t *__restrict__ fixed, double *__restrict__ y,
+                                                     int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (fixed[i]) y[i] = 0.0;
+}
+
+void zero_masked(const fo_ctx *c, const uint8_t *fixed, double *y, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>((c->ndof + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_masked, dim3(nb), dim3(256), 0, s, fixed, y, c->ndof);
+}
+
+// y = B x; with a velocity mask, the rows of masked unknowns are zero (the
+// iterates vanish there, so their columns never contribute).
 int descent_apply(fo_ctx *c, const double *x, double *y, hipStream_t s)
 {
     if (tiled(c)) {
         if (c->has_isolated) launch_fill<double>(y, c->ndof, 0.0, s);
-        return launch_descent_apply_tiled(c, x, y, s);
+        FO_TRY(launch_descent_apply_tiled(c, x, y, s));
+    } else {
+        launch_descent_apply_atomic(c, x, y, s);
     }
-    launch_descent_apply_atomic(c, x, y, s);
+    if (c->descent.fixed) zero_masked(c, c->descent.fixed, y, s);
     return FO_OK;
 }
 
@@ -181,6 +199,7 @@ int cg_apply(fo_ctx *c, OpKind k, const T *p, T *q, const int32_t *done, hipStre
         } else {
             launch_descent_apply_atomic(c, (const double *)p, (double *)q, s);
         }
+        if (c->descent.fixed) zero_masked(c, c->descent.fixed, (double *)q, s);
     } else {
         FO_TRY(elas_apply<T>(c, p, q, s));
     }
@@ -533,7 +552,8 @@ namespace {
 bool descent_same(const fo_ctx *c, const fo_descent_opts *d)
 {
     const DescentSetup &s = c->descent;
-    if (!s.valid || s.alpha != d->alpha || s.gamma_n != d->gamma_n || s.gamma_s != d->gamma_s)
+    if (!s.valid || s.alpha != d->alpha || s.gamma_n != d->gamma_n || s.gamma_s != d->gamma_s ||
+        s.fixed != d->fixed)
         return false;
     size_t nb = (size_t)std::max(0, d->n_boxes) * 2 * c->dim;
     if (s.boxes.size() != nb) return false;
@@ -552,11 +572,13 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
         FO_TRY(dev_alloc(c, &ds.diag, c->ndof));
         FO_TRY(dev_alloc(c, &ds.dinv, c->ndof));
         FO_TRY(dev_alloc(c, &ds.dinv32, c->ndof));
+        FO_TRY(dev_alloc(c, &ds.rhs, c->ndof));
     }
     ++c->descent_version;
     ds.alpha = d->alpha;
     ds.gamma_n = d->gamma_n;
     ds.gamma_s = d->gamma_s;
+    ds.fixed = d->fixed;
     int nbx = std::max(0, d->n_boxes);
     ds.boxes.assign(d->boxes, d->boxes + (size_t)nbx * 2 * c->dim);
     if (nbx > 0) {
@@ -576,8 +598,8 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
     } else {
         launch_descent_diag(c, ds.diag, s);
     }
-    launch_invert_diag<double>(ds.diag, nullptr, c->ndof, ds.dinv, s);
-    launch_invert_diag<float>(ds.diag, nullptr, c->ndof, ds.dinv32, s);
+    launch_invert_diag<double>(ds.diag, ds.fixed, c->ndof, ds.dinv, s);
+    launch_invert_diag<float>(ds.diag, ds.fixed, c->ndof, ds.dinv32, s);
     ds.valid = true;
     return FO_OK;
 }
@@ -1204,9 +1226,15 @@ int fo_descent_solve(fo_ctx *c, const fo_descent_opts *d, const double *rhs, dou
     FO_TRY(descent_prepare(c, d));
     hipStream_t s = c->stream;
     fo_solve_stats one{};
+    const double *b = rhs;
+    if (c->descent.fixed) {  // theta = 0 on the mask: solve with those entries of rhs zeroed
+        FO_HIP(hipMemcpyAsync(c->descent.rhs, rhs, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+        zero_masked(c, c->descent.fixed, c->descent.rhs, s);
+        b = c->descent.rhs;
+    }
     int rc = o->precision == FO_FP32_IR && fused_path(c, OP_DESCENT64)
-                 ? solve_ir(c, OP_DESCENT64, rhs, o, &one)
-                 : solve_fp64(c, OP_DESCENT64, rhs, c->descent.dinv, o, &one);
+                 ? solve_ir(c, OP_DESCENT64, b, o, &one)
+                 : solve_fp64(c, OP_DESCENT64, b, c->descent.dinv, o, &one);
     if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
     FO_HIP(hipMemcpyAsync(theta, c->x64, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (B_tt) {

@@ -154,6 +154,8 @@ struct DescentSetup {
     double *diag = nullptr;   // [n_dofs]
     double *dinv = nullptr;   // [n_dofs]
     float *dinv32 = nullptr;  // [n_dofs]
+    const uint8_t *fixed = nullptr;  // caller's mask (theta = 0 there), or null
+    double *rhs = nullptr;    // [n_dofs] right-hand side with the masked entries zeroed
 };
 
 }  // namespace fo
@@ -228,6 +230,9 @@ struct fo_ctx {
     // expression) and the work buffers, allocated on the first call
     double transport_h2 = 0.0;
     void *tr_buf = nullptr;
+
+    // inverse elasticity work buffers, allocated on the first call
+    void *inv_buf = nullptr;
 
     // batched multi-load solves (allocated when max_rhs > 1)
     fo::BatchState batch;

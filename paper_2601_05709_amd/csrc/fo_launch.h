@@ -77,6 +77,15 @@ int launch_heat_diag(const fo_ctx *c, const uint8_t *fixed, double *diag, hipStr
 int launch_mass_apply(const fo_ctx *c, const double *x, double *y, hipStream_t s);
 int launch_heat_rhs(const fo_ctx *c, const double *u, const double *f, double lambda_vol, double V, double *rhs,
                     hipStream_t s);
+// Inverse elasticity (ElasOp without clamping, VecMassOp, InvSdOp, facet
+// mass): y = K(phi) x on all unknowns; y = M x (vector P1 mass); the
+// descent right-hand side [n_dofs] from u and aux [N][4D] = (v, p, q, g);
+// y = M_Gamma1 x over the context's boundary facets.  Device arrays.
+int launch_elas_apply_free(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+int launch_vec_mass(const fo_ctx *c, const double *x, double *y, hipStream_t s);
+int launch_inverse_rhs(const fo_ctx *c, const double *u, const double *aux, double kappa, double alpha,
+                       double *rhs, hipStream_t s);
+void launch_facet_mass(const fo_ctx *c, const double *x, double *y, hipStream_t s);
 
 // Operator of the fused CG kernels.
 enum FusedKind { FUSED_ELAS = 0, FUSED_DESCENT = 1 };

@@ -559,4 +559,143 @@ struct HeatSdOp {
     }
 };
 
+// Vector P1 mass: y_(a,i) = int lambda_a x_i = |T| (x_(a,i) + sum_b x_(b,i)) /
+// ((d+1)(d+2)), component by component.
+template <int D>
+struct VecMassOp {
+    static constexpr int NX = D, NV = D;
+    using Elem = uint8_t;
+    __device__ Elem load(int64_t) const { return 0; }
+    __device__ void operator()(Elem, const double *const *X, const double *const *U, double out[D + 1][D]) const
+    {
+        const Geom<D, double> g = geom<D, double>(X);
+        const double m = fabs(g.det) / (D == 2 ? 2.0 : 6.0) / ((D + 1) * (D + 2));
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double sx = 0.0;
+#pragma unroll
+            for (int a = 0; a <= D; ++a) sx += U[a][i];
+#pragma unroll
+            for (int a = 0; a <= D; ++a) out[a][i] = m * (U[a][i] + sx);
+        }
+    }
+};
+
+// Linear-elastic stress of a displacement Jacobian Dm ((Dm)_ij = d_j u_i):
+// eps = sym(Dm), sigma = lam tr(eps) I + 2 mu eps.
+template <int D>
+__device__ __forceinline__ void lin_stress(const double Dm[D][D], double lam, double mu, double S[D][D],
+                                           double Ep[D][D])
+{
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) tr += Dm[i][i];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            Ep[i][j] = 0.5 * (Dm[i][j] + Dm[j][i]);
+            S[i][j] = 2.0 * mu * Ep[i][j] + (i == j ? lam * tr : 0.0);
+        }
+}
+
+// Descent right-hand side of the inverse elasticity problem (Section "Inverse
+// problem", eq. SDelast_inv) for one force-displacement pair, with A = kappa
+// in Omega and 1 outside (eq. AOmega), u the input and v, p, q, g tile-staged
+// (aux [N][4d]); w = u - v - g:
+//   S0 = -alpha Dg^T w   (the sigma(q) : grad eps(g) term vanishes for P1 g),
+//   S1 = [alpha/2 |w|^2 + A (sigma(u):eps(p) + sigma(v+g):eps(q))] I
+//        - A (Du^T sigma(p) + Dp^T sigma(u) + Dv^T sigma(q) + Dq^T sigma(v+g)),
+// out[a][i] = -(int S0_i lambda_a + int (S1 grad lambda_a)_i), exact for P1
+// fields (the |w|^2 and S0 integrals with the P1 mass).
+template <int D>
+struct InvSdOp {
+    static constexpr int NX = D, NV = D, NA = 4 * D;
+    using Elem = uint8_t;
+    const uint8_t *chi;
+    const double *aux;  // [N][4D]: v, p, q, g
+    double kappa, alpha, lam, mu;
+    __device__ Elem load(int64_t e) const { return chi[e]; }
+    __device__ void operator()(Elem in, const double *const *X, const double *const *U, const double *const *F,
+                               double out[D + 1][D]) const
+    {
+        double ga[D + 1][D];
+        const double vol = p1_grads<D>(X, ga);
+        const double Av = (in ? kappa : 1.0) * vol;
+        double Du[D][D], Dv[D][D], Dp[D][D], Dq[D][D], Dg[D][D], Dy[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double su = 0.0, sv = 0.0, sp = 0.0, sq = 0.0, sg = 0.0;
+#pragma unroll
+                for (int a = 0; a <= D; ++a) {
+                    su += U[a][i] * ga[a][j];
+                    sv += F[a][i] * ga[a][j];
+                    sp += F[a][D + i] * ga[a][j];
+                    sq += F[a][2 * D + i] * ga[a][j];
+                    sg += F[a][3 * D + i] * ga[a][j];
+                }
+                Du[i][j] = su;
+                Dv[i][j] = sv;
+                Dp[i][j] = sp;
+                Dq[i][j] = sq;
+                Dg[i][j] = sg;
+                Dy[i][j] = sv + sg;
+            }
+        double Su[D][D], Eu[D][D], Sp[D][D], Ep[D][D], Sq[D][D], Eq[D][D], Sy[D][D], Ey[D][D];
+        lin_stress<D>(Du, lam, mu, Su, Eu);
+        lin_stress<D>(Dp, lam, mu, Sp, Ep);
+        lin_stress<D>(Dq, lam, mu, Sq, Eq);
+        lin_stress<D>(Dy, lam, mu, Sy, Ey);
+        // int w lambda_a and int |w|^2 with the P1 mass
+        const double m = vol / ((D + 1) * (D + 2));
+        double w[D + 1][D], Mw[D + 1][D], ww = 0.0;
+#pragma unroll
+        for (int a = 0; a <= D; ++a)
+#pragma unroll
+            for (int i = 0; i < D; ++i) w[a][i] = U[a][i] - F[a][i] - F[a][3 * D + i];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double sw = 0.0;
+#pragma unroll
+            for (int a = 0; a <= D; ++a) sw += w[a][i];
+#pragma unroll
+            for (int a = 0; a <= D; ++a) {
+                Mw[a][i] = m * (w[a][i] + sw);
+                ww += Mw[a][i] * w[a][i];
+            }
+        }
+        double se = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) se += Su[i][j] * Ep[i][j] + Sy[i][j] * Eq[i][j];
+        const double iso = 0.5 * alpha * ww + Av * se;
+        double T[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    t += Du[k][i] * Sp[k][j] + Dp[k][i] * Su[k][j] + Dv[k][i] * Sq[k][j] + Dq[k][i] * Sy[k][j];
+                T[i][j] = Av * t;
+            }
+#pragma unroll
+        for (int a = 0; a <= D; ++a)
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s0 = 0.0, tg = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    s0 += Dg[k][i] * Mw[a][k];
+                    tg += T[i][k] * ga[a][k];
+                }
+                out[a][i] = alpha * s0 - iso * ga[a][i] + tg;
+            }
+    }
+};
+
 }  // namespace fo

@@ -192,6 +192,7 @@ int fo_pool_admit(fo_pool *p, const fo_request *q, int32_t *slot)
 {
     if (!p || !q || !slot || !q->phi || !q->b || !(q->V > 0)) return FO_ERR_ARG;
     if (q->descent.n_boxes < 0 || (q->descent.n_boxes > 0 && !q->descent.boxes)) return FO_ERR_ARG;
+    if (q->descent.fixed) return FO_ERR_ARG;  // a device mask cannot follow a request to its device
     const size_t est = fo_footprint_estimate(&q->mesh);
     if (est == 0) return FO_ERR_ARG;
     std::lock_guard<std::mutex> lk(p->mu);

@@ -580,7 +580,8 @@ static int prepare_dim()
            ensure_lds_attr<D, double, TransportDiagOp<D>>() | ensure_lds_attr<D, double, ReinitOp<D>>() |
            ensure_lds_attr<D, double, ReinitDiagOp<D>>() | ensure_lds_attr<D, double, ReinitRhsOp<D>>() |
            ensure_lds_attr<D, double, HeatOp<D>>() | ensure_lds_attr<D, double, HeatDiagOp<D>>() |
-           ensure_lds_attr<D, double, MassOp<D>>() | ensure_lds_attr<D, double, HeatSdOp<D>>();
+           ensure_lds_attr<D, double, MassOp<D>>() | ensure_lds_attr<D, double, HeatSdOp<D>>() |
+           ensure_lds_attr<D, double, VecMassOp<D>>() | ensure_lds_attr<D, double, InvSdOp<D>>();
 }
 
 int tiled_prepare(const fo_ctx *c)
@@ -775,6 +776,52 @@ void launch_facet_terms(const fo_ctx *c, const double *x, double *y, hipStream_t
     facet_terms(c, x, y, s);
 }
 
+// P1 mass on the boundary facets, node-parallel over the boundary nodes in
+// the same fixed facet order: y_g = sum_f |F| / (d(d+1)) (x_g + sum_b x_b)
+// (y is written on the boundary nodes only).
+template <int D>
+__global__ void k_facet_mass(const int32_t *__restrict__ bnode, const int32_t *__restrict__ bptr,
+                             const int32_t *__restrict__ bfac, int64_t NB, const int32_t *__restrict__ bf, int64_t F,
+                             const double *__restrict__ coords, const double *__restrict__ x,
+                             double *__restrict__ y)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < NB;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = bnode[k];
+        double acc[D];
+        for (int i = 0; i < D; ++i) acc[i] = 0.0;
+        for (int j = bptr[k]; j < bptr[k + 1]; ++j) {
+            const int64_t f = bfac[j];
+            const double *P[D];
+            int64_t nd[D];
+            for (int a = 0; a < D; ++a) {
+                nd[a] = bf[(int64_t)a * F + f];
+                P[a] = coords + nd[a] * D;
+            }
+            const double cf = facet_measure<D>(P) / (double)(D * (D + 1));
+            for (int i = 0; i < D; ++i) {
+                double t = x[g * D + i];
+                for (int a = 0; a < D; ++a) t += x[nd[a] * D + i];
+                acc[i] += cf * t;
+            }
+        }
+        for (int i = 0; i < D; ++i) y[g * D + i] = acc[i];
+    }
+}
+
+void launch_facet_mass(const fo_ctx *c, const double *x, double *y, hipStream_t s)
+{
+    launch_fill<double>(y, c->ndof, 0.0, s);
+    if (c->n_bnodes == 0) return;
+    const int nb = (int)std::min<int64_t>((c->n_bnodes + 255) / 256, 65535);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_facet_mass<2>, dim3(nb), dim3(256), 0, s, c->bnodes, c->bnode_ptr, c->bnode_fac,
+                           c->n_bnodes, c->bfacets, c->nbf, c->coords, x, y);
+    else
+        hipLaunchKernelGGL(k_facet_mass<3>, dim3(nb), dim3(256), 0, s, c->bnodes, c->bnode_ptr, c->bnode_fac,
+                           c->n_bnodes, c->bfacets, c->nbf, c->coords, x, y);
+}
+
 // ---------------------------------------------------------------------------
 // tiled launchers
 
@@ -921,6 +968,34 @@ int launch_heat_rhs(const fo_ctx *c, const double *u, const double *f, double la
                                     nullptr, s);
     return run_tiled<3, double>(c, HeatSdOp<3>{c->chi, f, c->ersatz, lambda_vol, V}, c->coords, u, rhs, nullptr,
                                 s);
+}
+
+int launch_elas_apply_free(const fo_ctx *c, const double *x, double *y, hipStream_t s)
+{
+    if (c->has_isolated) launch_fill<double>(y, c->ndof, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, ElasOp<2, double>{c->chi, c->ersatz, c->lam, c->mu}, c->coords, x, y,
+                                    nullptr, s);
+    return run_tiled<3, double>(c, ElasOp<3, double>{c->chi, c->ersatz, c->lam, c->mu}, c->coords, x, y, nullptr,
+                                s);
+}
+
+int launch_vec_mass(const fo_ctx *c, const double *x, double *y, hipStream_t s)
+{
+    launch_fill<double>(y, c->ndof, 0.0, s);
+    if (c->dim == 2) return run_tiled<2, double>(c, VecMassOp<2>{}, c->coords, x, y, nullptr, s);
+    return run_tiled<3, double>(c, VecMassOp<3>{}, c->coords, x, y, nullptr, s);
+}
+
+int launch_inverse_rhs(const fo_ctx *c, const double *u, const double *aux, double kappa, double alpha,
+                       double *rhs, hipStream_t s)
+{
+    launch_fill<double>(rhs, c->ndof, 0.0, s);
+    if (c->dim == 2)
+        return run_tiled<2, double>(c, InvSdOp<2>{c->chi, aux, kappa, alpha, c->lam, c->mu}, c->coords, u, rhs,
+                                    nullptr, s);
+    return run_tiled<3, double>(c, InvSdOp<3>{c->chi, aux, kappa, alpha, c->lam, c->mu}, c->coords, u, rhs,
+                                nullptr, s);
 }
 
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s)

@@ -48,7 +48,7 @@ class fo_solve_opts(C.Structure):
 
 class fo_descent_opts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("gamma_n", C.c_double), ("gamma_s", C.c_double),
-                ("n_boxes", C.c_int32), ("boxes", C.c_void_p)]
+                ("n_boxes", C.c_int32), ("boxes", C.c_void_p), ("fixed", C.c_void_p)]
 
 
 class fo_solve_stats(C.Structure):
@@ -107,6 +107,9 @@ EXPORTS = {
     "fo_heat_load": ([_vp, _vp, _vp], C.c_int),
     "fo_heat_solve": ([_vp, _vp, _vp, _vp, C.POINTER(fo_solve_opts), C.POINTER(fo_solve_stats)], C.c_int),
     "fo_heat_derivative": ([_vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp, _vp], C.c_int),
+    "fo_inverse_states": ([_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double,
+                           C.POINTER(fo_solve_opts), _vp, _vp, _vp, _vp, _vp, C.POINTER(fo_solve_stats)], C.c_int),
+    "fo_inverse_derivative": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp], C.c_int),
     "fo_reinit": ([_vp, _vp, C.c_int32, C.c_double, C.POINTER(fo_solve_opts), C.POINTER(fo_solve_stats)],
                   C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
@@ -208,15 +211,21 @@ class Stats:
 
 
 class DescentOpts:
-    def __init__(self, alpha=0.01, gamma_n=1e4, gamma_s=1e4, boxes=None, dim=None):
+    def __init__(self, alpha=0.01, gamma_n=1e4, gamma_s=1e4, boxes=None, dim=None, fixed=None):
+        """fixed: optional device uint8 tensor [n_dofs]; theta = 0 where it is set."""
         self.alpha, self.gamma_n, self.gamma_s = float(alpha), float(gamma_n), float(gamma_s)
+        self.fixed = fixed
         b = np.zeros((0, 2 * (dim or 2))) if boxes is None else np.asarray(boxes, dtype=np.float64)
-        self.boxes = np.ascontiguousarray(b.reshape(b.shape[0], -1))
+        self.boxes = np.ascontiguousarray(b.reshape(b.shape[0], -1) if b.size else b.reshape(0, 2 * (dim or 2)))
 
     def c(self) -> fo_descent_opts:
         n = self.boxes.shape[0]
         ptr = self.boxes.ctypes.data_as(C.c_void_p) if n else None
-        return fo_descent_opts(self.alpha, self.gamma_n, self.gamma_s, n, ptr)
+        fx = None
+        if self.fixed is not None:
+            import torch
+            fx = _ptr(self.fixed, torch.uint8, None, "fixed")
+        return fo_descent_opts(self.alpha, self.gamma_n, self.gamma_s, n, ptr, fx)
 
 
 def current_stream():
@@ -410,6 +419,32 @@ class Context:
                                         _ptr(f, torch.float64, self.n_nodes, "f"), float(lambda_vol), float(V),
                                         _ptr(rhs, torch.float64, self.n_dofs, "rhs"), _ptr(J, torch.float64, 1, "J"),
                                         _ptr(vol, torch.float64, 1, "vol")), "fo_heat_derivative")
+
+    def inverse_states(self, ctx_g: "Context", phi, f, g, kappa: float, alpha: float, beta: float, u, v, p, q, J,
+                       opts: Optional[SolveOpts] = None, allow_not_converged=False) -> Stats:
+        """States u, v, adjoints p, q and cost J of the inverse elasticity
+        problem (fo_inverse_states); self clamps Gamma_0, ctx_g the whole
+        boundary, both with ersatz = 1/kappa."""
+        import torch
+        opts = opts or SolveOpts(precision=FO_FP64, rtol=1e-10)
+        st = fo_solve_stats()
+        n = self.n_dofs
+        rc = lib().fo_inverse_states(self.h, ctx_g.h, _ptr(phi, torch.float64, self.n_nodes, "phi"),
+                                     _ptr(f, torch.float64, n, "f"), _ptr(g, torch.float64, n, "g"), float(kappa),
+                                     float(alpha), float(beta), C.byref(opts.c()), _ptr(u, torch.float64, n, "u"),
+                                     _ptr(v, torch.float64, n, "v"), _ptr(p, torch.float64, n, "p"),
+                                     _ptr(q, torch.float64, n, "q"), _ptr(J, torch.float64, 1, "J"), C.byref(st))
+        _check(rc, "fo_inverse_states", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
+        return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
+
+    def inverse_derivative(self, u, v, p, q, g, kappa: float, alpha: float, rhs):
+        """Descent right-hand side of the inverse problem (fo_inverse_derivative)."""
+        import torch
+        n = self.n_dofs
+        _check(lib().fo_inverse_derivative(self.h, *(_ptr(x, torch.float64, n, nm) for x, nm in
+                                                     ((u, "u"), (v, "v"), (p, "p"), (q, "q"), (g, "g"))),
+                                           float(kappa), float(alpha), _ptr(rhs, torch.float64, n, "rhs")),
+               "fo_inverse_derivative")
 
     def reinit(self, phi, steps: int = 8, t_end: float = 0.1, opts: Optional[SolveOpts] = None,
                allow_not_converged=False) -> Stats:

@@ -78,6 +78,25 @@ def test_null_arguments_rejected(lib):
     assert lib.fo_state_solve(None, None, None, 1, 1, None, None) == fo.FO_ERR_ARG
 
 
+def test_inverse_entries_reject_null_arguments(lib):
+    from paper_2601_05709_amd import fo
+    assert lib.fo_inverse_states(None, None, None, None, None, 10.0, 1.0, 1.0, None, None, None, None, None,
+                                 None, None) == fo.FO_ERR_ARG
+    assert lib.fo_inverse_derivative(None, None, None, None, None, None, 10.0, 1.0, None) == fo.FO_ERR_ARG
+
+
+def test_descent_opts_layout_and_defaults():
+    from paper_2601_05709_amd import fo
+    # the velocity mask is the last field of fo_descent_opts (after the boxes pointer)
+    assert [f[0] for f in fo.fo_descent_opts._fields_] == ["alpha", "gamma_n", "gamma_s", "n_boxes", "boxes",
+                                                            "fixed"]
+    assert fo.fo_descent_opts.fixed.offset == fo.fo_descent_opts.boxes.offset + C.sizeof(C.c_void_p)
+    # no boxes and no mask: an empty Omega_0 and a null mask
+    for dim in (2, 3):
+        d = fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, dim=dim).c()
+        assert d.n_boxes == 0 and not d.boxes and not d.fixed
+
+
 def test_adaptive_dt_matches_oracle_rule():
     """The product's host-side time-step rule and the oracle's agree."""
     import oracle as oc

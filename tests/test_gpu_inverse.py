@@ -1,0 +1,148 @@
+"""GPU parity of the inverse elasticity problem (fo_inverse_states,
+fo_inverse_derivative and the clamped H^1_0 velocity solve of
+fo_descent_solve) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import fo_inputs as fi
+from oracle import inverse as oi
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2601_05709_amd import fo  # noqa: E402
+
+CELLS = {
+    "2d_37x19": (37, 19),
+    "3d_16x8x8": (16, 8, 8),
+}
+
+
+def dev(a, dtype=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def zeros(n):
+    return torch.zeros(n, dtype=torch.float64, device="cuda")
+
+
+def contexts(wi):
+    m = wi.mesh
+    common = dict(E=wi.E, nu=wi.nu, plane_stress=wi.plane_stress, ersatz=1.0 / wi.kappa)
+    cf = fo.Context(m.dim, m.coords, m.conn, wi.fixed0, m.bfacets, m.bnormal, **common)
+    cg = fo.Context(m.dim, m.coords, m.conn, wi.fixed_all, None, None, **common)
+    return cf, cg
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def run_states(wi, cf, cg, phi, opts, allow_not_converged=False):
+    n = wi.mesh.n_dofs
+    out = {k: zeros(n) for k in "uvpq"}
+    J = zeros(1)
+    st = cf.inverse_states(cg, dev(phi), dev(wi.f), dev(wi.g), wi.kappa, wi.alpha, wi.beta, out["u"], out["v"],
+                           out["p"], out["q"], J, opts, allow_not_converged=allow_not_converged)
+    return out, float(J), st
+
+
+@pytest.mark.parametrize("name", list(CELLS))
+@pytest.mark.parametrize("precision", [fo.FO_FP64, fo.FO_FP32_IR])
+def test_inverse_states_and_derivative(name, precision):
+    wi = fi.inverse_elasticity(CELLS[name])
+    print("case inverse %s precision %d" % (name, precision), flush=True)
+    ref = oi.inverse_iteration(wi)
+    cf, cg = contexts(wi)
+    # the mixed-precision refinement stops at a looser residual than FP64 CG
+    rtol, tol = (1e-12, 1e-9) if precision == fo.FO_FP64 else (1e-11, 1e-8)
+    out, J, st = run_states(wi, cf, cg, wi.phi, fo.SolveOpts(precision=precision, rtol=rtol))
+    assert st.status == 0 and st.iters_inner > 0
+    for k in "uvpq":
+        got = out[k].cpu().numpy()
+        assert rel(got, ref[k]) < tol, k
+    assert np.all(out["u"].cpu().numpy()[wi.fixed0 == 1] == 0.0)
+    assert np.all(out["v"].cpu().numpy()[wi.fixed_all == 1] == 0.0)
+    assert np.all(out["q"].cpu().numpy()[wi.fixed_all == 1] == 0.0)
+    assert J == pytest.approx(ref["J"], rel=tol)
+    # the derivative from the oracle's states, checked on its own
+    rhs = zeros(wi.mesh.n_dofs)
+    g = dev(wi.g)
+    cf.inverse_derivative(dev(ref["u"]), dev(ref["v"]), dev(ref["p"]), dev(ref["q"]), g, wi.kappa, wi.alpha, rhs)
+    r = rhs.cpu().numpy()
+    np.testing.assert_allclose(r, ref["rhs"], rtol=1e-11, atol=1e-12 * np.abs(ref["rhs"]).max())
+    # and from the device's states
+    cf.inverse_derivative(out["u"], out["v"], out["p"], out["q"], g, wi.kappa, wi.alpha, rhs)
+    assert rel(rhs.cpu().numpy(), ref["rhs"]) < 10 * tol
+
+
+@pytest.mark.parametrize("name", list(CELLS))
+def test_inverse_clamped_velocity(name):
+    wi = fi.inverse_elasticity(CELLS[name])
+    print("case inverse velocity %s" % name, flush=True)
+    ref = oi.inverse_iteration(wi)
+    theta_ref, info = oi.velocity(wi, ref["rhs"])
+    assert info.status == 0
+    cf, _ = contexts(wi)
+    fixed = dev(wi.fixed_all, np.uint8)
+    theta = zeros(wi.mesh.n_dofs)
+    B_tt = zeros(1)
+    rhs = dev(ref["rhs"])
+    for precision, rtol, tol in ((fo.FO_FP64, 1e-12, 1e-9), (fo.FO_FP32_IR, 1e-11, 1e-8)):
+        theta.zero_()
+        st = cf.descent_solve(fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, fixed=fixed), rhs, theta,
+                              fo.SolveOpts(precision=precision, rtol=rtol), B_tt)
+        assert st.status == 0
+        t = theta.cpu().numpy()
+        assert np.all(t[wi.fixed_all == 1] == 0.0)
+        assert rel(t, theta_ref) < tol
+        # B(theta, theta) = rhs . theta, taken over the free unknowns
+        assert float(B_tt) == pytest.approx(float(np.dot(np.where(wi.fixed_all == 1, 0.0, ref["rhs"]), theta_ref)),
+                                            rel=tol)
+    # the same context without the mask solves the unclamped problem again
+    st = cf.descent_solve(fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0), rhs, theta,
+                          fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-12))
+    assert st.status == 0
+    assert np.abs(theta.cpu().numpy()[wi.fixed_all == 1]).max() > 0.0
+
+
+def test_inverse_moved_inclusion_and_edge_cases():
+    wi = fi.inverse_elasticity(CELLS["2d_37x19"])
+    cf, cg = contexts(wi)
+    n = wi.mesh.n_dofs
+    rhs = zeros(n)
+    g = dev(wi.g)
+    u = zeros(n)
+    # no level set yet: the derivative is refused
+    with pytest.raises(fo.FoError):
+        cf.inverse_derivative(u, u, u, u, g, wi.kappa, wi.alpha, rhs)
+    # kappa inconsistent with the contexts' ersatz value, or one context twice
+    J = zeros(1)
+    with pytest.raises(fo.FoError):
+        cf.inverse_states(cg, dev(wi.phi), dev(wi.f), g, 2.0 * wi.kappa, wi.alpha, wi.beta, u, u, u, u, J)
+    with pytest.raises(fo.FoError):
+        cf.inverse_states(cf, dev(wi.phi), dev(wi.f), g, wi.kappa, wi.alpha, wi.beta, u, u, u, u, J)
+    # two level sets in a row on the same contexts (the second a moved inclusion)
+    for shift in (0.0, 0.3):
+        phi = np.linalg.norm(wi.mesh.coords - np.array([1.0 + shift, 0.5]), axis=1) - 0.25
+        ref = oi.inverse_iteration(wi, phi=phi)
+        out, Jd, st = run_states(wi, cf, cg, phi, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-12))
+        for k in "uvpq":
+            assert rel(out[k].cpu().numpy(), ref[k]) < 1e-9, (shift, k)
+        assert Jd == pytest.approx(ref["J"], rel=1e-9)
+        cf.inverse_derivative(out["u"], out["v"], out["p"], out["q"], g, wi.kappa, wi.alpha, rhs)
+        assert rel(rhs.cpu().numpy(), ref["rhs"]) < 1e-8
+    # the true inclusion as the level set with g the data it generates: J and the derivative vanish
+    m = wi.mesh
+    ref0 = oi.inverse_iteration(wi)
+    ctx_true = fi.InverseWorkload(m, wi.fixed0, wi.fixed_all, wi.f, ref0["u"], wi.phi, wi.kappa, wi.alpha, wi.beta,
+                                  wi.E, wi.nu, wi.plane_stress)
+    # (the adjoint loads are rounding noise there, which a relative residual
+    # test need not reach: only the values are checked)
+    out, Jd, _ = run_states(ctx_true, cf, cg, wi.phi, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-12),
+                            allow_not_converged=True)
+    assert abs(Jd) < 1e-18
+    for k in "vpq":
+        assert np.abs(out[k].cpu().numpy()).max() < 1e-9 * np.abs(ref0[k]).max(), k
+    cf.inverse_derivative(out["u"], out["v"], out["p"], out["q"], dev(ref0["u"]), wi.kappa, wi.alpha, rhs)
+    assert np.abs(rhs.cpu().numpy()).max() < 1e-9 * np.abs(ref0["rhs"]).max() + 1e-14
