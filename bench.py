@@ -353,6 +353,48 @@ def main():
     log("heat model: state %d BiCGStab applications (%.1f ms), descent %d its, %.1f ms in all"
         % (st_ht.iters_inner, st_ht.seconds * 1e3, dst_ht.iters_inner, t_ht * 1e3))
 
+    # the paper's inverse elasticity problem (Kohn-Vogelius, kappa = 10) on a
+    # mesh of the same size: states u, v and adjoints p, q (FP32 CG + FP64
+    # refinement to rel. res 1e-8), cost, S0/S1 derivative and the H^1_0
+    # velocity solve (every boundary unknown clamped)
+    wi = fi.inverse_elasticity(cells)
+    mi = wi.mesh
+    t0 = time.perf_counter()
+    inv_common = dict(E=wi.E, nu=wi.nu, plane_stress=wi.plane_stress, ersatz=1.0 / wi.kappa)
+    cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
+    cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
+    log("inverse problem: two contexts created in %.2f s" % (time.perf_counter() - t0))
+
+    def dvec(a, dtype=torch.float64):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+    phi_inv, f_inv, g_inv = dvec(wi.phi), dvec(wi.f), dvec(wi.g)
+    fx_inv = dvec(wi.fixed_all, torch.uint8)
+    inv_out = [torch.zeros(mi.n_dofs, dtype=torch.float64, device="cuda") for _ in range(6)]
+    u_iv, v_iv, p_iv, q_iv, rhs_iv, th_iv = inv_out
+    J_iv = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Bt_iv = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dopts_iv = fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, dim=3, fixed=fx_inv)
+
+    def inverse_step():
+        s_iv = cf_inv.inverse_states(cg_inv, phi_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, u_iv, v_iv, p_iv,
+                                     q_iv, J_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8))
+        cf_inv.inverse_derivative(u_iv, v_iv, p_iv, q_iv, g_inv, wi.kappa, wi.alpha, rhs_iv)
+        d_iv = cf_inv.descent_solve(dopts_iv, rhs_iv, th_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), Bt_iv)
+        return s_iv, d_iv
+
+    inverse_step()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_iv, dst_iv = inverse_step()
+    torch.cuda.synchronize()
+    t_iv = time.perf_counter() - t0
+    log("inverse problem: 4 state solves %d + %d its (%.1f ms), velocity %d its, %.1f ms in all, J %.4g"
+        % (st_iv.iters_inner, st_iv.iters_outer, st_iv.seconds * 1e3, dst_iv.iters_inner, t_iv * 1e3,
+           float(J_iv.item())))
+    cf_inv.close()
+    cg_inv.close()
+
     # the paper's loop (Algorithm 1, fo_optimize): a few iterations from the
     # initial design with the PPL volume constraint at 90% of its volume, the
     # paper's time-stepping defaults and transport step
@@ -444,6 +486,11 @@ def main():
                          "FP64 state solve to rel. res 1e-8, S0/S1 derivative, FP32 + refinement velocity solve",
                  "ms": t_ht * 1e3, "state_ms": st_ht.seconds * 1e3, "state_operator_applications": st_ht.iters_inner,
                  "descent_iters": dst_ht.iters_inner, "J": float(J_ht.item())},
+        "inverse": {"what": "the paper's inverse elasticity problem (kappa = 10, alpha = beta = 1) on a mesh of the "
+                            "same size: u, v, p, q by FP32 CG + FP64 refinement to rel. res 1e-8, cost, S0/S1 "
+                            "derivative, H^1_0 velocity solve", "ms": t_iv * 1e3, "states_ms": st_iv.seconds * 1e3,
+                    "state_iters": {"inner_fp32": st_iv.iters_inner, "outer_fp64": st_iv.iters_outer},
+                    "descent_iters": dst_iv.iters_inner, "J": float(J_iv.item())},
         "loop": {"what": "the paper's Algorithm 1 (fo_optimize): state and velocity solves in FP32 + FP64 "
                          "refinement, PPL volume constraint at 90% of the initial volume, transport step, "
                          "from the initial design", "iterations": len(lp_recs), "seconds": t_lp,

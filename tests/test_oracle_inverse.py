@@ -76,3 +76,25 @@ def test_boundary_conditions_of_each_solution():
     th, info = oi.velocity(wi, r["rhs"])
     assert info.status == 0 and np.all(th[wi.fixed_all == 1] == 0)
     assert float(th @ r["rhs"]) > 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mass_matrices_integrate_exactly(dim):
+    """The vector mass integrates products of P1 fields exactly over D, the
+    facet mass over Gamma_1 (the boundary without the face x = 0):
+    1^T M 1 = d |D|, int x_0 over D, and 1^T M_G 1 = d |Gamma_1|, int x_0^2
+    over Gamma_1, in closed form for [0,2]x[0,1]^(d-1)."""
+    wi = fi.inverse_elasticity((12, 6) if dim == 2 else (6, 3, 3))
+    m = wi.mesh
+    M = oi.vector_mass(dim, m.coords, m.conn)
+    MG = oi.facet_mass(dim, m.coords, m.bfacets)
+    one = np.ones(m.n_dofs)
+    x0 = np.repeat(m.coords[:, 0], dim)
+    vol = 2.0
+    area = 5.0 if dim == 2 else 9.0
+    assert one @ (M @ one) == pytest.approx(dim * vol, rel=1e-13)
+    assert x0 @ (M @ one) == pytest.approx(dim * 2.0 * 1.0 * (1.0 if dim == 2 else 1.0), rel=1e-13)
+    assert one @ (MG @ one) == pytest.approx(dim * area, rel=1e-13)
+    # int_Gamma1 x_0^2: the faces y = 0, 1 (and z = 0, 1) give int_0^2 x^2 = 8/3 each, the face x = 2 gives 4
+    faces = 2 if dim == 2 else 4
+    assert x0 @ (MG @ x0) == pytest.approx(dim * (faces * 8.0 / 3.0 + 4.0), rel=1e-13)
