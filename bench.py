@@ -395,6 +395,35 @@ def main():
     cf_inv.close()
     cg_inv.close()
 
+    # eight force-displacement pairs in one call (the cost and derivative
+    # summed over the pairs), solved pair by pair
+    npairs = 8
+    wp = fi.inverse_elasticity(cells, n_pairs=npairs)
+    cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
+    cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
+    fP, gP = dvec(wp.columns(wp.fs)), dvec(wp.columns(wp.gs))
+    uP, vP, pP, qP = (torch.zeros(mi.n_dofs * npairs, dtype=torch.float64, device="cuda") for _ in range(4))
+    JP = torch.zeros(npairs, dtype=torch.float64, device="cuda")
+
+    def inverse_pairs_step():
+        s_p = cf_inv.inverse_states(cg_inv, phi_inv, fP, gP, wi.kappa, wi.alpha, wi.beta, uP, vP, pP, qP, JP,
+                                    fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), n_pairs=npairs)
+        cf_inv.inverse_derivative(uP, vP, pP, qP, gP, wi.kappa, wi.alpha, rhs_iv, n_pairs=npairs)
+        d_p = cf_inv.descent_solve(dopts_iv, rhs_iv, th_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), Bt_iv)
+        return s_p, d_p
+
+    inverse_pairs_step()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_ip, dst_ip = inverse_pairs_step()
+    torch.cuda.synchronize()
+    t_ip = time.perf_counter() - t0
+    log("inverse problem, %d pairs: 4 x %d solves %d + %d its (%.1f ms), velocity %d its, %.1f ms in all "
+        "(%.1f ms per pair)" % (npairs, npairs, st_ip.iters_inner, st_ip.iters_outer, st_ip.seconds * 1e3,
+                                dst_ip.iters_inner, t_ip * 1e3, t_ip * 1e3 / npairs))
+    cf_inv.close()
+    cg_inv.close()
+
     # the paper's loop (Algorithm 1, fo_optimize): a few iterations from the
     # initial design with the PPL volume constraint at 90% of its volume, the
     # paper's time-stepping defaults and transport step
@@ -490,7 +519,12 @@ def main():
                             "same size: u, v, p, q by FP32 CG + FP64 refinement to rel. res 1e-8, cost, S0/S1 "
                             "derivative, H^1_0 velocity solve", "ms": t_iv * 1e3, "states_ms": st_iv.seconds * 1e3,
                     "state_iters": {"inner_fp32": st_iv.iters_inner, "outer_fp64": st_iv.iters_outer},
-                    "descent_iters": dst_iv.iters_inner, "J": float(J_iv.item())},
+                    "descent_iters": dst_iv.iters_inner, "J": float(J_iv.item()),
+                    "pairs": {"what": "8 force-displacement pairs in one call: 4 x 8 solves by FP32 CG + FP64 "
+                                      "refinement, derivative summed over the pairs, one velocity solve", "n_pairs": npairs, "ms": t_ip * 1e3, "ms_per_pair": t_ip * 1e3 / npairs,
+                              "states_ms": st_ip.seconds * 1e3,
+                              "state_iters": {"inner": st_ip.iters_inner, "outer": st_ip.iters_outer},
+                              "descent_iters": dst_ip.iters_inner}},
         "loop": {"what": "the paper's Algorithm 1 (fo_optimize): state and velocity solves in FP32 + FP64 "
                          "refinement, PPL volume constraint at 90% of the initial volume, transport step, "
                          "from the initial design", "iterations": len(lp_recs), "seconds": t_lp,

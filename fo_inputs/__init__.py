@@ -405,17 +405,36 @@ class InverseWorkload:
     set (a disk or ball of the stiffer material) and the weights."""
 
     def __init__(self, mesh, fixed0, fixed_all, f, g, phi, kappa=10.0, alpha=1.0, beta=1.0, E=1.0, nu=0.3,
-                 plane_stress=1):
+                 plane_stress=1, fs=None, gs=None):
         self.mesh, self.fixed0, self.fixed_all = mesh, fixed0, fixed_all
         self.f, self.g, self.phi = f, g, phi
         self.kappa, self.alpha, self.beta = kappa, alpha, beta
         self.E, self.nu, self.plane_stress = E, nu, plane_stress
+        # all pairs (f_k, g_k); pair 0 is (f, g)
+        self.fs = [f] if fs is None else list(fs)
+        self.gs = [g] if gs is None else list(gs)
+
+    @property
+    def n_pairs(self) -> int:
+        return len(self.fs)
+
+    def pair(self, k: int) -> "InverseWorkload":
+        """The single-pair workload of pair k."""
+        return InverseWorkload(self.mesh, self.fixed0, self.fixed_all, self.fs[k], self.gs[k], self.phi, self.kappa,
+                               self.alpha, self.beta, self.E, self.nu, self.plane_stress)
+
+    def columns(self, arrays) -> np.ndarray:
+        """The pairs' vectors as the columns of an [n_dofs][n_pairs] array."""
+        return np.ascontiguousarray(np.stack(arrays, axis=1))
 
 
-def inverse_elasticity(cells, g_scale=(0.02, -0.01, 0.015)) -> InverseWorkload:
+def inverse_elasticity(cells, g_scale=(0.02, -0.01, 0.015), n_pairs: int = 1) -> InverseWorkload:
     """[0,2]x[0,1] (2D) or [0,2]x[0,1]^2 (3D); Gamma_0 = {x = 0}; an inward
     unit traction on the middle of the face x = 2; an inclusion of radius
-    0.25 centred at (1, 0.5[, 0.5])."""
+    0.25 centred at (1, 0.5[, 0.5]).  With n_pairs > 1, pair k >= 1 tilts
+    the traction by 0.35 k radians towards +y and moves its patch (width 0.4)
+    to y centred at 0.5 + 0.25 sin(1.3 k); its data g_k = x_0 a_k with a_k =
+    (a_0 cos 0.7k, a_1 + 0.004 k, a_2 sin(0.7k + 1))."""
     d = len(cells)
     lengths = (2.0, 1.0) if d == 2 else (2.0, 1.0, 1.0)
     base = structured_mesh(cells, lengths)
@@ -432,7 +451,18 @@ def inverse_elasticity(cells, g_scale=(0.02, -0.01, 0.015)) -> InverseWorkload:
     g = (mesh.coords[:, :1] * a[None, :]).ravel()
     c = np.array([1.0, 0.5, 0.5][:d])
     phi = np.linalg.norm(mesh.coords - c, axis=1) - 0.25
-    return InverseWorkload(mesh, clamp_mask(base), fixed_all, f, g, phi, plane_stress=1 if d == 2 else 0)
+    fs, gs = [f], [g]
+    for k in range(1, n_pairs):
+        t = 0.35 * k
+        direction = (-np.cos(t), np.sin(t)) + ((0.5 * np.sin(t),) if d == 3 else ())
+        yc = 0.5 + 0.25 * np.sin(1.3 * k)
+        lo_k = (yc - 0.2,) if d == 2 else (yc - 0.2, 0.3)
+        hi_k = (yc + 0.2,) if d == 2 else (yc + 0.2, 0.7)
+        fs.append(traction_load(base, direction, lo_k, hi_k))
+        ak = np.array([g_scale[0] * np.cos(0.7 * k), g_scale[1] + 0.004 * k, g_scale[2] * np.sin(0.7 * k + 1.0)])
+        gs.append((mesh.coords[:, :1] * ak[None, :d]).ravel())
+    return InverseWorkload(mesh, clamp_mask(base), fixed_all, f, g, phi, plane_stress=1 if d == 2 else 0,
+                           fs=fs, gs=gs)
 
 
 @functools.lru_cache(maxsize=8)

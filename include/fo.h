@@ -308,37 +308,44 @@ int fo_heat_derivative(fo_ctx *ctx, const double *u, const double *f, double lam
 
 /* Inverse elasticity problem (Section "Inverse problem": eqs. cost, f-prob,
  * g-prob, AOmega, w-f, w-g, the adjoint problems of eqs. dL1 and dL2, and
- * eq. SDelast_inv) for one force-displacement pair (f, g):
- *   J = alpha/2 int_D |u - v - g|^2 + beta/2 int_Gamma1 |u - g|^2,
- * u with traction f on Gamma_1 and u = 0 on Gamma_0, y = v + g with v = 0 on
- * the whole boundary, A = kappa in Omega and 1 outside (element mean of phi
- * negative: Omega).  Two contexts on the same mesh and device: ctx_f clamps
- * Gamma_0 and lists the Gamma_1 facets (its boundary facets carry the
- * beta-term), ctx_g clamps every boundary unknown; both are created with
- * ersatz = 1/kappa (their operator is K/kappa), tiled scatter.  g is the P1
- * Dirichlet data extended into D; it may be nonzero anywhere.  Device
- * pointers [n_dofs] unless stated.
+ * eq. SDelast_inv) for n_pairs force-displacement pairs (f_k, g_k):
+ *   J_k = alpha/2 int_D |u_k - v_k - g_k|^2 + beta/2 int_Gamma1 |u_k - g_k|^2,
+ * u_k with traction f_k on Gamma_1 and u_k = 0 on Gamma_0, y_k = v_k + g_k
+ * with v_k = 0 on the whole boundary, A = kappa in Omega and 1 outside
+ * (element mean of phi negative: Omega); the cost of several pairs is
+ * sum_k J_k.  Two contexts on the same mesh and device: ctx_f clamps Gamma_0
+ * and lists the Gamma_1 facets (its boundary facets carry the beta-term),
+ * ctx_g clamps every boundary unknown; both are created with ersatz =
+ * 1/kappa (their operator is K/kappa) and the tiled scatter; the pairs are
+ * solved one after the other.  g_k
+ * is the P1 Dirichlet data extended into D; it may be nonzero anywhere.
+ * Device arrays [n_dofs][ld] (pair k in column k, ld >= n_pairs) unless
+ * stated.
  *
  * fo_inverse_states: sets phi on both contexts and solves, by their state
  *   solves with opts, u (ctx_f), v with K v = -K g (ctx_g), the adjoints p
  *   with K p = -alpha M (u - v - g) - beta M_Gamma1 (u - g) (ctx_f) and q
  *   with K q = alpha M (u - v - g) (ctx_g), M the P1 mass and M_Gamma1 the
- *   P1 mass of the Gamma_1 facets; *J (device scalar) the cost.  stats sum
- *   the four solves.  Returns FO_OK, FO_NOT_CONVERGED, FO_ERR_BREAKDOWN,
- *   FO_ERR_ARG (kappa inconsistent with the contexts' ersatz value, contexts
- *   of different sizes or devices) or FO_ERR_STATE (atomic scatter).
- * fo_inverse_derivative: the descent right-hand side rhs of eq.
- *   SDelast_inv, rhs_(a,i) = -(int S0_i lambda_a + int (S1 grad lambda_a)_i)
- *   with S0 = -alpha Dg^T w and S1 = [alpha/2 |w|^2 + A (sigma(u):eps(p) +
+ *   P1 mass of the Gamma_1 facets; J (device [n_pairs]) the cost of each
+ *   pair.  stats sum the four solves.  Returns FO_OK, FO_NOT_CONVERGED,
+ *   FO_ERR_BREAKDOWN, FO_ERR_ARG (kappa inconsistent with the contexts'
+ *   ersatz value, contexts of different sizes or devices, n_pairs < 1,
+ *   ld < n_pairs) or FO_ERR_STATE (atomic scatter).
+ * fo_inverse_derivative: the descent right-hand side rhs (device [n_dofs])
+ *   of eq. SDelast_inv summed over the pairs in pair order, per pair
+ *   rhs_(a,i) = -(int S0_i lambda_a + int (S1 grad lambda_a)_i) with S0 =
+ *   -alpha Dg^T w and S1 = [alpha/2 |w|^2 + A (sigma(u):eps(p) +
  *   sigma(v+g):eps(q))] I - A (Du^T sigma(p) + Dp^T sigma(u) + Dv^T sigma(q)
  *   + Dq^T sigma(v+g)), w = u - v - g, (Du)_ij = d_j u_i, for the level set
  *   last set on ctx_f.  The velocity of the paper's H^1_0 setting is then
  *   fo_descent_solve on ctx_f with fixed = the boundary unknowns. */
-int fo_inverse_states(fo_ctx *ctx_f, fo_ctx *ctx_g, const double *phi, const double *f, const double *g,
-                      double kappa, double alpha, double beta, const fo_solve_opts *opts, double *u, double *v,
-                      double *p, double *q, double *J, fo_solve_stats *stats);
-int fo_inverse_derivative(fo_ctx *ctx_f, const double *u, const double *v, const double *p, const double *q,
-                          const double *g, double kappa, double alpha, double *rhs);
+int fo_inverse_states(fo_ctx *ctx_f, fo_ctx *ctx_g, const double *phi, int32_t n_pairs, int64_t ld,
+                      const double *f, const double *g, double kappa, double alpha, double beta,
+                      const fo_solve_opts *opts, double *u, double *v, double *p, double *q, double *J,
+                      fo_solve_stats *stats);
+int fo_inverse_derivative(fo_ctx *ctx_f, int32_t n_pairs, int64_t ld, const double *u, const double *v,
+                          const double *p, const double *q, const double *g, double kappa, double alpha,
+                          double *rhs);
 
 /* Kernel timing for measurement tools.  While enabled, every launch of the
  * kernels named below is bracketed by a pair of HIP events recorded on the

@@ -233,6 +233,7 @@ struct fo_ctx {
 
     // inverse elasticity work buffers, allocated on the first call
     void *inv_buf = nullptr;
+    size_t inv_cap = 0;                // doubles in inv_buf
 
     // batched multi-load solves (allocated when max_rhs > 1)
     fo::BatchState batch;

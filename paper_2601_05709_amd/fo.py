@@ -107,9 +107,10 @@ EXPORTS = {
     "fo_heat_load": ([_vp, _vp, _vp], C.c_int),
     "fo_heat_solve": ([_vp, _vp, _vp, _vp, C.POINTER(fo_solve_opts), C.POINTER(fo_solve_stats)], C.c_int),
     "fo_heat_derivative": ([_vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp, _vp], C.c_int),
-    "fo_inverse_states": ([_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double,
+    "fo_inverse_states": ([_vp, _vp, _vp, C.c_int32, C.c_int64, _vp, _vp, C.c_double, C.c_double, C.c_double,
                            C.POINTER(fo_solve_opts), _vp, _vp, _vp, _vp, _vp, C.POINTER(fo_solve_stats)], C.c_int),
-    "fo_inverse_derivative": ([_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp], C.c_int),
+    "fo_inverse_derivative": ([_vp, C.c_int32, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp],
+                              C.c_int),
     "fo_reinit": ([_vp, _vp, C.c_int32, C.c_double, C.POINTER(fo_solve_opts), C.POINTER(fo_solve_stats)],
                   C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
@@ -421,29 +422,37 @@ class Context:
                                         _ptr(vol, torch.float64, 1, "vol")), "fo_heat_derivative")
 
     def inverse_states(self, ctx_g: "Context", phi, f, g, kappa: float, alpha: float, beta: float, u, v, p, q, J,
-                       opts: Optional[SolveOpts] = None, allow_not_converged=False) -> Stats:
-        """States u, v, adjoints p, q and cost J of the inverse elasticity
-        problem (fo_inverse_states); self clamps Gamma_0, ctx_g the whole
+                       opts: Optional[SolveOpts] = None, n_pairs: int = 1, ld: Optional[int] = None,
+                       allow_not_converged=False) -> Stats:
+        """States u, v, adjoints p, q and the cost J [n_pairs] of the inverse
+        elasticity problem (fo_inverse_states) for n_pairs pairs stored as
+        columns of [n_dofs][ld] arrays; self clamps Gamma_0, ctx_g the whole
         boundary, both with ersatz = 1/kappa."""
         import torch
         opts = opts or SolveOpts(precision=FO_FP64, rtol=1e-10)
+        ld = n_pairs if ld is None else ld
         st = fo_solve_stats()
-        n = self.n_dofs
-        rc = lib().fo_inverse_states(self.h, ctx_g.h, _ptr(phi, torch.float64, self.n_nodes, "phi"),
-                                     _ptr(f, torch.float64, n, "f"), _ptr(g, torch.float64, n, "g"), float(kappa),
-                                     float(alpha), float(beta), C.byref(opts.c()), _ptr(u, torch.float64, n, "u"),
-                                     _ptr(v, torch.float64, n, "v"), _ptr(p, torch.float64, n, "p"),
-                                     _ptr(q, torch.float64, n, "q"), _ptr(J, torch.float64, 1, "J"), C.byref(st))
+        n = self.n_dofs * ld
+        rc = lib().fo_inverse_states(self.h, ctx_g.h, _ptr(phi, torch.float64, self.n_nodes, "phi"), int(n_pairs),
+                                     int(ld), _ptr(f, torch.float64, n, "f"), _ptr(g, torch.float64, n, "g"),
+                                     float(kappa), float(alpha), float(beta), C.byref(opts.c()),
+                                     _ptr(u, torch.float64, n, "u"), _ptr(v, torch.float64, n, "v"),
+                                     _ptr(p, torch.float64, n, "p"), _ptr(q, torch.float64, n, "q"),
+                                     _ptr(J, torch.float64, n_pairs, "J"), C.byref(st))
         _check(rc, "fo_inverse_states", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
         return Stats(st.status, st.iters_inner, st.iters_outer, st.rel_res, st.seconds)
 
-    def inverse_derivative(self, u, v, p, q, g, kappa: float, alpha: float, rhs):
-        """Descent right-hand side of the inverse problem (fo_inverse_derivative)."""
+    def inverse_derivative(self, u, v, p, q, g, kappa: float, alpha: float, rhs, n_pairs: int = 1,
+                           ld: Optional[int] = None):
+        """Descent right-hand side of the inverse problem summed over the
+        pairs (fo_inverse_derivative)."""
         import torch
-        n = self.n_dofs
-        _check(lib().fo_inverse_derivative(self.h, *(_ptr(x, torch.float64, n, nm) for x, nm in
-                                                     ((u, "u"), (v, "v"), (p, "p"), (q, "q"), (g, "g"))),
-                                           float(kappa), float(alpha), _ptr(rhs, torch.float64, n, "rhs")),
+        ld = n_pairs if ld is None else ld
+        n = self.n_dofs * ld
+        _check(lib().fo_inverse_derivative(self.h, int(n_pairs), int(ld),
+                                           *(_ptr(x, torch.float64, n, nm) for x, nm in
+                                             ((u, "u"), (v, "v"), (p, "p"), (q, "q"), (g, "g"))),
+                                           float(kappa), float(alpha), _ptr(rhs, torch.float64, self.n_dofs, "rhs")),
                "fo_inverse_derivative")
 
     def reinit(self, phi, steps: int = 8, t_end: float = 0.1, opts: Optional[SolveOpts] = None,

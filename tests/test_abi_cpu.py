@@ -80,9 +80,9 @@ def test_null_arguments_rejected(lib):
 
 def test_inverse_entries_reject_null_arguments(lib):
     from paper_2601_05709_amd import fo
-    assert lib.fo_inverse_states(None, None, None, None, None, 10.0, 1.0, 1.0, None, None, None, None, None,
+    assert lib.fo_inverse_states(None, None, None, 1, 1, None, None, 10.0, 1.0, 1.0, None, None, None, None, None,
                                  None, None) == fo.FO_ERR_ARG
-    assert lib.fo_inverse_derivative(None, None, None, None, None, None, 10.0, 1.0, None) == fo.FO_ERR_ARG
+    assert lib.fo_inverse_derivative(None, 1, 1, None, None, None, None, None, 10.0, 1.0, None) == fo.FO_ERR_ARG
 
 
 def test_descent_opts_layout_and_defaults():

@@ -77,6 +77,50 @@ def test_inverse_states_and_derivative(name, precision):
 
 
 @pytest.mark.parametrize("name", list(CELLS))
+@pytest.mark.parametrize("precision", [fo.FO_FP64, fo.FO_FP32_IR])
+def test_inverse_several_pairs(name, precision):
+    """Three force-displacement pairs as the columns of [n_dofs][4] arrays
+    (one padding column, NaN): each pair against the oracle, the derivative
+    against the sum of the oracle's."""
+    npairs, ld = 3, 4
+    wi = fi.inverse_elasticity(CELLS[name], n_pairs=npairs)
+    print("case inverse pairs %s precision %d" % (name, precision), flush=True)
+    refs = [oi.inverse_iteration(wi.pair(k)) for k in range(npairs)]
+    cf, cg = contexts(wi)
+    n = wi.mesh.n_dofs
+
+    def cols(arrs):
+        a = np.full((n, ld), np.nan)
+        a[:, :npairs] = np.stack(arrs, axis=1)
+        return dev(a)
+
+    out = {k: torch.zeros(n * ld, dtype=torch.float64, device="cuda") for k in "uvpq"}
+    J = zeros(npairs)
+    g = cols(wi.gs)
+    # (FP64 CG stalls near a relative residual of 1.3e-12 on the tilted pairs' solves)
+    rtol, tol = (1e-11, 1e-8) if precision == fo.FO_FP64 else (1e-10, 1e-7)
+    st = cf.inverse_states(cg, dev(wi.phi), cols(wi.fs), g, wi.kappa, wi.alpha, wi.beta, out["u"], out["v"],
+                           out["p"], out["q"], J, fo.SolveOpts(precision=precision, rtol=rtol), n_pairs=npairs, ld=ld)
+    assert st.status == 0
+    for k in range(npairs):
+        for key in "uvpq":
+            got = out[key].cpu().numpy().reshape(n, ld)[:, k]
+            assert rel(got, refs[k][key]) < tol, (k, key)
+        assert float(J[k]) == pytest.approx(refs[k]["J"], rel=tol)
+    rhs = zeros(n)
+    cf.inverse_derivative(out["u"], out["v"], out["p"], out["q"], g, wi.kappa, wi.alpha, rhs, n_pairs=npairs, ld=ld)
+    total = sum(r["rhs"] for r in refs)
+    assert rel(rhs.cpu().numpy(), total) < 10 * tol
+    # the sum is taken pair by pair: one pair alone gives that pair's term
+    cf.inverse_derivative(out["u"], out["v"], out["p"], out["q"], g, wi.kappa, wi.alpha, rhs, n_pairs=1, ld=ld)
+    assert rel(rhs.cpu().numpy(), refs[0]["rhs"]) < 10 * tol
+    # a stride below the pair count: refused
+    with pytest.raises(fo.FoError):
+        cf.inverse_states(cg, dev(wi.phi), cols(wi.fs), g, wi.kappa, wi.alpha, wi.beta, out["u"], out["v"],
+                          out["p"], out["q"], J, n_pairs=npairs, ld=npairs - 1)
+
+
+@pytest.mark.parametrize("name", list(CELLS))
 def test_inverse_clamped_velocity(name):
     wi = fi.inverse_elasticity(CELLS[name])
     print("case inverse velocity %s" % name, flush=True)

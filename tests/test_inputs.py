@@ -124,3 +124,24 @@ def test_seeded_generators_are_deterministic():
     assert r1.name == r2.name and np.array_equal(r1.phi, r2.phi) and np.array_equal(r1.b, r2.b)
     t = fi.poisson_arrivals(1000)
     assert np.all(np.diff(t) > 0) and 3.0 < t[-1] < 7.0
+
+
+def test_inverse_pairs():
+    """Pair 0 of a multi-pair inverse workload is the single-pair workload;
+    every pair's traction integrates to its direction times the patch
+    measure, and every g_k vanishes on Gamma_0."""
+    for cells, area in (((24, 12), 0.4), ((8, 4, 4), 0.16)):
+        one = fi.inverse_elasticity(cells)
+        w = fi.inverse_elasticity(cells, n_pairs=4)
+        d = len(cells)
+        assert w.n_pairs == 4 and one.n_pairs == 1
+        assert np.array_equal(w.fs[0], one.f) and np.array_equal(w.gs[0], one.g)
+        for k in range(4):
+            t = w.fs[k].reshape(-1, d).sum(axis=0)
+            ang = 0.35 * k
+            expect = np.array((-np.cos(ang), np.sin(ang)) + ((0.5 * np.sin(ang),) if d == 3 else ())) * area
+            np.testing.assert_allclose(t, expect, atol=1e-12)
+            assert np.all(w.gs[k][w.fixed0 == 1] == 0.0)
+            pk = w.pair(k)
+            assert pk.n_pairs == 1 and pk.f is w.fs[k] and pk.g is w.gs[k]
+        assert w.columns(w.fs).shape == (w.mesh.n_dofs, 4)
