@@ -353,6 +353,8 @@ def main():
     log("heat model: state %d BiCGStab applications (%.1f ms), descent %d its, %.1f ms in all"
         % (st_ht.iters_inner, st_ht.seconds * 1e3, dst_ht.iters_inner, t_ht * 1e3))
 
+    loop_iters = 4  # iterations of the timed loops (inverse and compliance)
+
     # the paper's inverse elasticity problem (Kohn-Vogelius, kappa = 10) on a
     # mesh of the same size: states u, v and adjoints p, q (FP32 CG + FP64
     # refinement to rel. res 1e-8), cost, S0/S1 derivative and the H^1_0
@@ -392,6 +394,20 @@ def main():
     log("inverse problem: 4 state solves %d + %d its (%.1f ms), velocity %d its, %.1f ms in all, J %.4g"
         % (st_iv.iters_inner, st_iv.iters_outer, st_iv.seconds * 1e3, dst_iv.iters_inner, t_iv * 1e3,
            float(J_iv.item())))
+
+    # Algorithm 1 on the inverse problem (fo_optimize_inverse): a few
+    # iterations from the initial inclusion, one pair
+    phi_il = phi_inv.clone()
+    cf_inv.optimize_inverse(cg_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, phi_il, 1, dopts_iv)  # warm-up
+    phi_il.copy_(phi_inv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    il_recs, _ = cf_inv.optimize_inverse(cg_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, phi_il, loop_iters,
+                                         dopts_iv)
+    torch.cuda.synchronize()
+    t_il = time.perf_counter() - t0
+    log("inverse loop: %d iterations in %.3f s (%.1f ms per iteration), J %s"
+        % (len(il_recs), t_il, 1e3 * t_il / len(il_recs), ["%.5g" % r["J"] for r in il_recs]))
     cf_inv.close()
     cg_inv.close()
 
@@ -427,7 +443,6 @@ def main():
     # the paper's loop (Algorithm 1, fo_optimize): a few iterations from the
     # initial design with the PPL volume constraint at 90% of its volume, the
     # paper's time-stepping defaults and transport step
-    loop_iters = 4
     b_lp = it_ir.b[:, 0].contiguous()
     V_lp = 0.9 * float(outs_ir[-1].vol.item())
     phi_lp = it_ir.phi0.clone()
@@ -524,7 +539,12 @@ def main():
                                       "refinement, derivative summed over the pairs, one velocity solve", "n_pairs": npairs, "ms": t_ip * 1e3, "ms_per_pair": t_ip * 1e3 / npairs,
                               "states_ms": st_ip.seconds * 1e3,
                               "state_iters": {"inner": st_ip.iters_inner, "outer": st_ip.iters_outer},
-                              "descent_iters": dst_ip.iters_inner}},
+                              "descent_iters": dst_ip.iters_inner},
+                    "loop": {"what": "Algorithm 1 on the inverse problem (fo_optimize_inverse), one pair, from "
+                                     "the initial inclusion", "iterations": len(il_recs), "seconds": t_il,
+                             "ms_per_iteration": 1e3 * t_il / len(il_recs),
+                             "records": [{k: r[k] for k in ("J", "steps", "state_iters", "descent_iters",
+                                                            "transport_iters")} for r in il_recs]}},
         "loop": {"what": "the paper's Algorithm 1 (fo_optimize): state and velocity solves in FP32 + FP64 "
                          "refinement, PPL volume constraint at 90% of the initial volume, transport step, "
                          "from the initial design", "iterations": len(lp_recs), "seconds": t_lp,

@@ -230,7 +230,7 @@ typedef struct {
 
 /* One iteration of fo_optimize (host). */
 typedef struct {
-    double J;                  /* compliance b . u                                  */
+    double J;                  /* cost: compliance b . u, or the inverse cost       */
     double vol;                /* sum_e chi_e |T_e|                                 */
     double C;                  /* vol / V (vol without a constraint)                */
     double L;                  /* Proximal-Perturbed Lagrangian (J without a constraint) */
@@ -346,6 +346,20 @@ int fo_inverse_states(fo_ctx *ctx_f, fo_ctx *ctx_g, const double *phi, int32_t n
 int fo_inverse_derivative(fo_ctx *ctx_f, int32_t n_pairs, int64_t ld, const double *u, const double *v,
                           const double *p, const double *q, const double *g, double kappa, double alpha,
                           double *rhs);
+
+/* Algorithm 1 on the inverse problem: fo_optimize's loop with, per
+ * iteration, fo_inverse_states (phi set on both contexts), the cost J =
+ * sum_k J_k (pair order), the stopping test on J (no constraint: opts->V must
+ * be <= 0, the PPL fields are unused), fo_inverse_derivative, the velocity
+ * fo_descent_solve on ctx_f with opts->velocity (the paper's H^1_0 setting:
+ * its fixed mask = the boundary unknowns), the adaptive final time and step
+ * count, fo_transport on ctx_f and, every reinit_step iterations, fo_reinit.
+ * Arguments as fo_inverse_states and fo_optimize; records hold J = L, vol =
+ * C = 0 and lambda = 0.  Allocates its work vectors (4 ld + 2 columns) for
+ * the call.  Returns as fo_optimize. */
+int fo_optimize_inverse(fo_ctx *ctx_f, fo_ctx *ctx_g, const fo_loop_opts *opts, int32_t n_pairs, int64_t ld,
+                        const double *f, const double *g, double kappa, double alpha, double beta, double *phi,
+                        fo_loop_record *records, int32_t *n_done, int32_t *stopped);
 
 /* Kernel timing for measurement tools.  While enabled, every launch of the
  * kernels named below is bracketed by a pair of HIP events recorded on the

@@ -37,7 +37,9 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .oracle import assemble_descent, assemble_elasticity, element_geometry, lame
+from .loop import LoopRecord, LoopResult, should_stop
+from .oracle import adaptive_dt, assemble_descent, assemble_elasticity, element_geometry, lame, transport
+from .reinit import reinit
 
 
 def element_kappa(conn, phi, kappa):
@@ -160,3 +162,45 @@ def velocity(wi, rhs, alpha_v=0.01, rtol=1e-12):
     Bd = assemble_descent(m.dim, m.coords, m.conn, m.bfacets, m.bnormal, alpha_v, 0.0, 0.0, None)
     theta, info = Bd.solve(np.where(wi.fixed_all == 1, 0.0, rhs), wi.fixed_all, rtol=rtol)
     return theta, info
+
+
+def pairs_iteration(wi, phi):
+    """Cost and descent right-hand side summed over the workload's pairs (in
+    pair order) for the level set phi."""
+    J, rhs = 0.0, None
+    for k in range(wi.n_pairs):
+        r = inverse_iteration(wi.pair(k), phi=phi)
+        J += r["J"]
+        rhs = r["rhs"] if rhs is None else rhs + r["rhs"]
+    return J, rhs
+
+
+def optimize_inverse(wi, n_iter: int, smooth: bool = False, dfactor=1e-2, t_range=(1e-3, 1e-1), s_range=(8, 16),
+                     start_to_check=30, prev=10, cost_tol=1e-2, alpha_v=0.01, rtol=1e-12, reinit_step=0,
+                     reinit_pars=(8, 0.1)) -> LoopResult:
+    """Algorithm 1 on the inverse problem (no constraint): per iteration the
+    states and adjoints of every pair, the summed cost, the stopping test on
+    the cost, the summed descent right-hand side, the H^1_0 velocity, the
+    adaptive final time and step count (eqs. tend, steps), the paper's
+    transport step and, every reinit_step iterations, the reinitialisation.
+    Records carry J (= L) and the time stepping; vol and C are 0."""
+    m = wi.mesh
+    phi = np.array(wi.phi, dtype=np.float64)
+    out = LoopResult(phi)
+    Js = []
+    for i in range(n_iter):
+        J, rhs = pairs_iteration(wi, phi)
+        rec = LoopRecord(J, 0.0, 0.0, J, 0.0)
+        out.records.append(rec)
+        Js.append(J)
+        if should_stop(i, Js, None, None, start_to_check, prev, cost_tol):
+            out.stopped = True
+            break
+        theta, _ = velocity(wi, rhs, alpha_v=alpha_v, rtol=rtol)
+        rec.B_tt = float(theta @ rhs)
+        rec.t_end, rec.steps, rec.dt = adaptive_dt(rec.B_tt, dfactor, t_range, s_range)
+        phi, _ = transport(m.dim, m.coords, m.conn, theta, rec.dt, rec.steps, phi, smooth=smooth, rtol=rtol)
+        if reinit_step and i % reinit_step == 0:
+            phi = reinit(m.dim, m.coords, m.conn, phi, steps=reinit_pars[0], t_end=reinit_pars[1])
+    out.phi = phi
+    return out

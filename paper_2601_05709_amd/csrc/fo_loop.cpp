@@ -5,7 +5,10 @@
 // implementation aspects", eqs. tend and steps), the paper's transport step
 // and, every reinit_step iterations, the reinitialisation.  Every step runs
 // on the device through the library's entry points; the host keeps the
-// multipliers and the histories (a few scalars per iteration).
+// multipliers and the histories (a few scalars per iteration).  The same
+// loop drives the compliance problem (fo_optimize) and the inverse problem
+// (fo_optimize_inverse: states, adjoints and derivative of Section "Inverse
+// problem", no constraint).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -167,6 +170,87 @@ int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, 
         if (st < 0) break;
     }
     (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(work);
+    return result;
+}
+
+int fo_optimize_inverse(fo_ctx *cf, fo_ctx *cg, const fo_loop_opts *o, int32_t n_pairs, int64_t ld, const double *f,
+                        const double *g, double kappa, double alpha, double beta, double *phi,
+                        fo_loop_record *records, int32_t *n_done, int32_t *stopped)
+{
+    if (!cf || !cg || !o || !f || !g || !phi || !records || !n_done || !stopped) return FO_ERR_ARG;
+    if (n_pairs < 1 || ld < n_pairs || o->V > 0.0) return FO_ERR_ARG;  // the inverse problem has no constraint
+    if (o->n_iter < 0 || !(o->dfactor > 0.0) || !(o->t_min > 0.0) || !(o->t_max > o->t_min) || o->s_min < 1 ||
+        o->s_max < o->s_min || o->prev < 1 || o->start_to_check < 0)
+        return FO_ERR_ARG;
+    if (o->reinit_step < 0 || (o->reinit_step > 0 && (o->reinit_iters < 1 || !(o->reinit_t > 0.0))))
+        return FO_ERR_ARG;
+    *n_done = 0;
+    *stopped = 0;
+    const int64_t n = cf->ndof;
+    double *work = nullptr;
+    const size_t n_dbl = (size_t)(4 * n * ld + 2 * n + n_pairs + 1);
+    if (hipMalloc(&work, n_dbl * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
+    double *u = work, *v = u + n * ld, *p = v + n * ld, *q = p + n * ld, *rhs = q + n * ld, *theta = rhs + n,
+           *Jd = theta + n, *btt = Jd + n_pairs;
+    std::vector<double> Jh, Jk((size_t)n_pairs);
+    int result = FO_OK;
+    auto fetch = [&](double *host, const double *dev, int k) -> int {
+        if (hipMemcpyAsync(host, dev, k * sizeof(double), hipMemcpyDeviceToHost, cf->stream) != hipSuccess ||
+            hipStreamSynchronize(cf->stream) != hipSuccess)
+            return FO_ERR_HIP;
+        return FO_OK;
+    };
+    for (int i = 0; i < o->n_iter; ++i) {
+        fo_loop_record &rec = records[i];
+        rec = fo_loop_record{};
+        rec.B_tt = rec.t_end = rec.dt = std::numeric_limits<double>::quiet_NaN();
+        fo_solve_stats ss{}, ds{}, ts{};
+        int st = fo_inverse_states(cf, cg, phi, n_pairs, ld, f, g, kappa, alpha, beta, &o->state, u, v, p, q, Jd,
+                                   &ss);
+        if (st >= 0) st = worse(st, fetch(Jk.data(), Jd, n_pairs));
+        rec.state_iters = ss.iters_inner;
+        if (st < 0) {
+            rec.status = st;
+            result = st;
+            *n_done = i + 1;
+            break;
+        }
+        double J = 0.0;
+        for (int k = 0; k < n_pairs; ++k) J += Jk[(size_t)k];  // pair order
+        rec.J = rec.L = J;
+        Jh.push_back(J);
+        *n_done = i + 1;
+        if (stop_test(i, Jh, Jh, Jh, false, *o)) {
+            rec.status = st;
+            result = worse(result, st);
+            *stopped = 1;
+            break;
+        }
+        st = worse(st, fo_inverse_derivative(cf, n_pairs, ld, u, v, p, q, g, kappa, alpha, rhs));
+        if (st >= 0) st = worse(st, fo_descent_solve(cf, &o->velocity, rhs, theta, &o->descent, &ds, btt));
+        double h = 0.0;
+        if (st >= 0) st = worse(st, fetch(&h, btt, 1));
+        rec.descent_iters = ds.iters_inner;
+        if (st >= 0) {
+            rec.B_tt = h;
+            int steps = 0;
+            time_steps(rec.B_tt, *o, &rec.t_end, &steps);
+            rec.steps = steps;
+            rec.dt = rec.t_end / steps;
+            st = worse(st, fo_transport(cf, theta, rec.dt, steps, o->smooth, phi, &o->transport, &ts));
+            rec.transport_iters = ts.iters_inner;
+        }
+        if (st >= 0 && o->reinit_step > 0 && i % o->reinit_step == 0) {
+            fo_solve_stats rs{};
+            st = worse(st, fo_reinit(cf, phi, o->reinit_iters, o->reinit_t, &o->transport, &rs));
+            rec.reinit_iters = rs.iters_inner;
+        }
+        rec.status = st;
+        result = worse(result, st);
+        if (st < 0) break;
+    }
+    (void)hipStreamSynchronize(cf->stream);
     (void)hipFree(work);
     return result;
 }

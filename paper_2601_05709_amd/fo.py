@@ -115,6 +115,9 @@ EXPORTS = {
                   C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int32)], C.c_int),
+    "fo_optimize_inverse": ([_vp, _vp, C.POINTER(fo_loop_opts), C.c_int32, C.c_int64, _vp, _vp, C.c_double,
+                             C.c_double, C.c_double, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32)], C.c_int),
     "fo_transport": ([_vp, _vp, C.c_double, C.c_int32, C.c_int32, _vp, C.POINTER(fo_solve_opts),
                       C.POINTER(fo_solve_stats)], C.c_int),
     "fo_profile_enable": ([_vp, C.c_int32], C.c_int),
@@ -478,32 +481,68 @@ class Context:
         V given: volume constraint vol / V = 1 by the PPL method.  Returns
         (records as dicts, stopped)."""
         import torch
-        so = state_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
-        do = descent_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
-        to = transport_opts or SolveOpts(rtol=1e-10)
-        o = fo_loop_opts(int(n_iter), float(V) if V else 0.0, float(dfactor), float(lv_time[0]),
-                         float(lv_time[1]), int(lv_iter[0]), int(lv_iter[1]), int(bool(smooth)),
-                         int(start_to_check), int(prev), float(cost_tol), float(lgrn_tol), float(ctrn_tol),
-                         float(ppl[0]), float(ppl[1]), float(ppl[2]), float(ppl[3]), so.c(), do.c(), to.c(),
-                         dopts.c(), int(reinit_step or 0), int(reinit_pars[0]), float(reinit_pars[1]))
+        o = _loop_opts(n_iter, V, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, lgrn_tol,
+                       ctrn_tol, ppl, state_opts, descent_opts, transport_opts, dopts, reinit_step, reinit_pars)
         recs = (fo_loop_record * max(1, int(n_iter)))()
         n_done, stopped = C.c_int32(0), C.c_int32(0)
         rc = lib().fo_optimize(self.h, C.byref(o), _ptr(b, torch.float64, self.n_dofs, "b"),
                                _ptr(phi, torch.float64, self.n_nodes, "phi"), recs, C.byref(n_done),
                                C.byref(stopped))
         _check(rc, "fo_optimize", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
-        out = []
-        for r in recs[:n_done.value]:
-            d = {k: getattr(r, k) for k, _ in fo_loop_record._fields_}
-            d["lambda"] = d.pop("lambda_")
-            out.append(d)
-        return out, bool(stopped.value)
+        return _records(recs, n_done.value), bool(stopped.value)
+
+    def optimize_inverse(self, ctx_g: "Context", f, g, kappa: float, alpha: float, beta: float, phi, n_iter: int,
+                         dopts: "DescentOpts", n_pairs: int = 1, ld: Optional[int] = None, smooth=False,
+                         dfactor=1e-2, lv_time=(1e-3, 1e-1), lv_iter=(8, 16), start_to_check=30, prev=10,
+                         cost_tol=1e-2, state_opts: Optional[SolveOpts] = None,
+                         descent_opts: Optional[SolveOpts] = None, transport_opts: Optional[SolveOpts] = None,
+                         reinit_step=0, reinit_pars=(8, 0.1), allow_not_converged=False):
+        """Algorithm 1 on the inverse problem (fo_optimize_inverse): self
+        clamps Gamma_0, ctx_g the whole boundary (both with ersatz 1/kappa);
+        f, g hold n_pairs columns of [n_dofs][ld]; dopts is the velocity form
+        (the paper's H^1_0 setting: fixed = the boundary unknowns).  phi is
+        updated in place.  Returns (records as dicts, stopped)."""
+        import torch
+        ld = n_pairs if ld is None else ld
+        o = _loop_opts(n_iter, None, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, 1e-2,
+                       1e-2, (0.999, 0.5, 2000.0, 0.5), state_opts, descent_opts, transport_opts, dopts,
+                       reinit_step, reinit_pars)
+        recs = (fo_loop_record * max(1, int(n_iter)))()
+        n_done, stopped = C.c_int32(0), C.c_int32(0)
+        n = self.n_dofs * ld
+        rc = lib().fo_optimize_inverse(self.h, ctx_g.h, C.byref(o), int(n_pairs), int(ld),
+                                       _ptr(f, torch.float64, n, "f"), _ptr(g, torch.float64, n, "g"), float(kappa),
+                                       float(alpha), float(beta), _ptr(phi, torch.float64, self.n_nodes, "phi"),
+                                       recs, C.byref(n_done), C.byref(stopped))
+        _check(rc, "fo_optimize_inverse", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
+        return _records(recs, n_done.value), bool(stopped.value)
 
     def levelset_update(self, theta, dt: float, phi):
         import torch
         _check(lib().fo_levelset_update(self.h, _ptr(theta, torch.float64, self.n_dofs, "theta"),
                                         float(dt), _ptr(phi, torch.float64, self.n_nodes, "phi")),
                "fo_levelset_update")
+
+
+def _loop_opts(n_iter, V, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, lgrn_tol, ctrn_tol,
+               ppl, state_opts, descent_opts, transport_opts, dopts, reinit_step, reinit_pars) -> fo_loop_opts:
+    so = state_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
+    do = descent_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
+    to = transport_opts or SolveOpts(rtol=1e-10)
+    return fo_loop_opts(int(n_iter), float(V) if V else 0.0, float(dfactor), float(lv_time[0]), float(lv_time[1]),
+                        int(lv_iter[0]), int(lv_iter[1]), int(bool(smooth)), int(start_to_check), int(prev),
+                        float(cost_tol), float(lgrn_tol), float(ctrn_tol), float(ppl[0]), float(ppl[1]),
+                        float(ppl[2]), float(ppl[3]), so.c(), do.c(), to.c(), dopts.c(), int(reinit_step or 0),
+                        int(reinit_pars[0]), float(reinit_pars[1]))
+
+
+def _records(recs, n):
+    out = []
+    for r in recs[:n]:
+        d = {k: getattr(r, k) for k, _ in fo_loop_record._fields_}
+        d["lambda"] = d.pop("lambda_")
+        out.append(d)
+    return out
 
 
 def adaptive_dt(B_tt: float, dfactor=1e-2, t_range=(1e-3, 1e-1), s_range=(8, 16)):

@@ -190,3 +190,47 @@ def test_inverse_moved_inclusion_and_edge_cases():
         assert np.abs(out[k].cpu().numpy()).max() < 1e-9 * np.abs(ref0[k]).max(), k
     cf.inverse_derivative(out["u"], out["v"], out["p"], out["q"], dev(ref0["u"]), wi.kappa, wi.alpha, rhs)
     assert np.abs(rhs.cpu().numpy()).max() < 1e-9 * np.abs(ref0["rhs"]).max() + 1e-14
+
+
+@pytest.mark.parametrize("name,npairs", [("2d_37x19", 2), ("3d_16x8x8", 1)])
+def test_inverse_loop_matches_oracle(name, npairs):
+    """fo_optimize_inverse against the oracle's Algorithm 1 on the inverse
+    problem over three iterations (cost, time stepping, final level set),
+    then the stopping rule."""
+    wi = fi.inverse_elasticity(CELLS[name], n_pairs=npairs)
+    print("case inverse loop %s pairs %d" % (name, npairs), flush=True)
+    cf, cg = contexts(wi)
+    dopts = fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, dim=wi.mesh.dim, fixed=dev(wi.fixed_all, np.uint8))
+    tight = dict(state_opts=fo.SolveOpts(rtol=1e-11), descent_opts=fo.SolveOpts(rtol=1e-11),
+                 transport_opts=fo.SolveOpts(rtol=1e-12))
+    f, g = dev(wi.columns(wi.fs)), dev(wi.columns(wi.gs))
+    ref = oi.optimize_inverse(wi, 3, rtol=1e-12)
+    phi = dev(wi.phi)
+    recs, stopped = cf.optimize_inverse(cg, f, g, wi.kappa, wi.alpha, wi.beta, phi, 3, dopts, n_pairs=npairs, **tight)
+    assert not stopped and not ref.stopped and len(recs) == 3
+    for k, (gr, o) in enumerate(zip(recs, ref.records)):
+        print("iteration %d: J %.12g / %.12g, steps %d / %d" % (k, gr["J"], o.J, gr["steps"], o.steps), flush=True)
+        assert gr["status"] == 0
+        assert gr["J"] == pytest.approx(o.J, rel=1e-8) and gr["L"] == gr["J"]
+        assert gr["steps"] == o.steps
+        assert gr["B_tt"] == pytest.approx(o.B_tt, rel=1e-7)
+        assert gr["t_end"] == pytest.approx(o.t_end, rel=1e-7)
+        assert gr["state_iters"] > 0 and gr["descent_iters"] > 0 and gr["transport_iters"] > 0
+    p = phi.cpu().numpy()
+    assert np.linalg.norm(p - ref.phi) <= 1e-7 * np.linalg.norm(ref.phi)
+    # the stopping rule: both stop at iteration 3 of 8
+    kw = dict(start_to_check=2, prev=2, cost_tol=0.5)
+    refs = oi.optimize_inverse(wi, 8, rtol=1e-12, **kw)
+    phi = dev(wi.phi)
+    recs, stopped = cf.optimize_inverse(cg, f, g, wi.kappa, wi.alpha, wi.beta, phi, 8, dopts, n_pairs=npairs, **kw,
+                                        **tight)
+    assert stopped and refs.stopped and len(recs) == len(refs.records) == 4
+    assert recs[-1]["steps"] == 0
+    # a volume constraint is refused (the inverse problem has none)
+    o = fo._loop_opts(3, 0.5, False, 1e-2, (1e-3, 1e-1), (8, 16), 30, 10, 1e-2, 1e-2, 1e-2, (0.999, 0.5, 2000.0, 0.5),
+                      None, None, None, dopts, 0, (8, 0.1))
+    recs_c = (fo.fo_loop_record * 3)()
+    nd, sp = fo.C.c_int32(0), fo.C.c_int32(0)
+    rc = fo.lib().fo_optimize_inverse(cf.h, cg.h, fo.C.byref(o), npairs, npairs, fo._ptr(f), fo._ptr(g), wi.kappa,
+                                      wi.alpha, wi.beta, fo._ptr(phi), recs_c, fo.C.byref(nd), fo.C.byref(sp))
+    assert rc == fo.FO_ERR_ARG

@@ -98,3 +98,23 @@ def test_mass_matrices_integrate_exactly(dim):
     # int_Gamma1 x_0^2: the faces y = 0, 1 (and z = 0, 1) give int_0^2 x^2 = 8/3 each, the face x = 2 gives 4
     faces = 2 if dim == 2 else 4
     assert x0 @ (MG @ x0) == pytest.approx(dim * (faces * 8.0 / 3.0 + 4.0), rel=1e-13)
+
+
+def test_inverse_loop_decreases_the_cost_and_sums_the_pairs():
+    """Algorithm 1 on the inverse problem: the cost falls over the first
+    iterations; a workload holding the same pair twice doubles the cost and
+    the right-hand side, so theta doubles and B(theta, theta) quadruples;
+    the stopping rule on the cost ends the loop where its definition says."""
+    wi = fi.inverse_elasticity((37, 19))
+    r = oi.optimize_inverse(wi, 5)
+    Js = [rec.J for rec in r.records]
+    assert all(b < a for a, b in zip(Js, Js[1:]))
+    assert all(rec.B_tt > 0 and rec.steps >= 8 for rec in r.records)
+    twice = fi.InverseWorkload(wi.mesh, wi.fixed0, wi.fixed_all, wi.f, wi.g, wi.phi, wi.kappa, wi.alpha, wi.beta,
+                               wi.E, wi.nu, wi.plane_stress, fs=[wi.f, wi.f], gs=[wi.g, wi.g])
+    r2 = oi.optimize_inverse(twice, 1)
+    assert r2.records[0].J == pytest.approx(2.0 * r.records[0].J, rel=1e-13)
+    assert r2.records[0].B_tt == pytest.approx(4.0 * r.records[0].B_tt, rel=1e-9)
+    # |J_3 - J_j| < 0.5 |J_3| for j = 1, 2: the first test, at i = 3, stops
+    rs = oi.optimize_inverse(wi, 8, start_to_check=2, prev=2, cost_tol=0.5)
+    assert rs.stopped and len(rs.records) == 4 and rs.records[-1].steps == 0
