@@ -353,7 +353,21 @@ def main():
     log("heat model: state %d BiCGStab applications (%.1f ms), descent %d its, %.1f ms in all"
         % (st_ht.iters_inner, st_ht.seconds * 1e3, dst_ht.iters_inner, t_ht * 1e3))
 
-    loop_iters = 4  # iterations of the timed loops (inverse and compliance)
+    loop_iters = 4  # iterations of the timed loops (heat, inverse and compliance)
+
+    # Algorithm 1 on the heat model (fo_optimize_heat): a few iterations with
+    # the PPL volume constraint at 90% of the initial volume
+    V_ht = 0.9 * float(vol_ht.item())
+    phi_hl = it_ir.phi0.clone()
+    it_ir.ctx.optimize_heat(g0_ht, f_ht, phi_hl, 1, it_ir.dopts, V=V_ht)  # warm-up
+    phi_hl.copy_(it_ir.phi0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hl_recs, _ = it_ir.ctx.optimize_heat(g0_ht, f_ht, phi_hl, loop_iters, it_ir.dopts, V=V_ht)
+    torch.cuda.synchronize()
+    t_hl = time.perf_counter() - t0
+    log("heat loop: %d iterations in %.3f s (%.1f ms per iteration), J %s"
+        % (len(hl_recs), t_hl, 1e3 * t_hl / len(hl_recs), ["%.5g" % r["J"] for r in hl_recs]))
 
     # the paper's inverse elasticity problem (Kohn-Vogelius, kappa = 10) on a
     # mesh of the same size: states u, v and adjoints p, q (FP32 CG + FP64
@@ -529,7 +543,12 @@ def main():
         "heat": {"what": "the paper's heat-conduction model on the same mesh (f = 1, u = 0 on x = 0): load, "
                          "FP64 state solve to rel. res 1e-8, S0/S1 derivative, FP32 + refinement velocity solve",
                  "ms": t_ht * 1e3, "state_ms": st_ht.seconds * 1e3, "state_operator_applications": st_ht.iters_inner,
-                 "descent_iters": dst_ht.iters_inner, "J": float(J_ht.item())},
+                 "descent_iters": dst_ht.iters_inner, "J": float(J_ht.item()),
+                 "loop": {"what": "Algorithm 1 on the heat model (fo_optimize_heat), PPL volume constraint at 90% "
+                                  "of the initial volume", "iterations": len(hl_recs), "seconds": t_hl,
+                          "ms_per_iteration": 1e3 * t_hl / len(hl_recs),
+                          "records": [{k: r[k] for k in ("J", "C", "lambda", "steps", "state_iters",
+                                                         "descent_iters", "transport_iters")} for r in hl_recs]}},
         "inverse": {"what": "the paper's inverse elasticity problem (kappa = 10, alpha = beta = 1) on a mesh of the "
                             "same size: u, v, p, q by FP32 CG + FP64 refinement to rel. res 1e-8, cost, S0/S1 "
                             "derivative, H^1_0 velocity solve", "ms": t_iv * 1e3, "states_ms": st_iv.seconds * 1e3,

@@ -230,7 +230,7 @@ typedef struct {
 
 /* One iteration of fo_optimize (host). */
 typedef struct {
-    double J;                  /* cost: compliance b . u, or the inverse cost       */
+    double J;                  /* cost: compliance b . u, heat u . K u, inverse cost */
     double vol;                /* sum_e chi_e |T_e|                                 */
     double C;                  /* vol / V (vol without a constraint)                */
     double L;                  /* Proximal-Perturbed Lagrangian (J without a constraint) */
@@ -346,6 +346,17 @@ int fo_inverse_states(fo_ctx *ctx_f, fo_ctx *ctx_g, const double *phi, int32_t n
 int fo_inverse_derivative(fo_ctx *ctx_f, int32_t n_pairs, int64_t ld, const double *u, const double *v,
                           const double *p, const double *q, const double *g, double kappa, double alpha,
                           double *rhs);
+
+/* Algorithm 1 on the heat-conduction model: fo_optimize's loop (the PPL
+ * volume constraint when opts->V > 0, the stopping rule, the velocity with
+ * opts->velocity, the adaptive time stepping, transport, reinitialisation)
+ * with, per iteration, fo_set_levelset, fo_heat_solve with opts->state (its
+ * rtol and max_iter), fo_heat_derivative (J = u . K u and the volume, then
+ * the right-hand side of S^J + lambda S^C).  gamma0: device [n_nodes] uint8
+ * (u = 0 where set); f: device [n_nodes] P1 source, its load computed once.
+ * Allocates its work vectors for the call.  Returns as fo_optimize. */
+int fo_optimize_heat(fo_ctx *ctx, const fo_loop_opts *opts, const uint8_t *gamma0, const double *f, double *phi,
+                     fo_loop_record *records, int32_t *n_done, int32_t *stopped);
 
 /* Algorithm 1 on the inverse problem: fo_optimize's loop with, per
  * iteration, fo_inverse_states (phi set on both contexts), the cost J =

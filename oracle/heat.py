@@ -97,3 +97,56 @@ def heat_iteration(dim, coords, conn, phi, f, fixed_nodes, ersatz=1e-3, lambda_v
     vol = float((chi * element_geometry(dim, coords, conn)[0]).sum())
     rhs = derivative(dim, coords, conn, A_e, chi, u, f, lambda_vol, V)
     return u, J, vol, rhs, A_e, chi
+
+
+def optimize_heat(w, f, fixed_nodes, n_iter: int, V=None, smooth: bool = False, dfactor=1e-2, t_range=(1e-3, 1e-1),
+                  s_range=(8, 16), start_to_check=30, prev=10, cost_tol=1e-2, lgrn_tol=1e-2, ctrn_tol=1e-2,
+                  rtol=1e-12, reinit_step=0, reinit_pars=(8, 0.1)):
+    """Algorithm 1 on the heat model for the mesh, level set, ersatz value
+    and velocity form of the fo_inputs.Workload w, the P1 source f and the
+    fixed nodes: per iteration the state, cost and volume, the stopping test,
+    the PPL update (V given), the descent right-hand side of S^J + lambda
+    S^C, the velocity solve, the adaptive time stepping, the paper's
+    transport step and, every reinit_step iterations, the reinitialisation.
+    Returns a LoopResult of the oracle loop."""
+    from .loop import PPL, LoopRecord, LoopResult, should_stop
+    from .oracle import adaptive_dt, assemble_descent, transport
+    from .reinit import reinit
+    m = w.mesh
+    dim = m.dim
+    Bd = assemble_descent(dim, m.coords, m.conn, m.bfacets, m.bnormal, w.alpha, w.gamma_n, w.gamma_s, w.boxes)
+    phi = np.array(w.phi, dtype=np.float64)
+    ppl = PPL(1) if V is not None else None
+    Vd = 1.0 if V is None else float(V)
+    out = LoopResult(phi)
+    Js, Ls, Cs = [], [], []
+    for i in range(n_iter):
+        u, J, vol, rhs0, A_e, chi = heat_iteration(dim, m.coords, m.conn, phi, f, fixed_nodes, ersatz=w.ersatz,
+                                                   lambda_vol=0.0, V=Vd)
+        lam = 0.0
+        C = vol / Vd
+        if ppl is not None:
+            if i >= 1:
+                ppl.update([C])
+            lam = float(ppl.lam[0])
+            L = ppl.lagrangian(J, [C])
+        else:
+            L = J
+        rec = LoopRecord(J, vol, C, L, lam)
+        out.records.append(rec)
+        Js.append(J)
+        Ls.append(L)
+        Cs.append(np.array([C]))
+        if should_stop(i, Js, Ls if ppl else None, Cs if ppl else None, start_to_check, prev, cost_tol, lgrn_tol,
+                       ctrn_tol):
+            out.stopped = True
+            break
+        rhs = rhs0 if lam == 0.0 else derivative(dim, m.coords, m.conn, A_e, chi, u, f, lam, Vd)
+        theta, _ = Bd.solve(rhs.ravel(), None, rtol=rtol)
+        rec.B_tt = float(theta @ rhs.ravel())
+        rec.t_end, rec.steps, rec.dt = adaptive_dt(rec.B_tt, dfactor, t_range, s_range)
+        phi, _ = transport(dim, m.coords, m.conn, theta, rec.dt, rec.steps, phi, smooth=smooth, rtol=rtol)
+        if reinit_step and i % reinit_step == 0:
+            phi = reinit(dim, m.coords, m.conn, phi, steps=reinit_pars[0], t_end=reinit_pars[1])
+    out.phi = phi
+    return out

@@ -5,14 +5,16 @@
 // implementation aspects", eqs. tend and steps), the paper's transport step
 // and, every reinit_step iterations, the reinitialisation.  Every step runs
 // on the device through the library's entry points; the host keeps the
-// multipliers and the histories (a few scalars per iteration).  The same
-// loop drives the compliance problem (fo_optimize) and the inverse problem
-// (fo_optimize_inverse: states, adjoints and derivative of Section "Inverse
-// problem", no constraint).
+// multipliers and the histories (a few scalars per iteration).  One driver
+// runs the loop for each model: the compliance problem (fo_optimize), the
+// heat-conduction model (fo_optimize_heat) and the inverse problem
+// (fo_optimize_inverse, no constraint); a model supplies the evaluation of
+// cost and volume for the current level set and the descent right-hand side.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <limits>
 #include <vector>
 
@@ -75,59 +77,62 @@ int worse(int a, int b)
     return std::max(a, b);
 }
 
-}  // namespace
-
-extern "C" {
-
-int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, fo_loop_record *records,
-                int32_t *n_done, int32_t *stopped)
+bool loop_opts_ok(const fo_loop_opts *o)
 {
-    if (!c || !o || !b || !phi || !records || !n_done || !stopped) return FO_ERR_ARG;
     if (o->n_iter < 0 || !(o->dfactor > 0.0) || !(o->t_min > 0.0) || !(o->t_max > o->t_min) || o->s_min < 1 ||
         o->s_max < o->s_min || o->prev < 1 || o->start_to_check < 0)
-        return FO_ERR_ARG;
-    if (o->reinit_step < 0 || (o->reinit_step > 0 && (o->reinit_iters < 1 || !(o->reinit_t > 0.0))))
-        return FO_ERR_ARG;
+        return false;
+    if (o->reinit_step < 0 || (o->reinit_step > 0 && (o->reinit_iters < 1 || !(o->reinit_t > 0.0)))) return false;
+    if (o->V > 0.0 && (!(o->ppl_r > 0.0 && o->ppl_r < 1.0) || !(o->ppl_alpha > 0.0) || !(o->ppl_beta > 0.0) ||
+                       !(o->ppl_delta0 > 0.0)))
+        return false;
+    return true;
+}
+
+// A model's part of an iteration.  eval: set the level set phi, solve the
+// state (and adjoints), return the cost and the volume on the host and the
+// state solves' operator applications.  rhs: the descent right-hand side of
+// S^J + lambda S^C for the last evaluation (device [n_dofs]).
+struct Model {
+    std::function<int(const double *phi, double *J, double *vol, int32_t *state_iters)> eval;
+    std::function<int(double lambda, double *rhs)> rhs;
+};
+
+// Copies k device doubles to the host (stream-ordered, then waits).
+int fetch(fo_ctx *c, double *host, const double *dev, int k)
+{
+    if (hipMemcpyAsync(host, dev, k * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return FO_ERR_HIP;
+    return FO_OK;
+}
+
+// The loop on the context c (velocity, transport and reinitialisation run
+// on c); rhs, theta, btt: device work space [n_dofs], [n_dofs], [1].
+int run_loop(fo_ctx *c, const fo_loop_opts *o, Model &m, double *phi, double *rhs, double *theta, double *btt,
+             fo_loop_record *records, int32_t *n_done, int32_t *stopped)
+{
     const bool constrained = o->V > 0.0;
-    if (constrained && (!(o->ppl_r > 0.0 && o->ppl_r < 1.0) || !(o->ppl_alpha > 0.0) || !(o->ppl_beta > 0.0) ||
-                        !(o->ppl_delta0 > 0.0)))
-        return FO_ERR_ARG;
-    *n_done = 0;
-    *stopped = 0;
-    const int64_t n = c->ndof;
-    double *work = nullptr;
-    if (hipMalloc(&work, (size_t)(3 * n + 4) * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
-    double *u = work, *rhs = u + n, *theta = rhs + n, *scal = theta + n;  // scal: J, vol, B_tt
     const double Vd = constrained ? o->V : 1.0;
     Ppl ppl{o->ppl_r, o->ppl_alpha, o->ppl_beta, o->ppl_delta0};
     std::vector<double> Jh, Lh, Ch;
     int result = FO_OK;
-    auto fetch = [&](double *host, const double *dev, int k) -> int {
-        if (hipMemcpyAsync(host, dev, k * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess)
-            return FO_ERR_HIP;
-        return FO_OK;
-    };
     for (int i = 0; i < o->n_iter; ++i) {
         fo_loop_record &rec = records[i];
         rec = fo_loop_record{};
         rec.B_tt = rec.t_end = rec.dt = std::numeric_limits<double>::quiet_NaN();
-        int st = fo_set_levelset(c, phi);
-        fo_solve_stats ss{}, ds{}, ts{};
-        if (st == FO_OK) st = fo_state_solve(c, b, u, 1, 1, &o->state, &ss);
-        if (st >= 0) st = worse(st, fo_shape_derivative(c, u, 1, 1, 0.0, Vd, rhs, nullptr, scal, scal + 1));
-        double h[3] = {0.0, 0.0, 0.0};
-        if (st >= 0) st = worse(st, fetch(h, scal, 2));
-        rec.state_iters = ss.iters_inner;
+        fo_solve_stats ds{}, ts{};
+        double J = 0.0, vol = 0.0;
+        int st = m.eval(phi, &J, &vol, &rec.state_iters);
         if (st < 0) {
             rec.status = st;
             result = st;
             *n_done = i + 1;
             break;
         }
-        rec.J = h[0];
-        rec.vol = h[1];
-        rec.C = h[1] / Vd;
+        rec.J = J;
+        rec.vol = vol;
+        rec.C = vol / Vd;
         if (constrained) {
             if (i >= 1) ppl.update(rec.C);
             rec.lambda = ppl.lam;
@@ -145,14 +150,14 @@ int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, 
             *stopped = 1;
             break;
         }
-        // S = S^J + lambda S^C: the derivative again, with the multiplier
-        if (rec.lambda != 0.0)
-            st = worse(st, fo_shape_derivative(c, u, 1, 1, rec.lambda, Vd, rhs, nullptr, scal, scal + 1));
-        if (st >= 0) st = worse(st, fo_descent_solve(c, &o->velocity, rhs, theta, &o->descent, &ds, scal + 2));
-        if (st >= 0) st = worse(st, fetch(h + 2, scal + 2, 1));
+        // S = S^J + lambda S^C
+        st = worse(st, m.rhs(rec.lambda, rhs));
+        if (st >= 0) st = worse(st, fo_descent_solve(c, &o->velocity, rhs, theta, &o->descent, &ds, btt));
+        double h = 0.0;
+        if (st >= 0) st = worse(st, fetch(c, &h, btt, 1));
         rec.descent_iters = ds.iters_inner;
         if (st >= 0) {
-            rec.B_tt = h[2];
+            rec.B_tt = h;
             int steps = 0;
             time_steps(rec.B_tt, *o, &rec.t_end, &steps);
             rec.steps = steps;
@@ -170,21 +175,92 @@ int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, 
         if (st < 0) break;
     }
     (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(work);
     return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, fo_loop_record *records,
+                int32_t *n_done, int32_t *stopped)
+{
+    if (!c || !o || !b || !phi || !records || !n_done || !stopped || !loop_opts_ok(o)) return FO_ERR_ARG;
+    *n_done = 0;
+    *stopped = 0;
+    const int64_t n = c->ndof;
+    double *work = nullptr;
+    if (hipMalloc(&work, (size_t)(3 * n + 4) * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
+    double *u = work, *rhs = u + n, *theta = rhs + n, *scal = theta + n;  // scal: J, vol, B_tt
+    const double Vd = o->V > 0.0 ? o->V : 1.0;
+    Model m;
+    m.eval = [&](const double *ph, double *J, double *vol, int32_t *its) -> int {
+        fo_solve_stats ss{};
+        int st = fo_set_levelset(c, ph);
+        if (st == FO_OK) st = fo_state_solve(c, b, u, 1, 1, &o->state, &ss);
+        *its = ss.iters_inner;
+        // the derivative without the constraint term: the multiplier is not known yet
+        if (st >= 0) st = worse(st, fo_shape_derivative(c, u, 1, 1, 0.0, Vd, rhs, nullptr, scal, scal + 1));
+        double h[2] = {0.0, 0.0};
+        if (st >= 0) st = worse(st, fetch(c, h, scal, 2));
+        *J = h[0];
+        *vol = h[1];
+        return st;
+    };
+    m.rhs = [&](double lambda, double *r) -> int {
+        if (lambda == 0.0) return FO_OK;  // rhs holds the derivative without the constraint term
+        return fo_shape_derivative(c, u, 1, 1, lambda, Vd, r, nullptr, scal, scal + 1);
+    };
+    const int rc = run_loop(c, o, m, phi, rhs, theta, scal + 2, records, n_done, stopped);
+    (void)hipFree(work);
+    return rc;
+}
+
+int fo_optimize_heat(fo_ctx *c, const fo_loop_opts *o, const uint8_t *gamma0, const double *f, double *phi,
+                     fo_loop_record *records, int32_t *n_done, int32_t *stopped)
+{
+    if (!c || !o || !gamma0 || !f || !phi || !records || !n_done || !stopped || !loop_opts_ok(o)) return FO_ERR_ARG;
+    *n_done = 0;
+    *stopped = 0;
+    const int64_t N = c->N, n = c->ndof;
+    double *work = nullptr;
+    if (hipMalloc(&work, (size_t)(2 * N + 2 * n + 4) * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
+    double *b = work, *u = b + N, *rhs = u + N, *theta = rhs + n, *scal = theta + n;  // scal: J, vol, B_tt
+    const double Vd = o->V > 0.0 ? o->V : 1.0;
+    int rc = fo_heat_load(c, f, b);  // the load does not depend on the level set
+    if (rc != FO_OK) {
+        (void)hipFree(work);
+        return rc;
+    }
+    Model m;
+    m.eval = [&](const double *ph, double *J, double *vol, int32_t *its) -> int {
+        fo_solve_stats ss{};
+        int st = fo_set_levelset(c, ph);
+        if (st == FO_OK) st = fo_heat_solve(c, gamma0, b, u, &o->state, &ss);
+        *its = ss.iters_inner;
+        if (st >= 0) st = worse(st, fo_heat_derivative(c, u, f, 0.0, Vd, rhs, scal, scal + 1));
+        double h[2] = {0.0, 0.0};
+        if (st >= 0) st = worse(st, fetch(c, h, scal, 2));
+        *J = h[0];
+        *vol = h[1];
+        return st;
+    };
+    m.rhs = [&](double lambda, double *r) -> int {
+        if (lambda == 0.0) return FO_OK;
+        return fo_heat_derivative(c, u, f, lambda, Vd, r, scal, scal + 1);
+    };
+    rc = run_loop(c, o, m, phi, rhs, theta, scal + 2, records, n_done, stopped);
+    (void)hipFree(work);
+    return rc;
 }
 
 int fo_optimize_inverse(fo_ctx *cf, fo_ctx *cg, const fo_loop_opts *o, int32_t n_pairs, int64_t ld, const double *f,
                         const double *g, double kappa, double alpha, double beta, double *phi,
                         fo_loop_record *records, int32_t *n_done, int32_t *stopped)
 {
-    if (!cf || !cg || !o || !f || !g || !phi || !records || !n_done || !stopped) return FO_ERR_ARG;
+    if (!cf || !cg || !o || !f || !g || !phi || !records || !n_done || !stopped || !loop_opts_ok(o))
+        return FO_ERR_ARG;
     if (n_pairs < 1 || ld < n_pairs || o->V > 0.0) return FO_ERR_ARG;  // the inverse problem has no constraint
-    if (o->n_iter < 0 || !(o->dfactor > 0.0) || !(o->t_min > 0.0) || !(o->t_max > o->t_min) || o->s_min < 1 ||
-        o->s_max < o->s_min || o->prev < 1 || o->start_to_check < 0)
-        return FO_ERR_ARG;
-    if (o->reinit_step < 0 || (o->reinit_step > 0 && (o->reinit_iters < 1 || !(o->reinit_t > 0.0))))
-        return FO_ERR_ARG;
     *n_done = 0;
     *stopped = 0;
     const int64_t n = cf->ndof;
@@ -193,66 +269,25 @@ int fo_optimize_inverse(fo_ctx *cf, fo_ctx *cg, const fo_loop_opts *o, int32_t n
     if (hipMalloc(&work, n_dbl * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
     double *u = work, *v = u + n * ld, *p = v + n * ld, *q = p + n * ld, *rhs = q + n * ld, *theta = rhs + n,
            *Jd = theta + n, *btt = Jd + n_pairs;
-    std::vector<double> Jh, Jk((size_t)n_pairs);
-    int result = FO_OK;
-    auto fetch = [&](double *host, const double *dev, int k) -> int {
-        if (hipMemcpyAsync(host, dev, k * sizeof(double), hipMemcpyDeviceToHost, cf->stream) != hipSuccess ||
-            hipStreamSynchronize(cf->stream) != hipSuccess)
-            return FO_ERR_HIP;
-        return FO_OK;
-    };
-    for (int i = 0; i < o->n_iter; ++i) {
-        fo_loop_record &rec = records[i];
-        rec = fo_loop_record{};
-        rec.B_tt = rec.t_end = rec.dt = std::numeric_limits<double>::quiet_NaN();
-        fo_solve_stats ss{}, ds{}, ts{};
-        int st = fo_inverse_states(cf, cg, phi, n_pairs, ld, f, g, kappa, alpha, beta, &o->state, u, v, p, q, Jd,
+    std::vector<double> Jk((size_t)n_pairs);
+    Model m;
+    m.eval = [&](const double *ph, double *J, double *vol, int32_t *its) -> int {
+        fo_solve_stats ss{};
+        int st = fo_inverse_states(cf, cg, ph, n_pairs, ld, f, g, kappa, alpha, beta, &o->state, u, v, p, q, Jd,
                                    &ss);
-        if (st >= 0) st = worse(st, fetch(Jk.data(), Jd, n_pairs));
-        rec.state_iters = ss.iters_inner;
-        if (st < 0) {
-            rec.status = st;
-            result = st;
-            *n_done = i + 1;
-            break;
-        }
-        double J = 0.0;
-        for (int k = 0; k < n_pairs; ++k) J += Jk[(size_t)k];  // pair order
-        rec.J = rec.L = J;
-        Jh.push_back(J);
-        *n_done = i + 1;
-        if (stop_test(i, Jh, Jh, Jh, false, *o)) {
-            rec.status = st;
-            result = worse(result, st);
-            *stopped = 1;
-            break;
-        }
-        st = worse(st, fo_inverse_derivative(cf, n_pairs, ld, u, v, p, q, g, kappa, alpha, rhs));
-        if (st >= 0) st = worse(st, fo_descent_solve(cf, &o->velocity, rhs, theta, &o->descent, &ds, btt));
-        double h = 0.0;
-        if (st >= 0) st = worse(st, fetch(&h, btt, 1));
-        rec.descent_iters = ds.iters_inner;
-        if (st >= 0) {
-            rec.B_tt = h;
-            int steps = 0;
-            time_steps(rec.B_tt, *o, &rec.t_end, &steps);
-            rec.steps = steps;
-            rec.dt = rec.t_end / steps;
-            st = worse(st, fo_transport(cf, theta, rec.dt, steps, o->smooth, phi, &o->transport, &ts));
-            rec.transport_iters = ts.iters_inner;
-        }
-        if (st >= 0 && o->reinit_step > 0 && i % o->reinit_step == 0) {
-            fo_solve_stats rs{};
-            st = worse(st, fo_reinit(cf, phi, o->reinit_iters, o->reinit_t, &o->transport, &rs));
-            rec.reinit_iters = rs.iters_inner;
-        }
-        rec.status = st;
-        result = worse(result, st);
-        if (st < 0) break;
-    }
-    (void)hipStreamSynchronize(cf->stream);
+        *its = ss.iters_inner;
+        if (st >= 0) st = worse(st, fetch(cf, Jk.data(), Jd, n_pairs));
+        *J = 0.0;
+        for (int k = 0; k < n_pairs; ++k) *J += Jk[(size_t)k];  // pair order
+        *vol = 0.0;
+        return st;
+    };
+    m.rhs = [&](double, double *r) -> int {
+        return fo_inverse_derivative(cf, n_pairs, ld, u, v, p, q, g, kappa, alpha, r);
+    };
+    const int rc = run_loop(cf, o, m, phi, rhs, theta, btt, records, n_done, stopped);
     (void)hipFree(work);
-    return result;
+    return rc;
 }
 
 }  // extern "C"

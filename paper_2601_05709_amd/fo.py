@@ -115,6 +115,8 @@ EXPORTS = {
                   C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int32)], C.c_int),
+    "fo_optimize_heat": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, _vp, C.POINTER(fo_loop_record),
+                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "fo_optimize_inverse": ([_vp, _vp, C.POINTER(fo_loop_opts), C.c_int32, C.c_int64, _vp, _vp, C.c_double,
                              C.c_double, C.c_double, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32)], C.c_int),
@@ -489,6 +491,29 @@ class Context:
                                _ptr(phi, torch.float64, self.n_nodes, "phi"), recs, C.byref(n_done),
                                C.byref(stopped))
         _check(rc, "fo_optimize", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
+        return _records(recs, n_done.value), bool(stopped.value)
+
+    def optimize_heat(self, gamma0, f, phi, n_iter: int, dopts: "DescentOpts", V: Optional[float] = None,
+                      smooth=False, dfactor=1e-2, lv_time=(1e-3, 1e-1), lv_iter=(8, 16), start_to_check=30, prev=10,
+                      cost_tol=1e-2, lgrn_tol=1e-2, ctrn_tol=1e-2, ppl=(0.999, 0.5, 2000.0, 0.5),
+                      state_opts: Optional[SolveOpts] = None, descent_opts: Optional[SolveOpts] = None,
+                      transport_opts: Optional[SolveOpts] = None, reinit_step=0, reinit_pars=(8, 0.1),
+                      allow_not_converged=False):
+        """Algorithm 1 on the heat-conduction model (fo_optimize_heat):
+        gamma0 uint8 [N] (u = 0 there), f the P1 source [N]; V given: volume
+        constraint by the PPL method.  phi is updated in place.  Returns
+        (records as dicts, stopped)."""
+        import torch
+        o = _loop_opts(n_iter, V, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, lgrn_tol,
+                       ctrn_tol, ppl, state_opts or SolveOpts(rtol=1e-8), descent_opts, transport_opts, dopts,
+                       reinit_step, reinit_pars)
+        recs = (fo_loop_record * max(1, int(n_iter)))()
+        n_done, stopped = C.c_int32(0), C.c_int32(0)
+        rc = lib().fo_optimize_heat(self.h, C.byref(o), _ptr(gamma0, torch.uint8, self.n_nodes, "gamma0"),
+                                    _ptr(f, torch.float64, self.n_nodes, "f"),
+                                    _ptr(phi, torch.float64, self.n_nodes, "phi"), recs, C.byref(n_done),
+                                    C.byref(stopped))
+        _check(rc, "fo_optimize_heat", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
         return _records(recs, n_done.value), bool(stopped.value)
 
     def optimize_inverse(self, ctx_g: "Context", f, g, kappa: float, alpha: float, beta: float, phi, n_iter: int,

@@ -92,3 +92,45 @@ def test_heat_edge_cases():
     ctx.transport(dev(np.full(m.n_dofs, 0.1)), 0.01, 2, phi, fo.SolveOpts(rtol=1e-12))
     ctx.heat_solve(fx, b, u, fo.SolveOpts(rtol=1e-12))
     assert np.linalg.norm(u.cpu().numpy() - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("name", ["2d_37x19", "3d_16x8x8"])
+@pytest.mark.parametrize("constrained", [False, True])
+def test_heat_loop_matches_oracle(name, constrained):
+    """fo_optimize_heat against the oracle's Algorithm 1 on the heat model
+    over three iterations (cost, volume, multiplier, time stepping, final
+    level set), then the stopping rule."""
+    w = WORKLOADS[name]()
+    m = w.mesh
+    f = source(m.coords)
+    fx = gamma0(m)
+    V = 0.9 * oh.heat_iteration(m.dim, m.coords, m.conn, w.phi, f, fx, ersatz=w.ersatz)[2] if constrained else None
+    print("case heat loop %s constrained %s" % (name, constrained), flush=True)
+    ref = oh.optimize_heat(w, f, fx, 3, V=V, dfactor=1.0, rtol=1e-12)
+    ctx = fo.Context.from_workload(w)
+    dopts = fo.DescentOpts(w.alpha, w.gamma_n, w.gamma_s, w.boxes, dim=m.dim)
+    tight = dict(state_opts=fo.SolveOpts(rtol=1e-12), descent_opts=fo.SolveOpts(rtol=1e-11),
+                 transport_opts=fo.SolveOpts(rtol=1e-12))
+    phi = dev(w.phi)
+    recs, stopped = ctx.optimize_heat(dev(fx, np.uint8), dev(f), phi, 3, dopts, V=V, dfactor=1.0, **tight)
+    assert not stopped and not ref.stopped and len(recs) == 3
+    for k, (g, o) in enumerate(zip(recs, ref.records)):
+        print("iteration %d: J %.12g / %.12g, vol %.12g / %.12g, lambda %.6g / %.6g, steps %d / %d" % (
+            k, g["J"], o.J, g["vol"], o.vol, g["lambda"], o.lam, g["steps"], o.steps), flush=True)
+        assert g["status"] == 0
+        assert g["vol"] == pytest.approx(o.vol, rel=1e-12)
+        assert g["J"] == pytest.approx(o.J, rel=1e-8)
+        assert g["L"] == pytest.approx(o.L, rel=1e-8)
+        assert g["lambda"] == pytest.approx(o.lam, rel=1e-9, abs=1e-12)
+        assert g["steps"] == o.steps
+        assert g["B_tt"] == pytest.approx(o.B_tt, rel=1e-7)
+        assert g["state_iters"] > 0 and g["descent_iters"] > 0 and g["transport_iters"] > 0
+    assert np.linalg.norm(phi.cpu().numpy() - ref.phi) <= 1e-7 * np.linalg.norm(ref.phi)
+    if constrained:
+        assert recs[1]["lambda"] > 0.0
+    kw = dict(start_to_check=2, prev=2, cost_tol=0.5)
+    refs = oh.optimize_heat(w, f, fx, 8, V=V, dfactor=1.0, rtol=1e-12, lgrn_tol=0.5, ctrn_tol=0.5, **kw)
+    phi = dev(w.phi)
+    recs, stopped = ctx.optimize_heat(dev(fx, np.uint8), dev(f), phi, 8, dopts, V=V, dfactor=1.0, lgrn_tol=0.5,
+                                      ctrn_tol=0.5, **kw, **tight)
+    assert stopped == refs.stopped and len(recs) == len(refs.records)

@@ -96,3 +96,25 @@ def test_strip_converges_to_the_one_dimensional_solution():
     e = [abs(c - 0.25 / 3.0) for c in costs]
     assert e[0] / e[1] > 3.8 and e[1] / e[2] > 3.8
     assert costs[2] == pytest.approx(0.25 / 3.0, rel=1e-3)
+
+
+def test_heat_loop_direction_multiplier_and_stop():
+    """Algorithm 1 on the heat model: without a constraint the cost falls
+    and the volume grows (conduction wants material); with a volume target
+    below the volume the multiplier rises while the constraint is violated;
+    the stopping rule ends the loop where its definition says."""
+    w = fi.cantilever_2d((48, 24))
+    m = w.mesh
+    f = np.ones(m.n_nodes)
+    g0 = (np.abs(m.coords[:, 0]) < 1e-12).astype(np.uint8)
+    r = oh.optimize_heat(w, f, g0, 4, dfactor=1.0)
+    Js = [x.J for x in r.records]
+    vols = [x.vol for x in r.records]
+    assert all(b < a for a, b in zip(Js, Js[1:])) and all(b > a for a, b in zip(vols, vols[1:]))
+    V = 0.9 * vols[0]
+    rc = oh.optimize_heat(w, f, g0, 4, V=V, dfactor=1.0)
+    lams = [x.lam for x in rc.records]
+    assert lams[0] == 0.0 and all(x.C > 1.0 for x in rc.records)
+    assert all(b > a for a, b in zip(lams, lams[1:]))
+    rs = oh.optimize_heat(w, f, g0, 8, dfactor=1.0, start_to_check=2, prev=2, cost_tol=0.5)
+    assert rs.stopped and len(rs.records) == 4 and rs.records[-1].steps == 0
