@@ -104,3 +104,54 @@ def test_heat_state_at_full_size(full):
     assert np.linalg.norm(r) <= 1.5e-8 * np.linalg.norm(bh[free])
     assert np.all(uh[~free] == 0.0)
     np.testing.assert_allclose(b.cpu().numpy(), bh, rtol=1e-13, atol=1e-18)
+
+
+def test_inverse_at_full_size():
+    """The inverse problem on the 96x48x48 inverse workload, as bench.py
+    times it (FP32 CG + FP64 refinement to 1e-8): each of the four solves'
+    residual with the oracle's stiffness matrix, the cost from the oracle's
+    masses on the GPU's states, the derivative recomputed by the oracle from
+    the same states, and the H^1_0 velocity's residual and mask."""
+    from oracle import inverse as oi
+    wi = fi.inverse_elasticity((96, 48, 48))
+    m = wi.mesh
+    n = m.n_dofs
+    print("case full size: inverse states", flush=True)
+    common = dict(E=wi.E, nu=wi.nu, plane_stress=wi.plane_stress, ersatz=1.0 / wi.kappa)
+    cf = fo.Context(m.dim, m.coords, m.conn, wi.fixed0, m.bfacets, m.bnormal, **common)
+    cg = fo.Context(m.dim, m.coords, m.conn, wi.fixed_all, None, None, **common)
+    out = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = dev(wi.g)
+    cf.inverse_states(cg, dev(wi.phi), dev(wi.f), g, wi.kappa, wi.alpha, wi.beta, *out, J,
+                      fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8))
+    u, v, p, q = (t.cpu().numpy() for t in out)
+    lam, mu = oc.lame(wi.E, wi.nu, m.dim, wi.plane_stress)
+    A_e, _ = oi.element_kappa(m.conn, wi.phi, wi.kappa)
+    K = oc.assemble_elasticity(m.dim, m.coords, m.conn, A_e, lam, mu).to_scipy()
+    M = oi.vector_mass(m.dim, m.coords, m.conn)
+    MG = oi.facet_mass(m.dim, m.coords, m.bfacets)
+    w = u - v - wi.g
+    free0, free_all = wi.fixed0 == 0, wi.fixed_all == 0
+    for name, x, b, free in (("u", u, wi.f, free0), ("v", v, -(K @ wi.g), free_all),
+                             ("p", p, -wi.alpha * (M @ w) - wi.beta * (MG @ (u - wi.g)), free0),
+                             ("q", q, wi.alpha * (M @ w), free_all)):
+        res = (K @ x - b)[free]
+        print("  %s: relative residual %.3e" % (name, np.linalg.norm(res) / np.linalg.norm(b[free])), flush=True)
+        assert np.linalg.norm(res) <= 1.5e-8 * np.linalg.norm(b[free]), name
+        assert np.all(x[~free] == 0.0), name
+    assert float(J) == pytest.approx(oi.cost(M, MG, u, v, wi.g, wi.alpha, wi.beta), rel=1e-9)
+    print("case full size: inverse derivative and velocity", flush=True)
+    rhs = torch.zeros(n, dtype=torch.float64, device="cuda")
+    cf.inverse_derivative(*out, g, wi.kappa, wi.alpha, rhs)
+    rhs_ref = oi.derivative(m.dim, m.coords, m.conn, A_e, lam, mu, u, v, p, q, wi.g, wi.alpha)
+    r = rhs.cpu().numpy()
+    assert np.linalg.norm(r - rhs_ref) <= 1e-12 * np.linalg.norm(rhs_ref)
+    theta = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dopts = fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, dim=3, fixed=dev(wi.fixed_all, np.uint8))
+    cf.descent_solve(dopts, rhs, theta, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8))
+    t = theta.cpu().numpy()
+    Bd = oc.assemble_descent(m.dim, m.coords, m.conn, m.bfacets, m.bnormal, 0.01, 0.0, 0.0, None).to_scipy()
+    res = (Bd @ t - r)[free_all]
+    assert np.linalg.norm(res) <= 1.5e-8 * np.linalg.norm(r[free_all])
+    assert np.all(t[~free_all] == 0.0)

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import fo_inputs as fi
+from oracle import assemble_descent as oc_assemble_descent
 from oracle import inverse as oi
 
 torch = pytest.importorskip("torch")
@@ -143,6 +144,16 @@ def test_inverse_clamped_velocity(name):
         # B(theta, theta) = rhs . theta, taken over the free unknowns
         assert float(B_tt) == pytest.approx(float(np.dot(np.where(wi.fixed_all == 1, 0.0, ref["rhs"]), theta_ref)),
                                             rel=tol)
+    # the masked operator: rows of masked unknowns are zero, the others those of B
+    y = zeros(wi.mesh.n_dofs)
+    cf.apply_descent(fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, fixed=fixed), theta, y)
+    yy = y.cpu().numpy()
+    assert np.all(yy[wi.fixed_all == 1] == 0.0)
+    m = wi.mesh
+    Bd = oc_assemble_descent(m.dim, m.coords, m.conn, m.bfacets, m.bnormal, 0.01, 0.0, 0.0, None).to_scipy()
+    free = wi.fixed_all == 0
+    np.testing.assert_allclose(yy[free], (Bd @ theta.cpu().numpy())[free], rtol=1e-12,
+                               atol=1e-13 * np.abs(yy).max())
     # the same context without the mask solves the unclamped problem again
     st = cf.descent_solve(fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0), rhs, theta,
                           fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-12))
