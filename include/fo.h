@@ -103,8 +103,11 @@ typedef struct {
     int32_t n_boxes;           /* Omega0 = union of open boxes (element centroid)  */
     const double *boxes;       /* host [n_boxes][2*dim]: lo[0..d), hi[0..d)        */
     const uint8_t *fixed;      /* NULL, or device [n_dofs]: theta = 0 where set
-                                  (e.g. H^1_0 velocities); read when the options
-                                  change (a new pointer counts as a change)        */
+                                  (e.g. H^1_0 velocities); the context keeps the
+                                  pointer and reads the mask on every solve or
+                                  apply with these options: keep it allocated and
+                                  unchanged meanwhile (new contents need a new
+                                  pointer, which counts as new options)            */
 } fo_descent_opts;
 
 typedef struct {
@@ -167,10 +170,13 @@ int fo_shape_derivative(fo_ctx *ctx, const double *u, int32_t n_rhs, int64_t ld,
                         double lambda_vol, double V, double *rhs, double *S1, double *J,
                         double *vol);
 
-/* Descent (velocity) solve B theta = rhs on all unknowns (H^1, no clamp).
- * B does not depend on phi: its diagonal is built on the first call with a
- * given opts and reused.  rhs, theta: device [n_dofs]; B_tt: device scalar
- * receiving B(theta, theta) = theta . rhs (> 0 for a descent direction). */
+/* Descent (velocity) solve B theta = rhs on all unknowns (H^1, no clamp),
+ * or, with dopts->fixed, theta = 0 on the masked unknowns and B theta = rhs
+ * on the others (the masked rows and columns of B and entries of rhs drop
+ * out).  B does not depend on phi: its diagonal is built on the first call
+ * with a given opts and reused.  rhs, theta: device [n_dofs]; B_tt: device
+ * scalar receiving B(theta, theta) = theta . rhs (> 0 for a descent
+ * direction).  fo_apply_descent: y = B x, zero on masked rows. */
 int fo_descent_solve(fo_ctx *ctx, const fo_descent_opts *dopts, const double *rhs,
                      double *theta, const fo_solve_opts *opts, fo_solve_stats *stats,
                      double *B_tt);
