@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-only", action="store_true", help="short run for profilers")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-load case")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the timed iteration, the precision check and the roofline (no transport, "
+                         "reinitialisation, heat, inverse or loop measurements)")
     ap.add_argument("--serving", action="store_true",
                     help="also run the serving stream (off by default: a pool teardown ended once in a host "
                          "segmentation fault whose cause is not yet shown)")
@@ -295,181 +298,228 @@ def main():
     st64 = outs_64[-1].state_stats
     log("FP64: %.3f s/step, state %d its, rel.res %.2e" % (t_64 / K64, st64.iters_inner, st64.rel_res))
 
-    # the paper's transport step (Crank-Nicolson Petrov-Galerkin, BiCGStab)
-    # with the velocity and adaptive final time of the last iteration, in
-    # place of the one explicit update step of the timed iteration
-    _, tr_steps, tr_dt = fo.adaptive_dt(float(outs_ir[-1].B_tt.item()))
-    phi_tr = it_ir.phi0.clone()
-    it_ir.ctx.transport(it_ir.theta, tr_dt, tr_steps, phi_tr, fo.SolveOpts(rtol=1e-10))  # warm-up
-    phi_tr.copy_(it_ir.phi0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_tr = it_ir.ctx.transport(it_ir.theta, tr_dt, tr_steps, phi_tr, fo.SolveOpts(rtol=1e-10))
-    torch.cuda.synchronize()
-    t_tr = time.perf_counter() - t0
-    log("transport step: %d Crank-Nicolson steps, %d BiCGStab operator applications, %.1f ms"
-        % (tr_steps, st_tr.iters_inner, t_tr * 1e3))
+    def extras():
+        """The measurements besides the timed iteration: the paper's transport
+        step and reinitialisation, the heat model and its loop, the inverse
+        problem (one pair, its loop, eight pairs) and the compliance loop."""
+        # the paper's transport step (Crank-Nicolson Petrov-Galerkin, BiCGStab)
+        # with the velocity and adaptive final time of the last iteration, in
+        # place of the one explicit update step of the timed iteration
+        _, tr_steps, tr_dt = fo.adaptive_dt(float(outs_ir[-1].B_tt.item()))
+        phi_tr = it_ir.phi0.clone()
+        it_ir.ctx.transport(it_ir.theta, tr_dt, tr_steps, phi_tr, fo.SolveOpts(rtol=1e-10))  # warm-up
+        phi_tr.copy_(it_ir.phi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_tr = it_ir.ctx.transport(it_ir.theta, tr_dt, tr_steps, phi_tr, fo.SolveOpts(rtol=1e-10))
+        torch.cuda.synchronize()
+        t_tr = time.perf_counter() - t0
+        log("transport step: %d Crank-Nicolson steps, %d BiCGStab operator applications, %.1f ms"
+            % (tr_steps, st_tr.iters_inner, t_tr * 1e3))
 
-    # the paper's reinitialisation (diffusive Eikonal, 8 steps to 0.1) of the
-    # transported level set
-    phi_rn = phi_tr.clone()
-    it_ir.ctx.reinit(phi_rn, 8, 0.1, fo.SolveOpts(rtol=1e-10))  # warm-up
-    phi_rn.copy_(phi_tr)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_rn = it_ir.ctx.reinit(phi_rn, 8, 0.1, fo.SolveOpts(rtol=1e-10))
-    torch.cuda.synchronize()
-    t_rn = time.perf_counter() - t0
-    log("reinitialisation: 8 steps, %d BiCGStab operator applications, %.1f ms" % (st_rn.iters_inner, t_rn * 1e3))
+        # the paper's reinitialisation (diffusive Eikonal, 8 steps to 0.1) of the
+        # transported level set
+        phi_rn = phi_tr.clone()
+        it_ir.ctx.reinit(phi_rn, 8, 0.1, fo.SolveOpts(rtol=1e-10))  # warm-up
+        phi_rn.copy_(phi_tr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_rn = it_ir.ctx.reinit(phi_rn, 8, 0.1, fo.SolveOpts(rtol=1e-10))
+        torch.cuda.synchronize()
+        t_rn = time.perf_counter() - t0
+        log("reinitialisation: 8 steps, %d BiCGStab operator applications, %.1f ms" % (st_rn.iters_inner, t_rn * 1e3))
 
-    # the heat-conduction model on the same mesh (scalar P1 state, f = 1,
-    # temperature fixed on the x = 0 face): load, state solve to rel. res
-    # 1e-8, derivative, then the velocity solve as in the timed iteration
-    f_ht = torch.ones(m.n_nodes, dtype=torch.float64, device="cuda")
-    g0_ht = torch.from_numpy((np.abs(m.coords[:, 0]) < 1e-12).astype(np.uint8)).cuda()
-    b_ht = torch.zeros_like(f_ht)
-    u_ht = torch.zeros_like(f_ht)
-    rhs_ht = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
-    J_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
-    vol_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
-    th_ht = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
-    Bt_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
-    it_ir.ctx.set_levelset(it_ir.phi0)
+        # the heat-conduction model on the same mesh (scalar P1 state, f = 1,
+        # temperature fixed on the x = 0 face): load, state solve to rel. res
+        # 1e-8, derivative, then the velocity solve as in the timed iteration
+        f_ht = torch.ones(m.n_nodes, dtype=torch.float64, device="cuda")
+        g0_ht = torch.from_numpy((np.abs(m.coords[:, 0]) < 1e-12).astype(np.uint8)).cuda()
+        b_ht = torch.zeros_like(f_ht)
+        u_ht = torch.zeros_like(f_ht)
+        rhs_ht = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+        J_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
+        vol_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
+        th_ht = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+        Bt_ht = torch.zeros(1, dtype=torch.float64, device="cuda")
+        it_ir.ctx.set_levelset(it_ir.phi0)
 
-    def heat_step():
-        it_ir.ctx.heat_load(f_ht, b_ht)
-        s_ht = it_ir.ctx.heat_solve(g0_ht, b_ht, u_ht, fo.SolveOpts(rtol=1e-8))
-        it_ir.ctx.heat_derivative(u_ht, f_ht, rhs_ht, J_ht, vol_ht)
-        d_ht = it_ir.ctx.descent_solve(it_ir.dopts, rhs_ht, th_ht, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8),
-                                       Bt_ht)
-        return s_ht, d_ht
+        def heat_step():
+            it_ir.ctx.heat_load(f_ht, b_ht)
+            s_ht = it_ir.ctx.heat_solve(g0_ht, b_ht, u_ht, fo.SolveOpts(rtol=1e-8))
+            it_ir.ctx.heat_derivative(u_ht, f_ht, rhs_ht, J_ht, vol_ht)
+            d_ht = it_ir.ctx.descent_solve(it_ir.dopts, rhs_ht, th_ht, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8),
+                                           Bt_ht)
+            return s_ht, d_ht
 
-    heat_step()  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_ht, dst_ht = heat_step()
-    torch.cuda.synchronize()
-    t_ht = time.perf_counter() - t0
-    log("heat model: state %d BiCGStab applications (%.1f ms), descent %d its, %.1f ms in all"
-        % (st_ht.iters_inner, st_ht.seconds * 1e3, dst_ht.iters_inner, t_ht * 1e3))
+        heat_step()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_ht, dst_ht = heat_step()
+        torch.cuda.synchronize()
+        t_ht = time.perf_counter() - t0
+        log("heat model: state %d BiCGStab applications (%.1f ms), descent %d its, %.1f ms in all"
+            % (st_ht.iters_inner, st_ht.seconds * 1e3, dst_ht.iters_inner, t_ht * 1e3))
 
-    loop_iters = 4  # iterations of the timed loops (heat, inverse and compliance)
+        loop_iters = 4  # iterations of the timed loops (heat, inverse and compliance)
 
-    # Algorithm 1 on the heat model (fo_optimize_heat): a few iterations with
-    # the PPL volume constraint at 90% of the initial volume
-    V_ht = 0.9 * float(vol_ht.item())
-    phi_hl = it_ir.phi0.clone()
-    it_ir.ctx.optimize_heat(g0_ht, f_ht, phi_hl, 1, it_ir.dopts, V=V_ht)  # warm-up
-    phi_hl.copy_(it_ir.phi0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hl_recs, _ = it_ir.ctx.optimize_heat(g0_ht, f_ht, phi_hl, loop_iters, it_ir.dopts, V=V_ht)
-    torch.cuda.synchronize()
-    t_hl = time.perf_counter() - t0
-    log("heat loop: %d iterations in %.3f s (%.1f ms per iteration), J %s"
-        % (len(hl_recs), t_hl, 1e3 * t_hl / len(hl_recs), ["%.5g" % r["J"] for r in hl_recs]))
+        # Algorithm 1 on the heat model (fo_optimize_heat): a few iterations with
+        # the PPL volume constraint at 90% of the initial volume
+        V_ht = 0.9 * float(vol_ht.item())
+        phi_hl = it_ir.phi0.clone()
+        it_ir.ctx.optimize_heat(g0_ht, f_ht, phi_hl, 1, it_ir.dopts, V=V_ht)  # warm-up
+        phi_hl.copy_(it_ir.phi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hl_recs, _ = it_ir.ctx.optimize_heat(g0_ht, f_ht, phi_hl, loop_iters, it_ir.dopts, V=V_ht)
+        torch.cuda.synchronize()
+        t_hl = time.perf_counter() - t0
+        log("heat loop: %d iterations in %.3f s (%.1f ms per iteration), J %s"
+            % (len(hl_recs), t_hl, 1e3 * t_hl / len(hl_recs), ["%.5g" % r["J"] for r in hl_recs]))
 
-    # the paper's inverse elasticity problem (Kohn-Vogelius, kappa = 10) on a
-    # mesh of the same size: states u, v and adjoints p, q (FP32 CG + FP64
-    # refinement to rel. res 1e-8), cost, S0/S1 derivative and the H^1_0
-    # velocity solve (every boundary unknown clamped)
-    wi = fi.inverse_elasticity(cells)
-    mi = wi.mesh
-    t0 = time.perf_counter()
-    inv_common = dict(E=wi.E, nu=wi.nu, plane_stress=wi.plane_stress, ersatz=1.0 / wi.kappa)
-    cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
-    cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
-    log("inverse problem: two contexts created in %.2f s" % (time.perf_counter() - t0))
+        # the paper's inverse elasticity problem (Kohn-Vogelius, kappa = 10) on a
+        # mesh of the same size: states u, v and adjoints p, q (FP32 CG + FP64
+        # refinement to rel. res 1e-8), cost, S0/S1 derivative and the H^1_0
+        # velocity solve (every boundary unknown clamped)
+        wi = fi.inverse_elasticity(cells)
+        mi = wi.mesh
+        t0 = time.perf_counter()
+        inv_common = dict(E=wi.E, nu=wi.nu, plane_stress=wi.plane_stress, ersatz=1.0 / wi.kappa)
+        cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
+        cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
+        log("inverse problem: two contexts created in %.2f s" % (time.perf_counter() - t0))
 
-    def dvec(a, dtype=torch.float64):
-        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+        def dvec(a, dtype=torch.float64):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
 
-    phi_inv, f_inv, g_inv = dvec(wi.phi), dvec(wi.f), dvec(wi.g)
-    fx_inv = dvec(wi.fixed_all, torch.uint8)
-    inv_out = [torch.zeros(mi.n_dofs, dtype=torch.float64, device="cuda") for _ in range(6)]
-    u_iv, v_iv, p_iv, q_iv, rhs_iv, th_iv = inv_out
-    J_iv = torch.zeros(1, dtype=torch.float64, device="cuda")
-    Bt_iv = torch.zeros(1, dtype=torch.float64, device="cuda")
-    dopts_iv = fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, dim=3, fixed=fx_inv)
+        phi_inv, f_inv, g_inv = dvec(wi.phi), dvec(wi.f), dvec(wi.g)
+        fx_inv = dvec(wi.fixed_all, torch.uint8)
+        inv_out = [torch.zeros(mi.n_dofs, dtype=torch.float64, device="cuda") for _ in range(6)]
+        u_iv, v_iv, p_iv, q_iv, rhs_iv, th_iv = inv_out
+        J_iv = torch.zeros(1, dtype=torch.float64, device="cuda")
+        Bt_iv = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dopts_iv = fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, dim=3, fixed=fx_inv)
 
-    def inverse_step():
-        s_iv = cf_inv.inverse_states(cg_inv, phi_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, u_iv, v_iv, p_iv,
-                                     q_iv, J_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8))
-        cf_inv.inverse_derivative(u_iv, v_iv, p_iv, q_iv, g_inv, wi.kappa, wi.alpha, rhs_iv)
-        d_iv = cf_inv.descent_solve(dopts_iv, rhs_iv, th_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), Bt_iv)
-        return s_iv, d_iv
+        def inverse_step():
+            s_iv = cf_inv.inverse_states(cg_inv, phi_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, u_iv, v_iv, p_iv,
+                                         q_iv, J_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8))
+            cf_inv.inverse_derivative(u_iv, v_iv, p_iv, q_iv, g_inv, wi.kappa, wi.alpha, rhs_iv)
+            d_iv = cf_inv.descent_solve(dopts_iv, rhs_iv, th_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), Bt_iv)
+            return s_iv, d_iv
 
-    inverse_step()  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_iv, dst_iv = inverse_step()
-    torch.cuda.synchronize()
-    t_iv = time.perf_counter() - t0
-    log("inverse problem: 4 state solves %d + %d its (%.1f ms), velocity %d its, %.1f ms in all, J %.4g"
-        % (st_iv.iters_inner, st_iv.iters_outer, st_iv.seconds * 1e3, dst_iv.iters_inner, t_iv * 1e3,
-           float(J_iv.item())))
+        inverse_step()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_iv, dst_iv = inverse_step()
+        torch.cuda.synchronize()
+        t_iv = time.perf_counter() - t0
+        log("inverse problem: 4 state solves %d + %d its (%.1f ms), velocity %d its, %.1f ms in all, J %.4g"
+            % (st_iv.iters_inner, st_iv.iters_outer, st_iv.seconds * 1e3, dst_iv.iters_inner, t_iv * 1e3,
+               float(J_iv.item())))
 
-    # Algorithm 1 on the inverse problem (fo_optimize_inverse): a few
-    # iterations from the initial inclusion, one pair
-    phi_il = phi_inv.clone()
-    cf_inv.optimize_inverse(cg_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, phi_il, 1, dopts_iv)  # warm-up
-    phi_il.copy_(phi_inv)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    il_recs, _ = cf_inv.optimize_inverse(cg_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, phi_il, loop_iters,
-                                         dopts_iv)
-    torch.cuda.synchronize()
-    t_il = time.perf_counter() - t0
-    log("inverse loop: %d iterations in %.3f s (%.1f ms per iteration), J %s"
-        % (len(il_recs), t_il, 1e3 * t_il / len(il_recs), ["%.5g" % r["J"] for r in il_recs]))
-    cf_inv.close()
-    cg_inv.close()
+        # Algorithm 1 on the inverse problem (fo_optimize_inverse): a few
+        # iterations from the initial inclusion, one pair
+        phi_il = phi_inv.clone()
+        cf_inv.optimize_inverse(cg_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, phi_il, 1, dopts_iv)  # warm-up
+        phi_il.copy_(phi_inv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        il_recs, _ = cf_inv.optimize_inverse(cg_inv, f_inv, g_inv, wi.kappa, wi.alpha, wi.beta, phi_il, loop_iters,
+                                             dopts_iv)
+        torch.cuda.synchronize()
+        t_il = time.perf_counter() - t0
+        log("inverse loop: %d iterations in %.3f s (%.1f ms per iteration), J %s"
+            % (len(il_recs), t_il, 1e3 * t_il / len(il_recs), ["%.5g" % r["J"] for r in il_recs]))
+        cf_inv.close()
+        cg_inv.close()
 
-    # eight force-displacement pairs in one call (the cost and derivative
-    # summed over the pairs), solved pair by pair
-    npairs = 8
-    wp = fi.inverse_elasticity(cells, n_pairs=npairs)
-    cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
-    cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
-    fP, gP = dvec(wp.columns(wp.fs)), dvec(wp.columns(wp.gs))
-    uP, vP, pP, qP = (torch.zeros(mi.n_dofs * npairs, dtype=torch.float64, device="cuda") for _ in range(4))
-    JP = torch.zeros(npairs, dtype=torch.float64, device="cuda")
+        # eight force-displacement pairs in one call (the cost and derivative
+        # summed over the pairs), solved pair by pair
+        npairs = 8
+        wp = fi.inverse_elasticity(cells, n_pairs=npairs)
+        cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
+        cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
+        fP, gP = dvec(wp.columns(wp.fs)), dvec(wp.columns(wp.gs))
+        uP, vP, pP, qP = (torch.zeros(mi.n_dofs * npairs, dtype=torch.float64, device="cuda") for _ in range(4))
+        JP = torch.zeros(npairs, dtype=torch.float64, device="cuda")
 
-    def inverse_pairs_step():
-        s_p = cf_inv.inverse_states(cg_inv, phi_inv, fP, gP, wi.kappa, wi.alpha, wi.beta, uP, vP, pP, qP, JP,
-                                    fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), n_pairs=npairs)
-        cf_inv.inverse_derivative(uP, vP, pP, qP, gP, wi.kappa, wi.alpha, rhs_iv, n_pairs=npairs)
-        d_p = cf_inv.descent_solve(dopts_iv, rhs_iv, th_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), Bt_iv)
-        return s_p, d_p
+        def inverse_pairs_step():
+            s_p = cf_inv.inverse_states(cg_inv, phi_inv, fP, gP, wi.kappa, wi.alpha, wi.beta, uP, vP, pP, qP, JP,
+                                        fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), n_pairs=npairs)
+            cf_inv.inverse_derivative(uP, vP, pP, qP, gP, wi.kappa, wi.alpha, rhs_iv, n_pairs=npairs)
+            d_p = cf_inv.descent_solve(dopts_iv, rhs_iv, th_iv, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), Bt_iv)
+            return s_p, d_p
 
-    inverse_pairs_step()  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_ip, dst_ip = inverse_pairs_step()
-    torch.cuda.synchronize()
-    t_ip = time.perf_counter() - t0
-    log("inverse problem, %d pairs: 4 x %d solves %d + %d its (%.1f ms), velocity %d its, %.1f ms in all "
-        "(%.1f ms per pair)" % (npairs, npairs, st_ip.iters_inner, st_ip.iters_outer, st_ip.seconds * 1e3,
-                                dst_ip.iters_inner, t_ip * 1e3, t_ip * 1e3 / npairs))
-    cf_inv.close()
-    cg_inv.close()
+        inverse_pairs_step()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_ip, dst_ip = inverse_pairs_step()
+        torch.cuda.synchronize()
+        t_ip = time.perf_counter() - t0
+        log("inverse problem, %d pairs: 4 x %d solves %d + %d its (%.1f ms), velocity %d its, %.1f ms in all "
+            "(%.1f ms per pair)" % (npairs, npairs, st_ip.iters_inner, st_ip.iters_outer, st_ip.seconds * 1e3,
+                                    dst_ip.iters_inner, t_ip * 1e3, t_ip * 1e3 / npairs))
+        cf_inv.close()
+        cg_inv.close()
 
-    # the paper's loop (Algorithm 1, fo_optimize): a few iterations from the
-    # initial design with the PPL volume constraint at 90% of its volume, the
-    # paper's time-stepping defaults and transport step
-    b_lp = it_ir.b[:, 0].contiguous()
-    V_lp = 0.9 * float(outs_ir[-1].vol.item())
-    phi_lp = it_ir.phi0.clone()
-    it_ir.ctx.optimize(b_lp, phi_lp, 1, it_ir.dopts, V=V_lp)  # warm-up
-    phi_lp.copy_(it_ir.phi0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lp_recs, _ = it_ir.ctx.optimize(b_lp, phi_lp, loop_iters, it_ir.dopts, V=V_lp)
-    torch.cuda.synchronize()
-    t_lp = time.perf_counter() - t0
-    log("loop: %d iterations in %.3f s (%.1f ms per iteration, transport %s steps, lambda %s)"
-        % (len(lp_recs), t_lp, 1e3 * t_lp / len(lp_recs), [r["steps"] for r in lp_recs],
-           ["%.3g" % r["lambda"] for r in lp_recs]))
+        # the paper's loop (Algorithm 1, fo_optimize): a few iterations from the
+        # initial design with the PPL volume constraint at 90% of its volume, the
+        # paper's time-stepping defaults and transport step
+        b_lp = it_ir.b[:, 0].contiguous()
+        V_lp = 0.9 * float(outs_ir[-1].vol.item())
+        phi_lp = it_ir.phi0.clone()
+        it_ir.ctx.optimize(b_lp, phi_lp, 1, it_ir.dopts, V=V_lp)  # warm-up
+        phi_lp.copy_(it_ir.phi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lp_recs, _ = it_ir.ctx.optimize(b_lp, phi_lp, loop_iters, it_ir.dopts, V=V_lp)
+        torch.cuda.synchronize()
+        t_lp = time.perf_counter() - t0
+        log("loop: %d iterations in %.3f s (%.1f ms per iteration, transport %s steps, lambda %s)"
+            % (len(lp_recs), t_lp, 1e3 * t_lp / len(lp_recs), [r["steps"] for r in lp_recs],
+               ["%.3g" % r["lambda"] for r in lp_recs]))
+
+        return {
+            "transport": {"what": "the paper's transport step (Crank-Nicolson Petrov-Galerkin, h^2 diffusion, "
+                                  "FP64 Jacobi BiCGStab to rel. res 1e-10), not part of the timed iteration",
+                          "ms": t_tr * 1e3, "steps": tr_steps, "dt": tr_dt,
+                          "operator_applications": st_tr.iters_inner, "max_rel_res": st_tr.rel_res},
+            "reinit": {"what": "the paper's reinitialisation (diffusive Eikonal, Petrov-Galerkin, explicit Euler then "
+                               "Adams-Bashforth 2, 8 steps to pseudo-time 0.1, FP64 Jacobi BiCGStab to rel. res 1e-10) "
+                               "of the transported level set, not part of the timed iteration",
+                       "ms": t_rn * 1e3, "operator_applications": st_rn.iters_inner, "max_rel_res": st_rn.rel_res},
+            "heat": {"what": "the paper's heat-conduction model on the same mesh (f = 1, u = 0 on x = 0): load, "
+                             "FP64 state solve to rel. res 1e-8, S0/S1 derivative, FP32 + refinement velocity solve",
+                     "ms": t_ht * 1e3, "state_ms": st_ht.seconds * 1e3, "state_operator_applications": st_ht.iters_inner,
+                     "descent_iters": dst_ht.iters_inner, "J": float(J_ht.item()),
+                     "loop": {"what": "Algorithm 1 on the heat model (fo_optimize_heat), PPL volume constraint at 90% "
+                                      "of the initial volume", "iterations": len(hl_recs), "seconds": t_hl,
+                              "ms_per_iteration": 1e3 * t_hl / len(hl_recs),
+                              "records": [{k: r[k] for k in ("J", "C", "lambda", "steps", "state_iters",
+                                                             "descent_iters", "transport_iters")} for r in hl_recs]}},
+            "inverse": {"what": "the paper's inverse elasticity problem (kappa = 10, alpha = beta = 1) on a mesh of the "
+                                "same size: u, v, p, q by FP32 CG + FP64 refinement to rel. res 1e-8, cost, S0/S1 "
+                                "derivative, H^1_0 velocity solve", "ms": t_iv * 1e3, "states_ms": st_iv.seconds * 1e3,
+                        "state_iters": {"inner_fp32": st_iv.iters_inner, "outer_fp64": st_iv.iters_outer},
+                        "descent_iters": dst_iv.iters_inner, "J": float(J_iv.item()),
+                        "pairs": {"what": "8 force-displacement pairs in one call: 4 x 8 solves by FP32 CG + FP64 "
+                                          "refinement, derivative summed over the pairs, one velocity solve", "n_pairs": npairs, "ms": t_ip * 1e3, "ms_per_pair": t_ip * 1e3 / npairs,
+                                  "states_ms": st_ip.seconds * 1e3,
+                                  "state_iters": {"inner": st_ip.iters_inner, "outer": st_ip.iters_outer},
+                                  "descent_iters": dst_ip.iters_inner},
+                        "loop": {"what": "Algorithm 1 on the inverse problem (fo_optimize_inverse), one pair, from "
+                                         "the initial inclusion", "iterations": len(il_recs), "seconds": t_il,
+                                 "ms_per_iteration": 1e3 * t_il / len(il_recs),
+                                 "records": [{k: r[k] for k in ("J", "steps", "state_iters", "descent_iters",
+                                                                "transport_iters")} for r in il_recs]}},
+            "loop": {"what": "the paper's Algorithm 1 (fo_optimize): state and velocity solves in FP32 + FP64 "
+                             "refinement, PPL volume constraint at 90% of the initial volume, transport step, "
+                             "from the initial design", "iterations": len(lp_recs), "seconds": t_lp,
+                     "ms_per_iteration": 1e3 * t_lp / len(lp_recs),
+                     "records": [{k: r[k] for k in ("J", "C", "lambda", "steps", "state_iters", "descent_iters",
+                                                    "transport_iters")} for r in lp_recs]},
+        }
+
+    extra = {} if args.main_only else extras()
 
     # agreement of the two precisions (both at rel. res 1e-8)
     u_ir = it_ir.u[:, 0].double()
@@ -532,50 +582,13 @@ def main():
                  "state_solve_ms": 1e3 * state64_secs / K64},
         "state_solve_ms": 1e3 * state_secs / K,
         "descent_iters": outs_ir[-1].descent_stats.iters_inner,
-        "transport": {"what": "the paper's transport step (Crank-Nicolson Petrov-Galerkin, h^2 diffusion, "
-                              "FP64 Jacobi BiCGStab to rel. res 1e-10), not part of the timed iteration",
-                      "ms": t_tr * 1e3, "steps": tr_steps, "dt": tr_dt,
-                      "operator_applications": st_tr.iters_inner, "max_rel_res": st_tr.rel_res},
-        "reinit": {"what": "the paper's reinitialisation (diffusive Eikonal, Petrov-Galerkin, explicit Euler then "
-                           "Adams-Bashforth 2, 8 steps to pseudo-time 0.1, FP64 Jacobi BiCGStab to rel. res 1e-10) "
-                           "of the transported level set, not part of the timed iteration",
-                   "ms": t_rn * 1e3, "operator_applications": st_rn.iters_inner, "max_rel_res": st_rn.rel_res},
-        "heat": {"what": "the paper's heat-conduction model on the same mesh (f = 1, u = 0 on x = 0): load, "
-                         "FP64 state solve to rel. res 1e-8, S0/S1 derivative, FP32 + refinement velocity solve",
-                 "ms": t_ht * 1e3, "state_ms": st_ht.seconds * 1e3, "state_operator_applications": st_ht.iters_inner,
-                 "descent_iters": dst_ht.iters_inner, "J": float(J_ht.item()),
-                 "loop": {"what": "Algorithm 1 on the heat model (fo_optimize_heat), PPL volume constraint at 90% "
-                                  "of the initial volume", "iterations": len(hl_recs), "seconds": t_hl,
-                          "ms_per_iteration": 1e3 * t_hl / len(hl_recs),
-                          "records": [{k: r[k] for k in ("J", "C", "lambda", "steps", "state_iters",
-                                                         "descent_iters", "transport_iters")} for r in hl_recs]}},
-        "inverse": {"what": "the paper's inverse elasticity problem (kappa = 10, alpha = beta = 1) on a mesh of the "
-                            "same size: u, v, p, q by FP32 CG + FP64 refinement to rel. res 1e-8, cost, S0/S1 "
-                            "derivative, H^1_0 velocity solve", "ms": t_iv * 1e3, "states_ms": st_iv.seconds * 1e3,
-                    "state_iters": {"inner_fp32": st_iv.iters_inner, "outer_fp64": st_iv.iters_outer},
-                    "descent_iters": dst_iv.iters_inner, "J": float(J_iv.item()),
-                    "pairs": {"what": "8 force-displacement pairs in one call: 4 x 8 solves by FP32 CG + FP64 "
-                                      "refinement, derivative summed over the pairs, one velocity solve", "n_pairs": npairs, "ms": t_ip * 1e3, "ms_per_pair": t_ip * 1e3 / npairs,
-                              "states_ms": st_ip.seconds * 1e3,
-                              "state_iters": {"inner": st_ip.iters_inner, "outer": st_ip.iters_outer},
-                              "descent_iters": dst_ip.iters_inner},
-                    "loop": {"what": "Algorithm 1 on the inverse problem (fo_optimize_inverse), one pair, from "
-                                     "the initial inclusion", "iterations": len(il_recs), "seconds": t_il,
-                             "ms_per_iteration": 1e3 * t_il / len(il_recs),
-                             "records": [{k: r[k] for k in ("J", "steps", "state_iters", "descent_iters",
-                                                            "transport_iters")} for r in il_recs]}},
-        "loop": {"what": "the paper's Algorithm 1 (fo_optimize): state and velocity solves in FP32 + FP64 "
-                         "refinement, PPL volume constraint at 90% of the initial volume, transport step, "
-                         "from the initial design", "iterations": len(lp_recs), "seconds": t_lp,
-                 "ms_per_iteration": 1e3 * t_lp / len(lp_recs),
-                 "records": [{k: r[k] for k in ("J", "C", "lambda", "steps", "state_iters", "descent_iters",
-                                                "transport_iters")} for r in lp_recs]},
         "err_u_ir_vs_fp64": err_u,
         "err_rhs_ir_vs_fp64": err_rhs,
         "J": float(outs_ir[-1].J[0].item()),
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    result.update(extra)
     if not args.no_batched:
         log("batched multi-load case (64 loads, 64x32x32)")
         result["batched"] = batched_case()
