@@ -85,6 +85,14 @@ def test_inverse_entries_reject_null_arguments(lib):
     assert lib.fo_inverse_derivative(None, 1, 1, None, None, None, None, None, 10.0, 1.0, None) == fo.FO_ERR_ARG
 
 
+def test_loop_entries_reject_null_arguments(lib):
+    from paper_2601_05709_amd import fo
+    assert lib.fo_optimize(None, None, None, None, None, None, None) == fo.FO_ERR_ARG
+    assert lib.fo_optimize_heat(None, None, None, None, None, None, None, None) == fo.FO_ERR_ARG
+    assert lib.fo_optimize_inverse(None, None, None, 1, 1, None, None, 10.0, 1.0, 1.0, None, None, None,
+                                   None) == fo.FO_ERR_ARG
+
+
 def test_descent_opts_layout_and_defaults():
     from paper_2601_05709_amd import fo
     # the velocity mask is the last field of fo_descent_opts (after the boxes pointer)
