@@ -39,7 +39,8 @@ int inv_buffers(fo_ctx *c, int64_t ld, InvBufs *o)
         if (c->inv_buf) {
             (void)hipStreamSynchronize(c->stream);
             (void)hipFree(c->inv_buf);
-            c->allocations.erase(std::find(c->allocations.begin(), c->allocations.end(), c->inv_buf));
+            auto it = std::find(c->allocations.begin(), c->allocations.end(), c->inv_buf);
+            if (it != c->allocations.end()) c->allocations.erase(it);
             c->bytes -= c->inv_cap * sizeof(double);
             c->inv_buf = nullptr;
             c->inv_cap = 0;

@@ -224,13 +224,14 @@ class DescentOpts:
         b = np.zeros((0, 2 * (dim or 2))) if boxes is None else np.asarray(boxes, dtype=np.float64)
         self.boxes = np.ascontiguousarray(b.reshape(b.shape[0], -1) if b.size else b.reshape(0, 2 * (dim or 2)))
 
-    def c(self) -> fo_descent_opts:
+    def c(self, n_dofs: Optional[int] = None) -> fo_descent_opts:
+        """The C struct; with n_dofs, the mask is checked to hold that many entries."""
         n = self.boxes.shape[0]
         ptr = self.boxes.ctypes.data_as(C.c_void_p) if n else None
         fx = None
         if self.fixed is not None:
             import torch
-            fx = _ptr(self.fixed, torch.uint8, None, "fixed")
+            fx = _ptr(self.fixed, torch.uint8, n_dofs, "fixed")
         return fo_descent_opts(self.alpha, self.gamma_n, self.gamma_s, n, ptr, fx)
 
 
@@ -374,7 +375,7 @@ class Context:
         import torch
         st = fo_solve_stats()
         allow = (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,)
-        rc = lib().fo_descent_solve(self.h, C.byref(dopts.c()),
+        rc = lib().fo_descent_solve(self.h, C.byref(dopts.c(self.n_dofs)),
                                     _ptr(rhs, torch.float64, self.n_dofs, "rhs"),
                                     _ptr(theta, torch.float64, self.n_dofs, "theta"),
                                     C.byref(opts.c()), C.byref(st),
@@ -384,7 +385,7 @@ class Context:
 
     def apply_descent(self, dopts: DescentOpts, x, y):
         import torch
-        _check(lib().fo_apply_descent(self.h, C.byref(dopts.c()), _ptr(x, torch.float64, self.n_dofs, "x"),
+        _check(lib().fo_apply_descent(self.h, C.byref(dopts.c(self.n_dofs)), _ptr(x, torch.float64, self.n_dofs, "x"),
                                       _ptr(y, torch.float64, self.n_dofs, "y")), "fo_apply_descent")
 
     def transport(self, theta, dt: float, steps: int, phi, opts: Optional[SolveOpts] = None,
@@ -484,7 +485,8 @@ class Context:
         (records as dicts, stopped)."""
         import torch
         o = _loop_opts(n_iter, V, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, lgrn_tol,
-                       ctrn_tol, ppl, state_opts, descent_opts, transport_opts, dopts, reinit_step, reinit_pars)
+                       ctrn_tol, ppl, state_opts, descent_opts, transport_opts, dopts, reinit_step, reinit_pars,
+                       n_dofs=self.n_dofs)
         recs = (fo_loop_record * max(1, int(n_iter)))()
         n_done, stopped = C.c_int32(0), C.c_int32(0)
         rc = lib().fo_optimize(self.h, C.byref(o), _ptr(b, torch.float64, self.n_dofs, "b"),
@@ -506,7 +508,7 @@ class Context:
         import torch
         o = _loop_opts(n_iter, V, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, lgrn_tol,
                        ctrn_tol, ppl, state_opts or SolveOpts(rtol=1e-8), descent_opts, transport_opts, dopts,
-                       reinit_step, reinit_pars)
+                       reinit_step, reinit_pars, n_dofs=self.n_dofs)
         recs = (fo_loop_record * max(1, int(n_iter)))()
         n_done, stopped = C.c_int32(0), C.c_int32(0)
         rc = lib().fo_optimize_heat(self.h, C.byref(o), _ptr(gamma0, torch.uint8, self.n_nodes, "gamma0"),
@@ -531,7 +533,7 @@ class Context:
         ld = n_pairs if ld is None else ld
         o = _loop_opts(n_iter, None, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, 1e-2,
                        1e-2, (0.999, 0.5, 2000.0, 0.5), state_opts, descent_opts, transport_opts, dopts,
-                       reinit_step, reinit_pars)
+                       reinit_step, reinit_pars, n_dofs=self.n_dofs)
         recs = (fo_loop_record * max(1, int(n_iter)))()
         n_done, stopped = C.c_int32(0), C.c_int32(0)
         n = self.n_dofs * ld
@@ -550,14 +552,15 @@ class Context:
 
 
 def _loop_opts(n_iter, V, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, lgrn_tol, ctrn_tol,
-               ppl, state_opts, descent_opts, transport_opts, dopts, reinit_step, reinit_pars) -> fo_loop_opts:
+               ppl, state_opts, descent_opts, transport_opts, dopts, reinit_step, reinit_pars,
+               n_dofs=None) -> fo_loop_opts:
     so = state_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
     do = descent_opts or SolveOpts(precision=FO_FP32_IR, rtol=1e-8)
     to = transport_opts or SolveOpts(rtol=1e-10)
     return fo_loop_opts(int(n_iter), float(V) if V else 0.0, float(dfactor), float(lv_time[0]), float(lv_time[1]),
                         int(lv_iter[0]), int(lv_iter[1]), int(bool(smooth)), int(start_to_check), int(prev),
                         float(cost_tol), float(lgrn_tol), float(ctrn_tol), float(ppl[0]), float(ppl[1]),
-                        float(ppl[2]), float(ppl[3]), so.c(), do.c(), to.c(), dopts.c(), int(reinit_step or 0),
+                        float(ppl[2]), float(ppl[3]), so.c(), do.c(), to.c(), dopts.c(n_dofs), int(reinit_step or 0),
                         int(reinit_pars[0]), float(reinit_pars[1]))
 
 

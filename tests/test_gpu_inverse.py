@@ -177,6 +177,11 @@ def test_inverse_moved_inclusion_and_edge_cases():
         cf.inverse_states(cg, dev(wi.phi), dev(wi.f), g, 2.0 * wi.kappa, wi.alpha, wi.beta, u, u, u, u, J)
     with pytest.raises(fo.FoError):
         cf.inverse_states(cf, dev(wi.phi), dev(wi.f), g, wi.kappa, wi.alpha, wi.beta, u, u, u, u, J)
+    # a velocity mask shorter than the unknowns is refused before any launch
+    short = torch.zeros(n - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        cf.descent_solve(fo.DescentOpts(alpha=0.01, gamma_n=0.0, gamma_s=0.0, fixed=short), rhs, u,
+                         fo.SolveOpts(rtol=1e-8))
     # two level sets in a row on the same contexts (the second a moved inclusion)
     for shift in (0.0, 0.3):
         phi = np.linalg.norm(wi.mesh.coords - np.array([1.0 + shift, 0.5]), axis=1) - 0.25
