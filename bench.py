@@ -405,7 +405,10 @@ def main():
         t0 = time.perf_counter()
         inv_common = dict(E=wi.E, nu=wi.nu, plane_stress=wi.plane_stress, ersatz=1.0 / wi.kappa)
         cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
-        cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
+        # the second context on a stream of its own: its solves run concurrently with the first's
+        side = torch.cuda.Stream()
+        cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None,
+                            stream=fo.C.c_void_p(side.cuda_stream), **inv_common)
         log("inverse problem: two contexts created in %.2f s" % (time.perf_counter() - t0))
 
         def dvec(a, dtype=torch.float64):
@@ -457,7 +460,8 @@ def main():
         npairs = 8
         wp = fi.inverse_elasticity(cells, n_pairs=npairs)
         cf_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed0, mi.bfacets, mi.bnormal, **inv_common)
-        cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None, **inv_common)
+        cg_inv = fo.Context(mi.dim, mi.coords, mi.conn, wi.fixed_all, None, None,
+                            stream=fo.C.c_void_p(side.cuda_stream), **inv_common)
         fP, gP = dvec(wp.columns(wp.fs)), dvec(wp.columns(wp.gs))
         uP, vP, pP, qP = (torch.zeros(mi.n_dofs * npairs, dtype=torch.float64, device="cuda") for _ in range(4))
         JP = torch.zeros(npairs, dtype=torch.float64, device="cuda")

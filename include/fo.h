@@ -323,7 +323,9 @@ int fo_heat_derivative(fo_ctx *ctx, const double *u, const double *f, double lam
  * and lists the Gamma_1 facets (its boundary facets carry the beta-term),
  * ctx_g clamps every boundary unknown; both are created with ersatz =
  * 1/kappa (their operator is K/kappa) and the tiled scatter; the pairs are
- * solved one after the other.  g_k
+ * solved one after the other.  Contexts on different streams solve u and v
+ * (then p and q) concurrently, one of them from a helper host thread (same
+ * results); the call returns when all work has finished.  g_k
  * is the P1 Dirichlet data extended into D; it may be nonzero anywhere.
  * Device arrays [n_dofs][ld] (pair k in column k, ld >= n_pairs) unless
  * stated.

@@ -12,12 +12,16 @@
 // solves, pair by pair (the batched multi-column path pays off only from
 // several dozen columns); the masses, the cost and the derivative also run
 // pair by pair, on the tiled scatter of the first context.  Pair k of an
-// [n_dofs][ld] array is column k.
+// [n_dofs][ld] array is column k.  When the two contexts run on different
+// streams, the solves of u and v (then of p and q) run at the same time, one
+// of them from a helper host thread: each solve alone leaves CUs idle during
+// its update kernels and the last round of its operator kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <thread>
 
 #include "fo_internal.h"
 #include "fo_launch.h"
@@ -152,6 +156,55 @@ int worse(int a, int b)
 
 bool kappa_matches(const fo_ctx *c, double kappa) { return std::fabs(kappa * c->ersatz - 1.0) <= 1e-12; }
 
+// The state solves of n_pairs columns (stride ld) of b on c, one after the
+// other; iterations and the worst status accumulate into acc.
+int solve_pairs(fo_ctx *c, const double *b, double *x, int n_pairs, int64_t ld, const fo_solve_opts *o,
+                fo_solve_stats *acc)
+{
+    for (int k = 0; k < n_pairs; ++k) {
+        fo_solve_stats one{};
+        const int rc = fo_state_solve(c, b + k, x + k, 1, ld, o, &one);
+        if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+        acc->iters_inner += one.iters_inner;
+        acc->iters_outer += one.iters_outer;
+        acc->rel_res = std::max(acc->rel_res, one.rel_res);
+        acc->status = worse(acc->status, rc);
+    }
+    return FO_OK;
+}
+
+// Solves on cf (bf -> xf) and on cg (bg -> xg): concurrently from a helper
+// thread when the contexts have their own streams, else in turn.
+int solve_both(fo_ctx *cf, const double *bf, double *xf, fo_ctx *cg, const double *bg, double *xg, int n_pairs,
+               int64_t ld, const fo_solve_opts *o, fo_solve_stats *acc)
+{
+    fo_solve_stats af{FO_OK, 0, 0, 0.0, 0.0}, ag{FO_OK, 0, 0, 0.0, 0.0};
+    int rf = FO_OK, rg = FO_OK;
+    if (cf->stream != cg->stream) {
+        std::thread t([&]() {
+            if (hipSetDevice(cg->device) != hipSuccess) {
+                rg = FO_ERR_HIP;
+                return;
+            }
+            rg = solve_pairs(cg, bg, xg, n_pairs, ld, o, &ag);
+        });
+        rf = solve_pairs(cf, bf, xf, n_pairs, ld, o, &af);
+        t.join();
+    } else {
+        rf = solve_pairs(cf, bf, xf, n_pairs, ld, o, &af);
+        if (rf == FO_OK) rg = solve_pairs(cg, bg, xg, n_pairs, ld, o, &ag);
+    }
+    if (rf != FO_OK) return rf;
+    if (rg != FO_OK) return rg;
+    for (const fo_solve_stats *a : {&af, &ag}) {
+        acc->iters_inner += a->iters_inner;
+        acc->iters_outer += a->iters_outer;
+        acc->rel_res = std::max(acc->rel_res, a->rel_res);
+        acc->status = worse(acc->status, a->status);
+    }
+    return FO_OK;
+}
+
 }  // namespace
 
 }  // namespace fo
@@ -180,32 +233,17 @@ int fo_inverse_states(fo_ctx *cf, fo_ctx *cg, const double *phi, int32_t n_pairs
     const int64_t n = cf->ndof;
     const int ng = grid_of(n);
     fo_solve_stats acc{FO_OK, 0, 0, 0.0, 0.0};
-    int status = FO_OK;
-    auto solve = [&](fo_ctx *c, const double *b, double *x) -> int {
-        for (int k = 0; k < n_pairs; ++k) {
-            fo_solve_stats one{};
-            const int rc = fo_state_solve(c, b + k, x + k, 1, ld, o, &one);
-            if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
-            acc.iters_inner += one.iters_inner;
-            acc.iters_outer += one.iters_outer;
-            acc.rel_res = std::max(acc.rel_res, one.rel_res);
-            status = worse(status, rc);
-        }
-        return FO_OK;
-    };
-    // u: K u = f on the Gamma_0-free unknowns
+    // loads of u (f / kappa, in b) and of v (-K g, in y; the full product K g)
     hipLaunchKernelGGL(k_scale_cols, dim3(grid_of(n * n_pairs)), dim3(256), 0, s, n, ld, (int)n_pairs, 1.0 / kappa,
                        f, B.b);
-    FO_HIP(hipStreamSynchronize(s));
-    FO_TRY(solve(cf, B.b, u));
-    // v: K v = -K g on the interior unknowns (the full product K g)
     for (int k = 0; k < n_pairs; ++k) {
         hipLaunchKernelGGL(k_get, dim3(ng), dim3(256), 0, s, n, ld, g + k, B.t0);
         FO_TRY(launch_elas_apply_free(cf, B.t0, B.t1, s));
-        hipLaunchKernelGGL(k_put, dim3(ng), dim3(256), 0, s, n, ld, -1.0, B.t1, B.b + k);
+        hipLaunchKernelGGL(k_put, dim3(ng), dim3(256), 0, s, n, ld, -1.0, B.t1, B.y + k);
     }
     FO_HIP(hipStreamSynchronize(s));
-    FO_TRY(solve(cg, B.b, v));
+    // u (clamped on Gamma_0) and v (clamped on the whole boundary)
+    FO_TRY(solve_both(cf, B.b, u, cg, B.y, v, n_pairs, ld, o, &acc));
     // cost and the adjoint loads, pair by pair
     const int nb = red_blocks(n);
     for (int k = 0; k < n_pairs; ++k) {
@@ -220,13 +258,11 @@ int fo_inverse_states(fo_ctx *cf, fo_ctx *cg, const double *phi, int32_t n_pairs
     }
     FO_HIP(hipStreamSynchronize(s));
     // p (clamped on Gamma_0) and q (clamped on the whole boundary)
-    FO_TRY(solve(cf, B.b, p));
-    FO_TRY(solve(cg, B.y, q));
+    FO_TRY(solve_both(cf, B.b, p, cg, B.y, q, n_pairs, ld, o, &acc));
     FO_HIP(hipGetLastError());
-    acc.status = status;
     acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st) *st = acc;
-    return status;
+    return acc.status;
 }
 
 int fo_inverse_derivative(fo_ctx *cf, int32_t n_pairs, int64_t ld, const double *u, const double *v,

@@ -250,3 +250,39 @@ def test_inverse_loop_matches_oracle(name, npairs):
     rc = fo.lib().fo_optimize_inverse(cf.h, cg.h, fo.C.byref(o), npairs, npairs, fo._ptr(f), fo._ptr(g), wi.kappa,
                                       wi.alpha, wi.beta, fo._ptr(phi), recs_c, fo.C.byref(nd), fo.C.byref(sp))
     assert rc == fo.FO_ERR_ARG
+
+
+def test_inverse_concurrent_solves_match_serial():
+    """With the two contexts on different streams the solves of u and v
+    (then p and q) run concurrently from a helper thread; every output equals
+    the one of the contexts sharing one stream, bit for bit (each solve is
+    deterministic), and so does the derivative."""
+    wi = fi.inverse_elasticity(CELLS["3d_16x8x8"], n_pairs=2)
+    m = wi.mesh
+    n = m.n_dofs
+    print("case inverse concurrent 3d_16x8x8 pairs 2", flush=True)
+    f, g = dev(wi.columns(wi.fs)), dev(wi.columns(wi.gs))
+    results = []
+    for separate in (False, True):
+        cf, cg = contexts(wi)
+        side = None
+        if separate:
+            side = torch.cuda.Stream()
+            common = dict(E=wi.E, nu=wi.nu, plane_stress=wi.plane_stress, ersatz=1.0 / wi.kappa)
+            cg = fo.Context(m.dim, m.coords, m.conn, wi.fixed_all, None, None, stream=fo.C.c_void_p(side.cuda_stream),
+                            **common)
+        out = [torch.zeros(n * 2, dtype=torch.float64, device="cuda") for _ in range(4)]
+        J = zeros(2)
+        rhs = zeros(n)
+        st = cf.inverse_states(cg, dev(wi.phi), f, g, wi.kappa, wi.alpha, wi.beta, *out, J,
+                               fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-10), n_pairs=2)
+        cf.inverse_derivative(*out, g, wi.kappa, wi.alpha, rhs, n_pairs=2)
+        torch.cuda.synchronize()
+        results.append(([t.cpu().numpy() for t in out], J.cpu().numpy(), rhs.cpu().numpy(), st.iters_inner))
+        cg.close()
+        cf.close()
+        del side
+    (a, Ja, ra, ia), (b, Jb, rb, ib) = results
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert np.array_equal(Ja, Jb) and np.array_equal(ra, rb) and ia == ib
