@@ -180,14 +180,20 @@ int solve_both(fo_ctx *cf, const double *bf, double *xf, fo_ctx *cg, const doubl
 {
     fo_solve_stats af{FO_OK, 0, 0, 0.0, 0.0}, ag{FO_OK, 0, 0, 0.0, 0.0};
     int rf = FO_OK, rg = FO_OK;
+    std::thread t;
     if (cf->stream != cg->stream) {
-        std::thread t([&]() {
-            if (hipSetDevice(cg->device) != hipSuccess) {
-                rg = FO_ERR_HIP;
-                return;
-            }
-            rg = solve_pairs(cg, bg, xg, n_pairs, ld, o, &ag);
-        });
+        try {  // no exception may cross the C ABI: without a thread, solve in turn
+            t = std::thread([&]() {
+                if (hipSetDevice(cg->device) != hipSuccess) {
+                    rg = FO_ERR_HIP;
+                    return;
+                }
+                rg = solve_pairs(cg, bg, xg, n_pairs, ld, o, &ag);
+            });
+        } catch (...) {
+        }
+    }
+    if (t.joinable()) {
         rf = solve_pairs(cf, bf, xf, n_pairs, ld, o, &af);
         t.join();
     } else {
