@@ -322,7 +322,8 @@ int fo_heat_derivative(fo_ctx *ctx, const double *u, const double *f, double lam
  * sum_k J_k.  Two contexts on the same mesh and device: ctx_f clamps Gamma_0
  * and lists the Gamma_1 facets (its boundary facets carry the beta-term),
  * ctx_g clamps every boundary unknown; both are created with ersatz =
- * 1/kappa (their operator is K/kappa) and the tiled scatter; the pairs are
+ * 1/kappa (their operator is K/kappa; fo_create takes ersatz in (0, 1], so
+ * kappa >= 1) and the tiled scatter; the pairs are
  * solved one after the other.  Contexts on different streams solve u and v
  * (then p and q) concurrently, one of them from a helper host thread (same
  * results); the call returns when all work has finished.  g_k

@@ -77,6 +77,34 @@ def test_inverse_states_and_derivative(name, precision):
     assert rel(rhs.cpu().numpy(), ref["rhs"]) < 10 * tol
 
 
+@pytest.mark.parametrize("kappa", [1.0, 100.0])
+def test_inverse_other_contrasts(kappa):
+    """kappa = 1 (one material: the contexts' ersatz value is 1) and kappa =
+    100 (stiff inclusion): states, cost and derivative against the oracle."""
+    base = fi.inverse_elasticity(CELLS["2d_37x19"])
+    wi = fi.InverseWorkload(base.mesh, base.fixed0, base.fixed_all, base.f, base.g, base.phi, kappa, base.alpha,
+                            base.beta, base.E, base.nu, base.plane_stress)
+    print("case inverse kappa %g" % kappa, flush=True)
+    ref = oi.inverse_iteration(wi)
+    cf, cg = contexts(wi)
+    out, J, st = run_states(wi, cf, cg, wi.phi, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-11))
+    assert st.status == 0
+    for k in "uvpq":
+        got = out[k].cpu().numpy()
+        if k == "v" and kappa == 1.0:
+            # one material: a linear g solves the homogeneous equations, so the
+            # lifted state is rounding noise on both sides
+            scale = np.abs(wi.g).max()
+            assert np.abs(got).max() < 1e-10 * scale and np.abs(ref[k]).max() < 1e-10 * scale
+            continue
+        assert rel(got, ref[k]) < 1e-8, k
+    assert J == pytest.approx(ref["J"], rel=1e-8)
+    rhs = zeros(wi.mesh.n_dofs)
+    cf.inverse_derivative(dev(ref["u"]), dev(ref["v"]), dev(ref["p"]), dev(ref["q"]), dev(wi.g), wi.kappa,
+                          wi.alpha, rhs)
+    np.testing.assert_allclose(rhs.cpu().numpy(), ref["rhs"], rtol=1e-11, atol=1e-12 * np.abs(ref["rhs"]).max())
+
+
 @pytest.mark.parametrize("name", list(CELLS))
 @pytest.mark.parametrize("precision", [fo.FO_FP64, fo.FO_FP32_IR])
 def test_inverse_several_pairs(name, precision):
