@@ -377,7 +377,7 @@ def main():
         st_ht, dst_ht = heat_step()
         torch.cuda.synchronize()
         t_ht = time.perf_counter() - t0
-        log("heat model: state %d BiCGStab applications (%.1f ms), descent %d its, %.1f ms in all"
+        log("heat model: state %d CG operator applications (%.1f ms), descent %d its, %.1f ms in all"
             % (st_ht.iters_inner, st_ht.seconds * 1e3, dst_ht.iters_inner, t_ht * 1e3))
 
         loop_iters = 4  # iterations of the timed loops (heat, inverse and compliance)

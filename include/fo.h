@@ -297,8 +297,9 @@ int fo_reinit(fo_ctx *ctx, double *phi, int32_t steps, double t_end, const fo_so
  *
  * fo_heat_load: b = int f lambda_a (exact P1 mass), b and f [N].
  * fo_heat_solve: u [N] with K u = b on the free nodes, u = 0 where gamma0
- *   [N] (uint8) is nonzero, by the transport step's FP64 Jacobi BiCGStab to
- *   opts->rtol (recomputed residual).  Returns FO_OK, FO_NOT_CONVERGED,
+ *   [N] (uint8) is nonzero, by FP64 Jacobi-preconditioned CG (the system is
+ *   SPD) to opts->rtol on the recomputed residual; stats->iters_inner counts
+ *   operator applications.  Returns FO_OK, FO_NOT_CONVERGED,
  *   FO_ERR_BREAKDOWN, FO_ERR_STATE (no level set, or the atomic scatter) or
  *   FO_ERR_ARG.
  * fo_heat_derivative: the descent right-hand side rhs [n_dofs] of S0 =

@@ -160,7 +160,10 @@ namespace {
 // ---------------------------------------------------------------------------
 // conjugate-gradient driver
 
-enum OpKind { OP_ELAS64 = 0, OP_ELAS32 = 1, OP_DESCENT64 = 2 };
+enum OpKind { OP_ELAS64 = 0, OP_ELAS32 = 1, OP_DESCENT64 = 2, OP_HEAT64 = 3 };
+
+// Unknowns of an operator: the scalar heat operator has one per node.
+int64_t op_len(const fo_ctx *c, OpKind k) { return k == OP_HEAT64 ? c->N : c->ndof; }
 
 template <typename T>
 struct CgVecs {
@@ -181,8 +184,8 @@ int poll(fo_ctx *c)
 template <typename T>
 int cg_apply(fo_ctx *c, OpKind k, const T *p, T *q, const int32_t *done, hipStream_t s, int *n_pq)
 {
-    const int64_t n = c->ndof;
-    if (k != OP_DESCENT64 && tiled(c)) {
+    const int64_t n = op_len(c, k);
+    if (k != OP_DESCENT64 && k != OP_HEAT64 && tiled(c)) {
         if (c->has_isolated) launch_fill<T>(q, n, T(0), s);
         *n_pq = c->tiles.n_tiles;
         if constexpr (sizeof(T) == 8)
@@ -200,6 +203,12 @@ int cg_apply(fo_ctx *c, OpKind k, const T *p, T *q, const int32_t *done, hipStre
             launch_descent_apply_atomic(c, (const double *)p, (double *)q, s);
         }
         if (c->descent.fixed) zero_masked(c, c->descent.fixed, (double *)q, s);
+    } else if (k == OP_HEAT64) {
+        if constexpr (sizeof(T) == 8) {
+            FO_TRY(launch_heat_apply(c, c->heat_mask, (const double *)p, (double *)q, s, done));
+        } else {
+            return FO_ERR_ARG;
+        }
     } else {
         FO_TRY(elas_apply<T>(c, p, q, s));
     }
@@ -214,7 +223,7 @@ int cg_apply(fo_ctx *c, OpKind k, const T *p, T *q, const int32_t *done, hipStre
 template <typename T>
 int cg_chunk(fo_ctx *c, OpKind k, CgVecs<T> v, int chunk, hipStream_t s)
 {
-    const int64_t n = c->ndof;
+    const int64_t n = op_len(c, k);
     for (int i = 0; i < chunk; ++i) {
         const int P = i & 1;
         int n_pq = 0;
@@ -346,6 +355,10 @@ template <typename T>
 int op_apply(fo_ctx *c, OpKind k, const T *x, T *y, hipStream_t s)
 {
     if (k == OP_DESCENT64) return descent_apply(c, (const double *)x, (double *)y, s);
+    if (k == OP_HEAT64) {
+        if constexpr (sizeof(T) == 8) return launch_heat_apply(c, c->heat_mask, (const double *)x, (double *)y, s);
+        return FO_ERR_ARG;
+    }
     return elas_apply<T>(c, x, y, s);
 }
 
@@ -353,6 +366,7 @@ int op_apply(fo_ctx *c, OpKind k, const T *x, T *y, hipStream_t s)
 // boundary facet lies in a tile.
 bool fused_path(const fo_ctx *c, OpKind k)
 {
+    if (k == OP_HEAT64) return false;
     return tiled(c) && (k != OP_DESCENT64 || c->tiles.facets_ok);
 }
 
@@ -363,7 +377,7 @@ int fused_kind(OpKind k) { return k == OP_DESCENT64 ? FUSED_DESCENT : FUSED_ELAS
 int solve_fp64(fo_ctx *c, OpKind k, const double *b, const double *dinv, const fo_solve_opts *o,
                fo_solve_stats *st)
 {
-    const int64_t n = c->ndof;
+    const int64_t n = op_len(c, k);
     hipStream_t s = c->stream;
     const bool fused = fused_path(c, k);
     CgVecs<double> v{c->x64, c->r64, c->p64, c->q64, dinv};
@@ -541,6 +555,13 @@ int solve_ir(fo_ctx *c, OpKind k, const double *b, const fo_solve_opts *o, fo_so
 }
 
 }  // namespace
+
+int fo::heat_cg_solve(fo_ctx *c, const uint8_t *fixed, const double *b, const double *dinv, const fo_solve_opts *o,
+                      fo_solve_stats *st)
+{
+    c->heat_mask = fixed;
+    return solve_fp64(c, OP_HEAT64, b, dinv, o, st);
+}
 
 int fo::fp64_solve(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats *st)
 {

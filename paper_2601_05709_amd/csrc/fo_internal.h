@@ -235,6 +235,9 @@ struct fo_ctx {
     void *inv_buf = nullptr;
     size_t inv_cap = 0;                // doubles in inv_buf
 
+    // fixed nodes of the heat state solve in progress (device [N])
+    const uint8_t *heat_mask = nullptr;
+
     // batched multi-load solves (allocated when max_rhs > 1)
     fo::BatchState batch;
 

@@ -134,6 +134,11 @@ int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
 int elas_apply64(fo_ctx *c, const double *x, double *y, hipStream_t s);
 // FP64 Jacobi-PCG of K(phi) x = b (contiguous b), solution left in c->x64.
 int fp64_solve(fo_ctx *c, const double *b, const fo_solve_opts *o, fo_solve_stats *st);
+// FP64 Jacobi-PCG of the scalar heat operator K x = b on the nodes where
+// fixed is 0 (b and dinv zero where it is set; contiguous [n_nodes]),
+// stopping on the recomputed residual; the solution is left in c->x64.
+int heat_cg_solve(fo_ctx *c, const uint8_t *fixed, const double *b, const double *dinv, const fo_solve_opts *o,
+                  fo_solve_stats *st);
 int64_t first_phase_cap(int64_t n);
 
 // batched multi-load path (fo_batch.hip)

@@ -7,8 +7,9 @@
 // grad_H, weak_HJ): pseudo-time steps of the diffusive Eikonal equation,
 // each solving Lhat varphi' = rhs (ReinitOp, ReinitRhsOp), explicit Euler
 // first and Adams-Bashforth 2 after it.  The heat-conduction model's state
-// (Section "Heat conduction": scalar P1 stiffness with identity rows on
-// Gamma_0) is solved the same way.
+// (Section "Heat conduction": scalar P1 stiffness, u = 0 on Gamma_0) is SPD
+// and goes to the library's FP64 Jacobi-PCG instead; its entry points live
+// here with the rest of the scalar P1 work.
 //
 // Both solve with Jacobi-preconditioned BiCGStab in FP64 from the previous
 // iterate.  The Krylov scalars stay on the device: every block of a vector
@@ -262,10 +263,9 @@ struct TrBufs {
     uint8_t *mask;            // [N] fixed nodes of the heat problem
 };
 
-// Which matrix the solver applies: the transport L, the reinitialisation
-// Lhat (its parameters at par + 8), or the heat stiffness with identity rows
-// on the fixed nodes.
-enum { SYS_TRANSPORT = 0, SYS_REINIT = 1, SYS_HEAT = 2 };
+// Which matrix the solver applies: the transport L, or the
+// reinitialisation Lhat (its parameters at par + 8).
+enum { SYS_TRANSPORT = 0, SYS_REINIT = 1 };
 
 int tr_buffers(fo_ctx *c, TrBufs *o)
 {
@@ -303,25 +303,10 @@ int tr_buffers(fo_ctx *c, TrBufs *o)
     return FO_OK;
 }
 
-// Heat system: y_i = x_i on fixed nodes (their rows of K were zeroed).
-__global__ __launch_bounds__(256) void k_heat_identity(const uint8_t *__restrict__ mask, const double *__restrict__ x,
-                                                       double *__restrict__ y, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (mask[i]) y[i] = x[i];
-}
-
 int sys_apply(const fo_ctx *c, const TrBufs &B, int sys, const double *x, double *y, hipStream_t s,
               const int32_t *stop = nullptr)
 {
     if (sys == SYS_REINIT) return launch_reinit_apply(c, B.w, B.par + 8, x, y, s, stop);
-    if (sys == SYS_HEAT) {
-        FO_TRY(launch_heat_apply(c, B.mask, x, y, s, stop));
-        const int64_t N = c->N;
-        hipLaunchKernelGGL(k_heat_identity, dim3((int)std::min<int64_t>((N + 255) / 256, 4096)), dim3(256), 0, s,
-                           B.mask, x, y, N);
-        return FO_OK;
-    }
     return launch_transport_apply(c, B.theta, B.par, 0, x, y, s, stop);
 }
 
@@ -444,15 +429,11 @@ __global__ void k_rn_par(double *par, double dt, double h2, int euler)
     par[3] = euler ? 1.0 : 0.0;
 }
 
-// Heat system set-up: b = 0 and diag = 1 on fixed nodes.
-__global__ __launch_bounds__(256) void k_heat_fix(const uint8_t *__restrict__ mask, double *__restrict__ b,
-                                                  double *__restrict__ diag, int64_t n)
+// Heat system set-up: b = 0 on fixed nodes.
+__global__ __launch_bounds__(256) void k_heat_fix(const uint8_t *__restrict__ mask, double *__restrict__ b, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (mask[i]) {
-            b[i] = 0.0;
-            diag[i] = 1.0;
-        }
+        if (mask[i]) b[i] = 0.0;
 }
 
 // Volume sum_e chi_e |T_e|: partials per block into part[blockIdx.x].
@@ -599,16 +580,16 @@ int fo_heat_solve(fo_ctx *c, const uint8_t *gamma0, const double *b, double *u, 
     const int ng = grid_for(N);
     FO_HIP(hipMemcpyAsync(B.mask, gamma0, (size_t)N, hipMemcpyDeviceToDevice, s));
     FO_HIP(hipMemcpyAsync(B.b, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_heat_fix, dim3(ng), dim3(256), 0, s, B.mask, B.b, N);
+    // Jacobi: the diagonal of K with the fixed rows zeroed, inverted with 0 there
     FO_TRY(launch_heat_diag(c, B.mask, B.dinv, s));
-    hipLaunchKernelGGL(k_heat_fix, dim3(ng), dim3(256), 0, s, B.mask, B.b, B.dinv, N);
-    launch_invert_diag<double>(B.dinv, nullptr, N, B.dinv, s);
-    launch_fill<double>(B.x, N, 0.0, s);
-    int64_t iters = 0;
-    double worst = 0.0;
-    int status = FO_OK;
-    int pred = 8;
-    FO_TRY(solve_step(c, B, SYS_HEAT, o, &pred, &iters, &worst, &status));
-    FO_HIP(hipMemcpyAsync(u, B.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_invert_diag<double>(B.dinv, B.mask, N, B.dinv, s);
+    fo_solve_stats one{};
+    const int status = heat_cg_solve(c, B.mask, B.b, B.dinv, o, &one);
+    if (status < 0 && status != FO_ERR_BREAKDOWN) return status;
+    const int64_t iters = one.iters_inner;
+    const double worst = one.rel_res;
+    FO_HIP(hipMemcpyAsync(u, c->x64, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     FO_HIP(hipStreamSynchronize(s));
     if (st) {
         st->status = status;
