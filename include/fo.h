@@ -21,18 +21,27 @@
  *   fo_levelset_update   transport of phi along theta (eq. transport without
  *                        the diffusion term), one explicit step.
  *
+ * Around it: the paper's transport step and reinitialisation (fo_transport,
+ * fo_reinit), Algorithm 1 as a loop on the device (fo_optimize), batched
+ * multi-load solves, a serving pool, and two more models on the same
+ * operators with their loops: the heat-conduction model (fo_heat_*,
+ * fo_optimize_heat) and the inverse elasticity problem (fo_inverse_*,
+ * fo_optimize_inverse).
+ *
  * Conventions
  *   - Mesh arrays passed to fo_create are HOST pointers; the library copies
  *     (and re-tiles) them, so the caller may free them afterwards.
  *   - All per-iteration arrays (phi, b, u, rhs, theta, S1, J, ...) are DEVICE
  *     pointers owned by the caller.  They must not alias each other unless
- *     stated.  Nothing is retained after a call returns.
+ *     stated.  Nothing is retained after a call returns, except the velocity
+ *     mask of fo_descent_opts (kept with the options, see there).
  *   - Unknowns are node-blocked: dof = node * dim + component.  Several right
  *     hand sides are stored RHS-contiguous: value (dof, k) at [dof * ld + k].
  *   - Element arrays are structure-of-arrays: conn[a * n_elems + e].
  *   - Every call enqueues its work on the context's stream.  Calls that must
- *     test convergence (the two solves) synchronise that stream before they
- *     return; the others return without synchronising.
+ *     test convergence (the solves, transport, reinitialisation and loops)
+ *     synchronise that stream before they return; the others return without
+ *     synchronising unless stated.
  *   - Errors are status codes; arguments are validated on the host before any
  *     work is enqueued.  A context is not thread safe.
  *   - Level set: Omega = {phi < 0} (eq. subdomain).  One coefficient per
