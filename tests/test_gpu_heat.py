@@ -84,7 +84,8 @@ def test_heat_edge_cases():
         ctx.heat_derivative(u, b, torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda"),
                             torch.zeros(1, dtype=torch.float64, device="cuda"),
                             torch.zeros(1, dtype=torch.float64, device="cuda"), V=0.0)
-    # the heat solve shares the transport solver: both stay right when interleaved
+    # the heat solve shares the context's CG buffers with the elasticity solve and
+    # its work buffers with the transport step: all stay right when interleaved
     f = source(m.coords)
     u_ref, *_ = oh.heat_iteration(m.dim, m.coords, m.conn, w.phi, f, gamma0(m), ersatz=w.ersatz)
     ctx.heat_load(dev(f), b)
@@ -92,6 +93,14 @@ def test_heat_edge_cases():
     ctx.transport(dev(np.full(m.n_dofs, 0.1)), 0.01, 2, phi, fo.SolveOpts(rtol=1e-12))
     ctx.heat_solve(fx, b, u, fo.SolveOpts(rtol=1e-12))
     assert np.linalg.norm(u.cpu().numpy() - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    ue = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    ctx.state_solve(dev(w.b.reshape(-1)), ue, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-10))
+    u2 = torch.zeros_like(u)
+    ctx.heat_solve(fx, b, u2, fo.SolveOpts(rtol=1e-12))
+    assert torch.equal(u, u2)
+    ue2 = torch.zeros_like(ue)
+    ctx.state_solve(dev(w.b.reshape(-1)), ue2, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-10))
+    assert torch.equal(ue, ue2)
 
 
 @pytest.mark.parametrize("name", ["2d_37x19", "3d_16x8x8"])
