@@ -269,10 +269,7 @@ def main():
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed iteration, the precision check and the roofline (no transport, "
                          "reinitialisation, heat, inverse or loop measurements)")
-    ap.add_argument("--serving", action="store_true",
-                    help="also run the serving stream (off by default: a pool teardown ended once in a host "
-                         "segmentation fault whose cause is not yet shown)")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream (the default)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--serving-requests", type=int, default=120)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -622,7 +619,7 @@ def main():
             % (bt["solves_per_s"], bt["fp64_columnwise"]["solves_per_s"], bt["speedup_vs_fp64_columnwise"],
                bt["fp32_ir_columnwise"]["solves_per_s"], bt["speedup_vs_fp32_ir_columnwise"],
                bt["apply"]["avg_us"]))
-    if args.serving and not args.no_serving:
+    if not args.no_serving:
         log("serving stream (%d requests, 200/s)" % args.serving_requests)
         result["serving"] = serving_case(args.serving_requests)
         sv = result["serving"]

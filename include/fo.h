@@ -465,14 +465,21 @@ int fo_tile_stats(const fo_ctx *ctx, int64_t *n_tiles, int64_t *max_nodes, int64
  * solve, compliance and shape derivative, descent solve.  A request is
  * admitted into a free slot when the device-memory budget has room for its
  * context (fo_footprint_estimate, replaced by the actual footprint once
- * created).  Every running request owns a context and a HIP stream and is
- * driven by a host worker thread, so requests admitted while others run
- * overlap on the GPU; the results of a request do not depend on what else
- * runs (every reduction has a fixed order).  A finished request's context
- * stays resident, keyed by mesh_key, and a later request with the same
- * nonzero key reuses it (mesh, tiles and workspace) instead of creating one;
- * idle resident contexts are evicted, least recently used first, when a new
+ * created).  Every running request owns a context and a HIP stream.  The
+ * requests run as cooperative fibers on the thread that calls fo_pool_step /
+ * fo_pool_wait: a request makes its library calls until one of them would
+ * wait for the device (a solver chunk's status, a stream drain), then the
+ * next request runs.  So requests admitted while others run overlap on the
+ * GPU, and every HIP object of the pool is created, used and destroyed on
+ * that one thread.  The results of a request do not depend on what else runs
+ * (every reduction has a fixed order).  A finished request's context stays
+ * resident, keyed by mesh_key, and a later request with the same nonzero key
+ * reuses it (mesh, tiles and workspace) instead of creating one; idle
+ * resident contexts are evicted, least recently used first, when a new
  * context needs the memory.
+ *
+ * Threading: a pool belongs to the thread that created it; every call but
+ * fo_pool_stats returns FO_ERR_STATE from another thread.
  *
  * Host memory: every pointer in fo_request is a host pointer; the arrays must
  * stay valid until the request is done (fo_pool_poll).  Requests with the
@@ -513,9 +520,16 @@ int fo_pool_create(fo_pool **out, size_t budget_bytes, int32_t max_slots);
  * an invalid request. */
 int fo_pool_admit(fo_pool *pool, const fo_request *req, int32_t *slot);
 
-/* Blocks up to timeout_us microseconds (< 0: no limit) until some request is
- * done and not yet released; *slot receives its index, or -1 on timeout or
- * when nothing runs. */
+/* One scheduling round: resumes every running request until it waits for
+ * the device or finishes (a request's context is created, on the calling
+ * thread, in its first round).  *running (may be NULL) receives the number
+ * of requests still running. */
+int fo_pool_step(fo_pool *pool, int32_t *running);
+
+/* Runs scheduling rounds (fo_pool_step) for up to timeout_us microseconds
+ * (< 0: no limit) until some request is done and not yet released; *slot
+ * receives its index, or -1 on timeout or when nothing runs.  Between rounds
+ * in which every request still waits for the device it pauses 20 us. */
 int fo_pool_wait(fo_pool *pool, int64_t timeout_us, int32_t *slot);
 
 /* *done = 1 when the slot's request finished (then *res is filled; the
@@ -528,7 +542,8 @@ int fo_pool_release(fo_pool *pool, int32_t slot);
 /* Budget accounting: bytes reserved, running requests, resident contexts. */
 int fo_pool_stats(const fo_pool *pool, size_t *used_bytes, int32_t *running, int32_t *resident);
 
-/* Waits for every running request, then frees all contexts. */
+/* Runs every running request to its end, then frees all contexts (on the
+ * calling thread, which is the pool's). */
 int fo_pool_destroy(fo_pool *pool);
 
 const char *fo_status_string(int status);

@@ -175,7 +175,7 @@ int poll(fo_ctx *c)
 {
     FO_HIP(hipMemcpyAsync(c->scal_host, c->scal, sizeof(SolveScalars), hipMemcpyDeviceToHost,
                           c->stream));
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     return FO_OK;
 }
 
@@ -300,13 +300,13 @@ int cg_loop(fo_ctx *c, Chunk chunk_fn, int chunk, int64_t *iters)
         const int k = pending[0];
         pending[0] = pending[1];
         --inflight;
-        FO_HIP(hipEventSynchronize(c->ev_poll[k]));
+        FO_HIP(fo::wait_event(c->ev_poll[k]));
         last = c->scal_host[k];
         if (last.done) break;
         if (last.it == before) {  // no progress: a launch failed
             hipError_t e = hipGetLastError();
             std::fprintf(stderr, "libfo: CG chunk made no progress (%s)\n", hipGetErrorString(e));
-            (void)hipStreamSynchronize(c->stream);
+            (void)fo::wait_stream(c->stream);
             return FO_ERR_HIP;
         }
         // iterations still needed at the rate of the last chunk
@@ -465,7 +465,7 @@ int solve_ir(fo_ctx *c, OpKind k, const double *b, const fo_solve_opts *o, fo_so
     launch_dots<double>(1, b, b, nullptr, nullptr, nullptr, nullptr, n, c->partials, nb, s);
     launch_finish_dots(c->partials, nb, 1, s2 + 1, s);
     FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     const double bnorm = std::sqrt(c->red_host[0]);
     double rn = bnorm;
     int status = FO_NOT_CONVERGED;
@@ -508,7 +508,7 @@ int solve_ir(fo_ctx *c, OpKind k, const double *b, const fo_solve_opts *o, fo_so
         ++outer;
         launch_residual64(b, c->q64, c->r64, n, c->partials, s2 + 1, s);
         FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-        FO_HIP(hipStreamSynchronize(s));
+        FO_HIP(fo::wait_stream(s));
         const double rn_new = std::sqrt(c->red_host[0]);
         if (!(rn_new == rn_new)) {
             status = FO_ERR_BREAKDOWN;
@@ -541,7 +541,7 @@ int solve_ir(fo_ctx *c, OpKind k, const double *b, const fo_solve_opts *o, fo_so
         ++outer;
         launch_residual64(b, c->q64, c->r64, n, c->partials, s2 + 1, s);
         FO_HIP(hipMemcpyAsync(c->red_host, s2 + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-        FO_HIP(hipStreamSynchronize(s));
+        FO_HIP(fo::wait_stream(s));
         rn = std::sqrt(c->red_host[0]);
         status = rc == FO_ERR_BREAKDOWN ? FO_ERR_BREAKDOWN : (rn <= o->rtol * bnorm ? FO_OK : FO_NOT_CONVERGED);
     }
@@ -608,7 +608,7 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
         FO_HIP(hipMemcpyAsync(bx, ds.boxes.data(), ds.boxes.size() * sizeof(double),
                               hipMemcpyHostToDevice, s));
         launch_in_boxes(c, nbx, bx, ds.in0, s);
-        FO_HIP(hipStreamSynchronize(s));
+        FO_HIP(fo::wait_stream(s));
         FO_HIP(hipFree(bx));
     } else {
         launch_fill<uint8_t>(ds.in0, c->E, 0, s);
@@ -660,7 +660,7 @@ int time_cg_op(fo_ctx *c, FusedVecs<T> v, int reps, double *avg_us)
         rc = launch_tile_cg<T>(c, v.kind, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s);
     (void)hipEventRecord(e1, s);
     float ms = 0.0f;
-    if (rc == FO_OK && (hipEventSynchronize(e1) != hipSuccess ||
+    if (rc == FO_OK && (fo::wait_event(e1) != hipSuccess ||
                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
         rc = FO_ERR_HIP;
     (void)hipEventDestroy(e0);
@@ -696,7 +696,7 @@ const char *fo_status_string(int s)
 int fo_destroy(fo_ctx *c)
 {
     if (!c) return FO_ERR_ARG;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->stream) (void)fo::wait_stream(c->stream);
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
     if (c->work) (void)hipStreamDestroy(c->work);
     for (hipEvent_t e : c->ev_poll)
@@ -1014,7 +1014,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess)
         return fail(FO_ERR_HIP);
     if (max_rhs > 1 && tiled(c) && (rc = batch_setup(c, max_rhs))) return fail(rc);
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(FO_ERR_HIP);
+    if (fo::wait_stream(s) != hipSuccess) return fail(FO_ERR_HIP);
     *out = c;
     return FO_OK;
 }
@@ -1051,7 +1051,7 @@ size_t fo_footprint_estimate(const fo_mesh *m)
 int fo_profile_enable(fo_ctx *c, int32_t on)
 {
     if (!c) return FO_ERR_ARG;
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     c->prof = on != 0;
     for (int k = 0; k < FO_PROF_COUNT; ++k) c->prof_used[k] = 0;
     return FO_OK;
@@ -1060,7 +1060,7 @@ int fo_profile_enable(fo_ctx *c, int32_t on)
 int fo_profile_read(fo_ctx *c, int32_t which, double *total_ms, int64_t *launches)
 {
     if (!c || which < 0 || which >= FO_PROF_COUNT) return FO_ERR_ARG;
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     double tot = 0.0;
     for (size_t i = 0; i < c->prof_used[which]; ++i) {
         float ms = 0.0f;
@@ -1204,7 +1204,7 @@ int fo_state_solve(fo_ctx *c, const double *b, double *u, int32_t n_rhs, int64_t
         acc.rel_res = std::max(acc.rel_res, one.rel_res);
         if (rc != FO_OK && (worst == FO_OK || rc < worst)) worst = rc;
     }
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     acc.status = worst;
     acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st) *st = acc;
@@ -1264,7 +1264,7 @@ int fo_descent_solve(fo_ctx *c, const fo_descent_opts *d, const double *rhs, dou
                             nb, s);
         launch_finish_dots(c->partials, nb, 1, B_tt, s);
     }
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     one.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st) *st = one;
     return rc;

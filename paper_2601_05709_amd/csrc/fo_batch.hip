@@ -902,7 +902,7 @@ static int bup(fo_ctx *c, T **dst, const std::vector<T> &v)
     FO_TRY(balloc(c, (void **)dst, v.size() * sizeof(T), true));
     if (!v.empty() && (hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream) !=
                            hipSuccess ||
-                       hipStreamSynchronize(c->stream) != hipSuccess))
+                       fo::wait_stream(c->stream) != hipSuccess))
         return FO_ERR_HIP;
     return FO_OK;
 }
@@ -1048,7 +1048,7 @@ static int mesh_host(fo_ctx *c, std::vector<double> &X, std::vector<int32_t> &co
             hipSuccess ||
         hipMemcpyAsync(conn.data(), c->conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream) !=
             hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+        fo::wait_stream(c->stream) != hipSuccess)
         return FO_ERR_HIP;
     return FO_OK;
 }
@@ -1092,7 +1092,7 @@ int batch_setup(fo_ctx *c, int max_rhs)
     FO_TRY(mesh_host(c, X, conn));
     const int mn = std::min(batch_default_nodes(D), batch_max_nodes(D, b.S));
     FO_TRY(build_batch_tiles(c, mn, 8, X, conn));
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     return FO_OK;
 }
 
@@ -1133,7 +1133,7 @@ int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us)
     (void)hipEventRecord(e1, s);
     float ms = 0.0f;
     int rc = FO_OK;
-    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+    if (fo::wait_event(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
         hipGetLastError() != hipSuccess)
         rc = FO_ERR_HIP;
     (void)hipEventDestroy(e0);
@@ -1173,7 +1173,7 @@ int batch_apply_block(fo_ctx *c, int NC, const float *X, float *Y)
     launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
     by_s<CollectL>(S, (const fo_ctx *)c, Y, s);
     FO_HIP(hipGetLastError());
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     return FO_OK;
 }
 
@@ -1209,7 +1209,7 @@ int batch_tune(fo_ctx *c, int n_rhs, int *best_nodes, int *best_group, double *b
     }
     if (best == 0) return FO_ERR_ARG;
     if (best != b.mn_cap || bg != b.group) FO_TRY(build_batch_tiles(c, best, bg, X, conn));
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     if (best_nodes) *best_nodes = best;
     if (best_group) *best_group = bg;
     if (best_us) *best_us = best_t;
@@ -1220,7 +1220,7 @@ static int poll_batch(fo_ctx *c)
 {
     FO_HIP(hipMemcpyAsync(c->batch.ctl_host, c->batch.ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost,
                           c->stream));
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     return FO_OK;
 }
 
@@ -1230,7 +1230,7 @@ static int residual_norms(fo_ctx *c, int S)
     BatchState &b = c->batch;
     by_s<ColsqL>(S, (const fo_ctx *)c, (const double *)b.r64, b.s2 + S, c->stream);
     FO_HIP(hipMemcpyAsync(b.s2_host, b.s2 + S, S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     return FO_OK;
 }
 
@@ -1280,7 +1280,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         BatchCtl ctl{0, 0, o->max_iter, 0};
         FO_HIP(hipMemcpyAsync(b.cols, cols.data(), S * sizeof(BatchCol), hipMemcpyHostToDevice, s));
         FO_HIP(hipMemcpyAsync(b.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
-        FO_HIP(hipStreamSynchronize(s));
+        FO_HIP(fo::wait_stream(s));
     }
     FO_TRY(residual_norms(c, S));
     std::vector<double> bnorm(S), rn(S);
@@ -1344,7 +1344,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         }
         // columns that finished their phase (or broke down)
         FO_HIP(hipMemcpyAsync(b.cols_host, b.cols, S * sizeof(BatchCol), hipMemcpyDeviceToHost, s));
-        FO_HIP(hipStreamSynchronize(s));
+        FO_HIP(fo::wait_stream(s));
         bool any = false;
         for (int k = 0; k < S; ++k) {
             fin[k] = !conv[k] && b.cols_host[k].done;
@@ -1416,7 +1416,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         else if (!(rn[k] <= o->rtol * bnorm[k])) fail[k] = 1;
     }
     hipLaunchKernelGGL(k_batch_unpack, dim3(grid_of(nd * n)), dim3(256), 0, s, b.x64, S, n, u, ld, nd);
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     double worst = 0.0;
     int max_outer_seen = 0;
     for (int k = 0; k < n; ++k) {

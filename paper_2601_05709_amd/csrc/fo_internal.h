@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/fo.h"
+#include "fo_wait.h"
 
 // Status plumbing of the host runtime: a failing HIP call is reported on
 // stderr and turns into FO_ERR_HIP; FO_TRY forwards any non-OK status.

@@ -41,7 +41,7 @@ int inv_buffers(fo_ctx *c, int64_t ld, InvBufs *o)
     const size_t n_dbl = (size_t)(2 * n * ld + 8 * n + 8);  // b, y [n][ld]; t0..t3 [n]; pack [4n]; scal [8]
     if (!c->inv_buf || c->inv_cap < n_dbl) {
         if (c->inv_buf) {
-            (void)hipStreamSynchronize(c->stream);
+            (void)fo::wait_stream(c->stream);
             (void)hipFree(c->inv_buf);
             auto it = std::find(c->allocations.begin(), c->allocations.end(), c->inv_buf);
             if (it != c->allocations.end()) c->allocations.erase(it);
@@ -247,7 +247,7 @@ int fo_inverse_states(fo_ctx *cf, fo_ctx *cg, const double *phi, int32_t n_pairs
         FO_TRY(launch_elas_apply_free(cf, B.t0, B.t1, s));
         hipLaunchKernelGGL(k_put, dim3(ng), dim3(256), 0, s, n, ld, -1.0, B.t1, B.y + k);
     }
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     // u (clamped on Gamma_0) and v (clamped on the whole boundary)
     FO_TRY(solve_both(cf, B.b, u, cg, B.y, v, n_pairs, ld, o, &acc));
     // cost and the adjoint loads, pair by pair
@@ -262,7 +262,7 @@ int fo_inverse_states(fo_ctx *cf, fo_ctx *cg, const double *phi, int32_t n_pairs
         hipLaunchKernelGGL(k_inv_adj, dim3(ng), dim3(256), 0, s, n, ld, alpha, beta, 1.0 / kappa, B.t2, B.t3,
                            B.b + k, B.y + k);
     }
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     // p (clamped on Gamma_0) and q (clamped on the whole boundary)
     FO_TRY(solve_both(cf, B.b, p, cg, B.y, q, n_pairs, ld, o, &acc));
     FO_HIP(hipGetLastError());
@@ -294,7 +294,7 @@ int fo_inverse_derivative(fo_ctx *cf, int32_t n_pairs, int64_t ld, const double 
         FO_TRY(launch_inverse_rhs(cf, ld > 1 ? B.t0 : u, B.pack, kappa, alpha, k == 0 ? rhs : B.t1, s));
         if (k > 0) launch_add64(rhs, B.t1, cf->ndof, s);
     }
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     return FO_OK;
 }
 

@@ -102,7 +102,7 @@ struct Model {
 int fetch(fo_ctx *c, double *host, const double *dev, int k)
 {
     if (hipMemcpyAsync(host, dev, k * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+        fo::wait_stream(c->stream) != hipSuccess)
         return FO_ERR_HIP;
     return FO_OK;
 }
@@ -174,7 +174,7 @@ int run_loop(fo_ctx *c, const fo_loop_opts *o, Model &m, double *phi, double *rh
         result = worse(result, st);
         if (st < 0) break;
     }
-    (void)hipStreamSynchronize(c->stream);
+    (void)fo::wait_stream(c->stream);
     return result;
 }
 

@@ -357,7 +357,7 @@ int solve_step(fo_ctx *c, const TrBufs &B, int sys, const fo_solve_opts *o, int 
     TrScal h{};
     auto read = [&]() -> int {
         FO_HIP(hipMemcpyAsync(&h, B.sc, sizeof(TrScal), hipMemcpyDeviceToHost, s));
-        FO_HIP(hipStreamSynchronize(s));
+        FO_HIP(fo::wait_stream(s));
         return FO_OK;
     };
     launch_dots<double>(1, B.b, B.b, nullptr, nullptr, nullptr, nullptr, N, c->partials, red_blocks(N), s);
@@ -505,7 +505,7 @@ int fo_transport(fo_ctx *c, const double *theta, double dt, int32_t steps, int32
         FO_TRY(solve_step(c, B, SYS_TRANSPORT, o, &pred, &iters, &worst, &status));
         FO_HIP(hipMemcpyAsync(phi, B.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     if (st) {
         st->status = status;
         st->iters_inner = (int32_t)std::min<int64_t>(iters, INT32_MAX);
@@ -547,7 +547,7 @@ int fo_reinit(fo_ctx *c, double *phi, int32_t steps, double t_end, const fo_solv
         FO_HIP(hipMemcpyAsync(B.prev, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         FO_HIP(hipMemcpyAsync(phi, B.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     if (st) {
         st->status = status;
         st->iters_inner = (int32_t)std::min<int64_t>(iters, INT32_MAX);
@@ -563,7 +563,7 @@ int fo_heat_load(fo_ctx *c, const double *f, double *b)
     if (!c || !f || !b) return FO_ERR_ARG;
     if (c->scatter != FO_SCATTER_TILED || c->tiles.n_tiles <= 0) return FO_ERR_STATE;
     FO_TRY(launch_mass_apply(c, f, b, c->stream));
-    FO_HIP(hipStreamSynchronize(c->stream));
+    FO_HIP(fo::wait_stream(c->stream));
     return FO_OK;
 }
 
@@ -590,7 +590,7 @@ int fo_heat_solve(fo_ctx *c, const uint8_t *gamma0, const double *b, double *u, 
     const int64_t iters = one.iters_inner;
     const double worst = one.rel_res;
     FO_HIP(hipMemcpyAsync(u, c->x64, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     if (st) {
         st->status = status;
         st->iters_inner = (int32_t)std::min<int64_t>(iters, INT32_MAX);
@@ -621,7 +621,7 @@ int fo_heat_derivative(fo_ctx *c, const double *u, const double *f, double lambd
     else
         hipLaunchKernelGGL(k_heat_vol<3>, dim3(nb), dim3(256), 0, s, c->conn, c->E, c->coords, c->chi, c->partials);
     launch_finish_dots(c->partials, nb, 1, vol, s);
-    FO_HIP(hipStreamSynchronize(s));
+    FO_HIP(fo::wait_stream(s));
     return FO_OK;
 }
 

@@ -134,6 +134,7 @@ EXPORTS = {
     "fo_footprint_estimate": ([C.POINTER(fo_mesh)], C.c_size_t),
     "fo_pool_create": ([C.POINTER(_vp), C.c_size_t, C.c_int32], C.c_int),
     "fo_pool_admit": ([_vp, C.POINTER(fo_request), C.POINTER(C.c_int32)], C.c_int),
+    "fo_pool_step": ([_vp, C.POINTER(C.c_int32)], C.c_int),
     "fo_pool_wait": ([_vp, C.c_int64, C.POINTER(C.c_int32)], C.c_int),
     "fo_pool_poll": ([_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(fo_pool_result)], C.c_int),
     "fo_pool_release": ([_vp, C.c_int32], C.c_int),

@@ -3,9 +3,10 @@
 A request is one iteration's finite-element work on its own mesh (level set,
 state solve, compliance and shape derivative, descent solve).  The pool
 (fo_pool_*) admits requests into slots while its device-memory budget has
-room, runs each on its own stream from a worker thread so that requests
-admitted while others run overlap on the GPU, and keeps finished contexts
-resident for later requests on the same mesh.  This module only marshals
+room and runs each on its own stream, as a fiber on the thread that drives
+the pool (fo_pool_wait / fo_pool_step), so that requests admitted while
+others run overlap on the GPU; finished contexts stay resident for later
+requests on the same mesh.  This module only marshals
 requests and drives arrivals in real time; every step runs in libfo.
 """
 from __future__ import annotations
@@ -106,6 +107,12 @@ class Pool:
         fo._check(rc, "fo_pool_admit")
         self._live[slot.value] = (req, q)
         return slot.value
+
+    def step(self) -> int:
+        """One scheduling round; returns the number of requests still running."""
+        running = C.c_int32(0)
+        fo._check(fo.lib().fo_pool_step(self.h, C.byref(running)), "fo_pool_step")
+        return running.value
 
     def wait(self, timeout_s: Optional[float]) -> int:
         slot = C.c_int32(-1)

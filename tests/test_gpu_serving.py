@@ -1,6 +1,8 @@
 """Serving pool on the GPU: results alone and in the mix, parity with the
-oracle, admission by device-memory budget, context reuse, and a short
-Poisson stream."""
+oracle, admission by device-memory budget, context reuse, calls from a
+thread that does not own the pool, and a short Poisson stream.  The pool runs
+its requests as fibers on the calling thread (fo_pool_step / fo_pool_wait),
+each on its own context and stream."""
 import ctypes as C
 
 import numpy as np
@@ -27,15 +29,6 @@ def requests(ids, keyed=True):
     return out
 
 
-# A pool teardown (fo_pool_destroy on the main thread, after the worker
-# threads that created and used the contexts have exited) ended once in a
-# host segmentation fault.  The pool's host logic is clean under
-# AddressSanitizer and ThreadSanitizer on the CPU; the cause in the device
-# resource release is not yet shown, so the GPU tests that tear down a pool
-# stay off until it is.
-POOL_TEARDOWN = pytest.mark.skip(reason="intermittent host segfault in fo_pool_destroy; cause not yet shown")
-
-
 def run_all(pool, reqs):
     slots = {}
     for k, r in enumerate(reqs):
@@ -53,7 +46,6 @@ def run_all(pool, reqs):
     return res
 
 
-@POOL_TEARDOWN
 def test_results_alone_and_in_the_mix_are_identical():
     """T18: every request's outputs are bitwise the same whether it runs alone
     or together with five others on the device."""
@@ -75,7 +67,6 @@ def test_results_alone_and_in_the_mix_are_identical():
     pool.close()
 
 
-@POOL_TEARDOWN
 def test_request_matches_oracle():
     (r,) = requests([3])
     w = r.w
@@ -91,7 +82,6 @@ def test_request_matches_oracle():
     assert res.B_tt == pytest.approx(ref.B_tt, rel=1e-6)
 
 
-@POOL_TEARDOWN
 def test_budget_admission_and_context_reuse():
     reqs = requests([0, 4, 8, 12])   # same seed base: mixed meshes
     pool = serving.Pool(1 << 40, max_slots=4)
@@ -124,6 +114,35 @@ def test_budget_admission_and_context_reuse():
     pool.close()
 
 
+def test_pool_refuses_other_threads_and_steps_running_requests():
+    """A pool belongs to its creating thread; fo_pool_step drives the running
+    requests (several started, all overlapping) to completion."""
+    import threading
+    reqs = requests(range(3))
+    pool = serving.Pool(2 << 30, max_slots=3)
+    slots = [pool.admit(r) for r in reqs]
+    assert None not in slots
+    assert pool.step() >= 1                 # started; the rest run in later rounds
+    seen = {}
+
+    def other():
+        seen["step"] = fo.lib().fo_pool_step(pool.h, None)
+        seen["release"] = fo.lib().fo_pool_release(pool.h, 0)
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen == {"step": fo.FO_ERR_STATE, "release": fo.FO_ERR_STATE}
+    while pool.step() > 0:
+        pass
+    out = [pool.poll(s) for s in slots]
+    assert all(r is not None and r.status == 0 for r in out)
+    assert max(r.t_start for r in out) < min(r.t_end for r in out)
+    for s in slots:
+        pool.release(s)
+    pool.close()
+
+
 def test_footprint_estimate_close_to_actual():
     for cells in ((64, 32), (128, 64), (16, 8, 8), (32, 16, 16)):
         w = fi.cantilever_2d(cells) if len(cells) == 2 else fi.cantilever_3d(cells)
@@ -141,7 +160,6 @@ def test_footprint_estimate_close_to_actual():
         assert 0.5 * est <= actual <= 1.25 * est, (cells, est, actual)
 
 
-@POOL_TEARDOWN
 def test_poisson_stream_completes():
     reqs = requests(range(24))
     arrivals = np.cumsum(np.random.default_rng(4).exponential(1.0 / 400.0, size=24))
