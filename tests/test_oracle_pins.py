@@ -526,3 +526,49 @@ def test_adaptive_dt_rule():
     assert t == 0.1 and s == 16 and dt == pytest.approx(0.1 / 16)
     t, s, dt = oc.adaptive_dt(1e9)
     assert t == 1e-3 and s == 8
+
+
+def test_levelset_update_weights_by_element_measure():
+    """The recovered nodal gradient is the |T|-weighted mean of the element
+    gradients around a node (lumped L2 projection of grad phi).  Two
+    triangles of areas 1/2 and 5/2 share the edge (1,0)-(0,1); by hand:
+    grad phi = (1, 2) on the first and (-0.8, 0.2) on the second, so the
+    shared nodes get G = (0.5 (1,2) + 2.5 (-0.8,0.2)) / 3 = (-0.5, 0.5)
+    (a count-weighted mean would give (0.1, 1.1)); with dt = 0.1:
+    phi_0 = 0 - 0.1 (1,1).(1,2) = -0.3, phi_1 = 1 - 0.1 (1,0).(-0.5,0.5) = 1.05,
+    phi_2 = 2 - 0.1 (0,2).(-0.5,0.5) = 1.9, phi_3 = 0 - 0.1 (2,-1).(-0.8,0.2) = 0.18."""
+    coords = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [3.0, 3.0]])
+    conn = np.ascontiguousarray(np.array([[0, 1, 2], [1, 2, 3]], dtype=np.int32).T)
+    phi = np.array([0.0, 1.0, 2.0, 0.0])
+    theta = np.array([[1.0, 1.0], [1.0, 0.0], [0.0, 2.0], [2.0, -1.0]]).ravel()
+    out = oc.levelset_update(2, coords, conn, theta, 0.1, phi)
+    np.testing.assert_allclose(out, [-0.3, 1.05, 1.9, 0.18], rtol=0, atol=1e-15)
+
+
+def test_reinit_near_flat_element_is_flat():
+    """An element whose vertex values agree up to rounding (0.1 + 0.2 against
+    0.3) gets the direction of an exactly flat element (grad H = 0), so the
+    reinitialisation of such a level set equals that of the exactly flat one
+    to rounding; taking g/|g| of the rounding noise instead changes the
+    result by about 1e-5 here."""
+    from oracle import reinit as rr
+    m = fi.structured_mesh((8, 4), (2.0, 1.0))
+    x = m.coords[:, 0]
+    phi = 0.3 + np.maximum(0.0, x - 0.5)      # constant on the patch x <= 0.5
+    noisy = phi.copy()
+    patch = np.where(x <= 0.5)[0]
+    noisy[patch[::2]] = 0.1 + 0.2              # 0.30000000000000004
+    assert np.any(noisy != phi)
+    a = rr.reinit(2, m.coords, m.conn, phi)
+    b = rr.reinit(2, m.coords, m.conn, noisy)
+    assert np.abs(a - b).max() < 1e-13
+
+
+def test_adaptive_dt_interior_value():
+    """B(theta, theta) = 2 with the paper's defaults, by hand:
+    t_end = 0.01 / 2 = 0.005 (inside [1e-3, 1e-1]);
+    s = 8 ((0.005 - 0.001) / 0.099)^(1/6) + 8 = 8 (4/99)^(1/6) + 8,
+    ln(4/99) = 1.3862944 - 4.5951199 = -3.2088255, /6 = -0.5348043,
+    exp = 0.5857847, so s = 12.686 -> 13 steps, dt = 0.005 / 13."""
+    t, s, dt = oc.adaptive_dt(2.0)
+    assert t == 0.005 and s == 13 and dt == pytest.approx(0.005 / 13, rel=1e-15)
