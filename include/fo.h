@@ -109,7 +109,8 @@ typedef struct {
     double alpha;              /* weight of int theta . xi                         */
     double gamma_n;            /* weight of int_{boundary} (theta.n)(xi.n)         */
     double gamma_s;            /* weight of int chi_Omega0 theta . xi              */
-    int32_t n_boxes;           /* Omega0 = union of open boxes (element centroid)  */
+    int32_t n_boxes;           /* Omega0 = union of open boxes (element centroid),
+                                  at most 64                                       */
     const double *boxes;       /* host [n_boxes][2*dim]: lo[0..d), hi[0..d)        */
     const uint8_t *fixed;      /* NULL, or device [n_dofs]: theta = 0 where set
                                   (e.g. H^1_0 velocities); the context keeps the
@@ -130,12 +131,23 @@ typedef struct {
 /* Create a context for one mesh and material.  Validates the mesh (indices in
  * range, no degenerate element), builds the element tiles, copies everything
  * to the current HIP device and allocates the Krylov workspace for up to
- * max_rhs simultaneous right-hand sides.  stream may be NULL (default stream).
- * The context owns its device memory until fo_destroy.
+ * max_rhs simultaneous right-hand sides, the velocity operator's arrays and
+ * the transport and reinitialisation work buffers.  stream may be NULL
+ * (default stream).  The context owns its device memory until fo_destroy.
+ * After creation the per-iteration calls (fo_set_levelset, the solves,
+ * derivatives, applies, fo_levelset_update, fo_transport, fo_reinit and the
+ * fo_heat_* calls) allocate no device memory; fo_batch_tune, the inverse
+ * problem's calls (their pair buffers, on first use or for a larger ld) and
+ * the loops fo_optimize* (their work vectors, per call) do.
  * Errors: FO_ERR_ARG, FO_ERR_MESH, FO_ERR_NOMEM, FO_ERR_HIP. */
 int fo_create(fo_ctx **out, const fo_mesh *mesh, const fo_material *mat, int32_t max_rhs,
               void *stream);
 int fo_destroy(fo_ctx *ctx);
+
+/* Number of device allocations (hipMalloc) the library has made in this
+ * process so far, for callers and tests that check that a sequence of calls
+ * allocates nothing. */
+int64_t fo_device_allocations(void);
 
 /* Device bytes owned by the context (for footprint-based admission). */
 size_t fo_footprint_bytes(const fo_ctx *ctx);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <functional>
 #include <cmath>
@@ -24,12 +25,13 @@ using namespace fo;
 namespace fo {
 
 // Enqueues one chunk; with profiling off, a graph of it (captured once on the
-// private stream, which only records) is replayed on the context stream.
+// private stream, which only records) is replayed on the context stream.  In
+// no-capture mode a chunk without a graph is enqueued directly.
 int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
                 const std::function<int(hipStream_t)> &enqueue)
 {
-    if (c->prof) return enqueue(c->stream);
     auto it = c->graphs.find(key);
+    if (c->prof || (c->no_capture && it == c->graphs.end())) return enqueue(c->stream);
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {
         hipGraph_t g = nullptr;
@@ -54,21 +56,48 @@ int graph_chunk(fo_ctx *c, std::tuple<int, int, int, int> key,
 
 }  // namespace fo
 
-namespace {
+namespace fo {
 
-template <typename T>
-int dev_alloc(fo_ctx *c, T **p, size_t count)
+namespace {
+std::atomic<int64_t> g_device_allocations{0};
+}
+
+hipError_t device_malloc(void **p, size_t bytes)
 {
-    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) g_device_allocations.fetch_add(1, std::memory_order_relaxed);
+    return e;
+}
+
+int ctx_alloc(fo_ctx *c, void **p, size_t bytes)
+{
+    bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    *p = nullptr;
+    if (c->ws) {
+        if (bytes > c->ws_cap - c->bytes) return FO_ERR_NOMEM;
+        *p = c->ws + c->bytes;
+        c->bytes += bytes;
+        return FO_OK;
+    }
     void *v = nullptr;
-    if (hipMalloc(&v, bytes) != hipSuccess) {
+    if (device_malloc(&v, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return FO_ERR_NOMEM;
     }
     c->allocations.push_back(v);
     c->bytes += bytes;
-    *p = static_cast<T *>(v);
+    *p = v;
     return FO_OK;
+}
+
+}  // namespace fo
+
+namespace {
+
+template <typename T>
+int dev_alloc(fo_ctx *c, T **p, size_t count)
+{
+    return fo::ctx_alloc_n(c, p, std::max<size_t>(count, 1));
 }
 
 
@@ -588,13 +617,7 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
     if (descent_same(c, d)) return FO_OK;
     hipStream_t s = c->stream;
     DescentSetup &ds = c->descent;
-    if (!ds.in0) {
-        FO_TRY(dev_alloc(c, &ds.in0, c->E));
-        FO_TRY(dev_alloc(c, &ds.diag, c->ndof));
-        FO_TRY(dev_alloc(c, &ds.dinv, c->ndof));
-        FO_TRY(dev_alloc(c, &ds.dinv32, c->ndof));
-        FO_TRY(dev_alloc(c, &ds.rhs, c->ndof));
-    }
+    if (d->n_boxes > kMaxBoxes) return FO_ERR_ARG;
     ++c->descent_version;
     ds.alpha = d->alpha;
     ds.gamma_n = d->gamma_n;
@@ -603,13 +626,11 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
     int nbx = std::max(0, d->n_boxes);
     ds.boxes.assign(d->boxes, d->boxes + (size_t)nbx * 2 * c->dim);
     if (nbx > 0) {
-        double *bx = nullptr;
-        if (hipMalloc(&bx, ds.boxes.size() * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
-        FO_HIP(hipMemcpyAsync(bx, ds.boxes.data(), ds.boxes.size() * sizeof(double),
+        // the host copy stays valid until the transfer has run
+        FO_HIP(hipMemcpyAsync(ds.boxes_dev, ds.boxes.data(), ds.boxes.size() * sizeof(double),
                               hipMemcpyHostToDevice, s));
-        launch_in_boxes(c, nbx, bx, ds.in0, s);
+        launch_in_boxes(c, nbx, ds.boxes_dev, ds.in0, s);
         FO_HIP(fo::wait_stream(s));
-        FO_HIP(hipFree(bx));
     } else {
         launch_fill<uint8_t>(ds.in0, c->E, 0, s);
     }
@@ -692,6 +713,8 @@ const char *fo_status_string(int s)
     default: return "unknown status";
     }
 }
+
+int64_t fo_device_allocations(void) { return g_device_allocations.load(std::memory_order_relaxed); }
 
 int fo_destroy(fo_ctx *c)
 {
@@ -814,6 +837,16 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         (rc = dev_alloc(c, &c->gbuf, N * (D + 1))))
         return fail(rc);
     if ((rc = dev_alloc(c, &c->s1buf, (size_t)E * D * D))) return fail(rc);
+    // velocity operator (its diagonal is built by the first velocity solve)
+    // and the transport / reinitialisation work buffers
+    {
+        DescentSetup &ds = c->descent;
+        if ((rc = dev_alloc(c, &ds.in0, E)) || (rc = dev_alloc(c, &ds.diag, n)) ||
+            (rc = dev_alloc(c, &ds.dinv, n)) || (rc = dev_alloc(c, &ds.dinv32, n)) ||
+            (rc = dev_alloc(c, &ds.rhs, n)) || (rc = dev_alloc(c, &ds.boxes_dev, (size_t)kMaxBoxes * 2 * D)) ||
+            (rc = fo::ctx_alloc(c, &c->tr_buf, tr_buffer_bytes(c))))
+            return fail(rc);
+    }
     {
         std::vector<uint8_t> used(N, 0);
         for (int64_t k = 0; k < (int64_t)(D + 1) * E; ++k) used[m->conn[k]] = 1;
@@ -1043,8 +1076,9 @@ size_t fo_footprint_estimate(const fo_mesh *m)
     const size_t MN = std::min<size_t>((size_t)tile_max_nodes((int)D), (ME * N * 5) / (2 * E) + 16);
     b += T * (32 + ME * 16 + MN * 10) + N * 8 + N * 3 * 4;
     b += std::min(T * MN, (D + 1) * E) * (D + 1) * 8;
-    b += E + 2 * n * 8;                                   // descent: Omega0 flags, diagonal
-    b += 64 * 256;                                        // allocation rounding
+    b += E + 3 * n * 8 + n * 4 + (size_t)kMaxBoxes * 2 * D * 8;  // velocity operator arrays
+    b += (N * D + 16 * N + 16 + 5 * (size_t)kRedBlocks + N / 8 + 1) * 8 + 512;  // transport buffers
+    b += 80 * 256;                                        // allocation rounding
     return b;
 }
 

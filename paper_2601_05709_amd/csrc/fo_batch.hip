@@ -882,16 +882,22 @@ static void batch_iteration(const fo_ctx *c, int NC, hipStream_t s)
 // ---------------------------------------------------------------------------
 // host side: tiles, buffers, solve
 
+// Batch buffers: the block vectors are the context's; the tile arrays of a
+// context with its own memory are separate allocations, released when
+// fo_batch_tune rebuilds the tiles (a context on a caller's workspace keeps
+// the tiles of its creation).
 static int balloc(fo_ctx *c, void **p, size_t bytes, bool tile)
 {
+    if (!tile || c->ws) return ctx_alloc(c, p, bytes);
+    bytes = std::max<size_t>(bytes, 1);
     void *v = nullptr;
-    if (hipMalloc(&v, std::max<size_t>(bytes, 1)) != hipSuccess) {
+    if (device_malloc(&v, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return FO_ERR_NOMEM;
     }
-    (tile ? c->batch.tile_allocs : c->allocations).push_back(v);
-    c->bytes += std::max<size_t>(bytes, 1);
-    if (tile) c->batch.tile_bytes += std::max<size_t>(bytes, 1);
+    c->batch.tile_allocs.push_back(v);
+    c->bytes += bytes;
+    c->batch.tile_bytes += bytes;
     *p = v;
     return FO_OK;
 }

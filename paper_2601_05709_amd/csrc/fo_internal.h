@@ -34,6 +34,32 @@
 
 namespace fo {
 
+// Every device allocation of the library goes through device_malloc, which
+// counts them (fo_device_allocations).
+hipError_t device_malloc(void **p, size_t bytes);
+
+// Device memory owned by a context: allocated (and recorded for fo_destroy)
+// or, for a context on a caller's workspace, carved from it (256-byte
+// aligned).  FO_ERR_NOMEM when it does not fit.
+int ctx_alloc(fo_ctx *c, void **p, size_t bytes);
+
+template <typename T>
+int ctx_alloc_n(fo_ctx *c, T **p, size_t count)
+{
+    void *v = nullptr;
+    const int rc = ctx_alloc(c, &v, count * sizeof(T));
+    *p = static_cast<T *>(v);
+    return rc;
+}
+
+// fo_optimize's loop on caller-provided work vectors of
+// optimize_work_doubles(c) doubles (u, rhs, theta, three scalars).
+size_t optimize_work_doubles(const fo_ctx *c);
+int optimize_on(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, fo_loop_record *records,
+                int32_t *n_done, int32_t *stopped, double *work);
+
+constexpr int kMaxBoxes = 64;      // boxes of Omega0 in the velocity options
+
 constexpr int kBlock = 256;        // threads per block of the vector kernels
 constexpr int kRedBlocks = 1024;   // partial sums per reduction (fixed: deterministic)
 constexpr int kUpdBlock = 1024;    // threads per block of the fused CG update (one node each)
@@ -157,6 +183,7 @@ struct DescentSetup {
     float *dinv32 = nullptr;  // [n_dofs]
     const uint8_t *fixed = nullptr;  // caller's mask (theta = 0 there), or null
     double *rhs = nullptr;    // [n_dofs] right-hand side with the masked entries zeroed
+    double *boxes_dev = nullptr;  // [kMaxBoxes][2 dim] device copy of the boxes
 };
 
 }  // namespace fo
@@ -173,6 +200,8 @@ struct fo_ctx {
     bool has_isolated = false;         // some node belongs to no element
     size_t bytes = 0;                  // device footprint
     std::vector<void *> allocations;   // everything hipMalloc'ed by this ctx
+    char *ws = nullptr;                // caller's workspace (device), or null
+    size_t ws_cap = 0;                 // its size
 
     // mesh, tile element order (elem_perm[tile order] = input element id)
     double *coords = nullptr;          // [N][dim]
@@ -228,9 +257,13 @@ struct fo_ctx {
     size_t prof_used[FO_PROF_COUNT] = {0, 0, 0, 0};
 
     // transport step: h^2 of the diffusion term (the paper's mesh-size
-    // expression) and the work buffers, allocated on the first call
+    // expression) and the work buffers of transport and reinitialisation
     double transport_h2 = 0.0;
     void *tr_buf = nullptr;
+
+    // graph_chunk enqueues chunks that have no captured graph yet directly
+    // instead of capturing them (no graph instantiation during the call)
+    bool no_capture = false;
 
     // inverse elasticity work buffers, allocated on the first call
     void *inv_buf = nullptr;

@@ -50,7 +50,7 @@ int inv_buffers(fo_ctx *c, int64_t ld, InvBufs *o)
             c->inv_cap = 0;
         }
         void *mem = nullptr;
-        if (hipMalloc(&mem, n_dbl * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
+        if (fo::device_malloc(&mem, n_dbl * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
         c->inv_buf = mem;
         c->inv_cap = n_dbl;
         c->allocations.push_back(mem);  // released by fo_destroy

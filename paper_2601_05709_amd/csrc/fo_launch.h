@@ -119,6 +119,7 @@ int launch_elas_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s);
 int launch_descent_apply_tiled(const fo_ctx *c, const double *x, double *y, hipStream_t s,
                                const int32_t *done = nullptr);
 int tiled_prepare(const fo_ctx *c);
+size_t tr_buffer_bytes(const fo_ctx *c);  // transport / reinitialisation work buffers
 int launch_descent_diag_tiled(const fo_ctx *c, double *diag, hipStream_t s);
 int launch_sd_rhs_tiled(const fo_ctx *c, double *rhs, hipStream_t s);
 int launch_phigrad_tiled(const fo_ctx *c, const double *phi, double *gbuf, hipStream_t s);

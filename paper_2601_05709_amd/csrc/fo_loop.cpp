@@ -180,17 +180,16 @@ int run_loop(fo_ctx *c, const fo_loop_opts *o, Model &m, double *phi, double *rh
 
 }  // namespace
 
-extern "C" {
+size_t fo::optimize_work_doubles(const fo_ctx *c) { return (size_t)(3 * c->ndof + 4); }
 
-int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, fo_loop_record *records,
-                int32_t *n_done, int32_t *stopped)
+// fo_optimize on caller-provided work vectors (optimize_work_doubles).
+int fo::optimize_on(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, fo_loop_record *records,
+                    int32_t *n_done, int32_t *stopped, double *work)
 {
-    if (!c || !o || !b || !phi || !records || !n_done || !stopped || !loop_opts_ok(o)) return FO_ERR_ARG;
+    if (!c || !o || !b || !phi || !records || !n_done || !stopped || !work || !loop_opts_ok(o)) return FO_ERR_ARG;
     *n_done = 0;
     *stopped = 0;
     const int64_t n = c->ndof;
-    double *work = nullptr;
-    if (hipMalloc(&work, (size_t)(3 * n + 4) * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
     double *u = work, *rhs = u + n, *theta = rhs + n, *scal = theta + n;  // scal: J, vol, B_tt
     const double Vd = o->V > 0.0 ? o->V : 1.0;
     Model m;
@@ -211,7 +210,19 @@ int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, 
         if (lambda == 0.0) return FO_OK;  // rhs holds the derivative without the constraint term
         return fo_shape_derivative(c, u, 1, 1, lambda, Vd, r, nullptr, scal, scal + 1);
     };
-    const int rc = run_loop(c, o, m, phi, rhs, theta, scal + 2, records, n_done, stopped);
+    return run_loop(c, o, m, phi, rhs, theta, scal + 2, records, n_done, stopped);
+}
+
+extern "C" {
+
+int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, fo_loop_record *records,
+                int32_t *n_done, int32_t *stopped)
+{
+    if (!c || !o || !b || !phi || !records || !n_done || !stopped || !loop_opts_ok(o)) return FO_ERR_ARG;
+    double *work = nullptr;
+    if (fo::device_malloc((void **)&work, fo::optimize_work_doubles(c) * sizeof(double)) != hipSuccess)
+        return FO_ERR_NOMEM;
+    const int rc = fo::optimize_on(c, o, b, phi, records, n_done, stopped, work);
     (void)hipFree(work);
     return rc;
 }
@@ -224,7 +235,8 @@ int fo_optimize_heat(fo_ctx *c, const fo_loop_opts *o, const uint8_t *gamma0, co
     *stopped = 0;
     const int64_t N = c->N, n = c->ndof;
     double *work = nullptr;
-    if (hipMalloc(&work, (size_t)(2 * N + 2 * n + 4) * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
+    if (fo::device_malloc((void **)&work, (size_t)(2 * N + 2 * n + 4) * sizeof(double)) != hipSuccess)
+        return FO_ERR_NOMEM;
     double *b = work, *u = b + N, *rhs = u + N, *theta = rhs + n, *scal = theta + n;  // scal: J, vol, B_tt
     const double Vd = o->V > 0.0 ? o->V : 1.0;
     int rc = fo_heat_load(c, f, b);  // the load does not depend on the level set
@@ -266,7 +278,7 @@ int fo_optimize_inverse(fo_ctx *cf, fo_ctx *cg, const fo_loop_opts *o, int32_t n
     const int64_t n = cf->ndof;
     double *work = nullptr;
     const size_t n_dbl = (size_t)(4 * n * ld + 2 * n + n_pairs + 1);
-    if (hipMalloc(&work, n_dbl * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
+    if (fo::device_malloc((void **)&work, n_dbl * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
     double *u = work, *v = u + n * ld, *p = v + n * ld, *q = p + n * ld, *rhs = q + n * ld, *theta = rhs + n,
            *Jd = theta + n, *btt = Jd + n_pairs;
     std::vector<double> Jk((size_t)n_pairs);

@@ -25,6 +25,10 @@
 #include "../../include/fo.h"
 #include "fo_wait.h"
 
+namespace fo {
+hipError_t device_malloc(void **p, size_t bytes);  // the library's counted allocation
+}
+
 namespace {
 
 using Clock = std::chrono::steady_clock;
@@ -111,7 +115,7 @@ void fo_pool::run(Slot &sl)
         int rc = FO_OK;
         if (hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking) != hipSuccess) rc = FO_ERR_HIP;
         if (rc == FO_OK) rc = fo_create(&r->ctx, &q.mesh, &q.mat, 1, r->stream);
-        if (rc == FO_OK && hipMalloc(&r->buf, buffer_bytes(q.mesh)) != hipSuccess) rc = FO_ERR_NOMEM;
+        if (rc == FO_OK && fo::device_malloc((void **)&r->buf, buffer_bytes(q.mesh)) != hipSuccess) rc = FO_ERR_NOMEM;
         if (rc == FO_OK) {
             const size_t actual = fo_footprint_bytes(r->ctx) + buffer_bytes(q.mesh);
             used = used + actual - std::min(used, r->bytes);

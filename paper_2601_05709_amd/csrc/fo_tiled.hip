@@ -1019,12 +1019,8 @@ int launch_phigrad_tiled(const fo_ctx *c, const double *phi, double *gbuf, hipSt
 template <typename T>
 static int up_vec(fo_ctx *c, T **dst, const std::vector<T> &src)
 {
-    size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return FO_ERR_NOMEM;
-    c->allocations.push_back(p);
-    c->bytes += bytes;
-    *dst = static_cast<T *>(p);
+    FO_TRY(ctx_alloc_n(c, dst, std::max<size_t>(src.size(), 1)));
+    void *p = *dst;
     if (!src.empty() &&
         hipMemcpyAsync(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess)
@@ -1049,13 +1045,7 @@ int upload_tiles(fo_ctx *c, const HostTiles &h)
         (rc = up_vec(c, &t.node_hrange, h.node_hrange)))
         return rc;
     // halo partials: widest op has d+1 values per node
-    size_t n = std::max<size_t>((size_t)t.n_shared_slots * (c->dim + 1), 1);
-    void *p = nullptr;
-    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) return FO_ERR_NOMEM;
-    c->allocations.push_back(p);
-    c->bytes += n * sizeof(double);
-    c->halo = static_cast<double *>(p);
-    return FO_OK;
+    return ctx_alloc_n(c, &c->halo, std::max<size_t>((size_t)t.n_shared_slots * (c->dim + 1), 1));
 }
 
 }  // namespace fo

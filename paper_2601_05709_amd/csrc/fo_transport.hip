@@ -267,18 +267,16 @@ struct TrBufs {
 // reinitialisation Lhat (its parameters at par + 8).
 enum { SYS_TRANSPORT = 0, SYS_REINIT = 1 };
 
+int64_t tr_doubles(const fo_ctx *c)
+{
+    const int64_t N = c->N;
+    return N * c->dim + 16 + 3 * N + N + 11 * N + 5 * (int64_t)kRedBlocks + (N + 7) / 8;
+}
+
 int tr_buffers(fo_ctx *c, TrBufs *o)
 {
     const int64_t N = c->N;
-    const int64_t n_dbl = N * c->dim + 16 + 3 * N + N + 11 * N + 5 * (int64_t)kRedBlocks + (N + 7) / 8;
-    if (!c->tr_buf) {
-        const size_t bytes = (size_t)n_dbl * sizeof(double) + sizeof(TrScal) + 256;
-        void *mem = nullptr;
-        if (hipMalloc(&mem, bytes) != hipSuccess) return FO_ERR_NOMEM;
-        c->tr_buf = mem;
-        c->allocations.push_back(mem);  // released by fo_destroy
-        c->bytes += bytes;
-    }
+    if (!c->tr_buf) return FO_ERR_STATE;
     double *m = reinterpret_cast<double *>(c->tr_buf);
     o->theta = m;
     m += N * c->dim;
@@ -302,6 +300,12 @@ int tr_buffers(fo_ctx *c, TrBufs *o)
     o->sc = reinterpret_cast<TrScal *>(m);
     return FO_OK;
 }
+
+}  // namespace
+
+size_t fo::tr_buffer_bytes(const fo_ctx *c) { return (size_t)tr_doubles(c) * sizeof(double) + sizeof(TrScal) + 256; }
+
+namespace {
 
 int sys_apply(const fo_ctx *c, const TrBufs &B, int sys, const double *x, double *y, hipStream_t s,
               const int32_t *stop = nullptr)

@@ -115,6 +115,7 @@ EXPORTS = {
                   C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int32)], C.c_int),
+    "fo_device_allocations": ([], C.c_int64),
     "fo_optimize_heat": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, _vp, C.POINTER(fo_loop_record),
                           C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "fo_optimize_inverse": ([_vp, _vp, C.POINTER(fo_loop_opts), C.c_int32, C.c_int64, _vp, _vp, C.c_double,
@@ -163,6 +164,11 @@ def lib():
             f.restype = res
         _lib = L
     return _lib
+
+
+def device_allocations() -> int:
+    """Device allocations the library has made in this process (fo_device_allocations)."""
+    return int(lib().fo_device_allocations())
 
 
 def status_string(s: int) -> str:

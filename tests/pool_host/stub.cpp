@@ -147,6 +147,7 @@ hipError_t hipMemcpyAsync(void *dst, const void *src, size_t bytes, hipMemcpyKin
 
 namespace fo {
 hipError_t wait_stream(hipStream_t s);
+hipError_t device_malloc(void **p, size_t bytes) { return hipMalloc(p, bytes); }
 }
 
 extern "C" {
