@@ -290,6 +290,23 @@ typedef struct {
 int fo_optimize(fo_ctx *ctx, const fo_loop_opts *opts, const double *b, double *phi,
                 fo_loop_record *records, int32_t *n_done, int32_t *stopped);
 
+/* fo_optimize for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that keep the allocator out of the
+ * request path): the same loop, with the same arguments and results, but its
+ * work vectors (3 n_dofs + 4 doubles) live in a static device array of the
+ * library (64 MiB per GPU, held from when the library is loaded on that GPU
+ * until the process ends) and no device memory is allocated: chunks of the
+ * solvers that have no captured graph on this context yet are launched
+ * directly instead of being captured.  The context must be one of fo_create
+ * (its velocity and transport arrays exist from creation).  n_dofs above
+ * FO_NOALLOC_MAX_DOFS: FO_ERR_ARG.  Every call on a GPU uses that GPU's one
+ * array, so calls that overlap on the same GPU (from several threads or
+ * contexts) race; calls one after another are independent (the loop
+ * initialises everything it reads).  Returns as fo_optimize. */
+enum { FO_NOALLOC_MAX_DOFS = 2796201 };
+int fo_optimize_noalloc(fo_ctx *ctx, const fo_loop_opts *opts, const double *b, double *phi,
+                        fo_loop_record *records, int32_t *n_done, int32_t *stopped);
+
 /* Reinitialisation of the level set (Section "Other implementation
  * aspects", eqs. Eikonal, HJ, grad_H, weak_HJ): `steps` pseudo-time steps up
  * to t_end (the paper's defaults: 8 steps, 0.1) of

@@ -115,6 +115,8 @@ EXPORTS = {
                   C.c_int),
     "fo_optimize": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int32)], C.c_int),
+    "fo_optimize_noalloc": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, C.POINTER(fo_loop_record),
+                             C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "fo_device_allocations": ([], C.c_int64),
     "fo_optimize_heat": ([_vp, C.POINTER(fo_loop_opts), _vp, _vp, _vp, C.POINTER(fo_loop_record),
                           C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
@@ -146,6 +148,7 @@ EXPORTS = {
 
 FO_PROF_ELAS_TILE_FP64, FO_PROF_ELAS_TILE_FP32, FO_PROF_HALO_FP64, FO_PROF_HALO_FP32 = 0, 1, 2, 3
 FO_KERNEL_CG_OP_FP64, FO_KERNEL_CG_OP_FP32, FO_KERNEL_BATCH_APPLY = 0, 1, 2
+FO_NOALLOC_MAX_DOFS = 2796201  # largest n_dofs of fo_optimize_noalloc (include/fo.h)
 
 _lib = None
 
@@ -485,10 +488,11 @@ class Context:
                  cost_tol=1e-2, lgrn_tol=1e-2, ctrn_tol=1e-2, ppl=(0.999, 0.5, 2000.0, 0.5),
                  state_opts: Optional[SolveOpts] = None, descent_opts: Optional[SolveOpts] = None,
                  transport_opts: Optional[SolveOpts] = None, reinit_step=0, reinit_pars=(8, 0.1),
-                 allow_not_converged=False):
+                 allow_not_converged=False, noalloc=False):
         """The level-set loop (fo_optimize): up to n_iter iterations of the
         paper's Algorithm 1 from phi (updated in place) with the load b;
-        V given: volume constraint vol / V = 1 by the PPL method.  Returns
+        V given: volume constraint vol / V = 1 by the PPL method.  noalloc:
+        the variant without device allocation (fo_optimize_noalloc).  Returns
         (records as dicts, stopped)."""
         import torch
         o = _loop_opts(n_iter, V, smooth, dfactor, lv_time, lv_iter, start_to_check, prev, cost_tol, lgrn_tol,
@@ -496,10 +500,11 @@ class Context:
                        n_dofs=self.n_dofs)
         recs = (fo_loop_record * max(1, int(n_iter)))()
         n_done, stopped = C.c_int32(0), C.c_int32(0)
-        rc = lib().fo_optimize(self.h, C.byref(o), _ptr(b, torch.float64, self.n_dofs, "b"),
-                               _ptr(phi, torch.float64, self.n_nodes, "phi"), recs, C.byref(n_done),
-                               C.byref(stopped))
-        _check(rc, "fo_optimize", (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
+        name = "fo_optimize_noalloc" if noalloc else "fo_optimize"
+        rc = getattr(lib(), name)(self.h, C.byref(o), _ptr(b, torch.float64, self.n_dofs, "b"),
+                                  _ptr(phi, torch.float64, self.n_nodes, "phi"), recs, C.byref(n_done),
+                                  C.byref(stopped))
+        _check(rc, name, (FO_OK, FO_NOT_CONVERGED) if allow_not_converged else (FO_OK,))
         return _records(recs, n_done.value), bool(stopped.value)
 
     def optimize_heat(self, gamma0, f, phi, n_iter: int, dopts: "DescentOpts", V: Optional[float] = None,
