@@ -454,11 +454,13 @@ int fo_time_kernel(fo_ctx *ctx, int32_t kernel, int32_t reps, double *avg_us);
  * multi-load compliance problem sums their derivatives (Section "Compliance
  * minimization", several loads) and the paper solves such PDE sets in its
  * task-parallel mode (Section "Parallelization").  Columns are processed in
- * blocks of up to 64; each block runs CG on all its columns at once, the
- * element contraction K_e X_e on the matrix cores in FP32, with the same FP64
- * residual replacement and stopping rule per column as the single-load
- * solve.  stats: iters_inner counts block iterations (one block operator
- * application each), summed over blocks; rel_res is the worst column.
+ * blocks of up to 64; each block is solved by the method of
+ * fo_set_batch_method (CG per column by default), the element contraction K_e X_e
+ * on the matrix cores in FP32, with FP64 residual replacement and the
+ * single-load solve's stopping rule per column.  stats: iters_inner counts
+ * block iterations (one block operator application each) plus the FP64 CG
+ * iterations of columns finished in FP64, summed over blocks; rel_res is the
+ * worst column.
  *
  * fo_batch_tune times the batched apply for every tile node cap that fits
  * the LDS and both element group sizes (elements with pairwise disjoint node
@@ -468,6 +470,23 @@ int fo_time_kernel(fo_ctx *ctx, int32_t kernel, int32_t reps, double *avg_us);
  * batch tiles (synchronises the stream) and needs a level set.  Errors:
  * FO_ERR_ARG without batch buffers or n_rhs out of [1, max_rhs]. */
 int fo_batch_tune(fo_ctx *ctx, int32_t n_rhs, int32_t *tile_nodes, int32_t *group, double *apply_us);
+
+/* Method of the batched solves (fo_state_solve with n_rhs > 1 and
+ * FO_FP32_IR).  FO_BATCH_COLUMN_CG (default): CG per column on the shared
+ * batched operator (a step length per column).  FO_BATCH_BLOCK_CG: block
+ * conjugate gradients (O'Leary): every iteration applies K to a block of
+ * directions, one per load case still running, and each case takes its best
+ * step in the span of the whole block (K-conjugate block directions, their
+ * s x s Gram matrix inverted in FP64 with numerically dependent directions
+ * dropped); a case leaves the block when its residual has fallen by the
+ * phase target (inner_rtol) and the block narrows 16 columns at a time.
+ * Phases restart from the FP64 residuals of the unconverged cases (FP64
+ * refinement, as the single-load path).  Both stop every column on the same
+ * FP64 criterion, so their results agree within the solve tolerance; which
+ * is faster depends on how independent the load cases are.  Errors:
+ * FO_ERR_ARG. */
+enum { FO_BATCH_BLOCK_CG = 0, FO_BATCH_COLUMN_CG = 1 };
+int fo_set_batch_method(fo_ctx *ctx, int32_t method);
 
 /* Y = K(phi) X for a block of load cases through the batched operator (FP32,
  * matrix cores): x, y device float [n_dofs][ncols], load case fastest; ncols

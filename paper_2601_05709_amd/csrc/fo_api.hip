@@ -1123,6 +1123,13 @@ int fo_time_kernel(fo_ctx *c, int32_t kernel, int32_t reps, double *avg_us)
                              reps, avg_us);
 }
 
+int fo_set_batch_method(fo_ctx *c, int32_t method)
+{
+    if (!c || (method != FO_BATCH_BLOCK_CG && method != FO_BATCH_COLUMN_CG)) return FO_ERR_ARG;
+    c->batch.method = method;
+    return FO_OK;
+}
+
 int fo_batch_tune(fo_ctx *c, int32_t n_rhs, int32_t *tile_nodes, int32_t *group, double *apply_us)
 {
     if (!c || n_rhs < 1 || n_rhs > c->max_rhs) return FO_ERR_ARG;

@@ -32,6 +32,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -809,6 +810,12 @@ static void launch_batch_apply(const fo_ctx *c, int NC, const float *P, float *Q
     }
 }
 
+void batch_apply_launch(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
+                        hipStream_t s)
+{
+    launch_batch_apply(c, NC, P, Q, ctl, cols, s);
+}
+
 // Dispatch on S = 16 NC for the node-parallel kernels.
 template <template <int> class K, class... A>
 static void by_s(int S, A... a)
@@ -932,7 +939,9 @@ void batch_release(fo_ctx *c)
     if (b.s2_host) (void)hipHostFree(b.s2_host);
     if (b.mask_host) (void)hipHostFree(b.mask_host);
     if (b.caps_host) (void)hipHostFree(b.caps_host);
+    if (b.bcg_host) (void)hipHostFree(b.bcg_host);
     b.caps_host = nullptr;
+    b.bcg_host = nullptr;
     b.ctl_host = nullptr;
     b.cols_host = nullptr;
     b.s2_host = nullptr;
@@ -1025,6 +1034,8 @@ static int build_batch_tiles(fo_ctx *c, int mn, int G, const std::vector<double>
     FO_TRY(bup(c, &ts.nodes, h.nodes));
     FO_TRY(bup(c, &ts.hpos, h.hpos));
     FO_TRY(bup(c, &ts.node_hrange, h.node_hrange));
+    FO_TRY(bup(c, &ts.halo_node, h.halo_node));
+    FO_TRY(bup(c, &ts.halo_ptr, h.halo_ptr));
     FO_TRY(bup(c, &b.selem, selem));
     FO_TRY(bup(c, &b.slconn, slconn));
     int32_t *sg = nullptr;
@@ -1082,12 +1093,17 @@ int batch_setup(fo_ctx *c, int max_rhs)
     FO_TRY(balloc(c, (void **)&b.caps, (size_t)b.S * sizeof(int32_t), false));
     FO_TRY(balloc(c, (void **)&b.cols, (size_t)b.S * sizeof(BatchCol), false));
     FO_TRY(balloc(c, (void **)&b.ctl, sizeof(BatchCtl), false));
+    FO_TRY(balloc(c, (void **)&b.bcg.st, sizeof(BcgState), false));
+    FO_TRY(balloc(c, (void **)&b.bcg.sums, (size_t)2 * b.S * b.S * sizeof(double), false));
+    FO_TRY(balloc(c, (void **)&b.bcg.part, bcg_part_floats(b.S) * sizeof(float), false));
     if (hipHostMalloc((void **)&b.ctl_host, sizeof(BatchCtl)) != hipSuccess ||
         hipHostMalloc((void **)&b.cols_host, b.S * sizeof(BatchCol)) != hipSuccess ||
         hipHostMalloc((void **)&b.s2_host, b.S * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&b.mask_host, b.S) != hipSuccess ||
-        hipHostMalloc((void **)&b.caps_host, b.S * sizeof(int32_t)) != hipSuccess)
+        hipHostMalloc((void **)&b.caps_host, b.S * sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&b.bcg_host, sizeof(BcgState)) != hipSuccess)
         return FO_ERR_NOMEM;
+    if (bcg_prepare()) return FO_ERR_HIP;
     // directions start at zero (the first direction of a column ignores them,
     // but stale non-finite bits must not survive a zero coefficient)
     launch_fill<float>(b.p32, n, 0.0f, c->stream);
@@ -1105,7 +1121,7 @@ int batch_setup(fo_ctx *c, int max_rhs)
 static void destroy_batch_graphs(fo_ctx *c)
 {
     for (auto it = c->graphs.begin(); it != c->graphs.end();) {
-        if (std::get<0>(it->first) >= 40 && std::get<0>(it->first) < 50) {
+        if (std::get<0>(it->first) >= 100 && std::get<0>(it->first) < 300) {  // batched solver families
             (void)hipGraphExecDestroy(it->second);
             it = c->graphs.erase(it);
         } else {
@@ -1336,7 +1352,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         if (it_total >= o->max_iter) break;
         if (!b.ctl_host->done) {
             const int32_t before = b.ctl_host->it;
-            auto key = std::make_tuple(40 + NC, chunk, b.version, 0);
+            auto key = std::make_tuple(100 + NC, chunk, b.version, 0);
             FO_TRY(graph_chunk(c, key, [&](hipStream_t ws) {
                 for (int j = 0; j < chunk; ++j) batch_iteration(c, NC, ws);
                 return (int)FO_OK;
@@ -1441,6 +1457,187 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
     return result;
 }
 
+// Block CG (O'Leary) on the columns of one block inside the FP64 residual
+// replacement: every phase restarts the block from the FP64 residuals of the
+// columns not yet converged, each scaled to unit norm, and runs block CG in
+// FP32 (fo_bcg.hip) until every column's residual fell by the phase target,
+// a column leaving the block when it gets there, or the phase reaches its
+// cap; then x64 += s x32 and r64 = b - K x64 in FP64 for the phase's
+// columns.  The block narrows (16 columns at a time) between chunks of
+// iterations as columns converge.  A column whose FP64 residual did not
+// fall in a phase is finished by FP64 CG on its residual equation.
+static int bcg_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t ld, const fo_solve_opts *o,
+                     fo_solve_stats *st)
+{
+    BatchState &b = c->batch;
+    hipStream_t s = c->stream;
+    const int NS = std::min(4, (n + 15) / 16);
+    const int S = 16 * NS;
+    const int64_t nd = c->ndof;
+    const int chunk = o->check_every > 0 ? o->check_every : 8;
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
+    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-2;
+    hipLaunchKernelGGL(k_batch_pack, dim3(grid_of(nd * S)), dim3(256), 0, s, b_in, ld, n, c->fixed, b.b64,
+                       S, nd);
+    launch_fill<double>(b.x64, nd * S, 0.0, s);
+    launch_fill<float>(b.x32, nd * S, 0.0f, s);
+    FO_HIP(hipMemcpyAsync(b.r64, b.b64, nd * S * sizeof(double), hipMemcpyDeviceToDevice, s));
+    {
+        std::vector<BatchCol> cols(S);
+        for (auto &col : cols) col = BatchCol{};  // not done: the apply runs while the block does
+        BatchCtl ctl{0, 0, o->max_iter, 0};
+        FO_HIP(hipMemcpyAsync(b.cols, cols.data(), S * sizeof(BatchCol), hipMemcpyHostToDevice, s));
+        FO_HIP(hipMemcpyAsync(b.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
+        FO_HIP(fo::wait_stream(s));
+    }
+    FO_TRY(residual_norms(c, S));
+    std::vector<double> bnorm(S), rn(S);
+    std::vector<int> conv(S, 0), status(S, FO_OK), outer(S, 0), fail(S, 0), finish64(S, 0);
+    for (int k = 0; k < S; ++k) {
+        bnorm[k] = rn[k] = std::sqrt(b.s2_host[k]);
+        conv[k] = k >= n || bnorm[k] == 0.0;
+    }
+    int64_t longest = 0;   // longest phase that reached its target
+    int result = FO_NOT_CONVERGED;
+    int32_t it_total = 0;
+    BcgState &h = *b.bcg_host;
+    while (true) {
+        int na = 0;
+        for (int k = 0; k < S; ++k) {
+            b.mask_host[k] = conv[k] ? 0 : 1;
+            na += b.mask_host[k];
+        }
+        if (na == 0) {
+            result = FO_OK;
+            break;
+        }
+        FO_TRY(poll_batch(c));
+        it_total = b.ctl_host->it;
+        if (it_total >= o->max_iter) break;
+        // phase start: R32 = R64 / ||R64||, X32 = 0 on the phase's columns
+        FO_HIP(hipMemcpyAsync(b.mask, b.mask_host, S, hipMemcpyHostToDevice, s));
+        by_s<RescaleL>(S, (const fo_ctx *)c, s);
+        // the phase's scales (k_batch_accumulate reads s2[0..S))
+        FO_HIP(hipMemcpyAsync(b.s2, b.s2 + S, S * sizeof(double), hipMemcpyDeviceToDevice, s));
+        std::memset(&h, 0, offsetof(BcgState, rr));
+        h.np = na;
+        h.first = 1;
+        h.cap = (int32_t)std::min<int64_t>(INT32_MAX / 2, longest > 0 ? std::max<int64_t>(2 * longest, 64)
+                                                                      : first_phase_cap(nd));
+        h.tol2 = phase_rtol * phase_rtol;
+        h.drop = kBcgDrop;
+        for (int q = 0, k = 0; q < 64; ++q) {
+            while (k < S && !b.mask_host[k]) ++k;
+            h.act[q] = (q < na) ? k++ : -1;
+        }
+        for (int k = 0; k < 64; ++k) h.run[k] = k < S ? b.mask_host[k] : 0;
+        FO_HIP(hipMemcpyAsync(b.bcg.st, &h, offsetof(BcgState, rr), hipMemcpyHostToDevice, s));
+        b.ctl_host->done = 0;
+        b.ctl_host->max_it = o->max_iter;
+        b.ctl_host->pad = na;
+        FO_HIP(hipMemcpyAsync(b.ctl, b.ctl_host, sizeof(BatchCtl), hipMemcpyHostToDevice, s));
+        int NP = (na + 15) / 16;
+        bcg_direction(c, b.bcg, NP, NS, s);
+        FO_HIP(hipGetLastError());
+        while (true) {
+            const int32_t before = b.ctl_host->it;
+            auto key = std::make_tuple(200 + 8 * NP + NS, chunk, b.version, 0);
+            FO_TRY(graph_chunk(c, key, [&](hipStream_t ws) {
+                for (int j = 0; j < chunk; ++j) bcg_iteration(c, b.bcg, NP, NS, ws);
+                return (int)FO_OK;
+            }));
+            FO_TRY(poll_batch(c));
+            if (b.ctl_host->done) break;
+            if (b.ctl_host->it == before) {
+                hipError_t e = hipGetLastError();
+                std::fprintf(stderr, "libfo: block CG chunk made no progress (%s)\n", hipGetErrorString(e));
+                return FO_ERR_HIP;
+            }
+            const int np2 = (b.ctl_host->pad + 15) / 16;
+            if (np2 >= 1 && np2 < NP) {  // narrower block: re-stride P for the next chunk
+                bcg_restride(c, 16 * NP, 16 * np2, s);
+                NP = np2;
+            }
+        }
+        FO_HIP(hipMemcpyAsync(&h, b.bcg.st, offsetof(BcgState, rr), hipMemcpyDeviceToHost, s));
+        FO_HIP(fo::wait_stream(s));
+        if (!h.capped && h.status == 0) longest = std::max<int64_t>(longest, h.it_phase);
+        // FP64 refinement of the phase's columns
+        hipLaunchKernelGGL(k_batch_accumulate, dim3(grid_of(nd * S)), dim3(256), 0, s, b.x64, b.x32, b.s2,
+                           b.mask, S, nd * S);
+        for (int k = 0; k < S; ++k) {
+            if (!b.mask_host[k]) continue;
+            launch_gather_col<double, double>(b.x64 + k, S, nd, c->t64, nullptr, s);
+            FO_TRY(elas_apply64(c, c->t64, c->q64, s));
+            hipLaunchKernelGGL(k_batch_residual_col, dim3(grid_of(nd)), dim3(256), 0, s, b.b64, c->q64,
+                               c->fixed, b.r64, S, k, nd);
+        }
+        FO_TRY(residual_norms(c, S));
+        for (int k = 0; k < S; ++k) {
+            if (!b.mask_host[k]) continue;
+            ++outer[k];
+            const double r = std::sqrt(b.s2_host[k]);
+            if (!(r == r)) {  // non-finite FP64 residual: the column fails
+                status[k] = FO_ERR_BREAKDOWN;
+                conv[k] = 1;
+                fail[k] = 1;
+                continue;
+            }
+            const bool stalled = !(r < 0.5 * rn[k]);
+            rn[k] = r;
+            if (r <= o->rtol * bnorm[k]) {
+                conv[k] = 1;
+            } else if (stalled) {  // FP32 makes no progress on this column: finish it in FP64
+                conv[k] = 1;
+                finish64[k] = 1;
+            } else if (outer[k] >= max_outer) {
+                conv[k] = 1;
+                fail[k] = 1;
+            }
+        }
+    }
+    // columns that FP32 cannot resolve: FP64 CG on their residual equation
+    int64_t extra = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!finish64[k]) continue;
+        launch_gather_col<double, double>(b.r64 + k, S, nd, c->t64, nullptr, s);
+        fo_solve_opts o2 = *o;
+        o2.rtol = o->rtol * bnorm[k] / rn[k];
+        fo_solve_stats s2st{};
+        const int rc = fp64_solve(c, c->t64, &o2, &s2st);
+        if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
+        extra += s2st.iters_inner;
+        hipLaunchKernelGGL(k_batch_add_col, dim3(grid_of(nd)), dim3(256), 0, s, b.x64, c->x64, S, k, nd);
+        launch_gather_col<double, double>(b.x64 + k, S, nd, c->t64, nullptr, s);
+        FO_TRY(elas_apply64(c, c->t64, c->q64, s));
+        hipLaunchKernelGGL(k_batch_residual_col, dim3(grid_of(nd)), dim3(256), 0, s, b.b64, c->q64, c->fixed,
+                           b.r64, S, k, nd);
+        FO_TRY(residual_norms(c, S));
+        rn[k] = std::sqrt(b.s2_host[k]);
+        ++outer[k];
+        if (rc == FO_ERR_BREAKDOWN) status[k] = FO_ERR_BREAKDOWN;
+        else if (!(rn[k] <= o->rtol * bnorm[k])) fail[k] = 1;
+    }
+    hipLaunchKernelGGL(k_batch_unpack, dim3(grid_of(nd * n)), dim3(256), 0, s, b.x64, S, n, u, ld, nd);
+    FO_HIP(fo::wait_stream(s));
+    double worst = 0.0;
+    int max_outer_seen = 0;
+    for (int k = 0; k < n; ++k) {
+        if (bnorm[k] > 0) worst = std::max(worst, rn[k] / bnorm[k]);
+        max_outer_seen = std::max(max_outer_seen, outer[k]);
+        if (fail[k] && result == FO_OK) result = FO_NOT_CONVERGED;
+    }
+    for (int k = 0; k < n; ++k)
+        if (status[k] == FO_ERR_BREAKDOWN) result = FO_ERR_BREAKDOWN;
+    if (st) {
+        st->status = result;
+        st->iters_inner += it_total + (int32_t)extra;
+        st->iters_outer = std::max(st->iters_outer, max_outer_seen);
+        st->rel_res = std::max(st->rel_res, worst);
+    }
+    return result;
+}
+
 int batch_solve(fo_ctx *c, const double *b, double *u, int n_rhs, int64_t ld, const fo_solve_opts *o,
                 fo_solve_stats *st)
 {
@@ -1448,7 +1645,8 @@ int batch_solve(fo_ctx *c, const double *b, double *u, int n_rhs, int64_t ld, co
     int worst = FO_OK;
     for (int c0 = 0; c0 < n_rhs; c0 += G) {
         const int n = std::min(G, n_rhs - c0);
-        int rc = batch_group(c, b + c0, u + c0, n, ld, o, st);
+        int rc = c->batch.method == FO_BATCH_COLUMN_CG ? batch_group(c, b + c0, u + c0, n, ld, o, st)
+                                                       : bcg_group(c, b + c0, u + c0, n, ld, o, st);
         if (rc < 0 && rc != FO_ERR_BREAKDOWN) return rc;
         if (rc != FO_OK && (worst == FO_OK || rc < worst)) worst = rc;
     }

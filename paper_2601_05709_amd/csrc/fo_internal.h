@@ -137,6 +137,33 @@ struct BatchCtl {
     int32_t pad;
 };
 
+// Device state of the block CG (one block of up to 64 load cases).
+constexpr int kBcgBlocks = 512;     // row blocks of its Gram products (fixed: deterministic sums)
+constexpr double kBcgDrop = 1e-5;   // relative pivot below which a block direction is dropped
+struct BcgState {
+    int32_t np;          // directions in the block P (columns >= np are zero)
+    int32_t first;       // the next direction kernel builds P = Z[:, act] (phase start)
+    int32_t status;      // 0 ok, FO_ERR_BREAKDOWN
+    int32_t it_phase;    // iterations of the current phase
+    int32_t cap;         // iteration cap of the phase
+    int32_t capped;      // the phase ended at its cap
+    int32_t pad[2];
+    double tol2;         // phase target of r.r per column (rescaled residuals)
+    double drop;         // relative pivot below which a direction is dropped
+    int32_t act[64];     // direction q was built from residual column act[q] (-1: none)
+    int32_t run[64];     // residual column still running in this phase
+    double rr[64];       // r.r of every column after the last update
+    double Gi[64 * 64];  // (P^T K P)^-1 on the kept directions (dropped ones zero)
+    float gam[64 * 64];  // Gamma [sp][S]
+    float del[64 * 64];  // Delta [sp][sp]
+};
+
+struct BcgBufs {
+    BcgState *st = nullptr;
+    double *sums = nullptr;   // Gram sums [sp*sp + sp*S] or [sp*S + S]
+    float *part = nullptr;    // per-block partials
+};
+
 // Buffers of the batched path: block vectors are [n_dofs][S] (column
 // fastest), S = 16 NC right-hand sides per block, NC = 1..4.
 struct BatchState {
@@ -171,6 +198,9 @@ struct BatchState {
     BatchCol *cols_host = nullptr;      // pinned [S]
     double *s2_host = nullptr;          // pinned [S]
     uint8_t *mask_host = nullptr;       // pinned [S]
+    BcgBufs bcg;                        // block CG
+    BcgState *bcg_host = nullptr;       // pinned copy (status, counts)
+    int method = FO_BATCH_COLUMN_CG;    // FO_BATCH_COLUMN_CG (default) or FO_BATCH_BLOCK_CG
 };
 
 struct DescentSetup {

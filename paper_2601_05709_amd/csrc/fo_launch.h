@@ -152,5 +152,13 @@ int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us);
 int batch_apply_block(fo_ctx *c, int NC, const float *X, float *Y);
 int batch_tune(fo_ctx *c, int n_rhs, int *best_nodes, int *best_group, double *best_us);
 int batch_max_nodes(int D, int S);
+void batch_apply_launch(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
+                        hipStream_t s);
+// block CG (fo_bcg.hip): buffers, phase-start direction, one iteration, block narrowing
+size_t bcg_part_floats(int S);
+int bcg_prepare();
+void bcg_direction(const fo_ctx *c, const BcgBufs &B, int NP, int NS, hipStream_t s);
+void bcg_iteration(const fo_ctx *c, const BcgBufs &B, int NP, int NS, hipStream_t s);
+void bcg_restride(const fo_ctx *c, int sp_from, int sp_to, hipStream_t s);
 
 }  // namespace fo

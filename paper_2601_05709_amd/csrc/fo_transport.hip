@@ -340,7 +340,7 @@ int tr_enqueue(fo_ctx *c, const TrBufs &B, int sys, int g)
 {
     for (int len = 32; len >= 1; len >>= 1)
         while (g >= len) {
-            auto key = std::make_tuple(40 + sys, len, (int)c->scatter, 0);
+            auto key = std::make_tuple(300 + sys, len, (int)c->scatter, 0);
             FO_TRY(graph_chunk(c, key, [&](hipStream_t s) { return tr_iterations(c, B, sys, len, s); }));
             g -= len;
         }

@@ -131,6 +131,7 @@ EXPORTS = {
     "fo_batch_tune": ([_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
                       C.c_int),
     "fo_apply_elasticity_batch": ([_vp, _vp, _vp, C.c_int32], C.c_int),
+    "fo_set_batch_method": ([_vp, C.c_int32], C.c_int),
     "fo_batch_stats": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "fo_tile_stats": ([_vp] + [C.POINTER(C.c_int64)] * 5, C.c_int),
@@ -148,6 +149,7 @@ EXPORTS = {
 
 FO_PROF_ELAS_TILE_FP64, FO_PROF_ELAS_TILE_FP32, FO_PROF_HALO_FP64, FO_PROF_HALO_FP32 = 0, 1, 2, 3
 FO_KERNEL_CG_OP_FP64, FO_KERNEL_CG_OP_FP32, FO_KERNEL_BATCH_APPLY = 0, 1, 2
+FO_BATCH_BLOCK_CG, FO_BATCH_COLUMN_CG = 0, 1
 FO_NOALLOC_MAX_DOFS = 2796201  # largest n_dofs of fo_optimize_noalloc (include/fo.h)
 
 _lib = None
@@ -349,6 +351,11 @@ class Context:
         _check(lib().fo_batch_tune(self.h, n_rhs, C.byref(nodes), C.byref(group), C.byref(us)),
                "fo_batch_tune")
         return nodes.value, group.value, us.value
+
+    def set_batch_method(self, method: int):
+        """Solver of the batched multi-load solves: FO_BATCH_COLUMN_CG (CG per
+        column, the default) or FO_BATCH_BLOCK_CG (block CG)."""
+        _check(lib().fo_set_batch_method(self.h, int(method)), "fo_set_batch_method")
 
     def batch_stats(self) -> dict:
         cols, nodes, group = C.c_int32(), C.c_int32(), C.c_int32()
