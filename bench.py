@@ -350,7 +350,7 @@ def phase_times(it):
     t, (ds,) = timed(lambda: c.descent_solve(it.dopts, it.rhs, it.theta, it.descent_opts, it.B_tt))
     out["descent_ms"] = 1e3 * t
     from paper_2601_05709_amd import fo
-    _, _, dt = fo.adaptive_dt(float(it.B_tt.item()))
+    _, _, dt = fo.time_steps(float(it.B_tt.item()))
     t, _ = timed(lambda: c.levelset_update(it.theta, dt, it.phi))
     out["update_ms"] = 1e3 * t
     out["total_ms"] = sum(v for k, v in out.items() if k.endswith("_ms"))
@@ -427,6 +427,10 @@ def main():
                     help="short run for profilers: the headline step only (one warm-up, one step)")
     ap.add_argument("--only", default=None, choices=["headline", "c2", "large"],
                     help="run one part alone (for profilers)")
+    ap.add_argument("--kernel-only", default=None, choices=["headline", "large"],
+                    help="for counter passes: build the workload's context and time its dominant kernel only "
+                         "(headline: the batched apply on 64x32x32 with 64 columns; large: the fused FP32 CG "
+                         "operator on 256x128x128), 20 launches")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 instance")
     ap.add_argument("--main-only", action="store_true",
                     help="no transport, reinitialisation, heat, inverse or loop measurements")
@@ -453,6 +457,21 @@ def main():
         K, W = 1, 1
     if args.only == "large":
         print(json.dumps(large_case()), flush=True)
+        return
+    if args.kernel_only:
+        if args.kernel_only == "headline":
+            cells, n_loads = c3_batched_size()
+            wk = fi.multi_load_3d(cells, n_loads, seed=3)
+            ctx = fo.Context.from_workload(wk, max_rhs=n_loads)
+            ctx.set_levelset(torch.from_numpy(wk.phi).cuda())
+            ctx.batch_tune(n_loads)
+            us = ctx.time_kernel(fo.FO_KERNEL_BATCH_APPLY, 20)
+        else:
+            wk = fi.cantilever_3d((256, 128, 128))
+            ctx = fo.Context.from_workload(wk)
+            ctx.set_levelset(torch.from_numpy(wk.phi).cuda())
+            us = ctx.time_kernel(fo.FO_KERNEL_CG_OP_FP32, 20)
+        print(json.dumps({"kernel_only": args.kernel_only, "avg_us": us}), flush=True)
         return
     result = {"metric": "solves/s and DOF-iters/s at rel. res 1e-8: batched FP32+refine vs plain FP64",
               "value": None, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": None,
@@ -496,7 +515,7 @@ def main():
         # the paper's transport step (Crank-Nicolson Petrov-Galerkin, BiCGStab)
         # with the velocity and adaptive final time of the last iteration, in
         # place of the one explicit update step of the timed iteration
-        _, tr_steps, tr_dt = fo.adaptive_dt(float(outs_ir[-1].B_tt.item()))
+        _, tr_steps, tr_dt = fo.time_steps(float(outs_ir[-1].B_tt.item()))
         phi_tr = it_ir.phi0.clone()
         it_ir.ctx.transport(it_ir.theta, tr_dt, tr_steps, phi_tr, fo.SolveOpts(rtol=1e-10))  # warm-up
         phi_tr.copy_(it_ir.phi0)

@@ -33,8 +33,7 @@
  *     (and re-tiles) them, so the caller may free them afterwards.
  *   - All per-iteration arrays (phi, b, u, rhs, theta, S1, J, ...) are DEVICE
  *     pointers owned by the caller.  They must not alias each other unless
- *     stated.  Nothing is retained after a call returns, except the velocity
- *     mask of fo_descent_opts (kept with the options, see there).
+ *     stated.  Nothing is retained after a call returns.
  *   - Unknowns are node-blocked: dof = node * dim + component.  Several right
  *     hand sides are stored RHS-contiguous: value (dof, k) at [dof * ld + k].
  *   - Element arrays are structure-of-arrays: conn[a * n_elems + e].
@@ -113,11 +112,12 @@ typedef struct {
                                   at most 64                                       */
     const double *boxes;       /* host [n_boxes][2*dim]: lo[0..d), hi[0..d)        */
     const uint8_t *fixed;      /* NULL, or device [n_dofs]: theta = 0 where set
-                                  (e.g. H^1_0 velocities); the context keeps the
-                                  pointer and reads the mask on every solve or
-                                  apply with these options: keep it allocated and
-                                  unchanged meanwhile (new contents need a new
-                                  pointer, which counts as new options)            */
+                                  (e.g. H^1_0 velocities); copied into the context
+                                  by the first solve or apply with these options
+                                  (the array may be freed afterwards); options are
+                                  new when any field or this pointer differs, so
+                                  new contents at the same address need a fresh
+                                  set-up (another pointer, or other options first) */
 } fo_descent_opts;
 
 typedef struct {
@@ -143,6 +143,24 @@ typedef struct {
 int fo_create(fo_ctx **out, const fo_mesh *mesh, const fo_material *mat, int32_t max_rhs,
               void *stream);
 int fo_destroy(fo_ctx *ctx);
+
+/* A context on a caller-owned device workspace (the library allocates no
+ * device memory for it).  fo_workspace_bytes returns the bytes such a context
+ * needs for this mesh, material and max_rhs on the current device: it runs
+ * the host part of fo_create (validation, tiles) and adds up the device
+ * arrays without touching the device; 0 for an invalid argument.
+ * fo_create_in is fo_create with every device array carved from ws (device
+ * pointer, 256-byte aligned, ws_bytes >= fo_workspace_bytes; FO_ERR_NOMEM if
+ * smaller, FO_ERR_ARG if misaligned or NULL); it still creates a private
+ * stream, events and small pinned host buffers.  The caller keeps ws
+ * allocated and otherwise unused until fo_destroy, and frees it afterwards.
+ * fo_footprint_bytes of such a context equals fo_workspace_bytes.  The
+ * per-iteration calls behave as on a fo_create context; fo_batch_tune
+ * returns FO_ERR_STATE (the batch tiles stay those built at creation), and
+ * the calls that allocate per call (inverse problem, loops) still do. */
+size_t fo_workspace_bytes(const fo_mesh *mesh, const fo_material *mat, int32_t max_rhs);
+int fo_create_in(fo_ctx **out, const fo_mesh *mesh, const fo_material *mat, int32_t max_rhs, void *stream,
+                 void *ws, size_t ws_bytes);
 
 /* Number of device allocations (hipMalloc) the library has made in this
  * process so far, for callers and tests that check that a sequence of calls
@@ -229,6 +247,17 @@ int fo_levelset_update(fo_ctx *ctx, const double *theta, double dt, double *phi)
  * FO_ERR_STATE (atomic scatter) or FO_ERR_ARG. */
 int fo_transport(fo_ctx *ctx, const double *theta, double dt, int32_t steps, int32_t smooth, double *phi,
                  const fo_solve_opts *opts, fo_solve_stats *stats);
+
+/* Final time and step count of the transport from B(theta, theta) (Section
+ * "Other implementation aspects", eqs. tend and steps, without the optional
+ * noise): t_end = dfactor / B_tt clamped to [t_min, t_max], steps = (s_max -
+ * s_min) ((t_end - t_min) / (t_max - t_min))^(1/6) + s_min clamped to [s_min,
+ * s_max] and rounded half to even, dt = t_end / steps (host outputs).  The
+ * loops use it for every iteration; fo_levelset_update takes its dt.  The
+ * paper's defaults: dfactor 1e-2, t in [1e-3, 1e-1], steps in [8, 16].
+ * Errors: FO_ERR_ARG. */
+int fo_time_steps(double B_tt, double dfactor, double t_min, double t_max, int32_t s_min, int32_t s_max,
+                  double *t_end, int32_t *steps, double *dt);
 
 /* Parameters of the level-set loop (fo_optimize).  The paper's defaults:
  * dfactor 1e-2, t in [1e-3, 1e-1], steps in [8, 16], smooth 0,

@@ -73,6 +73,10 @@ int ctx_alloc(fo_ctx *c, void **p, size_t bytes)
 {
     bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
     *p = nullptr;
+    if (c->measure) {
+        c->bytes += bytes;
+        return FO_OK;
+    }
     if (c->ws) {
         if (bytes > c->ws_cap - c->bytes) return FO_ERR_NOMEM;
         *p = c->ws + c->bytes;
@@ -603,7 +607,7 @@ bool descent_same(const fo_ctx *c, const fo_descent_opts *d)
 {
     const DescentSetup &s = c->descent;
     if (!s.valid || s.alpha != d->alpha || s.gamma_n != d->gamma_n || s.gamma_s != d->gamma_s ||
-        s.fixed != d->fixed)
+        s.fixed_src != d->fixed)
         return false;
     size_t nb = (size_t)std::max(0, d->n_boxes) * 2 * c->dim;
     if (s.boxes.size() != nb) return false;
@@ -622,7 +626,10 @@ int descent_prepare(fo_ctx *c, const fo_descent_opts *d)
     ds.alpha = d->alpha;
     ds.gamma_n = d->gamma_n;
     ds.gamma_s = d->gamma_s;
-    ds.fixed = d->fixed;
+    // the mask is copied: the caller's array is not read after this call
+    ds.fixed_src = d->fixed;
+    ds.fixed = d->fixed ? ds.mask_copy : nullptr;
+    if (d->fixed) FO_HIP(hipMemcpyAsync(ds.mask_copy, d->fixed, c->ndof, hipMemcpyDeviceToDevice, s));
     int nbx = std::max(0, d->n_boxes);
     ds.boxes.assign(d->boxes, d->boxes + (size_t)nbx * 2 * c->dim);
     if (nbx > 0) {
@@ -737,8 +744,13 @@ int fo_destroy(fo_ctx *c)
     return FO_OK;
 }
 
-int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t max_rhs,
-              void *stream)
+namespace {
+
+// fo_create, fo_create_in (ws: the caller's device workspace) and the dry run
+// of fo_workspace_bytes (measure: the same host work and allocation sequence,
+// no device call; *measured receives the bytes).
+int create_context(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t max_rhs, void *stream,
+                   void *ws, size_t ws_bytes, size_t *measured)
 {
     if (!out || !m || !mat) return FO_ERR_ARG;
     *out = nullptr;
@@ -761,6 +773,9 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         if (m->bfacets[k] < 0 || m->bfacets[k] >= N) return FO_ERR_MESH;
 
     fo_ctx *c = new fo_ctx();
+    c->measure = measured != nullptr;
+    c->ws = static_cast<char *>(ws);
+    c->ws_cap = ws ? ws_bytes : 0;
     c->dim = D;
     c->N = N;
     c->E = E;
@@ -771,19 +786,22 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
     c->mu = mat->E / (2.0 * (1.0 + mat->nu));
     c->lam = (D == 2 && mat->plane_stress) ? mat->E * mat->nu / (1.0 - mat->nu * mat->nu)
                                            : mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
-    (void)hipGetDevice(&c->device);
+    if (!c->measure) (void)hipGetDevice(&c->device);
     int rc = FO_OK;
     auto fail = [&](int code) {
         fo_destroy(c);
         return code;
     };
+    const bool live = !c->measure;  // device work (uploads, launches, streams)
 
     // element order: tiles along a Morton curve (identity if tiling is off)
     HostTiles ht;
     int cus = 256;
     {
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+            prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
     int tile_elems = tile_target_elems(D, E, cus);
@@ -844,6 +862,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
         if ((rc = dev_alloc(c, &ds.in0, E)) || (rc = dev_alloc(c, &ds.diag, n)) ||
             (rc = dev_alloc(c, &ds.dinv, n)) || (rc = dev_alloc(c, &ds.dinv32, n)) ||
             (rc = dev_alloc(c, &ds.rhs, n)) || (rc = dev_alloc(c, &ds.boxes_dev, (size_t)kMaxBoxes * 2 * D)) ||
+            (rc = dev_alloc(c, &ds.mask_copy, n)) ||
             (rc = fo::ctx_alloc(c, &c->tr_buf, tr_buffer_bytes(c))))
             return fail(rc);
     }
@@ -855,8 +874,8 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
     // shape-derivative partial sums: one row per RHS (+ volume)
     c->sd_part_cap = (int)std::min<int64_t>(((E + kBlock - 1) / kBlock) * (max_rhs + 1), INT32_MAX);
     if ((rc = dev_alloc(c, &c->sd_part, c->sd_part_cap))) return fail(rc);
-    if (hipHostMalloc((void **)&c->scal_host, 2 * sizeof(SolveScalars)) != hipSuccess ||
-        hipHostMalloc((void **)&c->red_host, 16 * sizeof(double)) != hipSuccess)
+    if (live && (hipHostMalloc((void **)&c->scal_host, 2 * sizeof(SolveScalars)) != hipSuccess ||
+                 hipHostMalloc((void **)&c->red_host, 16 * sizeof(double)) != hipSuccess))
         return fail(FO_ERR_NOMEM);
     std::vector<int32_t> bnode, bptr, bfac;
     if (m->n_bfacets > 0) {
@@ -889,7 +908,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
     }
     hipStream_t s = c->stream;
     auto up = [&](void *dst, const void *src, size_t bytes) {
-        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+        return live ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
     if (up(c->coords, m->coords, N * D * sizeof(double)) ||
         up(c->coords32, c32.data(), N * D * sizeof(float)) ||
@@ -916,9 +935,7 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
                 for (int q = 0; q < D; ++q) tx[(size_t)(t * MN + l) * D + q] = (float)(x[q] - o[q]);
             }
         }
-        if ((rc = dev_alloc(c, &c->tiles.tx32, tx.size())) ||
-            hipMemcpyAsync(c->tiles.tx32, tx.data(), tx.size() * sizeof(float), hipMemcpyHostToDevice, s) !=
-                hipSuccess)
+        if ((rc = dev_alloc(c, &c->tiles.tx32, tx.size())) || up(c->tiles.tx32, tx.data(), tx.size() * sizeof(float)))
             return fail(rc ? rc : FO_ERR_HIP);
     }
     // Boundary facets of the descent operator per tile node: a facet goes to
@@ -1041,15 +1058,44 @@ int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t ma
                 return fail(FO_ERR_HIP);
         }
     }
-    if ((rc = tiled_prepare(c))) return fail(rc);
-    if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess)
+    if (live && (rc = tiled_prepare(c))) return fail(rc);
+    if (live && (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
+                 hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
+                 hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess))
         return fail(FO_ERR_HIP);
-    if (max_rhs > 1 && tiled(c) && (rc = batch_setup(c, max_rhs))) return fail(rc);
-    if (fo::wait_stream(s) != hipSuccess) return fail(FO_ERR_HIP);
+    if (max_rhs > 1 && tiled(c) && (rc = batch_setup(c, max_rhs, m->coords, conn_t))) return fail(rc);
+    if (live && fo::wait_stream(s) != hipSuccess) return fail(FO_ERR_HIP);
+    if (measured) {
+        *measured = c->bytes;
+        fo_destroy(c);
+        return FO_OK;
+    }
     *out = c;
     return FO_OK;
+}
+
+}  // namespace
+
+int fo_create(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t max_rhs, void *stream)
+{
+    return create_context(out, m, mat, max_rhs, stream, nullptr, 0, nullptr);
+}
+
+size_t fo_workspace_bytes(const fo_mesh *m, const fo_material *mat, int32_t max_rhs)
+{
+    fo_ctx *c = nullptr;
+    size_t bytes = 0;
+    if (create_context(&c, m, mat, max_rhs, nullptr, nullptr, 0, &bytes) != FO_OK) return 0;
+    return bytes;
+}
+
+int fo_create_in(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32_t max_rhs, void *stream, void *ws,
+                 size_t ws_bytes)
+{
+    if (!out) return FO_ERR_ARG;
+    *out = nullptr;
+    if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes == 0) return FO_ERR_ARG;
+    return create_context(out, m, mat, max_rhs, stream, ws, ws_bytes, nullptr);
 }
 
 size_t fo_footprint_bytes(const fo_ctx *c) { return c ? c->bytes : 0; }
@@ -1076,7 +1122,7 @@ size_t fo_footprint_estimate(const fo_mesh *m)
     const size_t MN = std::min<size_t>((size_t)tile_max_nodes((int)D), (ME * N * 5) / (2 * E) + 16);
     b += T * (32 + ME * 16 + MN * 10) + N * 8 + N * 3 * 4;
     b += std::min(T * MN, (D + 1) * E) * (D + 1) * 8;
-    b += E + 3 * n * 8 + n * 4 + (size_t)kMaxBoxes * 2 * D * 8;  // velocity operator arrays
+    b += E + 3 * n * 8 + n * 4 + n + (size_t)kMaxBoxes * 2 * D * 8;  // velocity operator arrays
     b += (N * D + 16 * N + 16 + 5 * (size_t)kRedBlocks + N / 8 + 1) * 8 + 512;  // transport buffers
     b += 80 * 256;                                        // allocation rounding
     return b;

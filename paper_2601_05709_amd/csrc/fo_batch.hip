@@ -895,8 +895,8 @@ static void batch_iteration(const fo_ctx *c, int NC, hipStream_t s)
 // the tiles of its creation).
 static int balloc(fo_ctx *c, void **p, size_t bytes, bool tile)
 {
-    if (!tile || c->ws) return ctx_alloc(c, p, bytes);
-    bytes = std::max<size_t>(bytes, 1);
+    if (!tile || c->ws || c->measure) return ctx_alloc(c, p, bytes);
+    bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;  // counted as ctx_alloc counts
     void *v = nullptr;
     if (device_malloc(&v, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -913,7 +913,7 @@ template <typename T>
 static int bup(fo_ctx *c, T **dst, const std::vector<T> &v)
 {
     FO_TRY(balloc(c, (void **)dst, v.size() * sizeof(T), true));
-    if (!v.empty() && (hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream) !=
+    if (!c->measure && !v.empty() && (hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream) !=
                            hipSuccess ||
                        fo::wait_stream(c->stream) != hipSuccess))
         return FO_ERR_HIP;
@@ -1072,7 +1072,7 @@ static int mesh_host(fo_ctx *c, std::vector<double> &X, std::vector<int32_t> &co
 
 int batch_default_nodes(int D) { return D == 2 ? 256 : 160; }
 
-int batch_setup(fo_ctx *c, int max_rhs)
+int batch_setup(fo_ctx *c, int max_rhs, const double *coords, const std::vector<int32_t> &conn_t)
 {
     BatchState &b = c->batch;
     const int D = c->dim;
@@ -1096,25 +1096,26 @@ int batch_setup(fo_ctx *c, int max_rhs)
     FO_TRY(balloc(c, (void **)&b.bcg.st, sizeof(BcgState), false));
     FO_TRY(balloc(c, (void **)&b.bcg.sums, (size_t)2 * b.S * b.S * sizeof(double), false));
     FO_TRY(balloc(c, (void **)&b.bcg.part, bcg_part_floats(b.S) * sizeof(float), false));
-    if (hipHostMalloc((void **)&b.ctl_host, sizeof(BatchCtl)) != hipSuccess ||
-        hipHostMalloc((void **)&b.cols_host, b.S * sizeof(BatchCol)) != hipSuccess ||
-        hipHostMalloc((void **)&b.s2_host, b.S * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&b.mask_host, b.S) != hipSuccess ||
-        hipHostMalloc((void **)&b.caps_host, b.S * sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc((void **)&b.bcg_host, sizeof(BcgState)) != hipSuccess)
-        return FO_ERR_NOMEM;
-    if (bcg_prepare()) return FO_ERR_HIP;
-    // directions start at zero (the first direction of a column ignores them,
-    // but stale non-finite bits must not survive a zero coefficient)
-    launch_fill<float>(b.p32, n, 0.0f, c->stream);
-    launch_fill<float>(b.q32, n, 0.0f, c->stream);
-    if (batch_prepare_lds(D)) return FO_ERR_HIP;
-    std::vector<double> X;
-    std::vector<int32_t> conn;
-    FO_TRY(mesh_host(c, X, conn));
+    if (!c->measure) {
+        if (hipHostMalloc((void **)&b.ctl_host, sizeof(BatchCtl)) != hipSuccess ||
+            hipHostMalloc((void **)&b.cols_host, b.S * sizeof(BatchCol)) != hipSuccess ||
+            hipHostMalloc((void **)&b.s2_host, b.S * sizeof(double)) != hipSuccess ||
+            hipHostMalloc((void **)&b.mask_host, b.S) != hipSuccess ||
+            hipHostMalloc((void **)&b.caps_host, b.S * sizeof(int32_t)) != hipSuccess ||
+            hipHostMalloc((void **)&b.bcg_host, sizeof(BcgState)) != hipSuccess)
+            return FO_ERR_NOMEM;
+        if (bcg_prepare()) return FO_ERR_HIP;
+        // directions start at zero (the first direction of a column ignores them,
+        // but stale non-finite bits must not survive a zero coefficient)
+        launch_fill<float>(b.p32, n, 0.0f, c->stream);
+        launch_fill<float>(b.q32, n, 0.0f, c->stream);
+        if (batch_prepare_lds(D)) return FO_ERR_HIP;
+    }
+    // host copies of the mesh in the context's element order (for the tiles)
+    const std::vector<double> X(coords, coords + (size_t)c->N * D);
     const int mn = std::min(batch_default_nodes(D), batch_max_nodes(D, b.S));
-    FO_TRY(build_batch_tiles(c, mn, 8, X, conn));
-    FO_HIP(fo::wait_stream(c->stream));
+    FO_TRY(build_batch_tiles(c, mn, 8, X, conn_t));
+    if (!c->measure) FO_HIP(fo::wait_stream(c->stream));
     return FO_OK;
 }
 
@@ -1203,6 +1204,7 @@ int batch_apply_block(fo_ctx *c, int NC, const float *X, float *Y)
 // fastest apply.
 int batch_tune(fo_ctx *c, int n_rhs, int *best_nodes, int *best_group, double *best_us)
 {
+    if (c->ws) return FO_ERR_STATE;  // the tiles of a workspace context are the ones of its creation
     BatchState &b = c->batch;
     const int NC = std::min(4, std::max(1, (n_rhs + 15) / 16));
     const int S = 16 * NC;

@@ -211,7 +211,9 @@ struct DescentSetup {
     double *diag = nullptr;   // [n_dofs]
     double *dinv = nullptr;   // [n_dofs]
     float *dinv32 = nullptr;  // [n_dofs]
-    const uint8_t *fixed = nullptr;  // caller's mask (theta = 0 there), or null
+    const uint8_t *fixed = nullptr;  // the mask in use (theta = 0 there): mask_copy, or null
+    const uint8_t *fixed_src = nullptr;  // the caller's mask of the current options (identity only)
+    uint8_t *mask_copy = nullptr;    // [n_dofs] copy of the caller's mask, taken at set-up
     double *rhs = nullptr;    // [n_dofs] right-hand side with the masked entries zeroed
     double *boxes_dev = nullptr;  // [kMaxBoxes][2 dim] device copy of the boxes
 };
@@ -232,6 +234,7 @@ struct fo_ctx {
     std::vector<void *> allocations;   // everything hipMalloc'ed by this ctx
     char *ws = nullptr;                // caller's workspace (device), or null
     size_t ws_cap = 0;                 // its size
+    bool measure = false;              // dry run of fo_create: count the bytes, touch no device
 
     // mesh, tile element order (elem_perm[tile order] = input element id)
     double *coords = nullptr;          // [N][dim]

@@ -1,6 +1,8 @@
 // Host-side launch wrappers of the kernels in fo_kernels.hip / fo_tiled.hip.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -143,7 +145,7 @@ int heat_cg_solve(fo_ctx *c, const uint8_t *fixed, const double *b, const double
 int64_t first_phase_cap(int64_t n);
 
 // batched multi-load path (fo_batch.hip)
-int batch_setup(fo_ctx *c, int max_rhs);
+int batch_setup(fo_ctx *c, int max_rhs, const double *coords, const std::vector<int32_t> &conn_t);
 int batch_levelset(fo_ctx *c);
 void batch_release(fo_ctx *c);
 int batch_solve(fo_ctx *c, const double *b, double *u, int n_rhs, int64_t ld, const fo_solve_opts *o,

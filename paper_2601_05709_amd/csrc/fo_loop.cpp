@@ -215,6 +215,25 @@ int fo::optimize_on(fo_ctx *c, const fo_loop_opts *o, const double *b, double *p
 
 extern "C" {
 
+int fo_time_steps(double B_tt, double dfactor, double t_min, double t_max, int32_t s_min, int32_t s_max,
+                  double *t_end, int32_t *steps, double *dt)
+{
+    if (!t_end || !steps || !dt || !(dfactor > 0.0) || !(t_min > 0.0) || !(t_max > t_min) || s_min < 1 ||
+        s_max < s_min || !(B_tt == B_tt))
+        return FO_ERR_ARG;
+    fo_loop_opts o{};
+    o.dfactor = dfactor;
+    o.t_min = t_min;
+    o.t_max = t_max;
+    o.s_min = s_min;
+    o.s_max = s_max;
+    int s = 0;
+    time_steps(B_tt, o, t_end, &s);
+    *steps = s;
+    *dt = *t_end / s;
+    return FO_OK;
+}
+
 int fo_optimize(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, fo_loop_record *records,
                 int32_t *n_done, int32_t *stopped)
 {

@@ -1021,7 +1021,7 @@ static int up_vec(fo_ctx *c, T **dst, const std::vector<T> &src)
 {
     FO_TRY(ctx_alloc_n(c, dst, std::max<size_t>(src.size(), 1)));
     void *p = *dst;
-    if (!src.empty() &&
+    if (!c->measure && !src.empty() &&
         hipMemcpyAsync(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess)
         return FO_ERR_HIP;

@@ -91,6 +91,9 @@ class fo_pool_result(C.Structure):
 
 EXPORTS = {
     "fo_create": ([C.POINTER(_vp), C.POINTER(fo_mesh), C.POINTER(fo_material), C.c_int32, _vp], C.c_int),
+    "fo_create_in": ([C.POINTER(_vp), C.POINTER(fo_mesh), C.POINTER(fo_material), C.c_int32, _vp, _vp, C.c_size_t],
+                     C.c_int),
+    "fo_workspace_bytes": ([C.POINTER(fo_mesh), C.POINTER(fo_material), C.c_int32], C.c_size_t),
     "fo_destroy": ([_vp], C.c_int),
     "fo_footprint_bytes": ([_vp], C.c_size_t),
     "fo_set_scatter": ([_vp, C.c_int32], C.c_int),
@@ -145,6 +148,8 @@ EXPORTS = {
     "fo_pool_stats": ([_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "fo_pool_destroy": ([_vp], C.c_int),
     "fo_status_string": ([C.c_int], C.c_char_p),
+    "fo_time_steps": ([C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                       C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
 }
 
 FO_PROF_ELAS_TILE_FP64, FO_PROF_ELAS_TILE_FP32, FO_PROF_HALO_FP64, FO_PROF_HALO_FP32 = 0, 1, 2, 3
@@ -256,7 +261,10 @@ class Context:
     """One mesh + material resident on the GPU (fo_create / fo_destroy)."""
 
     def __init__(self, dim, coords, conn, fixed=None, bfacets=None, bnormal=None, E=1.0, nu=0.3,
-                 plane_stress=1, ersatz=1e-3, max_rhs=1, stream=None):
+                 plane_stress=1, ersatz=1e-3, max_rhs=1, stream=None, workspace=False):
+        """workspace: the context's device arrays are carved from one caller-owned
+        buffer of fo_workspace_bytes bytes (a torch tensor held here; fo_create_in)
+        instead of allocated by the library (fo_create)."""
         L = lib()
         self.dim = int(dim)
         self._coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -277,19 +285,30 @@ class Context:
         mat = fo_material(E, nu, int(plane_stress), ersatz)
         h = C.c_void_p()
         self.stream = stream if stream is not None else current_stream()
-        _check(L.fo_create(C.byref(h), C.byref(m), C.byref(mat), self.max_rhs, self.stream), "fo_create")
+        self.ws = None
+        if workspace:
+            import torch
+            nb = int(L.fo_workspace_bytes(C.byref(m), C.byref(mat), self.max_rhs))
+            if nb == 0:
+                raise FoError(FO_ERR_ARG, "fo_workspace_bytes")
+            self.ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            _check(L.fo_create_in(C.byref(h), C.byref(m), C.byref(mat), self.max_rhs, self.stream,
+                                  C.c_void_p(self.ws.data_ptr()), nb), "fo_create_in")
+        else:
+            _check(L.fo_create(C.byref(h), C.byref(m), C.byref(mat), self.max_rhs, self.stream), "fo_create")
         self.h = h
 
     @classmethod
-    def from_workload(cls, w, max_rhs=None, stream=None):
+    def from_workload(cls, w, max_rhs=None, stream=None, workspace=False):
         m = w.mesh
         return cls(m.dim, m.coords, m.conn, w.fixed, m.bfacets, m.bnormal, w.E, w.nu, w.plane_stress,
-                   w.ersatz, max_rhs or w.n_rhs, stream)
+                   w.ersatz, max_rhs or w.n_rhs, stream, workspace)
 
     def close(self):
         if getattr(self, "h", None):
             lib().fo_destroy(self.h)
             self.h = None
+        self.ws = None  # the workspace outlives the context it backs
 
     def __del__(self):
         try:
@@ -592,14 +611,10 @@ def _records(recs, n):
     return out
 
 
-def adaptive_dt(B_tt: float, dfactor=1e-2, t_range=(1e-3, 1e-1), s_range=(8, 16)):
-    """Time step of one explicit level-set step from the adaptive rule of the
-    paper (Section "Other implementation aspects", eqs. tend and steps, no
-    noise): t_end = dfactor / B(theta,theta) clipped to t_range; the step count
-    s from the concave rule, clipped to s_range and rounded; dt = t_end / s."""
-    tmin, tmax = t_range
-    smin, smax = s_range
-    t_end = min(max(dfactor / max(float(B_tt), 1e-300), tmin), tmax)
-    s = (smax - smin) * ((t_end - tmin) / (tmax - tmin)) ** (1.0 / 6.0) + smin
-    s = int(round(min(max(s, smin), smax)))
-    return t_end, s, t_end / s
+def time_steps(B_tt: float, dfactor=1e-2, t_range=(1e-3, 1e-1), s_range=(8, 16)):
+    """(t_end, steps, dt) of the transport from B(theta, theta) (fo_time_steps)."""
+    t_end, steps, dt = C.c_double(), C.c_int32(), C.c_double()
+    _check(lib().fo_time_steps(float(B_tt), float(dfactor), float(t_range[0]), float(t_range[1]),
+                               int(s_range[0]), int(s_range[1]), C.byref(t_end), C.byref(steps), C.byref(dt)),
+           "fo_time_steps")
+    return t_end.value, steps.value, dt.value

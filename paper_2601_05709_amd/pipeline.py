@@ -2,8 +2,8 @@
 
 The steps follow the paper's level-set algorithm (Section "Main algorithm"):
 state solve -> compliance and shape derivative -> velocity (descent) solve ->
-level-set transport.  Every step is a libfo call on device tensors; this file
-only sequences them and picks the explicit time step on the host.
+level-set transport.  Every step is a libfo call on device tensors (the time
+step of the update included, fo_time_steps); this file only sequences them.
 """
 from __future__ import annotations
 
@@ -65,6 +65,6 @@ class Iteration:
         ds = c.descent_solve(self.dopts, self.rhs, self.theta, self.descent_opts, self.B_tt)
         dt = 0.0
         if update:
-            _, _, dt = fo.adaptive_dt(float(self.B_tt.item()))
+            _, _, dt = fo.time_steps(float(self.B_tt.item()))
             c.levelset_update(self.theta, dt, self.phi)
         return IterationOut(self.u, self.rhs, self.theta, self.J, self.vol, self.B_tt, dt, st, ds)

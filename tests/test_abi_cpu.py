@@ -105,9 +105,57 @@ def test_descent_opts_layout_and_defaults():
         assert d.n_boxes == 0 and not d.boxes and not d.fixed
 
 
-def test_adaptive_dt_matches_oracle_rule():
+def test_time_steps_match_oracle_rule():
     """The product's host-side time-step rule and the oracle's agree."""
     import oracle as oc
     from paper_2601_05709_amd import fo
     for B in (1e-9, 0.01, 0.3, 1.0, 7.0, 1e9):
-        assert fo.adaptive_dt(B) == pytest.approx(oc.adaptive_dt(B), rel=1e-15)
+        assert fo.time_steps(B) == pytest.approx(oc.adaptive_dt(B), rel=1e-15)
+
+
+def test_workspace_bytes_on_the_host(lib):
+    """fo_workspace_bytes runs fo_create's host part only: it works without a
+    GPU, grows with the mesh and with the load-case block, and is 0 for an
+    invalid mesh."""
+    import fo_inputs as fi
+    from paper_2601_05709_amd import fo
+
+    def wsb(w, max_rhs=1, conn=None):
+        m = w.mesh
+        coords = np.ascontiguousarray(m.coords)
+        cn = np.ascontiguousarray(m.conn if conn is None else conn, dtype=np.int32)
+        bf = np.ascontiguousarray(m.bfacets, dtype=np.int32)
+        bn = np.ascontiguousarray(m.bnormal)
+        fx = np.ascontiguousarray(w.fixed, dtype=np.uint8)
+        mesh = fo.fo_mesh(m.dim, m.n_nodes, m.n_elems, coords.ctypes.data, cn.ctypes.data, fx.ctypes.data,
+                          int(bf.shape[1]), bf.ctypes.data, bn.ctypes.data)
+        mat = fo.fo_material(w.E, w.nu, w.plane_stress, w.ersatz)
+        return lib.fo_workspace_bytes(C.byref(mesh), C.byref(mat), max_rhs)
+
+    small, big = fi.cantilever_3d((8, 4, 4)), fi.cantilever_3d((16, 8, 8))
+    a, b = wsb(small), wsb(big)
+    assert 0 < a < b and a % 256 == 0
+    assert wsb(small, 20) > a
+    # the same as the estimate used for admission, to the estimate's accuracy
+    m = big.mesh
+    est = lib.fo_footprint_estimate(C.byref(fo.fo_mesh(m.dim, m.n_nodes, m.n_elems, m.coords.ctypes.data,
+                                                       np.ascontiguousarray(m.conn, dtype=np.int32).ctypes.data,
+                                                       None, int(m.bfacets.shape[1]),
+                                                       np.ascontiguousarray(m.bfacets, dtype=np.int32).ctypes.data,
+                                                       np.ascontiguousarray(m.bnormal).ctypes.data)))
+    assert 0.5 * est <= b <= 1.5 * est
+    bad = np.array(small.mesh.conn, dtype=np.int32)
+    bad[0, 0] = small.mesh.n_nodes  # out of range
+    assert wsb(small, 1, bad) == 0
+
+
+def test_time_steps_interior_value_and_errors(lib):
+    """B(theta, theta) = 2 with the paper's defaults: t_end = 0.005 and
+    8 (4/99)^(1/6) + 8 = 12.686 -> 13 steps (by hand)."""
+    from paper_2601_05709_amd import fo
+    t, s, dt = fo.time_steps(2.0)
+    assert t == 0.005 and s == 13 and dt == pytest.approx(0.005 / 13, rel=1e-15)
+    with pytest.raises(fo.FoError):
+        fo.time_steps(1.0, dfactor=0.0)
+    with pytest.raises(fo.FoError):
+        fo.time_steps(1.0, s_range=(8, 4))
