@@ -264,6 +264,17 @@ def headline_case(K, W, fp64_steps):
         errs.append(float(torch.linalg.norm(u_ir[:, k] - uref) / nr))
         errs64.append(float(torch.linalg.norm(it64.u[:, k] - uref) / nr))
     err_rhs = float(torch.linalg.norm(rhs_ir - it64.rhs) / torch.linalg.norm(it64.rhs))
+    # the batched solves at rel. res 1e-9: the tolerance at which the
+    # displacement error meets 1e-8 (a 1e-8 residual leaves errors up to a few
+    # 1e-8 on this ill-conditioned operator)
+    it.ctx.set_levelset(it.phi0)
+    u9 = torch.zeros_like(it.u)
+    o9 = fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-9)
+    t_9, (s9,) = timed(lambda: it.ctx.state_solve(it.b, u9, o9, n_rhs=n_loads))
+    errs9 = []
+    for k in ref_cols:
+        it64.ctx.state_solve(bcol[:, k].contiguous(), uref, fo.SolveOpts(precision=fo.FO_FP64, rtol=1e-12))
+        errs9.append(float(torch.linalg.norm(u9[:, k] - uref) / torch.linalg.norm(uref)))
     # the state solves alone: batched, plain FP64 column by column, and the
     # single-load FP32 + refinement path column by column
     b = it.b
@@ -317,7 +328,9 @@ def headline_case(K, W, fp64_steps):
         "accuracy": {"reference": "GPU FP64 CG to rel. res 1e-12 on 8 of the 64 columns",
                      "max_rel_err_u_batched": max(errs), "max_rel_err_u_fp64": max(errs64),
                      "target": 1e-8, "batched_meets_target": max(errs) <= 1e-8,
-                     "rel_diff_rhs_batched_vs_fp64": err_rhs},
+                     "rel_diff_rhs_batched_vs_fp64": err_rhs,
+                     "at_rel_res_1e-9": {"solves_per_s": n_loads / t_9, "seconds": t_9, "block_iters": s9.iters_inner,
+                                         "max_rel_err_u": max(errs9), "meets_target": max(errs9) <= 1e-8}},
         "solves_only": {"batched_s": t_b, "batched_solves_per_s": n_loads / t_b, "block_iters": sb.iters_inner,
                         "fp32_ir_columnwise_s": t_c, "fp32_ir_columnwise_solves_per_s": n_loads / t_c,
                         "fp32_ir_columnwise_mean_iters": its_c / n_loads,
@@ -507,6 +520,10 @@ def main():
     t_64, outs_64 = run_steps(it_64, K2)
     st64 = outs_64[-1].state_stats
     log("c2 FP64: %.3f s/step, state %d its, rel.res %.2e" % (t_64 / K2, st64.iters_inner, st64.rel_res))
+    if args.only == "c2":  # for profilers: the c2 iterations only
+        print(json.dumps({"only": "c2", "ir_ms_per_step": 1e3 * t_ir / K2, "fp64_ms_per_step": 1e3 * t_64 / K2}),
+              flush=True)
+        return
 
     def extras():
         """The measurements besides the timed iteration: the paper's transport
