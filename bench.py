@@ -438,8 +438,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="short run for profilers: the headline step only (one warm-up, one step)")
-    ap.add_argument("--only", default=None, choices=["headline", "c2", "large"],
-                    help="run one part alone (for profilers)")
+    ap.add_argument("--only", default=None, choices=["headline", "c2", "extras", "large"],
+                    help="run one part alone (for profilers; extras: the single-load iteration and the "
+                         "transport, reinitialisation, heat, inverse and loop measurements)")
     ap.add_argument("--kernel-only", default=None, choices=["headline", "large"],
                     help="for counter passes: build the workload's context and time its dominant kernel only "
                          "(headline: the batched apply on 64x32x32 with 64 columns; large: the fused FP32 CG "
@@ -751,6 +752,9 @@ def main():
         }
 
     extra = {} if args.main_only else extras()
+    if args.only == "extras":
+        print(json.dumps({"only": "extras", **extra}), flush=True)
+        return
 
     # agreement of the two precisions (both at rel. res 1e-8)
     u_ir = it_ir.u[:, 0].double()
