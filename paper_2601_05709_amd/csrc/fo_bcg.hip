@@ -204,18 +204,32 @@ __device__ void bcg_inverse(const double *__restrict__ gsum, int sp, int np, dou
         }
         __syncthreads();
         if (j < sp) {
+            // the wave's 16 rows: all loads first, then the updates, then the stores
             const double rj = live ? rk[j] : 0.0;
-            for (int i = w; i < sp; i += 4) {
-                double &x = A[i * sp + j];
+            double v[16], cv[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = w + 4 * r;
+                v[r] = i < sp ? A[i * sp + j] : 0.0;
+                cv[r] = (live && i < sp) ? ck[i] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = w + 4 * r;
                 if (!live) {
-                    if (i == k || j == k) x = 0.0;
+                    if (i == k || j == k) v[r] = 0.0;
                 } else if (i == k) {
-                    x = rj;
+                    v[r] = rj;
                 } else if (j == k) {
-                    x = -ck[i] * inv;
+                    v[r] = -cv[r] * inv;
                 } else {
-                    x -= ck[i] * rj;
+                    v[r] -= cv[r] * rj;
                 }
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = w + 4 * r;
+                if (i < sp) A[i * sp + j] = v[r];
             }
         }
         if (tid == 0 && live) *nlive += 1;
