@@ -329,3 +329,36 @@ def test_ir_finishes_in_fp64_when_fp32_stagnates():
     K, *_ = oracle_K(w)
     u_ref, _ = K.solve(w.b, w.fixed, rtol=1e-12)
     assert rel(u.cpu().numpy(), u_ref) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["2d_37x19", "3d_12x6x6"])
+def test_element_coef_on_exact_zero_means(name):
+    """A_e and chi_e where the vertex mean of phi is exactly 0 (Section 2,
+    material where phi < 0, strictly): phi takes small integer values, so every
+    vertex sum is exact in either order and both sides decide on the same
+    number.  A flipped element changes vol by |T_e| and the apply by a factor
+    1/ersatz on its rows, far above the 1e-13 rounding bars."""
+    w = WORKLOADS[name]()
+    m = w.mesh
+    phi = np.random.default_rng(8).integers(-3, 4, size=m.n_nodes).astype(np.float64)
+    sums = phi[m.conn].sum(axis=0)
+    assert (sums == 0).sum() > m.n_elems // 20, "workload has too few exact-zero means"
+    w.phi = phi
+    K, A, chi, lam, mu = oracle_K(w)
+    assert np.all(chi[sums == 0] == 0.0) and np.all(A[sums == 0] == w.ersatz)
+    ctx = fo.Context.from_workload(w, max_rhs=1)
+    ctx.set_levelset(dev(phi))
+    x = np.random.default_rng(9).standard_normal(m.n_dofs)
+    x[w.fixed == 1] = 0.0
+    y = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    ctx.apply_elasticity(dev(x), y)
+    ref = K.matvec(x)
+    ref[w.fixed == 1] = 0.0
+    assert relmax(y.cpu().numpy(), ref) < 1e-13
+    U = np.zeros((m.n_dofs, 1))
+    rhs = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    vol = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.shape_derivative(dev(U), rhs, J, vol, n_rhs=1)
+    _, _, _, vol_ref = oc.shape_derivative(m.dim, m.coords, m.conn, A, chi, lam, mu, U)
+    assert vol.item() == pytest.approx(vol_ref, rel=1e-13)
