@@ -517,6 +517,21 @@ int fo_batch_tune(fo_ctx *ctx, int32_t n_rhs, int32_t *tile_nodes, int32_t *grou
 enum { FO_BATCH_BLOCK_CG = 0, FO_BATCH_COLUMN_CG = 1 };
 int fo_set_batch_method(fo_ctx *ctx, int32_t method);
 
+/* Operator of the batched solves and of fo_apply_elasticity_batch; both
+ * compute K(phi) X in FP32 on the matrix cores for every column at once.
+ * FO_BATCH_OP_NODAL (default): K(phi) assembled per level set (in
+ * fo_set_levelset) into d x d blocks K_ij, one per pair of distinct nodes
+ * sharing an element (FP64 sums of the element entries of Section
+ * "Compliance minimization", rounded once to FP32, exactly symmetric), and
+ * applied as y_i = sum_{j != i} K_ij (x_j - x_i) (rows of K(phi) sum to zero);
+ * memory: N NB (4 + 4 d^2) bytes, NB the largest neighbour count rounded up to
+ * a multiple of 4.  FO_BATCH_OP_ELEMENT: the element contraction
+ * K_e[:, b >= 1] (X_b - X_0) per element tile, node rows summed in LDS and a
+ * halo (what fo_batch_tune tunes).  The two agree to FP32 rounding.  Takes
+ * effect at the next solve or apply.  Errors: FO_ERR_ARG. */
+enum { FO_BATCH_OP_NODAL = 0, FO_BATCH_OP_ELEMENT = 1 };
+int fo_set_batch_operator(fo_ctx *ctx, int32_t op);
+
 /* Y = K(phi) X for a block of load cases through the batched operator (FP32,
  * matrix cores): x, y device float [n_dofs][ncols], load case fastest; ncols
  * a multiple of 16 up to the context's column block width (fo_batch_stats).

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libfo.so")
 ARCH = os.environ.get("FO_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fo_api.hip", "fo_kernels.hip", "fo_tiled.hip", "fo_cg.hip", "fo_batch.hip", "fo_bcg.hip", "fo_transport.hip",
-           "fo_inverse.hip", "fo_static.hip", "fo_pool.cpp", "fo_fiber.cpp", "fo_tiles.cpp", "fo_loop.cpp"]
+           "fo_inverse.hip", "fo_static.hip", "fo_nodal.hip", "fo_pool.cpp", "fo_fiber.cpp", "fo_tiles.cpp", "fo_loop.cpp"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

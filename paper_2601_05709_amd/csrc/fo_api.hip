@@ -1176,6 +1176,13 @@ int fo_set_batch_method(fo_ctx *c, int32_t method)
     return FO_OK;
 }
 
+int fo_set_batch_operator(fo_ctx *c, int32_t op)
+{
+    if (!c || (op != FO_BATCH_OP_NODAL && op != FO_BATCH_OP_ELEMENT)) return FO_ERR_ARG;
+    c->batch.op = op;
+    return FO_OK;
+}
+
 int fo_batch_tune(fo_ctx *c, int32_t n_rhs, int32_t *tile_nodes, int32_t *group, double *apply_us)
 {
     if (!c || n_rhs < 1 || n_rhs > c->max_rhs) return FO_ERR_ARG;

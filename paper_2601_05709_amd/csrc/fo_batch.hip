@@ -36,6 +36,7 @@
 #include <cstring>
 #include <vector>
 
+#include "fo_batch_dev.h"
 #include "fo_element.h"
 #include "fo_internal.h"
 #include "fo_launch.h"
@@ -44,8 +45,6 @@
 #include "fo_xcd.h"
 
 namespace fo {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBatchKB = 32;          // elements per K_e batch held in LDS
 constexpr int kBatchLds = 163840;     // LDS per workgroup on gfx950
@@ -175,19 +174,7 @@ __global__ __launch_bounds__(64 * NC) void k_batch_apply(
     const int tid = threadIdx.x;
     const int t = xcd_tile(blockIdx.x, ta.n_tiles);
     if (t < 0) return;
-    if (tid == 0) {
-        int stop = ctl->done;
-        if (!stop) {
-            stop = ctl->it >= ctl->max_it;
-            if (!stop) {
-                int all = 1;
-                for (int k = 0; k < S; ++k) all &= cols[k].done;
-                stop = all;
-            }
-            if (stop && blockIdx.x == 0) ctl->done = 1;
-        }
-        s_stop = stop;
-    }
+    if (tid == 0) s_stop = batch_stop(ctl, cols, S);
     __syncthreads();
     if (s_stop) return;
 
@@ -421,7 +408,8 @@ __global__ __launch_bounds__(256) void k_batch_alpha(const BatchCtl *ctl, BatchC
 }
 
 // x += alpha p, r -= alpha q (q of shared nodes: their halo slots in tile
-// order; clamped rows q = 0); partials of r.D^-1 r and r.r per column.
+// order; hrange null: every row of q is in Q; clamped rows q = 0); partials
+// of r.D^-1 r and r.r per column.
 template <int D, int S>
 __global__ __launch_bounds__(256) void k_batch_update(
     const BatchCtl *ctl, const BatchCol *__restrict__ cols, float *__restrict__ X,
@@ -438,7 +426,7 @@ __global__ __launch_bounds__(256) void k_batch_update(
     for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
         const int64_t node = row / D;
         const int i = (int)(row - node * D);
-        const int2 hr = hrange[node];
+        const int2 hr = hrange ? hrange[node] : make_int2(-1, -1);
         float q;
         if (hr.x < 0) {
             q = Q[row * S + col];
@@ -716,7 +704,8 @@ __global__ __launch_bounds__(256) void k_batch_unpack(const double *__restrict__
 }
 
 // Y = K(phi) X assembled from the apply's outputs: interior rows from Q,
-// shared rows summed over their halo slots in tile order, clamped rows 0.
+// shared rows summed over their halo slots in tile order (hrange null: all
+// rows from Q), clamped rows 0.
 template <int D, int S>
 __global__ __launch_bounds__(256) void k_batch_collect(const float *__restrict__ Q,
                                                        const float *__restrict__ halo,
@@ -729,7 +718,7 @@ __global__ __launch_bounds__(256) void k_batch_collect(const float *__restrict__
     for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
         const int64_t node = row / D;
         const int i = (int)(row - node * D);
-        const int2 hr = hrange[node];
+        const int2 hr = hrange ? hrange[node] : make_int2(-1, -1);
         float q;
         if (hr.x < 0) {
             q = Q[row * S + col];
@@ -790,8 +779,8 @@ static void apply_g(const fo_ctx *c, const float *P, float *Q, BatchCtl *ctl, co
         apply_t<D, NC, 8>(c, P, Q, ctl, cols, s);
 }
 
-static void launch_batch_apply(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl,
-                               const BatchCol *cols, hipStream_t s)
+static void launch_element_apply(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl,
+                                 const BatchCol *cols, hipStream_t s)
 {
     if (c->dim == 2) {
         switch (NC) {
@@ -810,10 +799,34 @@ static void launch_batch_apply(const fo_ctx *c, int NC, const float *P, float *Q
     }
 }
 
+// The operator of the context's batched solves (fo_set_batch_operator).
+static void launch_batch_apply(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl,
+                               const BatchCol *cols, hipStream_t s)
+{
+    if (c->batch.op == FO_BATCH_OP_NODAL)
+        nodal_apply_launch(c, NC, P, Q, ctl, cols, s);
+    else
+        launch_element_apply(c, NC, P, Q, ctl, cols, s);
+}
+
 void batch_apply_launch(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
                         hipStream_t s)
 {
     launch_batch_apply(c, NC, P, Q, ctl, cols, s);
+}
+
+// Shared rows of Q live in the halo (element operator) or Q holds every row
+// (nodal operator: null).
+static const int2 *q_hrange(const fo_ctx *c)
+{
+    return c->batch.op == FO_BATCH_OP_NODAL ? nullptr : reinterpret_cast<const int2 *>(c->batch.tiles.node_hrange);
+}
+
+// The p.q partials of the apply at S columns: per tile or per nodal block.
+static const double *pq_parts(const fo_ctx *c) { return c->batch.op == FO_BATCH_OP_NODAL ? c->batch.pq_nodal : c->batch.pq_part; }
+static int pq_count(const fo_ctx *c, int S)
+{
+    return c->batch.op == FO_BATCH_OP_NODAL ? nodal_blocks(c->N, S) : c->batch.tiles.n_tiles;
 }
 
 // Dispatch on S = 16 NC for the node-parallel kernels.
@@ -833,7 +846,7 @@ struct UpdateL {
     static void run(const fo_ctx *c, hipStream_t s)
     {
         const BatchState &b = c->batch;
-        const int2 *hr = reinterpret_cast<const int2 *>(b.tiles.node_hrange);
+        const int2 *hr = q_hrange(c);
         if (c->dim == 2)
             hipLaunchKernelGGL((k_batch_update<2, S>), dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, b.x32,
                                b.r32, b.p32, b.q32, c->dinv32, hr, b.halo, c->ndof, b.rz_part);
@@ -879,8 +892,7 @@ static void batch_iteration(const fo_ctx *c, int NC, hipStream_t s)
     const BatchState &b = c->batch;
     const int S = 16 * NC;
     launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
-    hipLaunchKernelGGL(k_batch_alpha, dim3(S), dim3(256), 0, s, b.ctl, b.cols, b.pq_part,
-                       b.tiles.n_tiles, S);
+    hipLaunchKernelGGL(k_batch_alpha, dim3(S), dim3(256), 0, s, b.ctl, b.cols, pq_parts(c), pq_count(c, S), S);
     by_s<UpdateL>(S, c, s);
     hipLaunchKernelGGL(k_batch_beta, dim3(S), dim3(256), 0, s, b.ctl, b.cols, b.rz_part, b.n_upd, S);
     by_s<DirectionL>(S, c, (const uint8_t *)nullptr, s);
@@ -1114,6 +1126,7 @@ int batch_setup(fo_ctx *c, int max_rhs, const double *coords, const std::vector<
     // host copies of the mesh in the context's element order (for the tiles)
     const std::vector<double> X(coords, coords + (size_t)c->N * D);
     const int mn = std::min(batch_default_nodes(D), batch_max_nodes(D, b.S));
+    FO_TRY(nodal_setup(c, conn_t));
     FO_TRY(build_batch_tiles(c, mn, 8, X, conn_t));
     if (!c->measure) FO_HIP(fo::wait_stream(c->stream));
     return FO_OK;
@@ -1132,9 +1145,11 @@ static void destroy_batch_graphs(fo_ctx *c)
 }
 
 // Times `reps` back-to-back launches of the batched apply (NC column
-// chunks) on the current batch tiles; columns are all active.
-int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us)
+// chunks; op: FO_BATCH_OP_*, or -1 for the context's operator); columns are
+// all active.
+int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us, int op)
 {
+    if (op < 0) op = c->batch.op;
     BatchState &b = c->batch;
     hipStream_t s = c->stream;
     const int S = 16 * NC;
@@ -1144,7 +1159,13 @@ int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us)
     FO_HIP(hipMemcpyAsync(b.cols, cols.data(), S * sizeof(BatchCol), hipMemcpyHostToDevice, s));
     FO_HIP(hipMemcpyAsync(b.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
     launch_fill<float>(b.p32, c->ndof * S, 1.0f, s);
-    launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+    auto apply = [&]() {
+        if (op == FO_BATCH_OP_NODAL)
+            nodal_apply_launch(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+        else
+            launch_element_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+    };
+    apply();
     hipEvent_t e0, e1;
     FO_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1152,7 +1173,7 @@ int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us)
         return FO_ERR_HIP;
     }
     (void)hipEventRecord(e0, s);
-    for (int k = 0; k < reps; ++k) launch_batch_apply(c, NC, b.p32, b.q32, b.ctl, b.cols, s);
+    for (int k = 0; k < reps; ++k) apply();
     (void)hipEventRecord(e1, s);
     float ms = 0.0f;
     int rc = FO_OK;
@@ -1171,7 +1192,7 @@ struct CollectL {
     static void run(const fo_ctx *c, float *Y, hipStream_t s)
     {
         const BatchState &b = c->batch;
-        const int2 *hr = reinterpret_cast<const int2 *>(b.tiles.node_hrange);
+        const int2 *hr = q_hrange(c);
         if (c->dim == 2)
             hipLaunchKernelGGL((k_batch_collect<2, S>), dim3(b.n_upd), dim3(256), 0, s, b.q32, b.halo, hr,
                                c->fixed, Y, c->ndof);
@@ -1223,7 +1244,7 @@ int batch_tune(fo_ctx *c, int n_rhs, int *best_nodes, int *best_group, double *b
         for (int G : {4, 8}) {
             FO_TRY(build_batch_tiles(c, mn, G, X, conn));
             double us = 0.0;
-            FO_TRY(batch_time_apply(c, NC, 20, &us));
+            FO_TRY(batch_time_apply(c, NC, 20, &us, FO_BATCH_OP_ELEMENT));
             if (us < best_t) {
                 best_t = us;
                 best = mn;
@@ -1262,7 +1283,9 @@ static int residual_norms(fo_ctx *c, int S)
 int batch_levelset(fo_ctx *c)
 {
     const BatchState &b = c->batch;
-    if (b.S == 0 || b.n_slot_total == 0) return FO_OK;
+    if (b.S == 0) return FO_OK;
+    FO_TRY(nodal_levelset(c));
+    if (b.n_slot_total == 0) return FO_OK;
     const int grid = grid_of(b.n_slot_total);
     if (c->dim == 2)
         hipLaunchKernelGGL(k_batch_geom<2>, dim3(grid), dim3(256), 0, c->stream, b.selem, b.sgconn,
@@ -1354,7 +1377,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         if (it_total >= o->max_iter) break;
         if (!b.ctl_host->done) {
             const int32_t before = b.ctl_host->it;
-            auto key = std::make_tuple(100 + NC, chunk, b.version, 0);
+            auto key = std::make_tuple(100 + NC, chunk, b.version, b.op);  // the operator is captured
             FO_TRY(graph_chunk(c, key, [&](hipStream_t ws) {
                 for (int j = 0; j < chunk; ++j) batch_iteration(c, NC, ws);
                 return (int)FO_OK;
@@ -1543,7 +1566,7 @@ static int bcg_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t ld
         FO_HIP(hipGetLastError());
         while (true) {
             const int32_t before = b.ctl_host->it;
-            auto key = std::make_tuple(200 + 8 * NP + NS, chunk, b.version, 0);
+            auto key = std::make_tuple(200 + 8 * NP + NS, chunk, b.version, b.op);
             FO_TRY(graph_chunk(c, key, [&](hipStream_t ws) {
                 for (int j = 0; j < chunk; ++j) bcg_iteration(c, b.bcg, NP, NS, ws);
                 return (int)FO_OK;

@@ -1,0 +1,32 @@
+// Device helpers shared by the batched operator kernels (element tiles in
+// fo_batch.hip, assembled node blocks in fo_nodal.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fo_internal.h"
+
+namespace fo {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Whether the batched solve is over: marked done, the iteration cap reached,
+// or every one of the S columns done.  Read by thread 0 of every block of an
+// operator launch from state that no kernel of that launch writes, so all
+// blocks agree; block 0 records the decision.
+__device__ __forceinline__ int batch_stop(BatchCtl *ctl, const BatchCol *cols, int S)
+{
+    int stop = ctl->done;
+    if (!stop) {
+        stop = ctl->it >= ctl->max_it;
+        if (!stop) {
+            int all = 1;
+            for (int k = 0; k < S; ++k) all &= cols[k].done;
+            stop = all;
+        }
+        if (stop && blockIdx.x == 0) ctl->done = 1;
+    }
+    return stop;
+}
+
+}  // namespace fo

@@ -668,7 +668,7 @@ void bcg_iteration(const fo_ctx *c, const BcgBufs &B, int NP, int NS, hipStream_
     const BatchState &b = c->batch;
     const int S = 16 * NS, sp = 16 * NP;
     batch_apply_launch(c, NP, b.p32, b.q32, b.ctl, b.cols, s);
-    if (b.tiles.n_shared_nodes > 0) {
+    if (b.op == FO_BATCH_OP_ELEMENT && b.tiles.n_shared_nodes > 0) {  // the nodal operator writes every row
         const int64_t tot = b.tiles.n_shared_nodes * c->dim * sp;
         const int grid = (int)std::min<int64_t>((tot + 255) / 256, 8192);
         if (c->dim == 2)

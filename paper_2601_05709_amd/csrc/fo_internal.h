@@ -201,6 +201,16 @@ struct BatchState {
     BcgBufs bcg;                        // block CG
     BcgState *bcg_host = nullptr;       // pinned copy (status, counts)
     int method = FO_BATCH_COLUMN_CG;    // FO_BATCH_COLUMN_CG (default) or FO_BATCH_BLOCK_CG
+    // the operator: FO_BATCH_OP_NODAL (default: assembled node blocks) or
+    // FO_BATCH_OP_ELEMENT (element tiles above)
+    int op = FO_BATCH_OP_NODAL;
+    int nb = 0;                         // NB: neighbour slots per node (a multiple of 4)
+    int n_apply = 0;                    // blocks of the nodal apply at S columns (p.q partials)
+    int32_t *nbr = nullptr;             // [N][NB] neighbour nodes, ascending, padded with the node
+    int32_t *inc_ptr = nullptr;         // [N+1] node -> element incidence
+    int32_t *inc_elem = nullptr;        // [(d+1) E] incident elements, ascending per node
+    float *kb = nullptr;                // [N][NB][d][d] blocks K_ij (per level set; 0 for padding)
+    double *pq_nodal = nullptr;         // [n_apply][S] p.q partials of the nodal apply
 };
 
 struct DescentSetup {

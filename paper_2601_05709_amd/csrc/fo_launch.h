@@ -150,7 +150,13 @@ int batch_levelset(fo_ctx *c);
 void batch_release(fo_ctx *c);
 int batch_solve(fo_ctx *c, const double *b, double *u, int n_rhs, int64_t ld, const fo_solve_opts *o,
                 fo_solve_stats *st);
-int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us);
+int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us, int op = -1);
+// assembled node-block operator of the batched solves (fo_nodal.hip)
+int nodal_blocks(int64_t N, int S);
+int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn);
+int nodal_levelset(fo_ctx *c);
+void nodal_apply_launch(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
+                        hipStream_t s);
 int batch_apply_block(fo_ctx *c, int NC, const float *X, float *Y);
 int batch_tune(fo_ctx *c, int n_rhs, int *best_nodes, int *best_group, double *best_us);
 int batch_max_nodes(int D, int S);

@@ -1,0 +1,320 @@
+// Assembled node-block operator of the batched multi-load solves.
+//
+// The load cases of a batched solve share K(phi) (the element stiffness of
+// the elasticity state equation, Section "Compliance minimization", with the
+// ersatz coefficient A_e of the level set).  With tens of right-hand sides
+// per application the element matrices are worth assembling: once per level
+// set, K(phi) is summed into d x d blocks K_ij, one per ordered pair of
+// distinct nodes that share an element -- FP64 sums of the element entries,
+// rounded once to FP32.  Every row of an element matrix sums to zero (it
+// annihilates rigid translations), so K_ii = -sum_{j != i} K_ij and
+//     y_i = sum_{j != i} K_ij (x_j - x_i),
+// which needs no diagonal block and, like the element form's vertex
+// differences, removes the common part of smooth fields before the FP32
+// products.  The blocks are exactly symmetric: both nodes of a pair sum the
+// same element entries, written in a transposition-invariant form, in the
+// same (ascending element) order.
+//
+// Apply: one wave owns 64/SP nodes and their S columns (SP = S rounded up to
+// a power of two; lane l serves column l mod SP of node l / SP).  Per
+// neighbour j and component k, one v_mfma_f32_4x4x1f32 (16 blocks of 4
+// columns) adds K_ij[:, k] (x_j - x_i)[k, :] to the node's rows: lane 4b + r
+// supplies row r of the block column as the A operand, lane l its column of
+// (x_j - x_i)[k] as the B operand, and register r of the result holds row r
+// of the node for the lane's column.  Every output row is written once, by
+// the wave that owns its node: no scatter, no halo, no atomics, and the sums
+// run in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "fo_batch_dev.h"
+#include "fo_element.h"
+#include "fo_internal.h"
+#include "fo_launch.h"
+#include "fo_xcd.h"
+
+namespace fo {
+
+constexpr int kNodalWaves = 4;          // waves per block of the apply
+constexpr int kNodalMaxBlocks = 2048;   // blocks of the apply (p.q partials per block)
+
+// Node groups of the apply: a wave takes 64 / SP nodes at a time.
+static int nodal_lanes(int S) { return S <= 16 ? 16 : (S <= 32 ? 32 : 64); }
+
+int nodal_blocks(int64_t N, int S)
+{
+    const int64_t groups = (N + 64 / nodal_lanes(S) - 1) / (64 / nodal_lanes(S));
+    const int64_t b = (groups + kNodalWaves - 1) / kNodalWaves;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, kNodalMaxBlocks));
+}
+
+// K_ij for every (node i, neighbour slot s): the sum over the elements that
+// contain both nodes, in ascending element order, of
+//   w_e (lam c_ar c_bk + mu c_ak c_br + mu delta_rk c_a . c_b),
+// a, b the local indices of i, j in e, c the cofactor vectors and
+// w_e = A_e / (d! |det|) (A_e = 1 in the material, the ersatz value
+// outside).  Padding slots (j = i) get zero blocks.
+template <int D>
+__global__ __launch_bounds__(256) void k_nodal_assemble(const int32_t *__restrict__ nbr, int NB, int64_t N,
+                                                        const int32_t *__restrict__ inc_ptr,
+                                                        const int32_t *__restrict__ inc_elem,
+                                                        const int32_t *__restrict__ conn, int64_t E,
+                                                        const double *__restrict__ coords,
+                                                        const uint8_t *__restrict__ chi, double ersatz,
+                                                        double lam, double mu, float *__restrict__ kb)
+{
+    constexpr int NV = D + 1;
+    const int64_t total = N * NB;
+    for (int64_t task = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; task < total;
+         task += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = task / NB;
+        const int32_t j = nbr[task];
+        double K[D][D];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int k = 0; k < D; ++k) K[r][k] = 0.0;
+        if (j != i) {
+            for (int32_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
+                const int64_t e = inc_elem[q];
+                int32_t v[NV];
+                int a = -1, b = -1;
+#pragma unroll
+                for (int t = 0; t < NV; ++t) {
+                    v[t] = conn[(int64_t)t * E + e];
+                    if (v[t] == i) a = t;
+                    if (v[t] == j) b = t;
+                }
+                if (b < 0 || a < 0) continue;
+                double X[NV][D];
+                const double *Xp[NV];
+#pragma unroll
+                for (int t = 0; t < NV; ++t) {
+#pragma unroll
+                    for (int m = 0; m < D; ++m) X[t][m] = coords[(int64_t)v[t] * D + m];
+                    Xp[t] = X[t];
+                }
+                const Geom<D, double> g = geom<D, double>(Xp);
+                double C[NV][D];
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    double c0 = 0.0;
+#pragma unroll
+                    for (int t = 1; t < NV; ++t) {
+                        C[t][m] = g.c[t - 1][m];
+                        c0 -= g.c[t - 1][m];
+                    }
+                    C[0][m] = c0;
+                }
+                const double w = (chi[e] ? 1.0 : ersatz) * inv_measure_det2<D, double>(g.det);
+                double ca[D], cb[D];
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    ca[m] = a == 0 ? C[0][m] : a == 1 ? C[1][m] : a == 2 ? C[2][m] : C[NV - 1][m];
+                    cb[m] = b == 0 ? C[0][m] : b == 1 ? C[1][m] : b == 2 ? C[2][m] : C[NV - 1][m];
+                }
+                double dot = 0.0;
+#pragma unroll
+                for (int m = 0; m < D; ++m) dot += ca[m] * cb[m];
+                // each product is formed so that the (j, i) block is the exact
+                // transpose: (ca[r] cb[k]) and (ca[k] cb[r]) swap roles
+#pragma unroll
+                for (int r = 0; r < D; ++r)
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        K[r][k] += w * (lam * (ca[r] * cb[k]) + mu * (ca[k] * cb[r]) + (r == k ? mu * dot : 0.0));
+            }
+        }
+        float *out = kb + task * (D * D);
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int k = 0; k < D; ++k) out[r * D + k] = (float)K[r][k];
+    }
+}
+
+// Q = K(phi) P on S columns (block vectors [n_dofs][S]); clamped rows of Q
+// are 0.  p.q partials per block and column.  Block b takes a contiguous
+// run of node groups (runs dealt to the XCDs in contiguous ranges), its
+// waves interleaved over the run.
+template <int D, int S>
+__global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
+    const int32_t *__restrict__ nbr, const float *__restrict__ kb, int NB, int64_t N,
+    const float *__restrict__ P, float *__restrict__ Q, const uint8_t *__restrict__ fixed,
+    double *__restrict__ pq_part, int n_blk, BatchCtl *ctl, const BatchCol *__restrict__ cols)
+{
+    constexpr int SP = S <= 16 ? 16 : (S <= 32 ? 32 : 64), NPW = 64 / SP, DD = D * D;
+    __shared__ int s_stop;
+    __shared__ double red[64 * kNodalWaves];
+    const int tid = threadIdx.x;
+    const int blk = xcd_tile(blockIdx.x, n_blk);
+    if (blk < 0) return;
+    if (tid == 0) s_stop = batch_stop(ctl, cols, S);
+    __syncthreads();
+    if (s_stop) return;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int cl = lane % SP, col = cl < S ? cl : S - 1;
+    const bool live_col = cl < S;
+    const int r = lane & 3, rr = r < D ? r : D - 1;  // rows >= D: any valid row, result unused
+    const int64_t groups = (N + NPW - 1) / NPW;
+    const int64_t per = (groups + n_blk - 1) / n_blk;
+    const int64_t g0 = (int64_t)blk * per, g1 = std::min<int64_t>(groups, g0 + per);
+    double pq = 0.0;
+    for (int64_t grp = g0 + wave; grp < g1; grp += kNodalWaves) {
+        const int64_t n0 = grp * NPW + lane / SP;
+        const bool live = n0 < N;
+        const int64_t n = live ? n0 : N - 1;
+        float xi[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xi[k] = P[(n * D + k) * S + col];
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int32_t *nb = nbr + n * NB;
+        const float *kr = kb + n * NB * DD + rr * D;
+        for (int s0 = 0; s0 < NB; s0 += 4) {
+            const int4 j4 = *reinterpret_cast<const int4 *>(nb + s0);
+            const int jj[4] = {j4.x, j4.y, j4.z, j4.w};
+            float xv[4][D], kv[4][D];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    xv[u][k] = P[((int64_t)jj[u] * D + k) * S + col];
+                    kv[u][k] = kr[(s0 + u) * DD + k];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(kv[u][k], xv[u][k] - xi[k], acc, 0, 0, 0);
+        }
+        if (live && live_col) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int64_t row = n * D + i;
+                const float q = fixed[row] ? 0.f : acc[i];
+                Q[row * S + col] = q;
+                pq += (double)xi[i] * (double)q;
+            }
+        }
+    }
+    red[tid] = pq;
+    __syncthreads();
+    if (tid < S) {
+        double sum = 0.0;
+        for (int w = 0; w < kNodalWaves; ++w)
+            for (int g = 0; g < NPW; ++g) sum += red[w * 64 + g * SP + tid];
+        pq_part[(int64_t)blk * S + tid] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+// Node -> element incidence (ascending element ids) and the neighbour lists
+// (ascending, padded with the node itself to NB, a multiple of 4), from the
+// host mesh in the context's element order.  Allocates the device arrays in
+// the context (measure mode: counts them only).
+int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
+{
+    BatchState &b = c->batch;
+    const int D = c->dim, NV = D + 1;
+    const int64_t N = c->N, E = c->E;
+    std::vector<int32_t> inc_ptr(N + 1, 0), inc_elem((size_t)NV * E);
+    for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < NV; ++a) ++inc_ptr[conn[(size_t)a * E + e] + 1];
+    for (int64_t i = 0; i < N; ++i) inc_ptr[i + 1] += inc_ptr[i];
+    {
+        std::vector<int32_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (int64_t e = 0; e < E; ++e)
+            for (int a = 0; a < NV; ++a) inc_elem[fill[conn[(size_t)a * E + e]]++] = (int32_t)e;
+    }
+    std::vector<int32_t> nb_cnt(N);
+    std::vector<std::vector<int32_t>> lists(N);
+    int NB = 4;
+    for (int64_t i = 0; i < N; ++i) {
+        std::vector<int32_t> &l = lists[i];
+        for (int32_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q)
+            for (int a = 0; a < NV; ++a) {
+                const int32_t v = conn[(size_t)a * E + inc_elem[q]];
+                if (v != i) l.push_back(v);
+            }
+        std::sort(l.begin(), l.end());
+        l.erase(std::unique(l.begin(), l.end()), l.end());
+        NB = std::max(NB, (int)((l.size() + 3) / 4 * 4));
+    }
+    std::vector<int32_t> nbr((size_t)N * NB);
+    for (int64_t i = 0; i < N; ++i) {
+        const std::vector<int32_t> &l = lists[i];
+        for (int s = 0; s < NB; ++s) nbr[(size_t)i * NB + s] = s < (int)l.size() ? l[s] : (int32_t)i;
+    }
+    b.nb = NB;
+    b.n_apply = nodal_blocks(N, b.S);
+    FO_TRY(ctx_alloc_n(c, &b.nbr, nbr.size()));
+    FO_TRY(ctx_alloc_n(c, &b.inc_ptr, inc_ptr.size()));
+    FO_TRY(ctx_alloc_n(c, &b.inc_elem, inc_elem.size()));
+    FO_TRY(ctx_alloc_n(c, &b.kb, (size_t)N * NB * D * D));
+    FO_TRY(ctx_alloc_n(c, &b.pq_nodal, (size_t)b.n_apply * b.S));
+    if (c->measure) return FO_OK;
+    if (hipMemcpyAsync(b.nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(b.inc_ptr, inc_ptr.data(), inc_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(b.inc_elem, inc_elem.data(), inc_elem.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        fo::wait_stream(c->stream) != hipSuccess)
+        return FO_ERR_HIP;
+    return FO_OK;
+}
+
+// The blocks K_ij of the current level set (A_e from c->chi).
+int nodal_levelset(fo_ctx *c)
+{
+    const BatchState &b = c->batch;
+    if (!b.kb) return FO_OK;
+    const int64_t total = c->N * b.nb;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_nodal_assemble<2>, dim3(grid), dim3(256), 0, c->stream, b.nbr, b.nb, c->N, b.inc_ptr,
+                           b.inc_elem, c->conn, c->E, c->coords, c->chi, c->ersatz, c->lam, c->mu, b.kb);
+    else
+        hipLaunchKernelGGL(k_nodal_assemble<3>, dim3(grid), dim3(256), 0, c->stream, b.nbr, b.nb, c->N, b.inc_ptr,
+                           b.inc_elem, c->conn, c->E, c->coords, c->chi, c->ersatz, c->lam, c->mu, b.kb);
+    FO_HIP(hipGetLastError());
+    return FO_OK;
+}
+
+template <int D, int S>
+static void nodal_apply_t(const fo_ctx *c, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
+                          hipStream_t s)
+{
+    const BatchState &b = c->batch;
+    const int nblk = nodal_blocks(c->N, S);
+    hipLaunchKernelGGL((k_nodal_apply<D, S>), dim3(xcd_grid(nblk)), dim3(64 * kNodalWaves), 0, s, b.nbr, b.kb,
+                       b.nb, c->N, P, Q, c->fixed, b.pq_nodal, nblk, ctl, cols);
+}
+
+template <int D>
+static void nodal_apply_d(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl,
+                          const BatchCol *cols, hipStream_t s)
+{
+    switch (NC) {
+    case 1: nodal_apply_t<D, 16>(c, P, Q, ctl, cols, s); break;
+    case 2: nodal_apply_t<D, 32>(c, P, Q, ctl, cols, s); break;
+    case 3: nodal_apply_t<D, 48>(c, P, Q, ctl, cols, s); break;
+    default: nodal_apply_t<D, 64>(c, P, Q, ctl, cols, s); break;
+    }
+}
+
+void nodal_apply_launch(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
+                        hipStream_t s)
+{
+    if (c->dim == 2)
+        nodal_apply_d<2>(c, NC, P, Q, ctl, cols, s);
+    else
+        nodal_apply_d<3>(c, NC, P, Q, ctl, cols, s);
+}
+
+}  // namespace fo

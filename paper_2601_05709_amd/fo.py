@@ -135,6 +135,7 @@ EXPORTS = {
                       C.c_int),
     "fo_apply_elasticity_batch": ([_vp, _vp, _vp, C.c_int32], C.c_int),
     "fo_set_batch_method": ([_vp, C.c_int32], C.c_int),
+    "fo_set_batch_operator": ([_vp, C.c_int32], C.c_int),
     "fo_batch_stats": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "fo_tile_stats": ([_vp] + [C.POINTER(C.c_int64)] * 5, C.c_int),
@@ -155,6 +156,7 @@ EXPORTS = {
 FO_PROF_ELAS_TILE_FP64, FO_PROF_ELAS_TILE_FP32, FO_PROF_HALO_FP64, FO_PROF_HALO_FP32 = 0, 1, 2, 3
 FO_KERNEL_CG_OP_FP64, FO_KERNEL_CG_OP_FP32, FO_KERNEL_BATCH_APPLY = 0, 1, 2
 FO_BATCH_BLOCK_CG, FO_BATCH_COLUMN_CG = 0, 1
+FO_BATCH_OP_NODAL, FO_BATCH_OP_ELEMENT = 0, 1
 FO_NOALLOC_MAX_DOFS = 2796201  # largest n_dofs of fo_optimize_noalloc (include/fo.h)
 
 _lib = None
@@ -375,6 +377,11 @@ class Context:
         """Solver of the batched multi-load solves: FO_BATCH_COLUMN_CG (CG per
         column, the default) or FO_BATCH_BLOCK_CG (block CG)."""
         _check(lib().fo_set_batch_method(self.h, int(method)), "fo_set_batch_method")
+
+    def set_batch_operator(self, op: int):
+        """Operator of the batched solves: FO_BATCH_OP_NODAL (assembled node
+        blocks, the default) or FO_BATCH_OP_ELEMENT (element tiles)."""
+        _check(lib().fo_set_batch_operator(self.h, int(op)), "fo_set_batch_operator")
 
     def batch_stats(self) -> dict:
         cols, nodes, group = C.c_int32(), C.c_int32(), C.c_int32()

@@ -1,8 +1,9 @@
 """Parity of the batched multi-load path with the FP64 oracle.
 
-The batched operator contracts the element stiffness against a block of
-load cases on the matrix cores in FP32; the solver runs CG on all columns at
-once with FP64 residual replacement.  Each column must match the oracle's
+The batched operator applies K(phi) to a block of load cases on the matrix
+cores in FP32, either as the node blocks K_ij assembled per level set (the
+default) or as the element contraction over tiles; the solver runs CG on
+all columns at once (or block CG) with FP64 residual replacement.  Each column must match the oracle's
 single-load solution (displacement within 1e-8 at a 1e-11 residual), the
 batched operator must match the oracle's CSR product to FP32 rounding, and
 the batched result must agree with the column-by-column FP64 GPU solve.
@@ -38,13 +39,18 @@ BATCHES = {
 }
 
 
+OPS = {"nodal": fo.FO_BATCH_OP_NODAL, "element": fo.FO_BATCH_OP_ELEMENT}
+
+
 @pytest.mark.parametrize("name", ["3d_12x6x6_s20", "2d_37x19_s33"])
-@pytest.mark.parametrize("ncols", [16, 48, 64])
-def test_batched_apply_matches_oracle(name, ncols):
+@pytest.mark.parametrize("ncols", [16, 32, 48, 64])
+@pytest.mark.parametrize("op", list(OPS))
+def test_batched_apply_matches_oracle(name, ncols, op):
     w = BATCHES[name]()
-    print("case", name, ncols, flush=True)
+    print("case", name, ncols, op, flush=True)
     m = w.mesh
     ctx = fo.Context.from_workload(w, max_rhs=64)
+    ctx.set_batch_operator(OPS[op])
     ctx.set_levelset(dev(w.phi))
     K = oracle_K(w).to_scipy()
     rng = np.random.default_rng(11)
@@ -61,9 +67,11 @@ def test_batched_apply_matches_oracle(name, ncols):
     assert np.all(yh[w.fixed == 1, :] == 0.0)
 
 
-def test_batched_apply_is_bitwise_reproducible():
+@pytest.mark.parametrize("op", list(OPS))
+def test_batched_apply_is_bitwise_reproducible(op):
     w = BATCHES["3d_12x6x6_s20"]()
     ctx = fo.Context.from_workload(w, max_rhs=64)
+    ctx.set_batch_operator(OPS[op])
     ctx.set_levelset(dev(w.phi))
     rng = np.random.default_rng(2)
     x = rng.standard_normal((w.mesh.n_dofs, 64)).astype(np.float32)
@@ -77,14 +85,16 @@ def test_batched_apply_is_bitwise_reproducible():
 
 @pytest.mark.parametrize("name", list(BATCHES))
 @pytest.mark.parametrize("method", ["column", "block"])
-def test_batched_solve_matches_oracle(name, method):
+@pytest.mark.parametrize("op", list(OPS))
+def test_batched_solve_matches_oracle(name, method, op):
     """T17: every column equals the oracle's single-load solve, with CG per
-    column and with block CG."""
+    column and with block CG, on either batched operator."""
     w = BATCHES[name]()
-    print("case", name, method, flush=True)
+    print("case", name, method, op, flush=True)
     m = w.mesh
     s = w.n_rhs
     ctx = fo.Context.from_workload(w)
+    ctx.set_batch_operator(OPS[op])
     ctx.set_levelset(dev(w.phi))
     ctx.set_batch_method(fo.FO_BATCH_BLOCK_CG if method == "block" else fo.FO_BATCH_COLUMN_CG)
     u = torch.zeros(m.n_dofs, s, dtype=torch.float64, device="cuda")
@@ -218,3 +228,36 @@ def test_block_cg_and_column_cg_agree(name):
         assert np.linalg.norm(ub[:, k] - uc[:, k]) <= 1e-8 * np.linalg.norm(uc[:, k]), k
     with pytest.raises(fo.FoError):
         ctx.set_batch_method(7)
+
+
+def test_batched_operators_agree_and_switch():
+    """The nodal and element operators agree to FP32 rounding on the same
+    block, and switching the operator of one context between solves (cached
+    iteration graphs are per operator) gives the same solutions."""
+    w = BATCHES["3d_16x8x8_s64"]()
+    m = w.mesh
+    ctx = fo.Context.from_workload(w)
+    ctx.set_levelset(dev(w.phi))
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((m.n_dofs, 64)).astype(np.float32)
+    ys = {}
+    for op in (fo.FO_BATCH_OP_NODAL, fo.FO_BATCH_OP_ELEMENT):
+        ctx.set_batch_operator(op)
+        y = torch.zeros(m.n_dofs, 64, dtype=torch.float32, device="cuda")
+        ctx.apply_elasticity_batch(dev(x), y, 64)
+        ys[op] = y.cpu().numpy().astype(np.float64)
+    scale = np.abs(ys[fo.FO_BATCH_OP_ELEMENT]).max(axis=0)
+    assert (np.abs(ys[0] - ys[1]).max(axis=0) / scale).max() < 2e-6
+    opts = fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-10)
+    us = []
+    for op in (fo.FO_BATCH_OP_NODAL, fo.FO_BATCH_OP_ELEMENT, fo.FO_BATCH_OP_NODAL):
+        ctx.set_batch_operator(op)
+        u = torch.zeros(m.n_dofs, 64, dtype=torch.float64, device="cuda")
+        st = ctx.state_solve(dev(w.b), u, opts, n_rhs=64)
+        assert st.status == 0
+        us.append(u.cpu().numpy())
+    assert np.array_equal(us[0], us[2])
+    for k in range(64):
+        assert np.linalg.norm(us[0][:, k] - us[1][:, k]) <= 1e-8 * np.linalg.norm(us[1][:, k]), k
+    with pytest.raises(fo.FoError):
+        ctx.set_batch_operator(5)
