@@ -1179,6 +1179,7 @@ int fo_set_batch_method(fo_ctx *c, int32_t method)
 int fo_set_batch_operator(fo_ctx *c, int32_t op)
 {
     if (!c || (op != FO_BATCH_OP_NODAL && op != FO_BATCH_OP_ELEMENT)) return FO_ERR_ARG;
+    if (op == FO_BATCH_OP_NODAL && c->batch.S > 0 && !c->batch.kb) return FO_ERR_ARG;  // mesh too irregular
     c->batch.op = op;
     return FO_OK;
 }

@@ -826,7 +826,7 @@ static const int2 *q_hrange(const fo_ctx *c)
 static const double *pq_parts(const fo_ctx *c) { return c->batch.op == FO_BATCH_OP_NODAL ? c->batch.pq_nodal : c->batch.pq_part; }
 static int pq_count(const fo_ctx *c, int S)
 {
-    return c->batch.op == FO_BATCH_OP_NODAL ? nodal_blocks(c->N, S) : c->batch.tiles.n_tiles;
+    return c->batch.op == FO_BATCH_OP_NODAL ? nodal_blocks(c, S) : c->batch.tiles.n_tiles;
 }
 
 // Dispatch on S = 16 NC for the node-parallel kernels.

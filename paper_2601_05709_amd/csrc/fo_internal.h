@@ -204,13 +204,14 @@ struct BatchState {
     // the operator: FO_BATCH_OP_NODAL (default: assembled node blocks) or
     // FO_BATCH_OP_ELEMENT (element tiles above)
     int op = FO_BATCH_OP_NODAL;
-    int nb = 0;                         // NB: neighbour slots per node (a multiple of 4)
+    int nb = 0;                         // NB: neighbour slots per node (a multiple of 8)
     int n_apply = 0;                    // blocks of the nodal apply at S columns (p.q partials)
     int32_t *nbr = nullptr;             // [N][NB] neighbour nodes, ascending, padded with the node
     int32_t *inc_ptr = nullptr;         // [N+1] node -> element incidence
     int32_t *inc_elem = nullptr;        // [(d+1) E] incident elements, ascending per node
     float *kb = nullptr;                // [N][NB][d][d] blocks K_ij (per level set; 0 for padding)
     double *pq_nodal = nullptr;         // [n_apply][S] p.q partials of the nodal apply
+    int nodal_occ[4] = {0, 0, 0, 0};    // resident blocks of the apply at S = 16, 32, 48, 64
 };
 
 struct DescentSetup {

@@ -152,7 +152,7 @@ int batch_solve(fo_ctx *c, const double *b, double *u, int n_rhs, int64_t ld, co
                 fo_solve_stats *st);
 int batch_time_apply(fo_ctx *c, int NC, int reps, double *avg_us, int op = -1);
 // assembled node-block operator of the batched solves (fo_nodal.hip)
-int nodal_blocks(int64_t N, int S);
+int nodal_blocks(const fo_ctx *c, int S);
 int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn);
 int nodal_levelset(fo_ctx *c);
 void nodal_apply_launch(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,

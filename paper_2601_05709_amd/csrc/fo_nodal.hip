@@ -40,16 +40,30 @@ namespace fo {
 
 constexpr int kNodalWaves = 4;          // waves per block of the apply
 constexpr int kNodalMaxBlocks = 2048;   // blocks of the apply (p.q partials per block)
+constexpr int kNodalStage = 512;        // largest NB d^2 (floats) of the node-per-wave path
 
 // Node groups of the apply: a wave takes 64 / SP nodes at a time.
 static int nodal_lanes(int S) { return S <= 16 ? 16 : (S <= 32 ? 32 : 64); }
 
-int nodal_blocks(int64_t N, int S)
+// Upper bound of the apply's blocks at S columns (sizes the p.q partials).
+static int nodal_block_cap(int64_t N, int S)
 {
     const int64_t groups = (N + 64 / nodal_lanes(S) - 1) / (64 / nodal_lanes(S));
     const int64_t b = (groups + kNodalWaves - 1) / kNodalWaves;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, kNodalMaxBlocks));
 }
+
+// Blocks of the apply at S columns: as many as are resident at once (one
+// round, the waves' node runs balanced), within the cap.
+int nodal_blocks(const fo_ctx *c, int S)
+{
+    const int cap = nodal_block_cap(c->N, S);
+    const int occ = c->batch.nodal_occ[S / 16 - 1];
+    return occ > 0 ? std::min(cap, occ) : cap;
+}
+
+// Dynamic LDS of the apply: two staging buffers of NB d^2 floats per wave.
+static size_t nodal_lds(int NB, int D) { return (size_t)kNodalWaves * 2 * NB * D * D * sizeof(float); }
 
 // K_ij for every (node i, neighbour slot s): the sum over the elements that
 // contain both nodes, in ascending element order, of
@@ -155,7 +169,7 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     if (tid == 0) s_stop = batch_stop(ctl, cols, S);
     __syncthreads();
     if (s_stop) return;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int cl = lane % SP, col = cl < S ? cl : S - 1;
     const bool live_col = cl < S;
     const int r = lane & 3, rr = r < D ? r : D - 1;  // rows >= D: any valid row, result unused
@@ -163,6 +177,77 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     const int64_t per = (groups + n_blk - 1) / n_blk;
     const int64_t g0 = (int64_t)blk * per, g1 = std::min<int64_t>(groups, g0 + per);
     double pq = 0.0;
+    if constexpr (NPW == 1) {
+        // one node per wave: the node, its neighbour ids and their row
+        // addresses are wave-uniform (scalar loads); eight neighbours per
+        // round of loads (NB is a multiple of 8; padding slots add zero).  The
+        // node's blocks (NB d^2 floats, at most kNodalStage) are copied to
+        // the wave's LDS buffer in 16-byte pieces, the next node's while this
+        // one is contracted, and every lane reads its A operands from there
+        // (four distinct addresses per read): one coalesced load per node
+        // instead of a 12-byte load per lane and block.
+        extern __shared__ __align__(16) float s_kb[];  // [waves][2][NB d^2]
+        const int KW = NB * DD, KQ = KW / 4;
+        float *kbuf = s_kb + wave * 2 * KW;
+        f32x4 pre[kNodalStage / 256];
+        auto fetch = [&](int64_t n) {
+            const f32x4 *src = reinterpret_cast<const f32x4 *>(kb + n * KW);
+#pragma unroll
+            for (int q = 0; q < kNodalStage / 256; ++q)
+                if (lane + 64 * q < KQ) pre[q] = src[lane + 64 * q];
+        };
+        auto stash = [&](int half) {
+            f32x4 *dst = reinterpret_cast<f32x4 *>(kbuf + half * KW);
+#pragma unroll
+            for (int q = 0; q < kNodalStage / 256; ++q)
+                if (lane + 64 * q < KQ) dst[lane + 64 * q] = pre[q];
+            // the wave's LDS operations run in order; keep the compiler from
+            // moving the reads of this buffer above these writes
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" ::: "memory");
+        };
+        int cur = 0;
+        if (g0 + wave < g1) {
+            fetch(g0 + wave);
+            stash(0);
+        }
+        for (int64_t n = g0 + wave; n < g1; n += kNodalWaves) {
+            const int64_t nn = n + kNodalWaves;
+            if (nn < g1) fetch(nn);
+            float xi[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) xi[k] = P[(n * D + k) * S + col];
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int32_t *nb = nbr + n * NB;
+            const float *ka = kbuf + cur * KW + rr * D;
+            for (int s0 = 0; s0 < NB; s0 += 8) {
+                float xv[8][D];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t j = nb[s0 + u];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) xv[u][k] = P[(j * D + k) * S + col];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(ka[(s0 + u) * DD + k], xv[u][k] - xi[k], acc, 0, 0,
+                                                                 0);
+            }
+            if (nn < g1) stash(cur ^ 1);
+            cur ^= 1;
+            if (live_col) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const int64_t row = n * D + i;
+                    const float q = fixed[row] ? 0.f : acc[i];
+                    Q[row * S + col] = q;
+                    pq += (double)xi[i] * (double)q;
+                }
+            }
+        }
+    } else
     for (int64_t grp = g0 + wave; grp < g1; grp += kNodalWaves) {
         const int64_t n0 = grp * NPW + lane / SP;
         const bool live = n0 < N;
@@ -213,10 +298,15 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
 // ---------------------------------------------------------------------------
 // host side
 
+template <int D>
+static int nodal_occupancy(fo_ctx *c);
+
 // Node -> element incidence (ascending element ids) and the neighbour lists
-// (ascending, padded with the node itself to NB, a multiple of 4), from the
+// (ascending, padded with the node itself to NB, a multiple of 8), from the
 // host mesh in the context's element order.  Allocates the device arrays in
-// the context (measure mode: counts them only).
+// the context (measure mode: counts them only).  A mesh whose largest
+// neighbourhood exceeds the apply's staging buffer gets no nodal arrays and
+// keeps the element operator.
 int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
 {
     BatchState &b = c->batch;
@@ -233,7 +323,7 @@ int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
     }
     std::vector<int32_t> nb_cnt(N);
     std::vector<std::vector<int32_t>> lists(N);
-    int NB = 4;
+    int NB = 8;
     for (int64_t i = 0; i < N; ++i) {
         std::vector<int32_t> &l = lists[i];
         for (int32_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q)
@@ -243,21 +333,26 @@ int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
             }
         std::sort(l.begin(), l.end());
         l.erase(std::unique(l.begin(), l.end()), l.end());
-        NB = std::max(NB, (int)((l.size() + 3) / 4 * 4));
+        NB = std::max(NB, (int)((l.size() + 7) / 8 * 8));
     }
     std::vector<int32_t> nbr((size_t)N * NB);
     for (int64_t i = 0; i < N; ++i) {
         const std::vector<int32_t> &l = lists[i];
         for (int s = 0; s < NB; ++s) nbr[(size_t)i * NB + s] = s < (int)l.size() ? l[s] : (int32_t)i;
     }
+    if (NB * D * D > kNodalStage) {  // neighbourhoods too large: element operator only
+        b.op = FO_BATCH_OP_ELEMENT;
+        return FO_OK;
+    }
     b.nb = NB;
-    b.n_apply = nodal_blocks(N, b.S);
+    b.n_apply = nodal_block_cap(N, b.S);
     FO_TRY(ctx_alloc_n(c, &b.nbr, nbr.size()));
     FO_TRY(ctx_alloc_n(c, &b.inc_ptr, inc_ptr.size()));
     FO_TRY(ctx_alloc_n(c, &b.inc_elem, inc_elem.size()));
     FO_TRY(ctx_alloc_n(c, &b.kb, (size_t)N * NB * D * D));
     FO_TRY(ctx_alloc_n(c, &b.pq_nodal, (size_t)b.n_apply * b.S));
     if (c->measure) return FO_OK;
+    FO_TRY(D == 2 ? nodal_occupancy<2>(c) : nodal_occupancy<3>(c));
     if (hipMemcpyAsync(b.nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
         hipMemcpyAsync(b.inc_ptr, inc_ptr.data(), inc_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice,
@@ -291,9 +386,27 @@ static void nodal_apply_t(const fo_ctx *c, const float *P, float *Q, BatchCtl *c
                           hipStream_t s)
 {
     const BatchState &b = c->batch;
-    const int nblk = nodal_blocks(c->N, S);
-    hipLaunchKernelGGL((k_nodal_apply<D, S>), dim3(xcd_grid(nblk)), dim3(64 * kNodalWaves), 0, s, b.nbr, b.kb,
-                       b.nb, c->N, P, Q, c->fixed, b.pq_nodal, nblk, ctl, cols);
+    const int nblk = nodal_blocks(c, S);
+    hipLaunchKernelGGL((k_nodal_apply<D, S>), dim3(xcd_grid(nblk)), dim3(64 * kNodalWaves), nodal_lds(b.nb, D), s,
+                       b.nbr, b.kb, b.nb, c->N, P, Q, c->fixed, b.pq_nodal, nblk, ctl, cols);
+}
+
+// Resident blocks of every column-width instance (outside graph capture).
+template <int D>
+static int nodal_occupancy(fo_ctx *c)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) return FO_ERR_HIP;
+    const void *fn[4] = {(const void *)k_nodal_apply<D, 16>, (const void *)k_nodal_apply<D, 32>,
+                         (const void *)k_nodal_apply<D, 48>, (const void *)k_nodal_apply<D, 64>};
+    for (int k = 0; k < 4; ++k) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn[k], 64 * kNodalWaves, nodal_lds(c->batch.nb, D)) !=
+            hipSuccess)
+            return FO_ERR_HIP;
+        c->batch.nodal_occ[k] = std::max(1, per) * cus;
+    }
+    return FO_OK;
 }
 
 template <int D>
