@@ -407,14 +407,14 @@ __global__ __launch_bounds__(256) void k_batch_alpha(const BatchCtl *ctl, BatchC
     }
 }
 
-// x += alpha p, r -= alpha q (q of shared nodes: their halo slots in tile
-// order; hrange null: every row of q is in Q; clamped rows q = 0); partials
-// of r.D^-1 r and r.r per column.
+// r -= alpha q (q of shared nodes: their halo slots in tile order; hrange
+// null: every row of q is in Q; clamped rows q = 0); partials of r.D^-1 r
+// and r.r per column.  (x += alpha p is done by the direction kernel, which
+// reads p anyway.)
 template <int D, int S>
 __global__ __launch_bounds__(256) void k_batch_update(
-    const BatchCtl *ctl, const BatchCol *__restrict__ cols, float *__restrict__ X,
-    float *__restrict__ R, const float *__restrict__ P, const float *__restrict__ Q,
-    const float *__restrict__ dinv, const int2 *__restrict__ hrange,
+    const BatchCtl *ctl, const BatchCol *__restrict__ cols, float *__restrict__ R,
+    const float *__restrict__ Q, const float *__restrict__ dinv, const int2 *__restrict__ hrange,
     const float *__restrict__ halo, int64_t ndof, double *__restrict__ rz_part)
 {
     constexpr int RG = 256 / S;
@@ -436,7 +436,6 @@ __global__ __launch_bounds__(256) void k_batch_update(
         const float di = dinv[row];
         if (di == 0.f) q = 0.f;
         const int64_t ix = row * S + col;
-        X[ix] += alpha * P[ix];
         const float r = R[ix] - alpha * q;
         R[ix] = r;
         rz += (double)r * (double)(di * r);
@@ -496,25 +495,48 @@ __global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *col
     }
 }
 
-// p = D^-1 r + beta p for the columns still running, or (mask != null) for
-// the columns whose residual was just replaced (beta = the phase coefficient).
+// Per iteration (mask null): x += alpha p for every column that took a step
+// in this iteration (alpha != 0), then p = D^-1 r + beta p for the columns
+// still running.  Phase start (mask != null): p = D^-1 r + beta p for the
+// columns whose residual was just replaced (beta = the phase coefficient),
+// x untouched.  Two rows per thread and step, loads first.
 template <int S>
 __global__ __launch_bounds__(256) void k_batch_direction(const BatchCtl *ctl,
                                                          const BatchCol *__restrict__ cols,
                                                          const uint8_t *__restrict__ mask,
-                                                         float *__restrict__ P,
+                                                         float *__restrict__ P, float *__restrict__ X,
                                                          const float *__restrict__ R,
                                                          const float *__restrict__ dinv, int64_t ndof)
 {
     constexpr int RG = 256 / S;
     if (!mask && ctl->done) return;
     const int tid = threadIdx.x, col = tid % S, rg = tid / S;
-    if (mask ? !mask[col] : cols[col].done) return;
+    const bool dir = mask ? mask[col] != 0 : !cols[col].done;
+    const float alpha = mask ? 0.f : (float)cols[col].alpha;
+    if (!dir && alpha == 0.f) return;
     const float beta = (float)cols[col].beta;
-    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
-        const int64_t ix = row * S + col;
-        const float z = dinv[row] * R[ix];
-        P[ix] = beta == 0.f ? z : z + beta * P[ix];
+    const int64_t step = (int64_t)gridDim.x * RG;
+    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += 2 * step) {
+        const bool two = row + step < ndof;
+        const int64_t ix0 = row * S + col, ix1 = two ? ix0 + step * S : ix0;
+        const float p0 = P[ix0], p1 = P[ix1];
+        float x0 = 0.f, x1 = 0.f, z0 = 0.f, z1 = 0.f;
+        if (alpha != 0.f) {
+            x0 = X[ix0];
+            x1 = X[ix1];
+        }
+        if (dir) {
+            z0 = dinv[row] * R[ix0];
+            z1 = dinv[two ? row + step : row] * R[ix1];
+        }
+        if (alpha != 0.f) {
+            X[ix0] = x0 + alpha * p0;
+            if (two) X[ix1] = x1 + alpha * p1;
+        }
+        if (dir) {
+            P[ix0] = beta == 0.f ? z0 : z0 + beta * p0;
+            if (two) P[ix1] = beta == 0.f ? z1 : z1 + beta * p1;
+        }
     }
 }
 
@@ -848,11 +870,11 @@ struct UpdateL {
         const BatchState &b = c->batch;
         const int2 *hr = q_hrange(c);
         if (c->dim == 2)
-            hipLaunchKernelGGL((k_batch_update<2, S>), dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, b.x32,
-                               b.r32, b.p32, b.q32, c->dinv32, hr, b.halo, c->ndof, b.rz_part);
+            hipLaunchKernelGGL((k_batch_update<2, S>), dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, b.r32,
+                               b.q32, c->dinv32, hr, b.halo, c->ndof, b.rz_part);
         else
-            hipLaunchKernelGGL((k_batch_update<3, S>), dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, b.x32,
-                               b.r32, b.p32, b.q32, c->dinv32, hr, b.halo, c->ndof, b.rz_part);
+            hipLaunchKernelGGL((k_batch_update<3, S>), dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, b.r32,
+                               b.q32, c->dinv32, hr, b.halo, c->ndof, b.rz_part);
     }
 };
 
@@ -862,7 +884,7 @@ struct DirectionL {
     {
         const BatchState &b = c->batch;
         hipLaunchKernelGGL(k_batch_direction<S>, dim3(b.n_upd), dim3(256), 0, s, b.ctl, b.cols, mask,
-                           b.p32, b.r32, c->dinv32, c->ndof);
+                           b.p32, b.x32, b.r32, c->dinv32, c->ndof);
     }
 };
 

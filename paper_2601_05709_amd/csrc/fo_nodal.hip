@@ -45,20 +45,21 @@ constexpr int kNodalStage = 512;        // largest NB d^2 (floats) of the node-p
 // Node groups of the apply: a wave takes 64 / SP nodes at a time.
 static int nodal_lanes(int S) { return S <= 16 ? 16 : (S <= 32 ? 32 : 64); }
 
-// Upper bound of the apply's blocks at S columns (sizes the p.q partials).
+// Upper bound of the apply's blocks at S columns (sizes the p.q partials);
+// a multiple of 8 (one share per XCD).
 static int nodal_block_cap(int64_t N, int S)
 {
     const int64_t groups = (N + 64 / nodal_lanes(S) - 1) / (64 / nodal_lanes(S));
     const int64_t b = (groups + kNodalWaves - 1) / kNodalWaves;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(b, kNodalMaxBlocks));
+    return xcd_grid((int)std::max<int64_t>(1, std::min<int64_t>(b, kNodalMaxBlocks)));
 }
 
 // Blocks of the apply at S columns: as many as are resident at once (one
-// round, the waves' node runs balanced), within the cap.
+// round, the waves' node runs balanced), within the cap; a multiple of 8.
 int nodal_blocks(const fo_ctx *c, int S)
 {
     const int cap = nodal_block_cap(c->N, S);
-    const int occ = c->batch.nodal_occ[S / 16 - 1];
+    const int occ = c->batch.nodal_occ[S / 16 - 1] / 8 * 8;
     return occ > 0 ? std::min(cap, occ) : cap;
 }
 
@@ -151,21 +152,19 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(const int32_t *__restric
 }
 
 // Q = K(phi) P on S columns (block vectors [n_dofs][S]); clamped rows of Q
-// are 0.  p.q partials per block and column.  Block b takes a contiguous
-// run of node groups (runs dealt to the XCDs in contiguous ranges), its
-// waves interleaved over the run.
+// are 0.  p.q partials per block and column (gridDim.x of them, a multiple
+// of 8).
 template <int D, int S>
 __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     const int32_t *__restrict__ nbr, const float *__restrict__ kb, int NB, int64_t N,
     const float *__restrict__ P, float *__restrict__ Q, const uint8_t *__restrict__ fixed,
-    double *__restrict__ pq_part, int n_blk, BatchCtl *ctl, const BatchCol *__restrict__ cols)
+    double *__restrict__ pq_part, BatchCtl *ctl, const BatchCol *__restrict__ cols)
 {
     constexpr int SP = S <= 16 ? 16 : (S <= 32 ? 32 : 64), NPW = 64 / SP, DD = D * D;
     __shared__ int s_stop;
     __shared__ double red[64 * kNodalWaves];
     const int tid = threadIdx.x;
-    const int blk = xcd_tile(blockIdx.x, n_blk);
-    if (blk < 0) return;
+    const int blk = blockIdx.x;
     if (tid == 0) s_stop = batch_stop(ctl, cols, S);
     __syncthreads();
     if (s_stop) return;
@@ -174,8 +173,15 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     const bool live_col = cl < S;
     const int r = lane & 3, rr = r < D ? r : D - 1;  // rows >= D: any valid row, result unused
     const int64_t groups = (N + NPW - 1) / NPW;
-    const int64_t per = (groups + n_blk - 1) / n_blk;
-    const int64_t g0 = (int64_t)blk * per, g1 = std::min<int64_t>(groups, g0 + per);
+    // XCD x (blocks dealt round-robin: blockIdx mod 8) takes the x-th eighth
+    // of the node groups, and its W resident waves sweep it together: wave
+    // (b, w) takes groups g0 + 4 b + w + t W, t = 0, 1, ..., so at any time
+    // the XCD works on one contiguous window of W groups and the neighbour
+    // rows it gathers stay in its L2 between uses.
+    const int64_t per_x = (groups + 7) / 8;
+    const int nb_x = (int)(gridDim.x >> 3), W = nb_x * kNodalWaves;
+    const int64_t xs = (int64_t)(blk & 7) * per_x, g1 = std::min<int64_t>(groups, xs + per_x);
+    const int64_t g0 = xs + (int64_t)(blk >> 3) * kNodalWaves;
     double pq = 0.0;
     if constexpr (NPW == 1) {
         // one node per wave: the node, its neighbour ids and their row
@@ -211,8 +217,8 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
             fetch(g0 + wave);
             stash(0);
         }
-        for (int64_t n = g0 + wave; n < g1; n += kNodalWaves) {
-            const int64_t nn = n + kNodalWaves;
+        for (int64_t n = g0 + wave; n < g1; n += W) {
+            const int64_t nn = n + W;
             if (nn < g1) fetch(nn);
             float xi[D];
 #pragma unroll
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
             }
         }
     } else
-    for (int64_t grp = g0 + wave; grp < g1; grp += kNodalWaves) {
+    for (int64_t grp = g0 + wave; grp < g1; grp += W) {
         const int64_t n0 = grp * NPW + lane / SP;
         const bool live = n0 < N;
         const int64_t n = live ? n0 : N - 1;
@@ -387,8 +393,8 @@ static void nodal_apply_t(const fo_ctx *c, const float *P, float *Q, BatchCtl *c
 {
     const BatchState &b = c->batch;
     const int nblk = nodal_blocks(c, S);
-    hipLaunchKernelGGL((k_nodal_apply<D, S>), dim3(xcd_grid(nblk)), dim3(64 * kNodalWaves), nodal_lds(b.nb, D), s,
-                       b.nbr, b.kb, b.nb, c->N, P, Q, c->fixed, b.pq_nodal, nblk, ctl, cols);
+    hipLaunchKernelGGL((k_nodal_apply<D, S>), dim3(nblk), dim3(64 * kNodalWaves), nodal_lds(b.nb, D), s,
+                       b.nbr, b.kb, b.nb, c->N, P, Q, c->fixed, b.pq_nodal, ctl, cols);
 }
 
 // Resident blocks of every column-width instance (outside graph capture).
