@@ -70,10 +70,10 @@ def fused_cg_bytes(mesh, width):
 # the committed counter summaries (FETCH_SIZE / WRITE_SIZE per launch).
 TRAFFIC_SOURCES = ["fo_tiled.hip", "fo_element.h", "fo_ops.h", "fo_reduce.h", "fo_internal.h",
                    "fo_tiles.cpp", "fo_tiles.h", "fo_xcd.h"]
-BATCH_SOURCES = ["fo_batch.hip", "fo_element.h", "fo_internal.h", "fo_tiles.cpp", "fo_tiles.h", "fo_xcd.h"]
+BATCH_SOURCES = ["fo_nodal.hip", "fo_batch_dev.h", "fo_internal.h", "fo_xcd.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_tile_cg_fp32_cantilever3d_96x48x48.md")
 LARGE_PROFILE = os.path.join(ROOT, "profiles", "k_tile_cg_fp32_cantilever3d_256x128x128.md")
-BATCH_PROFILE = os.path.join(ROOT, "profiles", "k_batch_apply_multiload3d_64x32x32.md")
+BATCH_PROFILE = os.path.join(ROOT, "profiles", "k_nodal_apply_multiload3d_64x32x32.md")
 
 
 def kernel_source_hash(sources):
@@ -236,8 +236,7 @@ def headline_case(K, W, fp64_steps):
     it = Iteration(w, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8),
                    fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8), max_rhs=n_loads)
     it.ctx.set_levelset(it.phi0)
-    nodes, group, tune_us = it.ctx.batch_tune(n_loads)
-    log("c3: context and tile tuning in %.2f s (node cap %d, group %d)" % (time.perf_counter() - t0, nodes, group))
+    log("c3: context in %.2f s" % (time.perf_counter() - t0))
     for _ in range(W):
         it.run()
     t_ir, outs = timed(lambda: it.run(update=True, reset_phi=True), K)
@@ -293,22 +292,41 @@ def headline_case(K, W, fp64_steps):
     t_c, sc = timed(lambda: [it.ctx.state_solve(cols[k], uc, opts).iters_inner for k in range(n_loads)])
     its_c = sum(sc[0])
     apply_us = it.ctx.time_kernel(fo.FO_KERNEL_BATCH_APPLY, 50)
+    # the element-tile operator on the same solves (tuned tiles), for comparison
+    nodes, group, _ = it.ctx.batch_tune(n_loads)
+    it.ctx.set_batch_operator(fo.FO_BATCH_OP_ELEMENT)
+    el_apply_us = it.ctx.time_kernel(fo.FO_KERNEL_BATCH_APPLY, 20)
+    it.ctx.state_solve(b, u, opts, n_rhs=n_loads)
+    t_el, (sel,) = timed(lambda: it.ctx.state_solve(b, u, opts, n_rhs=n_loads))
+    it.ctx.set_batch_operator(fo.FO_BATCH_OP_NODAL)
     d = m.dim
     width = 16 * ((n_loads + 15) // 16)
-    flops = m.n_elems * width * 2 * (d * (d + 1)) * (d * d)
+    ns = it.ctx.nodal_stats()
+    # algorithmic work of the nodal apply: per off-diagonal block and column,
+    # d^2 products and adds of y_i += K_ij (x_j - x_i); bytes: the blocks
+    # (d^2 FP32 each) and neighbour ids, x read once, y written once
+    flops = 2 * d * d * width * ns["off_diagonal_blocks"]
+    abytes = ns["off_diagonal_blocks"] * (4 * d * d + 4) + 2 * m.n_dofs * width * 4
     state_s = sum(o.state_stats.seconds for o in outs)
     col_apps = sum(o.state_stats.iters_inner for o in outs) * n_loads
     state64_s = sum(o.state_stats.seconds for o in outs64)
     apps64 = sum(o.state_stats.iters_inner for o in outs64)
     traffic = recorded_traffic(BATCH_PROFILE, cells, BATCH_SOURCES)
     achieved = flops / (apply_us * 1e-6) / 1e12
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-                "frac": achieved / 157.3, "traffic": traffic,
-                "kernel": "k_batch_apply<3,4,G> (batched K(phi) P on the matrix cores, FP32 16x16x4, %d columns)"
-                          % width,
-                "flops_per_launch": flops, "avg_us": apply_us, "reps": 50,
-                "flop_count": "per element and column: the K_e[:, b>=1] (d(d+1) x d^2) times (x_b - x_0) contraction, "
-                              "2 d(d+1) d^2 = 216 flop in 3D"}
+    gbs = abytes / (apply_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                "label": "effective: the iteration's working set (about 260 MB) sits at the size of the 256 MB "
+                         "Infinity Cache",
+                "kernel": "k_nodal_apply<3,%d> (batched K(phi) P from the assembled node blocks on the matrix cores, "
+                          "v_mfma_f32_4x4x1f32, %d columns)" % (width, width),
+                "bytes_per_launch": abytes, "avg_us": apply_us, "reps": 50,
+                "byte_count": "off-diagonal blocks (d^2 FP32) and their neighbour ids, x read once and y written "
+                              "once (FP32, %d columns)" % width,
+                "arithmetic_intensity": flops / abytes,
+                "mfma_side": {"flops_per_launch": flops, "achieved_tflops": achieved, "peak_tflops": 157.3,
+                              "frac": achieved / 157.3,
+                              "flop_count": "2 d^2 per off-diagonal block and column (y_i += K_ij (x_j - x_i))"}}
     res = {
         "value": n_loads * K / t_ir, "ms_per_step": 1e3 * t_ir / K, "roofline": roofline,
         "config": {"workload": "3D cantilever %dx%dx%d cubes x 6 tets, %d load cases on one level set, one full "
@@ -337,12 +355,17 @@ def headline_case(K, W, fp64_steps):
                         "speedup_vs_fp32_ir_columnwise": t_c / t_b,
                         "block_cg": {"what": "the same 64 solves by block CG (phase target 1e-3)", "seconds": t_bcg,
                                      "solves_per_s": n_loads / t_bcg, "block_iters": sbcg.iters_inner,
-                                     "refinements": sbcg.iters_outer}},
-        "tiles": {"node_cap": nodes, "group": group},
+                                     "refinements": sbcg.iters_outer},
+                        "element_operator": {"what": "the same 64 solves (CG per column) on the element-tile operator "
+                                                     "(K_e contraction per tile, tuned)", "seconds": t_el,
+                                             "solves_per_s": n_loads / t_el, "block_iters": sel.iters_inner,
+                                             "apply_us": el_apply_us, "tiles": {"node_cap": nodes, "group": group}}},
+        "nodal_operator": ns,
     }
-    log("c3: x%.2f over plain FP64 per step; state solves alone x%.2f over column-wise FP32+refinement; "
-        "max column error %.2e (FP64 %.2e); apply %.0f us = %.1f TFLOP/s"
-        % (res["speedup_vs_fp64"], t_c / t_b, max(errs), max(errs64), apply_us, achieved))
+    log("c3: x%.2f over plain FP64 per step; state solves alone x%.2f over column-wise FP32+refinement, "
+        "x%.2f over the element operator; max column error %.2e (FP64 %.2e); apply %.1f us = %.0f GB/s "
+        "(element operator %.0f us)"
+        % (res["speedup_vs_fp64"], t_c / t_b, t_el / t_b, max(errs), max(errs64), apply_us, gbs, el_apply_us))
     it.ctx.close()
     it64.ctx.close()
     return w, res
@@ -443,7 +466,7 @@ def main():
                          "transport, reinitialisation, heat, inverse and loop measurements)")
     ap.add_argument("--kernel-only", default=None, choices=["headline", "large"],
                     help="for counter passes: build the workload's context and time its dominant kernel only "
-                         "(headline: the batched apply on 64x32x32 with 64 columns; large: the fused FP32 CG "
+                         "(headline: the nodal batched apply on 64x32x32 with 64 columns; large: the fused FP32 CG "
                          "operator on 256x128x128), 20 launches")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 instance")
     ap.add_argument("--main-only", action="store_true",
@@ -478,7 +501,6 @@ def main():
             wk = fi.multi_load_3d(cells, n_loads, seed=3)
             ctx = fo.Context.from_workload(wk, max_rhs=n_loads)
             ctx.set_levelset(torch.from_numpy(wk.phi).cuda())
-            ctx.batch_tune(n_loads)
             us = ctx.time_kernel(fo.FO_KERNEL_BATCH_APPLY, 20)
         else:
             wk = fi.cantilever_3d((256, 128, 128))

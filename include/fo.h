@@ -532,6 +532,13 @@ int fo_set_batch_method(fo_ctx *ctx, int32_t method);
 enum { FO_BATCH_OP_NODAL = 0, FO_BATCH_OP_ELEMENT = 1 };
 int fo_set_batch_operator(fo_ctx *ctx, int32_t op);
 
+/* Shape of the assembled operator of the batched path: neighbour slots per
+ * node (NB), off-diagonal blocks (ordered pairs of distinct nodes sharing an
+ * element) and the device bytes of its arrays; all 0 when the context has
+ * none (max_rhs = 1, or a mesh whose neighbourhoods exceed the apply's
+ * staging buffer, NB d^2 > 512).  Any pointer may be NULL. */
+int fo_nodal_stats(const fo_ctx *ctx, int32_t *slots, int64_t *off_diagonal_blocks, int64_t *bytes);
+
 /* Y = K(phi) X for a block of load cases through the batched operator (FP32,
  * matrix cores): x, y device float [n_dofs][ncols], load case fastest; ncols
  * a multiple of 16 up to the context's column block width (fo_batch_stats).

@@ -1184,6 +1184,16 @@ int fo_set_batch_operator(fo_ctx *c, int32_t op)
     return FO_OK;
 }
 
+int fo_nodal_stats(const fo_ctx *c, int32_t *slots, int64_t *off_diagonal_blocks, int64_t *bytes)
+{
+    if (!c) return FO_ERR_ARG;
+    const bool have = c->batch.kb != nullptr;
+    if (slots) *slots = have ? c->batch.nb : 0;
+    if (off_diagonal_blocks) *off_diagonal_blocks = have ? c->batch.n_offdiag : 0;
+    if (bytes) *bytes = have ? c->batch.nodal_bytes : 0;
+    return FO_OK;
+}
+
 int fo_batch_tune(fo_ctx *c, int32_t n_rhs, int32_t *tile_nodes, int32_t *group, double *apply_us)
 {
     if (!c || n_rhs < 1 || n_rhs > c->max_rhs) return FO_ERR_ARG;

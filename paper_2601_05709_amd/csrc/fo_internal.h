@@ -212,6 +212,8 @@ struct BatchState {
     float *kb = nullptr;                // [N][NB][d][d] blocks K_ij (per level set; 0 for padding)
     double *pq_nodal = nullptr;         // [n_apply][S] p.q partials of the nodal apply
     int nodal_occ[4] = {0, 0, 0, 0};    // resident blocks of the apply at S = 16, 32, 48, 64
+    int64_t n_offdiag = 0;              // off-diagonal blocks (ordered node pairs sharing an element)
+    int64_t nodal_bytes = 0;            // device bytes of the nodal arrays
 };
 
 struct DescentSetup {

@@ -342,8 +342,10 @@ int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
         NB = std::max(NB, (int)((l.size() + 7) / 8 * 8));
     }
     std::vector<int32_t> nbr((size_t)N * NB);
+    int64_t offdiag = 0;
     for (int64_t i = 0; i < N; ++i) {
         const std::vector<int32_t> &l = lists[i];
+        offdiag += (int64_t)l.size();
         for (int s = 0; s < NB; ++s) nbr[(size_t)i * NB + s] = s < (int)l.size() ? l[s] : (int32_t)i;
     }
     if (NB * D * D > kNodalStage) {  // neighbourhoods too large: element operator only
@@ -351,12 +353,15 @@ int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
         return FO_OK;
     }
     b.nb = NB;
+    b.n_offdiag = offdiag;
     b.n_apply = nodal_block_cap(N, b.S);
+    const size_t before = c->bytes;
     FO_TRY(ctx_alloc_n(c, &b.nbr, nbr.size()));
     FO_TRY(ctx_alloc_n(c, &b.inc_ptr, inc_ptr.size()));
     FO_TRY(ctx_alloc_n(c, &b.inc_elem, inc_elem.size()));
     FO_TRY(ctx_alloc_n(c, &b.kb, (size_t)N * NB * D * D));
     FO_TRY(ctx_alloc_n(c, &b.pq_nodal, (size_t)b.n_apply * b.S));
+    b.nodal_bytes = (int64_t)(c->bytes - before);
     if (c->measure) return FO_OK;
     FO_TRY(D == 2 ? nodal_occupancy<2>(c) : nodal_occupancy<3>(c));
     if (hipMemcpyAsync(b.nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) !=

@@ -136,6 +136,7 @@ EXPORTS = {
     "fo_apply_elasticity_batch": ([_vp, _vp, _vp, C.c_int32], C.c_int),
     "fo_set_batch_method": ([_vp, C.c_int32], C.c_int),
     "fo_set_batch_operator": ([_vp, C.c_int32], C.c_int),
+    "fo_nodal_stats": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "fo_batch_stats": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "fo_tile_stats": ([_vp] + [C.POINTER(C.c_int64)] * 5, C.c_int),
@@ -377,6 +378,13 @@ class Context:
         """Solver of the batched multi-load solves: FO_BATCH_COLUMN_CG (CG per
         column, the default) or FO_BATCH_BLOCK_CG (block CG)."""
         _check(lib().fo_set_batch_method(self.h, int(method)), "fo_set_batch_method")
+
+    def nodal_stats(self) -> dict:
+        """Assembled operator of the batched path: neighbour slots per node,
+        off-diagonal blocks and device bytes (zeros when absent)."""
+        nb, od, by = C.c_int32(), C.c_int64(), C.c_int64()
+        _check(lib().fo_nodal_stats(self.h, C.byref(nb), C.byref(od), C.byref(by)), "fo_nodal_stats")
+        return {"slots": nb.value, "off_diagonal_blocks": od.value, "bytes": by.value}
 
     def set_batch_operator(self, op: int):
         """Operator of the batched solves: FO_BATCH_OP_NODAL (assembled node

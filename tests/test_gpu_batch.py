@@ -261,3 +261,31 @@ def test_batched_operators_agree_and_switch():
         assert np.linalg.norm(us[0][:, k] - us[1][:, k]) <= 1e-8 * np.linalg.norm(us[1][:, k]), k
     with pytest.raises(fo.FoError):
         ctx.set_batch_operator(5)
+
+
+def test_nodal_operator_shape_matches_the_mesh_edges():
+    """The assembled operator holds one block per ordered pair of distinct
+    nodes that share an element: twice the mesh's edge count (counted here
+    from the connectivity), NB >= the largest node degree."""
+    for name in ("3d_12x6x6_s20", "2d_37x19_s33"):
+        w = BATCHES[name]()
+        m = w.mesh
+        conn = np.asarray(m.conn)
+        nv = conn.shape[0]
+        pairs = set()
+        for a in range(nv):
+            for b in range(a + 1, nv):
+                lo = np.minimum(conn[a], conn[b])
+                hi = np.maximum(conn[a], conn[b])
+                pairs.update(zip(lo.tolist(), hi.tolist()))
+        deg = np.zeros(m.n_nodes, dtype=np.int64)
+        for i, j in pairs:
+            deg[i] += 1
+            deg[j] += 1
+        ctx = fo.Context.from_workload(w, max_rhs=64)
+        ns = ctx.nodal_stats()
+        assert ns["off_diagonal_blocks"] == 2 * len(pairs)
+        assert ns["slots"] >= deg.max() and ns["slots"] % 8 == 0
+        d = m.dim
+        assert ns["bytes"] >= m.n_nodes * ns["slots"] * (4 + 4 * d * d)
+        assert fo.Context.from_workload(w, max_rhs=1).nodal_stats()["slots"] == 0
