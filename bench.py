@@ -396,6 +396,35 @@ def phase_times(it):
     return out
 
 
+def paper_mesh_case():
+    """The paper's 3D cantilever mesh size, 120x60x60 cubes x 6 tets (2.59M
+    elements): one full iteration in FP32 + refinement and in plain FP64 with
+    per-phase times (the second of each, after graph capture)."""
+    import torch
+    import fo_inputs as fi
+    from paper_2601_05709_amd import fo
+    from paper_2601_05709_amd.pipeline import Iteration
+    cells = (120, 60, 60)
+    w = fi.cantilever_3d(cells)
+    m = w.mesh
+    out = {"workload": "3D cantilever %dx%dx%d cubes x 6 tets (the paper's 3D mesh size), one load case, one full "
+                       "hot-path iteration" % cells, "n_elems": m.n_elems, "n_nodes": m.n_nodes, "n_dofs": m.n_dofs}
+    for key, prec in (("fp32_ir", fo.FO_FP32_IR), ("fp64", fo.FO_FP64)):
+        it = Iteration(w, fo.SolveOpts(precision=prec, rtol=1e-8), fo.SolveOpts(precision=prec, rtol=1e-8))
+        phase_times(it)
+        out[key] = phase_times(it)
+        if key == "fp32_ir":
+            u_ir = it.u[:, 0].clone()
+        else:
+            out["err_u_fp32_ir_vs_fp64"] = float(torch.linalg.norm(u_ir - it.u[:, 0]) / torch.linalg.norm(it.u[:, 0]))
+        it.ctx.close()
+    log("c2 paper mesh %dx%dx%d: FP32+refinement %.1f ms per iteration (state %d + %d its), FP64 %.1f ms (%d its)"
+        % (cells + (out["fp32_ir"]["total_ms"], out["fp32_ir"]["state_iters"]["inner"],
+                    out["fp32_ir"]["state_iters"]["outer"], out["fp64"]["total_ms"],
+                    out["fp64"]["state_iters"]["inner"])))
+    return out
+
+
 def large_case():
     """The large single instance, 256x128x128 cubes x 6 tets: one full
     iteration in FP32 + refinement and in plain FP64 with per-phase times, and
@@ -461,7 +490,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="short run for profilers: the headline step only (one warm-up, one step)")
-    ap.add_argument("--only", default=None, choices=["headline", "c2", "extras", "large"],
+    ap.add_argument("--only", default=None, choices=["headline", "c2", "extras", "large", "paper"],
                     help="run one part alone (for profilers; extras: the single-load iteration and the "
                          "transport, reinitialisation, heat, inverse and loop measurements)")
     ap.add_argument("--kernel-only", default=None, choices=["headline", "large"],
@@ -494,6 +523,9 @@ def main():
         K, W = 1, 1
     if args.only == "large":
         print(json.dumps(large_case()), flush=True)
+        return
+    if args.only == "paper":
+        print(json.dumps(paper_mesh_case()), flush=True)
         return
     if args.kernel_only:
         if args.kernel_only == "headline":
@@ -832,6 +864,8 @@ def main():
     result.update(extra)
     it_ir.ctx.close()
     it_64.ctx.close()
+    log("paper mesh size 120x60x60")
+    result["c2_paper"] = paper_mesh_case()
     if not args.no_large:
         log("large instance 256x128x128")
         result["large"] = large_case()

@@ -1,11 +1,12 @@
-"""The large single instance: one full iteration (state, derivative,
+"""The large single instances: one full iteration (state, derivative,
 velocity, update) on 64x32x32 cubes x 6 tetrahedra against the oracle's
 iteration, in FP64 and in FP32 + refinement (its error is measured on this
-mesh, where the oracle runs to 1e-12), and on 256x128x128 cubes x 6
-tetrahedra (25.2M elements, 12.8M unknowns) in the configuration bench.py
-times, checked on sampled nodes: the oracle assembles the elements around
-each sampled node, which gives that node's rows of K u, of the velocity
-operator and of the derivative exactly, and its updated level set."""
+mesh, where the oracle runs to 1e-12), and on the paper's 3D mesh size
+120x60x60 cubes x 6 tetrahedra (2.59M elements) and on 256x128x128 (25.2M
+elements, 12.8M unknowns) in the configuration bench.py times, checked on
+sampled nodes: the oracle assembles the elements around each sampled node,
+which gives that node's rows of K u, of the velocity operator and of the
+derivative exactly, and its updated level set."""
 import numpy as np
 import pytest
 
@@ -53,17 +54,18 @@ def patch(m, nodes):
     return conn, np.ascontiguousarray(m.bfacets[:, fsel]), np.ascontiguousarray(m.bnormal[fsel])
 
 
-def test_iteration_256x128x128_on_sampled_nodes():
-    cells = (256, 128, 128)
+@pytest.mark.parametrize("cells", [(120, 60, 60), (256, 128, 128)], ids=["120x60x60", "256x128x128"])
+def test_iteration_large_on_sampled_nodes(cells):
     w = fi.cantilever_3d(cells)
     m = w.mesh
     d = m.dim
-    print("case 256x128x128: context (%d elements, %d unknowns)" % (m.n_elems, m.n_dofs), flush=True)
+    tag = "x".join(map(str, cells))
+    print("case %s: context (%d elements, %d unknowns)" % (tag, m.n_elems, m.n_dofs), flush=True)
     it = Iteration(w, fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8),
                    fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8))
     ts = it.ctx.tile_stats()
     assert ts["n_tiles"] > 0 and ts["n_slots"] >= m.n_nodes
-    print("case 256x128x128: iteration", flush=True)
+    print("case %s: iteration" % tag, flush=True)
     out = it.run(update=True)
     torch.cuda.synchronize()
     assert out.state_stats.status == 0 and out.state_stats.rel_res <= 1e-8
@@ -89,7 +91,7 @@ def test_iteration_256x128x128_on_sampled_nodes():
     # state: the sampled rows of the residual b - K u
     K = oc.assemble_elasticity(d, m.coords, conn, A_e, lam, mu)
     r = (b - K.matvec(u))[rows][free]
-    print("case 256x128x128: max sampled state residual %.2e of ||b||" % (np.abs(r).max() / bn), flush=True)
+    print("case %s: max sampled state residual %.2e of ||b||" % (tag, np.abs(r).max() / bn), flush=True)
     assert np.abs(r).max() <= 1e-8 * bn
     assert np.all(u[rows][~free] == 0.0)
     # derivative: the sampled rows, recomputed by the oracle from the same u
