@@ -99,7 +99,9 @@ typedef struct {
     int32_t precision;         /* FO_FP64 or FO_FP32_IR                            */
     double rtol;               /* stop when ||b - A x||_2 <= rtol ||b||_2 (FP64)   */
     int32_t max_iter;          /* cap on operator applications (all levels)        */
-    double inner_rtol;         /* FO_FP32_IR: relative residual of each inner solve*/
+    double inner_rtol;         /* FO_FP32_IR: relative residual of each inner solve
+                                  (phase), 0: 0.1; a phase is asked for no more than
+                                  the solve still needs (half the remaining factor) */
     int32_t max_outer;         /* FO_FP32_IR: cap on refinement steps               */
     int32_t check_every;       /* iterations between host convergence polls, 0=auto*/
 } fo_solve_opts;

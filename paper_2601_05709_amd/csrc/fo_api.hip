@@ -503,7 +503,7 @@ int solve_ir(fo_ctx *c, OpKind k, const double *b, const fo_solve_opts *o, fo_so
     double rn = bnorm;
     int status = FO_NOT_CONVERGED;
     const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
-    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-2;
+    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 0.1;
     int fresh = 1;
     int64_t longest = 0;  // iterations of the longest phase that reached its target
     int capped_run = 0;   // consecutive phases stopped at their cap
@@ -527,7 +527,8 @@ int solve_ir(fo_ctx *c, OpKind k, const double *b, const fo_solve_opts *o, fo_so
         // stagnated (the FP32 recursion lost conjugacy): end it, replace the
         // residual and restart the direction
         const int cap = (int)std::min<int64_t>(left, longest > 0 ? std::max<int64_t>(4 * longest, 256) : first_cap);
-        launch_ir_phase(c, c->r64, s2, v.r, v.x, v.dinv, phase_rtol, cap, fresh, s);
+        launch_ir_phase(c, c->r64, s2, v.r, v.x, v.dinv, phase_target(phase_rtol, o->rtol, bnorm, rn), cap, fresh,
+                        s);
         const int64_t before = inner;
         FO_TRY(fused_run<float>(c, v, o, &inner));
         const bool capped = c->scal_host->it >= cap && c->scal_host->status != FO_ERR_BREAKDOWN;

@@ -585,12 +585,13 @@ __global__ __launch_bounds__(256) void k_batch_rescale(const double *__restrict_
 // New phase state of the masked columns after a residual replacement (the
 // single-load rule per column): with old scale s_o and new scale s_n, the
 // first direction is D^-1 r32 + beta (s_o / s_n) p_old, beta = rho_n s_n^2 /
-// (rho_o s_o^2); a fresh column restarts (coefficient 0).  Other columns keep
-// running; the solve is marked live again.
+// (rho_o s_o^2); a fresh column restarts (coefficient 0); its phase target
+// is ptol[k] (phase_target).  Other columns keep running; the solve is
+// marked live again.
 __global__ __launch_bounds__(256) void k_batch_phase(BatchCtl *ctl, BatchCol *cols,
                                                      const double *__restrict__ rz_part, int nb,
                                                      int S, double *s2, const uint8_t *mask,
-                                                     const int32_t *caps, double phase_rtol)
+                                                     const int32_t *caps, const double *__restrict__ ptol)
 {
     __shared__ double lds[4];
     const int k = blockIdx.x;
@@ -613,7 +614,7 @@ __global__ __launch_bounds__(256) void k_batch_phase(BatchCtl *ctl, BatchCol *co
         n.rho = a;
         n.rho_new = a;
         n.rr = b;
-        n.tol2 = phase_rtol * phase_rtol;
+        n.tol2 = ptol[k] * ptol[k];
         n.beta = coef;
         n.fresh = 0;
         n.it = 0;
@@ -973,6 +974,8 @@ void batch_release(fo_ctx *c)
     if (b.s2_host) (void)hipHostFree(b.s2_host);
     if (b.mask_host) (void)hipHostFree(b.mask_host);
     if (b.caps_host) (void)hipHostFree(b.caps_host);
+    if (b.ptol_host) (void)hipHostFree(b.ptol_host);
+    b.ptol_host = nullptr;
     if (b.bcg_host) (void)hipHostFree(b.bcg_host);
     b.caps_host = nullptr;
     b.bcg_host = nullptr;
@@ -1125,6 +1128,7 @@ int batch_setup(fo_ctx *c, int max_rhs, const double *coords, const std::vector<
     FO_TRY(balloc(c, (void **)&b.s2, (size_t)3 * b.S * sizeof(double), false));
     FO_TRY(balloc(c, (void **)&b.mask, (size_t)b.S, false));
     FO_TRY(balloc(c, (void **)&b.caps, (size_t)b.S * sizeof(int32_t), false));
+    FO_TRY(balloc(c, (void **)&b.ptol, (size_t)b.S * sizeof(double), false));
     FO_TRY(balloc(c, (void **)&b.cols, (size_t)b.S * sizeof(BatchCol), false));
     FO_TRY(balloc(c, (void **)&b.ctl, sizeof(BatchCtl), false));
     FO_TRY(balloc(c, (void **)&b.bcg.st, sizeof(BcgState), false));
@@ -1136,6 +1140,7 @@ int batch_setup(fo_ctx *c, int max_rhs, const double *coords, const std::vector<
             hipHostMalloc((void **)&b.s2_host, b.S * sizeof(double)) != hipSuccess ||
             hipHostMalloc((void **)&b.mask_host, b.S) != hipSuccess ||
             hipHostMalloc((void **)&b.caps_host, b.S * sizeof(int32_t)) != hipSuccess ||
+            hipHostMalloc((void **)&b.ptol_host, b.S * sizeof(double)) != hipSuccess ||
             hipHostMalloc((void **)&b.bcg_host, sizeof(BcgState)) != hipSuccess)
             return FO_ERR_NOMEM;
         if (bcg_prepare()) return FO_ERR_HIP;
@@ -1334,7 +1339,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
     const int64_t nd = c->ndof;
     const int chunk = o->check_every > 0 ? o->check_every : 16;
     const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
-    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-2;
+    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 0.1;
     hipLaunchKernelGGL(k_batch_pack, dim3(grid_of(nd * S)), dim3(256), 0, s, b_in, ld, n, c->fixed, b.b64,
                        S, nd);
     launch_fill<double>(b.x64, nd * S, 0.0, s);
@@ -1361,14 +1366,16 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         conv[k] = k >= n || bnorm[k] == 0.0;
     }
     // columns to (re)start from r64: mask_host
-    // a phase twice as long as the column's longest completed one has
-    // stagnated: it is stopped and restarted after the replacement
+    // a phase four times as long as the column's longest completed one (at
+    // least 256 iterations) has stagnated: it is stopped and restarted after
+    // the replacement (the single-load rule)
     auto select = [&](const std::vector<int> &fin) {
         bool any = false;
         for (int k = 0; k < S; ++k) {
             b.mask_host[k] = (fin[k] && !conv[k]) ? 1 : 0;
             b.caps_host[k] = (int32_t)std::min<int64_t>(
-                INT32_MAX / 2, longest[k] > 0 ? std::max<int64_t>(2 * longest[k], 64) : first_phase_cap(nd));
+                INT32_MAX / 2, longest[k] > 0 ? std::max<int64_t>(4 * longest[k], 256) : first_phase_cap(nd));
+            b.ptol_host[k] = phase_target(phase_rtol, o->rtol, bnorm[k], rn[k]);
             any = any || b.mask_host[k];
         }
         return any;
@@ -1377,8 +1384,9 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         FO_HIP(hipMemcpyAsync(b.mask, b.mask_host, S, hipMemcpyHostToDevice, s));
         by_s<RescaleL>(S, (const fo_ctx *)c, s);
         FO_HIP(hipMemcpyAsync(b.caps, b.caps_host, S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        FO_HIP(hipMemcpyAsync(b.ptol, b.ptol_host, S * sizeof(double), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_batch_phase, dim3(S), dim3(256), 0, s, b.ctl, b.cols, b.rz_part, b.n_upd, S, b.s2,
-                           b.mask, b.caps, phase_rtol);
+                           b.mask, b.caps, (const double *)b.ptol);
         by_s<DirectionL>(S, (const fo_ctx *)c, (const uint8_t *)b.mask, s);
         FO_HIP(hipGetLastError());
         return FO_OK;
@@ -1523,7 +1531,7 @@ static int bcg_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t ld
     const int64_t nd = c->ndof;
     const int chunk = o->check_every > 0 ? o->check_every : 8;
     const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
-    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-2;
+    const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 0.1;
     hipLaunchKernelGGL(k_batch_pack, dim3(grid_of(nd * S)), dim3(256), 0, s, b_in, ld, n, c->fixed, b.b64,
                        S, nd);
     launch_fill<double>(b.x64, nd * S, 0.0, s);

@@ -60,6 +60,17 @@ int optimize_on(fo_ctx *c, const fo_loop_opts *o, const double *b, double *phi, 
 
 constexpr int kMaxBoxes = 64;      // boxes of Omega0 in the velocity options
 
+// Relative residual reduction asked of an FP32 phase of the refinement: the
+// inner tolerance, but no more than the solve still needs (with a margin for
+// the drift of the FP32 residual from the true one), so that the last phase
+// does not overshoot the target by up to the inner factor.
+constexpr double kPhaseMargin = 0.5;
+inline double phase_target(double inner_rtol, double rtol, double bnorm, double rn)
+{
+    const double need = rn > 0.0 ? kPhaseMargin * rtol * bnorm / rn : 1.0;
+    return need > inner_rtol ? (need < 1.0 ? need : 1.0) : inner_rtol;
+}
+
 constexpr int kBlock = 256;        // threads per block of the vector kernels
 constexpr int kRedBlocks = 1024;   // partial sums per reduction (fixed: deterministic)
 constexpr int kUpdBlock = 1024;    // threads per block of the fused CG update (one node each)
@@ -191,6 +202,8 @@ struct BatchState {
     uint8_t *mask = nullptr;            // [S] columns selected for a residual replacement
     int32_t *caps = nullptr;            // [S] phase iteration caps of the selected columns
     int32_t *caps_host = nullptr;       // pinned [S]
+    double *ptol = nullptr;             // [S] phase targets of the selected columns (phase_target)
+    double *ptol_host = nullptr;        // pinned [S]
     float *geo = nullptr;               // [n_tiles][MS][16] slot cofactors and weight (per level set)
     BatchCol *cols = nullptr;           // [S]
     BatchCtl *ctl = nullptr;

@@ -218,7 +218,7 @@ class SolveOpts:
     precision: int = FO_FP64
     rtol: float = 1e-8
     max_iter: int = 200000
-    inner_rtol: float = 1e-2
+    inner_rtol: float = 0.1
     max_outer: int = 60
     check_every: int = 0
 
