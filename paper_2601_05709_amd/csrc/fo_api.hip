@@ -685,8 +685,8 @@ int time_cg_op(fo_ctx *c, FusedVecs<T> v, int reps, double *avg_us)
     }
     int rc = FO_OK;
     (void)hipEventRecord(e0, s);
-    for (int k = 0; k < reps && rc == FO_OK; ++k)
-        rc = launch_tile_cg<T>(c, v.kind, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s);
+    for (int k = 0; k < reps && rc == FO_OK; ++k)  // the warm-up folded the partials: the kernel alone
+        rc = launch_tile_cg<T>(c, v.kind, v.r, v.dinv, v.p[0], v.p[1], v.q, c->scal, 2, s, false);
     (void)hipEventRecord(e1, s);
     float ms = 0.0f;
     if (rc == FO_OK && (fo::wait_event(e1) != hipSuccess ||
@@ -851,7 +851,7 @@ int create_context(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32
         (rc = dev_alloc(c, &c->bb_part, (size_t)kRedBlocks)) ||
         (rc = dev_alloc(c, &c->partials, (size_t)kRedBlocks * 4)) ||
         (rc = dev_alloc(c, &c->pq_part, (size_t)std::max<int64_t>(ht.n_tiles, kRedBlocks))) ||
-        (rc = dev_alloc(c, &c->rz_part, (size_t)kRedBlocks * 2)) ||
+        (rc = dev_alloc(c, &c->rz_part, (size_t)kRedBlocks * 2)) || (rc = dev_alloc(c, &c->fold, 4)) ||
         (rc = dev_alloc(c, &c->scal, 4)) || (rc = dev_alloc(c, &c->dscratch, 16)) ||
         (rc = dev_alloc(c, &c->gbuf, N * (D + 1))))
         return fail(rc);
@@ -923,6 +923,10 @@ int create_context(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32
                     up(c->bnode_fac, bfac.data(), bfac.size() * sizeof(int32_t)))))
         return fail(FO_ERR_HIP);
     if ((rc = upload_tiles(c, ht))) return fail(rc);
+    // large meshes fold the fused CG's partials first (more than one pass of
+    // the loads that the tile kernel's wave 0 and the update's blocks issue)
+    c->fold_rz = upd_blocks(c->N) > 4 * 64;
+    c->fold_pq = ht.n_tiles > 4 * kUpdBlock;
     // FP32 operator geometry: tile-node coordinates relative to the tile's
     // first node, formed in FP64 (kept alive until the stream sync below)
     std::vector<float> tx((size_t)std::max<int64_t>((int64_t)ht.n_tiles * ht.max_nodes * D, 1), 0.0f);

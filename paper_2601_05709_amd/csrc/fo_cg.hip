@@ -217,6 +217,23 @@ __global__ __launch_bounds__(256) void k_residual64(const double *__restrict__ b
 // r.z / r.r partials are written by node-parallel kernels on upd_blocks(N)
 // blocks, the layout k_tile_cg reduces.
 
+// out[k] = the sum of part[k n .. k n + n), k < sets, in a fixed order (one
+// block): the folded partials of the fused CG on large meshes.
+__global__ __launch_bounds__(1024) void k_fold_partials(const double *__restrict__ part, int n, int sets,
+                                                        double *__restrict__ out)
+{
+    __shared__ double lds[16];
+    for (int k = 0; k < sets; ++k) {
+        const double v = block_sum_partials_any(part + (int64_t)k * n, n, lds);
+        if (threadIdx.x == 0) out[k] = v;
+    }
+}
+
+void launch_fold(const double *part, int n, int sets, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(1024), 0, s, part, n, sets, out);
+}
+
 int upd_blocks(int64_t N)
 {
     int64_t b = (N + kUpdBlock - 1) / kUpdBlock;
@@ -559,13 +576,20 @@ void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *
 {
     const int nb = upd_blocks(c->N);
     const T *halo = reinterpret_cast<const T *>(c->halo);
+    const double *pq = c->pq_part;
+    int n_pq = (int)c->tiles.n_tiles;
+    if (c->fold_pq) {  // one block folds the per-tile partials; the update blocks read one value
+        launch_fold(c->pq_part, n_pq, 1, c->fold + 2, s);
+        pq = c->fold + 2;
+        n_pq = 1;
+    }
     if (c->dim == 2)
         hipLaunchKernelGGL((k_cgn_update<T, 2>), dim3(nb), dim3(kUpdBlock), 0, s, c->scal, B, x, r, p, q,
-                           dinv, c->N, c->pq_part, c->tiles.n_tiles, c->rz_part,
+                           dinv, c->N, pq, n_pq, c->rz_part,
                            reinterpret_cast<const int2 *>(c->tiles.node_hrange), halo);
     else
         hipLaunchKernelGGL((k_cgn_update<T, 3>), dim3(nb), dim3(kUpdBlock), 0, s, c->scal, B, x, r, p, q,
-                           dinv, c->N, c->pq_part, c->tiles.n_tiles, c->rz_part,
+                           dinv, c->N, pq, n_pq, c->rz_part,
                            reinterpret_cast<const int2 *>(c->tiles.node_hrange), halo);
 }
 template void launch_cgn_update<double>(const fo_ctx *, int, double *, double *, const double *,

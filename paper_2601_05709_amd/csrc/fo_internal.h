@@ -291,6 +291,13 @@ struct fo_ctx {
     double *partials = nullptr;        // [kRedBlocks * 4] general partial sums
     double *pq_part = nullptr;         // [max(n_tiles, kRedBlocks)] p.Ap partials
     double *rz_part = nullptr;         // [2 * kRedBlocks] r.z, r.r partials
+    // Folded partials of the fused CG on large meshes: r.z, r.r (0, 1) and
+    // p.q (2), each summed by one block in a fixed order before the kernel that
+    // needs it, so that the tile kernel's blocks (and the update's) read one
+    // value instead of every partial.  Used when there are more partials than
+    // those kernels sum in one pass of loads.
+    double *fold = nullptr;            // [4]
+    bool fold_rz = false, fold_pq = false;
     double *bb_part = nullptr;         // [kRedBlocks] b.b partials
     fo::SolveScalars *scal = nullptr;  // device, two parity slots
     fo::SolveScalars *scal_host = nullptr;  // pinned [2]: copies of slot 0 (final state in [0])

@@ -49,6 +49,7 @@ void launch_residual64(const double *b, const double *q, double *r, int64_t n, d
 // fused CG for the tiled elasticity operator
 int node_blocks(int64_t N);
 int upd_blocks(int64_t N);  // blocks of the fused update = r.z/r.r partials per sum
+void launch_fold(const double *part, int n, int sets, double *out, hipStream_t s);
 template <typename T>
 void launch_cgn_start(const fo_ctx *c, const T *b, const T *q, T *r, const T *dinv, double rtol,
                       int max_it, hipStream_t s);
@@ -91,9 +92,11 @@ void launch_facet_mass(const fo_ctx *c, const double *x, double *y, hipStream_t 
 
 // Operator of the fused CG kernels.
 enum FusedKind { FUSED_ELAS = 0, FUSED_DESCENT = 1 };
+// fold = false: the folded partials of a large mesh are already in c->fold
+// (the launch times the tile kernel alone).
 template <typename T>
 int launch_tile_cg(const fo_ctx *c, int kind, const T *r, const T *dinv, const T *pin, T *pout, T *q,
-                   SolveScalars *sc, int A, hipStream_t s);
+                   SolveScalars *sc, int A, hipStream_t s, bool fold = true);
 void launch_ir_phase(const fo_ctx *c, const double *r64, double *s2, float *r32, float *x32,
                      const float *dinv, double phase_rtol, int max_it, int fresh, hipStream_t s);
 void launch_to_float(const double *a, float *b, int64_t n, hipStream_t s);

@@ -646,9 +646,12 @@ static int launch_tile_cg_op(const fo_ctx *c, Op op, FacetArgs<T> fa, const T *r
     if constexpr (sizeof(T) == 8) coords = c->coords;
     else coords = c->coords32;
     size_t lds = CgLds<D, T>::bytes(c->tiles.max_nodes, c->tiles.max_elems);
+    // with folded partials every tile reads two values (see launch_tile_cg)
+    const double *rz = c->fold_rz ? c->fold : c->rz_part;
+    const int nrz = c->fold_rz ? 1 : upd_blocks(c->N);
     hipLaunchKernelGGL((k_tile_cg<D, T, Op>), dim3(xcd_grid(c->tiles.n_tiles)), dim3(tile_threads(c)), lds,
                        s, op, tile_args(c), fa, coords, r, dinv, pin, pout, q,
-                       reinterpret_cast<T *>(c->halo), sc, A, c->rz_part, upd_blocks(c->N), c->pq_part);
+                       reinterpret_cast<T *>(c->halo), sc, A, rz, nrz, c->pq_part);
     return FO_OK;
 }
 
@@ -675,8 +678,10 @@ static int launch_tile_cg_dim(const fo_ctx *c, int kind, const T *r, const T *di
 
 template <typename T>
 int launch_tile_cg(const fo_ctx *c, int kind, const T *r, const T *dinv, const T *pin, T *pout, T *q,
-                   SolveScalars *sc, int A, hipStream_t s)
+                   SolveScalars *sc, int A, hipStream_t s, bool fold)
 {
+    // large meshes: one block folds the update's r.z / r.r partials first
+    if (c->fold_rz && fold) launch_fold(c->rz_part, upd_blocks(c->N), 2, c->fold, s);
     int which = -1;
     if (kind == FUSED_ELAS) which = sizeof(T) == 8 ? FO_PROF_ELAS_TILE_FP64 : FO_PROF_ELAS_TILE_FP32;
     auto *pt = which >= 0 ? prof_slot(c, which) : nullptr;
@@ -687,9 +692,9 @@ int launch_tile_cg(const fo_ctx *c, int kind, const T *r, const T *dinv, const T
     return rc;
 }
 template int launch_tile_cg<double>(const fo_ctx *, int, const double *, const double *, const double *,
-                                    double *, double *, SolveScalars *, int, hipStream_t);
+                                    double *, double *, SolveScalars *, int, hipStream_t, bool);
 template int launch_tile_cg<float>(const fo_ctx *, int, const float *, const float *, const float *,
-                                   float *, float *, SolveScalars *, int, hipStream_t);
+                                   float *, float *, SolveScalars *, int, hipStream_t, bool);
 
 // ---------------------------------------------------------------------------
 // boundary facets of the descent operator, node-parallel (deterministic)
