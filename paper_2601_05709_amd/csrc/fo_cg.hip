@@ -222,10 +222,22 @@ __global__ __launch_bounds__(256) void k_residual64(const double *__restrict__ b
 __global__ __launch_bounds__(1024) void k_fold_partials(const double *__restrict__ part, int n, int sets,
                                                         double *__restrict__ out)
 {
+    constexpr int U = 16;  // loads in flight per thread; the sum order is the plain strided one
     __shared__ double lds[16];
+    const int nt = (int)blockDim.x;
     for (int k = 0; k < sets; ++k) {
-        const double v = block_sum_partials_any(part + (int64_t)k * n, n, lds);
-        if (threadIdx.x == 0) out[k] = v;
+        const double *p = part + (int64_t)k * n;
+        double s = 0.0;
+        for (int base = (int)threadIdx.x; base < n; base += U * nt) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = p[min(base + u * nt, n - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (base + u * nt < n) s += v[u];
+        }
+        s = block_sum_any(s, lds);
+        if (threadIdx.x == 0) out[k] = s;
     }
 }
 
