@@ -378,6 +378,24 @@ __global__ __launch_bounds__(64 * NC) void k_batch_apply(
     }
 }
 
+// This thread's share of sum_i v[i * stride], i < n (i = threadIdx.x,
+// + blockDim.x, ...), added in that order with eight loads in flight.
+__device__ __forceinline__ double strided_sum(const double *__restrict__ v, int stride, int n)
+{
+    constexpr int U = 8;
+    const int nt = (int)blockDim.x;
+    double s = 0.0;
+    for (int base = (int)threadIdx.x; base < n; base += U * nt) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = v[(int64_t)min(base + u * nt, n - 1) * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * nt < n) s += t[u];
+    }
+    return s;
+}
+
 // alpha_k = rho_k / (p_k . q_k), one block per column.
 __global__ __launch_bounds__(256) void k_batch_alpha(const BatchCtl *ctl, BatchCol *cols,
                                                      const double *__restrict__ pq_part,
@@ -390,9 +408,7 @@ __global__ __launch_bounds__(256) void k_batch_alpha(const BatchCtl *ctl, BatchC
         if (threadIdx.x == 0) cols[k].alpha = 0.0;
         return;
     }
-    double s = 0.0;
-    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) s += pq_part[(int64_t)t * S + k];
-    s = block_sum(s, lds);
+    const double s = block_sum(strided_sum(pq_part + k, S, n_tiles), lds);
     if (threadIdx.x == 0) {
         BatchCol &c = cols[k];
         c.pq = s;
@@ -423,10 +439,34 @@ __global__ __launch_bounds__(256) void k_batch_update(
     const int tid = threadIdx.x, col = tid % S, rg = tid / S;
     const float alpha = (float)cols[col].alpha;
     double rz = 0.0, rr = 0.0;
-    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += (int64_t)gridDim.x * RG) {
+    const int64_t step = (int64_t)gridDim.x * RG;
+    int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof;
+    if (!hrange) {  // every row of q in Q: four rows per thread and step, loads first
+        constexpr int U = 4;
+        for (; row < ndof; row += U * step) {
+            float qv[U], rv[U], dv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t rw = min(row + u * step, ndof - 1);
+                qv[u] = Q[rw * S + col];
+                rv[u] = R[rw * S + col];
+                dv[u] = dinv[rw];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (row + u * step >= ndof) break;
+                const float q = dv[u] == 0.f ? 0.f : qv[u];
+                const float r = rv[u] - alpha * q;
+                R[(row + u * step) * S + col] = r;
+                rz += (double)r * (double)(dv[u] * r);
+                rr += (double)r * (double)r;
+            }
+        }
+    }
+    for (; row < ndof; row += step) {
         const int64_t node = row / D;
         const int i = (int)(row - node * D);
-        const int2 hr = hrange ? hrange[node] : make_int2(-1, -1);
+        const int2 hr = hrange[node];
         float q;
         if (hr.x < 0) {
             q = Q[row * S + col];
@@ -467,11 +507,7 @@ __global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *col
     const int k = blockIdx.x;
     if (k == 0 && threadIdx.x == 0) ctl->it += 1;
     if (cols[k].done) return;
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        a += rz_part[(int64_t)i * S + k];
-        b += rz_part[((int64_t)nb + i) * S + k];
-    }
+    double a = strided_sum(rz_part + k, S, nb), b = strided_sum(rz_part + (int64_t)nb * S + k, S, nb);
     a = block_sum(a, lds);
     b = block_sum(b, lds);
     if (threadIdx.x == 0) {
