@@ -1364,7 +1364,10 @@ int batch_levelset(fo_ctx *c)
 // column: a column whose FP32 residual fell by inner_rtol is stopped, its
 // x64 += s x32 and r64 = b - K x64 (FP64) are formed, and it continues from
 // the replaced residual with its direction kept (rescaled), while the other
-// columns keep iterating.  Columns c0..c0+n-1 of b (ld) -> u.
+// columns keep iterating.  With the nodal operator, K x64 of all the columns
+// that finished together is one launch over the FP64 node blocks; the
+// element operator takes them one at a time through the FP64 element apply.
+// Columns c0..c0+n-1 of b (ld) -> u.
 static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t ld,
                        const fo_solve_opts *o, fo_solve_stats *st)
 {
@@ -1468,12 +1471,17 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         FO_HIP(hipMemcpyAsync(b.mask, b.mask_host, S, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_batch_accumulate, dim3(grid_of(nd * S)), dim3(256), 0, s, b.x64, b.x32, b.s2,
                            b.mask, S, nd * S);
-        for (int k = 0; k < S; ++k) {
-            if (!fin[k]) continue;
-            launch_gather_col<double, double>(b.x64 + k, S, nd, c->t64, nullptr, s);
-            FO_TRY(elas_apply64(c, c->t64, c->q64, s));
-            hipLaunchKernelGGL(k_batch_residual_col, dim3(grid_of(nd)), dim3(256), 0, s, b.b64, c->q64,
-                               c->fixed, b.r64, S, k, nd);
+        if (b.op == FO_BATCH_OP_NODAL && b.kb64) {
+            // every finished column at once, from the FP64 node blocks
+            FO_TRY(nodal_residual64(c, S, b.x64, b.b64, b.mask, b.r64, s));
+        } else {
+            for (int k = 0; k < S; ++k) {
+                if (!fin[k]) continue;
+                launch_gather_col<double, double>(b.x64 + k, S, nd, c->t64, nullptr, s);
+                FO_TRY(elas_apply64(c, c->t64, c->q64, s));
+                hipLaunchKernelGGL(k_batch_residual_col, dim3(grid_of(nd)), dim3(256), 0, s, b.b64, c->q64,
+                                   c->fixed, b.r64, S, k, nd);
+            }
         }
         FO_TRY(residual_norms(c, S));
         for (int k = 0; k < S; ++k) {

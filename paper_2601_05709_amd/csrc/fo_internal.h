@@ -217,12 +217,15 @@ struct BatchState {
     // the operator: FO_BATCH_OP_NODAL (default: assembled node blocks) or
     // FO_BATCH_OP_ELEMENT (element tiles above)
     int op = FO_BATCH_OP_NODAL;
-    int nb = 0;                         // NB: neighbour slots per node (a multiple of 8)
+    int nb = 0;                         // NB: neighbour slots per node (a multiple of nb_chunk)
+    int nb_chunk = 8;                   // neighbours per round of loads of the apply: 7 or 8
+    int kw = 0;                         // floats of blocks per node: NB d^2 rounded up to a multiple of 4
     int n_apply = 0;                    // blocks of the nodal apply at S columns (p.q partials)
     int32_t *nbr = nullptr;             // [N][NB] neighbour nodes, ascending, padded with the node
     int32_t *inc_ptr = nullptr;         // [N+1] node -> element incidence
     int32_t *inc_elem = nullptr;        // [(d+1) E] incident elements, ascending per node
-    float *kb = nullptr;                // [N][NB][d][d] blocks K_ij (per level set; 0 for padding)
+    float *kb = nullptr;                // [N][kw] blocks K_ij, [NB][d][d] then zeros (per level set; 0 for padding)
+    double *kb64 = nullptr;             // [N][NB][d][d] the same blocks unrounded (FP64 residuals)
     double *pq_nodal = nullptr;         // [n_apply][S] p.q partials of the nodal apply
     int nodal_occ[4] = {0, 0, 0, 0};    // resident blocks of the apply at S = 16, 32, 48, 64
     int64_t n_offdiag = 0;              // off-diagonal blocks (ordered node pairs sharing an element)

@@ -40,7 +40,7 @@ namespace fo {
 
 constexpr int kNodalWaves = 4;          // waves per block of the apply
 constexpr int kNodalMaxBlocks = 2048;   // blocks of the apply (p.q partials per block)
-constexpr int kNodalStage = 512;        // largest NB d^2 (floats) of the node-per-wave path
+constexpr int kNodalStage = 512;        // largest block floats per node (NB d^2, rounded up to 4)
 
 // Node groups of the apply: a wave takes 64 / SP nodes at a time.
 static int nodal_lanes(int S) { return S <= 16 ? 16 : (S <= 32 ? 32 : 64); }
@@ -63,23 +63,27 @@ int nodal_blocks(const fo_ctx *c, int S)
     return occ > 0 ? std::min(cap, occ) : cap;
 }
 
-// Dynamic LDS of the apply: two staging buffers of NB d^2 floats per wave.
-static size_t nodal_lds(int NB, int D) { return (size_t)kNodalWaves * 2 * NB * D * D * sizeof(float); }
+// Dynamic LDS of the apply: two staging buffers of KW floats (a node's
+// blocks) per wave.
+static size_t nodal_lds(int KW) { return (size_t)kNodalWaves * 2 * KW * sizeof(float); }
 
 // K_ij for every (node i, neighbour slot s): the sum over the elements that
 // contain both nodes, in ascending element order, of
 //   w_e (lam c_ar c_bk + mu c_ak c_br + mu delta_rk c_a . c_b),
 // a, b the local indices of i, j in e, c the cofactor vectors and
 // w_e = A_e / (d! |det|) (A_e = 1 in the material, the ersatz value
-// outside).  Padding slots (j = i) get zero blocks.
+// outside).  Padding slots (j = i) get zero blocks, and so do the KW - NB d^2
+// floats after a node's last block.  kb gets the blocks rounded to FP32, kb64
+// (nullable; [N][NB][d][d]) the FP64 sums.
 template <int D>
-__global__ __launch_bounds__(256) void k_nodal_assemble(const int32_t *__restrict__ nbr, int NB, int64_t N,
+__global__ __launch_bounds__(256) void k_nodal_assemble(const int32_t *__restrict__ nbr, int NB, int KW, int64_t N,
                                                         const int32_t *__restrict__ inc_ptr,
                                                         const int32_t *__restrict__ inc_elem,
                                                         const int32_t *__restrict__ conn, int64_t E,
                                                         const double *__restrict__ coords,
                                                         const uint8_t *__restrict__ chi, double ersatz,
-                                                        double lam, double mu, float *__restrict__ kb)
+                                                        double lam, double mu, float *__restrict__ kb,
+                                                        double *__restrict__ kb64)
 {
     constexpr int NV = D + 1;
     const int64_t total = N * NB;
@@ -143,20 +147,32 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(const int32_t *__restric
                         K[r][k] += w * (lam * (ca[r] * cb[k]) + mu * (ca[k] * cb[r]) + (r == k ? mu * dot : 0.0));
             }
         }
-        float *out = kb + task * (D * D);
+        const int s = (int)(task - i * NB);
+        float *out = kb + i * KW + s * (D * D);
 #pragma unroll
         for (int r = 0; r < D; ++r)
 #pragma unroll
             for (int k = 0; k < D; ++k) out[r * D + k] = (float)K[r][k];
+        if (s == NB - 1)
+            for (int t = NB * D * D; t < KW; ++t) kb[i * KW + t] = 0.f;
+        if (kb64) {
+            double *o64 = kb64 + task * (D * D);
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+#pragma unroll
+                for (int k = 0; k < D; ++k) o64[r * D + k] = K[r][k];
+        }
     }
 }
 
 // Q = K(phi) P on S columns (block vectors [n_dofs][S]); clamped rows of Q
 // are 0.  p.q partials per block and column (gridDim.x of them, a multiple
-// of 8).
-template <int D, int S>
+// of 8).  NB is a multiple of C, the neighbours taken per round of loads (7
+// or 8, whichever pads the largest neighbourhood less); a node's blocks start
+// every KW floats (KW a multiple of 4).
+template <int D, int S, int C>
 __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
-    const int32_t *__restrict__ nbr, const float *__restrict__ kb, int NB, int64_t N,
+    const int32_t *__restrict__ nbr, const float *__restrict__ kb, int NB, int KW, int64_t N,
     const float *__restrict__ P, float *__restrict__ Q, const uint8_t *__restrict__ fixed,
     double *__restrict__ pq_part, BatchCtl *ctl, const BatchCol *__restrict__ cols)
 {
@@ -185,15 +201,15 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     double pq = 0.0;
     if constexpr (NPW == 1) {
         // one node per wave: the node, its neighbour ids and their row
-        // addresses are wave-uniform (scalar loads); eight neighbours per
-        // round of loads (NB is a multiple of 8; padding slots add zero).  The
-        // node's blocks (NB d^2 floats, at most kNodalStage) are copied to
-        // the wave's LDS buffer in 16-byte pieces, the next node's while this
-        // one is contracted, and every lane reads its A operands from there
-        // (four distinct addresses per read): one coalesced load per node
-        // instead of a 12-byte load per lane and block.
-        extern __shared__ __align__(16) float s_kb[];  // [waves][2][NB d^2]
-        const int KW = NB * DD, KQ = KW / 4;
+        // addresses are wave-uniform (scalar loads); C neighbours per round
+        // of loads (padding slots add zero).  The node's blocks (KW floats, at
+        // most kNodalStage) are copied to the wave's LDS buffer in 16-byte
+        // pieces, the next node's while this one is contracted, and every
+        // lane reads its A operands from there (four distinct addresses per
+        // read): one coalesced load per node instead of a 12-byte load per
+        // lane and block.
+        extern __shared__ __align__(16) float s_kb[];  // [waves][2][KW]
+        const int KQ = KW / 4;
         float *kbuf = s_kb + wave * 2 * KW;
         f32x4 pre[kNodalStage / 256];
         auto fetch = [&](int64_t n) {
@@ -226,16 +242,16 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int32_t *nb = nbr + n * NB;
             const float *ka = kbuf + cur * KW + rr * D;
-            for (int s0 = 0; s0 < NB; s0 += 8) {
-                float xv[8][D];
+            for (int s0 = 0; s0 < NB; s0 += C) {
+                float xv[C][D];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < C; ++u) {
                     const int64_t j = nb[s0 + u];
 #pragma unroll
                     for (int k = 0; k < D; ++k) xv[u][k] = P[(j * D + k) * S + col];
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < C; ++u)
 #pragma unroll
                     for (int k = 0; k < D; ++k)
                         acc = __builtin_amdgcn_mfma_f32_4x4x1f32(ka[(s0 + u) * DD + k], xv[u][k] - xi[k], acc, 0, 0,
@@ -263,20 +279,31 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
         for (int k = 0; k < D; ++k) xi[k] = P[(n * D + k) * S + col];
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         const int32_t *nb = nbr + n * NB;
-        const float *kr = kb + n * NB * DD + rr * D;
-        for (int s0 = 0; s0 < NB; s0 += 4) {
-            const int4 j4 = *reinterpret_cast<const int4 *>(nb + s0);
-            const int jj[4] = {j4.x, j4.y, j4.z, j4.w};
-            float xv[4][D], kv[4][D];
+        const float *kr = kb + n * KW + rr * D;
+        // rounds of R neighbours: four (one 16-byte id load) when C = 8
+        constexpr int R = C % 4 == 0 ? 4 : C;
+        for (int s0 = 0; s0 < NB; s0 += R) {
+            int jj[R];
+            if constexpr (R == 4) {
+                const int4 j4 = *reinterpret_cast<const int4 *>(nb + s0);
+                jj[0] = j4.x;
+                jj[1] = j4.y;
+                jj[2] = j4.z;
+                jj[3] = j4.w;
+            } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < R; ++u) jj[u] = nb[s0 + u];
+            }
+            float xv[R][D], kv[R][D];
+#pragma unroll
+            for (int u = 0; u < R; ++u)
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     xv[u][k] = P[((int64_t)jj[u] * D + k) * S + col];
                     kv[u][k] = kr[(s0 + u) * DD + k];
                 }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < R; ++u)
 #pragma unroll
                 for (int k = 0; k < D; ++k)
                     acc = __builtin_amdgcn_mfma_f32_4x4x1f32(kv[u][k], xv[u][k] - xi[k], acc, 0, 0, 0);
@@ -301,6 +328,58 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     }
 }
 
+// R[:, k] = B[:, k] - K(phi) X[:, k] in FP64 (block vectors [n_dofs][S],
+// S <= 64) for the columns k with mask[k] set, clamped rows 0: the residual
+// of the FP64 refinement, from the unrounded blocks, in the same difference
+// form y_i = sum_{j != i} K_ij (x_j - x_i).  One node per wave at a time, lane
+// k its column: the node's neighbour ids and blocks are wave-uniform (scalar
+// loads), C neighbours' rows in flight per round.
+template <int D, int C>
+__global__ __launch_bounds__(256) void k_nodal_residual64(const int32_t *__restrict__ nbr,
+                                                          const double *__restrict__ kb64, int NB, int64_t N,
+                                                          const double *__restrict__ X,
+                                                          const double *__restrict__ B,
+                                                          const uint8_t *__restrict__ fixed,
+                                                          const uint8_t *__restrict__ mask,
+                                                          double *__restrict__ R, int S)
+{
+    constexpr int DD = D * D;
+    const int lane = threadIdx.x & 63;
+    if (lane >= S || !mask[lane]) return;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t i = wave; i < N; i += nw) {
+        double xi[D], acc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            xi[k] = X[(i * D + k) * S + lane];
+            acc[k] = 0.0;
+        }
+        const int32_t *nb = nbr + i * NB;
+        const double *kr = kb64 + i * NB * DD;
+        for (int s0 = 0; s0 < NB; s0 += C) {
+            double dx[C][D];
+#pragma unroll
+            for (int u = 0; u < C; ++u) {
+                const int64_t j = nb[s0 + u];
+#pragma unroll
+                for (int k = 0; k < D; ++k) dx[u][k] = X[(j * D + k) * S + lane] - xi[k];
+            }
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+#pragma unroll
+                    for (int r = 0; r < D; ++r) acc[r] = fma(kr[(s0 + u) * DD + r * D + k], dx[u][k], acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            const int64_t row = i * D + r;
+            R[row * S + lane] = fixed[row] ? 0.0 : B[row * S + lane] - acc[r];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -308,8 +387,9 @@ template <int D>
 static int nodal_occupancy(fo_ctx *c);
 
 // Node -> element incidence (ascending element ids) and the neighbour lists
-// (ascending, padded with the node itself to NB, a multiple of 8), from the
-// host mesh in the context's element order.  Allocates the device arrays in
+// (ascending, padded with the node itself to NB, the largest neighbour count
+// rounded up to a multiple of 7 or of 8, whichever is smaller; 8 on a tie),
+// from the host mesh in the context's element order.  Allocates the device arrays in
 // the context (measure mode: counts them only).  A mesh whose largest
 // neighbourhood exceeds the apply's staging buffer gets no nodal arrays and
 // keeps the element operator.
@@ -329,7 +409,7 @@ int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
     }
     std::vector<int32_t> nb_cnt(N);
     std::vector<std::vector<int32_t>> lists(N);
-    int NB = 8;
+    int maxdeg = 1;
     for (int64_t i = 0; i < N; ++i) {
         std::vector<int32_t> &l = lists[i];
         for (int32_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q)
@@ -339,8 +419,10 @@ int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
             }
         std::sort(l.begin(), l.end());
         l.erase(std::unique(l.begin(), l.end()), l.end());
-        NB = std::max(NB, (int)((l.size() + 7) / 8 * 8));
+        maxdeg = std::max(maxdeg, (int)l.size());
     }
+    const int chunk = (maxdeg + 6) / 7 * 7 < (maxdeg + 7) / 8 * 8 ? 7 : 8;
+    const int NB = (maxdeg + chunk - 1) / chunk * chunk, KW = (NB * D * D + 3) / 4 * 4;
     std::vector<int32_t> nbr((size_t)N * NB);
     int64_t offdiag = 0;
     for (int64_t i = 0; i < N; ++i) {
@@ -348,18 +430,21 @@ int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn)
         offdiag += (int64_t)l.size();
         for (int s = 0; s < NB; ++s) nbr[(size_t)i * NB + s] = s < (int)l.size() ? l[s] : (int32_t)i;
     }
-    if (NB * D * D > kNodalStage) {  // neighbourhoods too large: element operator only
+    if (KW > kNodalStage) {  // neighbourhoods too large: element operator only
         b.op = FO_BATCH_OP_ELEMENT;
         return FO_OK;
     }
     b.nb = NB;
+    b.nb_chunk = chunk;
+    b.kw = KW;
     b.n_offdiag = offdiag;
     b.n_apply = nodal_block_cap(N, b.S);
     const size_t before = c->bytes;
     FO_TRY(ctx_alloc_n(c, &b.nbr, nbr.size()));
     FO_TRY(ctx_alloc_n(c, &b.inc_ptr, inc_ptr.size()));
     FO_TRY(ctx_alloc_n(c, &b.inc_elem, inc_elem.size()));
-    FO_TRY(ctx_alloc_n(c, &b.kb, (size_t)N * NB * D * D));
+    FO_TRY(ctx_alloc_n(c, &b.kb, (size_t)N * KW));
+    FO_TRY(ctx_alloc_n(c, &b.kb64, (size_t)N * NB * D * D));
     FO_TRY(ctx_alloc_n(c, &b.pq_nodal, (size_t)b.n_apply * b.S));
     b.nodal_bytes = (int64_t)(c->bytes - before);
     if (c->measure) return FO_OK;
@@ -383,11 +468,11 @@ int nodal_levelset(fo_ctx *c)
     const int64_t total = c->N * b.nb;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     if (c->dim == 2)
-        hipLaunchKernelGGL(k_nodal_assemble<2>, dim3(grid), dim3(256), 0, c->stream, b.nbr, b.nb, c->N, b.inc_ptr,
-                           b.inc_elem, c->conn, c->E, c->coords, c->chi, c->ersatz, c->lam, c->mu, b.kb);
+        hipLaunchKernelGGL(k_nodal_assemble<2>, dim3(grid), dim3(256), 0, c->stream, b.nbr, b.nb, b.kw, c->N, b.inc_ptr,
+                           b.inc_elem, c->conn, c->E, c->coords, c->chi, c->ersatz, c->lam, c->mu, b.kb, b.kb64);
     else
-        hipLaunchKernelGGL(k_nodal_assemble<3>, dim3(grid), dim3(256), 0, c->stream, b.nbr, b.nb, c->N, b.inc_ptr,
-                           b.inc_elem, c->conn, c->E, c->coords, c->chi, c->ersatz, c->lam, c->mu, b.kb);
+        hipLaunchKernelGGL(k_nodal_assemble<3>, dim3(grid), dim3(256), 0, c->stream, b.nbr, b.nb, b.kw, c->N, b.inc_ptr,
+                           b.inc_elem, c->conn, c->E, c->coords, c->chi, c->ersatz, c->lam, c->mu, b.kb, b.kb64);
     FO_HIP(hipGetLastError());
     return FO_OK;
 }
@@ -398,8 +483,30 @@ static void nodal_apply_t(const fo_ctx *c, const float *P, float *Q, BatchCtl *c
 {
     const BatchState &b = c->batch;
     const int nblk = nodal_blocks(c, S);
-    hipLaunchKernelGGL((k_nodal_apply<D, S>), dim3(nblk), dim3(64 * kNodalWaves), nodal_lds(b.nb, D), s,
-                       b.nbr, b.kb, b.nb, c->N, P, Q, c->fixed, b.pq_nodal, ctl, cols);
+    if (b.nb_chunk == 7)
+        hipLaunchKernelGGL((k_nodal_apply<D, S, 7>), dim3(nblk), dim3(64 * kNodalWaves), nodal_lds(b.kw), s,
+                           b.nbr, b.kb, b.nb, b.kw, c->N, P, Q, c->fixed, b.pq_nodal, ctl, cols);
+    else
+        hipLaunchKernelGGL((k_nodal_apply<D, S, 8>), dim3(nblk), dim3(64 * kNodalWaves), nodal_lds(b.kw), s,
+                           b.nbr, b.kb, b.nb, b.kw, c->N, P, Q, c->fixed, b.pq_nodal, ctl, cols);
+}
+
+int nodal_residual64(const fo_ctx *c, int S, const double *X, const double *B, const uint8_t *mask, double *R,
+                     hipStream_t s)
+{
+    const BatchState &b = c->batch;
+    if (!b.kb64 || S > 64) return FO_ERR_ARG;
+    const int grid = (int)std::min<int64_t>((c->N + 3) / 4, 2048);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, b.nbr, (const double *)b.kb64, b.nb, c->N, X, B,
+                           c->fixed, mask, R, S);
+    };
+    if (c->dim == 2)
+        b.nb_chunk == 7 ? go(k_nodal_residual64<2, 7>) : go(k_nodal_residual64<2, 8>);
+    else
+        b.nb_chunk == 7 ? go(k_nodal_residual64<3, 7>) : go(k_nodal_residual64<3, 8>);
+    FO_HIP(hipGetLastError());
+    return FO_OK;
 }
 
 // Resident blocks of every column-width instance (outside graph capture).
@@ -408,11 +515,15 @@ static int nodal_occupancy(fo_ctx *c)
 {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) return FO_ERR_HIP;
-    const void *fn[4] = {(const void *)k_nodal_apply<D, 16>, (const void *)k_nodal_apply<D, 32>,
-                         (const void *)k_nodal_apply<D, 48>, (const void *)k_nodal_apply<D, 64>};
+    const bool c7 = c->batch.nb_chunk == 7;
+    const void *fn[4] = {
+        c7 ? (const void *)k_nodal_apply<D, 16, 7> : (const void *)k_nodal_apply<D, 16, 8>,
+        c7 ? (const void *)k_nodal_apply<D, 32, 7> : (const void *)k_nodal_apply<D, 32, 8>,
+        c7 ? (const void *)k_nodal_apply<D, 48, 7> : (const void *)k_nodal_apply<D, 48, 8>,
+        c7 ? (const void *)k_nodal_apply<D, 64, 7> : (const void *)k_nodal_apply<D, 64, 8>};
     for (int k = 0; k < 4; ++k) {
         int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn[k], 64 * kNodalWaves, nodal_lds(c->batch.nb, D)) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn[k], 64 * kNodalWaves, nodal_lds(c->batch.kw)) !=
             hipSuccess)
             return FO_ERR_HIP;
         c->batch.nodal_occ[k] = std::max(1, per) * cus;

@@ -285,7 +285,9 @@ def test_nodal_operator_shape_matches_the_mesh_edges():
         ctx = fo.Context.from_workload(w, max_rhs=64)
         ns = ctx.nodal_stats()
         assert ns["off_diagonal_blocks"] == 2 * len(pairs)
-        assert ns["slots"] >= deg.max() and ns["slots"] % 8 == 0
+        # the largest neighbourhood padded to a multiple of 7 or 8, whichever is smaller
+        dm = int(deg.max())
+        assert ns["slots"] == min(-(-dm // 7) * 7, -(-dm // 8) * 8)
         d = m.dim
         assert ns["bytes"] >= m.n_nodes * ns["slots"] * (4 + 4 * d * d)
         assert fo.Context.from_workload(w, max_rhs=1).nodal_stats()["slots"] == 0
