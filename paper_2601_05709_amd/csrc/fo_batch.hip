@@ -402,13 +402,17 @@ __global__ __launch_bounds__(256) void k_batch_alpha(const BatchCtl *ctl, BatchC
                                                      int n_tiles, int S)
 {
     __shared__ double lds[4];
-    if (ctl->done) return;
     const int k = blockIdx.x;
-    if (cols[k].done) {
+    // the partials' loads go out together with the control loads: the grid is
+    // one round of blocks, so a chain of dependent loads is not hidden
+    const int stop = ctl->done, col_done = cols[k].done;
+    const double part = strided_sum(pq_part + k, S, n_tiles);
+    if (stop) return;
+    if (col_done) {
         if (threadIdx.x == 0) cols[k].alpha = 0.0;
         return;
     }
-    const double s = block_sum(strided_sum(pq_part + k, S, n_tiles), lds);
+    const double s = block_sum(part, lds);
     if (threadIdx.x == 0) {
         BatchCol &c = cols[k];
         c.pq = s;
@@ -434,31 +438,48 @@ __global__ __launch_bounds__(256) void k_batch_update(
     const float *__restrict__ halo, int64_t ndof, double *__restrict__ rz_part)
 {
     constexpr int RG = 256 / S;
+    constexpr int U = 4;
     __shared__ double red[2][256];
-    if (ctl->done) return;
     const int tid = threadIdx.x, col = tid % S, rg = tid / S;
-    const float alpha = (float)cols[col].alpha;
-    double rz = 0.0, rr = 0.0;
     const int64_t step = (int64_t)gridDim.x * RG;
     int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof;
-    if (!hrange) {  // every row of q in Q: four rows per thread and step, loads first
-        constexpr int U = 4;
+    // every row of q in Q (hrange null): four rows per thread and step, the
+    // next step's loads issued before this step's stores (they are the
+    // thread's own later rows); the first step's go out together with the
+    // control loads, since the grid is one round of blocks and a chain of
+    // dependent loads ahead of the data would not be hidden
+    float qv[U], rv[U], dv[U];
+    auto load = [&](int64_t r0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t rw = min(r0 + u * step, ndof - 1);
+            qv[u] = Q[rw * S + col];
+            rv[u] = R[rw * S + col];
+            dv[u] = dinv[rw];
+        }
+    };
+    if (!hrange && row < ndof) load(row);
+    const int stop = ctl->done;
+    const float alpha = (float)cols[col].alpha;
+    if (stop) return;
+    double rz = 0.0, rr = 0.0;
+    if (!hrange) {
         for (; row < ndof; row += U * step) {
-            float qv[U], rv[U], dv[U];
+            float qc[U], rc[U], dc[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t rw = min(row + u * step, ndof - 1);
-                qv[u] = Q[rw * S + col];
-                rv[u] = R[rw * S + col];
-                dv[u] = dinv[rw];
+                qc[u] = qv[u];
+                rc[u] = rv[u];
+                dc[u] = dv[u];
             }
+            if (row + U * step < ndof) load(row + U * step);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (row + u * step >= ndof) break;
-                const float q = dv[u] == 0.f ? 0.f : qv[u];
-                const float r = rv[u] - alpha * q;
+                const float q = dc[u] == 0.f ? 0.f : qc[u];
+                const float r = rc[u] - alpha * q;
                 R[(row + u * step) * S + col] = r;
-                rz += (double)r * (double)(dv[u] * r);
+                rz += (double)r * (double)(dc[u] * r);
                 rr += (double)r * (double)r;
             }
         }
@@ -503,11 +524,12 @@ __global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *col
                                                     int S)
 {
     __shared__ double lds[4];
-    if (ctl->done) return;
     const int k = blockIdx.x;
-    if (k == 0 && threadIdx.x == 0) ctl->it += 1;
-    if (cols[k].done) return;
+    const int stop = ctl->done, col_done = cols[k].done;  // loaded together with the partials
     double a = strided_sum(rz_part + k, S, nb), b = strided_sum(rz_part + (int64_t)nb * S + k, S, nb);
+    if (stop) return;
+    if (k == 0 && threadIdx.x == 0) ctl->it += 1;
+    if (col_done) return;
     a = block_sum(a, lds);
     b = block_sum(b, lds);
     if (threadIdx.x == 0) {
@@ -545,26 +567,42 @@ __global__ __launch_bounds__(256) void k_batch_direction(const BatchCtl *ctl,
                                                          const float *__restrict__ dinv, int64_t ndof)
 {
     constexpr int RG = 256 / S;
-    if (!mask && ctl->done) return;
     const int tid = threadIdx.x, col = tid % S, rg = tid / S;
+    const int64_t step = (int64_t)gridDim.x * RG;
+    int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof;
+    // the next step's loads are issued before this step's stores (the
+    // thread's own later rows); the first step's, all four streams, go out
+    // together with the control loads
+    float pv[2] = {0.f, 0.f}, xv[2] = {0.f, 0.f}, rv[2] = {0.f, 0.f}, dv[2] = {0.f, 0.f};
+    auto load = [&](int64_t r0, bool lx, bool lr) {
+        const bool two = r0 + step < ndof;
+        const int64_t ix0 = r0 * S + col, ix1 = two ? ix0 + step * S : ix0;
+        pv[0] = P[ix0];
+        pv[1] = P[ix1];
+        if (lx) {
+            xv[0] = X[ix0];
+            xv[1] = X[ix1];
+        }
+        if (lr) {
+            rv[0] = R[ix0];
+            rv[1] = R[ix1];
+            dv[0] = dinv[r0];
+            dv[1] = dinv[two ? r0 + step : r0];
+        }
+    };
+    if (row < ndof) load(row, true, true);
+    if (!mask && ctl->done) return;
     const bool dir = mask ? mask[col] != 0 : !cols[col].done;
     const float alpha = mask ? 0.f : (float)cols[col].alpha;
     if (!dir && alpha == 0.f) return;
     const float beta = (float)cols[col].beta;
-    const int64_t step = (int64_t)gridDim.x * RG;
-    for (int64_t row = rg < RG ? (int64_t)blockIdx.x * RG + rg : ndof; row < ndof; row += 2 * step) {
+    for (; row < ndof; row += 2 * step) {
         const bool two = row + step < ndof;
         const int64_t ix0 = row * S + col, ix1 = two ? ix0 + step * S : ix0;
-        const float p0 = P[ix0], p1 = P[ix1];
-        float x0 = 0.f, x1 = 0.f, z0 = 0.f, z1 = 0.f;
-        if (alpha != 0.f) {
-            x0 = X[ix0];
-            x1 = X[ix1];
-        }
-        if (dir) {
-            z0 = dinv[row] * R[ix0];
-            z1 = dinv[two ? row + step : row] * R[ix1];
-        }
+        const float p0 = pv[0], p1 = pv[1];
+        const float x0 = xv[0], x1 = xv[1];
+        const float z0 = dv[0] * rv[0], z1 = dv[1] * rv[1];
+        if (row + 2 * step < ndof) load(row + 2 * step, alpha != 0.f, dir);
         if (alpha != 0.f) {
             X[ix0] = x0 + alpha * p0;
             if (two) X[ix1] = x1 + alpha * p1;

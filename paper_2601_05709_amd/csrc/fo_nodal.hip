@@ -181,9 +181,6 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     __shared__ double red[64 * kNodalWaves];
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
-    if (tid == 0) s_stop = batch_stop(ctl, cols, S);
-    __syncthreads();
-    if (s_stop) return;
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int cl = lane % SP, col = cl < S ? cl : S - 1;
     const bool live_col = cl < S;
@@ -198,6 +195,22 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     const int nb_x = (int)(gridDim.x >> 3), W = nb_x * kNodalWaves;
     const int64_t xs = (int64_t)(blk & 7) * per_x, g1 = std::min<int64_t>(groups, xs + per_x);
     const int64_t g0 = xs + (int64_t)(blk >> 3) * kNodalWaves;
+    // one node per wave: the first node's blocks are loaded before the stop
+    // test (the grid is one round of blocks, so the test's dependent loads
+    // would otherwise stand in front of every block's first data)
+    const int KQ = KW / 4;
+    f32x4 pre[kNodalStage / 256];
+    auto fetch = [&](int64_t n) {
+        const f32x4 *src = reinterpret_cast<const f32x4 *>(kb + n * KW);
+#pragma unroll
+        for (int q = 0; q < kNodalStage / 256; ++q)
+            if (lane + 64 * q < KQ) pre[q] = src[lane + 64 * q];
+    };
+    if constexpr (NPW == 1)
+        if (g0 + wave < g1) fetch(g0 + wave);
+    if (tid == 0) s_stop = batch_stop(ctl, cols, S);
+    __syncthreads();
+    if (s_stop) return;
     double pq = 0.0;
     if constexpr (NPW == 1) {
         // one node per wave: the node, its neighbour ids and their row
@@ -209,15 +222,7 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
         // read): one coalesced load per node instead of a 12-byte load per
         // lane and block.
         extern __shared__ __align__(16) float s_kb[];  // [waves][2][KW]
-        const int KQ = KW / 4;
         float *kbuf = s_kb + wave * 2 * KW;
-        f32x4 pre[kNodalStage / 256];
-        auto fetch = [&](int64_t n) {
-            const f32x4 *src = reinterpret_cast<const f32x4 *>(kb + n * KW);
-#pragma unroll
-            for (int q = 0; q < kNodalStage / 256; ++q)
-                if (lane + 64 * q < KQ) pre[q] = src[lane + 64 * q];
-        };
         auto stash = [&](int half) {
             f32x4 *dst = reinterpret_cast<f32x4 *>(kbuf + half * KW);
 #pragma unroll
@@ -229,10 +234,7 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
             asm volatile("" ::: "memory");
         };
         int cur = 0;
-        if (g0 + wave < g1) {
-            fetch(g0 + wave);
-            stash(0);
-        }
+        if (g0 + wave < g1) stash(0);
         for (int64_t n = g0 + wave; n < g1; n += W) {
             const int64_t nn = n + W;
             if (nn < g1) fetch(nn);
