@@ -12,20 +12,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Whether the batched solve is over: marked done, the iteration cap reached,
 // or every one of the S columns done.  Read by thread 0 of every block of an
-// operator launch from state that no kernel of that launch writes, so all
-// blocks agree; block 0 records the decision.
+// operator launch from state that no kernel of that launch writes (block 0
+// may set done, which only confirms the same decision), so all blocks agree;
+// block 0 records the decision.  Every field is loaded at once: one round
+// trip, not one per test.
 __device__ __forceinline__ int batch_stop(BatchCtl *ctl, const BatchCol *cols, int S)
 {
-    int stop = ctl->done;
-    if (!stop) {
-        stop = ctl->it >= ctl->max_it;
-        if (!stop) {
-            int all = 1;
-            for (int k = 0; k < S; ++k) all &= cols[k].done;
-            stop = all;
-        }
-        if (stop && blockIdx.x == 0) ctl->done = 1;
-    }
+    const int done = ctl->done, it = ctl->it, max_it = ctl->max_it;
+    int all = 1;
+    for (int k = 0; k < S; ++k) all &= cols[k].done;
+    const int stop = done || it >= max_it || all;
+    if (stop && !done && blockIdx.x == 0) ctl->done = 1;
     return stop;
 }
 
