@@ -1475,6 +1475,9 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
     if (select(fin)) FO_TRY(restart_columns());
     int result = FO_NOT_CONVERGED;
     int32_t it_total = 0;
+    // the host copy of the control state is current after each chunk's
+    // readback; a restart (which clears done) makes it stale
+    bool ctl_stale = true;
     while (true) {
         bool all = true;
         for (int k = 0; k < S; ++k) all = all && conv[k];
@@ -1482,26 +1485,29 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
             result = FO_OK;
             break;
         }
-        FO_TRY(poll_batch(c));
+        if (ctl_stale) FO_TRY(poll_batch(c));
+        ctl_stale = false;
         it_total = b.ctl_host->it;
         if (it_total >= o->max_iter) break;
-        if (!b.ctl_host->done) {
-            const int32_t before = b.ctl_host->it;
+        const bool ran = !b.ctl_host->done;
+        const int32_t before = b.ctl_host->it;
+        if (ran) {
             auto key = std::make_tuple(100 + NC, chunk, b.version, b.op);  // the operator is captured
             FO_TRY(graph_chunk(c, key, [&](hipStream_t ws) {
                 for (int j = 0; j < chunk; ++j) batch_iteration(c, NC, ws);
                 return (int)FO_OK;
             }));
-            FO_TRY(poll_batch(c));
-            if (!b.ctl_host->done && b.ctl_host->it == before) {
-                hipError_t e = hipGetLastError();
-                std::fprintf(stderr, "libfo: batched CG chunk made no progress (%s)\n", hipGetErrorString(e));
-                return FO_ERR_HIP;
-            }
         }
-        // columns that finished their phase (or broke down)
+        // the control state and the columns that finished their phase (or
+        // broke down): one readback, one wait
+        FO_HIP(hipMemcpyAsync(b.ctl_host, b.ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
         FO_HIP(hipMemcpyAsync(b.cols_host, b.cols, S * sizeof(BatchCol), hipMemcpyDeviceToHost, s));
         FO_HIP(fo::wait_stream(s));
+        if (ran && !b.ctl_host->done && b.ctl_host->it == before) {
+            hipError_t e = hipGetLastError();
+            std::fprintf(stderr, "libfo: batched CG chunk made no progress (%s)\n", hipGetErrorString(e));
+            return FO_ERR_HIP;
+        }
         bool any = false;
         for (int k = 0; k < S; ++k) {
             fin[k] = !conv[k] && b.cols_host[k].done;
@@ -1513,8 +1519,14 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         hipLaunchKernelGGL(k_batch_accumulate, dim3(grid_of(nd * S)), dim3(256), 0, s, b.x64, b.x32, b.s2,
                            b.mask, S, nd * S);
         if (b.op == FO_BATCH_OP_NODAL && b.kb64) {
-            // every finished column at once, from the FP64 node blocks
-            FO_TRY(nodal_residual64(c, S, b.x64, b.b64, b.mask, b.r64, s));
+            // every finished column at once, from the FP64 node blocks, with
+            // the norms of the finished columns (the only ones read below)
+            int nbk = 0;
+            FO_TRY(nodal_residual64(c, S, b.x64, b.b64, b.mask, b.r64, b.rz_part, (int64_t)2 * b.n_upd * b.S, &nbk,
+                                    s));
+            hipLaunchKernelGGL(k_batch_colsum, dim3(S), dim3(256), 0, s, b.rz_part, nbk, S, b.s2 + S);
+            FO_HIP(hipMemcpyAsync(b.s2_host, b.s2 + S, S * sizeof(double), hipMemcpyDeviceToHost, s));
+            FO_HIP(fo::wait_stream(s));
         } else {
             for (int k = 0; k < S; ++k) {
                 if (!fin[k]) continue;
@@ -1523,8 +1535,8 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
                 hipLaunchKernelGGL(k_batch_residual_col, dim3(grid_of(nd)), dim3(256), 0, s, b.b64, c->q64,
                                    c->fixed, b.r64, S, k, nd);
             }
+            FO_TRY(residual_norms(c, S));
         }
-        FO_TRY(residual_norms(c, S));
         for (int k = 0; k < S; ++k) {
             if (!fin[k]) continue;
             ++outer[k];
@@ -1553,7 +1565,10 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
                 fail[k] = 1;
             }
         }
-        if (select(fin)) FO_TRY(restart_columns());
+        if (select(fin)) {
+            FO_TRY(restart_columns());
+            ctl_stale = true;
+        }
     }
     // columns that FP32 cannot resolve: FP64 CG on their residual equation
     int64_t extra = 0;

@@ -159,9 +159,11 @@ int nodal_blocks(const fo_ctx *c, int S);
 int nodal_setup(fo_ctx *c, const std::vector<int32_t> &conn);
 int nodal_levelset(fo_ctx *c);
 // R[:, k] = B[:, k] - K(phi) X[:, k] in FP64 for the masked columns of
-// [n_dofs][S] blocks (S <= 64; clamped rows 0).  FO_ERR_ARG without blocks.
+// [n_dofs][S] blocks (S <= 64; clamped rows 0), and per launched block and
+// column the partial sum of squares of the new R (part: [*nblk][S], at most
+// part_cap doubles; 0 outside the mask).  FO_ERR_ARG without blocks.
 int nodal_residual64(const fo_ctx *c, int S, const double *X, const double *B, const uint8_t *mask, double *R,
-                     hipStream_t s);
+                     double *part, int64_t part_cap, int *nblk, hipStream_t s);
 void nodal_apply_launch(const fo_ctx *c, int NC, const float *P, float *Q, BatchCtl *ctl, const BatchCol *cols,
                         hipStream_t s);
 int batch_apply_block(fo_ctx *c, int NC, const float *X, float *Y);

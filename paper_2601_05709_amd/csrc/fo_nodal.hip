@@ -333,8 +333,10 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
 // R[:, k] = B[:, k] - K(phi) X[:, k] in FP64 (block vectors [n_dofs][S],
 // S <= 64) for the columns k with mask[k] set, clamped rows 0: the residual
 // of the FP64 refinement, from the unrounded blocks, in the same difference
-// form y_i = sum_{j != i} K_ij (x_j - x_i).  One node per wave at a time, lane
-// k its column: the node's neighbour ids and blocks are wave-uniform (scalar
+// form y_i = sum_{j != i} K_ij (x_j - x_i), and per block and column the
+// partial sum of the squares of the new residual (part [gridDim.x][S]; 0 for
+// the columns outside the mask).  One node per wave at a time, lane k its
+// column: the node's neighbour ids and blocks are wave-uniform (scalar
 // loads), C neighbours' rows in flight per round.
 template <int D, int C>
 __global__ __launch_bounds__(256) void k_nodal_residual64(const int32_t *__restrict__ nbr,
@@ -343,14 +345,21 @@ __global__ __launch_bounds__(256) void k_nodal_residual64(const int32_t *__restr
                                                           const double *__restrict__ B,
                                                           const uint8_t *__restrict__ fixed,
                                                           const uint8_t *__restrict__ mask,
-                                                          double *__restrict__ R, int S)
+                                                          double *__restrict__ R, int S,
+                                                          double *__restrict__ part)
 {
     constexpr int DD = D * D;
+    __shared__ double red[256];
     const int lane = threadIdx.x & 63;
-    if (lane >= S || !mask[lane]) return;
+    const bool act = lane < S && mask[lane];
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t i = wave; i < N; i += nw) {
+    double ss = 0.0;
+    // the node loop stays wave-uniform (ids and blocks through scalar loads);
+    // a wave with no column in the mask skips it, other lanes are predicated
+    const bool any = __any(act);
+    for (int64_t i = any ? wave : N; i < N; i += nw) {
+        if (!act) continue;
         double xi[D], acc[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -377,8 +386,17 @@ __global__ __launch_bounds__(256) void k_nodal_residual64(const int32_t *__restr
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             const int64_t row = i * D + r;
-            R[row * S + lane] = fixed[row] ? 0.0 : B[row * S + lane] - acc[r];
+            const double v = fixed[row] ? 0.0 : B[row * S + lane] - acc[r];
+            R[row * S + lane] = v;
+            ss += v * v;
         }
+    }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    if ((int)threadIdx.x < S) {
+        double a = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += red[w * 64 + threadIdx.x];
+        part[(int64_t)blockIdx.x * S + threadIdx.x] = a;
     }
 }
 
@@ -494,20 +512,21 @@ static void nodal_apply_t(const fo_ctx *c, const float *P, float *Q, BatchCtl *c
 }
 
 int nodal_residual64(const fo_ctx *c, int S, const double *X, const double *B, const uint8_t *mask, double *R,
-                     hipStream_t s)
+                     double *part, int64_t part_cap, int *nblk, hipStream_t s)
 {
     const BatchState &b = c->batch;
-    if (!b.kb64 || S > 64) return FO_ERR_ARG;
-    const int grid = (int)std::min<int64_t>((c->N + 3) / 4, 2048);
+    if (!b.kb64 || S > 64 || part_cap < S) return FO_ERR_ARG;
+    const int grid = (int)std::min<int64_t>(std::min<int64_t>((c->N + 3) / 4, 2048), part_cap / S);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, b.nbr, (const double *)b.kb64, b.nb, c->N, X, B,
-                           c->fixed, mask, R, S);
+                           c->fixed, mask, R, S, part);
     };
     if (c->dim == 2)
         b.nb_chunk == 7 ? go(k_nodal_residual64<2, 7>) : go(k_nodal_residual64<2, 8>);
     else
         b.nb_chunk == 7 ? go(k_nodal_residual64<3, 7>) : go(k_nodal_residual64<3, 8>);
     FO_HIP(hipGetLastError());
+    *nblk = grid;
     return FO_OK;
 }
 
