@@ -516,9 +516,15 @@ __global__ __launch_bounds__(256) void k_batch_update(
     }
 }
 
-// Per column: convergence on r.r, beta = rho_new / rho.  A column that
-// converges keeps the rho of the residual that built its direction (the
-// direction is not updated), so a later phase continues from it.
+// Per column: the phase target on r.r, beta = rho_new / rho.  A column at
+// its target is marked reached and keeps iterating: the operator costs the
+// same for every column of the block, and the host ends phases only at the
+// end of a chunk of iterations, so the iterations up to there lower its
+// residual further instead of idling.  A column stopped at its cap keeps the
+// rho of the residual that built its direction (the direction is not
+// updated), so the next phase continues it with the CG coefficient of the
+// replaced residual; a reached column's direction already belongs to its
+// latest residual and the next phase keeps it as it is (rescaled).
 __global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *cols,
                                                     const double *__restrict__ rz_part, int nb,
                                                     int S)
@@ -540,15 +546,18 @@ __global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *col
             c.status = FO_ERR_BREAKDOWN;
             c.done = 1;
             c.fresh = 1;
-        } else if (b <= c.tol2) {
-            c.done = 1;
-        } else if (++c.it >= c.cap) {  // stagnating phase: stop, restart after the replacement
-            c.done = 1;
-            c.capped = 1;
-            c.fresh = 1;
         } else {
-            c.beta = c.rho > 0.0 ? a / c.rho : 0.0;
-            c.rho = a;
+            if (b <= c.tol2) c.reached = 1;
+            if (++c.it >= c.cap) {  // at the cap: stop; short of the target it stagnated (restart)
+                c.done = 1;
+                if (!c.reached) {
+                    c.capped = 1;
+                    c.fresh = 1;
+                }
+            } else {
+                c.beta = c.rho > 0.0 ? a / c.rho : 0.0;
+                c.rho = a;
+            }
         }
     }
 }
@@ -557,7 +566,8 @@ __global__ __launch_bounds__(256) void k_batch_beta(BatchCtl *ctl, BatchCol *col
 // in this iteration (alpha != 0), then p = D^-1 r + beta p for the columns
 // still running.  Phase start (mask != null): p = D^-1 r + beta p for the
 // columns whose residual was just replaced (beta = the phase coefficient),
-// x untouched.  Two rows per thread and step, loads first.
+// or p = beta p for those that keep their direction (keep), x untouched.
+// Two rows per thread and step, loads first.
 template <int S>
 __global__ __launch_bounds__(256) void k_batch_direction(const BatchCtl *ctl,
                                                          const BatchCol *__restrict__ cols,
@@ -599,6 +609,7 @@ __global__ __launch_bounds__(256) void k_batch_direction(const BatchCtl *ctl,
     const float alpha = mask ? 0.f : (float)cols[col].alpha;
     if (!dir && alpha == 0.f) return;
     const float beta = (float)cols[col].beta;
+    const bool keep = mask && cols[col].keep;
     for (; row < ndof; row += 2 * step) {
         const bool two = row + step < ndof;
         const int64_t ix0 = row * S + col, ix1 = two ? ix0 + step * S : ix0;
@@ -611,8 +622,8 @@ __global__ __launch_bounds__(256) void k_batch_direction(const BatchCtl *ctl,
             if (two) __builtin_nontemporal_store(x1 + alpha * p1, X + ix1);
         }
         if (dir) {
-            P[ix0] = beta == 0.f ? z0 : z0 + beta * p0;
-            if (two) P[ix1] = beta == 0.f ? z1 : z1 + beta * p1;
+            P[ix0] = keep ? beta * p0 : (beta == 0.f ? z0 : z0 + beta * p0);
+            if (two) P[ix1] = keep ? beta * p1 : (beta == 0.f ? z1 : z1 + beta * p1);
         }
     }
 }
@@ -685,9 +696,21 @@ __global__ __launch_bounds__(256) void k_batch_phase(BatchCtl *ctl, BatchCol *co
         const BatchCol c = cols[k];
         const double so2 = s2[k], sn2 = s2[S + k];
         double coef = 0.0;
-        if (!c.fresh && c.rho > 0.0 && isfinite(c.rho) && so2 > 0.0 && sn2 > 0.0)
-            coef = (a * sn2) / (c.rho * so2) * sqrt(so2 / sn2);
+        int keep = 0;
+        if (!c.fresh && so2 > 0.0 && sn2 > 0.0) {
+            if (c.reached && !c.done) {
+                // iterated on past its target: the direction was built from
+                // the residual just replaced; it is kept (residual
+                // replacement leaves the direction alone), in the new
+                // phase's scale
+                coef = sqrt(so2 / sn2);
+                keep = 1;
+            } else if (c.rho > 0.0 && isfinite(c.rho)) {
+                coef = (a * sn2) / (c.rho * so2) * sqrt(so2 / sn2);
+            }
+        }
         BatchCol n{};
+        n.keep = keep;
         n.rho = a;
         n.rho_new = a;
         n.rr = b;
@@ -1402,10 +1425,10 @@ int batch_levelset(fo_ctx *c)
 }
 
 // FP32 CG on all columns of one block with FP64 residual replacement per
-// column: a column whose FP32 residual fell by inner_rtol is stopped, its
-// x64 += s x32 and r64 = b - K x64 (FP64) are formed, and it continues from
-// the replaced residual with its direction kept (rescaled), while the other
-// columns keep iterating.  With the nodal operator, K x64 of all the columns
+// column: a column whose FP32 residual fell by its phase target iterates on
+// to the end of the chunk of iterations, then its x64 += s x32 and r64 =
+// b - K x64 (FP64) are formed, and it continues from the replaced residual
+// with its direction (rescaled), while the other columns keep iterating.  With the nodal operator, K x64 of all the columns
 // that finished together is one launch over the FP64 node blocks; the
 // element operator takes them one at a time through the FP64 element apply.
 // Columns c0..c0+n-1 of b (ld) -> u.
@@ -1510,7 +1533,7 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
         }
         bool any = false;
         for (int k = 0; k < S; ++k) {
-            fin[k] = !conv[k] && b.cols_host[k].done;
+            fin[k] = !conv[k] && (b.cols_host[k].done || b.cols_host[k].reached);
             b.mask_host[k] = fin[k] ? 1 : 0;
             any = any || fin[k];
         }

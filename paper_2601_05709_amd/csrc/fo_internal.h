@@ -138,6 +138,9 @@ struct BatchCol {
     int32_t it;      // iterations of the current phase
     int32_t cap;     // iteration cap of the current phase
     int32_t capped;  // the phase ended at its cap
+    int32_t reached; // reached the phase target; iterates on until the host ends the phase
+    int32_t keep;    // phase start: the direction is kept, only rescaled (beta = the scale)
+    int32_t pad;
 };
 
 // Iteration control of the batched CG (device; the host polls a copy).
