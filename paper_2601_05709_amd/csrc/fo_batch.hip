@@ -1440,7 +1440,9 @@ static int batch_group(fo_ctx *c, const double *b_in, double *u, int n, int64_t 
     const int NC = std::min(4, (n + 15) / 16);
     const int S = 16 * NC;
     const int64_t nd = c->ndof;
-    const int chunk = o->check_every > 0 ? o->check_every : 16;
+    // iterations per graph chunk (host poll); on 64x32x32 with 64 load cases
+    // 24 beat 8, 12 and 16 (fewer polls) and 32 tied; 48 lost to the later phase ends
+    const int chunk = o->check_every > 0 ? o->check_every : 24;
     const int max_outer = o->max_outer > 0 ? o->max_outer : 60;
     const double phase_rtol = o->inner_rtol > 0 ? o->inner_rtol : 0.1;
     hipLaunchKernelGGL(k_batch_pack, dim3(grid_of(nd * S)), dim3(256), 0, s, b_in, ld, n, c->fixed, b.b64,
