@@ -112,6 +112,33 @@ def test_batched_solve_matches_oracle(name, method, op):
     assert np.all(uh[w.fixed == 1, :] == 0.0)
 
 
+@pytest.mark.parametrize("check_every", [1, 5, 40])
+def test_batched_solve_chunk_lengths_match_oracle(check_every):
+    """Columns that reach their phase target iterate on to the end of the
+    chunk and keep their direction into the next phase: with chunks of 1
+    (every phase ends at its target), 5 and 40 iterations every column still
+    meets the oracle's solve and its residual, from the oracle's K."""
+    w = BATCHES["3d_12x6x6_s20"]()
+    print("case chunk", check_every, flush=True)
+    m = w.mesh
+    s = w.n_rhs
+    ctx = fo.Context.from_workload(w)
+    ctx.set_levelset(dev(w.phi))
+    u = torch.zeros(m.n_dofs, s, dtype=torch.float64, device="cuda")
+    opts = fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-11, check_every=check_every)
+    st = ctx.state_solve(dev(w.b), u, opts, n_rhs=s)
+    assert st.status == 0 and st.rel_res <= 1e-11
+    Kc = oracle_K(w)
+    uh = u.cpu().numpy()
+    for k in range(s):
+        u_ref, _ = Kc.solve(w.b[:, k], w.fixed, rtol=1e-12)
+        assert np.linalg.norm(uh[:, k] - u_ref) <= 1e-8 * np.linalg.norm(u_ref), k
+        r = w.b[:, k] - Kc.matvec(uh[:, k])
+        r[w.fixed == 1] = 0.0
+        bf = np.where(w.fixed == 1, 0.0, w.b[:, k])
+        assert np.linalg.norm(r) <= 2e-11 * np.linalg.norm(bf), k
+
+
 def test_batched_agrees_with_columnwise_fp64_and_groups():
     """70 load cases: one block of 64 and one of 6; the batched FP32+refinement
     solution equals the column-by-column FP64 GPU solve; ld > n_rhs."""
