@@ -67,6 +67,14 @@ int nodal_blocks(const fo_ctx *c, int S)
 // blocks) per wave.
 static size_t nodal_lds(int KW) { return (size_t)kNodalWaves * 2 * KW * sizeof(float); }
 
+// Rounds of loads per node compiled into the apply at S columns: NB / C when
+// one node per wave (S > 32) and it is 1 or 2, else 0 (a loop over NB).
+static int nodal_rounds(const BatchState &b, int S)
+{
+    const int r = b.nb_chunk > 0 ? b.nb / b.nb_chunk : 0;
+    return S > 32 && (r == 1 || r == 2) ? r : 0;
+}
+
 // K_ij for every (node i, neighbour slot s): the sum over the elements that
 // contain both nodes, in ascending element order, of
 //   w_e (lam c_ar c_bk + mu c_ak c_br + mu delta_rk c_a . c_b),
@@ -169,8 +177,11 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(const int32_t *__restric
 // are 0.  p.q partials per block and column (gridDim.x of them, a multiple
 // of 8).  NB is a multiple of C, the neighbours taken per round of loads (7
 // or 8, whichever pads the largest neighbourhood less); a node's blocks start
-// every KW floats (KW a multiple of 4).
-template <int D, int S, int C>
+// every KW floats (KW a multiple of 4).  NCH > 0: NB = NCH C, known when
+// compiling, so the one-node-per-wave loop is unrolled and every round's
+// neighbour ids and rows can be issued ahead of the matrix work (0: NB at
+// run time).
+template <int D, int S, int C, int NCH>
 __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
     const int32_t *__restrict__ nbr, const float *__restrict__ kb, int NB, int KW, int64_t N,
     const float *__restrict__ P, float *__restrict__ Q, const uint8_t *__restrict__ fixed,
@@ -244,7 +255,7 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int32_t *nb = nbr + n * NB;
             const float *ka = kbuf + cur * KW + rr * D;
-            for (int s0 = 0; s0 < NB; s0 += C) {
+            auto round = [&](int s0) {
                 float xv[C][D];
 #pragma unroll
                 for (int u = 0; u < C; ++u) {
@@ -258,6 +269,12 @@ __global__ __launch_bounds__(64 * kNodalWaves) void k_nodal_apply(
                     for (int k = 0; k < D; ++k)
                         acc = __builtin_amdgcn_mfma_f32_4x4x1f32(ka[(s0 + u) * DD + k], xv[u][k] - xi[k], acc, 0, 0,
                                                                  0);
+            };
+            if constexpr (NCH > 0) {
+#pragma unroll
+                for (int s0 = 0; s0 < NCH * C; s0 += C) round(s0);
+            } else {
+                for (int s0 = 0; s0 < NB; s0 += C) round(s0);
             }
             if (nn < g1) stash(cur ^ 1);
             cur ^= 1;
@@ -503,12 +520,15 @@ static void nodal_apply_t(const fo_ctx *c, const float *P, float *Q, BatchCtl *c
 {
     const BatchState &b = c->batch;
     const int nblk = nodal_blocks(c, S);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * kNodalWaves), nodal_lds(b.kw), s, b.nbr, b.kb, b.nb, b.kw, c->N,
+                           P, Q, c->fixed, b.pq_nodal, ctl, cols);
+    };
+    const int nch = nodal_rounds(b, S);
     if (b.nb_chunk == 7)
-        hipLaunchKernelGGL((k_nodal_apply<D, S, 7>), dim3(nblk), dim3(64 * kNodalWaves), nodal_lds(b.kw), s,
-                           b.nbr, b.kb, b.nb, b.kw, c->N, P, Q, c->fixed, b.pq_nodal, ctl, cols);
+        nch == 1 ? go(k_nodal_apply<D, S, 7, 1>) : nch == 2 ? go(k_nodal_apply<D, S, 7, 2>) : go(k_nodal_apply<D, S, 7, 0>);
     else
-        hipLaunchKernelGGL((k_nodal_apply<D, S, 8>), dim3(nblk), dim3(64 * kNodalWaves), nodal_lds(b.kw), s,
-                           b.nbr, b.kb, b.nb, b.kw, c->N, P, Q, c->fixed, b.pq_nodal, ctl, cols);
+        nch == 1 ? go(k_nodal_apply<D, S, 8, 1>) : nch == 2 ? go(k_nodal_apply<D, S, 8, 2>) : go(k_nodal_apply<D, S, 8, 0>);
 }
 
 int nodal_residual64(const fo_ctx *c, int S, const double *X, const double *B, const uint8_t *mask, double *R,
@@ -536,12 +556,19 @@ static int nodal_occupancy(fo_ctx *c)
 {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) return FO_ERR_HIP;
-    const bool c7 = c->batch.nb_chunk == 7;
-    const void *fn[4] = {
-        c7 ? (const void *)k_nodal_apply<D, 16, 7> : (const void *)k_nodal_apply<D, 16, 8>,
-        c7 ? (const void *)k_nodal_apply<D, 32, 7> : (const void *)k_nodal_apply<D, 32, 8>,
-        c7 ? (const void *)k_nodal_apply<D, 48, 7> : (const void *)k_nodal_apply<D, 48, 8>,
-        c7 ? (const void *)k_nodal_apply<D, 64, 7> : (const void *)k_nodal_apply<D, 64, 8>};
+    // the instance each width launches (nodal_apply_t), for its occupancy
+    const BatchState &bs = c->batch;
+    const bool c7 = bs.nb_chunk == 7;
+    auto pick = [&](int S, auto k70, auto k71, auto k72, auto k80, auto k81, auto k82) {
+        const int nch = nodal_rounds(bs, S);
+        if (c7) return nch == 1 ? (const void *)k71 : nch == 2 ? (const void *)k72 : (const void *)k70;
+        return nch == 1 ? (const void *)k81 : nch == 2 ? (const void *)k82 : (const void *)k80;
+    };
+#define FO_NODAL_INST(S_)                                                                                          \
+    pick(S_, k_nodal_apply<D, S_, 7, 0>, k_nodal_apply<D, S_, 7, 1>, k_nodal_apply<D, S_, 7, 2>,                     \
+         k_nodal_apply<D, S_, 8, 0>, k_nodal_apply<D, S_, 8, 1>, k_nodal_apply<D, S_, 8, 2>)
+    const void *fn[4] = {FO_NODAL_INST(16), FO_NODAL_INST(32), FO_NODAL_INST(48), FO_NODAL_INST(64)};
+#undef FO_NODAL_INST
     for (int k = 0; k < 4; ++k) {
         int per = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn[k], 64 * kNodalWaves, nodal_lds(c->batch.kw)) !=
