@@ -526,8 +526,10 @@ int fo_set_batch_method(fo_ctx *ctx, int32_t method);
  * sharing an element (FP64 sums of the element entries of Section
  * "Compliance minimization", rounded once to FP32, exactly symmetric), and
  * applied as y_i = sum_{j != i} K_ij (x_j - x_i) (rows of K(phi) sum to zero);
- * memory: about N NB (4 + 4 d^2) bytes, NB the largest neighbour count rounded
- * up to a multiple of 7 or of 8, whichever is smaller.  FO_BATCH_OP_ELEMENT: the element contraction
+ * the FP64 residual replacement of the batched solves applies the same
+ * blocks unrounded.  Memory: about N NB (4 + 12 d^2) bytes (ids, FP32 and FP64
+ * blocks), NB the largest neighbour count rounded up to a multiple of 7 or of
+ * 8, whichever is smaller.  FO_BATCH_OP_ELEMENT: the element contraction
  * K_e[:, b >= 1] (X_b - X_0) per element tile, node rows summed in LDS and a
  * halo (what fo_batch_tune tunes).  The two agree to FP32 rounding.  Takes
  * effect at the next solve or apply.  Errors: FO_ERR_ARG. */
