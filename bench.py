@@ -493,10 +493,11 @@ def main():
     ap.add_argument("--only", default=None, choices=["headline", "c2", "extras", "large", "paper"],
                     help="run one part alone (for profilers; extras: the single-load iteration and the "
                          "transport, reinitialisation, heat, inverse and loop measurements)")
-    ap.add_argument("--kernel-only", default=None, choices=["headline", "large"],
+    ap.add_argument("--kernel-only", default=None, choices=["headline", "large", "headline-solve"],
                     help="for counter passes: build the workload's context and time its dominant kernel only "
                          "(headline: the nodal batched apply on 64x32x32 with 64 columns; large: the fused FP32 CG "
-                         "operator on 256x128x128), 20 launches")
+                         "operator on 256x128x128), 20 launches; headline-solve: one warm-up and one timed batched "
+                         "state solve of the 64 load cases (the iteration's kernels in their solve)")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 instance")
     ap.add_argument("--main-only", action="store_true",
                     help="no transport, reinitialisation, heat, inverse or loop measurements")
@@ -528,6 +529,23 @@ def main():
         print(json.dumps(paper_mesh_case()), flush=True)
         return
     if args.kernel_only:
+        if args.kernel_only == "headline-solve":
+            cells, n_loads = c3_batched_size()
+            wk = fi.multi_load_3d(cells, n_loads, seed=3)
+            ctx = fo.Context.from_workload(wk, max_rhs=n_loads)
+            ctx.set_levelset(torch.from_numpy(wk.phi).cuda())
+            b = torch.from_numpy(wk.b).cuda()
+            u = torch.zeros(wk.mesh.n_dofs, n_loads, dtype=torch.float64, device="cuda")
+            opts = fo.SolveOpts(precision=fo.FO_FP32_IR, rtol=1e-8)
+            ctx.state_solve(b, u, opts, n_rhs=n_loads)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.state_solve(b, u, opts, n_rhs=n_loads)
+            torch.cuda.synchronize()
+            print(json.dumps({"kernel_only": args.kernel_only, "solve_ms": 1e3 * (time.perf_counter() - t0),
+                              "block_iters": st.iters_inner, "refinements": st.iters_outer,
+                              "rel_res": st.rel_res}), flush=True)
+            return
         if args.kernel_only == "headline":
             cells, n_loads = c3_batched_size()
             wk = fi.multi_load_3d(cells, n_loads, seed=3)
