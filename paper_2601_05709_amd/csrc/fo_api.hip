@@ -923,10 +923,13 @@ int create_context(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32
                     up(c->bnode_fac, bfac.data(), bfac.size() * sizeof(int32_t)))))
         return fail(FO_ERR_HIP);
     if ((rc = upload_tiles(c, ht))) return fail(rc);
-    // large meshes fold the fused CG's partials first (more than one pass of
-    // the loads that the tile kernel's wave 0 and the update's blocks issue)
+    // large meshes fold the fused CG's partials first: the r.z / r.r ones
+    // beyond one pass of the loads of the tile kernel's wave 0; the per-tile
+    // p.q ones, which every update block reads, beyond 8,192 tiles (120x60x60
+    // with 5,063 tiles solves in 131.8 ms reading them directly against 140.0
+    // with the fold; 256x128x128 with 49,152 tiles needs it)
     c->fold_rz = upd_blocks(c->N) > 4 * 64;
-    c->fold_pq = ht.n_tiles > 4 * kUpdBlock;
+    c->fold_pq = ht.n_tiles > 8 * kUpdBlock;
     // FP32 operator geometry: tile-node coordinates relative to the tile's
     // first node, formed in FP64 (kept alive until the stream sync below)
     std::vector<float> tx((size_t)std::max<int64_t>((int64_t)ht.n_tiles * ht.max_nodes * D, 1), 0.0f);
