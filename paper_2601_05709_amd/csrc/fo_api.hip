@@ -851,7 +851,7 @@ int create_context(fo_ctx **out, const fo_mesh *m, const fo_material *mat, int32
         (rc = dev_alloc(c, &c->bb_part, (size_t)kRedBlocks)) ||
         (rc = dev_alloc(c, &c->partials, (size_t)kRedBlocks * 4)) ||
         (rc = dev_alloc(c, &c->pq_part, (size_t)std::max<int64_t>(ht.n_tiles, kRedBlocks))) ||
-        (rc = dev_alloc(c, &c->rz_part, (size_t)kRedBlocks * 2)) || (rc = dev_alloc(c, &c->fold, 4)) ||
+        (rc = dev_alloc(c, &c->rz_part, (size_t)kRedBlocks * 2)) || (rc = dev_alloc(c, &c->fold, 4 + kFoldGroups)) ||
         (rc = dev_alloc(c, &c->scal, 4)) || (rc = dev_alloc(c, &c->dscratch, 16)) ||
         (rc = dev_alloc(c, &c->gbuf, N * (D + 1))))
         return fail(rc);

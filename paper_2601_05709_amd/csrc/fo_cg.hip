@@ -246,6 +246,20 @@ void launch_fold(const double *part, int n, int sets, double *out, hipStream_t s
     hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(1024), 0, s, part, n, sets, out);
 }
 
+// out[g] = the sum of part[g 1024 .. min((g + 1) 1024, n)), one block per
+// group, in a fixed order: the per-tile p.q partials of a large mesh in
+// groups, whose sums the update blocks read (49,152 tiles: 48 sums, folded
+// in parallel instead of by one block).
+__global__ __launch_bounds__(1024) void k_fold_groups(const double *__restrict__ part, int n,
+                                                      double *__restrict__ out)
+{
+    __shared__ double lds[16];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = i < n ? part[i] : 0.0;
+    v = block_sum_any(v, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
 int upd_blocks(int64_t N)
 {
     int64_t b = (N + kUpdBlock - 1) / kUpdBlock;
@@ -590,10 +604,17 @@ void launch_cgn_update(const fo_ctx *c, int B, T *x, T *r, const T *p, const T *
     const T *halo = reinterpret_cast<const T *>(c->halo);
     const double *pq = c->pq_part;
     int n_pq = (int)c->tiles.n_tiles;
-    if (c->fold_pq) {  // one block folds the per-tile partials; the update blocks read one value
-        launch_fold(c->pq_part, n_pq, 1, c->fold + 2, s);
-        pq = c->fold + 2;
-        n_pq = 1;
+    if (c->fold_pq) {
+        const int G = (n_pq + 1023) / 1024;
+        if (G <= kFoldGroups) {  // groups of 1024 folded in parallel; the update blocks read G sums
+            hipLaunchKernelGGL(k_fold_groups, dim3(G), dim3(1024), 0, s, c->pq_part, n_pq, c->fold + 4);
+            pq = c->fold + 4;
+            n_pq = G;
+        } else {  // one block folds them all; the update blocks read one value
+            launch_fold(c->pq_part, n_pq, 1, c->fold + 2, s);
+            pq = c->fold + 2;
+            n_pq = 1;
+        }
     }
     if (c->dim == 2)
         hipLaunchKernelGGL((k_cgn_update<T, 2>), dim3(nb), dim3(kUpdBlock), 0, s, c->scal, B, x, r, p, q,

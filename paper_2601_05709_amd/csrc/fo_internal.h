@@ -74,6 +74,7 @@ inline double phase_target(double inner_rtol, double rtol, double bnorm, double 
 constexpr int kBlock = 256;        // threads per block of the vector kernels
 constexpr int kRedBlocks = 1024;   // partial sums per reduction (fixed: deterministic)
 constexpr int kUpdBlock = 1024;    // threads per block of the fused CG update (one node each)
+constexpr int kFoldGroups = 256;   // most p.q partial groups of 1024 folded in parallel (fused CG)
 
 // Device-resident scalars of one Krylov solve.  The host polls a copy of
 // `done`/`status`/`it` every few iterations; everything else stays on the GPU.
@@ -302,7 +303,7 @@ struct fo_ctx {
     // needs it, so that the tile kernel's blocks (and the update's) read one
     // value instead of every partial.  Used when there are more partials than
     // those kernels sum in one pass of loads.
-    double *fold = nullptr;            // [4]
+    double *fold = nullptr;            // [4 + kFoldGroups]: folded r.z, r.r, p.q; the p.q group sums from 4
     bool fold_rz = false, fold_pq = false;
     double *bb_part = nullptr;         // [kRedBlocks] b.b partials
     fo::SolveScalars *scal = nullptr;  // device, two parity slots
